@@ -1,0 +1,101 @@
+"""Workload definitions: sizes, distributions and frozen numeric constants.
+
+The constants h_M, L_s and r_cut are numbers here, not computations: they were
+produced by ``python -m oracle.constants`` and a CPU test re-derives them from
+the oracle and checks these frozen values.
+
+Config 1: 200-atom protein in a 12 A ball, 12-atom ligand in a 4 A ball, n=512
+on [-24,24]^3, M=24 (49 Gaussians, 25 distinct), 12 long-range terms,
+128 poses with the ligand centre on an 18 A sphere, vdW distance 2.5 A.
+Config 2: 5,000-atom protein at 0.05 atoms/A^3, 50-atom ligand in a 6 A ball,
+n=2048 on [-52,52]^3, M=32, 22 long-range terms, RHOSVD eps 1e-8,
+1,000,000 poses with the ligand centre uniform in the shell 5-15 A beyond the
+protein surface, vdW distance 2.5 A.
+Config 4: 10,000-atom protein, 60-atom ligand, n=4096 on [-60,60]^3, 65,536
+poses in the same kind of shell, energies plus rigid-body gradients.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, replace
+
+import numpy as np
+
+from . import generators as gen
+
+
+@dataclass(frozen=True)
+class Config:
+    index: int
+    name: str
+    N: int                   # protein atoms
+    protein_radius: float    # A
+    protein_charge_std: float
+    L: int                   # ligand atoms
+    ligand_radius: float     # A
+    ligand_charge_std: float
+    n: int                   # grid points per axis (even)
+    b: float                 # box [-b, b]^3, A
+    M: int                   # sinc terms k = 0..M after folding +-k
+    h_M: float               # quadrature step (frozen)
+    L_s: float               # quadrature scale 2*sqrt(3)*b (frozen)
+    K_long: int              # number of long-range (widest) terms
+    r_cut: float             # short-range cutoff, A (frozen)
+    eps: float               # RHOSVD / T2C relative truncation
+    P: int                   # poses
+    pose_kind: str           # "sphere" or "shell"
+    pose_r_in: float
+    pose_r_out: float
+    sigma: float             # van der Waals minimum distance, A
+
+
+CONFIG1 = Config(
+    index=1, name="cfg1-N200-L12-n512", N=200, protein_radius=12.0, protein_charge_std=0.3,
+    L=12, ligand_radius=4.0, ligand_charge_std=0.3, n=512, b=24.0, M=24, h_M=0.2622,
+    L_s=83.13843876330611, K_long=12, r_cut=43.836027469049675, eps=1e-8, P=128,
+    pose_kind="sphere", pose_r_in=18.0, pose_r_out=18.0, sigma=2.5)
+
+_RP2 = gen.protein_radius(5000, 0.05)
+CONFIG2 = Config(
+    index=2, name="cfg2-N5000-L50-n2048", N=5000, protein_radius=_RP2, protein_charge_std=0.4,
+    L=50, ligand_radius=6.0, ligand_charge_std=0.4, n=2048, b=52.0, M=32, h_M=0.2239,
+    L_s=180.13328398716322, K_long=22, r_cut=15.962725425480096, eps=1e-8, P=1_000_000,
+    pose_kind="shell", pose_r_in=_RP2 + 5.0, pose_r_out=_RP2 + 15.0, sigma=2.5)
+
+_RP4 = gen.protein_radius(10000, 0.05)
+CONFIG4 = Config(
+    index=4, name="cfg4-N10000-L60-n4096-grad", N=10000, protein_radius=_RP4, protein_charge_std=0.4,
+    L=60, ligand_radius=6.0 * (60 / 50) ** (1.0 / 3.0), ligand_charge_std=0.4, n=4096, b=60.0,
+    M=32, h_M=0.228, L_s=207.84609690826525, K_long=22, r_cut=16.833903442913364, eps=1e-8,
+    P=65_536, pose_kind="shell", pose_r_in=_RP4 + 5.0, pose_r_out=_RP4 + 15.0, sigma=2.5)
+
+CONFIGS = {1: CONFIG1, 2: CONFIG2, 4: CONFIG4}
+
+
+@dataclass
+class Workload:
+    cfg: Config
+    protein_positions: np.ndarray   # (N, 3)
+    protein_charges: np.ndarray     # (N,)
+    ligand_positions: np.ndarray    # (L, 3)
+    ligand_charges: np.ndarray      # (L,)
+    quats: np.ndarray               # (P, 4) (w, x, y, z)
+    trans: np.ndarray               # (P, 3)
+
+
+def make(cfg: Config, P: int | None = None, **overrides) -> Workload:
+    """Seeded inputs for ``cfg``; ``P`` keeps the first P poses of the full pose stream."""
+    if overrides:
+        cfg = replace(cfg, **overrides)
+    c = cfg.index
+    prot = gen.ball_points(gen.rng(c, 1), cfg.N, cfg.protein_radius)
+    z = gen.charges(gen.rng(c, 2), cfg.N, cfg.protein_charge_std, net_zero=True)
+    lig = gen.ball_points(gen.rng(c, 3), cfg.L, cfg.ligand_radius)
+    zeta = gen.charges(gen.rng(c, 4), cfg.L, cfg.ligand_charge_std, net_zero=False)
+    q = gen.unit_quaternions(gen.rng(c, 5), cfg.P)
+    if cfg.pose_kind == "sphere":
+        t = gen.sphere_translations(gen.rng(c, 6), cfg.P, cfg.pose_r_in)
+    else:
+        t = gen.shell_translations(gen.rng(c, 6), cfg.P, cfg.pose_r_in, cfg.pose_r_out)
+    if P is not None:
+        q, t = q[:P].copy(), t[:P].copy()
+    return Workload(cfg, prot, z, lig, zeta, q, t)
