@@ -1,0 +1,180 @@
+/*
+ * rsdock.h -- C ABI of librsdock, an MI355X (gfx950) library that scores rigid
+ * protein-ligand poses by the electrostatic binding energy computed from the
+ * range-separated (RS) tensor representation of the protein potential.
+ *
+ * Method: Benner, Khoromskij, Khoromskaia, Stein, "Fast tensor-based electrostatic
+ * energy calculations in the perspective of protein-ligand docking problem",
+ * arXiv 2510.26611.
+ *   - Algorithm TEP (Sec. 3.4): the long-range part of the protein potential as a
+ *     rank-R canonical tensor on an n x n x n grid, rank-reduced by
+ *     canonical -> Tucker (RHOSVD) -> canonical          -> rsd_build_rs_tensor
+ *   - Algorithm PLIE (Sec. 3.4) with Lemma 3.3 (eq. 3.10): per-pose binding energy
+ *     E = sum_l zeta_l P(y_l), plus the short-range part of the RS format
+ *     (Def. 2.1) and the van der Waals constraint of eq. 3.14  -> rsd_score_poses
+ *
+ * Units: Angstrom, elementary charge, Coulomb constant 1 (energies in e^2/A).
+ * Floating point is IEEE FP64 throughout.
+ *
+ * Memory.  Unless a call's mem_flags holds RSD_DEVICE_PTRS, every array argument
+ * is a host pointer: the call copies inputs in, runs, copies outputs back and
+ * returns when the outputs are written.  With RSD_DEVICE_PTRS every array
+ * argument is a device pointer on the context's device; the call enqueues its
+ * work on the context's stream and returns before completion (outputs are valid
+ * after the stream has been synchronised).  The caller owns every argument
+ * array; the library owns tensors until rsd_tensor_free.
+ *
+ * Errors.  Every call returns rsd_status; on failure nothing is written to the
+ * outputs and rsd_last_error() (thread-local) describes the cause.
+ * Per-pose geometry is not an error: see RSD_FLAG_*.
+ *
+ * Threads.  A context and the tensors made with it may be used from one host
+ * thread at a time.
+ */
+#ifndef RSDOCK_H
+#define RSDOCK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RSD_OK = 0,
+  RSD_E_INVALID = -1,     /* bad argument (null pointer, size, non-finite input, ...) */
+  RSD_E_OOM = -2,         /* device allocation failed or the context's HBM budget is exceeded */
+  RSD_E_HIP = -3,         /* a HIP runtime call failed */
+  RSD_E_NUMERIC = -4,     /* the rank reduction did not converge */
+  RSD_E_UNSUPPORTED = -5, /* a size beyond what the kernels support */
+  RSD_E_IO = -6           /* file could not be read or written, or is not a tensor file */
+} rsd_status;
+
+/* mem_flags bits */
+#define RSD_DEVICE_PTRS 1u
+
+/* per-pose flag bits written by rsd_score_poses */
+#define RSD_FLAG_ACCEPT 1u     /* in the grid and min over atom pairs of d^2 >= vdw_min^2 (eq. 3.14) */
+#define RSD_FLAG_IN_DOMAIN 2u  /* every ligand atom inside the grid's node range */
+#define RSD_FLAG_INVALID 4u    /* non-finite pose input or | |q|^2 - 1 | > 1e-12 */
+
+typedef struct rsd_context rsd_context;
+typedef struct rsd_tensor rsd_tensor;
+
+/* Sinc-quadrature Gaussian sum for 1/r (Sec. 2, eq. 2.2) and its range separation (eq. 2.4).
+ * Nodes t_k = sinh(k h_M)/L_s, weights w_0 = a_0, w_k = 2 a_k with
+ * a_k = h_M cosh(k h_M)/(sqrt(pi) L_s), k = 0..M (the +-k terms folded, widest first).
+ * Terms k < K_long are long-range (held in the tensor), k >= K_long short-range
+ * (summed exactly over protein atoms with d^2 < r_cut^2).  eps is the relative
+ * truncation of the rank reduction (singular values below eps * largest are dropped). */
+typedef struct {
+  int32_t M;       /* 0 <= M <= 63 */
+  int32_t K_long;  /* 0 <= K_long <= M+1 */
+  double h_M;      /* > 0 */
+  double L_s;      /* > 0, Angstrom */
+  double r_cut;    /* >= 0, Angstrom */
+  double eps;      /* 0 <= eps < 1 */
+} rsd_sinc_params;
+
+/* Library version (major, minor). */
+rsd_status rsd_version(int32_t* major, int32_t* minor);
+
+/* Thread-local message for the last failing call on this thread ("" if none). */
+const char* rsd_last_error(void);
+
+/* Context: device id, the hipStream_t all work is enqueued on (NULL = the null
+ * stream; the caller keeps ownership of the stream) and an HBM budget in bytes
+ * for resident tensors plus library workspace (0 = no limit beyond the device). */
+rsd_status rsd_context_create(int32_t device, void* hip_stream, size_t hbm_budget_bytes,
+                              rsd_context** out);
+rsd_status rsd_context_set_stream(rsd_context* ctx, void* hip_stream);
+/* Bytes currently held by the context (tensors + workspace). */
+rsd_status rsd_context_memory(const rsd_context* ctx, size_t* bytes_in_use, size_t* budget);
+void rsd_context_free(rsd_context* ctx);
+
+/* Build the RS tensor of a protein (Algorithm TEP).
+ *   charges   [N]     protein charges z_m
+ *   positions [N*3]   protein atom coordinates (x, y, z) per atom, row-major; every
+ *                     coordinate must lie in the node range [-b + 2b/n, b]
+ *   n         grid points per axis, even, 4 <= n <= 32768; mesh h = 2b/n; nodes
+ *             X_j = -b + (j+1) h, j = 0..n-1 (Sec. 2, eq. 2.1, origin at node n/2)
+ *   b         half-width of the box [-b, b]^3, > 0
+ *   sp        quadrature, range split, cutoff and truncation (see rsd_sinc_params)
+ * Steps: long-range factor columns exp(-t_k^2 (X_j - x_{m,d})^2) collocated at the true
+ * atom positions (eq. 2.6); per mode the Gram matrix of the column-normalised factor
+ * matrix on FP64 matrix cores, its dominant eigenvectors, projection, Tucker core,
+ * and slice-wise SVD of the core into canonical terms (TEP step 4); and a cell list of
+ * the protein atoms for the short-range sum.  Synchronous: returns when the tensor
+ * is resident.  Errors: RSD_E_INVALID (sizes, non-finite or out-of-box input),
+ * RSD_E_OOM, RSD_E_NUMERIC, RSD_E_HIP. */
+rsd_status rsd_build_rs_tensor(rsd_context* ctx, const double* charges, const double* positions,
+                               int64_t N, int32_t n, double b, const rsd_sinc_params* sp,
+                               uint32_t mem_flags, rsd_tensor** out);
+
+/* Make a resident tensor from given canonical factors (e.g. ones built elsewhere).
+ *   F1, F2, F3 [n*R]  factor matrices, row-major n x R (entry (i, p) at i*R + p); the
+ *                     tensor is sum_p F1[:,p] (x) F2[:,p] (x) F3[:,p] (weights folded in)
+ *   R >= 0; charges/positions/N as in rsd_build_rs_tensor (for the short-range part).
+ * Synchronous. */
+rsd_status rsd_tensor_import(rsd_context* ctx, const double* F1, const double* F2, const double* F3,
+                             int64_t R, int32_t n, double b, const rsd_sinc_params* sp,
+                             const double* charges, const double* positions, int64_t N,
+                             uint32_t mem_flags, rsd_tensor** out);
+
+/* Score P poses of a rigid ligand (Algorithm PLIE, Lemma 3.3 with the short-range
+ * term of Def. 2.1, and the constraint of eq. 3.14).
+ *   lig_charges   [L]    ligand charges zeta_l
+ *   lig_positions [L*3]  ligand atom coordinates in its own frame; the pose rotates
+ *                        them about their geometric centre c = (sum_l x_l)/L
+ *   quats [P*4]  unit quaternions (w, x, y, z), used as given (q and -q score the same)
+ *   trans [P*3]  position of the ligand centre: y_l = R(q)(x_l - c) + t
+ *   vdw_min      van der Waals distance sigma >= 0
+ * Outputs (caller-allocated, P entries each):
+ *   energies       E = sum_l zeta_l (P_long(y_l) + P_short(y_l)); NaN unless in domain
+ *   energies_long  sum_l zeta_l P_long(y_l) (may be NULL)
+ *   flags          RSD_FLAG_* bits
+ *   counts         number of (ligand, protein) atom pairs with d^2 < r_cut^2
+ *   grads [P*6]    (dE/dt, dE/domega): translation gradient and the derivative with
+ *                  respect to a rotation vector omega applied as q' = quat(omega) q about
+ *                  the centre (the rigid-body force reduction of Sec. 5.2); may be NULL
+ * Long-range values are the trilinear interpolant of the tensor: per mode, the two
+ * factor rows around the point are linearly interpolated; the gradient is the exact
+ * derivative of that interpolant (the one-sided difference of eq. 3.12 inside the cell).
+ * Limits: 1 <= L <= 896.  P = 0 is a no-op.  Errors: RSD_E_INVALID (with host
+ * pointers also for an invalid pose), RSD_E_UNSUPPORTED, RSD_E_OOM, RSD_E_HIP. */
+rsd_status rsd_score_poses(rsd_context* ctx, const rsd_tensor* tensor,
+                           const double* lig_charges, const double* lig_positions, int64_t L,
+                           const double* quats, const double* trans, int64_t P, double vdw_min,
+                           uint32_t mem_flags, double* energies, double* energies_long,
+                           uint8_t* flags, int32_t* counts, double* grads);
+
+/* Tensor metadata: grid size, canonical rank R, Tucker ranks (0 for imported tensors)
+ * and resident device bytes.  Any output pointer may be NULL. */
+rsd_status rsd_tensor_query(const rsd_tensor* t, int32_t* n, int64_t* R, int32_t ranks[3],
+                            size_t* bytes);
+
+/* Copy the factors to host arrays F1, F2, F3 of n*R doubles each (row-major n x R).
+ * Synchronous. */
+rsd_status rsd_tensor_export(const rsd_tensor* t, double* F1, double* F2, double* F3);
+
+/* Versioned binary file: header (magic, version, n, b, R, ranks, sinc params, N),
+ * factors, protein atoms and a checksum.  Load rebuilds the cell list. */
+rsd_status rsd_tensor_save(const rsd_tensor* t, const char* path);
+rsd_status rsd_tensor_load(rsd_context* ctx, const char* path, rsd_tensor** out);
+
+void rsd_tensor_free(rsd_tensor* t);
+
+/* Kernel timing with HIP events on the context stream (off by default).  When on,
+ * every library kernel launch is bracketed by events and its duration is added to
+ * a per-kernel total once the stream reaches it; rsd_kernel_time synchronises the
+ * stream and reports the number of launches and total milliseconds of the named
+ * kernel ("score", "cells", "gram", ...) since timing was switched on. */
+rsd_status rsd_context_set_timing(rsd_context* ctx, int32_t enable);
+rsd_status rsd_kernel_time(rsd_context* ctx, const char* kernel, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSDOCK_H */

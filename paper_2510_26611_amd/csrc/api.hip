@@ -1,0 +1,620 @@
+// C ABI of librsdock: contexts, resident tensors, scoring entry point, file I/O, timing.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace rsd {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+void clear_error() { g_err.clear(); }
+
+// ---------------------------------------------------------------- context memory
+rsd_status Context::dev_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 8;
+  RSD_CHECK(budget == 0 || in_use + bytes <= budget, RSD_E_OOM,
+            "HBM budget exceeded: %zu in use + %zu requested > %zu", in_use, bytes, budget);
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    return RSD_E_OOM;
+  }
+  in_use += bytes;
+  return RSD_OK;
+}
+
+void Context::dev_free(void* p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  if (bytes == 0) bytes = 8;
+  in_use = in_use >= bytes ? in_use - bytes : 0;
+}
+
+rsd_status Context::workspace(size_t bytes, void** out) {
+  if (bytes > ws_bytes) {
+    if (ws) {
+      RSD_HIP(hipStreamSynchronize(stream));
+      dev_free(ws, ws_bytes);
+      ws = nullptr;
+      ws_bytes = 0;
+    }
+    size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+    RSD_TRY(dev_alloc(&ws, want));
+    ws_bytes = want;
+  }
+  *out = ws;
+  return RSD_OK;
+}
+
+rsd_status Context::timer_begin(const char* name, KernelTimer* t) {
+  t->name = name;
+  RSD_HIP(hipEventCreate(&t->start));
+  RSD_HIP(hipEventCreate(&t->stop));
+  RSD_HIP(hipEventRecord(t->start, stream));
+  return RSD_OK;
+}
+
+rsd_status Context::timer_end(KernelTimer* t) {
+  RSD_HIP(hipEventRecord(t->stop, stream));
+  pending.push_back(*t);
+  return RSD_OK;
+}
+
+rsd_status Context::collect_timers() {
+  if (pending.empty()) return RSD_OK;
+  RSD_HIP(hipStreamSynchronize(stream));
+  for (auto& t : pending) {
+    float ms = 0.f;
+    RSD_HIP(hipEventElapsedTime(&ms, t.start, t.stop));
+    auto& acc = ktime[t.name];
+    acc.first += 1;
+    acc.second += (double)ms;
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  pending.clear();
+  return RSD_OK;
+}
+
+size_t Tensor::bytes() const {
+  return F_bytes + cell_bytes + sizeof(double4) * (size_t)(N > 0 ? N : 1) + sizeof(double) * 2 * kMaxTerms;
+}
+
+void sinc_table(const rsd_sinc_params& sp, double* t, double* w) {
+  const double root_pi = std::sqrt(M_PI);
+  for (int k = 0; k <= sp.M; ++k) {
+    const double kh = (double)k * sp.h_M;
+    t[k] = std::sinh(kh) / sp.L_s;
+    const double a = sp.h_M * std::cosh(kh) / (root_pi * sp.L_s);
+    w[k] = k == 0 ? a : 2.0 * a;
+  }
+}
+
+// ---------------------------------------------------------------- helpers
+static rsd_status check_sinc(const rsd_sinc_params* sp) {
+  RSD_CHECK(sp != nullptr, RSD_E_INVALID, "sinc params are NULL");
+  RSD_CHECK(sp->M >= 0 && sp->M + 1 <= kMaxTerms, RSD_E_INVALID, "M=%d out of range [0, %d]", sp->M, kMaxTerms - 1);
+  RSD_CHECK(sp->K_long >= 0 && sp->K_long <= sp->M + 1, RSD_E_INVALID, "K_long=%d out of range", sp->K_long);
+  RSD_CHECK(std::isfinite(sp->h_M) && sp->h_M > 0, RSD_E_INVALID, "h_M must be finite and > 0");
+  RSD_CHECK(std::isfinite(sp->L_s) && sp->L_s > 0, RSD_E_INVALID, "L_s must be finite and > 0");
+  RSD_CHECK(std::isfinite(sp->r_cut) && sp->r_cut >= 0, RSD_E_INVALID, "r_cut must be finite and >= 0");
+  RSD_CHECK(std::isfinite(sp->eps) && sp->eps >= 0 && sp->eps < 1, RSD_E_INVALID, "eps must be in [0, 1)");
+  return RSD_OK;
+}
+
+static rsd_status check_grid(int32_t n, double b) {
+  RSD_CHECK(n >= 4 && n <= 32768 && n % 2 == 0, RSD_E_INVALID, "n=%d must be even and in [4, 32768]", n);
+  RSD_CHECK(std::isfinite(b) && b > 0, RSD_E_INVALID, "b must be finite and > 0");
+  return RSD_OK;
+}
+
+static bool is_device_ptrs(uint32_t f) { return (f & RSD_DEVICE_PTRS) != 0; }
+
+// Copy `count` doubles from a caller array (host or device) into a host vector.
+static rsd_status to_host(const double* src, size_t count, bool dev, std::vector<double>* out) {
+  out->resize(count);
+  if (count == 0) return RSD_OK;
+  if (dev) {
+    RSD_HIP(hipMemcpy(out->data(), src, sizeof(double) * count, hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(out->data(), src, sizeof(double) * count);
+  }
+  return RSD_OK;
+}
+
+static rsd_status check_protein(const std::vector<double>& z, const std::vector<double>& pos, int32_t n, double b) {
+  double h, X0, inv_h;
+  grid_constants(n, b, &h, &X0, &inv_h);
+  for (size_t i = 0; i < z.size(); ++i) {
+    RSD_CHECK(std::isfinite(z[i]), RSD_E_INVALID, "protein charge %zu is not finite", i);
+    for (int d = 0; d < 3; ++d) {
+      const double x = pos[3 * i + d];
+      RSD_CHECK(std::isfinite(x) && x >= X0 && x <= b, RSD_E_INVALID,
+                "protein atom %zu coordinate %d = %g outside the grid node range [%g, %g]", i, d, x, X0, b);
+    }
+  }
+  return RSD_OK;
+}
+
+// Create the tensor shell: grid constants, short-range table, protein copies, cell list.
+static rsd_status tensor_common(Context* ctx, Tensor* t, int32_t n, double b, const rsd_sinc_params* sp,
+                                std::vector<double>&& z, std::vector<double>&& pos, double** d_z,
+                                double** d_pos) {
+  t->ctx = ctx;
+  t->n = n;
+  t->b = b;
+  grid_constants(n, b, &t->h, &t->X0, &t->inv_h);
+  t->sp = *sp;
+  t->N = (int64_t)z.size();
+  t->host_charges = std::move(z);
+  t->host_positions = std::move(pos);
+  double tk[kMaxTerms], wk[kMaxTerms];
+  sinc_table(*sp, tk, wk);
+  t->shrt.S = sp->M + 1 - sp->K_long;
+  double tab[2 * kMaxTerms] = {0};
+  for (int k = 0; k < t->shrt.S; ++k) {
+    t->shrt.t2[k] = tk[sp->K_long + k] * tk[sp->K_long + k];
+    t->shrt.w[k] = wk[sp->K_long + k];
+    tab[k] = t->shrt.t2[k];
+    tab[kMaxTerms + k] = t->shrt.w[k];
+  }
+  RSD_TRY(ctx->dev_alloc((void**)&t->short_tab, sizeof(tab)));
+  RSD_HIP(hipMemcpy(t->short_tab, tab, sizeof(tab), hipMemcpyHostToDevice));
+  // device copies of the protein (freed by the caller of tensor_common)
+  const size_t N = (size_t)t->N;
+  RSD_TRY(ctx->dev_alloc((void**)d_z, sizeof(double) * (N ? N : 1)));
+  RSD_TRY(ctx->dev_alloc((void**)d_pos, sizeof(double) * 3 * (N ? N : 1)));
+  if (N) {
+    RSD_HIP(hipMemcpy(*d_z, t->host_charges.data(), sizeof(double) * N, hipMemcpyHostToDevice));
+    RSD_HIP(hipMemcpy(*d_pos, t->host_positions.data(), sizeof(double) * 3 * N, hipMemcpyHostToDevice));
+  }
+  RSD_TRY(build_cells(ctx, t, *d_z, *d_pos));
+  return RSD_OK;
+}
+
+static void tensor_release(Tensor* t) {
+  if (!t) return;
+  Context* c = t->ctx;
+  if (c) {
+    (void)hipSetDevice(c->device);
+    c->dev_free(t->F, t->F_bytes);
+    c->dev_free(t->atoms, sizeof(double4) * (size_t)(t->N > 0 ? t->N : 1));
+    c->dev_free(t->cell_start, t->cell_bytes);
+    c->dev_free(t->short_tab, sizeof(double) * 2 * kMaxTerms);
+  }
+  delete static_cast<rsd_tensor*>(t);
+}
+
+// Row-major n x R (device) -> column-chunked layout (device), zero padded.
+__global__ void k_relayout(const double* __restrict__ src, int64_t R, int n, int nchunk, double* __restrict__ dst) {
+  const int64_t total = (int64_t)nchunk * n * kChunk;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e % kChunk);
+    const int64_t rest = e / kChunk;
+    const int i = (int)(rest % n);
+    const int c = (int)(rest / n);
+    const int64_t col = (int64_t)c * kChunk + j;
+    dst[e] = col < R ? src[(int64_t)i * R + col] : 0.0;
+  }
+}
+
+__global__ void k_unlayout(const double* __restrict__ src, int64_t R, int n, double* __restrict__ dst) {
+  const int64_t total = (int64_t)n * R;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / R, col = e % R;
+    dst[e] = src[((col / kChunk) * n + i) * kChunk + (col % kChunk)];
+  }
+}
+
+rsd_status alloc_factors(Context* ctx, Tensor* t, int64_t R) {
+  t->R = R;
+  t->nchunk = (int)((R + kChunk - 1) / kChunk);
+  t->F_bytes = sizeof(double) * 3 * (size_t)t->nchunk * (size_t)t->n * kChunk;
+  return ctx->dev_alloc((void**)&t->F, t->F_bytes);
+}
+
+rsd_status import_factors(Context* ctx, Tensor* t, const double* const F[3], int64_t R, bool dev) {
+  RSD_TRY(alloc_factors(ctx, t, R));
+  if (t->nchunk == 0) return RSD_OK;
+  const size_t one = sizeof(double) * (size_t)t->n * (size_t)R;
+  void* ws = nullptr;
+  RSD_TRY(ctx->workspace(one, &ws));
+  const int64_t mode = (int64_t)t->nchunk * t->n * kChunk;
+  for (int d = 0; d < 3; ++d) {
+    RSD_HIP(hipMemcpyAsync(ws, F[d], one, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
+    k_relayout<<<1024, 256, 0, ctx->stream>>>((const double*)ws, R, t->n, t->nchunk, t->F + d * mode);
+    RSD_HIP(hipGetLastError());
+    RSD_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  return RSD_OK;
+}
+
+}  // namespace rsd
+
+using namespace rsd;
+
+// ================================================================ C ABI
+extern "C" {
+
+rsd_status rsd_version(int32_t* major, int32_t* minor) {
+  if (major) *major = 1;
+  if (minor) *minor = 0;
+  return RSD_OK;
+}
+
+const char* rsd_last_error(void) { return g_err.c_str(); }
+
+rsd_status rsd_context_create(int32_t device, void* hip_stream, size_t hbm_budget_bytes, rsd_context** out) {
+  clear_error();
+  RSD_CHECK(out != nullptr, RSD_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  RSD_HIP(hipGetDeviceCount(&count));
+  RSD_CHECK(device >= 0 && device < count, RSD_E_INVALID, "device %d not present (%d devices)", device, count);
+  RSD_HIP(hipSetDevice(device));
+  rsd_context* c = new (std::nothrow) rsd_context();
+  RSD_CHECK(c != nullptr, RSD_E_OOM, "host allocation failed");
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->budget = hbm_budget_bytes;
+  *out = c;
+  return RSD_OK;
+}
+
+rsd_status rsd_context_set_stream(rsd_context* ctx, void* hip_stream) {
+  clear_error();
+  RSD_CHECK(ctx != nullptr, RSD_E_INVALID, "ctx is NULL");
+  RSD_HIP(hipSetDevice(ctx->device));
+  RSD_HIP(hipStreamSynchronize(ctx->stream));
+  RSD_TRY(ctx->collect_timers());
+  ctx->stream = (hipStream_t)hip_stream;
+  return RSD_OK;
+}
+
+rsd_status rsd_context_memory(const rsd_context* ctx, size_t* bytes_in_use, size_t* budget) {
+  clear_error();
+  RSD_CHECK(ctx != nullptr, RSD_E_INVALID, "ctx is NULL");
+  if (bytes_in_use) *bytes_in_use = ctx->in_use;
+  if (budget) *budget = ctx->budget;
+  return RSD_OK;
+}
+
+void rsd_context_free(rsd_context* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& t : ctx->pending) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  ctx->dev_free(ctx->ws, ctx->ws_bytes);
+  delete ctx;
+}
+
+static rsd_status make_tensor(rsd_context* ctx, const double* const F[3], int64_t R, bool build, int32_t n,
+                              double b, const rsd_sinc_params* sp, const double* charges,
+                              const double* positions, int64_t N, uint32_t mem_flags, rsd_tensor** out) {
+  clear_error();
+  RSD_CHECK(out != nullptr, RSD_E_INVALID, "out is NULL");
+  *out = nullptr;
+  RSD_CHECK(ctx != nullptr, RSD_E_INVALID, "ctx is NULL");
+  RSD_TRY(check_sinc(sp));
+  RSD_TRY(check_grid(n, b));
+  RSD_CHECK(N >= (build ? 1 : 0) && N <= (int64_t)1 << 30, RSD_E_INVALID, "N=%lld out of range", (long long)N);
+  RSD_CHECK(N == 0 || (charges && positions), RSD_E_INVALID, "charges/positions are NULL");
+  const bool dev = is_device_ptrs(mem_flags);
+  RSD_HIP(hipSetDevice(ctx->device));
+  std::vector<double> z, pos;
+  RSD_TRY(to_host(charges, (size_t)N, dev, &z));
+  RSD_TRY(to_host(positions, 3 * (size_t)N, dev, &pos));
+  RSD_TRY(check_protein(z, pos, n, b));
+  rsd_tensor* t = new (std::nothrow) rsd_tensor();
+  RSD_CHECK(t != nullptr, RSD_E_OOM, "host allocation failed");
+  double* d_z = nullptr;
+  double* d_pos = nullptr;
+  rsd_status st = tensor_common(ctx, t, n, b, sp, std::move(z), std::move(pos), &d_z, &d_pos);
+  if (st == RSD_OK) {
+    if (build) {
+      st = build_factors(ctx, t, d_z, d_pos);
+    } else {
+      st = import_factors(ctx, t, F, R, dev);
+    }
+  }
+  if (st == RSD_OK) {
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+      set_error("hipStreamSynchronize: %s", hipGetErrorString(e));
+      st = RSD_E_HIP;
+    }
+  }
+  ctx->dev_free(d_z, sizeof(double) * (size_t)(N ? N : 1));
+  ctx->dev_free(d_pos, sizeof(double) * 3 * (size_t)(N ? N : 1));
+  if (st != RSD_OK) {
+    std::string keep = g_err;
+    tensor_release(t);
+    g_err = keep;
+    return st;
+  }
+  *out = t;
+  return RSD_OK;
+}
+
+rsd_status rsd_build_rs_tensor(rsd_context* ctx, const double* charges, const double* positions, int64_t N,
+                               int32_t n, double b, const rsd_sinc_params* sp, uint32_t mem_flags,
+                               rsd_tensor** out) {
+  return make_tensor(ctx, nullptr, 0, true, n, b, sp, charges, positions, N, mem_flags, out);
+}
+
+rsd_status rsd_tensor_import(rsd_context* ctx, const double* F1, const double* F2, const double* F3, int64_t R,
+                             int32_t n, double b, const rsd_sinc_params* sp, const double* charges,
+                             const double* positions, int64_t N, uint32_t mem_flags, rsd_tensor** out) {
+  clear_error();
+  RSD_CHECK(R >= 0 && R <= (int64_t)1 << 24, RSD_E_INVALID, "R=%lld out of range", (long long)R);
+  RSD_CHECK(R == 0 || (F1 && F2 && F3), RSD_E_INVALID, "factor pointers are NULL");
+  if (R > 0 && !is_device_ptrs(mem_flags)) {
+    for (const double* F : {F1, F2, F3})
+      for (int64_t e = 0; e < (int64_t)n * R; ++e)
+        RSD_CHECK(std::isfinite(F[e]), RSD_E_INVALID, "factor entry %lld is not finite", (long long)e);
+  }
+  const double* F[3] = {F1, F2, F3};
+  return make_tensor(ctx, F, R, false, n, b, sp, charges, positions, N, mem_flags, out);
+}
+
+rsd_status rsd_tensor_query(const rsd_tensor* t, int32_t* n, int64_t* R, int32_t ranks[3], size_t* bytes) {
+  clear_error();
+  RSD_CHECK(t != nullptr, RSD_E_INVALID, "tensor is NULL");
+  if (n) *n = t->n;
+  if (R) *R = t->R;
+  if (ranks) {
+    for (int d = 0; d < 3; ++d) ranks[d] = t->ranks[d];
+  }
+  if (bytes) *bytes = t->bytes();
+  return RSD_OK;
+}
+
+rsd_status rsd_tensor_export(const rsd_tensor* t, double* F1, double* F2, double* F3) {
+  clear_error();
+  RSD_CHECK(t != nullptr, RSD_E_INVALID, "tensor is NULL");
+  RSD_CHECK(t->R == 0 || (F1 && F2 && F3), RSD_E_INVALID, "output pointers are NULL");
+  if (t->R == 0) return RSD_OK;
+  Context* ctx = t->ctx;
+  RSD_HIP(hipSetDevice(ctx->device));
+  const size_t one = sizeof(double) * (size_t)t->n * (size_t)t->R;
+  void* ws = nullptr;
+  RSD_TRY(ctx->workspace(one, &ws));
+  double* out[3] = {F1, F2, F3};
+  const int64_t mode = (int64_t)t->nchunk * t->n * kChunk;
+  for (int d = 0; d < 3; ++d) {
+    k_unlayout<<<1024, 256, 0, ctx->stream>>>(t->F + d * mode, t->R, t->n, (double*)ws);
+    RSD_HIP(hipGetLastError());
+    RSD_HIP(hipMemcpyAsync(out[d], ws, one, hipMemcpyDeviceToHost, ctx->stream));
+    RSD_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  return RSD_OK;
+}
+
+void rsd_tensor_free(rsd_tensor* t) { tensor_release(t); }
+
+rsd_status rsd_score_poses(rsd_context* ctx, const rsd_tensor* t, const double* lig_charges,
+                           const double* lig_positions, int64_t L, const double* quats, const double* trans,
+                           int64_t P, double vdw_min, uint32_t mem_flags, double* energies,
+                           double* energies_long, uint8_t* flags, int32_t* counts, double* grads) {
+  clear_error();
+  RSD_CHECK(ctx != nullptr && t != nullptr, RSD_E_INVALID, "ctx or tensor is NULL");
+  RSD_CHECK(t->ctx == ctx, RSD_E_INVALID, "tensor belongs to another context");
+  RSD_CHECK(L >= 1 && L <= kMaxLigand, RSD_E_UNSUPPORTED, "L=%lld outside [1, %d]", (long long)L, kMaxLigand);
+  RSD_CHECK(P >= 0 && P <= ((int64_t)1 << 33), RSD_E_INVALID, "P=%lld out of range", (long long)P);
+  RSD_CHECK(std::isfinite(vdw_min) && vdw_min >= 0, RSD_E_INVALID, "vdw_min must be finite and >= 0");
+  RSD_CHECK(lig_charges && lig_positions, RSD_E_INVALID, "ligand pointers are NULL");
+  if (P == 0) return RSD_OK;
+  RSD_CHECK(quats && trans && energies && flags && counts, RSD_E_INVALID, "pose/output pointers are NULL");
+  RSD_HIP(hipSetDevice(ctx->device));
+  const bool dev = is_device_ptrs(mem_flags);
+  ScoreIO io{};
+  io.L = (int)L;
+  io.P = P;
+  io.vdw_min = vdw_min;
+  if (dev) {
+    io.lig_charges = lig_charges;
+    io.lig_positions = lig_positions;
+    io.quats = quats;
+    io.trans = trans;
+    io.E = energies;
+    io.El = energies_long;
+    io.flags = flags;
+    io.counts = counts;
+    io.grads = grads;
+    return launch_score(ctx, t, io);
+  }
+  // host pointers: validate, stage, run, copy back, synchronise
+  for (int64_t l = 0; l < L; ++l) {
+    RSD_CHECK(std::isfinite(lig_charges[l]) && std::isfinite(lig_positions[3 * l]) &&
+                  std::isfinite(lig_positions[3 * l + 1]) && std::isfinite(lig_positions[3 * l + 2]),
+              RSD_E_INVALID, "ligand atom %lld is not finite", (long long)l);
+  }
+  for (int64_t p = 0; p < P; ++p) {
+    const double* q = quats + 4 * p;
+    const double* tt = trans + 3 * p;
+    const double qq = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3];
+    const bool ok = std::isfinite(q[0]) && std::isfinite(q[1]) && std::isfinite(q[2]) && std::isfinite(q[3]) &&
+                    std::isfinite(tt[0]) && std::isfinite(tt[1]) && std::isfinite(tt[2]) &&
+                    std::fabs(qq - 1.0) <= 1e-12;
+    RSD_CHECK(ok, RSD_E_INVALID, "pose %lld: non-finite input or |q|^2 - 1 beyond 1e-12", (long long)p);
+  }
+  // staging buffer: inputs then outputs (separate from the context workspace used by the kernels)
+  const size_t nin = (size_t)L * 4 + (size_t)P * 7;
+  const size_t nout = (size_t)P * (2 + (grads ? 6 : 0));
+  const size_t bytes = sizeof(double) * (nin + nout) + (size_t)P * (sizeof(int32_t) + 1) + 64;
+  char* stage = nullptr;
+  RSD_TRY(ctx->dev_alloc((void**)&stage, bytes));
+  double* d = (double*)stage;
+  io.lig_charges = d;
+  io.lig_positions = d + L;
+  io.quats = d + 4 * L;
+  io.trans = d + 4 * L + 4 * P;
+  io.E = d + nin;
+  io.El = io.E + P;
+  io.grads = grads ? io.El + P : nullptr;
+  io.counts = (int32_t*)(d + nin + nout);
+  io.flags = (uint8_t*)(io.counts + P);
+  hipStream_t s = ctx->stream;
+  rsd_status st = RSD_OK;
+  auto cp = [&](void* dst, const void* src, size_t n, hipMemcpyKind k) {
+    if (st != RSD_OK || n == 0) return;
+    hipError_t e = hipMemcpyAsync(dst, src, n, k, s);
+    if (e != hipSuccess) {
+      set_error("hipMemcpyAsync: %s", hipGetErrorString(e));
+      st = RSD_E_HIP;
+    }
+  };
+  cp((void*)io.lig_charges, lig_charges, sizeof(double) * L, hipMemcpyHostToDevice);
+  cp((void*)io.lig_positions, lig_positions, sizeof(double) * 3 * L, hipMemcpyHostToDevice);
+  cp((void*)io.quats, quats, sizeof(double) * 4 * P, hipMemcpyHostToDevice);
+  cp((void*)io.trans, trans, sizeof(double) * 3 * P, hipMemcpyHostToDevice);
+  if (st == RSD_OK) st = launch_score(ctx, t, io);
+  cp(energies, io.E, sizeof(double) * P, hipMemcpyDeviceToHost);
+  if (energies_long) cp(energies_long, io.El, sizeof(double) * P, hipMemcpyDeviceToHost);
+  cp(flags, io.flags, (size_t)P, hipMemcpyDeviceToHost);
+  cp(counts, io.counts, sizeof(int32_t) * P, hipMemcpyDeviceToHost);
+  if (grads) cp(grads, io.grads, sizeof(double) * 6 * P, hipMemcpyDeviceToHost);
+  hipError_t e = hipStreamSynchronize(s);
+  if (st == RSD_OK && e != hipSuccess) {
+    set_error("hipStreamSynchronize: %s", hipGetErrorString(e));
+    st = RSD_E_HIP;
+  }
+  ctx->dev_free(stage, bytes);
+  return st;
+}
+
+// ---------------------------------------------------------------- file I/O
+static const char kMagic[8] = {'R', 'S', 'D', 'T', 'E', 'N', 'S', '1'};
+
+static uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* c = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+struct FileHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t n;
+  double b;
+  int64_t R;
+  int32_t ranks[3];
+  int32_t pad;
+  rsd_sinc_params sp;
+  int64_t N;
+};
+
+rsd_status rsd_tensor_save(const rsd_tensor* t, const char* path) {
+  clear_error();
+  RSD_CHECK(t != nullptr && path != nullptr, RSD_E_INVALID, "tensor or path is NULL");
+  const size_t nR = (size_t)t->n * (size_t)t->R;
+  std::vector<double> F(3 * nR);
+  if (t->R > 0) RSD_TRY(rsd_tensor_export(t, F.data(), F.data() + nR, F.data() + 2 * nR));
+  FileHeader hd{};
+  std::memcpy(hd.magic, kMagic, 8);
+  hd.version = 1;
+  hd.n = t->n;
+  hd.b = t->b;
+  hd.R = t->R;
+  for (int d = 0; d < 3; ++d) hd.ranks[d] = t->ranks[d];
+  hd.sp = t->sp;
+  hd.N = t->N;
+  FILE* f = std::fopen(path, "wb");
+  RSD_CHECK(f != nullptr, RSD_E_IO, "cannot open %s for writing", path);
+  uint64_t h = 1469598103934665603ull;
+  h = fnv1a(h, &hd, sizeof(hd));
+  h = fnv1a(h, F.data(), sizeof(double) * F.size());
+  h = fnv1a(h, t->host_charges.data(), sizeof(double) * t->host_charges.size());
+  h = fnv1a(h, t->host_positions.data(), sizeof(double) * t->host_positions.size());
+  bool ok = std::fwrite(&hd, sizeof(hd), 1, f) == 1;
+  ok = ok && (F.empty() || std::fwrite(F.data(), sizeof(double), F.size(), f) == F.size());
+  ok = ok && (t->N == 0 || std::fwrite(t->host_charges.data(), sizeof(double), t->host_charges.size(), f) ==
+                               t->host_charges.size());
+  ok = ok && (t->N == 0 || std::fwrite(t->host_positions.data(), sizeof(double), t->host_positions.size(), f) ==
+                               t->host_positions.size());
+  ok = ok && std::fwrite(&h, sizeof(h), 1, f) == 1;
+  ok = (std::fclose(f) == 0) && ok;
+  RSD_CHECK(ok, RSD_E_IO, "write to %s failed", path);
+  return RSD_OK;
+}
+
+rsd_status rsd_tensor_load(rsd_context* ctx, const char* path, rsd_tensor** out) {
+  clear_error();
+  RSD_CHECK(ctx != nullptr && path != nullptr && out != nullptr, RSD_E_INVALID, "NULL argument");
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  RSD_CHECK(f != nullptr, RSD_E_IO, "cannot open %s", path);
+  FileHeader hd{};
+  bool ok = std::fread(&hd, sizeof(hd), 1, f) == 1 && std::memcmp(hd.magic, kMagic, 8) == 0 && hd.version == 1 &&
+            hd.R >= 0 && hd.R <= ((int64_t)1 << 24) && hd.N >= 0 && hd.N <= ((int64_t)1 << 30) && hd.n >= 4 &&
+            hd.n <= 32768;
+  if (!ok) {
+    std::fclose(f);
+    set_error("%s is not a tensor file of this version", path);
+    return RSD_E_IO;
+  }
+  const size_t nR = (size_t)hd.n * (size_t)hd.R;
+  std::vector<double> F(3 * nR), z((size_t)hd.N), pos(3 * (size_t)hd.N);
+  uint64_t stored = 0;
+  ok = (F.empty() || std::fread(F.data(), sizeof(double), F.size(), f) == F.size()) &&
+       (z.empty() || std::fread(z.data(), sizeof(double), z.size(), f) == z.size()) &&
+       (pos.empty() || std::fread(pos.data(), sizeof(double), pos.size(), f) == pos.size()) &&
+       std::fread(&stored, sizeof(stored), 1, f) == 1;
+  std::fclose(f);
+  RSD_CHECK(ok, RSD_E_IO, "%s is truncated", path);
+  uint64_t h = 1469598103934665603ull;
+  h = fnv1a(h, &hd, sizeof(hd));
+  h = fnv1a(h, F.data(), sizeof(double) * F.size());
+  h = fnv1a(h, z.data(), sizeof(double) * z.size());
+  h = fnv1a(h, pos.data(), sizeof(double) * pos.size());
+  RSD_CHECK(h == stored, RSD_E_IO, "%s: checksum mismatch", path);
+  RSD_TRY(rsd_tensor_import(ctx, F.data(), F.data() + nR, F.data() + 2 * nR, hd.R, hd.n, hd.b, &hd.sp, z.data(),
+                            pos.data(), hd.N, 0u, out));
+  for (int d = 0; d < 3; ++d) (*out)->ranks[d] = hd.ranks[d];
+  return RSD_OK;
+}
+
+// ---------------------------------------------------------------- timing
+rsd_status rsd_context_set_timing(rsd_context* ctx, int32_t enable) {
+  clear_error();
+  RSD_CHECK(ctx != nullptr, RSD_E_INVALID, "ctx is NULL");
+  RSD_HIP(hipSetDevice(ctx->device));
+  RSD_TRY(ctx->collect_timers());
+  ctx->timing = enable != 0;
+  ctx->ktime.clear();
+  return RSD_OK;
+}
+
+rsd_status rsd_kernel_time(rsd_context* ctx, const char* kernel, int64_t* launches, double* total_ms) {
+  clear_error();
+  RSD_CHECK(ctx != nullptr && kernel != nullptr, RSD_E_INVALID, "NULL argument");
+  RSD_HIP(hipSetDevice(ctx->device));
+  RSD_TRY(ctx->collect_timers());
+  auto it = ctx->ktime.find(kernel);
+  if (launches) *launches = it == ctx->ktime.end() ? 0 : it->second.first;
+  if (total_ms) *total_ms = it == ctx->ktime.end() ? 0.0 : it->second.second;
+  return RSD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// Internal declarations of librsdock (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "rsdock.h"
+
+namespace rsd {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define RSD_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t rsd_e_ = (call);                                                         \
+    if (rsd_e_ != hipSuccess) {                                                         \
+      ::rsd::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(rsd_e_),       \
+                       __FILE__, __LINE__);                                             \
+      return RSD_E_HIP;                                                                 \
+    }                                                                                   \
+  } while (0)
+
+#define RSD_CHECK(cond, code, ...)     \
+  do {                                 \
+    if (!(cond)) {                     \
+      ::rsd::set_error(__VA_ARGS__);   \
+      return (code);                   \
+    }                                  \
+  } while (0)
+
+#define RSD_TRY(expr)                  \
+  do {                                 \
+    rsd_status rsd_s_ = (expr);        \
+    if (rsd_s_ != RSD_OK) return rsd_s_; \
+  } while (0)
+
+// ---------------------------------------------------------------- layout constants
+// Factor matrices are stored column-chunked: for mode d and chunk c the block
+// F[d][c] is an n x kChunk row-major array (row i at offset i*kChunk), so the
+// kChunk doubles of one row are one contiguous 512-byte segment and rows i and
+// i+1 of a chunk are adjacent.  Columns beyond R are zero.
+constexpr int kChunk = 64;
+constexpr int kMaxTerms = 64;   // M + 1 <= 64
+constexpr int kMaxLigand = 896;   // keeps one wave's LDS within 64 KB
+
+struct ShortTable {            // short-range Gaussians (terms k >= K_long)
+  int S;
+  double t2[kMaxTerms];        // t_k^2
+  double w[kMaxTerms];         // folded weights
+};
+
+struct CellGrid {              // uniform cells over the box [-b, b]^3, x fastest
+  double origin;               // -b (same on every axis)
+  double edge;
+  double inv_edge;
+  int dim;                     // cells per axis
+  int ncells;                  // dim^3
+};
+
+// ---------------------------------------------------------------- context
+struct KernelTimer {
+  std::string name;
+  hipEvent_t start, stop;
+};
+
+struct Context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;           // 0 = unlimited
+  size_t in_use = 0;
+  // growable scratch owned by the context
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool timing = false;
+  std::vector<KernelTimer> pending;
+  std::map<std::string, std::pair<int64_t, double>> ktime;
+
+  rsd_status dev_alloc(void** p, size_t bytes);
+  void dev_free(void* p, size_t bytes);
+  rsd_status workspace(size_t bytes, void** out);
+  rsd_status timer_begin(const char* name, KernelTimer* t);
+  rsd_status timer_end(KernelTimer* t);
+  rsd_status collect_timers();
+};
+
+// RAII-free helper to bracket a kernel launch with timing events.
+#define RSD_TIMED_LAUNCH(ctx, name, launch)                        \
+  do {                                                             \
+    ::rsd::KernelTimer rsd_kt_;                                    \
+    if ((ctx)->timing) RSD_TRY((ctx)->timer_begin((name), &rsd_kt_)); \
+    launch;                                                        \
+    RSD_HIP(hipGetLastError());                                    \
+    if ((ctx)->timing) RSD_TRY((ctx)->timer_end(&rsd_kt_));        \
+  } while (0)
+
+// ---------------------------------------------------------------- tensor
+struct Tensor {
+  Context* ctx = nullptr;
+  int n = 0;
+  double b = 0, h = 0, X0 = 0, inv_h = 0;
+  int64_t R = 0;
+  int nchunk = 0;              // ceil(R / kChunk); the kernels handle nchunk == 0
+  int ranks[3] = {0, 0, 0};
+  rsd_sinc_params sp{};
+  double* F = nullptr;         // 3 * nchunk * n * kChunk doubles
+  size_t F_bytes = 0;
+  int64_t N = 0;
+  double4* atoms = nullptr;    // cell-sorted (x, y, z, charge)
+  int* cell_start = nullptr;   // ncells + 1
+  size_t cell_bytes = 0;
+  CellGrid cells{};
+  double* short_tab = nullptr; // device copy of ShortTable t2[], w[] (2 * kMaxTerms)
+  ShortTable shrt{};
+  std::vector<double> host_charges;    // kept for save/load
+  std::vector<double> host_positions;
+  size_t bytes() const;
+};
+
+// sinc table (host): t_k and folded w_k, k = 0..M
+void sinc_table(const rsd_sinc_params& sp, double* t, double* w);
+
+// grid constants with the fixed operation order shared by every component
+inline void grid_constants(int n, double b, double* h, double* X0, double* inv_h) {
+  *h = (2.0 * b) / (double)n;
+  *X0 = -b + *h;
+  *inv_h = 1.0 / *h;
+}
+
+// ---------------------------------------------------------------- launchers (device work)
+rsd_status build_cells(Context* ctx, Tensor* t, const double* d_charges, const double* d_positions);
+
+struct ScoreIO {
+  const double* lig_charges;   // device
+  const double* lig_positions; // device
+  int L;
+  const double* quats;         // device
+  const double* trans;         // device
+  int64_t P;
+  double vdw_min;
+  double* E;
+  double* El;                  // may be null
+  uint8_t* flags;
+  int32_t* counts;
+  double* grads;               // may be null
+};
+rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io);
+
+// rank reduction on the device (build.hip)
+rsd_status build_factors(Context* ctx, Tensor* t, const double* d_charges, const double* d_positions);
+
+}  // namespace rsd
+
+struct rsd_context : rsd::Context {};
+struct rsd_tensor : rsd::Tensor {};

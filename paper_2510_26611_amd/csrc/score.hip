@@ -1,0 +1,464 @@
+// Pose scoring kernels for gfx950 (wave64).
+//
+// Per pose (one wavefront):
+//   A1  pose transform y_l = R(q) (x_l - c) + t about the geometric centre (eq. 3.14);
+//   A2  long-range potential at every ligand atom from the rank-R canonical tensor
+//       (Lemma 3.3, eq. 3.10): per mode the two factor rows around the point are
+//       linearly interpolated and the R products are summed; lanes own columns, so
+//       every factor-row load is one contiguous 512-byte segment;
+//   A3  short-range potential (Def. 2.1): protein atoms within reach of the ligand
+//       are taken from the cell list row by row; lanes own protein atoms, loop over
+//       ligand atoms, and push the pairs with d^2 < r_c^2 into a per-wave LDS queue
+//       that is drained 64 pairs at a time, so the Gaussians are evaluated by full
+//       wavefronts however sparse the hits are;
+//   A4  vdW flag (min d^2 >= sigma^2, eq. 3.14) and the pair count from the same
+//       traversal;
+//   A5  one wavefront reduction of the energy (and gradient) partials.
+//
+// Exactness.  The library is compiled with -ffp-contract=off: every a*b+c below
+// rounds twice unless written as fma().  The transform, the grid coordinate and
+// d^2 are written in one fixed operation order (see the comments), so the values
+// that decide flags, counts and grid rows are reproducible bit for bit by any
+// IEEE FP64 implementation that follows the same order.
+#include "internal.h"
+
+namespace rsd {
+namespace {
+
+constexpr int kQueue = 128;   // per-wave ring of short-range pairs (two drains deep)
+
+struct PairE {                // queued short-range pair (energy only)
+  double d2, zz;
+};
+struct PairG {                // queued pair with what the gradient needs
+  double d2, zz, dx, dy, dz;
+  int l, pad;
+};
+
+struct ScoreParams {
+  const double* __restrict__ F;
+  int64_t mode_stride;        // nchunk * n * kChunk
+  int64_t chunk_stride;       // n * kChunk
+  int n, nchunk;
+  double X0, inv_h, smax;     // smax = n - 1
+  const double4* __restrict__ atoms;
+  const int* __restrict__ cell_start;
+  CellGrid cells;
+  int64_t N;
+  const double* __restrict__ t2;   // short-range t_k^2
+  const double* __restrict__ w;    // short-range weights
+  int S;
+  double rc2, sig2, reach;          // reach = max(r_cut, vdw_min)
+  const double4* __restrict__ lig;  // centred ligand (u_x, u_y, u_z, zeta)
+  const double* __restrict__ rlig;  // max_l |u_l|
+  int L;
+  const double* __restrict__ quats;
+  const double* __restrict__ trans;
+  int64_t P;
+  double* __restrict__ E;
+  double* __restrict__ El;
+  uint8_t* __restrict__ flags;
+  int32_t* __restrict__ counts;
+  double* __restrict__ grads;
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ int lane_prefix(uint64_t mask) {   // set bits of mask below this lane
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+// Cell coordinate floor(v) clamped to [0, dim-1]; clamping happens in FP64 so that huge or
+// non-finite v never reaches an out-of-range float-to-int conversion.
+__device__ __forceinline__ int cell_floor(double v, int dim) {
+  if (!(v >= 0.0)) return 0;
+  if (v >= (double)(dim - 1)) return dim - 1;
+  return (int)v;
+}
+
+// Geometric centre c = (((0 + x_0) + x_1) + ...) / L and centred coordinates u_l = x_l - c;
+// also max |u_l|.  One wavefront.
+__global__ __launch_bounds__(64) void k_ligand_prep(const double* __restrict__ pos,
+                                                    const double* __restrict__ zeta, int L,
+                                                    double4* __restrict__ out, double* __restrict__ rlig) {
+  __shared__ double c[3];
+  const int lane = threadIdx.x;
+  if (lane == 0) {
+    double cx = 0.0, cy = 0.0, cz = 0.0;
+    for (int l = 0; l < L; ++l) {
+      cx = cx + pos[3 * l + 0];
+      cy = cy + pos[3 * l + 1];
+      cz = cz + pos[3 * l + 2];
+    }
+    const double dl = (double)L;
+    c[0] = cx / dl;
+    c[1] = cy / dl;
+    c[2] = cz / dl;
+  }
+  __syncthreads();
+  double r2max = 0.0;
+  for (int l = lane; l < L; l += 64) {
+    const double ux = pos[3 * l + 0] - c[0];
+    const double uy = pos[3 * l + 1] - c[1];
+    const double uz = pos[3 * l + 2] - c[2];
+    out[l] = make_double4(ux, uy, uz, zeta[l]);
+    r2max = fmax(r2max, (ux * ux + uy * uy) + uz * uz);
+  }
+  r2max = wave_min(-r2max);
+  if (lane == 0) rlig[0] = sqrt(-r2max);
+}
+
+template <bool GRAD>
+struct PairT;
+template <>
+struct PairT<false> {
+  using type = PairE;
+};
+template <>
+struct PairT<true> {
+  using type = PairG;
+};
+
+template <bool GRAD>
+__global__ __launch_bounds__(256) void k_score(const ScoreParams a) {
+  using Pair = typename PairT<GRAD>::type;
+  extern __shared__ double4 smem[];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int W = blockDim.x >> 6;
+  const int L = a.L;
+  double4* s_lig = smem;
+  double4* s_y = smem + L + (size_t)wv * L;                          // (y_0, y_1, y_2, zeta)
+  char* tail = (char*)(smem + (size_t)L * (1 + W));
+  Pair* q = (Pair*)(tail) + (size_t)wv * kQueue;
+  int* rowoff = (int*)(tail + sizeof(Pair) * kQueue * W) + wv * 128;
+  int* rowstart = rowoff + 64;
+
+  for (int i = threadIdx.x; i < L; i += blockDim.x) s_lig[i] = a.lig[i];
+  __syncthreads();
+  const int64_t p = (int64_t)blockIdx.x * W + wv;
+  if (p >= a.P) return;    // whole wavefront leaves; no block barrier follows
+
+  // ---- pose input and validity: |q|^2 = ((w*w + x*x) + y*y) + z*z
+  const double qw = a.quats[4 * p + 0], qx = a.quats[4 * p + 1];
+  const double qy = a.quats[4 * p + 2], qz = a.quats[4 * p + 3];
+  const double tx = a.trans[3 * p + 0], ty = a.trans[3 * p + 1], tz = a.trans[3 * p + 2];
+  const double qq = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+  const bool finite = isfinite(qw) && isfinite(qx) && isfinite(qy) && isfinite(qz) &&
+                      isfinite(tx) && isfinite(ty) && isfinite(tz);
+  if (!(finite && fabs(qq - 1.0) <= 1e-12)) {
+    if (lane == 0) {
+      a.E[p] = __builtin_nan("");
+      if (a.El) a.El[p] = __builtin_nan("");
+      a.flags[p] = (uint8_t)RSD_FLAG_INVALID;
+      a.counts[p] = 0;
+      if (GRAD) {
+        for (int k = 0; k < 6; ++k) a.grads[6 * p + k] = __builtin_nan("");
+      }
+    }
+    return;
+  }
+  // ---- A1: rotation matrix rows, each entry in this fixed operation order
+  const double R00 = 1.0 - 2.0 * (qy * qy + qz * qz), R01 = 2.0 * (qx * qy - qw * qz), R02 = 2.0 * (qx * qz + qw * qy);
+  const double R10 = 2.0 * (qx * qy + qw * qz), R11 = 1.0 - 2.0 * (qx * qx + qz * qz), R12 = 2.0 * (qy * qz - qw * qx);
+  const double R20 = 2.0 * (qx * qz - qw * qy), R21 = 2.0 * (qy * qz + qw * qx), R22 = 1.0 - 2.0 * (qx * qx + qy * qy);
+
+  bool out_of_domain = false;
+  for (int l = lane; l < L; l += 64) {
+    const double4 u = s_lig[l];
+    const double y0 = ((R00 * u.x + R01 * u.y) + R02 * u.z) + tx;
+    const double y1 = ((R10 * u.x + R11 * u.y) + R12 * u.z) + ty;
+    const double y2 = ((R20 * u.x + R21 * u.y) + R22 * u.z) + tz;
+    s_y[l] = make_double4(y0, y1, y2, u.w);
+    const double s0 = (y0 - a.X0) * a.inv_h, s1 = (y1 - a.X0) * a.inv_h, s2 = (y2 - a.X0) * a.inv_h;
+    const bool in = (s0 >= 0.0 && s0 <= a.smax) && (s1 >= 0.0 && s1 <= a.smax) && (s2 >= 0.0 && s2 <= a.smax);
+    out_of_domain |= !in;
+  }
+  const bool dom = __ballot(out_of_domain) == 0ull;
+  wave_sync();
+
+  double eL = 0.0, eS = 0.0;
+  double gt0 = 0.0, gt1 = 0.0, gt2 = 0.0, gw0 = 0.0, gw1 = 0.0, gw2 = 0.0;
+
+  // ---- A2: long-range, lanes own factor columns
+  if (dom && a.nchunk > 0) {
+    const int nm2 = a.n - 2;
+    const int64_t cs = a.chunk_stride;
+    for (int l = 0; l < L; ++l) {
+      const double4 y = s_y[l];
+      const double s0 = (y.x - a.X0) * a.inv_h, s1 = (y.y - a.X0) * a.inv_h, s2 = (y.z - a.X0) * a.inv_h;
+      const int i0 = min((int)floor(s0), nm2), i1 = min((int)floor(s1), nm2), i2 = min((int)floor(s2), nm2);
+      const double f0 = s0 - (double)i0, f1 = s1 - (double)i1, f2 = s2 - (double)i2;
+      const double* p0 = a.F + (int64_t)i0 * kChunk + lane;
+      const double* p1 = a.F + a.mode_stride + (int64_t)i1 * kChunk + lane;
+      const double* p2 = a.F + 2 * a.mode_stride + (int64_t)i2 * kChunk + lane;
+      double part = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+      int c = 0;
+      for (; c + 4 <= a.nchunk; c += 4) {
+        double A0[4], B0[4], A1[4], B1[4], A2[4], B2[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          A0[u] = p0[u * cs]; B0[u] = p0[u * cs + kChunk];
+          A1[u] = p1[u * cs]; B1[u] = p1[u * cs + kChunk];
+          A2[u] = p2[u * cs]; B2[u] = p2[u * cs + kChunk];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double d0 = B0[u] - A0[u], d1 = B1[u] - A1[u], d2 = B2[u] - A2[u];
+          const double l0 = fma(f0, d0, A0[u]), l1 = fma(f1, d1, A1[u]), l2 = fma(f2, d2, A2[u]);
+          const double l01 = l0 * l1;
+          part = fma(l01, l2, part);
+          if (GRAD) {
+            g0 = fma(d0 * l1, l2, g0);
+            g1 = fma(l0 * d1, l2, g1);
+            g2 = fma(l01, d2, g2);
+          }
+        }
+        p0 += 4 * cs; p1 += 4 * cs; p2 += 4 * cs;
+      }
+      for (; c < a.nchunk; ++c) {
+        const double A0 = p0[0], B0 = p0[kChunk], A1 = p1[0], B1 = p1[kChunk], A2 = p2[0], B2 = p2[kChunk];
+        const double d0 = B0 - A0, d1 = B1 - A1, d2 = B2 - A2;
+        const double l0 = fma(f0, d0, A0), l1 = fma(f1, d1, A1), l2 = fma(f2, d2, A2);
+        const double l01 = l0 * l1;
+        part = fma(l01, l2, part);
+        if (GRAD) {
+          g0 = fma(d0 * l1, l2, g0);
+          g1 = fma(l0 * d1, l2, g1);
+          g2 = fma(l01, d2, g2);
+        }
+        p0 += cs; p1 += cs; p2 += cs;
+      }
+      eL = fma(y.w, part, eL);
+      if (GRAD) {
+        const double zh = y.w * a.inv_h;
+        const double v0 = y.x - tx, v1 = y.y - ty, v2 = y.z - tz;   // R u_l
+        const double G0 = zh * g0, G1 = zh * g1, G2 = zh * g2;
+        gt0 += G0; gt1 += G1; gt2 += G2;
+        gw0 += v1 * G2 - v2 * G1;
+        gw1 += v2 * G0 - v0 * G2;
+        gw2 += v0 * G1 - v1 * G0;
+      }
+    }
+  }
+
+  // ---- A3 + A4: short-range sum, pair count and minimum distance over the cell list
+  int cnt = 0;
+  double mind = __builtin_inf();
+  if (a.N > 0) {
+    const CellGrid g = a.cells;
+    const double reach = a.rlig[0] + a.reach;
+    const double Rc = reach * (1.0 + 1e-9) + 1e-9;     // conservative search radius about t
+    const double Rc2 = Rc * Rc;
+    const int cy0 = cell_floor((ty - Rc - g.origin) * g.inv_edge, g.dim);
+    const int cy1 = cell_floor((ty + Rc - g.origin) * g.inv_edge, g.dim);
+    const int cz0 = cell_floor((tz - Rc - g.origin) * g.inv_edge, g.dim);
+    const int cz1 = cell_floor((tz + Rc - g.origin) * g.inv_edge, g.dim);
+    const int ny = cy1 - cy0 + 1;
+    const int nrows = ny * (cz1 - cz0 + 1);
+    int qh = 0, qt = 0;   // ring head / tail (wave-uniform)
+
+    auto drain = [&](int m) {   // evaluate queued pairs [qh, qh + m), m <= 64
+      wave_sync();
+      if (lane < m) {
+        const Pair e = q[(qh + lane) & (kQueue - 1)];
+        double gs = 0.0, dg = 0.0;
+        for (int k = 0; k < a.S; ++k) {
+          const double t2 = a.t2[k];
+          const double ex = exp(-(t2 * e.d2));
+          gs = fma(a.w[k], ex, gs);
+          if (GRAD) dg = fma(a.w[k] * (-2.0 * t2), ex, dg);
+        }
+        eS = fma(e.zz, gs, eS);
+        if constexpr (GRAD) {
+          const double cc = e.zz * dg;
+          const double G0 = cc * e.dx, G1 = cc * e.dy, G2 = cc * e.dz;
+          const double4 y = s_y[e.l];
+          const double v0 = y.x - tx, v1 = y.y - ty, v2 = y.z - tz;
+          gt0 += G0; gt1 += G1; gt2 += G2;
+          gw0 += v1 * G2 - v2 * G1;
+          gw1 += v2 * G0 - v0 * G2;
+          gw2 += v0 * G1 - v1 * G0;
+        }
+      }
+      qh += m;
+      wave_sync();
+    };
+
+    for (int rb = 0; rb < nrows; rb += 64) {
+      const int r = rb + lane;
+      int seg_start = 0, seg_len = 0;
+      if (r < nrows) {
+        const int cy = cy0 + r % ny, cz = cz0 + r / ny;
+        const double ylo = g.origin + cy * g.edge, yhi = ylo + g.edge;
+        const double zlo = g.origin + cz * g.edge, zhi = zlo + g.edge;
+        const double dy = fmax(fmax(ylo - ty, ty - yhi), 0.0);
+        const double dz = fmax(fmax(zlo - tz, tz - zhi), 0.0);
+        const double rem = Rc2 - (dy * dy + dz * dz);
+        if (rem >= 0.0) {
+          const double hw = sqrt(rem);
+          const int cx0 = cell_floor((tx - hw - g.origin) * g.inv_edge, g.dim);
+          const int cx1 = cell_floor((tx + hw - g.origin) * g.inv_edge, g.dim);
+          const int base = (cz * g.dim + cy) * g.dim;
+          seg_start = a.cell_start[base + cx0];
+          seg_len = a.cell_start[base + cx1 + 1] - seg_start;
+        }
+      }
+      // inclusive scan of the segment lengths across the wavefront
+      int incl = seg_len;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+      }
+      const int total = __shfl(incl, 63, 64);
+      rowoff[lane] = incl - seg_len;
+      rowstart[lane] = seg_start;
+      wave_sync();
+      for (int cb = 0; cb < total; cb += 64) {
+        const int k = cb + lane;
+        const bool act = k < total;
+        double4 at = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (act) {
+          int lo = 0, hi = 63;               // last row whose offset is <= k
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rowoff[mid] <= k) lo = mid; else hi = mid - 1;
+          }
+          at = a.atoms[rowstart[lo] + (k - rowoff[lo])];
+        }
+        for (int l = 0; l < L; ++l) {
+          const double4 y = s_y[l];
+          const double dx = y.x - at.x, dy = y.y - at.y, dz = y.z - at.z;
+          const double d2 = (dx * dx + dy * dy) + dz * dz;     // ((dx^2 + dy^2) + dz^2), no fma
+          const bool hit = act && (d2 < a.rc2);
+          if (act) mind = fmin(mind, d2);
+          const uint64_t m = __ballot(hit);
+          if (m != 0ull) {
+            if (hit) {
+              Pair& e = q[(qt + lane_prefix(m)) & (kQueue - 1)];
+              e.d2 = d2;
+              e.zz = at.w * y.w;
+              if constexpr (GRAD) {
+                e.dx = dx; e.dy = dy; e.dz = dz; e.l = l;
+              }
+              ++cnt;
+            }
+            qt += __popcll(m);
+            if (qt - qh >= 64) drain(64);
+          }
+        }
+      }
+      wave_sync();
+    }
+    if (qt > qh) drain(qt - qh);
+  }
+
+  // ---- A5: reductions and output
+  eL = wave_sum(eL);
+  eS = wave_sum(eS);
+  cnt = wave_sum_i(cnt);
+  mind = wave_min(mind);
+  if (GRAD) {
+    gt0 = wave_sum(gt0); gt1 = wave_sum(gt1); gt2 = wave_sum(gt2);
+    gw0 = wave_sum(gw0); gw1 = wave_sum(gw1); gw2 = wave_sum(gw2);
+  }
+  if (lane == 0) {
+    const double nan = __builtin_nan("");
+    a.E[p] = dom ? eL + eS : nan;
+    if (a.El) a.El[p] = dom ? eL : nan;
+    a.flags[p] = (uint8_t)(dom ? (RSD_FLAG_IN_DOMAIN | (mind >= a.sig2 ? RSD_FLAG_ACCEPT : 0u)) : 0u);
+    a.counts[p] = cnt;
+    if (GRAD) {
+      double* gp = a.grads + 6 * p;
+      gp[0] = dom ? gt0 : nan; gp[1] = dom ? gt1 : nan; gp[2] = dom ? gt2 : nan;
+      gp[3] = dom ? gw0 : nan; gp[4] = dom ? gw1 : nan; gp[5] = dom ? gw2 : nan;
+    }
+  }
+}
+
+}  // namespace
+
+rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
+  if (io.P == 0) return RSD_OK;
+  const bool grad = io.grads != nullptr;
+  const int L = io.L;
+  // workspace: centred ligand (L double4) + max radius
+  void* ws = nullptr;
+  RSD_TRY(ctx->workspace(sizeof(double4) * (size_t)L + 256, &ws));
+  double4* lig = (double4*)ws;
+  double* rlig = (double*)(lig + L);
+  hipStream_t s = ctx->stream;
+  RSD_TIMED_LAUNCH(ctx, "ligand_prep",
+                   (k_ligand_prep<<<1, 64, 0, s>>>(io.lig_positions, io.lig_charges, L, lig, rlig)));
+
+  ScoreParams a{};
+  a.F = t->F;
+  a.chunk_stride = (int64_t)t->n * kChunk;
+  a.mode_stride = (int64_t)t->nchunk * a.chunk_stride;
+  a.n = t->n;
+  a.nchunk = t->nchunk;
+  a.X0 = t->X0;
+  a.inv_h = t->inv_h;
+  a.smax = (double)(t->n - 1);
+  a.atoms = t->atoms;
+  a.cell_start = t->cell_start;
+  a.cells = t->cells;
+  a.N = t->N;
+  a.t2 = t->short_tab;
+  a.w = t->short_tab + kMaxTerms;
+  a.S = t->shrt.S;
+  a.rc2 = t->sp.r_cut * t->sp.r_cut;
+  a.sig2 = io.vdw_min * io.vdw_min;
+  a.reach = t->sp.r_cut > io.vdw_min ? t->sp.r_cut : io.vdw_min;
+  a.lig = lig;
+  a.rlig = rlig;
+  a.L = L;
+  a.quats = io.quats;
+  a.trans = io.trans;
+  a.P = io.P;
+  a.E = io.E;
+  a.El = io.El;
+  a.flags = io.flags;
+  a.counts = io.counts;
+  a.grads = io.grads;
+
+  const size_t pair_bytes = grad ? sizeof(PairG) : sizeof(PairE);
+  int W = 4;
+  auto lds = [&](int w) {
+    return sizeof(double4) * (size_t)L * (1 + w) + (size_t)w * (pair_bytes * kQueue + 128 * sizeof(int));
+  };
+  while (W > 1 && lds(W) > 64 * 1024) W >>= 1;
+  RSD_CHECK(lds(W) <= 64 * 1024, RSD_E_UNSUPPORTED, "ligand of %d atoms needs too much LDS", L);
+  const int64_t blocks = (io.P + W - 1) / W;
+  RSD_CHECK(blocks <= 0x7fffffffLL, RSD_E_UNSUPPORTED, "too many poses in one call");
+  if (grad) {
+    RSD_TIMED_LAUNCH(ctx, "score",
+                     (k_score<true><<<(unsigned)blocks, 64 * W, lds(W), s>>>(a)));
+  } else {
+    RSD_TIMED_LAUNCH(ctx, "score",
+                     (k_score<false><<<(unsigned)blocks, 64 * W, lds(W), s>>>(a)));
+  }
+  return RSD_OK;
+}
+
+}  // namespace rsd

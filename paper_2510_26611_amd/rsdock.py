@@ -1,0 +1,217 @@
+"""Python binding of librsdock: argument marshalling only; all work runs in the HIP library.
+
+Arrays may be numpy arrays (host pointers: the call is synchronous and outputs come
+back as numpy arrays) or torch CUDA tensors (device pointers: work is enqueued on
+the context's stream, outputs are torch CUDA tensors).  Names follow the C ABI in
+include/rsdock.h: build_rs_tensor (Algorithm TEP) and score_poses (Algorithm PLIE
+with the short-range term and the van der Waals flag).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib
+from ._lib import FLAG_ACCEPT, FLAG_IN_DOMAIN, FLAG_INVALID, RSD_DEVICE_PTRS, SincParams  # noqa: F401
+
+
+class RsdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"librsdock error {code}: {msg}")
+        self.code = code
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise RsdError(status, _lib.lib().rsd_last_error().decode(errors="replace"))
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _arr(x, dtype=np.float64):
+    """(pointer, keepalive, is_device) for a numpy array or torch tensor."""
+    if _is_torch(x):
+        import torch
+        want = {np.float64: torch.float64, np.uint8: torch.uint8, np.int32: torch.int32}[dtype]
+        if x.dtype != want or not x.is_contiguous():
+            raise TypeError(f"expected a contiguous torch.{want} tensor")
+        return C.c_void_p(x.data_ptr()), x, bool(x.is_cuda)
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return a.ctypes.data_as(C.c_void_p), a, False
+
+
+@dataclass
+class Sinc:
+    """Quadrature (eq. 2.2), range split (eq. 2.4), short-range cutoff and truncation eps."""
+    M: int
+    h_M: float
+    L_s: float
+    K_long: int
+    r_cut: float
+    eps: float
+
+    def c(self) -> SincParams:
+        return SincParams(int(self.M), int(self.K_long), float(self.h_M), float(self.L_s),
+                          float(self.r_cut), float(self.eps))
+
+    @classmethod
+    def from_config(cls, cfg) -> "Sinc":
+        return cls(cfg.M, cfg.h_M, cfg.L_s, cfg.K_long, cfg.r_cut, cfg.eps)
+
+
+class Context:
+    """rsd_context: a device, the stream work is enqueued on, and an HBM budget."""
+
+    def __init__(self, device: int = 0, stream=None, hbm_budget: int = 0):
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    stream = torch.cuda.current_stream(device).cuda_stream
+            except ImportError:
+                stream = None
+        h = C.c_void_p()
+        _check(_lib.lib().rsd_context_create(int(device), C.c_void_p(stream or 0), int(hbm_budget), C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def set_stream(self, stream) -> None:
+        _check(_lib.lib().rsd_context_set_stream(self.handle, C.c_void_p(stream or 0)))
+
+    def memory(self):
+        used, budget = C.c_size_t(), C.c_size_t()
+        _check(_lib.lib().rsd_context_memory(self.handle, C.byref(used), C.byref(budget)))
+        return used.value, budget.value
+
+    def set_timing(self, enable: bool) -> None:
+        _check(_lib.lib().rsd_context_set_timing(self.handle, int(bool(enable))))
+
+    def kernel_time(self, name: str):
+        n, ms = C.c_int64(), C.c_double()
+        _check(_lib.lib().rsd_kernel_time(self.handle, name.encode(), C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            _lib.lib().rsd_context_free(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Tensor:
+    """rsd_tensor: a resident RS tensor (canonical factors + protein cell list)."""
+
+    def __init__(self, ctx: Context, handle: C.c_void_p):
+        self.ctx = ctx
+        self.handle = handle
+
+    def query(self):
+        n, R, ranks, nbytes = C.c_int32(), C.c_int64(), (C.c_int32 * 3)(), C.c_size_t()
+        _check(_lib.lib().rsd_tensor_query(self.handle, C.byref(n), C.byref(R), ranks, C.byref(nbytes)))
+        return dict(n=n.value, R=R.value, ranks=tuple(ranks), bytes=nbytes.value)
+
+    def export(self):
+        info = self.query()
+        F = [np.empty((info["n"], info["R"])) for _ in range(3)]
+        _check(_lib.lib().rsd_tensor_export(self.handle, *[f.ctypes.data_as(C.c_void_p) for f in F]))
+        return F
+
+    def save(self, path: str) -> None:
+        _check(_lib.lib().rsd_tensor_save(self.handle, str(path).encode()))
+
+    def free(self) -> None:
+        if getattr(self, "handle", None):
+            _lib.lib().rsd_tensor_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _protein_args(charges, positions):
+    zp, zk, zdev = _arr(charges)
+    xp, xk, xdev = _arr(positions)
+    if zdev != xdev:
+        raise TypeError("charges and positions must both be host or both be device arrays")
+    N = int(zk.shape[0]) if hasattr(zk, "shape") else len(zk)
+    return zp, xp, N, (zk, xk), RSD_DEVICE_PTRS if zdev else 0
+
+
+def build_rs_tensor(ctx: Context, charges, positions, n: int, b: float, sinc: Sinc) -> Tensor:
+    """rsd_build_rs_tensor: Algorithm TEP on the device."""
+    zp, xp, N, keep, flags = _protein_args(charges, positions)
+    out = C.c_void_p()
+    sp = sinc.c()
+    _check(_lib.lib().rsd_build_rs_tensor(ctx.handle, zp, xp, N, int(n), float(b), C.byref(sp), flags,
+                                          C.byref(out)))
+    return Tensor(ctx, out)
+
+
+def tensor_import(ctx: Context, F, n: int, b: float, sinc: Sinc, charges, positions) -> Tensor:
+    """rsd_tensor_import: resident tensor from given n x R factors (host arrays)."""
+    Fs = [np.ascontiguousarray(f, dtype=np.float64) for f in F]
+    R = int(Fs[0].shape[1]) if Fs[0].ndim == 2 else 0
+    zp, xp, N, keep, flags = _protein_args(charges, positions)
+    if flags:
+        raise TypeError("tensor_import from Python takes host arrays")
+    out = C.c_void_p()
+    sp = sinc.c()
+    _check(_lib.lib().rsd_tensor_import(ctx.handle, *[f.ctypes.data_as(C.c_void_p) for f in Fs], R, int(n),
+                                        float(b), C.byref(sp), zp, xp, N, 0, C.byref(out)))
+    return Tensor(ctx, out)
+
+
+def tensor_load(ctx: Context, path: str) -> Tensor:
+    out = C.c_void_p()
+    _check(_lib.lib().rsd_tensor_load(ctx.handle, str(path).encode(), C.byref(out)))
+    return Tensor(ctx, out)
+
+
+def score_poses(ctx: Context, tensor: Tensor, lig_charges, lig_positions, quats, trans, vdw_min: float,
+                grads: bool = False, energies_long: bool = False, out: dict | None = None) -> dict:
+    """rsd_score_poses.  Returns dict(E, flags, counts[, E_long][, grads])."""
+    zp, zk, zdev = _arr(lig_charges)
+    lp, lk, ldev = _arr(lig_positions)
+    qp, qk, qdev = _arr(quats)
+    tp, tk, tdev = _arr(trans)
+    if not (zdev == ldev == qdev == tdev):
+        raise TypeError("all inputs must be host arrays or all device tensors")
+    L = int(zk.shape[0])
+    P = int(qk.shape[0])
+    if out is None:
+        if qdev:
+            import torch
+            dev = qk.device
+            out = dict(E=torch.empty(P, dtype=torch.float64, device=dev),
+                       flags=torch.empty(P, dtype=torch.uint8, device=dev),
+                       counts=torch.empty(P, dtype=torch.int32, device=dev))
+            if energies_long:
+                out["E_long"] = torch.empty(P, dtype=torch.float64, device=dev)
+            if grads:
+                out["grads"] = torch.empty((P, 6), dtype=torch.float64, device=dev)
+        else:
+            out = dict(E=np.empty(P), flags=np.empty(P, dtype=np.uint8), counts=np.empty(P, dtype=np.int32))
+            if energies_long:
+                out["E_long"] = np.empty(P)
+            if grads:
+                out["grads"] = np.empty((P, 6))
+    ep = _arr(out["E"])[0]
+    fp = _arr(out["flags"], np.uint8)[0]
+    cp = _arr(out["counts"], np.int32)[0]
+    elp = _arr(out["E_long"])[0] if "E_long" in out else None
+    gp = _arr(out["grads"])[0] if "grads" in out else None
+    _check(_lib.lib().rsd_score_poses(ctx.handle, tensor.handle, zp, lp, L, qp, tp, P, float(vdw_min),
+                                      RSD_DEVICE_PTRS if qdev else 0, ep, elp, fp, cp, gp))
+    return out
