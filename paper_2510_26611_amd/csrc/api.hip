@@ -5,6 +5,8 @@
 #include <cstring>
 #include <new>
 
+#include <rocblas/rocblas.h>
+
 #include "internal.h"
 
 namespace rsd {
@@ -192,6 +194,7 @@ static void tensor_release(Tensor* t) {
   Context* c = t->ctx;
   if (c) {
     (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);   // scoring work queued on the stream may still read the tensor
     c->dev_free(t->F, t->F_bytes);
     c->dev_free(t->atoms, sizeof(double4) * (size_t)(t->N > 0 ? t->N : 1));
     c->dev_free(t->cell_start, t->cell_bytes);
@@ -303,6 +306,7 @@ void rsd_context_free(rsd_context* ctx) {
     (void)hipEventDestroy(t.stop);
   }
   ctx->dev_free(ctx->ws, ctx->ws_bytes);
+  if (ctx->blas) rocblas_destroy_handle((rocblas_handle)ctx->blas);
   delete ctx;
 }
 

@@ -1,12 +1,558 @@
-// Rank reduction of the long-range sum on the device (Algorithm TEP step 4).
+// Rank reduction of the long-range sum on the device (Algorithm TEP, steps 3-5).
+//
+// The collective long-range potential of eq. 2.6 is a canonical tensor of rank
+// N*K_long whose mode-d factor columns are the 1-D Gaussians
+// g_{k,m,d}[j] = exp(-t_k^2 (X_j - x_{m,d})^2).  Its rank is cut by the
+// canonical -> Tucker -> canonical transform with the reduced HOSVD (RHOSVD):
+//   1. per mode, the side matrix A_d (n x N*K_long) with unit-norm columns,
+//      weights xi_{m,k} = z_m w_k prod_d ||g_{k,m,d}||;
+//   2. the Gram matrix A_d A_d^T (n x n) on FP64 matrix cores (the dense step),
+//      its dominant eigenvectors U_d (eigenvalues >= eps^2 * largest, i.e. singular
+//      values >= eps * largest);
+//   3. the projections B_d = U_d^T A_d and the Tucker core
+//      beta = sum_c xi_c B_1[:,c] x B_2[:,c] x B_3[:,c], as one matrix product whose
+//      left operand is the Khatri-Rao product of B_1 and B_2 formed in LDS;
+//   4. a batched SVD of the core's mode-3 slices; kept terms (singular value >= eps
+//      times the largest over all slices) become canonical terms, assembled as
+//      F_d = U_d V_d directly into the column-chunked layout the scorer reads.
+// Library calls: rocSOLVER for the symmetric eigenproblem and the small slice SVDs.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 #include "internal.h"
 
 namespace rsd {
+namespace {
 
-rsd_status build_factors(Context* ctx, Tensor* t, const double* d_charges, const double* d_positions) {
-  (void)ctx; (void)t; (void)d_charges; (void)d_positions;
-  set_error("rsd_build_rs_tensor: device rank reduction not available in this build");
-  return RSD_E_UNSUPPORTED;
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+constexpr int TM = 64;       // output tile rows
+constexpr int TN = 64;       // output tile cols
+constexpr int TK = 32;       // contraction depth per LDS stage
+constexpr int LDT = TM + 4;  // padded LDS row (doubles)
+
+// ----------------------------------------------------------------- operand loaders
+// Each loader fills an LDS stage s[kk][mm] (kk < TK, mm < 64) with element (k0+kk, m0+mm)
+// of its operand, zero outside [k0, k1) x [0, dim).  256 threads; thread t owns row
+// kk = t / 8 and the 8 columns (t % 8) * 8 .. +7.
+
+struct OpKM {                 // element (k, m) = p[k * ld + m]
+  const double* __restrict__ p;
+  int64_t ld;
+  int dim;
+  __device__ void setup(int) {}
+  __device__ void fill(double* s, int64_t k0, int64_t k1, int m0) const {
+    const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
+    const int64_t k = k0 + kk;
+    double v[8];
+    if (k < k1 && m0 + c + 8 <= dim) {
+      const double2* src = reinterpret_cast<const double2*>(p + k * ld + m0 + c);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double2 x = src[j];
+        v[2 * j] = x.x;
+        v[2 * j + 1] = x.y;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = (k < k1 && m0 + c + j < dim) ? p[k * ld + m0 + c + j] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[kk * LDT + c + j] = v[j];
+  }
+};
+
+struct OpKMScaled {           // element (k, m) = p[k * ld + m] * scale[k]
+  const double* __restrict__ p;
+  const double* __restrict__ scale;
+  int64_t ld;
+  int dim;
+  __device__ void setup(int) {}
+  __device__ void fill(double* s, int64_t k0, int64_t k1, int m0) const {
+    const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
+    const int64_t k = k0 + kk;
+    const double sc = k < k1 ? scale[k] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      s[kk * LDT + c + j] = (k < k1 && m0 + c + j < dim) ? p[k * ld + m0 + c + j] * sc : 0.0;
+  }
+};
+
+struct OpKhatriRao {          // element (k, m = a*r2 + b) = P1[k*ld1 + a] * P2[k*ld2 + b]
+  const double* __restrict__ P1;
+  const double* __restrict__ P2;
+  int64_t ld1, ld2;
+  int r2;
+  int dim;                    // r1 * r2
+  int a_[8], b_[8];
+  __device__ void setup(int m0) {
+    const int c = (threadIdx.x & 7) * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int m = m0 + c + j;
+      a_[j] = m < dim ? m / r2 : 0;
+      b_[j] = m < dim ? m % r2 : 0;
+    }
+  }
+  __device__ void fill(double* s, int64_t k0, int64_t k1, int m0) const {
+    const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
+    const int64_t k = k0 + kk;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      s[kk * LDT + c + j] = (k < k1 && m0 + c + j < dim) ? P1[k * ld1 + a_[j]] * P2[k * ld2 + b_[j]] : 0.0;
+  }
+};
+
+struct OpGauss {              // element (k = grid row i, m = column c) = exp(-t_c^2 (X_i - x_c)^2) / nu_c
+  const double* __restrict__ pos;    // N x 3
+  const double* __restrict__ t2;     // K_long
+  const double* __restrict__ inv_nu; // columns
+  int K, d, n;
+  double b, h;
+  int dim;                           // number of columns
+  double x_[8], t2_[8], s_[8];
+  __device__ void setup(int m0) {
+    const int c = (threadIdx.x & 7) * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int col = m0 + c + j;
+      if (col < dim) {
+        x_[j] = pos[3 * (col / K) + d];
+        t2_[j] = t2[col % K];
+        s_[j] = inv_nu[col];
+      } else {
+        x_[j] = 0.0; t2_[j] = 0.0; s_[j] = 0.0;
+      }
+    }
+  }
+  __device__ void fill(double* s, int64_t k0, int64_t k1, int m0) const {
+    const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
+    const int64_t i = k0 + kk;
+    const double X = -b + (double)(i + 1) * h;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const double dx = X - x_[j];
+      s[kk * LDT + c + j] = (i < k1) ? exp(-(t2_[j] * (dx * dx))) * s_[j] : 0.0;
+    }
+  }
+};
+
+// ----------------------------------------------------------------- FP64 MFMA GEMM
+// C[split][m][n] (+)= sum_{k in split} A(k, m) * B(k, n) for one 64 x 64 tile per workgroup.
+// Four wavefronts, each a 32 x 32 sub-tile of 2 x 2 v_mfma_f64_16x16x4 blocks.
+// Lane l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator item v of lane l is
+// D[4v + l/16][l%16].
+struct GemmShape {
+  int M, N;
+  int64_t K, kper;            // contraction length and per-split chunk
+  double* C;
+  int64_t ldc;
+  int64_t split_stride;       // elements between split slices of C
+  int accumulate;             // add into C instead of overwriting
+  int tri;                    // enumerate only tiles with m-block <= n-block
+  int tiles_n;                // number of n tiles (for tri)
+};
+
+template <class AOp, class BOp>
+__global__ __launch_bounds__(256) void k_gemm(AOp A, BOp B, const GemmShape g) {
+  __shared__ double sA[TK * LDT];
+  __shared__ double sB[TK * LDT];
+  int bm, bn;
+  if (g.tri) {
+    int idx = blockIdx.x, row = 0, len = g.tiles_n;
+    while (idx >= len) { idx -= len; ++row; --len; }
+    bm = row;
+    bn = row + idx;
+  } else {
+    bn = blockIdx.x;
+    bm = blockIdx.y;
+  }
+  const int m0 = bm * TM, n0 = bn * TN;
+  const int64_t k0 = (int64_t)blockIdx.z * g.kper;
+  const int64_t k1 = min(g.K, k0 + g.kper);
+  A.setup(m0);
+  B.setup(n0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  d4v acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
+  for (int64_t kb = k0; kb < k1; kb += TK) {
+    A.fill(sA, kb, k1, m0);
+    B.fill(sB, kb, k1, n0);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      const double a0 = sA[(kk + lk) * LDT + wm + lr];
+      const double a1 = sA[(kk + lk) * LDT + wm + 16 + lr];
+      const double b0 = sB[(kk + lk) * LDT + wn + lr];
+      const double b1 = sB[(kk + lk) * LDT + wn + 16 + lr];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* C = g.C + (int64_t)blockIdx.z * g.split_stride;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm + 16 * i + 4 * v + lk;
+        const int n = n0 + wn + 16 * j + lr;
+        if (m < g.M && n < g.N) {
+          double* c = C + (int64_t)m * g.ldc + n;
+          *c = g.accumulate ? *c + acc[i][j][v] : acc[i][j][v];
+        }
+      }
+}
+
+// Sum split slices: out[m*ldo + n] = sum_s part[s*stride + m*ldp + n].
+__global__ void k_reduce_splits(const double* __restrict__ part, int splits, int64_t stride, int M, int N,
+                                int64_t ldp, double* __restrict__ out, int64_t ldo) {
+  const int64_t total = (int64_t)M * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = e / N, nn = e % N;
+    double s = 0.0;
+    for (int q = 0; q < splits; ++q) s += part[q * stride + m * ldp + nn];
+    out[m * ldo + nn] = s;
+  }
+}
+
+// ----------------------------------------------------------------- small kernels
+// Column norms nu_c = ||g_c|| of columns c in [c0, c1) of mode d (one wavefront per column).
+__global__ void k_col_norms(const double* __restrict__ pos, const double* __restrict__ t2, int K, int d, int n,
+                            double b, double h, int64_t c0, int64_t c1, double* __restrict__ nu,
+                            double* __restrict__ inv_nu) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = c0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (c >= c1) return;
+  const double x = pos[3 * (c / K) + d];
+  const double tt = t2[c % K];
+  double s = 0.0;
+  for (int i = lane; i < n; i += 64) {
+    const double dx = (-b + (double)(i + 1) * h) - x;
+    const double g = exp(-(tt * (dx * dx)));
+    s = fma(g, g, s);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) {
+    const double r = sqrt(s);
+    nu[c] = r;
+    inv_nu[c] = r > 0.0 ? 1.0 / r : 0.0;
+  }
+}
+
+// Normalised side-matrix chunk: A[(c - c0) * n + i] = g_c[i] / nu_c  (column-contiguous).
+__global__ void k_gen_columns(const double* __restrict__ pos, const double* __restrict__ t2, int K, int d, int n,
+                              double b, double h, int64_t c0, int64_t c1, const double* __restrict__ inv_nu,
+                              double* __restrict__ A) {
+  const int64_t total = (c1 - c0) * (int64_t)n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = c0 + e / n;
+    const int i = (int)(e % n);
+    const double x = pos[3 * (c / K) + d];
+    const double dx = (-b + (double)(i + 1) * h) - x;
+    A[e] = exp(-(t2[c % K] * (dx * dx))) * inv_nu[c];
+  }
+}
+
+// Top-r eigenvectors (eigenvalues ascending in Z, column-major n x n) -> U[i * ldu + a], descending.
+__global__ void k_take_eigvecs(const double* __restrict__ Z, int n, int r, double* __restrict__ U, int ldu) {
+  const int64_t total = (int64_t)n * ldu;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / ldu), a = (int)(e % ldu);
+    U[e] = a < r ? Z[(int64_t)(n - 1 - a) * n + i] : 0.0;
+  }
+}
+
+// xi_c = z_m w_k nu1_c nu2_c nu3_c for column c = m*K + k.
+__global__ void k_weights(const double* __restrict__ z, const double* __restrict__ w, int K, int64_t C,
+                          const double* __restrict__ nu1, const double* __restrict__ nu2,
+                          const double* __restrict__ nu3, double* __restrict__ xi) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C; c += (int64_t)gridDim.x * blockDim.x)
+    xi[c] = z[c / K] * w[c % K] * nu1[c] * nu2[c] * nu3[c];
+}
+
+// Core beta[(a*r2 + b) * ldb + c] -> column-major slices S[c][b][a] (r1 x r2, lda = r1).
+__global__ void k_core_slices(const double* __restrict__ beta, int r1, int r2, int r3, int64_t ldb,
+                              double* __restrict__ S) {
+  const int64_t total = (int64_t)r1 * r2 * r3;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e % r1);
+    const int64_t rest = e / r1;
+    const int bb = (int)(rest % r2);
+    const int c = (int)(rest / r2);
+    S[e] = beta[((int64_t)a * r2 + bb) * ldb + c];
+  }
+}
+
+// F[chunk][i][j] = sum_a U[i * ldu + a] * V[a * R + p] with p = chunk * kChunk + j (zero for p >= R).
+__global__ void k_assemble(const double* __restrict__ U, int ldu, int r, const double* __restrict__ V, int64_t R,
+                           int n, int nchunk, double* __restrict__ F) {
+  const int64_t total = (int64_t)nchunk * n * kChunk;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e % kChunk);
+    const int64_t rest = e / kChunk;
+    const int i = (int)(rest % n);
+    const int64_t p = (rest / n) * kChunk + j;
+    double s = 0.0;
+    if (p < R) {
+      const double* u = U + (int64_t)i * ldu;
+      for (int a = 0; a < r; ++a) s = fma(u[a], V[(int64_t)a * R + p], s);
+    }
+    F[e] = s;
+  }
+}
+
+// ----------------------------------------------------------------- host helpers
+struct DevBuf {
+  Context* ctx = nullptr;
+  double* p = nullptr;
+  size_t bytes = 0;
+  rsd_status alloc(Context* c, size_t n) {
+    ctx = c;
+    bytes = sizeof(double) * (n ? n : 1);
+    return c->dev_alloc((void**)&p, bytes);
+  }
+  ~DevBuf() {   // work queued on the stream may still read the buffer
+    if (p) {
+      (void)hipStreamSynchronize(ctx->stream);
+      ctx->dev_free(p, bytes);
+    }
+  }
+};
+
+inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+inline unsigned grid1d(int64_t total) { return (unsigned)std::min<int64_t>(std::max<int64_t>(1, (total + 255) / 256), 65536); }
+
+template <class AOp, class BOp>
+rsd_status gemm(Context* ctx, const char* name, const AOp& A, const BOp& B, GemmShape g, int splits) {
+  dim3 grid;
+  if (g.tri) {
+    g.tiles_n = div_up(g.N, TN);
+    grid = dim3((unsigned)(g.tiles_n * (g.tiles_n + 1) / 2), 1, (unsigned)splits);
+  } else {
+    grid = dim3((unsigned)div_up(g.N, TN), (unsigned)div_up(g.M, TM), (unsigned)splits);
+  }
+  RSD_TIMED_LAUNCH(ctx, name, (k_gemm<AOp, BOp><<<grid, 256, 0, ctx->stream>>>(A, B, g)));
+  return RSD_OK;
+}
+
+rsd_status check_info(Context* ctx, rocblas_int* d_info, int count, const char* what) {
+  std::vector<rocblas_int> info((size_t)count);
+  RSD_HIP(hipMemcpyAsync(info.data(), d_info, sizeof(rocblas_int) * count, hipMemcpyDeviceToHost, ctx->stream));
+  RSD_HIP(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < count; ++i)
+    RSD_CHECK(info[i] == 0, RSD_E_NUMERIC, "%s did not converge (info %d at %d)", what, (int)info[i], i);
+  return RSD_OK;
+}
+
+}  // namespace
+
+rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const double* d_pos) {
+  const int n = t->n;
+  const int K = t->sp.K_long;
+  const int64_t N = t->N;
+  const int64_t C = N * K;                    // columns of each side matrix
+  const double eps = t->sp.eps;
+  hipStream_t s = ctx->stream;
+  RSD_CHECK(C < ((int64_t)1 << 30), RSD_E_UNSUPPORTED, "too many side-matrix columns (N*K_long)");
+  if (C == 0) return alloc_factors(ctx, t, 0);
+
+  // long-range nodes and weights
+  double tk[kMaxTerms], wk[kMaxTerms];
+  sinc_table(t->sp, tk, wk);
+  std::vector<double> t2h((size_t)K), wh((size_t)K);
+  for (int k = 0; k < K; ++k) {
+    t2h[k] = tk[k] * tk[k];
+    wh[k] = wk[k];
+  }
+  DevBuf t2d, wd;
+  RSD_TRY(t2d.alloc(ctx, K));
+  RSD_TRY(wd.alloc(ctx, K));
+  RSD_HIP(hipMemcpyAsync(t2d.p, t2h.data(), sizeof(double) * K, hipMemcpyHostToDevice, s));
+  RSD_HIP(hipMemcpyAsync(wd.p, wh.data(), sizeof(double) * K, hipMemcpyHostToDevice, s));
+
+  if (!ctx->blas) {
+    rocblas_handle hnew = nullptr;
+    RSD_CHECK(rocblas_create_handle(&hnew) == rocblas_status_success, RSD_E_HIP, "rocblas_create_handle failed");
+    ctx->blas = hnew;
+  }
+  rocblas_handle hb = (rocblas_handle)ctx->blas;
+  RSD_CHECK(rocblas_set_stream(hb, s) == rocblas_status_success, RSD_E_HIP, "rocblas_set_stream failed");
+
+  // column chunks of the side matrix: at most ~1 GiB each
+  const int64_t max_cols = std::max<int64_t>(TK, ((int64_t)1 << 27) / n / TK * TK);
+  const int64_t chunk_cols = std::min<int64_t>(C, max_cols);
+  DevBuf Abuf, nu[3], inv_nu, G, Gpart, W, Ebuf;
+  RSD_TRY(Abuf.alloc(ctx, (size_t)chunk_cols * n));
+  for (int d = 0; d < 3; ++d) RSD_TRY(nu[d].alloc(ctx, (size_t)C));
+  RSD_TRY(inv_nu.alloc(ctx, (size_t)C));
+  RSD_TRY(G.alloc(ctx, (size_t)n * n));
+  const int Tn = div_up(n, TN);
+  const int tri_tiles = Tn * (Tn + 1) / 2;
+  const int gsplit = std::max(1, std::min(16, div_up(1024, tri_tiles)));
+  RSD_TRY(Gpart.alloc(ctx, (size_t)gsplit * n * n));
+  RSD_TRY(W.alloc(ctx, n));
+  RSD_TRY(Ebuf.alloc(ctx, n));
+  rocblas_int* d_info = nullptr;
+  RSD_TRY(ctx->dev_alloc((void**)&d_info, 4096));
+  struct InfoGuard {
+    Context* c;
+    void* p;
+    ~InfoGuard() { c->dev_free(p, 4096); }
+  } ig{ctx, d_info};
+
+  int r[3] = {0, 0, 0};
+  int ldu[3] = {0, 0, 0};
+  DevBuf U[3], Bt[3];
+  const double h = t->h, b = t->b;
+  for (int d = 0; d < 3; ++d) {
+    // 1. column norms and the Gram matrix, chunk by chunk
+    RSD_TIMED_LAUNCH(ctx, "gen", (k_col_norms<<<div_up(C, 4), 256, 0, s>>>(d_pos, t2d.p, K, d, n, b, h, 0, C,
+                                                                             nu[d].p, inv_nu.p)));
+    RSD_HIP(hipMemsetAsync(Gpart.p, 0, Gpart.bytes, s));
+    for (int64_t c0 = 0; c0 < C; c0 += chunk_cols) {
+      const int64_t c1 = std::min(C, c0 + chunk_cols);
+      RSD_TIMED_LAUNCH(ctx, "gen", (k_gen_columns<<<grid1d((c1 - c0) * n), 256, 0, s>>>(
+                                       d_pos, t2d.p, K, d, n, b, h, c0, c1, inv_nu.p, Abuf.p)));
+      OpKM op{Abuf.p, n, n};
+      GemmShape g{};
+      g.M = n; g.N = n; g.K = c1 - c0;
+      g.kper = (int64_t)div_up(g.K, (int64_t)gsplit * TK) * TK;
+      g.C = Gpart.p; g.ldc = n; g.split_stride = (int64_t)n * n;
+      g.accumulate = 1; g.tri = 1;
+      RSD_TRY(gemm(ctx, "gram", op, op, g, gsplit));
+    }
+    RSD_TIMED_LAUNCH(ctx, "gram", (k_reduce_splits<<<grid1d((int64_t)n * n), 256, 0, s>>>(
+                                      Gpart.p, gsplit, (int64_t)n * n, n, n, n, G.p, n)));
+    // 2. eigenvectors (row-major upper tiles = column-major lower triangle)
+    KernelTimer kt;
+    if (ctx->timing) RSD_TRY(ctx->timer_begin("eig", &kt));
+    rocblas_status rs = rocsolver_dsyevd(hb, rocblas_evect_original, rocblas_fill_lower, n, G.p, n, W.p, Ebuf.p,
+                                         d_info);
+    RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dsyevd failed (%d)", (int)rs);
+    if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+    RSD_TRY(check_info(ctx, d_info, 1, "symmetric eigensolver"));
+    std::vector<double> lam((size_t)n);
+    RSD_HIP(hipMemcpy(lam.data(), W.p, sizeof(double) * n, hipMemcpyDeviceToHost));
+    const double lmax = lam[n - 1];
+    RSD_CHECK(lmax > 0.0 && std::isfinite(lmax), RSD_E_NUMERIC, "Gram matrix of mode %d has no positive eigenvalue", d);
+    int rd = 0;
+    for (int i = n - 1; i >= 0 && lam[i] >= eps * eps * lmax; --i) ++rd;
+    RSD_CHECK(rd >= 1 && rd <= 1024, RSD_E_UNSUPPORTED, "mode-%d rank %d outside [1, 1024]", d, rd);
+    r[d] = rd;
+    ldu[d] = ((rd + 7) / 8) * 8;
+    RSD_TRY(U[d].alloc(ctx, (size_t)n * ldu[d]));
+    RSD_TIMED_LAUNCH(ctx, "eig", (k_take_eigvecs<<<grid1d((int64_t)n * ldu[d]), 256, 0, s>>>(G.p, n, rd, U[d].p,
+                                                                                            ldu[d])));
+    // 3. projection B_d^T[c][a] = sum_i A(i, c) U[i][a], side-matrix columns regenerated in LDS
+    RSD_TRY(Bt[d].alloc(ctx, (size_t)C * ldu[d]));
+    OpGauss ga{};
+    ga.pos = d_pos; ga.t2 = t2d.p; ga.inv_nu = inv_nu.p; ga.K = K; ga.d = d; ga.n = n; ga.b = b; ga.h = h;
+    ga.dim = (int)C;
+    OpKM ub{U[d].p, ldu[d], rd};
+    GemmShape g{};
+    g.M = (int)C; g.N = rd; g.K = n; g.kper = ((n + TK - 1) / TK) * TK;
+    g.C = Bt[d].p; g.ldc = ldu[d]; g.split_stride = 0; g.accumulate = 0; g.tri = 0;
+    RSD_TRY(gemm(ctx, "project", ga, ub, g, 1));
+  }
+  t->ranks[0] = r[0];
+  t->ranks[1] = r[1];
+  t->ranks[2] = r[2];
+
+  // 4. Tucker core beta[(a*r2 + b)][c] = sum_col xi_col B1[col][a] B2[col][b] B3[col][c]
+  DevBuf xi;
+  RSD_TRY(xi.alloc(ctx, (size_t)C));
+  RSD_TIMED_LAUNCH(ctx, "core", (k_weights<<<grid1d(C), 256, 0, s>>>(d_z, wd.p, K, C, nu[0].p, nu[1].p, nu[2].p,
+                                                                     xi.p)));
+  const int M12 = r[0] * r[1];
+  const int tiles = div_up(M12, TM) * div_up(r[2], TN);
+  const int csplit = std::max(1, std::min(64, div_up(1024, tiles)));
+  DevBuf Cpart, beta;
+  RSD_TRY(Cpart.alloc(ctx, (size_t)csplit * M12 * r[2]));
+  RSD_TRY(beta.alloc(ctx, (size_t)M12 * r[2]));
+  OpKhatriRao kr{Bt[0].p, Bt[1].p, ldu[0], ldu[1], r[1], M12, {}, {}};
+  OpKMScaled b3{Bt[2].p, xi.p, ldu[2], r[2]};
+  {
+    GemmShape g{};
+    g.M = M12; g.N = r[2]; g.K = C;
+    g.kper = (int64_t)div_up(C, (int64_t)csplit * TK) * TK;
+    g.C = Cpart.p; g.ldc = r[2]; g.split_stride = (int64_t)M12 * r[2]; g.accumulate = 0; g.tri = 0;
+    RSD_TRY(gemm(ctx, "core", kr, b3, g, csplit));
+    RSD_TIMED_LAUNCH(ctx, "core", (k_reduce_splits<<<grid1d((int64_t)M12 * r[2]), 256, 0, s>>>(
+                                      Cpart.p, csplit, (int64_t)M12 * r[2], M12, r[2], r[2], beta.p, r[2])));
+  }
+
+  // 5. Tucker -> canonical: batched SVD of the mode-3 slices (r1 x r2, column-major)
+  const int r1 = r[0], r2 = r[1], r3 = r[2];
+  const int mn = std::min(r1, r2);
+  DevBuf S, Sv, Uv, Vv, Ev;
+  RSD_TRY(S.alloc(ctx, (size_t)r1 * r2 * r3));
+  RSD_TRY(Sv.alloc(ctx, (size_t)mn * r3));
+  RSD_TRY(Uv.alloc(ctx, (size_t)r1 * mn * r3));
+  RSD_TRY(Vv.alloc(ctx, (size_t)mn * r2 * r3));
+  RSD_TRY(Ev.alloc(ctx, (size_t)mn * r3));
+  RSD_TIMED_LAUNCH(ctx, "t2c", (k_core_slices<<<grid1d((int64_t)r1 * r2 * r3), 256, 0, s>>>(beta.p, r1, r2, r3,
+                                                                                            r3, S.p)));
+  RSD_CHECK(r3 <= 4096, RSD_E_UNSUPPORTED, "too many core slices");
+  {
+    KernelTimer kt;
+    if (ctx->timing) RSD_TRY(ctx->timer_begin("t2c", &kt));
+    rocblas_status rs = rocsolver_dgesvd_strided_batched(
+        hb, rocblas_svect_singular, rocblas_svect_singular, r1, r2, S.p, r1, (rocblas_stride)r1 * r2, Sv.p,
+        (rocblas_stride)mn, Uv.p, r1, (rocblas_stride)r1 * mn, Vv.p, mn, (rocblas_stride)mn * r2, Ev.p,
+        (rocblas_stride)mn, rocblas_outofplace, d_info, r3);
+    RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dgesvd_strided_batched failed (%d)", (int)rs);
+    if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+  }
+  RSD_TRY(check_info(ctx, d_info, r3, "slice SVD"));
+  std::vector<double> sv((size_t)mn * r3), uv((size_t)r1 * mn * r3), vv((size_t)mn * r2 * r3);
+  RSD_HIP(hipMemcpy(sv.data(), Sv.p, sizeof(double) * sv.size(), hipMemcpyDeviceToHost));
+  RSD_HIP(hipMemcpy(uv.data(), Uv.p, sizeof(double) * uv.size(), hipMemcpyDeviceToHost));
+  RSD_HIP(hipMemcpy(vv.data(), Vv.p, sizeof(double) * vv.size(), hipMemcpyDeviceToHost));
+  double smax = 0.0;
+  for (double x : sv) smax = std::max(smax, x);
+  std::vector<std::pair<int, int>> kept;
+  for (int c = 0; c < r3; ++c)
+    for (int q = 0; q < mn; ++q)
+      if (sv[(size_t)c * mn + q] >= eps * smax && sv[(size_t)c * mn + q] > 0.0) kept.emplace_back(c, q);
+  const int64_t R = (int64_t)kept.size();
+  RSD_CHECK(R <= ((int64_t)1 << 20), RSD_E_UNSUPPORTED, "canonical rank %lld too large", (long long)R);
+  // V_d (r_d x R) on the host: column p = s*u (mode 1), v (mode 2), e_c (mode 3)
+  std::vector<double> V1((size_t)r1 * R), V2((size_t)r2 * R), V3((size_t)r3 * R, 0.0);
+  for (int64_t p = 0; p < R; ++p) {
+    const int c = kept[p].first, q = kept[p].second;
+    const double sq = sv[(size_t)c * mn + q];
+    for (int a = 0; a < r1; ++a) V1[(size_t)a * R + p] = sq * uv[(size_t)c * r1 * mn + (size_t)q * r1 + a];
+    for (int bb = 0; bb < r2; ++bb) V2[(size_t)bb * R + p] = vv[(size_t)c * mn * r2 + (size_t)bb * mn + q];
+    V3[(size_t)c * R + p] = 1.0;
+  }
+  RSD_TRY(alloc_factors(ctx, t, R));
+  if (R == 0) return RSD_OK;
+  const int64_t mode = (int64_t)t->nchunk * n * kChunk;
+  const std::vector<double>* Vh[3] = {&V1, &V2, &V3};
+  for (int d = 0; d < 3; ++d) {
+    DevBuf Vd;
+    RSD_TRY(Vd.alloc(ctx, Vh[d]->size()));
+    RSD_HIP(hipMemcpyAsync(Vd.p, Vh[d]->data(), sizeof(double) * Vh[d]->size(), hipMemcpyHostToDevice, s));
+    RSD_TIMED_LAUNCH(ctx, "assemble", (k_assemble<<<grid1d(mode), 256, 0, s>>>(U[d].p, ldu[d], r[d], Vd.p, R, n,
+                                                                               t->nchunk, t->F + d * mode)));
+    RSD_HIP(hipStreamSynchronize(s));
+  }
+  return RSD_OK;
 }
 
 }  // namespace rsd

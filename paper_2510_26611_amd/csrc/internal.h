@@ -78,6 +78,7 @@ struct Context {
   // growable scratch owned by the context
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  void* blas = nullptr;        // rocblas_handle for the eigen/SVD steps of the build (lazy)
   bool timing = false;
   std::vector<KernelTimer> pending;
   std::map<std::string, std::pair<int64_t, double>> ktime;
@@ -152,6 +153,8 @@ struct ScoreIO {
 };
 rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io);
 
+// factor storage of a tensor with canonical rank R (api.hip)
+rsd_status alloc_factors(Context* ctx, Tensor* t, int64_t R);
 // rank reduction on the device (build.hip)
 rsd_status build_factors(Context* ctx, Tensor* t, const double* d_charges, const double* d_positions);
 

@@ -1,0 +1,103 @@
+"""GPU parity of rsd_build_rs_tensor (Algorithm TEP on the device) against the oracle.
+
+Two independent rank reductions of the same tensor agree only to the truncation level,
+so the build is checked against the uncompressed long-range tensor T0 (eq. 2.6) at
+sampled grid nodes, self-calibrated by the oracle's own exact-SVD compression:
+    max |T_gpu - T0| <= 10 * max(max |T_oracle - T0|, eps * max |T0|).
+End to end, the trilinear value at any point is a convex combination of 8 node values,
+so |E_gpu - E_oracle| <= sum_l |zeta_l| (err_gpu + err_oracle) + 1e-10 * scale.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+from gpu_common import oracle_factors, oracle_score, sinc_parts  # noqa: E402
+from oracle import tensor as otensor  # noqa: E402
+from workloads import configs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2510_26611_amd as rs
+    return rs
+
+
+@pytest.fixture(scope="module")
+def ctx(rs):
+    c = rs.Context(0)
+    yield c
+    c.close()
+
+
+def _nodes(cfg, count, seed):
+    g = np.random.default_rng(seed)
+    return g.integers(0, cfg.n, size=(count, 3))
+
+
+def _canon_at(F, idx):
+    return np.sum(F[0][idx[:, 0]] * F[1][idx[:, 1]] * F[2][idx[:, 2]], axis=1)
+
+
+def _check_build(rs, ctx, cfg, P_score, label):
+    wl = configs.make(cfg, P=P_score)
+    (tl, wlong), _ = sinc_parts(cfg)
+    tk, can = oracle_factors(cfg, wl)
+    t = rs.build_rs_tensor(ctx, wl.protein_charges, wl.protein_positions, cfg.n, cfg.b, rs.Sinc.from_config(cfg))
+    info = t.query()
+    Fg = t.export()
+    idx = _nodes(cfg, 4000, 17)
+    T0 = otensor.long_range_at_nodes(wl.protein_charges, wl.protein_positions, tl, wlong, cfg.n, cfg.b, idx)
+    err_o = np.max(np.abs(_canon_at(can.F, idx) - T0))
+    err_g = np.max(np.abs(_canon_at(Fg, idx) - T0))
+    floor = cfg.eps * np.max(np.abs(T0))
+    print(f"{label}: ranks gpu {info['ranks']} R={info['R']} | oracle {tk.ranks} R={can.R} | "
+          f"max|T-T0| gpu {err_g:.3e} oracle {err_o:.3e} (max|T0| {np.max(np.abs(T0)):.3e})")
+    assert err_g <= 10.0 * max(err_o, floor)
+    for d in range(3):
+        assert info["ranks"][d] >= tk.ranks[d] - 1
+    # end to end: GPU-built tensor scored on the GPU vs the oracle's tensor scored by the oracle
+    ref = oracle_score(cfg, wl, can.F, wl.quats, wl.trans)
+    out = rs.score_poses(ctx, t, wl.ligand_charges, wl.ligand_positions, wl.quats, wl.trans, cfg.sigma)
+    assert np.array_equal(out["flags"], ref["flags"])
+    assert np.array_equal(out["counts"], ref["counts"])
+    ok = ~np.isnan(ref["E"])
+    bound = np.sum(np.abs(wl.ligand_charges)) * 2.0 * (err_g + err_o) + 1e-10 * ref["scale"]
+    assert np.all(np.abs(out["E"] - ref["E"])[ok] <= bound[ok])
+    return t, Fg
+
+
+def test_cfg1_build_within_rhosvd_bound(rs, ctx):
+    t, F1 = _check_build(rs, ctx, configs.CONFIG1, 128, "cfg1")
+    # a second build of the same protein is bitwise identical
+    cfg = configs.CONFIG1
+    wl = configs.make(cfg, P=1)
+    t2 = rs.build_rs_tensor(ctx, wl.protein_charges, wl.protein_positions, cfg.n, cfg.b, rs.Sinc.from_config(cfg))
+    F2 = t2.export()
+    for d in range(3):
+        assert np.array_equal(F1[d], F2[d])
+
+
+@pytest.mark.timeout(900)
+def test_cfg2_build_within_rhosvd_bound(rs, ctx):
+    _check_build(rs, ctx, configs.CONFIG2, 512, "cfg2")
+
+
+def test_build_argument_errors(rs, ctx):
+    cfg = configs.CONFIG1
+    wl = configs.make(cfg, P=1)
+    with pytest.raises(rs.RsdError) as e:
+        rs.build_rs_tensor(ctx, wl.protein_charges[:0], wl.protein_positions[:0], cfg.n, cfg.b,
+                           rs.Sinc.from_config(cfg))
+    assert e.value.code == -1
+    z = wl.protein_charges.copy()
+    z[5] = np.inf
+    with pytest.raises(rs.RsdError) as e:
+        rs.build_rs_tensor(ctx, z, wl.protein_positions, cfg.n, cfg.b, rs.Sinc.from_config(cfg))
+    assert e.value.code == -1
