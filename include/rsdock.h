@@ -91,6 +91,8 @@ rsd_status rsd_context_create(int32_t device, void* hip_stream, size_t hbm_budge
 rsd_status rsd_context_set_stream(rsd_context* ctx, void* hip_stream);
 /* Bytes currently held by the context (tensors + workspace). */
 rsd_status rsd_context_memory(const rsd_context* ctx, size_t* bytes_in_use, size_t* budget);
+/* Free a context.  If tensors made with it are still alive the context stops accepting
+ * work and is released together with the last of them (rsd_tensor_free). */
 void rsd_context_free(rsd_context* ctx);
 
 /* Build the RS tensor of a protein (Algorithm TEP).
@@ -164,6 +166,13 @@ rsd_status rsd_tensor_save(const rsd_tensor* t, const char* path);
 rsd_status rsd_tensor_load(rsd_context* ctx, const char* path, rsd_tensor** out);
 
 void rsd_tensor_free(rsd_tensor* t);
+
+/* Tuning options of a context (the autotuner sets these):
+ *   "score_mode"      0 automatic, 1 one wavefront per pose for the whole pose,
+ *                     2 long-range part in rank-chunk-major order across the XCDs
+ *   "poses_per_wave"  poses per wavefront in mode 2 (0 automatic, 1..4)
+ * Errors: RSD_E_INVALID for an unknown name or value. */
+rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t value);
 
 /* Kernel timing with HIP events on the context stream (off by default).  When on,
  * every library kernel launch is bracketed by events and its duration is added to

@@ -28,6 +28,7 @@ EXPORTED = [
     "rsd_context_memory", "rsd_context_free", "rsd_build_rs_tensor", "rsd_tensor_import",
     "rsd_score_poses", "rsd_tensor_query", "rsd_tensor_export", "rsd_tensor_save",
     "rsd_tensor_load", "rsd_tensor_free", "rsd_context_set_timing", "rsd_kernel_time",
+    "rsd_context_set_option",
 ]
 
 
@@ -63,6 +64,7 @@ def _declare(lib: C.CDLL) -> C.CDLL:
         "rsd_tensor_load": (st, [_P, C.c_char_p, C.POINTER(_P)]),
         "rsd_tensor_free": (None, [_P]),
         "rsd_context_set_timing": (st, [_P, _I32]),
+        "rsd_context_set_option": (st, [_P, C.c_char_p, _I64]),
         "rsd_kernel_time": (st, [_P, C.c_char_p, C.POINTER(_I64), C.POINTER(_D)]),
     }
     for name, (res, args) in sig.items():

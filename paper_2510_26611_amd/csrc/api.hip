@@ -189,6 +189,20 @@ static rsd_status tensor_common(Context* ctx, Tensor* t, int32_t n, double b, co
   return RSD_OK;
 }
 
+static void context_destroy(Context* ctx) {
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& t : ctx->pending) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  ctx->pending.clear();
+  ctx->dev_free(ctx->ws, ctx->ws_bytes);
+  ctx->ws = nullptr;
+  if (ctx->blas) rocblas_destroy_handle((rocblas_handle)ctx->blas);
+  delete static_cast<rsd_context*>(ctx);
+}
+
 static void tensor_release(Tensor* t) {
   if (!t) return;
   Context* c = t->ctx;
@@ -199,8 +213,10 @@ static void tensor_release(Tensor* t) {
     c->dev_free(t->atoms, sizeof(double4) * (size_t)(t->N > 0 ? t->N : 1));
     c->dev_free(t->cell_start, t->cell_bytes);
     c->dev_free(t->short_tab, sizeof(double) * 2 * kMaxTerms);
+    c->live_tensors -= 1;
   }
   delete static_cast<rsd_tensor*>(t);
+  if (c && c->closing && c->live_tensors == 0) context_destroy(c);
 }
 
 // Row-major n x R (device) -> column-chunked layout (device), zero padded.
@@ -298,16 +314,12 @@ rsd_status rsd_context_memory(const rsd_context* ctx, size_t* bytes_in_use, size
 }
 
 void rsd_context_free(rsd_context* ctx) {
-  if (!ctx) return;
-  (void)hipSetDevice(ctx->device);
-  (void)hipStreamSynchronize(ctx->stream);
-  for (auto& t : ctx->pending) {
-    (void)hipEventDestroy(t.start);
-    (void)hipEventDestroy(t.stop);
+  if (!ctx || ctx->closing) return;
+  if (ctx->live_tensors > 0) {   // released when the last of its tensors is freed
+    ctx->closing = true;
+    return;
   }
-  ctx->dev_free(ctx->ws, ctx->ws_bytes);
-  if (ctx->blas) rocblas_destroy_handle((rocblas_handle)ctx->blas);
-  delete ctx;
+  context_destroy(ctx);
 }
 
 static rsd_status make_tensor(rsd_context* ctx, const double* const F[3], int64_t R, bool build, int32_t n,
@@ -316,7 +328,7 @@ static rsd_status make_tensor(rsd_context* ctx, const double* const F[3], int64_
   clear_error();
   RSD_CHECK(out != nullptr, RSD_E_INVALID, "out is NULL");
   *out = nullptr;
-  RSD_CHECK(ctx != nullptr, RSD_E_INVALID, "ctx is NULL");
+  RSD_CHECK(ctx != nullptr && !ctx->closing, RSD_E_INVALID, "ctx is NULL or freed");
   RSD_TRY(check_sinc(sp));
   RSD_TRY(check_grid(n, b));
   RSD_CHECK(N >= (build ? 1 : 0) && N <= (int64_t)1 << 30, RSD_E_INVALID, "N=%lld out of range", (long long)N);
@@ -329,6 +341,8 @@ static rsd_status make_tensor(rsd_context* ctx, const double* const F[3], int64_
   RSD_TRY(check_protein(z, pos, n, b));
   rsd_tensor* t = new (std::nothrow) rsd_tensor();
   RSD_CHECK(t != nullptr, RSD_E_OOM, "host allocation failed");
+  t->ctx = ctx;
+  ctx->live_tensors += 1;
   double* d_z = nullptr;
   double* d_pos = nullptr;
   rsd_status st = tensor_common(ctx, t, n, b, sp, std::move(z), std::move(pos), &d_z, &d_pos);
@@ -420,6 +434,7 @@ rsd_status rsd_score_poses(rsd_context* ctx, const rsd_tensor* t, const double* 
                            double* energies_long, uint8_t* flags, int32_t* counts, double* grads) {
   clear_error();
   RSD_CHECK(ctx != nullptr && t != nullptr, RSD_E_INVALID, "ctx or tensor is NULL");
+  RSD_CHECK(!ctx->closing, RSD_E_INVALID, "context has been freed");
   RSD_CHECK(t->ctx == ctx, RSD_E_INVALID, "tensor belongs to another context");
   RSD_CHECK(L >= 1 && L <= kMaxLigand, RSD_E_UNSUPPORTED, "L=%lld outside [1, %d]", (long long)L, kMaxLigand);
   RSD_CHECK(P >= 0 && P <= ((int64_t)1 << 33), RSD_E_INVALID, "P=%lld out of range", (long long)P);
@@ -597,6 +612,24 @@ rsd_status rsd_tensor_load(rsd_context* ctx, const char* path, rsd_tensor** out)
                             pos.data(), hd.N, 0u, out));
   for (int d = 0; d < 3; ++d) (*out)->ranks[d] = hd.ranks[d];
   return RSD_OK;
+}
+
+// ---------------------------------------------------------------- tuning
+rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t value) {
+  clear_error();
+  RSD_CHECK(ctx != nullptr && name != nullptr, RSD_E_INVALID, "NULL argument");
+  if (std::strcmp(name, "score_mode") == 0) {
+    RSD_CHECK(value >= 0 && value <= 2, RSD_E_INVALID, "score_mode must be 0, 1 or 2");
+    ctx->opt_score_mode = (int)value;
+    return RSD_OK;
+  }
+  if (std::strcmp(name, "poses_per_wave") == 0) {
+    RSD_CHECK(value >= 0 && value <= 4, RSD_E_INVALID, "poses_per_wave must be in [0, 4]");
+    ctx->opt_poses_per_wave = (int)value;
+    return RSD_OK;
+  }
+  set_error("unknown option '%s'", name);
+  return RSD_E_INVALID;
 }
 
 // ---------------------------------------------------------------- timing

@@ -79,6 +79,11 @@ struct Context {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   void* blas = nullptr;        // rocblas_handle for the eigen/SVD steps of the build (lazy)
+  int live_tensors = 0;        // tensors made with this context and not yet freed
+  bool closing = false;        // rsd_context_free was called; released with the last tensor
+  // tuning options (rsd_context_set_option)
+  int opt_score_mode = 0;      // 0 auto, 1 fused per-pose kernel, 2 chunk-major long-range kernel
+  int opt_poses_per_wave = 0;  // chunk-major kernel: poses per wavefront (0 = automatic)
   bool timing = false;
   std::vector<KernelTimer> pending;
   std::map<std::string, std::pair<int64_t, double>> ktime;

@@ -20,6 +20,8 @@
 // d^2 are written in one fixed operation order (see the comments), so the values
 // that decide flags, counts and grid rows are reproducible bit for bit by any
 // IEEE FP64 implementation that follows the same order.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace rsd {
@@ -60,6 +62,8 @@ struct ScoreParams {
   uint8_t* __restrict__ flags;
   int32_t* __restrict__ counts;
   double* __restrict__ grads;
+  double* __restrict__ es;          // short-range energy per pose (split mode)
+  double* __restrict__ gs;          // short-range gradient per pose (split mode)
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -127,6 +131,36 @@ __global__ __launch_bounds__(64) void k_ligand_prep(const double* __restrict__ p
   if (lane == 0) rlig[0] = sqrt(-r2max);
 }
 
+// Rotation matrix of q = (w, x, y, z) in the fixed operation order shared by every kernel,
+// after the validity test | ((w*w + x*x) + y*y) + z*z - 1 | <= 1e-12 with finite inputs.
+__device__ __forceinline__ bool pose_frame(const double* __restrict__ q4, const double* __restrict__ t3,
+                                           double R[9], double t[3]) {
+  const double qw = q4[0], qx = q4[1], qy = q4[2], qz = q4[3];
+  t[0] = t3[0];
+  t[1] = t3[1];
+  t[2] = t3[2];
+  const double qq = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+  const bool finite = isfinite(qw) && isfinite(qx) && isfinite(qy) && isfinite(qz) && isfinite(t[0]) &&
+                      isfinite(t[1]) && isfinite(t[2]);
+  R[0] = 1.0 - 2.0 * (qy * qy + qz * qz); R[1] = 2.0 * (qx * qy - qw * qz); R[2] = 2.0 * (qx * qz + qw * qy);
+  R[3] = 2.0 * (qx * qy + qw * qz); R[4] = 1.0 - 2.0 * (qx * qx + qz * qz); R[5] = 2.0 * (qy * qz - qw * qx);
+  R[6] = 2.0 * (qx * qz - qw * qy); R[7] = 2.0 * (qy * qz + qw * qx); R[8] = 1.0 - 2.0 * (qx * qx + qy * qy);
+  return finite && fabs(qq - 1.0) <= 1e-12;
+}
+
+// y_i = ((R_i0 u_0 + R_i1 u_1) + R_i2 u_2) + t_i
+__device__ __forceinline__ double3 place(const double R[9], const double t[3], const double4 u) {
+  return make_double3(((R[0] * u.x + R[1] * u.y) + R[2] * u.z) + t[0],
+                      ((R[3] * u.x + R[4] * u.y) + R[5] * u.z) + t[1],
+                      ((R[6] * u.x + R[7] * u.y) + R[8] * u.z) + t[2]);
+}
+
+// Grid coordinate s = (y - X0) * inv_h; in range iff 0 <= s <= n-1.
+__device__ __forceinline__ bool in_grid(double y, double X0, double inv_h, double smax) {
+  const double s = (y - X0) * inv_h;
+  return s >= 0.0 && s <= smax;
+}
+
 template <bool GRAD>
 struct PairT;
 template <>
@@ -138,7 +172,9 @@ struct PairT<true> {
   using type = PairG;
 };
 
-template <bool GRAD>
+// LONG = true: the whole pose (A1-A5) in one wavefront.  LONG = false: A1, A3, A4 only;
+// the short-range energy/gradient go to es/gs and k_combine adds the long-range partials.
+template <bool GRAD, bool LONG>
 __global__ __launch_bounds__(256) void k_score(const ScoreParams a) {
   using Pair = typename PairT<GRAD>::type;
   extern __shared__ double4 smem[];
@@ -158,39 +194,32 @@ __global__ __launch_bounds__(256) void k_score(const ScoreParams a) {
   const int64_t p = (int64_t)blockIdx.x * W + wv;
   if (p >= a.P) return;    // whole wavefront leaves; no block barrier follows
 
-  // ---- pose input and validity: |q|^2 = ((w*w + x*x) + y*y) + z*z
-  const double qw = a.quats[4 * p + 0], qx = a.quats[4 * p + 1];
-  const double qy = a.quats[4 * p + 2], qz = a.quats[4 * p + 3];
-  const double tx = a.trans[3 * p + 0], ty = a.trans[3 * p + 1], tz = a.trans[3 * p + 2];
-  const double qq = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
-  const bool finite = isfinite(qw) && isfinite(qx) && isfinite(qy) && isfinite(qz) &&
-                      isfinite(tx) && isfinite(ty) && isfinite(tz);
-  if (!(finite && fabs(qq - 1.0) <= 1e-12)) {
+  // ---- A1: pose frame and atom positions
+  double R[9], tv[3];
+  const bool valid = pose_frame(a.quats + 4 * p, a.trans + 3 * p, R, tv);
+  const double tx = tv[0], ty = tv[1], tz = tv[2];
+  if (!valid) {
     if (lane == 0) {
-      a.E[p] = __builtin_nan("");
-      if (a.El) a.El[p] = __builtin_nan("");
+      const double nan = __builtin_nan("");
       a.flags[p] = (uint8_t)RSD_FLAG_INVALID;
       a.counts[p] = 0;
-      if (GRAD) {
-        for (int k = 0; k < 6; ++k) a.grads[6 * p + k] = __builtin_nan("");
+      if (LONG) {
+        a.E[p] = nan;
+        if (a.El) a.El[p] = nan;
+        if (GRAD) {
+          for (int k = 0; k < 6; ++k) a.grads[6 * p + k] = nan;
+        }
       }
     }
     return;
   }
-  // ---- A1: rotation matrix rows, each entry in this fixed operation order
-  const double R00 = 1.0 - 2.0 * (qy * qy + qz * qz), R01 = 2.0 * (qx * qy - qw * qz), R02 = 2.0 * (qx * qz + qw * qy);
-  const double R10 = 2.0 * (qx * qy + qw * qz), R11 = 1.0 - 2.0 * (qx * qx + qz * qz), R12 = 2.0 * (qy * qz - qw * qx);
-  const double R20 = 2.0 * (qx * qz - qw * qy), R21 = 2.0 * (qy * qz + qw * qx), R22 = 1.0 - 2.0 * (qx * qx + qy * qy);
-
   bool out_of_domain = false;
   for (int l = lane; l < L; l += 64) {
     const double4 u = s_lig[l];
-    const double y0 = ((R00 * u.x + R01 * u.y) + R02 * u.z) + tx;
-    const double y1 = ((R10 * u.x + R11 * u.y) + R12 * u.z) + ty;
-    const double y2 = ((R20 * u.x + R21 * u.y) + R22 * u.z) + tz;
-    s_y[l] = make_double4(y0, y1, y2, u.w);
-    const double s0 = (y0 - a.X0) * a.inv_h, s1 = (y1 - a.X0) * a.inv_h, s2 = (y2 - a.X0) * a.inv_h;
-    const bool in = (s0 >= 0.0 && s0 <= a.smax) && (s1 >= 0.0 && s1 <= a.smax) && (s2 >= 0.0 && s2 <= a.smax);
+    const double3 y = place(R, tv, u);
+    s_y[l] = make_double4(y.x, y.y, y.z, u.w);
+    const bool in = in_grid(y.x, a.X0, a.inv_h, a.smax) && in_grid(y.y, a.X0, a.inv_h, a.smax) &&
+                    in_grid(y.z, a.X0, a.inv_h, a.smax);
     out_of_domain |= !in;
   }
   const bool dom = __ballot(out_of_domain) == 0ull;
@@ -200,7 +229,7 @@ __global__ __launch_bounds__(256) void k_score(const ScoreParams a) {
   double gt0 = 0.0, gt1 = 0.0, gt2 = 0.0, gw0 = 0.0, gw1 = 0.0, gw2 = 0.0;
 
   // ---- A2: long-range, lanes own factor columns
-  if (dom && a.nchunk > 0) {
+  if (LONG && dom && a.nchunk > 0) {
     const int nm2 = a.n - 2;
     const int64_t cs = a.chunk_stride;
     for (int l = 0; l < L; ++l) {
@@ -384,14 +413,206 @@ __global__ __launch_bounds__(256) void k_score(const ScoreParams a) {
   }
   if (lane == 0) {
     const double nan = __builtin_nan("");
-    a.E[p] = dom ? eL + eS : nan;
-    if (a.El) a.El[p] = dom ? eL : nan;
     a.flags[p] = (uint8_t)(dom ? (RSD_FLAG_IN_DOMAIN | (mind >= a.sig2 ? RSD_FLAG_ACCEPT : 0u)) : 0u);
     a.counts[p] = cnt;
+    if (LONG) {
+      a.E[p] = dom ? eL + eS : nan;
+      if (a.El) a.El[p] = dom ? eL : nan;
+      if (GRAD) {
+        double* gp = a.grads + 6 * p;
+        gp[0] = dom ? gt0 : nan; gp[1] = dom ? gt1 : nan; gp[2] = dom ? gt2 : nan;
+        gp[3] = dom ? gw0 : nan; gp[4] = dom ? gw1 : nan; gp[5] = dom ? gw2 : nan;
+      }
+    } else {
+      a.es[p] = eS;
+      if (GRAD) {
+        double* gp = a.gs + 6 * p;
+        gp[0] = gt0; gp[1] = gt1; gp[2] = gt2; gp[3] = gw0; gp[4] = gw1; gp[5] = gw2;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- chunk-major long-range
+// A2 reorganised for the 8 XCDs: a work item is (rank chunk c, block of poses), and the
+// items are ordered chunk-major and dealt to XCDs in contiguous ranges (workgroup w runs
+// on XCD w % 8), so each XCD streams all poses against one chunk of the factors
+// (3 modes x n rows x 64 columns) while that chunk sits in its L2.  Every item writes,
+// per pose, its chunk's share of sum_l zeta_l P_long(y_l) (and of the gradient).
+struct LongParams {
+  const double* __restrict__ F;
+  int64_t mode_stride, chunk_stride;
+  int n, nchunk;
+  double X0, inv_h, smax;
+  const double4* __restrict__ lig;
+  int L;
+  const double* __restrict__ quats;
+  const double* __restrict__ trans;
+  int64_t P;
+  int ppw;                       // poses per wavefront
+  int64_t nblk;                  // pose blocks of 4 * ppw poses
+  int64_t items, per_xcd;
+  double* __restrict__ part;     // [nchunk][P][S], S = 1 (energy) or 7 (energy, dE/dt, dE/domega)
+};
+
+struct GridPt {                  // one ligand atom of one pose: grid rows and weights
+  double f0, f1, f2;
+  int i0, i1, i2, pad;
+};
+
+template <bool GRAD>
+__global__ __launch_bounds__(256) void k_long(const LongParams a) {
+  constexpr int S = GRAD ? 7 : 1;
+  extern __shared__ double4 smem[];
+  const int64_t j = blockIdx.x >> 3;
+  if (j >= a.per_xcd) return;
+  const int64_t item = (int64_t)(blockIdx.x & 7) * a.per_xcd + j;
+  if (item >= a.items) return;
+  const int c = (int)(item / a.nblk);
+  const int64_t p0 = (item % a.nblk) * (4 * a.ppw);
+  const int L = a.L;
+  const int PB = 4 * a.ppw;
+  double4* s_lig = smem;
+  GridPt* s_pt = (GridPt*)(smem + L);
+  double4* s_v = (double4*)(s_pt + PB * L);    // GRAD: R u_l per point
+  int* s_bad = (int*)(GRAD ? (void*)(s_v + PB * L) : (void*)s_v);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < L; i += 256) s_lig[i] = a.lig[i];
+  for (int i = tid; i < PB; i += 256) s_bad[i] = 0;
+  __syncthreads();
+  const int nm2 = a.n - 2;
+  for (int e = tid; e < PB * L; e += 256) {
+    const int lp = e / L, l = e - lp * L;
+    const int64_t p = p0 + lp;
+    GridPt g{};
+    bool ok = false;
+    if (p < a.P) {
+      double R[9], tv[3];
+      if (pose_frame(a.quats + 4 * p, a.trans + 3 * p, R, tv)) {
+        const double3 y = place(R, tv, s_lig[l]);
+        if (in_grid(y.x, a.X0, a.inv_h, a.smax) && in_grid(y.y, a.X0, a.inv_h, a.smax) &&
+            in_grid(y.z, a.X0, a.inv_h, a.smax)) {
+          const double s0 = (y.x - a.X0) * a.inv_h, s1 = (y.y - a.X0) * a.inv_h, s2 = (y.z - a.X0) * a.inv_h;
+          g.i0 = min((int)floor(s0), nm2);
+          g.i1 = min((int)floor(s1), nm2);
+          g.i2 = min((int)floor(s2), nm2);
+          g.f0 = s0 - (double)g.i0;
+          g.f1 = s1 - (double)g.i1;
+          g.f2 = s2 - (double)g.i2;
+          ok = true;
+          if (GRAD) s_v[e] = make_double4(y.x - tv[0], y.y - tv[1], y.z - tv[2], 0.0);
+        }
+      }
+    }
+    s_pt[e] = g;
+    if (!ok) atomicOr(&s_bad[lp], 1);
+  }
+  __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6;
+  const double* F0 = a.F + (int64_t)c * a.chunk_stride + lane;
+  const double* F1 = F0 + a.mode_stride;
+  const double* F2 = F1 + a.mode_stride;
+  for (int k = 0; k < a.ppw; ++k) {
+    const int lp = wv * a.ppw + k;
+    const int64_t p = p0 + lp;
+    if (p >= a.P) break;
+    double e = 0.0, gt0 = 0.0, gt1 = 0.0, gt2 = 0.0, gw0 = 0.0, gw1 = 0.0, gw2 = 0.0;
+    if (!s_bad[lp]) {
+      const GridPt* pts = s_pt + lp * L;
+      int l = 0;
+      for (; l + 4 <= L; l += 4) {
+        double A0[4], B0[4], A1[4], B1[4], A2[4], B2[4], f0[4], f1[4], f2[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const GridPt g = pts[l + u];
+          f0[u] = g.f0; f1[u] = g.f1; f2[u] = g.f2;
+          const double* q0 = F0 + (int64_t)g.i0 * kChunk;
+          const double* q1 = F1 + (int64_t)g.i1 * kChunk;
+          const double* q2 = F2 + (int64_t)g.i2 * kChunk;
+          A0[u] = q0[0]; B0[u] = q0[kChunk];
+          A1[u] = q1[0]; B1[u] = q1[kChunk];
+          A2[u] = q2[0]; B2[u] = q2[kChunk];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double d0 = B0[u] - A0[u], d1 = B1[u] - A1[u], d2 = B2[u] - A2[u];
+          const double l0 = fma(f0[u], d0, A0[u]), l1 = fma(f1[u], d1, A1[u]), l2 = fma(f2[u], d2, A2[u]);
+          const double zeta = s_lig[l + u].w;
+          const double l01 = l0 * l1;
+          e = fma(zeta, l01 * l2, e);
+          if (GRAD) {
+            const double zh = zeta * a.inv_h;
+            const double G0 = zh * (d0 * l1 * l2), G1 = zh * (l0 * d1 * l2), G2 = zh * (l01 * d2);
+            const double4 v = s_v[lp * L + l + u];
+            gt0 += G0; gt1 += G1; gt2 += G2;
+            gw0 += v.y * G2 - v.z * G1;
+            gw1 += v.z * G0 - v.x * G2;
+            gw2 += v.x * G1 - v.y * G0;
+          }
+        }
+      }
+      for (; l < L; ++l) {
+        const GridPt g = pts[l];
+        const double* q0 = F0 + (int64_t)g.i0 * kChunk;
+        const double* q1 = F1 + (int64_t)g.i1 * kChunk;
+        const double* q2 = F2 + (int64_t)g.i2 * kChunk;
+        const double A0 = q0[0], B0 = q0[kChunk], A1 = q1[0], B1 = q1[kChunk], A2 = q2[0], B2 = q2[kChunk];
+        const double d0 = B0 - A0, d1 = B1 - A1, d2 = B2 - A2;
+        const double l0 = fma(g.f0, d0, A0), l1 = fma(g.f1, d1, A1), l2 = fma(g.f2, d2, A2);
+        const double zeta = s_lig[l].w;
+        const double l01 = l0 * l1;
+        e = fma(zeta, l01 * l2, e);
+        if (GRAD) {
+          const double zh = zeta * a.inv_h;
+          const double G0 = zh * (d0 * l1 * l2), G1 = zh * (l0 * d1 * l2), G2 = zh * (l01 * d2);
+          const double4 v = s_v[lp * L + l];
+          gt0 += G0; gt1 += G1; gt2 += G2;
+          gw0 += v.y * G2 - v.z * G1;
+          gw1 += v.z * G0 - v.x * G2;
+          gw2 += v.x * G1 - v.y * G0;
+        }
+      }
+    }
+    e = wave_sum(e);
     if (GRAD) {
-      double* gp = a.grads + 6 * p;
-      gp[0] = dom ? gt0 : nan; gp[1] = dom ? gt1 : nan; gp[2] = dom ? gt2 : nan;
-      gp[3] = dom ? gw0 : nan; gp[4] = dom ? gw1 : nan; gp[5] = dom ? gw2 : nan;
+      gt0 = wave_sum(gt0); gt1 = wave_sum(gt1); gt2 = wave_sum(gt2);
+      gw0 = wave_sum(gw0); gw1 = wave_sum(gw1); gw2 = wave_sum(gw2);
+    }
+    if (lane == 0) {
+      double* o = a.part + ((int64_t)c * a.P + p) * S;
+      o[0] = e;
+      if (GRAD) {
+        o[1] = gt0; o[2] = gt1; o[3] = gt2; o[4] = gw0; o[5] = gw1; o[6] = gw2;
+      }
+    }
+  }
+}
+
+// E = sum_c part[c] + short part for poses in the grid; NaN otherwise (invalid poses keep
+// the NaN energy they need, their flags already say why).
+template <bool GRAD>
+__global__ void k_combine(const double* __restrict__ part, int nchunk, int64_t P, const double* __restrict__ es,
+                          const double* __restrict__ gs, const uint8_t* __restrict__ flags, double* __restrict__ E,
+                          double* __restrict__ El, double* __restrict__ grads) {
+  constexpr int S = GRAD ? 7 : 1;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+    const bool dom = (flags[p] & RSD_FLAG_IN_DOMAIN) != 0;
+    double acc[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) acc[k] = 0.0;
+    if (dom) {
+      for (int c = 0; c < nchunk; ++c) {
+        const double* o = part + ((int64_t)c * P + p) * S;
+#pragma unroll
+        for (int k = 0; k < S; ++k) acc[k] += o[k];
+      }
+    }
+    const double nan = __builtin_nan("");
+    E[p] = dom ? acc[0] + es[p] : nan;
+    if (El) El[p] = dom ? acc[0] : nan;
+    if (GRAD) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) grads[6 * p + k] = dom ? acc[1 + k] + gs[6 * p + k] : nan;
     }
   }
 }
@@ -402,12 +623,33 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   if (io.P == 0) return RSD_OK;
   const bool grad = io.grads != nullptr;
   const int L = io.L;
-  // workspace: centred ligand (L double4) + max radius
-  void* ws = nullptr;
-  RSD_TRY(ctx->workspace(sizeof(double4) * (size_t)L + 256, &ws));
-  double4* lig = (double4*)ws;
-  double* rlig = (double*)(lig + L);
+  const int64_t P = io.P;
   hipStream_t s = ctx->stream;
+
+  // long-range mode: fused (one wavefront does the whole pose) or chunk-major (k_long)
+  const int S = grad ? 7 : 1;
+  auto long_lds = [&](int ppw) {
+    const int PB = 4 * ppw;
+    return sizeof(double4) * (size_t)L + (size_t)PB * L * (sizeof(GridPt) + (grad ? sizeof(double4) : 0)) +
+           sizeof(int) * (size_t)PB;
+  };
+  int ppw = ctx->opt_poses_per_wave > 0 ? ctx->opt_poses_per_wave : 4;
+  while (ppw > 1 && long_lds(ppw) > 48 * 1024) --ppw;
+  bool split = t->nchunk > 0 && long_lds(ppw) <= 64 * 1024;
+  if (ctx->opt_score_mode == 1) split = false;
+  if (ctx->opt_score_mode == 0 && (t->nchunk < 2 || P < 256)) split = false;
+
+  // workspace: ligand (L double4) | radius | short energy (P) | short gradient (6P) | partials
+  const size_t off_r = sizeof(double4) * (size_t)L;
+  const size_t off_es = off_r + 256;
+  const size_t off_gs = off_es + sizeof(double) * (size_t)(split ? P : 0);
+  const size_t off_part = off_gs + sizeof(double) * (size_t)(split && grad ? 6 * P : 0);
+  const size_t total = off_part + sizeof(double) * (size_t)(split ? (int64_t)t->nchunk * P * S : 0);
+  void* ws = nullptr;
+  RSD_TRY(ctx->workspace(total, &ws));
+  char* w8 = (char*)ws;
+  double4* lig = (double4*)w8;
+  double* rlig = (double*)(w8 + off_r);
   RSD_TIMED_LAUNCH(ctx, "ligand_prep",
                    (k_ligand_prep<<<1, 64, 0, s>>>(io.lig_positions, io.lig_charges, L, lig, rlig)));
 
@@ -435,12 +677,14 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   a.L = L;
   a.quats = io.quats;
   a.trans = io.trans;
-  a.P = io.P;
+  a.P = P;
   a.E = io.E;
   a.El = io.El;
   a.flags = io.flags;
   a.counts = io.counts;
   a.grads = io.grads;
+  a.es = (double*)(w8 + off_es);
+  a.gs = (double*)(w8 + off_gs);
 
   const size_t pair_bytes = grad ? sizeof(PairG) : sizeof(PairE);
   int W = 4;
@@ -449,14 +693,49 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   };
   while (W > 1 && lds(W) > 64 * 1024) W >>= 1;
   RSD_CHECK(lds(W) <= 64 * 1024, RSD_E_UNSUPPORTED, "ligand of %d atoms needs too much LDS", L);
-  const int64_t blocks = (io.P + W - 1) / W;
+  const int64_t blocks = (P + W - 1) / W;
   RSD_CHECK(blocks <= 0x7fffffffLL, RSD_E_UNSUPPORTED, "too many poses in one call");
+  const dim3 g1((unsigned)blocks), b1(64 * W);
+  if (!split) {
+    if (grad) {
+      RSD_TIMED_LAUNCH(ctx, "score", (k_score<true, true><<<g1, b1, lds(W), s>>>(a)));
+    } else {
+      RSD_TIMED_LAUNCH(ctx, "score", (k_score<false, true><<<g1, b1, lds(W), s>>>(a)));
+    }
+    return RSD_OK;
+  }
+  LongParams lp{};
+  lp.F = t->F;
+  lp.chunk_stride = a.chunk_stride;
+  lp.mode_stride = a.mode_stride;
+  lp.n = t->n;
+  lp.nchunk = t->nchunk;
+  lp.X0 = t->X0;
+  lp.inv_h = t->inv_h;
+  lp.smax = a.smax;
+  lp.lig = lig;
+  lp.L = L;
+  lp.quats = io.quats;
+  lp.trans = io.trans;
+  lp.P = P;
+  lp.ppw = ppw;
+  lp.nblk = (P + 4 * ppw - 1) / (4 * ppw);
+  lp.items = lp.nblk * t->nchunk;
+  lp.per_xcd = (lp.items + 7) / 8;
+  lp.part = (double*)(w8 + off_part);
+  RSD_CHECK(lp.per_xcd * 8 <= 0x7fffffffLL, RSD_E_UNSUPPORTED, "too many poses in one call");
+  const dim3 g2((unsigned)(lp.per_xcd * 8));
+  const unsigned gc = (unsigned)std::min<int64_t>((P + 255) / 256, 65536);
   if (grad) {
-    RSD_TIMED_LAUNCH(ctx, "score",
-                     (k_score<true><<<(unsigned)blocks, 64 * W, lds(W), s>>>(a)));
+    RSD_TIMED_LAUNCH(ctx, "short", (k_score<true, false><<<g1, b1, lds(W), s>>>(a)));
+    RSD_TIMED_LAUNCH(ctx, "long", (k_long<true><<<g2, 256, long_lds(ppw), s>>>(lp)));
+    RSD_TIMED_LAUNCH(ctx, "combine", (k_combine<true><<<gc, 256, 0, s>>>(lp.part, t->nchunk, P, a.es, a.gs, io.flags,
+                                                                           io.E, io.El, io.grads)));
   } else {
-    RSD_TIMED_LAUNCH(ctx, "score",
-                     (k_score<false><<<(unsigned)blocks, 64 * W, lds(W), s>>>(a)));
+    RSD_TIMED_LAUNCH(ctx, "short", (k_score<false, false><<<g1, b1, lds(W), s>>>(a)));
+    RSD_TIMED_LAUNCH(ctx, "long", (k_long<false><<<g2, 256, long_lds(ppw), s>>>(lp)));
+    RSD_TIMED_LAUNCH(ctx, "combine", (k_combine<false><<<gc, 256, 0, s>>>(lp.part, t->nchunk, P, a.es, a.gs,
+                                                                            io.flags, io.E, io.El, nullptr)));
   }
   return RSD_OK;
 }

@@ -77,6 +77,7 @@ class Context:
         h = C.c_void_p()
         _check(_lib.lib().rsd_context_create(int(device), C.c_void_p(stream or 0), int(hbm_budget), C.byref(h)))
         self.handle = h
+        self._raw = h          # the library keeps a freed context alive while its tensors live
         self.device = device
 
     def set_stream(self, stream) -> None:
@@ -86,6 +87,9 @@ class Context:
         used, budget = C.c_size_t(), C.c_size_t()
         _check(_lib.lib().rsd_context_memory(self.handle, C.byref(used), C.byref(budget)))
         return used.value, budget.value
+
+    def set_option(self, name: str, value: int) -> None:
+        _check(_lib.lib().rsd_context_set_option(self.handle, name.encode(), int(value)))
 
     def set_timing(self, enable: bool) -> None:
         _check(_lib.lib().rsd_context_set_timing(self.handle, int(bool(enable))))

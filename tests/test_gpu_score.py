@@ -39,11 +39,13 @@ def cfg1(rs, ctx):
     tk, can = oracle_factors(cfg, wl)
     t = rs.tensor_import(ctx, can.F, cfg.n, cfg.b, rs.Sinc.from_config(cfg), wl.protein_charges,
                          wl.protein_positions)
-    return cfg, wl, can.F, t
+    yield cfg, wl, can.F, t
+    t.free()
 
 
-def _run(rs, ctx, t, wl, q, tr, sigma, grad=True, device=True):
+def _run(rs, ctx, t, wl, q, tr, sigma, grad=True, device=True, mode=0):
     import torch
+    ctx.set_option("score_mode", mode)
     if device:
         args = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in
                 (wl.ligand_charges, wl.ligand_positions, q, tr)]
@@ -54,36 +56,40 @@ def _run(rs, ctx, t, wl, q, tr, sigma, grad=True, device=True):
                           energies_long=True)
 
 
-def test_cfg1_parity_device_and_host_pointers(rs, ctx, cfg1):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_cfg1_parity_device_and_host_pointers(rs, ctx, cfg1, mode):
     cfg, wl, F, t = cfg1
     ref = oracle_score(cfg, wl, F, wl.quats, wl.trans, grad=True)
-    gd = _run(rs, ctx, t, wl, wl.quats, wl.trans, cfg.sigma, device=True)
+    gd = _run(rs, ctx, t, wl, wl.quats, wl.trans, cfg.sigma, device=True, mode=mode)
     assert_parity(gd, ref, grad=True, label="cfg1 device")
-    gh = _run(rs, ctx, t, wl, wl.quats, wl.trans, cfg.sigma, device=False)
+    gh = _run(rs, ctx, t, wl, wl.quats, wl.trans, cfg.sigma, device=False, mode=mode)
     assert_parity(gh, ref, grad=True, label="cfg1 host")
     for k in gd:
         assert np.array_equal(gd[k], gh[k], equal_nan=True), k
     assert np.all(ref["flags"] & 2)
 
 
-def test_cfg1_repeatable_bitwise(rs, ctx, cfg1):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_cfg1_repeatable_bitwise(rs, ctx, cfg1, mode):
     cfg, wl, F, t = cfg1
-    a = _run(rs, ctx, t, wl, wl.quats, wl.trans, cfg.sigma)
-    b = _run(rs, ctx, t, wl, wl.quats, wl.trans, cfg.sigma)
+    a = _run(rs, ctx, t, wl, wl.quats, wl.trans, cfg.sigma, mode=mode)
+    b = _run(rs, ctx, t, wl, wl.quats, wl.trans, cfg.sigma, mode=mode)
     for k in a:
         assert np.array_equal(a[k], b[k], equal_nan=True), k
 
 
-def test_cfg1_pose_alone_equals_pose_in_batch(rs, ctx, cfg1):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_cfg1_pose_alone_equals_pose_in_batch(rs, ctx, cfg1, mode):
     cfg, wl, F, t = cfg1
-    full = _run(rs, ctx, t, wl, wl.quats, wl.trans, cfg.sigma)
+    full = _run(rs, ctx, t, wl, wl.quats, wl.trans, cfg.sigma, mode=mode)
     for p in (0, 5, 127):
-        one = _run(rs, ctx, t, wl, wl.quats[p:p + 1], wl.trans[p:p + 1], cfg.sigma)
+        one = _run(rs, ctx, t, wl, wl.quats[p:p + 1], wl.trans[p:p + 1], cfg.sigma, mode=mode)
         for k in full:
             assert np.array_equal(one[k][0], full[k][p], equal_nan=True), (k, p)
 
 
-def test_cfg1_near_thresholds_and_edge_poses(rs, ctx, cfg1):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_cfg1_near_thresholds_and_edge_poses(rs, ctx, cfg1, mode):
     cfg, wl, F, t = cfg1
     # pull the ligand in so that it touches the protein, then pin pairs on sigma and r_cut
     tr = wl.trans * (15.5 / 18.0)
@@ -96,14 +102,15 @@ def test_cfg1_near_thresholds_and_edge_poses(rs, ctx, cfg1):
     q[-3] = [0.0, 0.0, 0.0, 0.0]    # not a unit quaternion -> invalid on the device path
     q[-4, 2] = np.nan
     ref = oracle_score(cfg, wl, F, q, tt, grad=True)
-    g = _run(rs, ctx, t, wl, q, tt, cfg.sigma)
+    g = _run(rs, ctx, t, wl, q, tt, cfg.sigma, mode=mode)
     assert_parity(g, ref, grad=True, label="cfg1 thresholds")
     assert ref["flags"][-3] == 4 and ref["flags"][-4] == 4 and ref["flags"][-1] == 0
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("R", [0, 1, 63, 64, 65, 130, 257])
 @pytest.mark.parametrize("L", [1, 7, 65, 200])
-def test_ragged_rank_and_ligand_sizes(rs, ctx, R, L):
+def test_ragged_rank_and_ligand_sizes(rs, ctx, R, L, mode):
     """Random factors (any factors are valid input) on a 96-point grid; R and L cross chunk edges."""
     g = np.random.default_rng(1000 + R * 7 + L)
     n, b = 96, 30.0
@@ -125,8 +132,8 @@ def test_ragged_rank_and_ligand_sizes(rs, ctx, R, L):
     import dataclasses
     c2 = dataclasses.replace(cfg, n=n, b=b, K_long=16, r_cut=9.5)
     ref = oracle_score(c2, W, F, q, tr, grad=True)
-    gpu = _run(rs, ctx, t, W, q, tr, cfg.sigma)
-    assert_parity(gpu, ref, grad=True, label=f"R={R} L={L}")
+    gpu = _run(rs, ctx, t, W, q, tr, cfg.sigma, mode=mode)
+    assert_parity(gpu, ref, grad=True, label=f"R={R} L={L} mode={mode}")
     t.free()
 
 
@@ -209,17 +216,44 @@ def cfg2(rs, ctx):
     tk, can = oracle_factors(cfg, wl)
     t = rs.tensor_import(ctx, can.F, cfg.n, cfg.b, rs.Sinc.from_config(cfg), wl.protein_charges,
                          wl.protein_positions)
-    return cfg, wl, can.F, t
+    yield cfg, wl, can.F, t
+    t.free()
 
 
 @pytest.mark.timeout(900)
-def test_cfg2_parity_4096_poses_and_thresholds(rs, ctx, cfg2):
+@pytest.mark.parametrize("mode", [2, 1])
+def test_cfg2_parity_4096_poses_and_thresholds(rs, ctx, cfg2, mode):
     cfg, wl, F, t = cfg2
     q1, t1 = near_threshold_poses(cfg, wl, wl.quats, wl.trans, cfg.sigma, 48)
     q2, t2 = near_threshold_poses(cfg, wl, wl.quats[48:], wl.trans[48:], cfg.r_cut, 48)
     q = np.concatenate([wl.quats, q1, q2])
     tr = np.concatenate([wl.trans, t1, t2])
     ref = oracle_score(cfg, wl, F, q, tr, grad=False)
-    g = _run(rs, ctx, t, wl, q, tr, cfg.sigma, grad=False)
-    worst = assert_parity(g, ref, label="cfg2")
+    g = _run(rs, ctx, t, wl, q, tr, cfg.sigma, grad=False, mode=mode)
+    worst = assert_parity(g, ref, label=f"cfg2 mode {mode}")
     print(f"cfg2 parity: worst energy error {worst:.3g} x tolerance; accept {np.mean(ref['flags'] & 1):.3f}")
+
+
+def test_context_freed_before_its_tensor(rs):
+    """rsd_context_free with live tensors defers the release to the last rsd_tensor_free."""
+    cfg = configs.CONFIG1
+    g = np.random.default_rng(9)
+    n, b = 32, 10.0
+    F = [g.normal(size=(n, 5)) for _ in range(3)]
+    pos = gen.ball_points(gen.rng(4, 1), 10, 3.0)
+    z = gen.charges(gen.rng(4, 2), 10, 0.3, True)
+    c = rs.Context(0)
+    t = rs.tensor_import(c, F, n, b, rs.Sinc(cfg.M, cfg.h_M, cfg.L_s, 12, 5.0, 1e-8), z, pos)
+    c.close()
+    with pytest.raises(rs.RsdError) as e:
+        rs.score_poses(_ClosedCtx(c), t, z[:2], pos[:2],
+                       gen.unit_quaternions(gen.rng(4, 5), 1), np.zeros((1, 3)), 2.5)
+    assert e.value.code == -1
+    t.free()
+
+
+class _ClosedCtx:
+    """Carries the raw handle of a context after close() to call into the library with it."""
+
+    def __init__(self, c):
+        self.handle = c._raw
