@@ -171,6 +171,8 @@ void rsd_tensor_free(rsd_tensor* t);
  *   "score_mode"      0 automatic, 1 one wavefront per pose for the whole pose,
  *                     2 long-range part in rank-chunk-major order across the XCDs
  *   "poses_per_wave"  poses per wavefront in mode 2 (0 automatic, 1..4)
+ *   "t2c_solver"      SVD of the Tucker core slices in the build: 0 automatic, 1 one-sided
+ *                     Jacobi with the slice in LDS, 2 rocSOLVER gesvd
  * Errors: RSD_E_INVALID for an unknown name or value. */
 rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t value);
 

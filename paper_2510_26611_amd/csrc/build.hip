@@ -316,6 +316,117 @@ __global__ void k_assemble(const double* __restrict__ U, int ldu, int r, const d
   }
 }
 
+// One-sided (Hestenes) Jacobi SVD of the mode-3 slices of the core, one workgroup per
+// slice held in LDS.  Column pairs are orthogonalised in the round-robin order (n/2
+// disjoint pairs per round, one wavefront per pair); a sweep is n-1 rounds; sweeps
+// stop when no pair needed a rotation.  Then column q of the rotated slice is
+// s_q u_q, and v_q = S^T u_q / s_q is taken from the original slice (v_q enters the
+// tensor only multiplied by s_q, so the division loses nothing that matters).
+// Output layout matches a thin LAPACK-style SVD with ns = n values per slice:
+// sv[c*n + q], u[c*m*n + q*m + a], vt[c*n*n + q + b*n].
+constexpr int kJacobiMaxElems = 18432;   // m * n doubles of one slice (144 KB of LDS)
+constexpr int kJacobiMaxSweeps = 80;
+
+__device__ __forceinline__ int rr_player(int pos, int round, int np) {
+  return pos == 0 ? 0 : 1 + (pos - 1 + round) % (np - 1);
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_svd(const double* __restrict__ S, int m, int n, double skip_rel2,
+                                                    double* __restrict__ sv, double* __restrict__ uv,
+                                                    double* __restrict__ vt, int* __restrict__ sweeps) {
+  extern __shared__ double sA[];
+  __shared__ int s_rot;
+  __shared__ double s_part[4];
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const double* Sc = S + (int64_t)c * m * n;
+  double fro = 0.0;
+  for (int e = tid; e < m * n; e += 256) {
+    const double x = Sc[e];
+    sA[e] = x;
+    fro = fma(x, x, fro);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) fro += __shfl_xor(fro, off, 64);
+  if (lane == 0) s_part[wv] = fro;
+  __syncthreads();
+  // columns below sqrt(skip_rel2) of the slice norm hold nothing above the truncation level;
+  // pairs involving them are left alone (rotating them only churns rounding noise)
+  const double skip = skip_rel2 * (s_part[0] + s_part[1] + s_part[2] + s_part[3]);
+  const int np = n + (n & 1);
+  // rotate a pair only when its cosine exceeds the rounding level of an m-term dot product
+  const double tol = fmax(1e-14, 4.0 * m * 1.1102230246251565e-16);
+  int sweep = 0;
+  for (; sweep < kJacobiMaxSweeps && n > 1; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int round = 0; round < np - 1; ++round) {
+      for (int k = wv; k < np / 2; k += 4) {
+        const int pa = rr_player(k, round, np), pb = rr_player(np - 1 - k, round, np);
+        const int p = min(pa, pb), q = max(pa, pb);
+        if (q >= n) continue;
+        double* ap = sA + p * m;
+        double* aq = sA + q * m;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int row = lane; row < m; row += 64) {
+          const double x = ap[row], y = aq[row];
+          al = fma(x, x, al);
+          be = fma(y, y, be);
+          ga = fma(x, y, ga);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          al += __shfl_xor(al, off, 64);
+          be += __shfl_xor(be, off, 64);
+          ga += __shfl_xor(ga, off, 64);
+        }
+        if (ga != 0.0 && fmin(al, be) > skip && fabs(ga) > tol * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          for (int row = lane; row < m; row += 64) {
+            const double x = ap[row], y = aq[row];
+            ap[row] = cs * x - sn * y;
+            aq[row] = sn * x + cs * y;
+          }
+          if (lane == 0) s_rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int rot = s_rot;
+    __syncthreads();
+    if (!rot) break;
+  }
+  if (tid == 0) sweeps[c] = sweep;
+  // singular values and normalised left vectors
+  for (int q = wv; q < n; q += 4) {
+    double s2 = 0.0;
+    for (int row = lane; row < m; row += 64) s2 = fma(sA[q * m + row], sA[q * m + row], s2);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+    const double sq = sqrt(s2);
+    const double inv = sq > 0.0 ? 1.0 / sq : 0.0;
+    for (int row = lane; row < m; row += 64) {
+      const double u = sA[q * m + row] * inv;
+      sA[q * m + row] = u;
+      uv[(int64_t)c * m * n + (int64_t)q * m + row] = u;
+    }
+    if (lane == 0) sv[(int64_t)c * n + q] = sq;
+  }
+  __syncthreads();
+  // v_q = S^T u_q / s_q
+  for (int e = tid; e < n * n; e += 256) {
+    const int q = e % n, bcol = e / n;
+    const double* scol = Sc + (int64_t)bcol * m;
+    const double* u = sA + q * m;
+    double w = 0.0;
+    for (int a = 0; a < m; ++a) w = fma(scol[a], u[a], w);
+    const double sq = sv[(int64_t)c * n + q];
+    vt[(int64_t)c * n * n + q + (int64_t)bcol * n] = sq > 0.0 ? w / sq : 0.0;
+  }
+}
+
 // ----------------------------------------------------------------- host helpers
 struct DevBuf {
   Context* ctx = nullptr;
@@ -396,17 +507,20 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
   // column chunks of the side matrix: at most ~1 GiB each
   const int64_t max_cols = std::max<int64_t>(TK, ((int64_t)1 << 27) / n / TK * TK);
   const int64_t chunk_cols = std::min<int64_t>(C, max_cols);
-  DevBuf Abuf, nu[3], inv_nu, G, Gpart, W, Ebuf;
+  DevBuf Abuf, nu[3], inv_nu[3], G3, Gpart, W3, E3;
   RSD_TRY(Abuf.alloc(ctx, (size_t)chunk_cols * n));
-  for (int d = 0; d < 3; ++d) RSD_TRY(nu[d].alloc(ctx, (size_t)C));
-  RSD_TRY(inv_nu.alloc(ctx, (size_t)C));
-  RSD_TRY(G.alloc(ctx, (size_t)n * n));
+  for (int d = 0; d < 3; ++d) {
+    RSD_TRY(nu[d].alloc(ctx, (size_t)C));
+    RSD_TRY(inv_nu[d].alloc(ctx, (size_t)C));
+  }
+  const int64_t nn = (int64_t)n * n;
+  RSD_TRY(G3.alloc(ctx, (size_t)(3 * nn)));
   const int Tn = div_up(n, TN);
   const int tri_tiles = Tn * (Tn + 1) / 2;
   const int gsplit = std::max(1, std::min(16, div_up(1024, tri_tiles)));
-  RSD_TRY(Gpart.alloc(ctx, (size_t)gsplit * n * n));
-  RSD_TRY(W.alloc(ctx, n));
-  RSD_TRY(Ebuf.alloc(ctx, n));
+  RSD_TRY(Gpart.alloc(ctx, (size_t)gsplit * nn));
+  RSD_TRY(W3.alloc(ctx, 3 * (size_t)n));
+  RSD_TRY(E3.alloc(ctx, 3 * (size_t)n));
   rocblas_int* d_info = nullptr;
   RSD_TRY(ctx->dev_alloc((void**)&d_info, 4096));
   struct InfoGuard {
@@ -419,35 +533,42 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
   int ldu[3] = {0, 0, 0};
   DevBuf U[3], Bt[3];
   const double h = t->h, b = t->b;
+  // 1. column norms and the Gram matrix of every mode, chunk by chunk
   for (int d = 0; d < 3; ++d) {
-    // 1. column norms and the Gram matrix, chunk by chunk
     RSD_TIMED_LAUNCH(ctx, "gen", (k_col_norms<<<div_up(C, 4), 256, 0, s>>>(d_pos, t2d.p, K, d, n, b, h, 0, C,
-                                                                             nu[d].p, inv_nu.p)));
+                                                                             nu[d].p, inv_nu[d].p)));
     RSD_HIP(hipMemsetAsync(Gpart.p, 0, Gpart.bytes, s));
     for (int64_t c0 = 0; c0 < C; c0 += chunk_cols) {
       const int64_t c1 = std::min(C, c0 + chunk_cols);
       RSD_TIMED_LAUNCH(ctx, "gen", (k_gen_columns<<<grid1d((c1 - c0) * n), 256, 0, s>>>(
-                                       d_pos, t2d.p, K, d, n, b, h, c0, c1, inv_nu.p, Abuf.p)));
+                                       d_pos, t2d.p, K, d, n, b, h, c0, c1, inv_nu[d].p, Abuf.p)));
       OpKM op{Abuf.p, n, n};
       GemmShape g{};
       g.M = n; g.N = n; g.K = c1 - c0;
       g.kper = (int64_t)div_up(g.K, (int64_t)gsplit * TK) * TK;
-      g.C = Gpart.p; g.ldc = n; g.split_stride = (int64_t)n * n;
+      g.C = Gpart.p; g.ldc = n; g.split_stride = nn;
       g.accumulate = 1; g.tri = 1;
       RSD_TRY(gemm(ctx, "gram", op, op, g, gsplit));
     }
-    RSD_TIMED_LAUNCH(ctx, "gram", (k_reduce_splits<<<grid1d((int64_t)n * n), 256, 0, s>>>(
-                                      Gpart.p, gsplit, (int64_t)n * n, n, n, n, G.p, n)));
-    // 2. eigenvectors (row-major upper tiles = column-major lower triangle)
+    RSD_TIMED_LAUNCH(ctx, "gram", (k_reduce_splits<<<grid1d(nn), 256, 0, s>>>(Gpart.p, gsplit, nn, n, n, n,
+                                                                                G3.p + d * nn, n)));
+  }
+  // 2. eigenvectors of the three Gram matrices in one batched call
+  //    (row-major upper tiles = column-major lower triangle)
+  {
     KernelTimer kt;
     if (ctx->timing) RSD_TRY(ctx->timer_begin("eig", &kt));
-    rocblas_status rs = rocsolver_dsyevd(hb, rocblas_evect_original, rocblas_fill_lower, n, G.p, n, W.p, Ebuf.p,
-                                         d_info);
-    RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dsyevd failed (%d)", (int)rs);
+    rocblas_status rs = rocsolver_dsyevd_strided_batched(hb, rocblas_evect_original, rocblas_fill_lower, n, G3.p, n,
+                                                         (rocblas_stride)nn, W3.p, (rocblas_stride)n, E3.p,
+                                                         (rocblas_stride)n, d_info, 3);
+    RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dsyevd_strided_batched failed (%d)", (int)rs);
     if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
-    RSD_TRY(check_info(ctx, d_info, 1, "symmetric eigensolver"));
-    std::vector<double> lam((size_t)n);
-    RSD_HIP(hipMemcpy(lam.data(), W.p, sizeof(double) * n, hipMemcpyDeviceToHost));
+  }
+  RSD_TRY(check_info(ctx, d_info, 3, "symmetric eigensolver"));
+  std::vector<double> lam3(3 * (size_t)n);
+  RSD_HIP(hipMemcpy(lam3.data(), W3.p, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
+  for (int d = 0; d < 3; ++d) {
+    const double* lam = lam3.data() + (size_t)d * n;
     const double lmax = lam[n - 1];
     RSD_CHECK(lmax > 0.0 && std::isfinite(lmax), RSD_E_NUMERIC, "Gram matrix of mode %d has no positive eigenvalue", d);
     int rd = 0;
@@ -456,12 +577,12 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
     r[d] = rd;
     ldu[d] = ((rd + 7) / 8) * 8;
     RSD_TRY(U[d].alloc(ctx, (size_t)n * ldu[d]));
-    RSD_TIMED_LAUNCH(ctx, "eig", (k_take_eigvecs<<<grid1d((int64_t)n * ldu[d]), 256, 0, s>>>(G.p, n, rd, U[d].p,
-                                                                                            ldu[d])));
+    RSD_TIMED_LAUNCH(ctx, "eig", (k_take_eigvecs<<<grid1d((int64_t)n * ldu[d]), 256, 0, s>>>(G3.p + d * nn, n, rd,
+                                                                                            U[d].p, ldu[d])));
     // 3. projection B_d^T[c][a] = sum_i A(i, c) U[i][a], side-matrix columns regenerated in LDS
     RSD_TRY(Bt[d].alloc(ctx, (size_t)C * ldu[d]));
     OpGauss ga{};
-    ga.pos = d_pos; ga.t2 = t2d.p; ga.inv_nu = inv_nu.p; ga.K = K; ga.d = d; ga.n = n; ga.b = b; ga.h = h;
+    ga.pos = d_pos; ga.t2 = t2d.p; ga.inv_nu = inv_nu[d].p; ga.K = K; ga.d = d; ga.n = n; ga.b = b; ga.h = h;
     ga.dim = (int)C;
     OpKM ub{U[d].p, ldu[d], rd};
     GemmShape g{};
@@ -496,30 +617,43 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
                                       Cpart.p, csplit, (int64_t)M12 * r[2], M12, r[2], r[2], beta.p, r[2])));
   }
 
-  // 5. Tucker -> canonical: batched SVD of the mode-3 slices (r1 x r2, column-major)
+  // 5. Tucker -> canonical: SVD of the mode-3 slices (r1 x r2, column-major)
   const int r1 = r[0], r2 = r[1], r3 = r[2];
-  const int mn = std::min(r1, r2);
+  const bool jacobi = ctx->opt_t2c == 2 ? false : (ctx->opt_t2c == 1 || (int64_t)r1 * r2 <= kJacobiMaxElems);
+  RSD_CHECK(!jacobi || (int64_t)r1 * r2 <= kJacobiMaxElems, RSD_E_UNSUPPORTED, "core slice too large for LDS");
+  const int ns = jacobi ? r2 : std::min(r1, r2);      // singular values per slice
   DevBuf S, Sv, Uv, Vv, Ev;
   RSD_TRY(S.alloc(ctx, (size_t)r1 * r2 * r3));
-  RSD_TRY(Sv.alloc(ctx, (size_t)mn * r3));
-  RSD_TRY(Uv.alloc(ctx, (size_t)r1 * mn * r3));
-  RSD_TRY(Vv.alloc(ctx, (size_t)mn * r2 * r3));
-  RSD_TRY(Ev.alloc(ctx, (size_t)mn * r3));
+  RSD_TRY(Sv.alloc(ctx, (size_t)ns * r3));
+  RSD_TRY(Uv.alloc(ctx, (size_t)r1 * ns * r3));
+  RSD_TRY(Vv.alloc(ctx, (size_t)ns * r2 * r3));
+  RSD_TRY(Ev.alloc(ctx, (size_t)ns * r3));
   RSD_TIMED_LAUNCH(ctx, "t2c", (k_core_slices<<<grid1d((int64_t)r1 * r2 * r3), 256, 0, s>>>(beta.p, r1, r2, r3,
                                                                                             r3, S.p)));
-  RSD_CHECK(r3 <= 4096, RSD_E_UNSUPPORTED, "too many core slices");
-  {
+  RSD_CHECK(r3 <= 1024, RSD_E_UNSUPPORTED, "too many core slices");
+  if (jacobi) {
+    RSD_HIP(hipFuncSetAttribute((const void*)k_jacobi_svd, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(double) * (size_t)r1 * r2)));
+    const double skip_rel2 = std::max(1e-3 * eps * 1e-3 * eps, 1e-30);
+    RSD_TIMED_LAUNCH(ctx, "t2c", (k_jacobi_svd<<<r3, 256, sizeof(double) * (size_t)r1 * r2, s>>>(
+                                     S.p, r1, r2, skip_rel2, Sv.p, Uv.p, Vv.p, (int*)d_info)));
+    std::vector<int> sw((size_t)r3);
+    RSD_HIP(hipMemcpyAsync(sw.data(), d_info, sizeof(int) * r3, hipMemcpyDeviceToHost, s));
+    RSD_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < r3; ++c)
+      RSD_CHECK(sw[c] < kJacobiMaxSweeps, RSD_E_NUMERIC, "Jacobi SVD of core slice %d did not converge", c);
+  } else {
     KernelTimer kt;
     if (ctx->timing) RSD_TRY(ctx->timer_begin("t2c", &kt));
     rocblas_status rs = rocsolver_dgesvd_strided_batched(
         hb, rocblas_svect_singular, rocblas_svect_singular, r1, r2, S.p, r1, (rocblas_stride)r1 * r2, Sv.p,
-        (rocblas_stride)mn, Uv.p, r1, (rocblas_stride)r1 * mn, Vv.p, mn, (rocblas_stride)mn * r2, Ev.p,
-        (rocblas_stride)mn, rocblas_outofplace, d_info, r3);
+        (rocblas_stride)ns, Uv.p, r1, (rocblas_stride)r1 * ns, Vv.p, ns, (rocblas_stride)ns * r2, Ev.p,
+        (rocblas_stride)ns, rocblas_outofplace, d_info, r3);
     RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dgesvd_strided_batched failed (%d)", (int)rs);
     if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+    RSD_TRY(check_info(ctx, d_info, r3, "slice SVD"));
   }
-  RSD_TRY(check_info(ctx, d_info, r3, "slice SVD"));
-  std::vector<double> sv((size_t)mn * r3), uv((size_t)r1 * mn * r3), vv((size_t)mn * r2 * r3);
+  std::vector<double> sv((size_t)ns * r3), uv((size_t)r1 * ns * r3), vv((size_t)ns * r2 * r3);
   RSD_HIP(hipMemcpy(sv.data(), Sv.p, sizeof(double) * sv.size(), hipMemcpyDeviceToHost));
   RSD_HIP(hipMemcpy(uv.data(), Uv.p, sizeof(double) * uv.size(), hipMemcpyDeviceToHost));
   RSD_HIP(hipMemcpy(vv.data(), Vv.p, sizeof(double) * vv.size(), hipMemcpyDeviceToHost));
@@ -527,17 +661,17 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
   for (double x : sv) smax = std::max(smax, x);
   std::vector<std::pair<int, int>> kept;
   for (int c = 0; c < r3; ++c)
-    for (int q = 0; q < mn; ++q)
-      if (sv[(size_t)c * mn + q] >= eps * smax && sv[(size_t)c * mn + q] > 0.0) kept.emplace_back(c, q);
+    for (int q = 0; q < ns; ++q)
+      if (sv[(size_t)c * ns + q] >= eps * smax && sv[(size_t)c * ns + q] > 0.0) kept.emplace_back(c, q);
   const int64_t R = (int64_t)kept.size();
   RSD_CHECK(R <= ((int64_t)1 << 20), RSD_E_UNSUPPORTED, "canonical rank %lld too large", (long long)R);
-  // V_d (r_d x R) on the host: column p = s*u (mode 1), v (mode 2), e_c (mode 3)
+  // V_d (r_d x R) on the host: columns p = s*u (mode 1), v (mode 2), e_c (mode 3)
   std::vector<double> V1((size_t)r1 * R), V2((size_t)r2 * R), V3((size_t)r3 * R, 0.0);
   for (int64_t p = 0; p < R; ++p) {
     const int c = kept[p].first, q = kept[p].second;
-    const double sq = sv[(size_t)c * mn + q];
-    for (int a = 0; a < r1; ++a) V1[(size_t)a * R + p] = sq * uv[(size_t)c * r1 * mn + (size_t)q * r1 + a];
-    for (int bb = 0; bb < r2; ++bb) V2[(size_t)bb * R + p] = vv[(size_t)c * mn * r2 + (size_t)bb * mn + q];
+    const double sq = sv[(size_t)c * ns + q];
+    for (int a = 0; a < r1; ++a) V1[(size_t)a * R + p] = sq * uv[(size_t)c * r1 * ns + (size_t)q * r1 + a];
+    for (int bb = 0; bb < r2; ++bb) V2[(size_t)bb * R + p] = vv[(size_t)c * ns * r2 + (size_t)bb * ns + q];
     V3[(size_t)c * R + p] = 1.0;
   }
   RSD_TRY(alloc_factors(ctx, t, R));

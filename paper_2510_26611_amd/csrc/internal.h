@@ -84,6 +84,7 @@ struct Context {
   // tuning options (rsd_context_set_option)
   int opt_score_mode = 0;      // 0 auto, 1 fused per-pose kernel, 2 chunk-major long-range kernel
   int opt_poses_per_wave = 0;  // chunk-major kernel: poses per wavefront (0 = automatic)
+  int opt_t2c = 0;             // core slice SVDs: 0 auto, 1 Jacobi in LDS, 2 rocSOLVER
   bool timing = false;
   std::vector<KernelTimer> pending;
   std::map<std::string, std::pair<int64_t, double>> ktime;

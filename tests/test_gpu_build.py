@@ -89,6 +89,22 @@ def test_cfg2_build_within_rhosvd_bound(rs, ctx):
     _check_build(rs, ctx, configs.CONFIG2, 512, "cfg2")
 
 
+def test_t2c_jacobi_and_library_svd_agree(rs, ctx):
+    """The two slice-SVD solvers give the same tensor to the truncation level."""
+    cfg = configs.CONFIG1
+    wl = configs.make(cfg, P=1)
+    F = []
+    for solver in (1, 2):
+        ctx.set_option("t2c_solver", solver)
+        t = rs.build_rs_tensor(ctx, wl.protein_charges, wl.protein_positions, cfg.n, cfg.b, rs.Sinc.from_config(cfg))
+        F.append(t.export())
+        t.free()
+    ctx.set_option("t2c_solver", 0)
+    idx = _nodes(cfg, 3000, 5)
+    a, b = _canon_at(F[0], idx), _canon_at(F[1], idx)
+    assert np.max(np.abs(a - b)) <= 1e-7 * np.max(np.abs(a))
+
+
 def test_build_argument_errors(rs, ctx):
     cfg = configs.CONFIG1
     wl = configs.make(cfg, P=1)
