@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFS = 78.6
 METRIC = "poses scored/sec at ≤1e-10 rel err vs FP64 oracle; served p50/p99 latency"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "score_cfg2_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "long_cfg2_traffic.json")
 SCORE_SRC = os.path.join(ROOT, "paper_2510_26611_amd", "csrc", "score.hip")
 
 
