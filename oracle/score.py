@@ -245,3 +245,76 @@ def score(F, n, b, atoms, z, t_short, w_short, r_cut, lig_charges, lig_positions
         out["grads"] = grads
         out["grad_scale"] = gscale
     return out
+
+
+def long_range_uncompressed(charges, positions, t_long, w_long, n: int, b: float, y: np.ndarray,
+                            want_grad: bool = False, corners_out: dict | None = None):
+    """Trilinear interpolant of the uncompressed long-range tensor T0 (eq. 2.6) at points y (Q, 3).
+
+    The 8 corner values of each point's grid cell are evaluated term by term from the
+    definition of T0; the value is sum_corners w0 w1 w2 T0(corner) with weights (1-f_d, f_d),
+    and its derivative along axis d replaces (1-f_d, f_d) by (-inv_h, +inv_h).  Points
+    outside the grid give NaN.  Used at sizes where the factor matrices of T0 are too large.
+    """
+    _, X0, inv_h, _ = _tensor.grid(n, b)
+    y = np.atleast_2d(y)
+    s = (y - X0) * inv_h
+    inside = np.all((s >= 0.0) & (s <= n - 1), axis=1)
+    val = np.full(y.shape[0], np.nan)
+    grad = np.full((y.shape[0], 3), np.nan) if want_grad else None
+    ok = np.nonzero(inside)[0]
+    if ok.size == 0:
+        return val, inside, grad
+    so = s[ok]
+    i = np.minimum(np.floor(so), n - 2).astype(np.int64)
+    f = so - i
+    corners = np.array([[a, bb, c] for a in (0, 1) for bb in (0, 1) for c in (0, 1)])
+    V = np.stack([_tensor.long_range_at_nodes(charges, positions, t_long, w_long, n, b, i + cr) for cr in corners],
+                 axis=1)                                              # (Q, 8)
+    wts = [np.stack([1.0 - f[:, d], f[:, d]], axis=1) for d in range(3)]
+    dws = np.array([-inv_h, inv_h])
+    W = np.stack([wts[0][:, a] * wts[1][:, bb] * wts[2][:, c] for a, bb, c in corners], axis=1)
+    val[ok] = np.sum(W * V, axis=1)
+    if corners_out is not None:   # node indices, node values and weights of every evaluated point
+        corners_out.update(points=ok, index=i[:, None, :] + corners[None, :, :], value=V, weight=W)
+    if want_grad:
+        G0 = np.stack([dws[a] * wts[1][:, bb] * wts[2][:, c] for a, bb, c in corners], axis=1)
+        G1 = np.stack([wts[0][:, a] * dws[bb] * wts[2][:, c] for a, bb, c in corners], axis=1)
+        G2 = np.stack([wts[0][:, a] * wts[1][:, bb] * dws[c] for a, bb, c in corners], axis=1)
+        grad[ok] = np.stack([np.sum(G0 * V, axis=1), np.sum(G1 * V, axis=1), np.sum(G2 * V, axis=1)], axis=1)
+    return val, inside, grad
+
+
+def score_uncompressed(charges, positions, t_long, w_long, n, b, t_short, w_short, r_cut, lig_charges,
+                       lig_positions, quats, trans, vdw_min, want_grad: bool = False, corners_out: dict | None = None):
+    """Energies, flags, counts (and gradients) of poses from the uncompressed tensor T0.
+
+    Same quantities as `score`, with the long-range part taken from the interpolant of T0
+    itself (no rank reduction); the short-range part, flags and counts are identical.
+    """
+    atoms = np.asarray(positions, dtype=np.float64)
+    z = np.asarray(charges, dtype=np.float64)
+    zeta = np.asarray(lig_charges, dtype=np.float64)
+    quats = np.atleast_2d(quats)
+    trans = np.atleast_2d(trans)
+    _, u = ligand_frame(lig_positions)
+    R = rotation_matrix(quats)
+    v = rotate(R, u)
+    y = v + trans[:, None, :]
+    P, L = y.shape[0], y.shape[1]
+    pts = y.reshape(-1, 3)
+    lv, inside, lg = long_range_uncompressed(z, atoms, t_long, w_long, n, b, pts, want_grad, corners_out)
+    sv, cnt, md2, _, sg, _ = short_range(atoms, z, t_short, w_short, r_cut, pts, want_grad)
+    inside = inside.reshape(P, L).all(axis=1)
+    E = np.where(inside, (zeta[None, :] * (lv + sv).reshape(P, L)).sum(axis=1), np.nan)
+    flags = np.where(inside, FLAG_IN_DOMAIN, 0) | np.where(inside & (md2.reshape(P, L).min(axis=1) >= vdw_min * vdw_min),
+                                                           FLAG_ACCEPT, 0)
+    valid = quat_valid(quats, trans)
+    flags = np.where(valid, flags, FLAG_INVALID).astype(np.uint8)
+    out = dict(E=np.where(valid, E, np.nan), flags=flags, counts=np.where(valid, cnt.reshape(P, L).sum(axis=1), 0))
+    if want_grad:
+        gp = (lg + sg).reshape(P, L, 3) * zeta[None, :, None]
+        g = np.concatenate([gp.sum(axis=1), np.cross(v, gp).sum(axis=1)], axis=1)
+        g[~(inside & valid)] = np.nan
+        out["grads"] = g
+    return out

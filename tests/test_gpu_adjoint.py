@@ -1,0 +1,210 @@
+"""GPU checks of the adjoint (dE/dt, dE/domega), the autograd wrapper and the projected-gradient
+driver, including the 10,000-atom / 60-atom / n=4096 workload at full size.
+
+Full-size parity is against the oracle's interpolant of the *uncompressed* tensor T0: per pose,
+|E_gpu - E_T0| <= sum_l |zeta_l| sum_corners w |T_gpu - T0|(corner) + 1e-10 * scale, with the
+node errors evaluated at exactly the corners the pose uses (the GPU's own trilinear evaluation
+of its factors matches the factor values to the 1e-10 parity shown elsewhere).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+from gpu_common import oracle_factors, oracle_score, sinc_parts  # noqa: E402
+from oracle import score as oscore, tensor as otensor  # noqa: E402
+from workloads import configs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2510_26611_amd as rs
+    ctx = rs.Context(0)
+    yield rs, ctx, torch
+    ctx.close()
+
+
+def _dev(torch, *arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
+
+
+def _straddles(cfg, u, q, t, hfd):
+    _, X0, inv_h, _ = otensor.grid(cfg.n, cfg.b)
+    y = oscore.transform(q[None], t[None], u)[0]
+    reach = hfd * (1.0 + np.max(np.linalg.norm(u, axis=1))) * 2.0
+    return bool(np.any(np.floor((y - reach - X0) * inv_h) != np.floor((y + reach - X0) * inv_h)))
+
+
+def test_autograd_gradients_equal_kernel_and_fd(env):
+    rs, ctx, torch = env
+    from paper_2510_26611_amd.autograd import pose_energy
+    cfg = configs.CONFIG1
+    wl = configs.make(cfg, P=32)
+    _, can = oracle_factors(cfg, wl)
+    t = rs.tensor_import(ctx, can.F, cfg.n, cfg.b, rs.Sinc.from_config(cfg), wl.protein_charges, wl.protein_positions)
+    lz, lx, q, tr = _dev(torch, wl.ligand_charges, wl.ligand_positions, wl.quats, wl.trans)
+    q.requires_grad_(True)
+    tr.requires_grad_(True)
+    E, flags, counts = pose_energy(ctx, t, lz, lx, q, tr, cfg.sigma)
+    wts = torch.linspace(0.5, 1.5, E.shape[0], dtype=torch.float64, device=E.device)
+    (E * wts).sum().backward()
+    g = rs.score_poses(ctx, t, lz, lx, q.detach(), tr.detach(), cfg.sigma, grads=True)["grads"]
+    assert torch.equal(tr.grad, wts[:, None] * g[:, :3])
+    # tangent quaternion gradient: directional derivative along random tangent directions
+    _, u = oscore.ligand_frame(wl.ligand_positions)
+    gen = np.random.default_rng(3)
+    hq = 1e-6
+    qn, gq = q.detach().cpu().numpy(), q.grad.cpu().numpy()
+    checked = 0
+    for p in range(8):
+        if _straddles(cfg, u, qn[p], wl.trans[p], 4 * hq):
+            continue
+        d = gen.normal(size=4)
+        d -= d.dot(qn[p]) * qn[p]
+        d /= np.linalg.norm(d)
+        qp = qn[p] + hq * d
+        qm = qn[p] - hq * d
+        Ep = oscore.score(can.F, cfg.n, cfg.b, wl.protein_positions, wl.protein_charges, *sinc_parts(cfg)[1], cfg.r_cut,
+                          wl.ligand_charges, wl.ligand_positions, (qp / np.linalg.norm(qp))[None], wl.trans[p:p + 1],
+                          cfg.sigma)["E"][0]
+        Em = oscore.score(can.F, cfg.n, cfg.b, wl.protein_positions, wl.protein_charges, *sinc_parts(cfg)[1], cfg.r_cut,
+                          wl.ligand_charges, wl.ligand_positions, (qm / np.linalg.norm(qm))[None], wl.trans[p:p + 1],
+                          cfg.sigma)["E"][0]
+        fd = (Ep - Em) / (2 * hq)
+        w = float(wts[p])
+        assert abs(gq[p] @ d / w - fd) <= 1e-5 * (abs(fd) + np.linalg.norm(gq[p]) / w) + 1e-9
+        checked += 1
+    assert checked >= 4
+    t.free()
+
+
+@pytest.fixture(scope="module")
+def cfg4(env):
+    rs, ctx, torch = env
+    cfg = configs.CONFIG4
+    wl = configs.make(cfg)
+    t = rs.build_rs_tensor(ctx, wl.protein_charges, wl.protein_positions, cfg.n, cfg.b, rs.Sinc.from_config(cfg))
+    yield cfg, wl, t
+    t.free()
+
+
+def _node_values(F, idx):
+    return np.sum(F[0][idx[..., 0]] * F[1][idx[..., 1]] * F[2][idx[..., 2]], axis=-1)
+
+
+@pytest.mark.timeout(900)
+def test_cfg4_full_size_energy_gradient_flags(env, cfg4):
+    rs, ctx, torch = env
+    cfg, wl, t = cfg4
+    info = t.query()
+    print(f"cfg4 tensor: ranks {info['ranks']} R={info['R']} bytes={info['bytes']}")
+    lz, lx, q, tr = _dev(torch, wl.ligand_charges, wl.ligand_positions, wl.quats, wl.trans)
+    out = rs.score_poses(ctx, t, lz, lx, q, tr, cfg.sigma, grads=True)
+    torch.cuda.synchronize()
+    E = out["E"].cpu().numpy()
+    G = out["grads"].cpu().numpy()
+    flags = out["flags"].cpu().numpy()
+    counts = out["counts"].cpu().numpy()
+    assert np.isfinite(E[(flags & 2) != 0]).all()
+    # sampled poses against the interpolant of the uncompressed tensor
+    (tl, wlong), (ts, ws) = sinc_parts(cfg)
+    sample = np.array([0, 1, 7, 1000, 40000, 65535])
+    corners = {}
+    ref = oscore.score_uncompressed(wl.protein_charges, wl.protein_positions, tl, wlong, cfg.n, cfg.b, ts, ws, cfg.r_cut,
+                                    wl.ligand_charges, wl.ligand_positions, wl.quats[sample], wl.trans[sample],
+                                    cfg.sigma, want_grad=True, corners_out=corners)
+    assert np.array_equal(flags[sample], ref["flags"])
+    assert np.array_equal(counts[sample], ref["counts"])
+    F = t.export()
+    dT = np.abs(_node_values(F, corners["index"]) - corners["value"])      # (points, 8)
+    print(f"cfg4 node error at the sampled corners: max {dT.max():.3e} (max |T0| {np.abs(corners['value']).max():.3e})")
+    assert dT.max() <= 20 * cfg.eps * np.abs(corners["value"]).max()
+    L = cfg.L
+    pt_err = np.zeros(len(sample) * L)
+    pt_err[corners["points"]] = np.sum(corners["weight"] * dT, axis=1)
+    inv_h = otensor.grid(cfg.n, cfg.b)[2]
+    g_err = np.zeros(len(sample) * L)
+    g_err[corners["points"]] = 2.0 * inv_h * np.max(dT, axis=1) * 3.0
+    zeta = np.abs(wl.ligand_charges)
+    _, u = oscore.ligand_frame(wl.ligand_positions)
+    rad = 1.0 + np.linalg.norm(u, axis=1)
+    for k, p in enumerate(sample):
+        if not (ref["flags"][k] & 2):
+            continue
+        be = np.sum(zeta * pt_err[k * L:(k + 1) * L]) + 1e-10 * np.sum(zeta) * 10
+        assert abs(E[p] - ref["E"][k]) <= be, (p, E[p], ref["E"][k], be)
+        bg = np.sum(zeta * rad * g_err[k * L:(k + 1) * L]) + 1e-9
+        assert np.all(np.abs(G[p] - ref["grads"][k]) <= bg), (p, G[p], ref["grads"][k], bg)
+    # central finite differences of the GPU energy (1e-5 A / 1e-5 rad) on poses whose stencil stays in one cell
+    h = 1e-5
+    cand = np.arange(0, 65536, 23)[:2000]
+    keep = [p for p in cand if (flags[p] & 2) and not _straddles(cfg, u, wl.quats[p], wl.trans[p], h)]
+    assert len(keep) > 100
+    keep = np.array(keep)
+    qs, ts_ = [], []
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = h
+        for sgn in (1, -1):
+            qs.append(wl.quats[keep])
+            ts_.append(wl.trans[keep] + sgn * e)
+    for i in range(3):
+        for sgn in (1, -1):
+            dq = np.zeros(4)
+            dq[0] = math.cos(h / 2)
+            dq[1 + i] = sgn * math.sin(h / 2)
+            qq = wl.quats[keep]
+            w1, v1 = dq[0], dq[1:]
+            prod = np.concatenate([(w1 * qq[:, 0] - qq[:, 1:] @ v1)[:, None],
+                                   w1 * qq[:, 1:] + qq[:, :1] * v1[None, :] + np.cross(v1[None, :], qq[:, 1:])], axis=1)
+            qs.append(prod / np.linalg.norm(prod, axis=1, keepdims=True))
+            ts_.append(wl.trans[keep])
+    Qa, Ta = _dev(torch, np.concatenate(qs), np.concatenate(ts_))
+    Ef = rs.score_poses(ctx, t, lz, lx, Qa, Ta, cfg.sigma)["E"].cpu().numpy().reshape(12, len(keep))
+    fd = np.stack([(Ef[2 * i] - Ef[2 * i + 1]) / (2 * h) for i in range(6)], axis=1)
+    ga = G[keep]
+    err = np.abs(fd - ga)
+    tol = 1e-6 * np.max(np.abs(ga), axis=1, keepdims=True) + 2e-16 * np.abs(E[keep])[:, None] / h * 4
+    print(f"cfg4 FD check on {len(keep)} poses: max |FD - adjoint| {err.max():.3e}")
+    assert np.all(err <= tol)
+
+
+@pytest.mark.timeout(900)
+def test_cfg4_projected_gradient_50_steps(env, cfg4):
+    rs, ctx, torch = env
+    from paper_2510_26611_amd.optim import projected_gradient
+    cfg, wl, t = cfg4
+    lz, lx, q, tr = _dev(torch, wl.ligand_charges, wl.ligand_positions, wl.quats, wl.trans)
+    res = projected_gradient(ctx, t, lz, lx, q, tr, cfg.sigma, steps=50)
+    torch.cuda.synchronize()
+    h0, h1 = res.history[0], res.history[-1]
+    print(f"PG: accepted {h0['accepted']} -> {h1['accepted']}, mean E {h0['mean_E']:.5f} -> {h1['mean_E']:.5f}")
+    assert h1["accepted"] >= h0["accepted"]
+    assert h1["mean_E"] < h0["mean_E"]
+    # parity at the GPU's own iterate: flags, counts and energies of sampled final poses
+    qf, tf = res.quats.cpu().numpy(), res.trans.cpu().numpy()
+    sample = np.array([3, 30000, 65000])
+    (tl, wlong), (ts, ws) = sinc_parts(cfg)
+    corners = {}
+    ref = oscore.score_uncompressed(wl.protein_charges, wl.protein_positions, tl, wlong, cfg.n, cfg.b, ts, ws, cfg.r_cut,
+                                    wl.ligand_charges, wl.ligand_positions, qf[sample], tf[sample], cfg.sigma,
+                                    corners_out=corners)
+    out = rs.score_poses(ctx, t, wl.ligand_charges, wl.ligand_positions, qf[sample], tf[sample], cfg.sigma)
+    assert np.array_equal(out["flags"], ref["flags"])
+    assert np.array_equal(out["counts"], ref["counts"])
+    F = t.export()
+    dT = np.abs(_node_values(F, corners["index"]) - corners["value"])
+    pt_err = np.zeros(len(sample) * cfg.L)
+    pt_err[corners["points"]] = np.sum(corners["weight"] * dT, axis=1)
+    zeta = np.abs(wl.ligand_charges)
+    for k in range(len(sample)):
+        if ref["flags"][k] & 2:
+            be = np.sum(zeta * pt_err[k * cfg.L:(k + 1) * cfg.L]) + 1e-9
+            assert abs(out["E"][k] - ref["E"][k]) <= be

@@ -270,3 +270,15 @@ def test_gradient_approaches_direct_forces_first_order():
         errs.append(np.max(np.abs(g - Gd)) / np.max(np.abs(Gd)))
     assert errs[1] < 0.05
     assert 1.5 < errs[0] / errs[1] < 3.0
+
+
+def test_uncompressed_interpolant_equals_canonical_evaluation():
+    """The corner-value form of the T0 interpolant equals the per-mode lerp of T0's own factors."""
+    s = Small(n=48, uncompressed=True, P=6)
+    out_f = s.score(grad=True)
+    out_u = score.score_uncompressed(s.z, s.pos, s.tl, s.wl, s.n, s.b, s.ts, s.ws, s.rc, s.zeta, s.lig,
+                                     s.q, s.t, 2.5, want_grad=True)
+    assert np.array_equal(out_f["flags"], out_u["flags"])
+    assert np.array_equal(out_f["counts"], out_u["counts"])
+    assert np.allclose(out_u["E"], out_f["E"], rtol=0, atol=1e-12 * np.max(out_f["scale"]))
+    assert np.allclose(out_u["grads"], out_f["grads"], rtol=0, atol=1e-11 * np.max(out_f["grad_scale"]))
