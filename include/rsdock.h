@@ -151,6 +151,37 @@ rsd_status rsd_score_poses(rsd_context* ctx, const rsd_tensor* tensor,
                            uint32_t mem_flags, double* energies, double* energies_long,
                            uint8_t* flags, int32_t* counts, double* grads);
 
+/* Many requests per launch.  A request is one rsd_score_poses call with device pointers
+ * and no gradients; the tensors may differ between requests but belong to one context.
+ * rsd_batch_create validates the requests, allocates the batch's device scratch (per-request
+ * ligand frames, short-range energies, long-range partials) and uploads a request table;
+ * it is synchronous.  rsd_batch_run enqueues four launches on the context stream that score
+ * every request (ligand frames; short-range, vdW and counts; long-range in rank-chunk-major
+ * order over all requests; combine); it allocates nothing and does not synchronise, so it
+ * may be captured in a HIP graph and replayed.  The request arrays are read at run time:
+ * new poses written into the same buffers are scored by the next run.  Each pose scores
+ * bit for bit as in rsd_score_poses with option score_mode = 2.
+ * Errors: RSD_E_INVALID, RSD_E_UNSUPPORTED (sizes), RSD_E_OOM, RSD_E_HIP. */
+typedef struct {
+  const rsd_tensor* tensor;
+  const double* lig_charges;    /* [L] */
+  const double* lig_positions;  /* [L*3] */
+  int64_t L;
+  const double* quats;          /* [P*4] */
+  const double* trans;          /* [P*3] */
+  int64_t P;                    /* >= 0 */
+  double vdw_min;
+  double* energies;             /* [P] */
+  double* energies_long;        /* [P] or NULL */
+  uint8_t* flags;               /* [P] */
+  int32_t* counts;              /* [P] */
+} rsd_request;
+
+typedef struct rsd_batch rsd_batch;
+rsd_status rsd_batch_create(rsd_context* ctx, const rsd_request* requests, int32_t n_requests, rsd_batch** out);
+rsd_status rsd_batch_run(rsd_batch* batch);
+void rsd_batch_free(rsd_batch* batch);
+
 /* Tensor metadata: grid size, canonical rank R, Tucker ranks (0 for imported tensors)
  * and resident device bytes.  Any output pointer may be NULL. */
 rsd_status rsd_tensor_query(const rsd_tensor* t, int32_t* n, int64_t* R, int32_t ranks[3],

@@ -28,13 +28,20 @@ EXPORTED = [
     "rsd_context_memory", "rsd_context_free", "rsd_build_rs_tensor", "rsd_tensor_import",
     "rsd_score_poses", "rsd_tensor_query", "rsd_tensor_export", "rsd_tensor_save",
     "rsd_tensor_load", "rsd_tensor_free", "rsd_context_set_timing", "rsd_kernel_time",
-    "rsd_context_set_option",
+    "rsd_context_set_option", "rsd_batch_create", "rsd_batch_run", "rsd_batch_free",
 ]
 
 
 class SincParams(C.Structure):
     _fields_ = [("M", C.c_int32), ("K_long", C.c_int32), ("h_M", C.c_double), ("L_s", C.c_double),
                 ("r_cut", C.c_double), ("eps", C.c_double)]
+
+
+class Request(C.Structure):
+    _fields_ = [("tensor", C.c_void_p), ("lig_charges", C.c_void_p), ("lig_positions", C.c_void_p),
+                ("L", C.c_int64), ("quats", C.c_void_p), ("trans", C.c_void_p), ("P", C.c_int64),
+                ("vdw_min", C.c_double), ("energies", C.c_void_p), ("energies_long", C.c_void_p),
+                ("flags", C.c_void_p), ("counts", C.c_void_p)]
 
 
 _P = C.c_void_p
@@ -66,6 +73,9 @@ def _declare(lib: C.CDLL) -> C.CDLL:
         "rsd_context_set_timing": (st, [_P, _I32]),
         "rsd_context_set_option": (st, [_P, C.c_char_p, _I64]),
         "rsd_kernel_time": (st, [_P, C.c_char_p, C.POINTER(_I64), C.POINTER(_D)]),
+        "rsd_batch_create": (st, [_P, C.POINTER(Request), _I32, C.POINTER(_P)]),
+        "rsd_batch_run": (st, [_P]),
+        "rsd_batch_free": (None, [_P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

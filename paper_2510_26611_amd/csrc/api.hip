@@ -614,6 +614,48 @@ rsd_status rsd_tensor_load(rsd_context* ctx, const char* path, rsd_tensor** out)
   return RSD_OK;
 }
 
+// ---------------------------------------------------------------- batches
+struct rsd_batch {
+  rsd::Batch* b;
+  rsd_context* ctx;
+};
+
+rsd_status rsd_batch_create(rsd_context* ctx, const rsd_request* requests, int32_t n_requests, rsd_batch** out) {
+  clear_error();
+  RSD_CHECK(out != nullptr, RSD_E_INVALID, "out is NULL");
+  *out = nullptr;
+  RSD_CHECK(ctx != nullptr && !ctx->closing, RSD_E_INVALID, "ctx is NULL or freed");
+  RSD_HIP(hipSetDevice(ctx->device));
+  rsd::Batch* b = nullptr;
+  RSD_TRY(rsd::batch_create(ctx, requests, n_requests, &b));
+  rsd_batch* h = new (std::nothrow) rsd_batch{b, ctx};
+  if (!h) {
+    rsd::batch_free(b);
+    set_error("host allocation failed");
+    return RSD_E_OOM;
+  }
+  ctx->live_tensors += 1;   // the batch keeps its context alive like a tensor does
+  *out = h;
+  return RSD_OK;
+}
+
+rsd_status rsd_batch_run(rsd_batch* batch) {
+  clear_error();
+  RSD_CHECK(batch != nullptr, RSD_E_INVALID, "batch is NULL");
+  RSD_HIP(hipSetDevice(batch->ctx->device));
+  return rsd::batch_run(batch->b);
+}
+
+void rsd_batch_free(rsd_batch* batch) {
+  if (!batch) return;
+  rsd_context* ctx = batch->ctx;
+  (void)hipSetDevice(ctx->device);
+  rsd::batch_free(batch->b);
+  delete batch;
+  ctx->live_tensors -= 1;
+  if (ctx->closing && ctx->live_tensors == 0) context_destroy(ctx);
+}
+
 // ---------------------------------------------------------------- tuning
 rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t value) {
   clear_error();

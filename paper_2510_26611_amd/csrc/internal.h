@@ -159,6 +159,12 @@ struct ScoreIO {
 };
 rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io);
 
+// many requests per launch (score.hip)
+struct Batch;
+rsd_status batch_create(Context* ctx, const rsd_request* req, int32_t nreq, Batch** out);
+rsd_status batch_run(Batch* b);
+void batch_free(Batch* b);
+
 // factor storage of a tensor with canonical rank R (api.hip)
 rsd_status alloc_factors(Context* ctx, Tensor* t, int64_t R);
 // rank reduction on the device (build.hip)

@@ -21,6 +21,9 @@
 // that decide flags, counts and grid rows are reproducible bit for bit by any
 // IEEE FP64 implementation that follows the same order.
 #include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
 
 #include "internal.h"
 
@@ -101,9 +104,8 @@ __device__ __forceinline__ int cell_floor(double v, int dim) {
 
 // Geometric centre c = (((0 + x_0) + x_1) + ...) / L and centred coordinates u_l = x_l - c;
 // also max |u_l|.  One wavefront.
-__global__ __launch_bounds__(64) void k_ligand_prep(const double* __restrict__ pos,
-                                                    const double* __restrict__ zeta, int L,
-                                                    double4* __restrict__ out, double* __restrict__ rlig) {
+__device__ void ligand_prep(const double* __restrict__ pos, const double* __restrict__ zeta, int L,
+                            double4* __restrict__ out, double* __restrict__ rlig) {
   __shared__ double c[3];
   const int lane = threadIdx.x;
   if (lane == 0) {
@@ -129,6 +131,12 @@ __global__ __launch_bounds__(64) void k_ligand_prep(const double* __restrict__ p
   }
   r2max = wave_min(-r2max);
   if (lane == 0) rlig[0] = sqrt(-r2max);
+}
+
+__global__ __launch_bounds__(64) void k_ligand_prep(const double* __restrict__ pos,
+                                                    const double* __restrict__ zeta, int L,
+                                                    double4* __restrict__ out, double* __restrict__ rlig) {
+  ligand_prep(pos, zeta, L, out, rlig);
 }
 
 // Rotation matrix of q = (w, x, y, z) in the fixed operation order shared by every kernel,
@@ -175,6 +183,11 @@ struct PairT<true> {
 // LONG = true: the whole pose (A1-A5) in one wavefront.  LONG = false: A1, A3, A4 only;
 // the short-range energy/gradient go to es/gs and k_combine adds the long-range partials.
 template <bool GRAD, bool LONG>
+__device__ void score_pose(const ScoreParams& a, const int64_t p, const double4* __restrict__ s_lig,
+                           double4* __restrict__ s_y, typename PairT<GRAD>::type* __restrict__ q,
+                           int* __restrict__ rowoff, int* __restrict__ rowstart, const int lane);
+
+template <bool GRAD, bool LONG>
 __global__ __launch_bounds__(256) void k_score(const ScoreParams a) {
   using Pair = typename PairT<GRAD>::type;
   extern __shared__ double4 smem[];
@@ -193,7 +206,16 @@ __global__ __launch_bounds__(256) void k_score(const ScoreParams a) {
   __syncthreads();
   const int64_t p = (int64_t)blockIdx.x * W + wv;
   if (p >= a.P) return;    // whole wavefront leaves; no block barrier follows
+  score_pose<GRAD, LONG>(a, p, s_lig, s_y, q, rowoff, rowstart, lane);
+}
 
+// One pose on one wavefront: A1, A3, A4 (and A2 when LONG), A5.
+template <bool GRAD, bool LONG>
+__device__ void score_pose(const ScoreParams& a, const int64_t p, const double4* __restrict__ s_lig,
+                           double4* __restrict__ s_y, typename PairT<GRAD>::type* __restrict__ q,
+                           int* __restrict__ rowoff, int* __restrict__ rowstart, const int lane) {
+  using Pair = typename PairT<GRAD>::type;
+  const int L = a.L;
   // ---- A1: pose frame and atom positions
   double R[9], tv[3];
   const bool valid = pose_frame(a.quats + 4 * p, a.trans + 3 * p, R, tv);
@@ -461,15 +483,22 @@ struct GridPt {                  // one ligand atom of one pose: grid rows and w
 };
 
 template <bool GRAD>
+__device__ void long_item(const LongParams& a, const int c, const int64_t p0, double4* smem);
+
+template <bool GRAD>
 __global__ __launch_bounds__(256) void k_long(const LongParams a) {
-  constexpr int S = GRAD ? 7 : 1;
   extern __shared__ double4 smem[];
   const int64_t j = blockIdx.x >> 3;
   if (j >= a.per_xcd) return;
   const int64_t item = (int64_t)(blockIdx.x & 7) * a.per_xcd + j;
   if (item >= a.items) return;
-  const int c = (int)(item / a.nblk);
-  const int64_t p0 = (item % a.nblk) * (4 * a.ppw);
+  long_item<GRAD>(a, (int)(item / a.nblk), (item % a.nblk) * (4 * a.ppw), smem);
+}
+
+// Chunk c of the long-range sum for the poses [p0, p0 + 4*ppw); the whole workgroup calls it.
+template <bool GRAD>
+__device__ void long_item(const LongParams& a, const int c, const int64_t p0, double4* smem) {
+  constexpr int S = GRAD ? 7 : 1;
   const int L = a.L;
   const int PB = 4 * a.ppw;
   double4* s_lig = smem;
@@ -591,68 +620,122 @@ __global__ __launch_bounds__(256) void k_long(const LongParams a) {
 // E = sum_c part[c] + short part for poses in the grid; NaN otherwise (invalid poses keep
 // the NaN energy they need, their flags already say why).
 template <bool GRAD>
+__device__ __forceinline__ void combine_pose(const double* __restrict__ part, int nchunk, int64_t P,
+                                             const double* __restrict__ es, const double* __restrict__ gs,
+                                             const uint8_t* __restrict__ flags, double* __restrict__ E,
+                                             double* __restrict__ El, double* __restrict__ grads, int64_t p) {
+  constexpr int S = GRAD ? 7 : 1;
+  const bool dom = (flags[p] & RSD_FLAG_IN_DOMAIN) != 0;
+  double acc[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) acc[k] = 0.0;
+  if (dom) {
+    for (int c = 0; c < nchunk; ++c) {
+      const double* o = part + ((int64_t)c * P + p) * S;
+#pragma unroll
+      for (int k = 0; k < S; ++k) acc[k] += o[k];
+    }
+  }
+  const double nan = __builtin_nan("");
+  E[p] = dom ? acc[0] + es[p] : nan;
+  if (El) El[p] = dom ? acc[0] : nan;
+  if (GRAD) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) grads[6 * p + k] = dom ? acc[1 + k] + gs[6 * p + k] : nan;
+  }
+}
+
+template <bool GRAD>
 __global__ void k_combine(const double* __restrict__ part, int nchunk, int64_t P, const double* __restrict__ es,
                           const double* __restrict__ gs, const uint8_t* __restrict__ flags, double* __restrict__ E,
                           double* __restrict__ El, double* __restrict__ grads) {
-  constexpr int S = GRAD ? 7 : 1;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
-    const bool dom = (flags[p] & RSD_FLAG_IN_DOMAIN) != 0;
-    double acc[S];
-#pragma unroll
-    for (int k = 0; k < S; ++k) acc[k] = 0.0;
-    if (dom) {
-      for (int c = 0; c < nchunk; ++c) {
-        const double* o = part + ((int64_t)c * P + p) * S;
-#pragma unroll
-        for (int k = 0; k < S; ++k) acc[k] += o[k];
-      }
-    }
-    const double nan = __builtin_nan("");
-    E[p] = dom ? acc[0] + es[p] : nan;
-    if (El) El[p] = dom ? acc[0] : nan;
-    if (GRAD) {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) grads[6 * p + k] = dom ? acc[1 + k] + gs[6 * p + k] : nan;
-    }
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x)
+    combine_pose<GRAD>(part, nchunk, P, es, gs, flags, E, El, grads, p);
+}
+
+// ---------------------------------------------------------------- many requests per launch
+// A batch scores requests with different tensors, ligands and pose counts in four launches
+// (ligand frames, short-range, long-range, combine) for all of them.  Workgroups find their
+// request by binary search over per-request prefix counts kept in the device table; the
+// long-range work list is request-major, chunk-major and dealt to the XCDs in contiguous
+// ranges exactly as for one request.  Every per-pose number is computed by the same
+// device functions as rsd_score_poses in chunk-major mode, so a pose scores bit for bit the
+// same alone and in a batch.
+struct BatchDesc {
+  ScoreParams sp;
+  LongParams lp;
+  const double* lig_pos;
+  const double* lig_z;
+  int64_t pose_base, short_base, long_base;
+};
+
+// last request r with key(r) <= x (requests with nothing to do share the next one's key)
+template <class Key>
+__device__ __forceinline__ int find_request(const BatchDesc* __restrict__ d, int nreq, int64_t x, Key key) {
+  int lo = 0, hi = nreq - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (key(d[mid]) <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(64) void k_batch_prep(const BatchDesc* __restrict__ d) {
+  const BatchDesc& r = d[blockIdx.x];
+  if (r.sp.P > 0) ligand_prep(r.lig_pos, r.lig_z, r.sp.L, const_cast<double4*>(r.sp.lig), const_cast<double*>(r.sp.rlig));
+}
+
+__global__ __launch_bounds__(256) void k_batch_short(const BatchDesc* __restrict__ d, int nreq) {
+  extern __shared__ double4 smem[];
+  const int64_t blk = blockIdx.x;
+  const int r = find_request(d, nreq, blk, [](const BatchDesc& x) { return x.short_base; });
+  const ScoreParams& a = d[r].sp;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int W = blockDim.x >> 6;
+  const int L = a.L;
+  double4* s_lig = smem;
+  double4* s_y = smem + L + (size_t)wv * L;
+  char* tail = (char*)(smem + (size_t)L * (1 + W));
+  PairE* q = (PairE*)(tail) + (size_t)wv * kQueue;
+  int* rowoff = (int*)(tail + sizeof(PairE) * kQueue * W) + wv * 128;
+  int* rowstart = rowoff + 64;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) s_lig[i] = a.lig[i];
+  __syncthreads();
+  const int64_t p = (blk - d[r].short_base) * W + wv;
+  if (p >= a.P) return;
+  score_pose<false, false>(a, p, s_lig, s_y, q, rowoff, rowstart, lane);
+}
+
+__global__ __launch_bounds__(256) void k_batch_long(const BatchDesc* __restrict__ d, int nreq, int64_t items,
+                                                    int64_t per_xcd) {
+  extern __shared__ double4 smem[];
+  const int64_t j = blockIdx.x >> 3;
+  if (j >= per_xcd) return;
+  const int64_t g = (int64_t)(blockIdx.x & 7) * per_xcd + j;
+  if (g >= items) return;
+  const int r = find_request(d, nreq, g, [](const BatchDesc& x) { return x.long_base; });
+  const LongParams& lp = d[r].lp;
+  const int64_t local = g - d[r].long_base;
+  long_item<false>(lp, (int)(local / lp.nblk), (local % lp.nblk) * (4 * lp.ppw), smem);
+}
+
+__global__ void k_batch_combine(const BatchDesc* __restrict__ d, int nreq, int64_t poses) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < poses; g += (int64_t)gridDim.x * blockDim.x) {
+    const int r = find_request(d, nreq, g, [](const BatchDesc& x) { return x.pose_base; });
+    const BatchDesc& x = d[r];
+    combine_pose<false>(x.lp.part, x.lp.nchunk, x.sp.P, x.sp.es, nullptr, x.sp.flags, x.sp.E, x.sp.El, nullptr,
+                        g - x.pose_base);
   }
 }
 
 }  // namespace
 
-rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
-  if (io.P == 0) return RSD_OK;
-  const bool grad = io.grads != nullptr;
-  const int L = io.L;
-  const int64_t P = io.P;
-  hipStream_t s = ctx->stream;
+namespace {
 
-  // long-range mode: fused (one wavefront does the whole pose) or chunk-major (k_long)
-  const int S = grad ? 7 : 1;
-  auto long_lds = [&](int ppw) {
-    const int PB = 4 * ppw;
-    return sizeof(double4) * (size_t)L + (size_t)PB * L * (sizeof(GridPt) + (grad ? sizeof(double4) : 0)) +
-           sizeof(int) * (size_t)PB;
-  };
-  int ppw = ctx->opt_poses_per_wave > 0 ? ctx->opt_poses_per_wave : 4;
-  while (ppw > 1 && long_lds(ppw) > 48 * 1024) --ppw;
-  bool split = t->nchunk > 0 && long_lds(ppw) <= 64 * 1024;
-  if (ctx->opt_score_mode == 1) split = false;
-  if (ctx->opt_score_mode == 0 && (t->nchunk < 2 || P < 256)) split = false;
-
-  // workspace: ligand (L double4) | radius | short energy (P) | short gradient (6P) | partials
-  const size_t off_r = sizeof(double4) * (size_t)L;
-  const size_t off_es = off_r + 256;
-  const size_t off_gs = off_es + sizeof(double) * (size_t)(split ? P : 0);
-  const size_t off_part = off_gs + sizeof(double) * (size_t)(split && grad ? 6 * P : 0);
-  const size_t total = off_part + sizeof(double) * (size_t)(split ? (int64_t)t->nchunk * P * S : 0);
-  void* ws = nullptr;
-  RSD_TRY(ctx->workspace(total, &ws));
-  char* w8 = (char*)ws;
-  double4* lig = (double4*)w8;
-  double* rlig = (double*)(w8 + off_r);
-  RSD_TIMED_LAUNCH(ctx, "ligand_prep",
-                   (k_ligand_prep<<<1, 64, 0, s>>>(io.lig_positions, io.lig_charges, L, lig, rlig)));
-
+// Scoring parameters of one request (both kernels' views); lig/rlig/es/gs/part are device scratch.
+ScoreParams make_score_params(const Tensor* t, const ScoreIO& io, const double4* lig, const double* rlig, double* es,
+                              double* gs) {
   ScoreParams a{};
   a.F = t->F;
   a.chunk_stride = (int64_t)t->n * kChunk;
@@ -674,70 +757,265 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   a.reach = t->sp.r_cut > io.vdw_min ? t->sp.r_cut : io.vdw_min;
   a.lig = lig;
   a.rlig = rlig;
-  a.L = L;
+  a.L = io.L;
   a.quats = io.quats;
   a.trans = io.trans;
-  a.P = P;
+  a.P = io.P;
   a.E = io.E;
   a.El = io.El;
   a.flags = io.flags;
   a.counts = io.counts;
   a.grads = io.grads;
-  a.es = (double*)(w8 + off_es);
-  a.gs = (double*)(w8 + off_gs);
+  a.es = es;
+  a.gs = gs;
+  return a;
+}
 
+size_t short_lds(int L, int W, bool grad) {
   const size_t pair_bytes = grad ? sizeof(PairG) : sizeof(PairE);
-  int W = 4;
-  auto lds = [&](int w) {
-    return sizeof(double4) * (size_t)L * (1 + w) + (size_t)w * (pair_bytes * kQueue + 128 * sizeof(int));
-  };
-  while (W > 1 && lds(W) > 64 * 1024) W >>= 1;
-  RSD_CHECK(lds(W) <= 64 * 1024, RSD_E_UNSUPPORTED, "ligand of %d atoms needs too much LDS", L);
-  const int64_t blocks = (P + W - 1) / W;
-  RSD_CHECK(blocks <= 0x7fffffffLL, RSD_E_UNSUPPORTED, "too many poses in one call");
-  const dim3 g1((unsigned)blocks), b1(64 * W);
-  if (!split) {
-    if (grad) {
-      RSD_TIMED_LAUNCH(ctx, "score", (k_score<true, true><<<g1, b1, lds(W), s>>>(a)));
-    } else {
-      RSD_TIMED_LAUNCH(ctx, "score", (k_score<false, true><<<g1, b1, lds(W), s>>>(a)));
-    }
-    return RSD_OK;
-  }
+  return sizeof(double4) * (size_t)L * (1 + W) + (size_t)W * (pair_bytes * kQueue + 128 * sizeof(int));
+}
+
+size_t long_lds(int L, int ppw, bool grad) {
+  const int PB = 4 * ppw;
+  return sizeof(double4) * (size_t)L + (size_t)PB * L * (sizeof(GridPt) + (grad ? sizeof(double4) : 0)) +
+         sizeof(int) * (size_t)PB;
+}
+
+int pick_ppw(int L, bool grad, int want) {
+  int ppw = want > 0 ? want : 4;
+  while (ppw > 1 && long_lds(L, ppw, grad) > 48 * 1024) --ppw;
+  return ppw;
+}
+
+LongParams make_long_params(const Tensor* t, const ScoreIO& io, const double4* lig, int ppw, double* part) {
   LongParams lp{};
   lp.F = t->F;
-  lp.chunk_stride = a.chunk_stride;
-  lp.mode_stride = a.mode_stride;
+  lp.chunk_stride = (int64_t)t->n * kChunk;
+  lp.mode_stride = (int64_t)t->nchunk * lp.chunk_stride;
   lp.n = t->n;
   lp.nchunk = t->nchunk;
   lp.X0 = t->X0;
   lp.inv_h = t->inv_h;
-  lp.smax = a.smax;
+  lp.smax = (double)(t->n - 1);
   lp.lig = lig;
-  lp.L = L;
+  lp.L = io.L;
   lp.quats = io.quats;
   lp.trans = io.trans;
-  lp.P = P;
+  lp.P = io.P;
   lp.ppw = ppw;
-  lp.nblk = (P + 4 * ppw - 1) / (4 * ppw);
+  lp.nblk = (io.P + 4 * ppw - 1) / (4 * ppw);
   lp.items = lp.nblk * t->nchunk;
   lp.per_xcd = (lp.items + 7) / 8;
-  lp.part = (double*)(w8 + off_part);
+  lp.part = part;
+  return lp;
+}
+
+}  // namespace
+
+rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
+  if (io.P == 0) return RSD_OK;
+  const bool grad = io.grads != nullptr;
+  const int L = io.L;
+  const int64_t P = io.P;
+  hipStream_t s = ctx->stream;
+
+  // long-range mode: fused (one wavefront does the whole pose) or chunk-major (k_long)
+  const int S = grad ? 7 : 1;
+  const int ppw = pick_ppw(L, grad, ctx->opt_poses_per_wave);
+  bool split = t->nchunk > 0 && long_lds(L, ppw, grad) <= 64 * 1024;
+  if (ctx->opt_score_mode == 1) split = false;
+  if (ctx->opt_score_mode == 0 && (t->nchunk < 2 || P < 256)) split = false;
+
+  // workspace: ligand (L double4) | radius | short energy (P) | short gradient (6P) | partials
+  const size_t off_r = sizeof(double4) * (size_t)L;
+  const size_t off_es = off_r + 256;
+  const size_t off_gs = off_es + sizeof(double) * (size_t)(split ? P : 0);
+  const size_t off_part = off_gs + sizeof(double) * (size_t)(split && grad ? 6 * P : 0);
+  const size_t total = off_part + sizeof(double) * (size_t)(split ? (int64_t)t->nchunk * P * S : 0);
+  void* ws = nullptr;
+  RSD_TRY(ctx->workspace(total, &ws));
+  char* w8 = (char*)ws;
+  double4* lig = (double4*)w8;
+  double* rlig = (double*)(w8 + off_r);
+  RSD_TIMED_LAUNCH(ctx, "ligand_prep",
+                   (k_ligand_prep<<<1, 64, 0, s>>>(io.lig_positions, io.lig_charges, L, lig, rlig)));
+  const ScoreParams a = make_score_params(t, io, lig, rlig, (double*)(w8 + off_es), (double*)(w8 + off_gs));
+
+  int W = 4;
+  while (W > 1 && short_lds(L, W, grad) > 64 * 1024) W >>= 1;
+  RSD_CHECK(short_lds(L, W, grad) <= 64 * 1024, RSD_E_UNSUPPORTED, "ligand of %d atoms needs too much LDS", L);
+  const int64_t blocks = (P + W - 1) / W;
+  RSD_CHECK(blocks <= 0x7fffffffLL, RSD_E_UNSUPPORTED, "too many poses in one call");
+  const dim3 g1((unsigned)blocks), b1(64 * W);
+  const size_t lds1 = short_lds(L, W, grad);
+  if (!split) {
+    if (grad) {
+      RSD_TIMED_LAUNCH(ctx, "score", (k_score<true, true><<<g1, b1, lds1, s>>>(a)));
+    } else {
+      RSD_TIMED_LAUNCH(ctx, "score", (k_score<false, true><<<g1, b1, lds1, s>>>(a)));
+    }
+    return RSD_OK;
+  }
+  const LongParams lp = make_long_params(t, io, lig, ppw, (double*)(w8 + off_part));
   RSD_CHECK(lp.per_xcd * 8 <= 0x7fffffffLL, RSD_E_UNSUPPORTED, "too many poses in one call");
   const dim3 g2((unsigned)(lp.per_xcd * 8));
+  const size_t lds2 = long_lds(L, ppw, grad);
   const unsigned gc = (unsigned)std::min<int64_t>((P + 255) / 256, 65536);
   if (grad) {
-    RSD_TIMED_LAUNCH(ctx, "short", (k_score<true, false><<<g1, b1, lds(W), s>>>(a)));
-    RSD_TIMED_LAUNCH(ctx, "long", (k_long<true><<<g2, 256, long_lds(ppw), s>>>(lp)));
+    RSD_TIMED_LAUNCH(ctx, "short", (k_score<true, false><<<g1, b1, lds1, s>>>(a)));
+    RSD_TIMED_LAUNCH(ctx, "long", (k_long<true><<<g2, 256, lds2, s>>>(lp)));
     RSD_TIMED_LAUNCH(ctx, "combine", (k_combine<true><<<gc, 256, 0, s>>>(lp.part, t->nchunk, P, a.es, a.gs, io.flags,
                                                                            io.E, io.El, io.grads)));
   } else {
-    RSD_TIMED_LAUNCH(ctx, "short", (k_score<false, false><<<g1, b1, lds(W), s>>>(a)));
-    RSD_TIMED_LAUNCH(ctx, "long", (k_long<false><<<g2, 256, long_lds(ppw), s>>>(lp)));
+    RSD_TIMED_LAUNCH(ctx, "short", (k_score<false, false><<<g1, b1, lds1, s>>>(a)));
+    RSD_TIMED_LAUNCH(ctx, "long", (k_long<false><<<g2, 256, lds2, s>>>(lp)));
     RSD_TIMED_LAUNCH(ctx, "combine", (k_combine<false><<<gc, 256, 0, s>>>(lp.part, t->nchunk, P, a.es, a.gs,
                                                                             io.flags, io.E, io.El, nullptr)));
   }
   return RSD_OK;
+}
+
+// ---------------------------------------------------------------- batches
+struct Batch {
+  Context* ctx = nullptr;
+  int nreq = 0;
+  void* mem = nullptr;
+  size_t bytes = 0;
+  BatchDesc* d = nullptr;
+  int W = 4;
+  size_t lds_short = 0, lds_long = 0;
+  int64_t short_blocks = 0, long_items = 0, per_xcd = 0, poses = 0;
+};
+
+rsd_status batch_create(Context* ctx, const rsd_request* req, int32_t nreq, Batch** out) {
+  *out = nullptr;
+  RSD_CHECK(nreq >= 1 && nreq <= 65536, RSD_E_INVALID, "request count %d outside [1, 65536]", nreq);
+  RSD_CHECK(req != nullptr, RSD_E_INVALID, "requests are NULL");
+  int maxL = 1;
+  for (int r = 0; r < nreq; ++r) {
+    const rsd_request& q = req[r];
+    RSD_CHECK(q.tensor != nullptr && static_cast<const Tensor*>(q.tensor)->ctx == ctx, RSD_E_INVALID,
+              "request %d: tensor missing or from another context", r);
+    RSD_CHECK(q.L >= 1 && q.L <= kMaxLigand, RSD_E_UNSUPPORTED, "request %d: L=%lld outside [1, %d]", r,
+              (long long)q.L, kMaxLigand);
+    RSD_CHECK(q.P >= 0 && q.P <= ((int64_t)1 << 31), RSD_E_INVALID, "request %d: P out of range", r);
+    RSD_CHECK(std::isfinite(q.vdw_min) && q.vdw_min >= 0, RSD_E_INVALID, "request %d: bad vdw_min", r);
+    RSD_CHECK(q.P == 0 || (q.lig_charges && q.lig_positions && q.quats && q.trans && q.energies && q.flags &&
+                           q.counts),
+              RSD_E_INVALID, "request %d: NULL pointer", r);
+    maxL = std::max(maxL, (int)q.L);
+  }
+  Batch* b = new (std::nothrow) Batch();
+  RSD_CHECK(b != nullptr, RSD_E_OOM, "host allocation failed");
+  b->ctx = ctx;
+  b->nreq = nreq;
+  while (b->W > 1 && short_lds(maxL, b->W, false) > 64 * 1024) b->W >>= 1;
+  // sizes and offsets of the scratch: table | ligands | radii | short energies | partials
+  std::vector<int64_t> off_lig(nreq), off_es(nreq), off_part(nreq);
+  std::vector<int> ppw(nreq);
+  int64_t nlig = 0, nes = 0, npart = 0;
+  for (int r = 0; r < nreq; ++r) {
+    const Tensor* t = static_cast<const Tensor*>(req[r].tensor);
+    off_lig[r] = nlig;
+    nlig += req[r].L;
+    off_es[r] = nes;
+    nes += req[r].P;
+    off_part[r] = npart;
+    npart += (int64_t)t->nchunk * req[r].P;
+    ppw[r] = pick_ppw((int)req[r].L, false, ctx->opt_poses_per_wave);
+    b->lds_long = std::max(b->lds_long, long_lds((int)req[r].L, ppw[r], false));
+  }
+  b->lds_short = short_lds(maxL, b->W, false);
+  const size_t sz_desc = sizeof(BatchDesc) * (size_t)nreq;
+  const size_t o_lig = (sz_desc + 255) / 256 * 256;
+  const size_t o_r = o_lig + sizeof(double4) * (size_t)nlig;
+  const size_t o_es = o_r + sizeof(double) * (size_t)nreq;
+  const size_t o_part = o_es + sizeof(double) * (size_t)nes;
+  b->bytes = o_part + sizeof(double) * (size_t)npart;
+  rsd_status st = ctx->dev_alloc(&b->mem, b->bytes);
+  if (st != RSD_OK) {
+    delete b;
+    return st;
+  }
+  char* m = (char*)b->mem;
+  std::vector<BatchDesc> h((size_t)nreq);
+  int64_t pb = 0, sb = 0, lb = 0;
+  for (int r = 0; r < nreq; ++r) {
+    const rsd_request& q = req[r];
+    const Tensor* t = static_cast<const Tensor*>(q.tensor);
+    ScoreIO io{};
+    io.lig_charges = q.lig_charges;
+    io.lig_positions = q.lig_positions;
+    io.L = (int)q.L;
+    io.quats = q.quats;
+    io.trans = q.trans;
+    io.P = q.P;
+    io.vdw_min = q.vdw_min;
+    io.E = q.energies;
+    io.El = q.energies_long;
+    io.flags = q.flags;
+    io.counts = q.counts;
+    io.grads = nullptr;
+    double4* lig = (double4*)(m + o_lig) + off_lig[r];
+    double* rlig = (double*)(m + o_r) + r;
+    double* es = (double*)(m + o_es) + off_es[r];
+    double* part = (double*)(m + o_part) + off_part[r];
+    h[r].sp = make_score_params(t, io, lig, rlig, es, nullptr);
+    h[r].lp = make_long_params(t, io, lig, ppw[r], part);
+    h[r].lig_pos = q.lig_positions;
+    h[r].lig_z = q.lig_charges;
+    h[r].pose_base = pb;
+    h[r].short_base = sb;
+    h[r].long_base = lb;
+    pb += q.P;
+    sb += (q.P + b->W - 1) / b->W;
+    lb += h[r].lp.items;
+  }
+  b->poses = pb;
+  b->short_blocks = sb;
+  b->long_items = lb;
+  b->per_xcd = (lb + 7) / 8;
+  b->d = (BatchDesc*)m;
+  if (sb > 0x7fffffffLL || b->per_xcd * 8 > 0x7fffffffLL) {
+    ctx->dev_free(b->mem, b->bytes);
+    delete b;
+    set_error("batch too large for one launch");
+    return RSD_E_UNSUPPORTED;
+  }
+  hipError_t e = hipMemcpyAsync(b->d, h.data(), sz_desc, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    ctx->dev_free(b->mem, b->bytes);
+    delete b;
+    set_error("batch upload: %s", hipGetErrorString(e));
+    return RSD_E_HIP;
+  }
+  *out = b;
+  return RSD_OK;
+}
+
+rsd_status batch_run(Batch* b) {
+  Context* ctx = b->ctx;
+  hipStream_t s = ctx->stream;
+  if (b->poses == 0) return RSD_OK;
+  RSD_TIMED_LAUNCH(ctx, "ligand_prep", (k_batch_prep<<<b->nreq, 64, 0, s>>>(b->d)));
+  RSD_TIMED_LAUNCH(ctx, "short", (k_batch_short<<<(unsigned)b->short_blocks, 64 * b->W, b->lds_short, s>>>(
+                                     b->d, b->nreq)));
+  if (b->long_items > 0) {
+    RSD_TIMED_LAUNCH(ctx, "long", (k_batch_long<<<(unsigned)(b->per_xcd * 8), 256, b->lds_long, s>>>(
+                                      b->d, b->nreq, b->long_items, b->per_xcd)));
+  }
+  const unsigned gc = (unsigned)std::min<int64_t>((b->poses + 255) / 256, 65536);
+  RSD_TIMED_LAUNCH(ctx, "combine", (k_batch_combine<<<gc, 256, 0, s>>>(b->d, b->nreq, b->poses)));
+  return RSD_OK;
+}
+
+void batch_free(Batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->ctx->stream);
+  b->ctx->dev_free(b->mem, b->bytes);
+  delete b;
 }
 
 }  // namespace rsd

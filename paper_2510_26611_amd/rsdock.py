@@ -219,3 +219,57 @@ def score_poses(ctx: Context, tensor: Tensor, lig_charges, lig_positions, quats,
     _check(_lib.lib().rsd_score_poses(ctx.handle, tensor.handle, zp, lp, L, qp, tp, P, float(vdw_min),
                                       RSD_DEVICE_PTRS if qdev else 0, ep, elp, fp, cp, gp))
     return out
+
+
+class Batch:
+    """rsd_batch: many requests (device tensors, energies only) scored by one set of launches.
+
+    `requests` is a list of dicts with keys tensor, lig_charges, lig_positions, quats, trans,
+    vdw_min and optionally out (dict of E, flags, counts[, E_long] device tensors; allocated
+    when absent).  run() only enqueues work, so it can be captured in a HIP graph.
+    """
+
+    def __init__(self, ctx: Context, requests: list):
+        import torch
+        self.ctx = ctx
+        self.requests = []
+        arr = (_lib.Request * len(requests))()
+        for i, r in enumerate(requests):
+            q, t = r["quats"], r["trans"]
+            P = int(q.shape[0])
+            out = r.get("out")
+            if out is None:
+                dev = q.device
+                out = dict(E=torch.empty(P, dtype=torch.float64, device=dev),
+                           flags=torch.empty(P, dtype=torch.uint8, device=dev),
+                           counts=torch.empty(P, dtype=torch.int32, device=dev))
+            keep = dict(r, out=out)
+            self.requests.append(keep)
+            for x in (r["lig_charges"], r["lig_positions"], q, t, out["E"]):
+                if not (_is_torch(x) and x.is_cuda and x.is_contiguous() and x.dtype == torch.float64):
+                    raise TypeError("batch arrays must be contiguous float64 device tensors")
+            arr[i] = _lib.Request(r["tensor"].handle.value, r["lig_charges"].data_ptr(), r["lig_positions"].data_ptr(),
+                                  int(r["lig_charges"].shape[0]), q.data_ptr(), t.data_ptr(), P,
+                                  float(r["vdw_min"]), out["E"].data_ptr(),
+                                  out["E_long"].data_ptr() if "E_long" in out else None,
+                                  out["flags"].data_ptr(), out["counts"].data_ptr())
+        h = C.c_void_p()
+        _check(_lib.lib().rsd_batch_create(ctx.handle, arr, len(requests), C.byref(h)))
+        self.handle = h
+
+    def run(self) -> None:
+        _check(_lib.lib().rsd_batch_run(self.handle))
+
+    def outputs(self) -> list:
+        return [r["out"] for r in self.requests]
+
+    def free(self) -> None:
+        if getattr(self, "handle", None):
+            _lib.lib().rsd_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
