@@ -82,6 +82,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--score-mode", type=int, default=0, help="0 automatic, 1 fused per-pose, 2 chunk-major")
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4"],
+                    help="cfg2 (default): one 5,000-atom protein, 1e6 poses; cfg1: 200 atoms, 128 poses; "
+                         "cfg3: 64 protein/ligand pairs batched; cfg4: 10,000 atoms, 65,536 poses with gradients")
+    ap.add_argument("--pairs", type=int, default=64, help="cfg3: number of protein/ligand pairs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="only run a device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -108,7 +112,10 @@ def main() -> int:
     import paper_2510_26611_amd as rs
     from workloads import configs
 
-    cfg = configs.CONFIG2
+    if args.workload == "cfg3":
+        return run_batched(args, rs, configs, torch, np, dev)
+    cfg = {"cfg1": configs.CONFIG1, "cfg2": configs.CONFIG2, "cfg4": configs.CONFIG4}[args.workload]
+    want_grad = args.workload == "cfg4"
     P = args.poses or cfg.P
     wl = configs.make(cfg, P=P)
     stream = torch.cuda.current_stream(dev)
@@ -120,6 +127,8 @@ def main() -> int:
     out = dict(E=torch.empty(P, dtype=torch.float64, device=dev),
                flags=torch.empty(P, dtype=torch.uint8, device=dev),
                counts=torch.empty(P, dtype=torch.int32, device=dev))
+    if want_grad:
+        out["grads"] = torch.empty((P, 6), dtype=torch.float64, device=dev)
     sinc = rs.Sinc.from_config(cfg)
     torch.cuda.synchronize()
 
@@ -128,7 +137,7 @@ def main() -> int:
     def step():
         t = rs.build_rs_tensor(ctx, d_z, d_x, cfg.n, cfg.b, sinc)
         info.update(t.query())
-        rs.score_poses(ctx, t, d_lz, d_lx, d_q, d_t, cfg.sigma, out=out)
+        rs.score_poses(ctx, t, d_lz, d_lx, d_q, d_t, cfg.sigma, out=out, grads=want_grad)
         t.free()   # frees after the scoring work queued on the stream has finished
 
     for _ in range(args.warmup):
@@ -153,7 +162,7 @@ def main() -> int:
     score_ms = sum(kt[k][1] for k in ("score", "long", "short", "combine", "ligand_prep")) / args.steps
     alg_bytes = P * (48.0 * cfg.L * R + 56)           # two factor rows per mode per atom + pose inputs
     achieved = alg_bytes / (dom_ms / 1e3) / 1e9
-    traffic = _traffic(P)
+    traffic = _traffic(P) if args.workload == "cfg2" else None
     flags = out["flags"].cpu().numpy()
     res = {
         "metric": METRIC, "value": P / (ms_step / 1e3), "unit": "poses/s", "n_gpus": 1,
@@ -183,9 +192,101 @@ def main() -> int:
         res["build_mfma"] = {"flops_per_build": gram + proj + core, "ms_per_build": mf,
                              "achieved_tflops": (gram + proj + core) / (mf / 1e3) / 1e12,
                              "peak_tflops": FP64_MFMA_PEAK_TFS}
-    if not args.no_cpu_baseline:
+    if want_grad:
+        res["metric"] = "poses scored/sec with energy + 6-DoF adjoint gradient at the oracle's tolerance"
+    if not args.no_cpu_baseline and args.workload == "cfg2":
         res["cpu_baseline"] = cpu_baseline(cfg, wl, args.cpu_sample)
     print(json.dumps(res), flush=True)
+    ctx.close()
+    return 0
+
+
+def run_batched(args, rs, configs, torch, np, dev) -> int:
+    """64 protein/ligand pairs (n=4096): per-request calls vs one batch vs a replayed HIP graph."""
+    pairs = configs.make_pairs(args.pairs)
+    cfg = configs.CONFIG3
+    stream = torch.cuda.current_stream(dev)
+    ctx = rs.Context(0, stream=stream.cuda_stream)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    sinc = rs.Sinc.from_config(cfg)
+    t0 = time.perf_counter()
+    tensors, reqs = [], []
+    for w in pairs:
+        t = rs.build_rs_tensor(ctx, to(w.protein_charges), to(w.protein_positions), cfg.n, cfg.b, sinc)
+        tensors.append(t)
+        P = w.cfg.P
+        reqs.append(dict(tensor=t, lig_charges=to(w.ligand_charges), lig_positions=to(w.ligand_positions),
+                         quats=to(w.quats), trans=to(w.trans), vdw_min=cfg.sigma,
+                         out=dict(E=torch.empty(P, dtype=torch.float64, device=dev),
+                                  flags=torch.empty(P, dtype=torch.uint8, device=dev),
+                                  counts=torch.empty(P, dtype=torch.int32, device=dev))))
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    total = sum(w.cfg.P for w in pairs)
+    Rs = [t.query()["R"] for t in tensors]
+    alg = sum(48.0 * w.cfg.L * R * w.cfg.P for w, R in zip(pairs, Rs))
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) / args.steps
+
+    def per_request():
+        for r in reqs:
+            rs.score_poses(ctx, r["tensor"], r["lig_charges"], r["lig_positions"], r["quats"], r["trans"],
+                           r["vdw_min"], out=r["out"])
+
+    ms_req = timed(per_request) * 1e3
+    ctx.set_timing(True)
+    per_request()
+    kt_req = {k: ctx.kernel_time(k) for k in ("ligand_prep", "short", "long", "combine", "score")}
+    ctx.set_timing(False)
+    batch = rs.Batch(ctx, reqs)
+    ms_batch = timed(batch.run) * 1e3
+    s = torch.cuda.Stream()
+    s.wait_stream(stream)
+    ctx.set_stream(s.cuda_stream)
+    with torch.cuda.stream(s):
+        batch.run()
+    s.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        batch.run()
+    ctx.set_stream(stream.cuda_stream)
+    ms_graph = timed(graph.replay) * 1e3
+    ctx.set_timing(True)
+    batch.run()
+    kt = {k: ctx.kernel_time(k) for k in ("ligand_prep", "short", "long", "combine")}
+    ctx.set_timing(False)
+    long_ms = kt["long"][1]
+    res = {
+        "metric": METRIC, "value": total / (ms_graph / 1e3), "unit": "poses/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"cfg3-{len(pairs)}pairs-n{cfg.n}", "pairs": len(pairs), "poses": total,
+                   "protein_atoms": [int(w.cfg.N) for w in pairs], "ligand_atoms": [int(w.cfg.L) for w in pairs],
+                   "canonical_ranks": Rs, "grid_n": cfg.n, "box_b_A": cfg.b,
+                   "parallelism": "single GPU, all requests in one set of launches"},
+        "per_request_poses_per_s": total / (ms_req / 1e3), "per_request_ms": ms_req,
+        "batch_poses_per_s": total / (ms_batch / 1e3), "batch_ms": ms_batch,
+        "graph_poses_per_s": total / (ms_graph / 1e3), "graph_ms": ms_graph,
+        "roofline": {"kernel": "long", "kernel_ms": long_ms, "bound": "hbm", "achieved": alg / (long_ms / 1e3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / (long_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None},
+        "breakdown": {k: {"launches": v[0], "ms": v[1]} for k, v in kt.items()},
+        "per_request_breakdown": {k: {"launches": v[0], "ms": v[1]} for k, v in kt_req.items() if v[0]},
+        "tensor_build_s_total": build_s,
+    }
+    print(json.dumps(res), flush=True)
+    del graph
+    batch.free()
+    for t in tensors:
+        t.free()
     ctx.close()
     return 0
 

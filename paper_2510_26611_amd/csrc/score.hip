@@ -666,7 +666,9 @@ struct BatchDesc {
   LongParams lp;
   const double* lig_pos;
   const double* lig_z;
-  int64_t pose_base, short_base, long_base;
+  int64_t pose_base;    // first pose of the request in the combine launch
+  int64_t short_base;   // first short-range block of the request within its ligand-size bucket
+  int64_t xcd_base;     // first long-range slot of the request on every XCD
 };
 
 // last request r with key(r) <= x (requests with nothing to do share the next one's key)
@@ -677,7 +679,7 @@ __device__ __forceinline__ int find_request(const BatchDesc* __restrict__ d, int
     const int mid = (lo + hi + 1) >> 1;
     if (key(d[mid]) <= x) lo = mid; else hi = mid - 1;
   }
-  return lo;
+  return __builtin_amdgcn_readfirstlane(lo);   // wave-uniform: the request table is then read with scalar loads
 }
 
 __global__ __launch_bounds__(64) void k_batch_prep(const BatchDesc* __restrict__ d) {
@@ -685,11 +687,13 @@ __global__ __launch_bounds__(64) void k_batch_prep(const BatchDesc* __restrict__
   if (r.sp.P > 0) ligand_prep(r.lig_pos, r.lig_z, r.sp.L, const_cast<double4*>(r.sp.lig), const_cast<double*>(r.sp.rlig));
 }
 
-__global__ __launch_bounds__(256) void k_batch_short(const BatchDesc* __restrict__ d, int nreq) {
+// Requests [first, first + nreq) of one ligand-size bucket (LDS sized for that bucket).
+__global__ __launch_bounds__(256) void k_batch_short(const BatchDesc* __restrict__ dall, int first, int nreq) {
   extern __shared__ double4 smem[];
+  const BatchDesc* d = dall + first;
   const int64_t blk = blockIdx.x;
   const int r = find_request(d, nreq, blk, [](const BatchDesc& x) { return x.short_base; });
-  const ScoreParams& a = d[r].sp;
+  const ScoreParams a = d[r].sp;   // by value: the fields then stay in registers inside the loops
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int W = blockDim.x >> 6;
@@ -707,17 +711,18 @@ __global__ __launch_bounds__(256) void k_batch_short(const BatchDesc* __restrict
   score_pose<false, false>(a, p, s_lig, s_y, q, rowoff, rowstart, lane);
 }
 
-__global__ __launch_bounds__(256) void k_batch_long(const BatchDesc* __restrict__ d, int nreq, int64_t items,
-                                                    int64_t per_xcd) {
+// Each request's work list is split into 8 contiguous parts, part x running on XCD x, exactly
+// as for a single request; XCD x walks its parts of the requests in order.
+__global__ __launch_bounds__(256) void k_batch_long(const BatchDesc* __restrict__ d, int nreq) {
   extern __shared__ double4 smem[];
   const int64_t j = blockIdx.x >> 3;
-  if (j >= per_xcd) return;
-  const int64_t g = (int64_t)(blockIdx.x & 7) * per_xcd + j;
-  if (g >= items) return;
-  const int r = find_request(d, nreq, g, [](const BatchDesc& x) { return x.long_base; });
-  const LongParams& lp = d[r].lp;
-  const int64_t local = g - d[r].long_base;
-  long_item<false>(lp, (int)(local / lp.nblk), (local % lp.nblk) * (4 * lp.ppw), smem);
+  const int r = find_request(d, nreq, j, [](const BatchDesc& x) { return x.xcd_base; });
+  const LongParams lp = d[r].lp;
+  const int64_t jl = j - d[r].xcd_base;
+  if (jl >= lp.per_xcd) return;
+  const int64_t item = (int64_t)(blockIdx.x & 7) * lp.per_xcd + jl;
+  if (item >= lp.items) return;
+  long_item<false>(lp, (int)(item / lp.nblk), (item % lp.nblk) * (4 * lp.ppw), smem);
 }
 
 __global__ void k_batch_combine(const BatchDesc* __restrict__ d, int nreq, int64_t poses) {
@@ -883,18 +888,25 @@ struct Batch {
   void* mem = nullptr;
   size_t bytes = 0;
   BatchDesc* d = nullptr;
-  int W = 4;
-  size_t lds_short = 0, lds_long = 0;
-  int64_t short_blocks = 0, long_items = 0, per_xcd = 0, poses = 0;
+  struct Bucket {
+    int first, count, W;
+    size_t lds;
+    int64_t blocks;
+  };
+  std::vector<Bucket> buckets;   // short-range launches, one per ligand-size class
+  size_t lds_long = 0;
+  int64_t long_slots = 0, poses = 0;
 };
 
-rsd_status batch_create(Context* ctx, const rsd_request* req, int32_t nreq, Batch** out) {
+// ligand-size classes for the short-range launches (LDS grows with L)
+static int ligand_bucket(int64_t L) { return L <= 32 ? 0 : L <= 64 ? 1 : L <= 128 ? 2 : L <= 256 ? 3 : 4; }
+
+rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, Batch** out) {
   *out = nullptr;
   RSD_CHECK(nreq >= 1 && nreq <= 65536, RSD_E_INVALID, "request count %d outside [1, 65536]", nreq);
-  RSD_CHECK(req != nullptr, RSD_E_INVALID, "requests are NULL");
-  int maxL = 1;
+  RSD_CHECK(req_in != nullptr, RSD_E_INVALID, "requests are NULL");
   for (int r = 0; r < nreq; ++r) {
-    const rsd_request& q = req[r];
+    const rsd_request& q = req_in[r];
     RSD_CHECK(q.tensor != nullptr && static_cast<const Tensor*>(q.tensor)->ctx == ctx, RSD_E_INVALID,
               "request %d: tensor missing or from another context", r);
     RSD_CHECK(q.L >= 1 && q.L <= kMaxLigand, RSD_E_UNSUPPORTED, "request %d: L=%lld outside [1, %d]", r,
@@ -904,29 +916,31 @@ rsd_status batch_create(Context* ctx, const rsd_request* req, int32_t nreq, Batc
     RSD_CHECK(q.P == 0 || (q.lig_charges && q.lig_positions && q.quats && q.trans && q.energies && q.flags &&
                            q.counts),
               RSD_E_INVALID, "request %d: NULL pointer", r);
-    maxL = std::max(maxL, (int)q.L);
   }
+  // table order: by ligand-size bucket (stable), so each short-range launch covers a contiguous range
+  std::vector<int> order((size_t)nreq);
+  for (int r = 0; r < nreq; ++r) order[r] = r;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return ligand_bucket(req_in[x].L) < ligand_bucket(req_in[y].L); });
   Batch* b = new (std::nothrow) Batch();
   RSD_CHECK(b != nullptr, RSD_E_OOM, "host allocation failed");
   b->ctx = ctx;
   b->nreq = nreq;
-  while (b->W > 1 && short_lds(maxL, b->W, false) > 64 * 1024) b->W >>= 1;
-  // sizes and offsets of the scratch: table | ligands | radii | short energies | partials
   std::vector<int64_t> off_lig(nreq), off_es(nreq), off_part(nreq);
   std::vector<int> ppw(nreq);
   int64_t nlig = 0, nes = 0, npart = 0;
-  for (int r = 0; r < nreq; ++r) {
-    const Tensor* t = static_cast<const Tensor*>(req[r].tensor);
-    off_lig[r] = nlig;
-    nlig += req[r].L;
-    off_es[r] = nes;
-    nes += req[r].P;
-    off_part[r] = npart;
-    npart += (int64_t)t->nchunk * req[r].P;
-    ppw[r] = pick_ppw((int)req[r].L, false, ctx->opt_poses_per_wave);
-    b->lds_long = std::max(b->lds_long, long_lds((int)req[r].L, ppw[r], false));
+  for (int k = 0; k < nreq; ++k) {
+    const rsd_request& q = req_in[order[k]];
+    const Tensor* t = static_cast<const Tensor*>(q.tensor);
+    off_lig[k] = nlig;
+    nlig += q.L;
+    off_es[k] = nes;
+    nes += q.P;
+    off_part[k] = npart;
+    npart += (int64_t)t->nchunk * q.P;
+    ppw[k] = pick_ppw((int)q.L, false, ctx->opt_poses_per_wave);
+    b->lds_long = std::max(b->lds_long, long_lds((int)q.L, ppw[k], false));
   }
-  b->lds_short = short_lds(maxL, b->W, false);
   const size_t sz_desc = sizeof(BatchDesc) * (size_t)nreq;
   const size_t o_lig = (sz_desc + 255) / 256 * 256;
   const size_t o_r = o_lig + sizeof(double4) * (size_t)nlig;
@@ -940,9 +954,9 @@ rsd_status batch_create(Context* ctx, const rsd_request* req, int32_t nreq, Batc
   }
   char* m = (char*)b->mem;
   std::vector<BatchDesc> h((size_t)nreq);
-  int64_t pb = 0, sb = 0, lb = 0;
-  for (int r = 0; r < nreq; ++r) {
-    const rsd_request& q = req[r];
+  int64_t pb = 0, xb = 0;
+  for (int k = 0; k < nreq; ++k) {
+    const rsd_request& q = req_in[order[k]];
     const Tensor* t = static_cast<const Tensor*>(q.tensor);
     ScoreIO io{};
     io.lig_charges = q.lig_charges;
@@ -957,27 +971,47 @@ rsd_status batch_create(Context* ctx, const rsd_request* req, int32_t nreq, Batc
     io.flags = q.flags;
     io.counts = q.counts;
     io.grads = nullptr;
-    double4* lig = (double4*)(m + o_lig) + off_lig[r];
-    double* rlig = (double*)(m + o_r) + r;
-    double* es = (double*)(m + o_es) + off_es[r];
-    double* part = (double*)(m + o_part) + off_part[r];
-    h[r].sp = make_score_params(t, io, lig, rlig, es, nullptr);
-    h[r].lp = make_long_params(t, io, lig, ppw[r], part);
-    h[r].lig_pos = q.lig_positions;
-    h[r].lig_z = q.lig_charges;
-    h[r].pose_base = pb;
-    h[r].short_base = sb;
-    h[r].long_base = lb;
+    double4* lig = (double4*)(m + o_lig) + off_lig[k];
+    double* rlig = (double*)(m + o_r) + k;
+    double* es = (double*)(m + o_es) + off_es[k];
+    double* part = (double*)(m + o_part) + off_part[k];
+    h[k].sp = make_score_params(t, io, lig, rlig, es, nullptr);
+    h[k].lp = make_long_params(t, io, lig, ppw[k], part);
+    h[k].lig_pos = q.lig_positions;
+    h[k].lig_z = q.lig_charges;
+    h[k].pose_base = pb;
+    h[k].xcd_base = xb;
     pb += q.P;
-    sb += (q.P + b->W - 1) / b->W;
-    lb += h[r].lp.items;
+    xb += h[k].lp.per_xcd;
+  }
+  // short-range buckets
+  for (int k = 0; k < nreq;) {
+    const int bk = ligand_bucket(req_in[order[k]].L);
+    int e = k;
+    int maxL = 1;
+    while (e < nreq && ligand_bucket(req_in[order[e]].L) == bk) maxL = std::max(maxL, (int)req_in[order[e++]].L);
+    Batch::Bucket bu{k, e - k, 4, 0, 0};
+    while (bu.W > 1 && short_lds(maxL, bu.W, false) > 64 * 1024) bu.W >>= 1;
+    bu.lds = short_lds(maxL, bu.W, false);
+    int64_t sb = 0;
+    for (int i = k; i < e; ++i) {
+      h[i].short_base = sb;
+      sb += (h[i].sp.P + bu.W - 1) / bu.W;
+    }
+    bu.blocks = sb;
+    if (sb > 0x7fffffffLL) {
+      ctx->dev_free(b->mem, b->bytes);
+      delete b;
+      set_error("batch too large for one launch");
+      return RSD_E_UNSUPPORTED;
+    }
+    if (sb > 0) b->buckets.push_back(bu);
+    k = e;
   }
   b->poses = pb;
-  b->short_blocks = sb;
-  b->long_items = lb;
-  b->per_xcd = (lb + 7) / 8;
+  b->long_slots = xb;
   b->d = (BatchDesc*)m;
-  if (sb > 0x7fffffffLL || b->per_xcd * 8 > 0x7fffffffLL) {
+  if (xb * 8 > 0x7fffffffLL) {
     ctx->dev_free(b->mem, b->bytes);
     delete b;
     set_error("batch too large for one launch");
@@ -1000,11 +1034,13 @@ rsd_status batch_run(Batch* b) {
   hipStream_t s = ctx->stream;
   if (b->poses == 0) return RSD_OK;
   RSD_TIMED_LAUNCH(ctx, "ligand_prep", (k_batch_prep<<<b->nreq, 64, 0, s>>>(b->d)));
-  RSD_TIMED_LAUNCH(ctx, "short", (k_batch_short<<<(unsigned)b->short_blocks, 64 * b->W, b->lds_short, s>>>(
-                                     b->d, b->nreq)));
-  if (b->long_items > 0) {
-    RSD_TIMED_LAUNCH(ctx, "long", (k_batch_long<<<(unsigned)(b->per_xcd * 8), 256, b->lds_long, s>>>(
-                                      b->d, b->nreq, b->long_items, b->per_xcd)));
+  for (const auto& bu : b->buckets) {
+    RSD_TIMED_LAUNCH(ctx, "short", (k_batch_short<<<(unsigned)bu.blocks, 64 * bu.W, bu.lds, s>>>(
+                                       b->d, bu.first, bu.count)));
+  }
+  if (b->long_slots > 0) {
+    RSD_TIMED_LAUNCH(ctx, "long", (k_batch_long<<<(unsigned)(b->long_slots * 8), 256, b->lds_long, s>>>(
+                                      b->d, b->nreq)));
   }
   const unsigned gc = (unsigned)std::min<int64_t>((b->poses + 255) / 256, 65536);
   RSD_TIMED_LAUNCH(ctx, "combine", (k_batch_combine<<<gc, 256, 0, s>>>(b->d, b->nreq, b->poses)));

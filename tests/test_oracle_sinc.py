@@ -47,7 +47,7 @@ def test_widest_terms_are_long_range():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("cfg", [configs.CONFIG1, configs.CONFIG2, configs.CONFIG4])
+@pytest.mark.parametrize("cfg", [configs.CONFIG1, configs.CONFIG2, configs.CONFIG3, configs.CONFIG4])
 def test_frozen_constants_rederived(cfg):
     assert cfg.L_s == pytest.approx(2.0 * math.sqrt(3.0) * cfg.b, rel=1e-15)
     assert constants.optimal_step(cfg.M, cfg.b) == cfg.h_M

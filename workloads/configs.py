@@ -68,7 +68,21 @@ CONFIG4 = Config(
     M=32, h_M=0.228, L_s=207.84609690826525, K_long=22, r_cut=16.833903442913364, eps=1e-8,
     P=65_536, pose_kind="shell", pose_r_in=_RP4 + 5.0, pose_r_out=_RP4 + 15.0, sigma=2.5)
 
-CONFIGS = {1: CONFIG1, 2: CONFIG2, 4: CONFIG4}
+# Config 3: 64 protein/ligand pairs; protein sizes log-uniform in [1e3, 2e4] atoms (density
+# 0.05 / A^3), ligand sizes uniform in [10, 200] atoms (ball radius 6 (L/50)^(1/3) A), pose
+# counts log-uniform in [1e3, 2e5], translations in the 5-15 A shell of each protein, n=4096.
+# One box for every pair: b = 73 A covers the largest protein (45.7 A) + 15 A + the largest
+# ligand (9.5 A) + 2 A, so one quadrature and cutoff serve all pairs.
+CONFIG3 = Config(
+    index=3, name="cfg3-64pairs-n4096", N=0, protein_radius=0.0, protein_charge_std=0.4, L=0, ligand_radius=0.0,
+    ligand_charge_std=0.4, n=4096, b=73.0, M=32, h_M=0.2335, L_s=252.87941790505607, K_long=22,
+    r_cut=18.15278338984615, eps=1e-8, P=0, pose_kind="shell", pose_r_in=0.0, pose_r_out=0.0, sigma=2.5)
+CONFIG3_PAIRS = 64
+CONFIG3_N = (1_000, 20_000)
+CONFIG3_L = (10, 200)
+CONFIG3_P = (1_000, 200_000)
+
+CONFIGS = {1: CONFIG1, 2: CONFIG2, 3: CONFIG3, 4: CONFIG4}
 
 
 @dataclass
@@ -99,3 +113,31 @@ def make(cfg: Config, P: int | None = None, **overrides) -> Workload:
     if P is not None:
         q, t = q[:P].copy(), t[:P].copy()
     return Workload(cfg, prot, z, lig, zeta, q, t)
+
+
+def make_pairs(pairs: int = CONFIG3_PAIRS, pose_scale: float = 1.0) -> list:
+    """Config 3 workload: `pairs` Workloads with their own protein, ligand and pose count.
+
+    Sizes and counts come from stream 7; pair i draws its atoms, charges and poses from
+    streams 1-6 with item index i.  pose_scale shrinks every pose count (tests)."""
+    cfg = CONFIG3
+    g = gen.rng(3, 7)
+    Ns = np.exp(g.uniform(np.log(CONFIG3_N[0]), np.log(CONFIG3_N[1]), pairs)).astype(int)
+    Ls = g.integers(CONFIG3_L[0], CONFIG3_L[1] + 1, pairs)
+    Ps = np.exp(g.uniform(np.log(CONFIG3_P[0]), np.log(CONFIG3_P[1]), pairs)).astype(int)
+    out = []
+    for i in range(pairs):
+        N, L = int(Ns[i]), int(Ls[i])
+        P = max(1, int(Ps[i] * pose_scale))
+        rp = gen.protein_radius(N, 0.05)
+        rl = 6.0 * (L / 50.0) ** (1.0 / 3.0)
+        c = replace(cfg, N=N, protein_radius=rp, L=L, ligand_radius=rl, P=P, pose_r_in=rp + 5.0,
+                    pose_r_out=rp + 15.0, name=f"cfg3-pair{i}")
+        prot = gen.ball_points(gen.rng(3, 1, i), N, rp)
+        z = gen.charges(gen.rng(3, 2, i), N, cfg.protein_charge_std, net_zero=True)
+        lig = gen.ball_points(gen.rng(3, 3, i), L, rl)
+        zeta = gen.charges(gen.rng(3, 4, i), L, cfg.ligand_charge_std, net_zero=False)
+        q = gen.unit_quaternions(gen.rng(3, 5, i), P)
+        t = gen.shell_translations(gen.rng(3, 6, i), P, c.pose_r_in, c.pose_r_out)
+        out.append(Workload(c, prot, z, lig, zeta, q, t))
+    return out

@@ -26,9 +26,13 @@ MIN_SEPARATION = 1.2  # Angstrom, minimum distance between atoms of one cluster
 _BATCH = 4096         # candidate batch size of the rejection sampler (fixed: part of the stream definition)
 
 
-def rng(config: int, stream: int) -> np.random.Generator:
-    """Generator for (config, stream); seed = 1000*config + stream."""
-    return np.random.Generator(np.random.PCG64(1000 * int(config) + int(stream)))
+def rng(config: int, stream: int, item: int | None = None) -> np.random.Generator:
+    """Generator for (config, stream); seed = 1000*config + stream.  Workloads made of many
+    independent items (protein/ligand pairs, requests) add the item index as a second seed word."""
+    base = 1000 * int(config) + int(stream)
+    if item is None:
+        return np.random.Generator(np.random.PCG64(base))
+    return np.random.Generator(np.random.PCG64([base, int(item)]))
 
 
 def ball_points(g: np.random.Generator, count: int, radius: float,
