@@ -202,6 +202,8 @@ void rsd_tensor_free(rsd_tensor* t);
  *   "score_mode"      0 automatic, 1 one wavefront per pose for the whole pose,
  *                     2 long-range part in rank-chunk-major order across the XCDs
  *   "poses_per_wave"  poses per wavefront in mode 2 (0 automatic, 1..4)
+ *   "eig_solver"      eigenvectors of the Gram matrices in the build: 0 automatic (subspace
+ *                     iteration for n >= 1024), 1 dense batched eigensolver, 2 subspace iteration
  *   "t2c_solver"      SVD of the Tucker core slices in the build: 0 automatic, 1 one-sided
  *                     Jacobi with the slice in LDS, 2 rocSOLVER gesvd
  * Errors: RSD_E_INVALID for an unknown name or value. */

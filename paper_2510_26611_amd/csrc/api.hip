@@ -670,6 +670,11 @@ rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t va
     ctx->opt_poses_per_wave = (int)value;
     return RSD_OK;
   }
+  if (std::strcmp(name, "eig_solver") == 0) {
+    RSD_CHECK(value >= 0 && value <= 2, RSD_E_INVALID, "eig_solver must be 0, 1 or 2");
+    ctx->opt_eig = (int)value;
+    return RSD_OK;
+  }
   if (std::strcmp(name, "t2c_solver") == 0) {
     RSD_CHECK(value >= 0 && value <= 2, RSD_E_INVALID, "t2c_solver must be 0, 1 or 2");
     ctx->opt_t2c = (int)value;

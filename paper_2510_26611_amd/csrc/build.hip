@@ -66,6 +66,22 @@ struct OpKM {                 // element (k, m) = p[k * ld + m]
   }
 };
 
+struct OpMK {                 // element (k, m) = p[m * ld + k]  (each m-row contiguous along k)
+  const double* __restrict__ p;
+  int64_t ld;
+  int dim;
+  __device__ void setup(int) {}
+  __device__ void fill(double* s, int64_t k0, int64_t k1, int m0) const {
+    const int t = threadIdx.x, mm = t >> 2, kk = (t & 3) * 8;
+    const int m = m0 + mm;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t k = k0 + kk + j;
+      s[(kk + j) * LDT + mm] = (m < dim && k < k1) ? p[(int64_t)m * ld + k] : 0.0;
+    }
+  }
+};
+
 struct OpKMScaled {           // element (k, m) = p[k * ld + m] * scale[k]
   const double* __restrict__ p;
   const double* __restrict__ scale;
@@ -277,6 +293,26 @@ __global__ void k_take_eigvecs(const double* __restrict__ Z, int n, int r, doubl
   }
 }
 
+// Mirror the computed upper tiles of a row-major symmetric matrix onto its lower part.
+__global__ void k_symmetrize(double* __restrict__ G, int n) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    if (i > j) G[e] = G[(int64_t)j * n + i];
+  }
+}
+
+// Deterministic test vectors in [-1, 1): splitmix64 of (seed, index).
+__global__ void k_random_fill(double* __restrict__ X, int64_t count, uint64_t seed) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(e + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    X[e] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+}
+
 // xi_c = z_m w_k nu1_c nu2_c nu3_c for column c = m*K + k.
 __global__ void k_weights(const double* __restrict__ z, const double* __restrict__ w, int K, int64_t C,
                           const double* __restrict__ nu1, const double* __restrict__ nu2,
@@ -470,6 +506,85 @@ rsd_status check_info(Context* ctx, rocblas_int* d_info, int count, const char* 
   return RSD_OK;
 }
 
+// Dominant eigenvectors of the symmetric PSD Gram matrix G (n x n, row-major, upper tiles
+// filled) by randomized subspace iteration: Y = G Omega, one power step, Q = orth(Y)
+// (Householder QR), Rayleigh-Ritz on Q^T G Q.  The subspace of k columns is doubled until its
+// k-th Ritz value lies below eps^2 times the largest, with 16 columns of margin, so every
+// eigenvalue that the rank rule keeps is inside it.  Output: U (n x ldu, row-major, first r
+// columns), eigenvalues descending in lam.
+rsd_status subspace_eigvecs(Context* ctx, rocblas_handle hb, double* G, int n, double eps, uint64_t seed,
+                            rocblas_int* d_info, DevBuf* U, int* r_out, int* ldu_out, std::vector<double>* lam) {
+  hipStream_t s = ctx->stream;
+  RSD_TIMED_LAUNCH(ctx, "eig", (k_symmetrize<<<grid1d((int64_t)n * n), 256, 0, s>>>(G, n)));
+  int k = std::min(n, 128);
+  for (;;) {
+    DevBuf Om, Y, Z, T, W, E, tau;
+    RSD_TRY(Om.alloc(ctx, (size_t)n * k));
+    RSD_TRY(Y.alloc(ctx, (size_t)n * k));
+    RSD_TRY(Z.alloc(ctx, (size_t)n * k));
+    RSD_TRY(T.alloc(ctx, (size_t)k * k));
+    RSD_TRY(W.alloc(ctx, k));
+    RSD_TRY(E.alloc(ctx, k));
+    RSD_TRY(tau.alloc(ctx, k));
+    RSD_TIMED_LAUNCH(ctx, "eig", (k_random_fill<<<grid1d((int64_t)n * k), 256, 0, s>>>(Om.p, (int64_t)n * k, seed)));
+    auto qr = [&](double* A) -> rsd_status {   // A: column-major n x k -> orthonormal Q in place
+      RSD_CHECK(rocsolver_dgeqrf(hb, n, k, A, n, tau.p) == rocblas_status_success, RSD_E_HIP, "rocsolver_dgeqrf failed");
+      RSD_CHECK(rocsolver_dorgqr(hb, n, k, k, A, n, tau.p) == rocblas_status_success, RSD_E_HIP, "rocsolver_dorgqr failed");
+      return RSD_OK;
+    };
+    GemmShape g{};
+    g.split_stride = 0; g.accumulate = 0; g.tri = 0;
+    // Y^T = Omega^T G  (k x n row-major = n x k column-major)
+    g.M = k; g.N = n; g.K = n; g.kper = ((int64_t)n + TK - 1) / TK * TK; g.C = Y.p; g.ldc = n;
+    RSD_TRY(gemm(ctx, "eig", OpKM{Om.p, k, k}, OpKM{G, n, n}, g, 1));
+    KernelTimer kt;
+    if (ctx->timing) RSD_TRY(ctx->timer_begin("eig", &kt));
+    RSD_TRY(qr(Y.p));
+    if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+    // one power step: Y^T = Q^T G, orthonormalise again
+    g.C = Z.p;
+    RSD_TRY(gemm(ctx, "eig", OpMK{Y.p, n, k}, OpKM{G, n, n}, g, 1));
+    if (ctx->timing) RSD_TRY(ctx->timer_begin("eig", &kt));
+    RSD_TRY(qr(Z.p));
+    if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+    // Rayleigh-Ritz: W^T = Q^T G (k x n), T = Q^T G Q (k x k)
+    g.C = Y.p;
+    RSD_TRY(gemm(ctx, "eig", OpMK{Z.p, n, k}, OpKM{G, n, n}, g, 1));
+    GemmShape gt = g;
+    gt.M = k; gt.N = k; gt.K = n; gt.C = T.p; gt.ldc = k;
+    RSD_TRY(gemm(ctx, "eig", OpMK{Z.p, n, k}, OpMK{Y.p, n, k}, gt, 1));
+    if (ctx->timing) RSD_TRY(ctx->timer_begin("eig", &kt));
+    rocblas_status rs = rocsolver_dsyevd(hb, rocblas_evect_original, rocblas_fill_upper, k, T.p, k, W.p, E.p, d_info);
+    RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dsyevd failed (%d)", (int)rs);
+    if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+    RSD_TRY(check_info(ctx, d_info, 1, "Ritz eigensolver"));
+    std::vector<double> w((size_t)k);
+    RSD_HIP(hipMemcpy(w.data(), W.p, sizeof(double) * k, hipMemcpyDeviceToHost));
+    const double lmax = w[k - 1];
+    RSD_CHECK(lmax > 0.0 && std::isfinite(lmax), RSD_E_NUMERIC, "Gram matrix has no positive eigenvalue");
+    int r = 0;
+    for (int i = k - 1; i >= 0 && w[i] >= eps * eps * lmax; --i) ++r;
+    if (r > k - 16 && k < n) {
+      k = std::min(n, 2 * k);
+      continue;
+    }
+    RSD_CHECK(r >= 1 && r <= 1024, RSD_E_UNSUPPORTED, "rank %d outside [1, 1024]", r);
+    const int ldu = ((r + 7) / 8) * 8;
+    DevBuf Vsel;
+    RSD_TRY(Vsel.alloc(ctx, (size_t)k * ldu));
+    RSD_TIMED_LAUNCH(ctx, "eig", (k_take_eigvecs<<<grid1d((int64_t)k * ldu), 256, 0, s>>>(T.p, k, r, Vsel.p, ldu)));
+    RSD_TRY(U->alloc(ctx, (size_t)n * ldu));
+    GemmShape gu = g;
+    gu.M = n; gu.N = r; gu.K = k; gu.kper = ((int64_t)k + TK - 1) / TK * TK; gu.C = U->p; gu.ldc = ldu;
+    RSD_TRY(gemm(ctx, "eig", OpKM{Z.p, n, n}, OpKM{Vsel.p, ldu, r}, gu, 1));
+    lam->assign(w.rbegin(), w.rend());
+    *r_out = r;
+    *ldu_out = ldu;
+    RSD_HIP(hipStreamSynchronize(s));
+    return RSD_OK;
+  }
+}
+
 }  // namespace
 
 rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const double* d_pos) {
@@ -553,9 +668,11 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
     RSD_TIMED_LAUNCH(ctx, "gram", (k_reduce_splits<<<grid1d(nn), 256, 0, s>>>(Gpart.p, gsplit, nn, n, n, n,
                                                                                 G3.p + d * nn, n)));
   }
-  // 2. eigenvectors of the three Gram matrices in one batched call
+  // 2. eigenvectors: randomized subspace iteration (large n) or one batched dense call
   //    (row-major upper tiles = column-major lower triangle)
-  {
+  const bool subspace = ctx->opt_eig == 2 || (ctx->opt_eig == 0 && n >= 1024);
+  std::vector<double> lam3(3 * (size_t)n, 0.0);
+  if (!subspace) {
     KernelTimer kt;
     if (ctx->timing) RSD_TRY(ctx->timer_begin("eig", &kt));
     rocblas_status rs = rocsolver_dsyevd_strided_batched(hb, rocblas_evect_original, rocblas_fill_lower, n, G3.p, n,
@@ -563,22 +680,29 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
                                                          (rocblas_stride)n, d_info, 3);
     RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dsyevd_strided_batched failed (%d)", (int)rs);
     if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+    RSD_TRY(check_info(ctx, d_info, 3, "symmetric eigensolver"));
+    RSD_HIP(hipMemcpy(lam3.data(), W3.p, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
   }
-  RSD_TRY(check_info(ctx, d_info, 3, "symmetric eigensolver"));
-  std::vector<double> lam3(3 * (size_t)n);
-  RSD_HIP(hipMemcpy(lam3.data(), W3.p, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
   for (int d = 0; d < 3; ++d) {
-    const double* lam = lam3.data() + (size_t)d * n;
-    const double lmax = lam[n - 1];
-    RSD_CHECK(lmax > 0.0 && std::isfinite(lmax), RSD_E_NUMERIC, "Gram matrix of mode %d has no positive eigenvalue", d);
-    int rd = 0;
-    for (int i = n - 1; i >= 0 && lam[i] >= eps * eps * lmax; --i) ++rd;
-    RSD_CHECK(rd >= 1 && rd <= 1024, RSD_E_UNSUPPORTED, "mode-%d rank %d outside [1, 1024]", d, rd);
-    r[d] = rd;
-    ldu[d] = ((rd + 7) / 8) * 8;
-    RSD_TRY(U[d].alloc(ctx, (size_t)n * ldu[d]));
-    RSD_TIMED_LAUNCH(ctx, "eig", (k_take_eigvecs<<<grid1d((int64_t)n * ldu[d]), 256, 0, s>>>(G3.p + d * nn, n, rd,
-                                                                                            U[d].p, ldu[d])));
+    if (subspace) {
+      std::vector<double> lam;
+      RSD_TRY(subspace_eigvecs(ctx, hb, G3.p + d * nn, n, eps, 0x5EEDull + (uint64_t)d, d_info, &U[d], &r[d],
+                               &ldu[d], &lam));
+    } else {
+      const double* lam = lam3.data() + (size_t)d * n;
+      const double lmax = lam[n - 1];
+      RSD_CHECK(lmax > 0.0 && std::isfinite(lmax), RSD_E_NUMERIC, "Gram matrix of mode %d has no positive eigenvalue",
+                d);
+      int rd = 0;
+      for (int i = n - 1; i >= 0 && lam[i] >= eps * eps * lmax; --i) ++rd;
+      RSD_CHECK(rd >= 1 && rd <= 1024, RSD_E_UNSUPPORTED, "mode-%d rank %d outside [1, 1024]", d, rd);
+      r[d] = rd;
+      ldu[d] = ((rd + 7) / 8) * 8;
+      RSD_TRY(U[d].alloc(ctx, (size_t)n * ldu[d]));
+      RSD_TIMED_LAUNCH(ctx, "eig", (k_take_eigvecs<<<grid1d((int64_t)n * ldu[d]), 256, 0, s>>>(G3.p + d * nn, n, rd,
+                                                                                              U[d].p, ldu[d])));
+    }
+    const int rd = r[d];
     // 3. projection B_d^T[c][a] = sum_i A(i, c) U[i][a], side-matrix columns regenerated in LDS
     RSD_TRY(Bt[d].alloc(ctx, (size_t)C * ldu[d]));
     OpGauss ga{};

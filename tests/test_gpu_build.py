@@ -105,6 +105,22 @@ def test_t2c_jacobi_and_library_svd_agree(rs, ctx):
     assert np.max(np.abs(a - b)) <= 1e-7 * np.max(np.abs(a))
 
 
+def test_eig_subspace_and_dense_agree(rs, ctx):
+    """Gram eigenvectors by subspace iteration and by the dense eigensolver give the same tensor."""
+    cfg = configs.CONFIG1
+    wl = configs.make(cfg, P=1)
+    F = []
+    for solver in (1, 2):
+        ctx.set_option("eig_solver", solver)
+        t = rs.build_rs_tensor(ctx, wl.protein_charges, wl.protein_positions, cfg.n, cfg.b, rs.Sinc.from_config(cfg))
+        F.append(t.export())
+        t.free()
+    ctx.set_option("eig_solver", 0)
+    idx = _nodes(cfg, 3000, 6)
+    a, b = _canon_at(F[0], idx), _canon_at(F[1], idx)
+    assert np.max(np.abs(a - b)) <= 1e-7 * np.max(np.abs(a))
+
+
 def test_build_argument_errors(rs, ctx):
     cfg = configs.CONFIG1
     wl = configs.make(cfg, P=1)
