@@ -29,7 +29,8 @@
  * Per-pose geometry is not an error: see RSD_FLAG_*.
  *
  * Threads.  A context and the tensors made with it may be used from one host
- * thread at a time.
+ * thread at a time.  A tensor may be scored through any context on its device (for
+ * example one context per stream); it must outlive every call and batch that uses it.
  */
 #ifndef RSDOCK_H
 #define RSDOCK_H
@@ -154,13 +155,14 @@ rsd_status rsd_score_poses(rsd_context* ctx, const rsd_tensor* tensor,
 /* Many requests per launch.  A request is one rsd_score_poses call with device pointers
  * and no gradients; the tensors may differ between requests but belong to one context.
  * rsd_batch_create validates the requests, allocates the batch's device scratch (per-request
- * ligand frames, short-range energies, long-range partials) and uploads a request table;
- * it is synchronous.  rsd_batch_run enqueues four launches on the context stream that score
+ * ligand frames, short-range energies, long-range partials) and enqueues the upload of a
+ * request table on the context stream (it returns without waiting for the device).  rsd_batch_run enqueues four launches on the context stream that score
  * every request (ligand frames; short-range, vdW and counts; long-range in rank-chunk-major
  * order over all requests; combine); it allocates nothing and does not synchronise, so it
  * may be captured in a HIP graph and replayed.  The request arrays are read at run time:
  * new poses written into the same buffers are scored by the next run.  Each pose scores
- * bit for bit as in rsd_score_poses with option score_mode = 2.
+ * bit for bit as in rsd_score_poses with option score_mode = 2.  The tensors may come from
+ * any context on the same device and must stay alive until the batch is freed.
  * Errors: RSD_E_INVALID, RSD_E_UNSUPPORTED (sizes), RSD_E_OOM, RSD_E_HIP. */
 typedef struct {
   const rsd_tensor* tensor;

@@ -435,7 +435,7 @@ rsd_status rsd_score_poses(rsd_context* ctx, const rsd_tensor* t, const double* 
   clear_error();
   RSD_CHECK(ctx != nullptr && t != nullptr, RSD_E_INVALID, "ctx or tensor is NULL");
   RSD_CHECK(!ctx->closing, RSD_E_INVALID, "context has been freed");
-  RSD_CHECK(t->ctx == ctx, RSD_E_INVALID, "tensor belongs to another context");
+  RSD_CHECK(t->ctx->device == ctx->device, RSD_E_INVALID, "tensor lives on another device");
   RSD_CHECK(L >= 1 && L <= kMaxLigand, RSD_E_UNSUPPORTED, "L=%lld outside [1, %d]", (long long)L, kMaxLigand);
   RSD_CHECK(P >= 0 && P <= ((int64_t)1 << 33), RSD_E_INVALID, "P=%lld out of range", (long long)P);
   RSD_CHECK(std::isfinite(vdw_min) && vdw_min >= 0, RSD_E_INVALID, "vdw_min must be finite and >= 0");

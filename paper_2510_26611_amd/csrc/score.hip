@@ -679,7 +679,14 @@ __device__ __forceinline__ int find_request(const BatchDesc* __restrict__ d, int
     const int mid = (lo + hi + 1) >> 1;
     if (key(d[mid]) <= x) lo = mid; else hi = mid - 1;
   }
-  return __builtin_amdgcn_readfirstlane(lo);   // wave-uniform: the request table is then read with scalar loads
+  return lo;
+}
+
+// find_request for a key that is the same in every lane (a workgroup index): the result is
+// then made wave-uniform so that the request table is read with scalar loads
+template <class Key>
+__device__ __forceinline__ int find_request_uniform(const BatchDesc* __restrict__ d, int nreq, int64_t x, Key key) {
+  return __builtin_amdgcn_readfirstlane(find_request(d, nreq, x, key));
 }
 
 __global__ __launch_bounds__(64) void k_batch_prep(const BatchDesc* __restrict__ d) {
@@ -692,7 +699,7 @@ __global__ __launch_bounds__(256) void k_batch_short(const BatchDesc* __restrict
   extern __shared__ double4 smem[];
   const BatchDesc* d = dall + first;
   const int64_t blk = blockIdx.x;
-  const int r = find_request(d, nreq, blk, [](const BatchDesc& x) { return x.short_base; });
+  const int r = find_request_uniform(d, nreq, blk, [](const BatchDesc& x) { return x.short_base; });
   const ScoreParams a = d[r].sp;   // by value: the fields then stay in registers inside the loops
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -716,7 +723,7 @@ __global__ __launch_bounds__(256) void k_batch_short(const BatchDesc* __restrict
 __global__ __launch_bounds__(256) void k_batch_long(const BatchDesc* __restrict__ d, int nreq) {
   extern __shared__ double4 smem[];
   const int64_t j = blockIdx.x >> 3;
-  const int r = find_request(d, nreq, j, [](const BatchDesc& x) { return x.xcd_base; });
+  const int r = find_request_uniform(d, nreq, j, [](const BatchDesc& x) { return x.xcd_base; });
   const LongParams lp = d[r].lp;
   const int64_t jl = j - d[r].xcd_base;
   if (jl >= lp.per_xcd) return;
@@ -896,6 +903,7 @@ struct Batch {
   std::vector<Bucket> buckets;   // short-range launches, one per ligand-size class
   size_t lds_long = 0;
   int64_t long_slots = 0, poses = 0;
+  std::vector<BatchDesc> host_table;   // source of the (asynchronous) table upload
 };
 
 // ligand-size classes for the short-range launches (LDS grows with L)
@@ -907,8 +915,8 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
   RSD_CHECK(req_in != nullptr, RSD_E_INVALID, "requests are NULL");
   for (int r = 0; r < nreq; ++r) {
     const rsd_request& q = req_in[r];
-    RSD_CHECK(q.tensor != nullptr && static_cast<const Tensor*>(q.tensor)->ctx == ctx, RSD_E_INVALID,
-              "request %d: tensor missing or from another context", r);
+    RSD_CHECK(q.tensor != nullptr && static_cast<const Tensor*>(q.tensor)->ctx->device == ctx->device, RSD_E_INVALID,
+              "request %d: tensor missing or on another device", r);
     RSD_CHECK(q.L >= 1 && q.L <= kMaxLigand, RSD_E_UNSUPPORTED, "request %d: L=%lld outside [1, %d]", r,
               (long long)q.L, kMaxLigand);
     RSD_CHECK(q.P >= 0 && q.P <= ((int64_t)1 << 31), RSD_E_INVALID, "request %d: P out of range", r);
@@ -1017,8 +1025,8 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     set_error("batch too large for one launch");
     return RSD_E_UNSUPPORTED;
   }
-  hipError_t e = hipMemcpyAsync(b->d, h.data(), sz_desc, hipMemcpyHostToDevice, ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  b->host_table = std::move(h);
+  hipError_t e = hipMemcpyAsync(b->d, b->host_table.data(), sz_desc, hipMemcpyHostToDevice, ctx->stream);
   if (e != hipSuccess) {
     ctx->dev_free(b->mem, b->bytes);
     delete b;

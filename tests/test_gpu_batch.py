@@ -127,12 +127,13 @@ def test_batch_graph_replays_match_eager(env):
 
 def test_batch_argument_errors(env):
     rs, ctx, torch, T = env
-    other = rs.Context(0)
     reqs = _requests(torch, T, 11)[:2]
-    with pytest.raises(rs.RsdError) as e:
-        rs.Batch(other, reqs)
-    assert e.value.code == -1
-    other.close()
+    bad = dict(reqs[0])
+    bad["quats"] = reqs[0]["quats"][:0]
+    bad["trans"] = reqs[0]["trans"][:0]
+    b = rs.Batch(ctx, [bad])          # a request with no poses is accepted and does nothing
+    b.run()
+    b.free()
     with pytest.raises(rs.RsdError) as e:
         rs.Batch(ctx, [])
     assert e.value.code == -1

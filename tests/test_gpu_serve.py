@@ -1,0 +1,74 @@
+"""GPU test of the continuous-batching server: mixed requests over three resident tensors
+under a tight HBM budget; every served result equals the same request scored alone."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+from gpu_common import oracle_factors  # noqa: E402
+from workloads import configs, generators as gen  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.timeout(600)
+def test_server_mix_equals_alone_under_budget():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2510_26611_amd as rs
+    from paper_2510_26611_amd import serve
+
+    ctx = rs.Context(0)
+    cfg = configs.CONFIG1
+    wl = configs.make(cfg)
+    _, can = oracle_factors(cfg, wl)
+    tensors = {"cfg1": rs.tensor_import(ctx, can.F, cfg.n, cfg.b, rs.Sinc.from_config(cfg), wl.protein_charges,
+                                        wl.protein_positions)}
+    pos = gen.ball_points(gen.rng(61, 1), 300, 8.0)
+    z = gen.charges(gen.rng(61, 2), 300, 0.4, True)
+    tensors["built"] = rs.build_rs_tensor(ctx, z, pos, 256, 30.0, rs.Sinc(cfg.M, cfg.h_M, cfg.L_s, 16, 9.5, 1e-8))
+    g = np.random.default_rng(5)
+    tensors["rand"] = rs.tensor_import(ctx, [g.normal(size=(96, 257)) * 0.01 for _ in range(3)], 96, 30.0,
+                                       rs.Sinc(cfg.M, cfg.h_M, cfg.L_s, 16, 9.5, 1e-8), z[:60], pos[:60] * 0.7)
+    radius = {"cfg1": 18.0, "built": 20.0, "rand": 9.0}
+    gt = np.random.default_rng(8)
+    names = list(tensors)
+    trace, t = [], 0.0
+    for i in range(40):
+        t += gt.exponential(0.002)
+        name = names[i % 3]
+        L = int(gt.integers(1, 121))
+        P = int(gt.integers(1, 3000))
+        lig = gen.ball_points(gen.rng(5, 3, i), L, max(1.5, 1.2 * L ** (1 / 3)))
+        zeta = gen.charges(gen.rng(5, 4, i), L, 0.3, False)
+        q = gen.unit_quaternions(gen.rng(5, 5, i), P)
+        tr = gen.sphere_translations(gen.rng(5, 6, i), P, radius[name])
+        trace.append(serve.Request(i, name, zeta, lig, q, tr, 2.5, t))
+    trace.append(serve.Request(99, "nope", zeta, lig, q, tr, 2.5, t))
+    resident = sum(x.query()["bytes"] for x in tensors.values())
+    mean_cost = np.mean([serve.request_bytes(r, 8) for r in trace[:40]])
+    srv = serve.Server(tensors, hbm_budget_bytes=int(resident + 4 * mean_cost + (1 << 20)))
+    stats = srv.run(trace)
+    print(f"served {stats['served']} p50 {stats['latency_p50_s'] * 1e3:.2f} ms p99 {stats['latency_p99_s'] * 1e3:.2f} ms")
+    assert stats["served"] == 40 and stats["rejected"] == 1
+    assert trace[-1].error == serve.E_UNKNOWN_PROTEIN
+    assert np.isfinite(stats["latency_p99_s"])
+    ctx.set_option("score_mode", 2)
+    bad = []
+    for r in trace[:40]:
+        alone = rs.score_poses(ctx, tensors[r.protein], r.lig_charges, r.lig_positions, r.quats, r.trans, r.vdw_min)
+        for k in ("E", "flags", "counts"):
+            if not np.array_equal(r.result[k], alone[k], equal_nan=True):
+                diff = np.nonzero(~((r.result[k] == alone[k]) | (np.isnan(r.result[k].astype(float)) &
+                                                                  np.isnan(alone[k].astype(float)))))[0]
+                print(f"rid {r.rid} protein {r.protein} L {r.L} P {r.P} key {k}: {diff.size} poses differ, "
+                      f"first {diff[:5]}, batch {r.result[k][diff[:3]]} alone {alone[k][diff[:3]]} "
+                      f"flags {alone['flags'][diff[:3]]}")
+                bad.append((r.rid, k))
+    assert not bad, bad
+    srv.close()
+    for x in tensors.values():
+        x.free()
+    ctx.close()
