@@ -208,6 +208,9 @@ void rsd_tensor_free(rsd_tensor* t);
  *                     iteration for n >= 1024), 1 dense batched eigensolver, 2 subspace iteration
  *   "t2c_solver"      SVD of the Tucker core slices in the build: 0 automatic, 1 one-sided
  *                     Jacobi with the slice in LDS, 2 rocSOLVER gesvd
+ *   "gram_solver"     Gram matrices of the side matrices in the build: 0 automatic (1),
+ *                     1 Toeplitz-times-Hankel form of the uniform grid (O(n N K + n^2 K)),
+ *                     2 dense product of the generated side matrix on matrix cores (O(n^2 N K))
  * Errors: RSD_E_INVALID for an unknown name or value. */
 rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t value);
 

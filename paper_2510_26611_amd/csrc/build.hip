@@ -6,7 +6,8 @@
 // canonical -> Tucker -> canonical transform with the reduced HOSVD (RHOSVD):
 //   1. per mode, the side matrix A_d (n x N*K_long) with unit-norm columns,
 //      weights xi_{m,k} = z_m w_k prod_d ||g_{k,m,d}||;
-//   2. the Gram matrix A_d A_d^T (n x n) on FP64 matrix cores (the dense step),
+//   2. the Gram matrix A_d A_d^T (n x n), by default from its Toeplitz-times-Hankel
+//      structure on the uniform grid (optionally as a dense FP64 matrix-core product),
 //      its dominant eigenvectors U_d (eigenvalues >= eps^2 * largest, i.e. singular
 //      values >= eps * largest);
 //   3. the projections B_d = U_d^T A_d and the Tucker core
@@ -281,6 +282,98 @@ __global__ void k_gen_columns(const double* __restrict__ pos, const double* __re
     const double x = pos[3 * (c / K) + d];
     const double dx = (-b + (double)(i + 1) * h) - x;
     A[e] = exp(-(t2[c % K] * (dx * dx))) * inv_nu[c];
+  }
+}
+
+// ----------------------------------------------------------------- Gram matrix on a uniform grid
+// With nodes X_i = -b + (i+1) h, the product of two samples of one Gaussian column splits as
+//   g(X_i) g(X_j) = exp(-t^2 (X_i - X_j)^2 / 2) * exp(-2 t^2 (x - (X_i + X_j)/2)^2),
+// a factor that depends on i - j only (Toeplitz) times one that depends on i + j only (Hankel).
+// Summed over the unit-norm columns c = (m, k) of a mode,
+//   G[i][j] = sum_k T_k[|i - j|] * H_k[i + j],
+//   T_k[e] = exp(-t_k^2 (e h)^2 / 2),  H_k[s] = sum_m exp(-2 t_k^2 (x_m - (-b + (s/2 + 1) h))^2) / nu_{m,k}^2,
+// the same matrix as A_d A_d^T up to rounding, for O(K (2n-1) N + K n^2) work instead of O(n^2 N K).
+
+// H_k[s] for s in [0, 2n-1), one thread per s, one k per grid row; atoms staged through LDS.
+__global__ __launch_bounds__(256) void k_gram_hankel(const double* __restrict__ pos, const double* __restrict__ t2,
+                                                     const double* __restrict__ inv_nu, int K, int d, int n, double b,
+                                                     double h, int64_t N, double* __restrict__ H) {
+  __shared__ double sx[256], sc[256];
+  const int k = blockIdx.y;
+  const int64_t ns = 2 * (int64_t)n - 1;
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const double mid = -b + (0.5 * (double)s + 1.0) * h;
+  const double a = 2.0 * t2[k];
+  double acc = 0.0;
+  for (int64_t m0 = 0; m0 < N; m0 += 256) {
+    __syncthreads();
+    const int64_t m = m0 + threadIdx.x;
+    if (m < N) {
+      const double v = inv_nu[m * K + k];
+      sx[threadIdx.x] = pos[3 * m + d];
+      sc[threadIdx.x] = v * v;
+    }
+    __syncthreads();
+    const int cnt = (int)(N - m0 < 256 ? N - m0 : 256);
+    for (int j = 0; j < cnt; ++j) {
+      const double dx = sx[j] - mid;
+      acc = fma(sc[j], exp(-(a * (dx * dx))), acc);
+    }
+  }
+  if (s < ns) H[(int64_t)k * ns + s] = acc;
+}
+
+// T_k[e] for e in [0, n).
+__global__ void k_gram_toeplitz(const double* __restrict__ t2, int K, int n, double h, double* __restrict__ T) {
+  const int64_t total = (int64_t)K * n;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(x / n);
+    const double e = (double)(x % n) * h;
+    T[x] = exp(-(0.5 * t2[k] * (e * e)));
+  }
+}
+
+// G[i][j] = sum_k T_k[|i-j|] H_k[i+j] for one 64 x 64 tile per workgroup.  A tile needs 127
+// consecutive entries of each table per term (i - j and i + j each span 127 values), staged
+// in LDS eight terms at a time.  Every entry is formed from (|i-j|, i+j) only, so G is exactly
+// symmetric.
+__global__ __launch_bounds__(256) void k_gram_assemble(const double* __restrict__ T, const double* __restrict__ H,
+                                                       int K, int n, double* __restrict__ G) {
+  constexpr int KG = 8;
+  __shared__ double sT[KG][128], sH[KG][128];
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int dbase = i0 - j0 - 63;    // i - j - dbase in [0, 126]
+  const int sbase = i0 + j0;         // i + j - sbase in [0, 126]
+  const int64_t ns = 2 * (int64_t)n - 1;
+  const int jj = threadIdx.x & 63, ib = threadIdx.x >> 6;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int k0 = 0; k0 < K; k0 += KG) {
+    __syncthreads();
+    for (int x = threadIdx.x; x < KG * 128; x += 256) {
+      const int kk = x >> 7, e = x & 127, k = k0 + kk;
+      const int dlt = abs(dbase + e);
+      const int64_t sidx = (int64_t)sbase + e;
+      sT[kk][e] = (k < K && dlt < n) ? T[(int64_t)k * n + dlt] : 0.0;
+      sH[kk][e] = (k < K && sidx < ns) ? H[(int64_t)k * ns + sidx] : 0.0;
+    }
+    __syncthreads();
+    const int kn = K - k0 < KG ? K - k0 : KG;
+    for (int kk = 0; kk < kn; ++kk) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int ii = ib + 4 * q;
+        acc[q] = fma(sT[kk][ii - jj + 63], sH[kk][ii + jj], acc[q]);
+      }
+    }
+  }
+  const int j = j0 + jj;
+  if (j >= n) return;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int i = i0 + ib + 4 * q;
+    if (i < n) G[(int64_t)i * n + j] = acc[q];
   }
 }
 
@@ -619,11 +712,11 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
   rocblas_handle hb = (rocblas_handle)ctx->blas;
   RSD_CHECK(rocblas_set_stream(hb, s) == rocblas_status_success, RSD_E_HIP, "rocblas_set_stream failed");
 
-  // column chunks of the side matrix: at most ~1 GiB each
+  const bool dense_gram = ctx->opt_gram == 2;
+  // dense form: column chunks of the side matrix, at most ~1 GiB each
   const int64_t max_cols = std::max<int64_t>(TK, ((int64_t)1 << 27) / n / TK * TK);
   const int64_t chunk_cols = std::min<int64_t>(C, max_cols);
-  DevBuf Abuf, nu[3], inv_nu[3], G3, Gpart, W3, E3;
-  RSD_TRY(Abuf.alloc(ctx, (size_t)chunk_cols * n));
+  DevBuf Abuf, nu[3], inv_nu[3], G3, Gpart, W3, E3, Ttab, Htab;
   for (int d = 0; d < 3; ++d) {
     RSD_TRY(nu[d].alloc(ctx, (size_t)C));
     RSD_TRY(inv_nu[d].alloc(ctx, (size_t)C));
@@ -633,7 +726,13 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
   const int Tn = div_up(n, TN);
   const int tri_tiles = Tn * (Tn + 1) / 2;
   const int gsplit = std::max(1, std::min(16, div_up(1024, tri_tiles)));
-  RSD_TRY(Gpart.alloc(ctx, (size_t)gsplit * nn));
+  if (dense_gram) {
+    RSD_TRY(Abuf.alloc(ctx, (size_t)chunk_cols * n));
+    RSD_TRY(Gpart.alloc(ctx, (size_t)gsplit * nn));
+  } else {
+    RSD_TRY(Ttab.alloc(ctx, (size_t)K * n));
+    RSD_TRY(Htab.alloc(ctx, (size_t)K * (2 * (size_t)n - 1)));
+  }
   RSD_TRY(W3.alloc(ctx, 3 * (size_t)n));
   RSD_TRY(E3.alloc(ctx, 3 * (size_t)n));
   rocblas_int* d_info = nullptr;
@@ -649,9 +748,19 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
   DevBuf U[3], Bt[3];
   const double h = t->h, b = t->b;
   // 1. column norms and the Gram matrix of every mode, chunk by chunk
+  if (!dense_gram)
+    RSD_TIMED_LAUNCH(ctx, "gram", (k_gram_toeplitz<<<grid1d((int64_t)K * n), 256, 0, s>>>(t2d.p, K, n, h, Ttab.p)));
   for (int d = 0; d < 3; ++d) {
     RSD_TIMED_LAUNCH(ctx, "gen", (k_col_norms<<<div_up(C, 4), 256, 0, s>>>(d_pos, t2d.p, K, d, n, b, h, 0, C,
                                                                              nu[d].p, inv_nu[d].p)));
+    if (!dense_gram) {
+      const dim3 gh((unsigned)div_up(2 * (int64_t)n - 1, 256), (unsigned)K);
+      RSD_TIMED_LAUNCH(ctx, "gram", (k_gram_hankel<<<gh, 256, 0, s>>>(d_pos, t2d.p, inv_nu[d].p, K, d, n, b, h, N,
+                                                                      Htab.p)));
+      const dim3 ga((unsigned)Tn, (unsigned)Tn);
+      RSD_TIMED_LAUNCH(ctx, "gram", (k_gram_assemble<<<ga, 256, 0, s>>>(Ttab.p, Htab.p, K, n, G3.p + d * nn)));
+      continue;
+    }
     RSD_HIP(hipMemsetAsync(Gpart.p, 0, Gpart.bytes, s));
     for (int64_t c0 = 0; c0 < C; c0 += chunk_cols) {
       const int64_t c1 = std::min(C, c0 + chunk_cols);

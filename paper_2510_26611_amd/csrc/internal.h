@@ -86,6 +86,7 @@ struct Context {
   int opt_poses_per_wave = 0;  // chunk-major kernel: poses per wavefront (0 = automatic)
   int opt_t2c = 0;             // core slice SVDs: 0 auto, 1 Jacobi in LDS, 2 rocSOLVER
   int opt_eig = 0;             // Gram eigenvectors: 0 auto, 1 dense batched eigensolver, 2 subspace iteration
+  int opt_gram = 0;            // Gram matrices: 0 auto, 1 Toeplitz x Hankel form, 2 dense matrix-core product
   bool timing = false;
   std::vector<KernelTimer> pending;
   std::map<std::string, std::pair<int64_t, double>> ktime;
