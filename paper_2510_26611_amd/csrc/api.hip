@@ -27,9 +27,15 @@ void clear_error() { g_err.clear(); }
 rsd_status Context::dev_alloc(void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 8;
+  if (budget != 0 && in_use + bytes > budget) block_trim();
   RSD_CHECK(budget == 0 || in_use + bytes <= budget, RSD_E_OOM,
             "HBM budget exceeded: %zu in use + %zu requested > %zu", in_use, bytes, budget);
   hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess && !block_cache.empty()) {
+    (void)hipGetLastError();
+    block_trim();
+    e = hipMalloc(p, bytes);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     *p = nullptr;
@@ -45,6 +51,42 @@ void Context::dev_free(void* p, size_t bytes) {
   (void)hipFree(p);
   if (bytes == 0) bytes = 8;
   in_use = in_use >= bytes ? in_use - bytes : 0;
+}
+
+rsd_status Context::block_alloc(void** p, size_t* bytes) {
+  const size_t want = *bytes == 0 ? 8 : *bytes;
+  int best = -1;
+  for (int i = 0; i < (int)block_cache.size(); ++i) {
+    const size_t have = block_cache[i].second;
+    if (have >= want && have <= 2 * want + (64u << 20) && (best < 0 || have < block_cache[best].second)) best = i;
+  }
+  if (best >= 0) {
+    *p = block_cache[best].first;
+    *bytes = block_cache[best].second;
+    block_cache.erase(block_cache.begin() + best);
+    return RSD_OK;
+  }
+  *bytes = want;
+  return dev_alloc(p, want);
+}
+
+void Context::block_release(void* p, size_t bytes) {
+  if (!p) return;
+  block_cache.emplace_back(p, bytes);
+  if (block_cache.size() > 4) {   // keep the four largest
+    int small = 0;
+    for (int i = 1; i < (int)block_cache.size(); ++i)
+      if (block_cache[i].second < block_cache[small].second) small = i;
+    dev_free(block_cache[small].first, block_cache[small].second);
+    block_cache.erase(block_cache.begin() + small);
+  }
+}
+
+void Context::block_trim() {
+  if (block_cache.empty()) return;
+  (void)hipStreamSynchronize(stream);
+  for (auto& b : block_cache) dev_free(b.first, b.second);
+  block_cache.clear();
 }
 
 rsd_status Context::workspace(size_t bytes, void** out) {
@@ -197,6 +239,7 @@ static void context_destroy(Context* ctx) {
     (void)hipEventDestroy(t.stop);
   }
   ctx->pending.clear();
+  ctx->block_trim();
   ctx->dev_free(ctx->ws, ctx->ws_bytes);
   ctx->ws = nullptr;
   if (ctx->blas) rocblas_destroy_handle((rocblas_handle)ctx->blas);

@@ -185,8 +185,8 @@ __global__ __launch_bounds__(256) void k_gemm(AOp A, BOp B, const GemmShape g) {
     bm = row;
     bn = row + idx;
   } else {
-    bn = blockIdx.x;
-    bm = blockIdx.y;
+    bm = blockIdx.x;   // the long dimension (side-matrix columns) in x, which allows 2^31 - 1 tiles
+    bn = blockIdx.y;
   }
   const int m0 = bm * TM, n0 = bn * TN;
   const int64_t k0 = (int64_t)blockIdx.z * g.kper;
@@ -584,7 +584,9 @@ rsd_status gemm(Context* ctx, const char* name, const AOp& A, const BOp& B, Gemm
     g.tiles_n = div_up(g.N, TN);
     grid = dim3((unsigned)(g.tiles_n * (g.tiles_n + 1) / 2), 1, (unsigned)splits);
   } else {
-    grid = dim3((unsigned)div_up(g.N, TN), (unsigned)div_up(g.M, TM), (unsigned)splits);
+    RSD_CHECK(div_up(g.N, TN) <= 65535 && splits <= 65535, RSD_E_UNSUPPORTED, "%s: product shape exceeds the launch grid",
+              name);
+    grid = dim3((unsigned)div_up(g.M, TM), (unsigned)div_up(g.N, TN), (unsigned)splits);
   }
   RSD_TIMED_LAUNCH(ctx, name, (k_gemm<AOp, BOp><<<grid, 256, 0, ctx->stream>>>(A, B, g)));
   return RSD_OK;

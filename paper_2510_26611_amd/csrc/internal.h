@@ -91,8 +91,17 @@ struct Context {
   std::vector<KernelTimer> pending;
   std::map<std::string, std::pair<int64_t, double>> ktime;
 
+  // Released batch scratch kept for reuse.  A cached block is handed only to later work on
+  // this context's stream, which stream order makes safe (set_stream drains the old stream
+  // first), so releasing needs no device-wide wait as hipFree would.  Cached blocks count as
+  // in use and are freed when an allocation would exceed the budget or fail.
+  std::vector<std::pair<void*, size_t>> block_cache;
+
   rsd_status dev_alloc(void** p, size_t bytes);
   void dev_free(void* p, size_t bytes);
+  rsd_status block_alloc(void** p, size_t* bytes);   // in: bytes wanted; out: size of the block handed out
+  void block_release(void* p, size_t bytes);
+  void block_trim();
   rsd_status workspace(size_t bytes, void** out);
   rsd_status timer_begin(const char* name, KernelTimer* t);
   rsd_status timer_end(KernelTimer* t);

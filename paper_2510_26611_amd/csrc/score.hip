@@ -904,6 +904,7 @@ struct Batch {
   size_t lds_long = 0;
   int64_t long_slots = 0, poses = 0;
   std::vector<BatchDesc> host_table;   // source of the (asynchronous) table upload
+  hipEvent_t uploaded = nullptr;       // recorded after the upload: host_table may go once it completes
 };
 
 // ligand-size classes for the short-range launches (LDS grows with L)
@@ -955,7 +956,7 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
   const size_t o_es = o_r + sizeof(double) * (size_t)nreq;
   const size_t o_part = o_es + sizeof(double) * (size_t)nes;
   b->bytes = o_part + sizeof(double) * (size_t)npart;
-  rsd_status st = ctx->dev_alloc(&b->mem, b->bytes);
+  rsd_status st = ctx->block_alloc(&b->mem, &b->bytes);
   if (st != RSD_OK) {
     delete b;
     return st;
@@ -1008,7 +1009,7 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     }
     bu.blocks = sb;
     if (sb > 0x7fffffffLL) {
-      ctx->dev_free(b->mem, b->bytes);
+      ctx->block_release(b->mem, b->bytes);
       delete b;
       set_error("batch too large for one launch");
       return RSD_E_UNSUPPORTED;
@@ -1020,15 +1021,21 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
   b->long_slots = xb;
   b->d = (BatchDesc*)m;
   if (xb * 8 > 0x7fffffffLL) {
-    ctx->dev_free(b->mem, b->bytes);
+    ctx->block_release(b->mem, b->bytes);
     delete b;
     set_error("batch too large for one launch");
     return RSD_E_UNSUPPORTED;
   }
   b->host_table = std::move(h);
-  hipError_t e = hipMemcpyAsync(b->d, b->host_table.data(), sz_desc, hipMemcpyHostToDevice, ctx->stream);
+  hipError_t e = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->d, b->host_table.data(), sz_desc, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->uploaded, ctx->stream);
   if (e != hipSuccess) {
-    ctx->dev_free(b->mem, b->bytes);
+    if (b->uploaded) {
+      (void)hipStreamSynchronize(ctx->stream);
+      (void)hipEventDestroy(b->uploaded);
+    }
+    ctx->block_release(b->mem, b->bytes);
     delete b;
     set_error("batch upload: %s", hipGetErrorString(e));
     return RSD_E_HIP;
@@ -1055,10 +1062,15 @@ rsd_status batch_run(Batch* b) {
   return RSD_OK;
 }
 
+// The scratch goes back to the context's block cache without waiting for the batch's queued
+// launches: only later work on the same stream can receive it.
 void batch_free(Batch* b) {
   if (!b) return;
-  (void)hipStreamSynchronize(b->ctx->stream);
-  b->ctx->dev_free(b->mem, b->bytes);
+  if (b->uploaded) {
+    (void)hipEventSynchronize(b->uploaded);
+    (void)hipEventDestroy(b->uploaded);
+  }
+  b->ctx->block_release(b->mem, b->bytes);
   delete b;
 }
 

@@ -1,14 +1,20 @@
 """Continuous-batching request server over resident RS tensors.
 
 Requests (protein id, ligand, poses, vdW distance) arrive over time.  Each protein's RS
-tensor and cell list stay resident on the device.  The scheduler admits waiting requests in
-arrival order while their device memory (inputs, outputs and the batch scratch: per-chunk
-long-range partials, short-range energies, ligand frames) fits the HBM budget next to the
-resident tensors; every admission round becomes one rsd_batch (all its requests scored by
-one set of launches).  Rounds alternate between streams, each with its own context, so a
-round's kernels overlap the previous round's on the device while the host uploads and
-plans the next one.  Latency is measured from arrival to the moment a request's results are
-back on the host.
+tensor and cell list stay resident on the device.  A waiting request is admitted, in arrival
+order, once its device memory (inputs and outputs) fits the HBM budget next to the resident
+tensors and the scratch reserved for the rounds in flight.  Work is issued in rounds: every
+round is one rsd_batch over pose slices of the admitted, unfinished requests, with a fixed
+pose budget shared evenly among them (each gets at least `min_slice` poses while the budget
+lasts, in admission order).  A request that arrives while others are on the device therefore
+joins the next round instead of waiting for them to finish, and a small request completes
+in a round or two even behind a very large one.
+
+Rounds alternate between streams, each with its own context: a round's uploads, host-side
+planning and downloads overlap the neighbouring rounds' kernels, while an event between the
+streams keeps the kernels of successive rounds in issue order (two rounds sharing the device
+would only delay both).  Latency is measured from arrival to the moment the last slice of a
+request is back on the host.
 
 The scheduler is plain Python with no device calls (unit-testable on the CPU); the executor
 does the device work through the library.
@@ -71,33 +77,38 @@ def validate(req: Request, proteins: dict) -> int:
     return 0 if ok else E_MALFORMED
 
 
-def request_bytes(req: Request, nchunk: int) -> int:
-    """Device bytes a request holds while in flight (inputs, outputs, batch scratch)."""
-    P, L = req.P, req.L
-    inputs = 8 * (4 * L + 7 * P)
-    outputs = P * (8 + 1 + 4)
-    scratch = 32 * L + 8 + 8 * P + 8 * nchunk * P + 512
-    return inputs + outputs + scratch
+def request_bytes(req: Request) -> int:
+    """Device bytes a request holds from admission to completion (inputs and outputs)."""
+    return 8 * (4 * req.L + 7 * req.P) + req.P * (8 + 1 + 4)
+
+
+def round_scratch_bytes(round_poses: int, nchunk: int, max_ligand: int = 896, slices: int = 64) -> int:
+    """Batch scratch of one round of at most `round_poses` poses and `slices` slices: per-chunk
+    long-range partials, short-range energies, ligand frames and the request table."""
+    return 8 * round_poses * (nchunk + 1) + slices * (32 * max_ligand + 8 + 1024) + 4096
 
 
 class Scheduler:
-    """FIFO admission under a byte budget, with a bound on rounds in flight and poses per round."""
+    """Admission by byte budget in arrival order, and pose slices per round shared evenly."""
 
-    def __init__(self, budget_bytes: int, resident_bytes: int, max_rounds: int = 2, max_round_poses: int = 4_000_000):
+    def __init__(self, budget_bytes: int, resident_bytes: int, scratch_bytes: int = 0, max_rounds: int = 2,
+                 round_poses: int = 250_000, min_slice: int = 16_384):
         self.budget = int(budget_bytes)
-        self.resident = int(resident_bytes)
+        self.reserved = int(resident_bytes) + int(scratch_bytes)
         self.in_flight = 0
         self.max_rounds = max_rounds
-        self.max_round_poses = max_round_poses
+        self.round_poses = int(round_poses)
+        self.min_slice = int(min_slice)
         self.rounds = 0
         self.waiting: deque = deque()
+        self.active: list = []          # admitted, not finished, in admission order
 
     def free_bytes(self) -> int:
-        return self.budget - self.resident - self.in_flight
+        return self.budget - self.reserved - self.in_flight
 
     def submit(self, req: Request, cost: int) -> bool:
-        """Queue a request; a request that could never fit the budget is rejected."""
-        if cost > self.budget - self.resident:
+        """Queue a request; one that could never fit the budget is rejected."""
+        if cost > self.budget - self.reserved:
             req.state, req.error = REJECTED, E_TOO_LARGE
             return False
         req._cost = cost
@@ -105,89 +116,174 @@ class Scheduler:
         return True
 
     def cancel(self, req: Request) -> bool:
-        """Cancel a waiting request (its slot goes to the next one)."""
+        """Cancel a request that has not been admitted yet."""
         if req.state == WAITING and req in self.waiting:
             self.waiting.remove(req)
             req.state = CANCELLED
             return True
         return False
 
+    def admit(self) -> list:
+        """Move waiting requests that fit the budget, in arrival order, to the active set."""
+        got = []
+        while self.waiting and self.waiting[0]._cost <= self.free_bytes():
+            r = self.waiting.popleft()
+            self.in_flight += r._cost
+            r.state, r._next, r._done = RUNNING, 0, 0
+            self.active.append(r)
+            got.append(r)
+        return got
+
     def next_round(self) -> list:
-        """Requests to admit now (in arrival order), or [] if none fits or too many rounds run."""
+        """Slices (request, first pose, count) for the next round, or [] if none can be issued."""
         if self.rounds >= self.max_rounds:
             return []
-        take, poses, free = [], 0, self.free_bytes()
-        while self.waiting:
-            r = self.waiting[0]
-            if r._cost > free or (take and poses + r.P > self.max_round_poses):
+        live = [r for r in self.active if r._next < r.P]
+        if not live:
+            return []
+        quota = max(self.min_slice, self.round_poses // len(live))
+        left, take = self.round_poses, []
+        for r in live:
+            n = min(r.P - r._next, quota, left)
+            if n <= 0:
                 break
-            self.waiting.popleft()
-            take.append(r)
-            free -= r._cost
-            poses += r.P
-        if take:
-            self.in_flight += sum(r._cost for r in take)
-            self.rounds += 1
-            for r in take:
-                r.state = RUNNING
-        return take
+            take.append([r, n])
+            left -= n
+        for t in take:                  # what short requests left unused goes to the others, in order
+            if left <= 0:
+                break
+            extra = min(t[0].P - t[0]._next - t[1], left)
+            t[1] += extra
+            left -= extra
+        out = []
+        for r, n in take:
+            out.append((r, r._next, n))
+            r._next += n
+        self.rounds += 1
+        return out
 
-    def finish_round(self, reqs: list) -> None:
-        self.in_flight -= sum(r._cost for r in reqs)
+    def finish_round(self, slices: list) -> list:
+        """Account a completed round; returns the requests it completed."""
         self.rounds -= 1
-        for r in reqs:
-            r.state = DONE
+        done = []
+        for r, _, n in slices:
+            r._done += n
+            if r._done == r.P:
+                r.state = DONE
+                self.in_flight -= r._cost
+                self.active.remove(r)
+                done.append(r)
+        return done
+
+
+def latency_stats(trace: list, wall: float) -> dict:
+    """Throughput over the wall time and arrival-to-result latency percentiles of the served requests."""
+    served = [r for r in trace if r.state == DONE]
+    lat = np.array([r.t_done - r.arrival for r in served]) if served else np.zeros(0)
+    wait = np.array([r.t_admit - r.arrival for r in served]) if served else np.zeros(0)
+    poses = int(sum(r.P for r in served))
+    pct = lambda a, q: float(np.percentile(a, q)) if a.size else float("nan")  # noqa: E731
+    return {
+        "requests": len(trace), "served": len(served),
+        "rejected": sum(r.state == REJECTED for r in trace),
+        "poses": poses, "wall_s": wall,
+        "poses_per_s": poses / wall if wall > 0 else 0.0,
+        "latency_p50_s": pct(lat, 50), "latency_p99_s": pct(lat, 99),
+        "latency_max_s": float(lat.max()) if lat.size else float("nan"),
+        "queue_wait_p50_s": pct(wait, 50),
+    }
+
+
+def serve_plain(ctx, tensors: dict, trace: list, realtime: bool = True, progress=None) -> dict:
+    """The baseline the server is compared with: requests one at a time in arrival order, each
+    scored by one plain rsd_score_poses call on host arrays (upload, launches, download)."""
+    t0 = time.perf_counter()
+    order = sorted(trace, key=lambda r: r.arrival)
+    for i, r in enumerate(order):
+        code = validate(r, tensors)
+        if code:
+            r.state, r.error = REJECTED, code
+            continue
+        if realtime:
+            delay = r.arrival - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+        r.t_admit = time.perf_counter() - t0
+        r.result = rsdock.score_poses(ctx, tensors[r.protein], r.lig_charges, r.lig_positions, r.quats, r.trans,
+                                      r.vdw_min)
+        r.t_done = time.perf_counter() - t0
+        r.state = DONE
+        if progress is not None:
+            progress(i + 1, len(order))
+    return latency_stats(trace, time.perf_counter() - t0)
 
 
 class Server:
     """Serve a trace of requests against resident tensors on one GPU."""
 
-    def __init__(self, tensors: dict, hbm_budget_bytes: int, streams: int = 2, max_round_poses: int = 4_000_000,
-                 device: int = 0):
+    def __init__(self, tensors: dict, hbm_budget_bytes: int, streams: int = 2, round_poses: int = 250_000,
+                 min_slice: int = 16_384, device: int = 0):
         import torch
         self.torch = torch
         self.tensors = tensors
         self.dev = torch.device(f"cuda:{device}")
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(streams)]
         self.ctxs = [rsdock.Context(device, stream=s.cuda_stream) for s in self.streams]
-        self.nchunk = {k: -(-t.query()["R"] // 64) for k, t in tensors.items()}
+        nchunk = max(-(-t.query()["R"] // 64) for t in tensors.values())
         resident = sum(t.query()["bytes"] for t in tensors.values())
-        self.sched = Scheduler(hbm_budget_bytes, resident, max_rounds=streams, max_round_poses=max_round_poses)
+        self.sched = Scheduler(hbm_budget_bytes, resident, streams * round_scratch_bytes(round_poses, nchunk),
+                               max_rounds=streams, round_poses=round_poses, min_slice=min_slice)
+        self.last_compute = None
 
-    def _launch(self, reqs: list, k: int):
+    def _upload(self, r: Request) -> None:
+        """Inputs to the device and output buffers (device + pinned host) for a newly admitted request."""
         torch, dev = self.torch, self.dev
+        host = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).pin_memory()
+                for a in (r.lig_charges, r.lig_positions, r.quats, r.trans)]
+        r._host_in = host
+        r._dev = [h.to(dev, non_blocking=True) for h in host]
+        r._out = dict(E=torch.empty(r.P, dtype=torch.float64, device=dev),
+                      flags=torch.empty(r.P, dtype=torch.uint8, device=dev),
+                      counts=torch.empty(r.P, dtype=torch.int32, device=dev))
+        r._res = {k: torch.empty(v.shape, dtype=v.dtype, pin_memory=True) for k, v in r._out.items()}
+
+    def _launch(self, slices: list, k: int) -> dict:
+        torch = self.torch
         s = self.streams[k]
-        batch_reqs, keep = [], []
         with torch.cuda.stream(s):
-            for r in reqs:
-                host = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).pin_memory()
-                        for a in (r.lig_charges, r.lig_positions, r.quats, r.trans)]
-                d = [h.to(dev, non_blocking=True) for h in host]
-                out = dict(E=torch.empty(r.P, dtype=torch.float64, device=dev),
-                           flags=torch.empty(r.P, dtype=torch.uint8, device=dev),
-                           counts=torch.empty(r.P, dtype=torch.int32, device=dev))
-                batch_reqs.append(dict(tensor=self.tensors[r.protein], lig_charges=d[0], lig_positions=d[1],
-                                       quats=d[2], trans=d[3], vdw_min=r.vdw_min, out=out))
-                keep.append((host, d))
-            b = rsdock.Batch(self.ctxs[k], batch_reqs)
+            for r, off, _ in slices:
+                if off == 0:
+                    self._upload(r)
+            breqs = []
+            for r, off, n in slices:
+                z, x, q, t = r._dev
+                breqs.append(dict(tensor=self.tensors[r.protein], lig_charges=z, lig_positions=x,
+                                  quats=q[off:off + n], trans=t[off:off + n], vdw_min=r.vdw_min,
+                                  out={key: v[off:off + n] for key, v in r._out.items()}))
+            b = rsdock.Batch(self.ctxs[k], breqs)
+            if self.last_compute is not None:
+                s.wait_event(self.last_compute)
             b.run()
-            res = []
-            for br in batch_reqs:
-                o = br["out"]
-                res.append({key: torch.empty(v.shape, dtype=v.dtype, pin_memory=True).copy_(v, non_blocking=True)
-                            for key, v in o.items()})
+            ce = torch.cuda.Event()
+            ce.record(s)
+            self.last_compute = ce
+            for r, off, n in slices:
+                for key, v in r._out.items():
+                    r._res[key][off:off + n].copy_(v[off:off + n], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
-        return dict(reqs=reqs, batch=b, event=ev, results=res, keep=(keep, batch_reqs), stream=k)
+        return dict(slices=slices, batch=b, event=ev)
 
-    def run(self, trace: list, realtime: bool = True) -> dict:
-        """Serve `trace` (Requests with arrival offsets); returns latency and throughput statistics."""
+    def run(self, trace: list, realtime: bool = True, progress=None) -> dict:
+        """Serve `trace` (Requests with arrival offsets); returns latency and throughput statistics.
+
+        `progress(done, total)` is called whenever requests complete."""
         pending = deque(sorted(trace, key=lambda r: r.arrival))
         rounds = {}
         t0 = time.perf_counter()
         free_streams = deque(range(len(self.streams)))
-        done_poses = 0
-        while pending or self.sched.waiting or rounds:
+        finished = 0
+        while pending or self.sched.waiting or self.sched.active or rounds:
             now = time.perf_counter() - t0
             while pending and (pending[0].arrival <= now or not realtime):
                 r = pending.popleft()
@@ -195,48 +291,44 @@ class Server:
                 if code:
                     r.state, r.error = REJECTED, code
                     continue
-                self.sched.submit(r, request_bytes(r, self.nchunk[r.protein]))
+                if r.P == 0:
+                    r.state, r.t_admit, r.t_done = DONE, now, now
+                    r.result = dict(E=np.empty(0), flags=np.empty(0, np.uint8), counts=np.empty(0, np.int32))
+                    continue
+                self.sched.submit(r, request_bytes(r))
             progressed = False
             for k in list(rounds):
                 rd = rounds[k]
                 if rd["event"].query():
                     t_done = time.perf_counter() - t0
-                    for r, res in zip(rd["reqs"], rd["results"]):
-                        r.result = {key: v.numpy() for key, v in res.items()}
-                        r.t_done = t_done
-                        done_poses += r.P
                     rd["batch"].free()
-                    self.sched.finish_round(rd["reqs"])
+                    for r in self.sched.finish_round(rd["slices"]):
+                        r.result = {key: v.numpy() for key, v in r._res.items()}
+                        r.t_done = t_done
+                        r._dev = r._out = r._host_in = r._res = None
+                        finished += 1
+                        if progress is not None:
+                            progress(finished, len(trace))
                     free_streams.append(k)
                     del rounds[k]
                     progressed = True
+            t_adm = time.perf_counter() - t0
+            for r in self.sched.admit():
+                r.t_admit = t_adm
             while free_streams:
-                take = self.sched.next_round()
-                if not take:
+                slices = self.sched.next_round()
+                if not slices:
                     break
                 k = free_streams.popleft()
-                t_adm = time.perf_counter() - t0
-                for r in take:
-                    r.t_admit = t_adm
-                rounds[k] = self._launch(take, k)
+                rounds[k] = self._launch(slices, k)
                 progressed = True
             if not progressed:
-                if pending and realtime and not self.sched.waiting and not rounds:
+                idle = not (self.sched.waiting or self.sched.active or rounds)
+                if pending and realtime and idle:
                     time.sleep(max(0.0, min(0.01, pending[0].arrival - (time.perf_counter() - t0))))
                 else:
                     time.sleep(0.0002)
-        wall = time.perf_counter() - t0
-        served = [r for r in trace if r.state == DONE]
-        lat = np.array([r.t_done - r.arrival for r in served]) if served else np.zeros(0)
-        return {
-            "requests": len(trace), "served": len(served),
-            "rejected": sum(r.state == REJECTED for r in trace),
-            "poses": int(sum(r.P for r in served)), "wall_s": wall,
-            "poses_per_s": sum(r.P for r in served) / wall if wall > 0 else 0.0,
-            "latency_p50_s": float(np.percentile(lat, 50)) if lat.size else float("nan"),
-            "latency_p99_s": float(np.percentile(lat, 99)) if lat.size else float("nan"),
-            "latency_max_s": float(lat.max()) if lat.size else float("nan"),
-        }
+        return latency_stats(trace, time.perf_counter() - t0)
 
     def close(self) -> None:
         for c in self.ctxs:

@@ -1,5 +1,6 @@
 """GPU test of the continuous-batching server: mixed requests over three resident tensors
-under a tight HBM budget; every served result equals the same request scored alone."""
+under a tight HBM budget, split into pose slices across rounds; every served result equals
+the same request scored alone."""
 import os
 import sys
 
@@ -48,8 +49,12 @@ def test_server_mix_equals_alone_under_budget():
         trace.append(serve.Request(i, name, zeta, lig, q, tr, 2.5, t))
     trace.append(serve.Request(99, "nope", zeta, lig, q, tr, 2.5, t))
     resident = sum(x.query()["bytes"] for x in tensors.values())
-    mean_cost = np.mean([serve.request_bytes(r, 8) for r in trace[:40]])
-    srv = serve.Server(tensors, hbm_budget_bytes=int(resident + 4 * mean_cost + (1 << 20)))
+    nchunk = max(-(-x.query()["R"] // 64) for x in tensors.values())
+    mean_cost = np.mean([serve.request_bytes(r) for r in trace[:40]])
+    # small rounds so that requests are split into slices; room for about four requests in flight
+    scratch = 2 * serve.round_scratch_bytes(2000, nchunk)
+    srv = serve.Server(tensors, hbm_budget_bytes=int(resident + scratch + 4 * mean_cost), round_poses=2000,
+                       min_slice=256)
     stats = srv.run(trace)
     print(f"served {stats['served']} p50 {stats['latency_p50_s'] * 1e3:.2f} ms p99 {stats['latency_p99_s'] * 1e3:.2f} ms")
     assert stats["served"] == 40 and stats["rejected"] == 1

@@ -52,3 +52,18 @@ def test_frozen_constants_rederived(cfg):
     assert cfg.L_s == pytest.approx(2.0 * math.sqrt(3.0) * cfg.b, rel=1e-15)
     assert constants.optimal_step(cfg.M, cfg.b) == cfg.h_M
     assert constants.short_cutoff(cfg.M, cfg.h_M, cfg.L_s, cfg.K_long) == pytest.approx(cfg.r_cut, rel=1e-12)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("i", range(len(configs.CONFIG5_PROTEINS)))
+def test_serving_constants_rederived(i):
+    """Config 5 proteins: box from the radius rule, grid from the size rule, h_M and r_c re-derived."""
+    N, b, n, h_M, L_s, r_cut = configs.CONFIG5_PROTEINS[i]
+    c = configs.config5_protein(i)
+    r_lig = 6.0 * (configs.CONFIG5_L[1] / 50.0) ** (1.0 / 3.0)
+    assert b == math.ceil(c.protein_radius + 15.0 + r_lig + 2.0)
+    b_max = max(p[1] for p in configs.CONFIG5_PROTEINS)
+    assert n == 1 << math.ceil(math.log2(16384 * b / b_max))
+    assert L_s == pytest.approx(2.0 * math.sqrt(3.0) * b, rel=1e-15)
+    assert constants.optimal_step(32, b) == h_M
+    assert constants.short_cutoff(32, h_M, L_s, 22) == pytest.approx(r_cut, rel=1e-12)

@@ -82,6 +82,26 @@ CONFIG3_N = (1_000, 20_000)
 CONFIG3_L = (10, 200)
 CONFIG3_P = (1_000, 200_000)
 
+# Config 5 (serving): 8 resident proteins with N log-spaced over [1e3, 1e5] (density 0.05 / A^3),
+# box b = ceil(R_P + 15 + R_L(200) + 2) A, grid n = next power of two >= 16384 b / b_max, M=32,
+# K_long=22, eps 1e-8.  Per protein: (N, b, n, h_M, L_s, r_cut), the last three frozen from
+# oracle.constants like the other configs.  Requests: Poisson arrivals at 200 / s, protein
+# uniform over the 8, L uniform in [10, 200], P log-uniform in [1e4, 1e6], translations in the
+# 5-15 A shell of the request's protein, vdW distance 2.5 A.
+CONFIG5_PROTEINS = (
+    (1000, 44.0, 8192, 0.2193, 152.4204710660612, 14.941343046913628),
+    (1931, 48.0, 8192, 0.2217, 166.27687752661222, 15.463537931186579),
+    (3728, 53.0, 16384, 0.2245, 183.597385602301, 16.056913646927836),
+    (7197, 60.0, 16384, 0.228, 207.84609690826525, 16.833903442913364),
+    (13895, 68.0, 16384, 0.2315, 235.5589098293673, 17.66806182606335),
+    (26827, 77.0, 16384, 0.2351, 266.7358243656071, 18.48685992293717),
+    (51795, 90.0, 16384, 0.2396, 311.7691453623979, 19.576226336846226),
+    (100000, 105.0, 16384, 0.244, 363.7306695894642, 20.736774899464613),
+)
+CONFIG5_RATE = 200.0            # requests per second
+CONFIG5_L = (10, 200)
+CONFIG5_P = (10_000, 1_000_000)
+
 CONFIGS = {1: CONFIG1, 2: CONFIG2, 3: CONFIG3, 4: CONFIG4}
 
 
@@ -140,4 +160,65 @@ def make_pairs(pairs: int = CONFIG3_PAIRS, pose_scale: float = 1.0) -> list:
         q = gen.unit_quaternions(gen.rng(3, 5, i), P)
         t = gen.shell_translations(gen.rng(3, 6, i), P, c.pose_r_in, c.pose_r_out)
         out.append(Workload(c, prot, z, lig, zeta, q, t))
+    return out
+
+
+def config5_protein(i: int) -> Config:
+    """Config of resident protein i (0..7) of the serving workload (no poses of its own)."""
+    N, b, n, h_M, L_s, r_cut = CONFIG5_PROTEINS[i]
+    rp = gen.protein_radius(N, 0.05)
+    return Config(index=5, name=f"cfg5-protein{i}-N{N}-n{n}", N=N, protein_radius=rp, protein_charge_std=0.4, L=0,
+                  ligand_radius=0.0, ligand_charge_std=0.4, n=n, b=b, M=32, h_M=h_M, L_s=L_s, K_long=22,
+                  r_cut=r_cut, eps=1e-8, P=0, pose_kind="shell", pose_r_in=rp + 5.0, pose_r_out=rp + 15.0, sigma=2.5)
+
+
+def make_serving_proteins(count: int = 8) -> list:
+    """The resident proteins of config 5: (Config, positions, charges); protein i uses item i of streams 1-2."""
+    out = []
+    for i in range(count):
+        c = config5_protein(i)
+        pos = gen.ball_points(gen.rng(5, 1, i), c.N, c.protein_radius)
+        z = gen.charges(gen.rng(5, 2, i), c.N, c.protein_charge_std, net_zero=True)
+        out.append((c, pos, z))
+    return out
+
+
+@dataclass
+class ServingRequest:
+    index: int
+    arrival: float                  # seconds after the start of the trace
+    protein: int
+    ligand_positions: np.ndarray    # (L, 3)
+    ligand_charges: np.ndarray      # (L,)
+    quats: np.ndarray               # (P, 4)
+    trans: np.ndarray               # (P, 3)
+    sigma: float = 2.5
+
+
+def make_serving_trace(count: int, rate: float = CONFIG5_RATE, proteins: int = 8, pose_scale: float = 1.0,
+                       first: int = 0, seed_offset: int = 0) -> list:
+    """Requests `first`..`first+count-1` of the config-5 stream (arrivals rescaled to `rate`).
+
+    Sizes come from stream 7 and inter-arrival gaps (unit rate, divided by `rate`) from stream 8,
+    both drawn for the whole prefix so that a request is the same whatever `count` is; request j
+    draws its ligand and poses from streams 3-6 with item j.  `seed_offset` selects an
+    independent trace (rate sweeps); `pose_scale` shrinks every pose count (tests)."""
+    total = first + count
+    g7 = gen.rng(5 + 100 * seed_offset, 7)
+    prot = g7.integers(0, proteins, total)
+    Ls = g7.integers(CONFIG5_L[0], CONFIG5_L[1] + 1, total)
+    Ps = np.exp(g7.uniform(np.log(CONFIG5_P[0]), np.log(CONFIG5_P[1]), total)).astype(int)
+    gaps = gen.rng(5 + 100 * seed_offset, 8).exponential(1.0, total)
+    arr = np.cumsum(gaps) / rate
+    out = []
+    for j in range(first, total):
+        c = config5_protein(int(prot[j]))
+        L = int(Ls[j])
+        P = max(1, int(Ps[j] * pose_scale))
+        item = j + 1_000_000 * seed_offset
+        lig = gen.ball_points(gen.rng(5, 3, item), L, 6.0 * (L / 50.0) ** (1.0 / 3.0))
+        zeta = gen.charges(gen.rng(5, 4, item), L, 0.4, net_zero=False)
+        q = gen.unit_quaternions(gen.rng(5, 5, item), P)
+        t = gen.shell_translations(gen.rng(5, 6, item), P, c.pose_r_in, c.pose_r_out)
+        out.append(ServingRequest(j, float(arr[j]), int(prot[j]), lig, zeta, q, t))
     return out
