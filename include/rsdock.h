@@ -211,8 +211,39 @@ void rsd_tensor_free(rsd_tensor* t);
  *   "gram_solver"     Gram matrices of the side matrices in the build: 0 automatic (1),
  *                     1 Toeplitz-times-Hankel form of the uniform grid (O(n N K + n^2 K)),
  *                     2 dense product of the generated side matrix on matrix cores (O(n^2 N K))
+ *   "short_waves"     wavefronts (poses) per workgroup of the short-range kernel: 0 automatic,
+ *                     1, 2 or 4 (must fit 64 KB of LDS for the ligand)
+ *   "use_tuning"      1 (default): calls whose three launch-shape options above are automatic
+ *                     take the shape rsd_autotune recorded for their workload; 0: ignore it
  * Errors: RSD_E_INVALID for an unknown name or value. */
 rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t value);
+
+/* Launch-shape tuner (the scoring kernels' tile parameters: poses per wavefront of the
+ * rank-chunk-major long-range kernel, wavefronts per workgroup of the short-range kernel, and
+ * chunk-major versus fused per-pose long-range evaluation).  Every candidate shape whose LDS
+ * fits is timed on the given poses with HIP events on the context stream (one untimed call,
+ * then the best of three), and the fastest is recorded in the context for the workload key
+ * (grid n, rank chunks of 64 columns, protein atoms, ligand atoms, gradients or not).
+ * Later rsd_score_poses calls and batch requests on this context with matching key, at least
+ * 256 poses and automatic launch-shape options use it.  Pass a representative sample of the
+ * workload (same tensor, ligand and pose distribution; ~1e4 poses is plenty).  Inputs are
+ * device pointers with the layout of rsd_score_poses; the scores go to library scratch and
+ * are discarded.  Per-pose results do not depend on the shape except that the fused and the
+ * chunk-major evaluation sum the ranks in different orders (both within the parity
+ * tolerance).  Synchronises the context stream.  `report` may be NULL.
+ * Errors: as rsd_score_poses; RSD_E_OOM if the scratch does not fit the budget. */
+typedef struct rsd_tune_report {
+  int32_t score_mode;      /* chosen: 1 fused, 2 chunk-major */
+  int32_t poses_per_wave;  /* chosen (chunk-major) */
+  int32_t short_waves;     /* chosen */
+  int32_t candidates;      /* shapes timed */
+  double best_ms;          /* per call on the sample, chosen shape */
+  double default_ms;       /* per call on the sample, untuned automatic shape */
+} rsd_tune_report;
+
+rsd_status rsd_autotune(rsd_context* ctx, const rsd_tensor* t, const double* lig_charges,
+                        const double* lig_positions, int64_t L, const double* quats, const double* trans,
+                        int64_t P, double vdw_min, int32_t grads, rsd_tune_report* report);
 
 /* Kernel timing with HIP events on the context stream (off by default).  When on,
  * every library kernel launch is bracketed by events and its duration is added to

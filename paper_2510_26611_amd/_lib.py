@@ -28,7 +28,7 @@ EXPORTED = [
     "rsd_context_memory", "rsd_context_free", "rsd_build_rs_tensor", "rsd_tensor_import",
     "rsd_score_poses", "rsd_tensor_query", "rsd_tensor_export", "rsd_tensor_save",
     "rsd_tensor_load", "rsd_tensor_free", "rsd_context_set_timing", "rsd_kernel_time",
-    "rsd_context_set_option", "rsd_batch_create", "rsd_batch_run", "rsd_batch_free",
+    "rsd_context_set_option", "rsd_batch_create", "rsd_batch_run", "rsd_batch_free", "rsd_autotune",
 ]
 
 
@@ -42,6 +42,11 @@ class Request(C.Structure):
                 ("L", C.c_int64), ("quats", C.c_void_p), ("trans", C.c_void_p), ("P", C.c_int64),
                 ("vdw_min", C.c_double), ("energies", C.c_void_p), ("energies_long", C.c_void_p),
                 ("flags", C.c_void_p), ("counts", C.c_void_p)]
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("score_mode", C.c_int32), ("poses_per_wave", C.c_int32), ("short_waves", C.c_int32),
+                ("candidates", C.c_int32), ("best_ms", C.c_double), ("default_ms", C.c_double)]
 
 
 _P = C.c_void_p
@@ -76,6 +81,7 @@ def _declare(lib: C.CDLL) -> C.CDLL:
         "rsd_batch_create": (st, [_P, C.POINTER(Request), _I32, C.POINTER(_P)]),
         "rsd_batch_run": (st, [_P]),
         "rsd_batch_free": (None, [_P]),
+        "rsd_autotune": (st, [_P, _P, _P, _P, _I64, _P, _P, _I64, _D, _I32, C.POINTER(TuneReport)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -523,7 +523,8 @@ rsd_status rsd_score_poses(rsd_context* ctx, const rsd_tensor* t, const double* 
   const size_t nout = (size_t)P * (2 + (grads ? 6 : 0));
   const size_t bytes = sizeof(double) * (nin + nout) + (size_t)P * (sizeof(int32_t) + 1) + 64;
   char* stage = nullptr;
-  RSD_TRY(ctx->dev_alloc((void**)&stage, bytes));
+  size_t stage_bytes = bytes;
+  RSD_TRY(ctx->block_alloc((void**)&stage, &stage_bytes));
   double* d = (double*)stage;
   io.lig_charges = d;
   io.lig_positions = d + L;
@@ -559,7 +560,43 @@ rsd_status rsd_score_poses(rsd_context* ctx, const rsd_tensor* t, const double* 
     set_error("hipStreamSynchronize: %s", hipGetErrorString(e));
     st = RSD_E_HIP;
   }
-  ctx->dev_free(stage, bytes);
+  ctx->block_release(stage, stage_bytes);   // reused in stream order by later calls
+  return st;
+}
+
+// ---------------------------------------------------------------- launch-shape tuner
+rsd_status rsd_autotune(rsd_context* ctx, const rsd_tensor* t, const double* lig_charges,
+                        const double* lig_positions, int64_t L, const double* quats, const double* trans,
+                        int64_t P, double vdw_min, int32_t grads, rsd_tune_report* report) {
+  clear_error();
+  RSD_CHECK(ctx != nullptr && t != nullptr, RSD_E_INVALID, "ctx or tensor is NULL");
+  RSD_CHECK(!ctx->closing, RSD_E_INVALID, "context has been freed");
+  RSD_CHECK(t->ctx->device == ctx->device, RSD_E_INVALID, "tensor lives on another device");
+  RSD_CHECK(L >= 1 && L <= kMaxLigand, RSD_E_UNSUPPORTED, "L=%lld outside [1, %d]", (long long)L, kMaxLigand);
+  RSD_CHECK(P >= 1 && P <= ((int64_t)1 << 33), RSD_E_INVALID, "P=%lld out of range", (long long)P);
+  RSD_CHECK(std::isfinite(vdw_min) && vdw_min >= 0, RSD_E_INVALID, "vdw_min must be finite and >= 0");
+  RSD_CHECK(lig_charges && lig_positions && quats && trans, RSD_E_INVALID, "input pointers are NULL");
+  RSD_HIP(hipSetDevice(ctx->device));
+  // scratch outputs: E | E_long unused | gradients | counts | flags
+  size_t bytes = (size_t)P * (sizeof(double) * (1 + (grads ? 6 : 0)) + sizeof(int32_t) + 1) + 256;
+  char* out = nullptr;
+  RSD_TRY(ctx->block_alloc((void**)&out, &bytes));
+  ScoreIO io{};
+  io.lig_charges = lig_charges;
+  io.lig_positions = lig_positions;
+  io.L = (int)L;
+  io.quats = quats;
+  io.trans = trans;
+  io.P = P;
+  io.vdw_min = vdw_min;
+  io.E = (double*)out;
+  io.El = nullptr;
+  io.grads = grads ? io.E + P : nullptr;
+  io.counts = (int32_t*)(io.E + P * (grads ? 7 : 1));
+  io.flags = (uint8_t*)(io.counts + P);
+  const rsd_status st = rsd::autotune(ctx, t, io, report);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->block_release(out, bytes);
   return st;
 }
 
@@ -721,6 +758,16 @@ rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t va
   if (std::strcmp(name, "t2c_solver") == 0) {
     RSD_CHECK(value >= 0 && value <= 2, RSD_E_INVALID, "t2c_solver must be 0, 1 or 2");
     ctx->opt_t2c = (int)value;
+    return RSD_OK;
+  }
+  if (std::strcmp(name, "short_waves") == 0) {
+    RSD_CHECK(value == 0 || value == 1 || value == 2 || value == 4, RSD_E_INVALID, "short_waves must be 0, 1, 2 or 4");
+    ctx->opt_short_waves = (int)value;
+    return RSD_OK;
+  }
+  if (std::strcmp(name, "use_tuning") == 0) {
+    RSD_CHECK(value == 0 || value == 1, RSD_E_INVALID, "use_tuning must be 0 or 1");
+    ctx->opt_use_tuning = (int)value;
     return RSD_OK;
   }
   if (std::strcmp(name, "gram_solver") == 0) {

@@ -5,8 +5,10 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <array>
 #include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "rsdock.h"
@@ -87,6 +89,10 @@ struct Context {
   int opt_t2c = 0;             // core slice SVDs: 0 auto, 1 Jacobi in LDS, 2 rocSOLVER
   int opt_eig = 0;             // Gram eigenvectors: 0 auto, 1 dense batched eigensolver, 2 subspace iteration
   int opt_gram = 0;            // Gram matrices: 0 auto, 1 Toeplitz x Hankel form, 2 dense matrix-core product
+  int opt_short_waves = 0;     // short-range kernel: wavefronts per workgroup (0 = automatic)
+  int opt_use_tuning = 1;      // apply shapes recorded by rsd_autotune to automatic calls
+  // launch shapes recorded by rsd_autotune: (n, nchunk, N, L, grad) -> (mode, ppw, short waves)
+  std::map<std::tuple<int, int, int64_t, int, int>, std::array<int, 3>> tuned;
   bool timing = false;
   std::vector<KernelTimer> pending;
   std::map<std::string, std::pair<int64_t, double>> ktime;
@@ -169,6 +175,7 @@ struct ScoreIO {
   double* grads;               // may be null
 };
 rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io);
+rsd_status autotune(Context* ctx, const Tensor* t, const ScoreIO& io, rsd_tune_report* rep);
 
 // many requests per launch (score.hip)
 struct Batch;

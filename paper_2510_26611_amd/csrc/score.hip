@@ -825,19 +825,32 @@ LongParams make_long_params(const Tensor* t, const ScoreIO& io, const double4* l
 
 }  // namespace
 
+// Launch shape recorded by rsd_autotune for this workload, applied when the caller left all
+// three shape options automatic.
+void tuned_shape(const Context* ctx, const Tensor* t, int L, bool grad, int64_t P, int* mode, int* ppw, int* W) {
+  if (!ctx->opt_use_tuning || *mode != 0 || *ppw != 0 || *W != 0 || P < 256) return;
+  const auto it = ctx->tuned.find(std::make_tuple(t->n, t->nchunk, t->N, L, (int)grad));
+  if (it == ctx->tuned.end()) return;
+  *mode = it->second[0];
+  *ppw = it->second[1];
+  *W = it->second[2];
+}
+
 rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   if (io.P == 0) return RSD_OK;
   const bool grad = io.grads != nullptr;
   const int L = io.L;
   const int64_t P = io.P;
   hipStream_t s = ctx->stream;
+  int mode = ctx->opt_score_mode, ppw_want = ctx->opt_poses_per_wave, W_want = ctx->opt_short_waves;
+  tuned_shape(ctx, t, L, grad, P, &mode, &ppw_want, &W_want);
 
   // long-range mode: fused (one wavefront does the whole pose) or chunk-major (k_long)
   const int S = grad ? 7 : 1;
-  const int ppw = pick_ppw(L, grad, ctx->opt_poses_per_wave);
+  const int ppw = pick_ppw(L, grad, ppw_want);
   bool split = t->nchunk > 0 && long_lds(L, ppw, grad) <= 64 * 1024;
-  if (ctx->opt_score_mode == 1) split = false;
-  if (ctx->opt_score_mode == 0 && (t->nchunk < 2 || P < 256)) split = false;
+  if (mode == 1) split = false;
+  if (mode == 0 && (t->nchunk < 2 || P < 256)) split = false;
 
   // workspace: ligand (L double4) | radius | short energy (P) | short gradient (6P) | partials
   const size_t off_r = sizeof(double4) * (size_t)L;
@@ -854,8 +867,9 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
                    (k_ligand_prep<<<1, 64, 0, s>>>(io.lig_positions, io.lig_charges, L, lig, rlig)));
   const ScoreParams a = make_score_params(t, io, lig, rlig, (double*)(w8 + off_es), (double*)(w8 + off_gs));
 
-  int W = 4;
-  while (W > 1 && short_lds(L, W, grad) > 64 * 1024) W >>= 1;
+  int W = W_want > 0 ? W_want : 4;
+  if (W_want <= 0)
+    while (W > 1 && short_lds(L, W, grad) > 64 * 1024) W >>= 1;
   RSD_CHECK(short_lds(L, W, grad) <= 64 * 1024, RSD_E_UNSUPPORTED, "ligand of %d atoms needs too much LDS", L);
   const int64_t blocks = (P + W - 1) / W;
   RSD_CHECK(blocks <= 0x7fffffffLL, RSD_E_UNSUPPORTED, "too many poses in one call");
@@ -884,6 +898,79 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
     RSD_TIMED_LAUNCH(ctx, "long", (k_long<false><<<g2, 256, lds2, s>>>(lp)));
     RSD_TIMED_LAUNCH(ctx, "combine", (k_combine<false><<<gc, 256, 0, s>>>(lp.part, t->nchunk, P, a.es, a.gs,
                                                                             io.flags, io.E, io.El, nullptr)));
+  }
+  return RSD_OK;
+}
+
+// ---------------------------------------------------------------- launch-shape tuner
+rsd_status autotune(Context* ctx, const Tensor* t, const ScoreIO& io, rsd_tune_report* rep) {
+  const bool grad = io.grads != nullptr;
+  const int L = io.L;
+  hipStream_t s = ctx->stream;
+  const int saved[4] = {ctx->opt_score_mode, ctx->opt_poses_per_wave, ctx->opt_short_waves, ctx->opt_use_tuning};
+  const bool saved_timing = ctx->timing;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  struct Shape {
+    int mode, ppw, W;
+    double ms;
+  };
+  std::vector<Shape> cand;
+  double def_ms = 0.0;
+  auto body = [&]() -> rsd_status {
+    RSD_HIP(hipEventCreate(&e0));
+    RSD_HIP(hipEventCreate(&e1));
+    ctx->timing = false;
+    ctx->opt_use_tuning = 0;
+    auto time_shape = [&](int mode, int ppw, int W, double* ms) -> rsd_status {
+      ctx->opt_score_mode = mode;
+      ctx->opt_poses_per_wave = ppw;
+      ctx->opt_short_waves = W;
+      RSD_TRY(launch_score(ctx, t, io));   // untimed: code load, workspace growth
+      double best = 1e300;
+      for (int r = 0; r < 3; ++r) {
+        RSD_HIP(hipEventRecord(e0, s));
+        RSD_TRY(launch_score(ctx, t, io));
+        RSD_HIP(hipEventRecord(e1, s));
+        RSD_HIP(hipEventSynchronize(e1));
+        float f = 0.0f;
+        RSD_HIP(hipEventElapsedTime(&f, e0, e1));
+        best = std::min(best, (double)f);
+      }
+      *ms = best;
+      return RSD_OK;
+    };
+    RSD_TRY(time_shape(0, 0, 0, &def_ms));
+    for (int W : {1, 2, 4}) {
+      if (short_lds(L, W, grad) > 64 * 1024) continue;
+      cand.push_back({1, 0, W, 0.0});
+      if (t->nchunk == 0) continue;
+      for (int ppw = 1; ppw <= 4; ++ppw)
+        if (pick_ppw(L, grad, ppw) == ppw && long_lds(L, ppw, grad) <= 64 * 1024) cand.push_back({2, ppw, W, 0.0});
+    }
+    for (auto& c : cand) RSD_TRY(time_shape(c.mode, c.ppw, c.W, &c.ms));
+    return RSD_OK;
+  };
+  const rsd_status st = body();
+  ctx->opt_score_mode = saved[0];
+  ctx->opt_poses_per_wave = saved[1];
+  ctx->opt_short_waves = saved[2];
+  ctx->opt_use_tuning = saved[3];
+  ctx->timing = saved_timing;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st != RSD_OK) return st;
+  RSD_CHECK(!cand.empty(), RSD_E_UNSUPPORTED, "no launch shape fits the LDS for L=%d", L);
+  const Shape* best = &cand[0];
+  for (const auto& c : cand)
+    if (c.ms < best->ms) best = &c;
+  ctx->tuned[std::make_tuple(t->n, t->nchunk, t->N, L, (int)grad)] = {best->mode, best->ppw, best->W};
+  if (rep) {
+    rep->score_mode = best->mode;
+    rep->poses_per_wave = best->ppw;
+    rep->short_waves = best->W;
+    rep->candidates = (int32_t)cand.size();
+    rep->best_ms = best->ms;
+    rep->default_ms = def_ms;
   }
   return RSD_OK;
 }
@@ -947,7 +1034,9 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     nes += q.P;
     off_part[k] = npart;
     npart += (int64_t)t->nchunk * q.P;
-    ppw[k] = pick_ppw((int)q.L, false, ctx->opt_poses_per_wave);
+    int mode_k = ctx->opt_score_mode, ppw_k = ctx->opt_poses_per_wave, w_k = ctx->opt_short_waves;
+    tuned_shape(ctx, t, (int)q.L, false, q.P, &mode_k, &ppw_k, &w_k);
+    ppw[k] = pick_ppw((int)q.L, false, ppw_k);
     b->lds_long = std::max(b->lds_long, long_lds((int)q.L, ppw[k], false));
   }
   const size_t sz_desc = sizeof(BatchDesc) * (size_t)nreq;

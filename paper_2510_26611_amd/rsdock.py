@@ -91,6 +91,18 @@ class Context:
     def set_option(self, name: str, value: int) -> None:
         _check(_lib.lib().rsd_context_set_option(self.handle, name.encode(), int(value)))
 
+    def autotune(self, tensor: "Tensor", lig_charges, lig_positions, quats, trans, vdw_min: float,
+                 grads: bool = False) -> dict:
+        """rsd_autotune on a sample of a workload (device tensors); returns the report as a dict."""
+        args = [_arr(x) for x in (lig_charges, lig_positions, quats, trans)]
+        if not all(a[2] for a in args):
+            raise TypeError("autotune takes device tensors")
+        rep = _lib.TuneReport()
+        _check(_lib.lib().rsd_autotune(self.handle, tensor.handle, args[0][0], args[1][0], int(args[0][1].shape[0]),
+                                       args[2][0], args[3][0], int(args[2][1].shape[0]), float(vdw_min),
+                                       int(bool(grads)), C.byref(rep)))
+        return {k: getattr(rep, k) for k, _ in _lib.TuneReport._fields_}
+
     def set_timing(self, enable: bool) -> None:
         _check(_lib.lib().rsd_context_set_timing(self.handle, int(bool(enable))))
 

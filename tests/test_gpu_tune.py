@@ -1,0 +1,100 @@
+"""GPU tests of rsd_autotune: the recorded launch shape is used by later automatic calls,
+results stay at parity with the oracle, and flags/counts do not depend on the shape."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+from gpu_common import assert_parity, oracle_factors, oracle_score  # noqa: E402
+from workloads import configs, generators as gen  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2510_26611_amd as rs
+    ctx = rs.Context(0)
+    cfg = configs.CONFIG1
+    wl = configs.make(cfg)
+    q = gen.unit_quaternions(gen.rng(71, 5), 3000)
+    tr = gen.sphere_translations(gen.rng(71, 6), 3000, 18.0)
+    wl.quats, wl.trans = q, tr
+    _, can = oracle_factors(cfg, wl)
+    t = rs.tensor_import(ctx, can.F, cfg.n, cfg.b, rs.Sinc.from_config(cfg), wl.protein_charges,
+                         wl.protein_positions)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    dev = dict(z=d(wl.ligand_charges), x=d(wl.ligand_positions), q=d(q), t=d(tr))
+    yield rs, torch, ctx, cfg, wl, can.F, t, dev
+    t.free()
+    ctx.close()
+
+
+def _score(rs, torch, ctx, t, dev, sigma, grads):
+    out = rs.score_poses(ctx, t, dev["z"], dev["x"], dev["q"], dev["t"], sigma, grads=grads)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+@pytest.mark.parametrize("grads", [False, True])
+def test_tuned_shape_is_used_and_stays_at_parity(env, grads):
+    rs, torch, ctx, cfg, wl, F, t, dev = env
+    ctx.set_option("use_tuning", 0)
+    before = _score(rs, torch, ctx, t, dev, cfg.sigma, grads)
+    ctx.set_option("use_tuning", 1)
+    rep = ctx.autotune(t, dev["z"], dev["x"], dev["q"][:2048], dev["t"][:2048], cfg.sigma, grads=grads)
+    print(rep)
+    assert rep["score_mode"] in (1, 2) and rep["short_waves"] in (1, 2, 4) and rep["candidates"] >= 3
+    # the untuned shape is one of the candidates: the best is no slower than it (timing noise aside)
+    assert 0 < rep["best_ms"] <= 1.25 * rep["default_ms"]
+    if rep["score_mode"] == 2:
+        assert 1 <= rep["poses_per_wave"] <= 4
+    # a later automatic call launches the recorded kernels
+    ctx.set_timing(True)
+    after = _score(rs, torch, ctx, t, dev, cfg.sigma, grads)
+    n_long = ctx.kernel_time("long")[0]
+    n_fused = ctx.kernel_time("score")[0]
+    ctx.set_timing(False)
+    assert (n_long, n_fused) == ((1, 0) if rep["score_mode"] == 2 else (0, 1))
+    # flags and counts never depend on the shape; energies are at parity either way
+    assert np.array_equal(after["flags"], before["flags"]) and np.array_equal(after["counts"], before["counts"])
+    ref = oracle_score(cfg, wl, F, wl.quats, wl.trans, grad=grads)
+    assert_parity(after, ref, grad=grads, label=f"tuned shape {rep}")
+    # with the table ignored the untuned result comes back bit for bit
+    ctx.set_option("use_tuning", 0)
+    again = _score(rs, torch, ctx, t, dev, cfg.sigma, grads)
+    ctx.set_option("use_tuning", 1)
+    for k in before:
+        assert np.array_equal(again[k], before[k], equal_nan=True), k
+
+
+def test_explicit_options_override_the_table(env):
+    rs, torch, ctx, cfg, wl, F, t, dev = env
+    ctx.autotune(t, dev["z"], dev["x"], dev["q"][:1024], dev["t"][:1024], cfg.sigma)
+    for mode, kernel in ((1, "score"), (2, "long")):
+        ctx.set_option("score_mode", mode)
+        ctx.set_timing(True)
+        _score(rs, torch, ctx, t, dev, cfg.sigma, False)
+        assert ctx.kernel_time(kernel)[0] == 1
+        ctx.set_timing(False)
+    ctx.set_option("score_mode", 0)
+    ctx.set_option("short_waves", 2)
+    out = _score(rs, torch, ctx, t, dev, cfg.sigma, False)
+    ctx.set_option("short_waves", 0)
+    ref = oracle_score(cfg, wl, F, wl.quats, wl.trans)
+    assert_parity(out, ref, label="short_waves=2")
+
+
+def test_autotune_argument_errors(env):
+    rs, torch, ctx, cfg, wl, F, t, dev = env
+    with pytest.raises(TypeError):
+        ctx.autotune(t, wl.ligand_charges, wl.ligand_positions, wl.quats, wl.trans, cfg.sigma)
+    with pytest.raises(rs.RsdError) as e:
+        ctx.autotune(t, dev["z"], dev["x"], dev["q"][:0], dev["t"][:0], cfg.sigma)
+    assert e.value.code == -1
+    with pytest.raises(rs.RsdError):
+        ctx.set_option("short_waves", 3)
