@@ -1,0 +1,67 @@
+"""Pins of the oracle against the worked example the paper prints (Table 3.2, Sec. 3.3).
+
+The paper's tensor values come from its own discretisation (Galerkin factors, charges
+snapped to the grid), so they are not reproduced value by value; what is pinned is the
+direct energy of the caption, the first-order decay of the paper's tensor error with the
+grid size, and that the oracle's collocated/trilinear energy of the same two-charge system
+converges to the direct value at least that fast.
+"""
+import math
+import os
+
+import numpy as np
+
+from oracle import constants, direct, rhosvd, score, sinc
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table_3_2_two_charges.txt")
+
+
+def _table():
+    rows, e_direct = [], None
+    with open(GOLDEN) as f:
+        for line in f:
+            if line.startswith("# direct:"):
+                e_direct = float(line.split(":")[1])
+            elif line.strip() and not line.startswith("#"):
+                n, rank, e_t, diff = line.split()
+                rows.append((int(n), int(rank), float(e_t), float(diff)))
+    return e_direct, rows
+
+
+ZETA = -1.0 / math.sqrt(2.0)                       # ligand charge; protein charge +1 (reading)
+POS = np.full(3, math.sqrt(3.0))                    # 3 a.u. from the origin, off every grid plane
+
+
+def test_fixture_is_self_consistent_and_first_order():
+    e_direct, rows = _table()
+    for _, _, e_t, diff in rows:
+        assert abs((e_direct - e_t) - diff) <= 1.5e-4      # the printed columns agree to their 4 digits
+    errs = [r[3] for r in rows]
+    ratios = [a / b for a, b in zip(errs, errs[1:])]
+    assert all(1.9 <= q <= 2.1 for q in ratios)            # O(h): the error halves per grid doubling
+
+
+def test_direct_energy_of_the_caption():
+    e_direct, _ = _table()
+    E = direct.energies(np.zeros((1, 3)), np.ones(1), np.array([ZETA]), np.zeros((1, 3)),
+                        np.array([[1.0, 0.0, 0.0, 0.0]]), POS[None, :])[0]
+    assert round(E, 4) == e_direct
+
+
+def test_rs_energy_of_two_charges_converges_at_least_first_order():
+    e_direct = ZETA / 3.0
+    b, M, K = 8.0, 24, 12
+    L_s = constants.scale_length(b)
+    h_M = constants.optimal_step(M, b)
+    t, w = sinc.sinc_table(M, h_M, L_s)
+    (tl, wl), (ts, ws) = sinc.split(t, w, K)
+    r_cut = constants.short_cutoff(M, h_M, L_s, K)
+    errs = []
+    for n in (32, 64, 128, 256):
+        _, can = rhosvd.build(np.ones(1), np.zeros((1, 3)), tl, wl, n, b, 1e-12)
+        out = score.score(can.F, n, b, np.zeros((1, 3)), np.ones(1), ts, ws, r_cut, np.array([ZETA]),
+                          np.zeros((1, 3)), np.array([[1.0, 0.0, 0.0, 0.0]]), POS[None, :], 0.5)
+        errs.append(abs(out["E"][0] - e_direct))
+    ratios = [a / c for a, c in zip(errs, errs[1:])]
+    assert all(q >= 2.0 for q in ratios), (errs, ratios)     # at least the paper's first order
+    assert errs[-1] < 1e-3 * abs(e_direct)
