@@ -190,6 +190,15 @@ def main() -> int:
     achieved = alg_bytes / (dom_ms / 1e3) / 1e9
     traffic = _traffic(P) if args.workload == "cfg2" else None
     flags = out["flags"].cpu().numpy()
+    # the same scoring call with host arrays (PCIe upload and download inside the call)
+    t = rs.build_rs_tensor(ctx, d_z, d_x, cfg.n, cfg.b, sinc)
+    rs.score_poses(ctx, t, wl.ligand_charges, wl.ligand_positions, wl.quats[:4096], wl.trans[:4096], cfg.sigma,
+                   grads=want_grad)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rs.score_poses(ctx, t, wl.ligand_charges, wl.ligand_positions, wl.quats, wl.trans, cfg.sigma, grads=want_grad)
+    host_io_s = time.perf_counter() - t1
+    t.free()
     res = {
         "metric": METRIC, "value": P / (ms_step / 1e3), "unit": "poses/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
@@ -204,6 +213,7 @@ def main() -> int:
                      "traffic": traffic},
         "breakdown": {k: {"launches": v[0], "ms_per_step": v[1] / args.steps} for k, v in kt.items() if v[0]},
         "autotune": tune,
+        "score_host_arrays_poses_per_s": P / host_io_s,
         "score_only_poses_per_s": P / (score_ms / 1e3),
         "accept_fraction": float(np.mean(flags & 1)),
     }

@@ -668,7 +668,7 @@ struct BatchDesc {
   const double* lig_z;
   int64_t pose_base;    // first pose of the request in the combine launch
   int64_t short_base;   // first short-range block of the request within its ligand-size bucket
-  int64_t xcd_base;     // first long-range slot of the request on every XCD
+  int64_t xcd_base;     // first long-range slot of the request on every XCD, within its bucket
 };
 
 // last request r with key(r) <= x (requests with nothing to do share the next one's key)
@@ -718,10 +718,12 @@ __global__ __launch_bounds__(256) void k_batch_short(const BatchDesc* __restrict
   score_pose<false, false>(a, p, s_lig, s_y, q, rowoff, rowstart, lane);
 }
 
-// Each request's work list is split into 8 contiguous parts, part x running on XCD x, exactly
-// as for a single request; XCD x walks its parts of the requests in order.
-__global__ __launch_bounds__(256) void k_batch_long(const BatchDesc* __restrict__ d, int nreq) {
+// Requests [first, first + nreq) of one ligand-size bucket (LDS sized for that bucket).  Each
+// request's work list is split into 8 contiguous parts, part x running on XCD x, exactly as
+// for a single request; XCD x walks its parts of the requests in order.
+__global__ __launch_bounds__(256) void k_batch_long(const BatchDesc* __restrict__ dall, int first, int nreq) {
   extern __shared__ double4 smem[];
+  const BatchDesc* d = dall + first;
   const int64_t j = blockIdx.x >> 3;
   const int r = find_request_uniform(d, nreq, j, [](const BatchDesc& x) { return x.xcd_base; });
   const LongParams lp = d[r].lp;
@@ -788,6 +790,17 @@ size_t short_lds(int L, int W, bool grad) {
   return sizeof(double4) * (size_t)L * (1 + W) + (size_t)W * (pair_bytes * kQueue + 128 * sizeof(int));
 }
 
+constexpr size_t kLdsDefault = 64 * 1024;   // dynamic LDS a kernel gets without asking
+constexpr size_t kLdsMax = 160 * 1024;       // LDS of one gfx950 compute unit
+
+// Dynamic LDS beyond the default must be allowed per kernel function.
+rsd_status allow_lds(const void* kernel, size_t bytes) {
+  if (bytes <= kLdsDefault) return RSD_OK;
+  RSD_CHECK(bytes <= kLdsMax, RSD_E_UNSUPPORTED, "kernel needs %zu bytes of LDS", bytes);
+  RSD_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return RSD_OK;
+}
+
 size_t long_lds(int L, int ppw, bool grad) {
   const int PB = 4 * ppw;
   return sizeof(double4) * (size_t)L + (size_t)PB * L * (sizeof(GridPt) + (grad ? sizeof(double4) : 0)) +
@@ -848,7 +861,7 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   // long-range mode: fused (one wavefront does the whole pose) or chunk-major (k_long)
   const int S = grad ? 7 : 1;
   const int ppw = pick_ppw(L, grad, ppw_want);
-  bool split = t->nchunk > 0 && long_lds(L, ppw, grad) <= 64 * 1024;
+  bool split = t->nchunk > 0 && long_lds(L, ppw, grad) <= kLdsMax;
   if (mode == 1) split = false;
   if (mode == 0 && (t->nchunk < 2 || P < 256)) split = false;
 
@@ -888,6 +901,7 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   const dim3 g2((unsigned)(lp.per_xcd * 8));
   const size_t lds2 = long_lds(L, ppw, grad);
   const unsigned gc = (unsigned)std::min<int64_t>((P + 255) / 256, 65536);
+  RSD_TRY(allow_lds(grad ? (const void*)k_long<true> : (const void*)k_long<false>, lds2));
   if (grad) {
     RSD_TIMED_LAUNCH(ctx, "short", (k_score<true, false><<<g1, b1, lds1, s>>>(a)));
     RSD_TIMED_LAUNCH(ctx, "long", (k_long<true><<<g2, 256, lds2, s>>>(lp)));
@@ -945,7 +959,7 @@ rsd_status autotune(Context* ctx, const Tensor* t, const ScoreIO& io, rsd_tune_r
       cand.push_back({1, 0, W, 0.0});
       if (t->nchunk == 0) continue;
       for (int ppw = 1; ppw <= 4; ++ppw)
-        if (pick_ppw(L, grad, ppw) == ppw && long_lds(L, ppw, grad) <= 64 * 1024) cand.push_back({2, ppw, W, 0.0});
+        if (pick_ppw(L, grad, ppw) == ppw && long_lds(L, ppw, grad) <= kLdsMax) cand.push_back({2, ppw, W, 0.0});
     }
     for (auto& c : cand) RSD_TRY(time_shape(c.mode, c.ppw, c.W, &c.ms));
     return RSD_OK;
@@ -984,17 +998,16 @@ struct Batch {
   BatchDesc* d = nullptr;
   struct Bucket {
     int first, count, W;
-    size_t lds;
-    int64_t blocks;
+    size_t lds, lds_long;
+    int64_t blocks, long_slots;
   };
-  std::vector<Bucket> buckets;   // short-range launches, one per ligand-size class
-  size_t lds_long = 0;
-  int64_t long_slots = 0, poses = 0;
+  std::vector<Bucket> buckets;   // short- and long-range launches, one pair per ligand-size class
+  int64_t poses = 0;
   std::vector<BatchDesc> host_table;   // source of the (asynchronous) table upload
   hipEvent_t uploaded = nullptr;       // recorded after the upload: host_table may go once it completes
 };
 
-// ligand-size classes for the short-range launches (LDS grows with L)
+// ligand-size classes of the launches (LDS, hence occupancy, depends on L)
 static int ligand_bucket(int64_t L) { return L <= 32 ? 0 : L <= 64 ? 1 : L <= 128 ? 2 : L <= 256 ? 3 : 4; }
 
 rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, Batch** out) {
@@ -1037,7 +1050,6 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     int mode_k = ctx->opt_score_mode, ppw_k = ctx->opt_poses_per_wave, w_k = ctx->opt_short_waves;
     tuned_shape(ctx, t, (int)q.L, false, q.P, &mode_k, &ppw_k, &w_k);
     ppw[k] = pick_ppw((int)q.L, false, ppw_k);
-    b->lds_long = std::max(b->lds_long, long_lds((int)q.L, ppw[k], false));
   }
   const size_t sz_desc = sizeof(BatchDesc) * (size_t)nreq;
   const size_t o_lig = (sz_desc + 255) / 256 * 256;
@@ -1052,7 +1064,7 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
   }
   char* m = (char*)b->mem;
   std::vector<BatchDesc> h((size_t)nreq);
-  int64_t pb = 0, xb = 0;
+  int64_t pb = 0;
   for (int k = 0; k < nreq; ++k) {
     const rsd_request& q = req_in[order[k]];
     const Tensor* t = static_cast<const Tensor*>(q.tensor);
@@ -1078,43 +1090,48 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     h[k].lig_pos = q.lig_positions;
     h[k].lig_z = q.lig_charges;
     h[k].pose_base = pb;
-    h[k].xcd_base = xb;
     pb += q.P;
-    xb += h[k].lp.per_xcd;
   }
-  // short-range buckets
+  // ligand-size buckets: one short-range and one long-range launch each, LDS sized per bucket
   for (int k = 0; k < nreq;) {
     const int bk = ligand_bucket(req_in[order[k]].L);
     int e = k;
     int maxL = 1;
     while (e < nreq && ligand_bucket(req_in[order[e]].L) == bk) maxL = std::max(maxL, (int)req_in[order[e++]].L);
-    Batch::Bucket bu{k, e - k, 4, 0, 0};
+    Batch::Bucket bu{k, e - k, 4, 0, 0, 0, 0};
     while (bu.W > 1 && short_lds(maxL, bu.W, false) > 64 * 1024) bu.W >>= 1;
     bu.lds = short_lds(maxL, bu.W, false);
-    int64_t sb = 0;
+    int64_t sb = 0, xb = 0;
     for (int i = k; i < e; ++i) {
       h[i].short_base = sb;
       sb += (h[i].sp.P + bu.W - 1) / bu.W;
+      h[i].xcd_base = xb;
+      xb += h[i].lp.per_xcd;
+      bu.lds_long = std::max(bu.lds_long, long_lds(h[i].lp.L, ppw[i], false));
     }
     bu.blocks = sb;
-    if (sb > 0x7fffffffLL) {
+    bu.long_slots = xb;
+    rsd_status lst = RSD_OK;
+    if (bu.lds > kLdsDefault) {
+      set_error("ligand of %d atoms needs too much LDS", maxL);
+      lst = RSD_E_UNSUPPORTED;
+    } else {
+      lst = allow_lds((const void*)k_batch_long, bu.lds_long);
+    }
+    if (lst == RSD_OK && (sb > 0x7fffffffLL || xb * 8 > 0x7fffffffLL)) {
+      set_error("batch too large for one launch");
+      lst = RSD_E_UNSUPPORTED;
+    }
+    if (lst != RSD_OK) {
       ctx->block_release(b->mem, b->bytes);
       delete b;
-      set_error("batch too large for one launch");
-      return RSD_E_UNSUPPORTED;
+      return lst;
     }
-    if (sb > 0) b->buckets.push_back(bu);
+    if (sb > 0 || xb > 0) b->buckets.push_back(bu);
     k = e;
   }
   b->poses = pb;
-  b->long_slots = xb;
   b->d = (BatchDesc*)m;
-  if (xb * 8 > 0x7fffffffLL) {
-    ctx->block_release(b->mem, b->bytes);
-    delete b;
-    set_error("batch too large for one launch");
-    return RSD_E_UNSUPPORTED;
-  }
   b->host_table = std::move(h);
   hipError_t e = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming);
   if (e == hipSuccess) e = hipMemcpyAsync(b->d, b->host_table.data(), sz_desc, hipMemcpyHostToDevice, ctx->stream);
@@ -1139,12 +1156,14 @@ rsd_status batch_run(Batch* b) {
   if (b->poses == 0) return RSD_OK;
   RSD_TIMED_LAUNCH(ctx, "ligand_prep", (k_batch_prep<<<b->nreq, 64, 0, s>>>(b->d)));
   for (const auto& bu : b->buckets) {
-    RSD_TIMED_LAUNCH(ctx, "short", (k_batch_short<<<(unsigned)bu.blocks, 64 * bu.W, bu.lds, s>>>(
-                                       b->d, bu.first, bu.count)));
+    if (bu.blocks > 0)
+      RSD_TIMED_LAUNCH(ctx, "short", (k_batch_short<<<(unsigned)bu.blocks, 64 * bu.W, bu.lds, s>>>(
+                                         b->d, bu.first, bu.count)));
   }
-  if (b->long_slots > 0) {
-    RSD_TIMED_LAUNCH(ctx, "long", (k_batch_long<<<(unsigned)(b->long_slots * 8), 256, b->lds_long, s>>>(
-                                      b->d, b->nreq)));
+  for (const auto& bu : b->buckets) {
+    if (bu.long_slots > 0)
+      RSD_TIMED_LAUNCH(ctx, "long", (k_batch_long<<<(unsigned)(bu.long_slots * 8), 256, bu.lds_long, s>>>(
+                                        b->d, bu.first, bu.count)));
   }
   const unsigned gc = (unsigned)std::min<int64_t>((b->poses + 255) / 256, 65536);
   RSD_TIMED_LAUNCH(ctx, "combine", (k_batch_combine<<<gc, 256, 0, s>>>(b->d, b->nreq, b->poses)));

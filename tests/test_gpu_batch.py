@@ -7,6 +7,7 @@ import pytest
 
 sys.path.insert(0, os.path.dirname(__file__))
 from gpu_common import assert_parity, oracle_factors, oracle_score  # noqa: E402
+from oracle import score as oscore, sinc as osinc  # noqa: E402
 from workloads import configs, generators as gen  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -26,18 +27,21 @@ def env():
     pos = gen.ball_points(gen.rng(81, 1), 60, 6.0)
     z = gen.charges(gen.rng(81, 2), 60, 0.3, True)
     sinc2 = rs.Sinc(cfg.M, cfg.h_M, cfg.L_s, 16, 9.5, 1e-8)
-    t2 = rs.tensor_import(ctx, [g.normal(size=(96, 257)) * 0.01 for _ in range(3)], 96, 30.0, sinc2, z, pos)
+    F2 = [g.normal(size=(96, 257)) * 0.01 for _ in range(3)]
+    t2 = rs.tensor_import(ctx, F2, 96, 30.0, sinc2, z, pos)
     t3 = rs.tensor_import(ctx, [np.zeros((96, 0))] * 3, 96, 30.0, sinc2, z, pos)
-    yield rs, ctx, torch, dict(cfg=cfg, wl=wl, F=can.F, t1=t1, t2=t2, t3=t3)
+    yield rs, ctx, torch, dict(cfg=cfg, wl=wl, F=can.F, t1=t1, t2=t2, t3=t3, F2=F2, z2=z, pos2=pos, sinc2=sinc2)
     for t in (t1, t2, t3):
         t.free()
     ctx.close()
 
 
 def _requests(torch, T, seed):
-    """Mixed requests: three tensors, ligands of 1..200 atoms, 0..1000 poses."""
+    """Mixed requests: three tensors, ligands of 1..600 atoms (the last needs more than 64 KB of
+    LDS in the long-range kernel), 0..1000 poses."""
     specs = [("t1", 12, 128, 18.0), ("t2", 65, 1000, 9.0), ("t1", 1, 1, 12.0), ("t3", 7, 50, 9.0),
-             ("t2", 200, 333, 14.0), ("t1", 12, 0, 18.0), ("t2", 13, 257, 9.0), ("t1", 30, 700, 17.0)]
+             ("t2", 200, 333, 14.0), ("t1", 12, 0, 18.0), ("t2", 13, 257, 9.0), ("t1", 30, 700, 17.0),
+             ("t2", 600, 150, 16.0)]
     reqs = []
     for i, (tn, L, P, rad) in enumerate(specs):
         if tn == "t1" and L == 12:
@@ -88,6 +92,15 @@ def test_batch_equals_alone_bitwise_and_oracle(env):
     ref = oracle_score(cfg, T["wl"], T["F"], r0["np_q"], r0["np_t"])
     got = {k: v.cpu().numpy() for k, v in r0["out"].items()}
     assert_parity(got, ref, label="batch request 0")
+    # the 600-atom ligand against the oracle on the random factors
+    rb = reqs[-1]
+    sc = T["sinc2"]
+    t, w = osinc.sinc_table(sc.M, sc.h_M, sc.L_s)
+    _, (ts, ws) = osinc.split(t, w, sc.K_long)
+    ref = oscore.score(T["F2"], 96, 30.0, T["pos2"], T["z2"], ts, ws, sc.r_cut, rb["np_zeta"], rb["np_lig"],
+                       rb["np_q"], rb["np_t"], rb["vdw_min"])
+    got = {k: v.cpu().numpy() for k, v in rb["out"].items()}
+    assert_parity(got, ref, label="batch request with 600 ligand atoms")
     b.free()
 
 
