@@ -169,6 +169,29 @@ __device__ __forceinline__ bool in_grid(double y, double X0, double inv_h, doubl
   return s >= 0.0 && s <= smax;
 }
 
+// Two columns of one chunk for one atom: lerp each mode between rows i and i+1 (A, B),
+// multiply the modes and accumulate the value (and the three one-sided derivative products).
+template <bool GRAD>
+__device__ __forceinline__ void long_pair(const double2 A0, const double2 B0, const double2 A1, const double2 B1,
+                                          const double2 A2, const double2 B2, const double f0, const double f1,
+                                          const double f2, double& part, double& g0, double& g1, double& g2) {
+  const double dx0 = B0.x - A0.x, dx1 = B1.x - A1.x, dx2 = B2.x - A2.x;
+  const double dy0 = B0.y - A0.y, dy1 = B1.y - A1.y, dy2 = B2.y - A2.y;
+  const double lx0 = fma(f0, dx0, A0.x), lx1 = fma(f1, dx1, A1.x), lx2 = fma(f2, dx2, A2.x);
+  const double ly0 = fma(f0, dy0, A0.y), ly1 = fma(f1, dy1, A1.y), ly2 = fma(f2, dy2, A2.y);
+  const double lx01 = lx0 * lx1, ly01 = ly0 * ly1;
+  part = fma(lx01, lx2, part);
+  part = fma(ly01, ly2, part);
+  if (GRAD) {
+    g0 = fma(dx0 * lx1, lx2, g0);
+    g0 = fma(dy0 * ly1, ly2, g0);
+    g1 = fma(lx0 * dx1, lx2, g1);
+    g1 = fma(ly0 * dy1, ly2, g1);
+    g2 = fma(lx01, dx2, g2);
+    g2 = fma(ly01, dy2, g2);
+  }
+}
+
 template <bool GRAD>
 struct PairT;
 template <>
@@ -250,58 +273,46 @@ __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4*
   double eL = 0.0, eS = 0.0;
   double gt0 = 0.0, gt1 = 0.0, gt2 = 0.0, gw0 = 0.0, gw1 = 0.0, gw2 = 0.0;
 
-  // ---- A2: long-range, lanes own factor columns
+  // ---- A2: long-range.  The two half-wavefronts take two different atoms; lane j of a half
+  // owns columns 2j and 2j+1 of every chunk and loads them from rows i and i+1 as 16-byte
+  // loads (twice the bytes per lane of 8-byte loads through the same return path).
   if (LONG && dom && a.nchunk > 0) {
     const int nm2 = a.n - 2;
-    const int64_t cs = a.chunk_stride;
-    for (int l = 0; l < L; ++l) {
-      const double4 y = s_y[l];
+    const int64_t cs = a.chunk_stride / 2;                 // in double2
+    const int half = lane >> 5, col2 = lane & 31;
+    for (int l = 0; l < L; l += 2) {
+      const int lx = l + half;
+      const int la = lx < L ? lx : L - 1;                  // a missing partner repeats atom L-1 with no charge
+      const double4 y = s_y[la];
+      const double zeta = lx < L ? y.w : 0.0;
       const double s0 = (y.x - a.X0) * a.inv_h, s1 = (y.y - a.X0) * a.inv_h, s2 = (y.z - a.X0) * a.inv_h;
       const int i0 = min((int)floor(s0), nm2), i1 = min((int)floor(s1), nm2), i2 = min((int)floor(s2), nm2);
       const double f0 = s0 - (double)i0, f1 = s1 - (double)i1, f2 = s2 - (double)i2;
-      const double* p0 = a.F + (int64_t)i0 * kChunk + lane;
-      const double* p1 = a.F + a.mode_stride + (int64_t)i1 * kChunk + lane;
-      const double* p2 = a.F + 2 * a.mode_stride + (int64_t)i2 * kChunk + lane;
+      const double2* p0 = (const double2*)(a.F + (int64_t)i0 * kChunk) + col2;
+      const double2* p1 = (const double2*)(a.F + a.mode_stride + (int64_t)i1 * kChunk) + col2;
+      const double2* p2 = (const double2*)(a.F + 2 * a.mode_stride + (int64_t)i2 * kChunk) + col2;
       double part = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
       int c = 0;
-      for (; c + 4 <= a.nchunk; c += 4) {
-        double A0[4], B0[4], A1[4], B1[4], A2[4], B2[4];
+      for (; c + 2 <= a.nchunk; c += 2) {
+        double2 A0[2], B0[2], A1[2], B1[2], A2[2], B2[2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          A0[u] = p0[u * cs]; B0[u] = p0[u * cs + kChunk];
-          A1[u] = p1[u * cs]; B1[u] = p1[u * cs + kChunk];
-          A2[u] = p2[u * cs]; B2[u] = p2[u * cs + kChunk];
+        for (int u = 0; u < 2; ++u) {
+          A0[u] = p0[u * cs]; B0[u] = p0[u * cs + kChunk / 2];
+          A1[u] = p1[u * cs]; B1[u] = p1[u * cs + kChunk / 2];
+          A2[u] = p2[u * cs]; B2[u] = p2[u * cs + kChunk / 2];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const double d0 = B0[u] - A0[u], d1 = B1[u] - A1[u], d2 = B2[u] - A2[u];
-          const double l0 = fma(f0, d0, A0[u]), l1 = fma(f1, d1, A1[u]), l2 = fma(f2, d2, A2[u]);
-          const double l01 = l0 * l1;
-          part = fma(l01, l2, part);
-          if (GRAD) {
-            g0 = fma(d0 * l1, l2, g0);
-            g1 = fma(l0 * d1, l2, g1);
-            g2 = fma(l01, d2, g2);
-          }
-        }
-        p0 += 4 * cs; p1 += 4 * cs; p2 += 4 * cs;
+        for (int u = 0; u < 2; ++u)
+          long_pair<GRAD>(A0[u], B0[u], A1[u], B1[u], A2[u], B2[u], f0, f1, f2, part, g0, g1, g2);
+        p0 += 2 * cs; p1 += 2 * cs; p2 += 2 * cs;
       }
       for (; c < a.nchunk; ++c) {
-        const double A0 = p0[0], B0 = p0[kChunk], A1 = p1[0], B1 = p1[kChunk], A2 = p2[0], B2 = p2[kChunk];
-        const double d0 = B0 - A0, d1 = B1 - A1, d2 = B2 - A2;
-        const double l0 = fma(f0, d0, A0), l1 = fma(f1, d1, A1), l2 = fma(f2, d2, A2);
-        const double l01 = l0 * l1;
-        part = fma(l01, l2, part);
-        if (GRAD) {
-          g0 = fma(d0 * l1, l2, g0);
-          g1 = fma(l0 * d1, l2, g1);
-          g2 = fma(l01, d2, g2);
-        }
+        long_pair<GRAD>(p0[0], p0[kChunk / 2], p1[0], p1[kChunk / 2], p2[0], p2[kChunk / 2], f0, f1, f2, part, g0, g1, g2);
         p0 += cs; p1 += cs; p2 += cs;
       }
-      eL = fma(y.w, part, eL);
+      eL = fma(zeta, part, eL);
       if (GRAD) {
-        const double zh = y.w * a.inv_h;
+        const double zh = zeta * a.inv_h;
         const double v0 = y.x - tx, v1 = y.y - ty, v2 = y.z - tz;   // R u_l
         const double G0 = zh * g0, G1 = zh * g1, G2 = zh * g2;
         gt0 += G0; gt1 += G1; gt2 += G2;
@@ -538,7 +549,13 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
   }
   __syncthreads();
   const int lane = tid & 63, wv = tid >> 6;
-  const double* F0 = a.F + (int64_t)c * a.chunk_stride + lane;
+  // The two half-wavefronts take two different atoms; lane j of a half owns columns 2j and
+  // 2j+1 of the chunk and loads them from rows i and i+1 as 16-byte loads.  The return path
+  // from L2 moves a fixed number of lanes per clock, so 16 instead of 8 bytes per lane nearly
+  // halves the time of these gathers.  Atoms past L in the last group use atom L-1's rows with
+  // a zero charge.
+  const int half = lane >> 5;
+  const double* F0 = a.F + (int64_t)c * a.chunk_stride + 2 * (lane & 31);
   const double* F1 = F0 + a.mode_stride;
   const double* F2 = F1 + a.mode_stride;
   for (int k = 0; k < a.ppw; ++k) {
@@ -548,57 +565,44 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
     double e = 0.0, gt0 = 0.0, gt1 = 0.0, gt2 = 0.0, gw0 = 0.0, gw1 = 0.0, gw2 = 0.0;
     if (!s_bad[lp]) {
       const GridPt* pts = s_pt + lp * L;
-      int l = 0;
-      for (; l + 4 <= L; l += 4) {
-        double A0[4], B0[4], A1[4], B1[4], A2[4], B2[4], f0[4], f1[4], f2[4];
+      for (int l0 = 0; l0 < L; l0 += 4) {
+        double2 A0[2], B0[2], A1[2], B1[2], A2[2], B2[2];
+        double f0[2], f1[2], f2[2], zeta[2];
+        int la[2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const GridPt g = pts[l + u];
+        for (int u = 0; u < 2; ++u) {
+          const int lx = l0 + 2 * u + half;
+          la[u] = lx < L ? lx : L - 1;
+          zeta[u] = lx < L ? s_lig[la[u]].w : 0.0;
+          const GridPt g = pts[la[u]];
           f0[u] = g.f0; f1[u] = g.f1; f2[u] = g.f2;
-          const double* q0 = F0 + (int64_t)g.i0 * kChunk;
-          const double* q1 = F1 + (int64_t)g.i1 * kChunk;
-          const double* q2 = F2 + (int64_t)g.i2 * kChunk;
-          A0[u] = q0[0]; B0[u] = q0[kChunk];
-          A1[u] = q1[0]; B1[u] = q1[kChunk];
-          A2[u] = q2[0]; B2[u] = q2[kChunk];
+          const double2* q0 = (const double2*)(F0 + (int64_t)g.i0 * kChunk);
+          const double2* q1 = (const double2*)(F1 + (int64_t)g.i1 * kChunk);
+          const double2* q2 = (const double2*)(F2 + (int64_t)g.i2 * kChunk);
+          A0[u] = q0[0]; B0[u] = q0[kChunk / 2];
+          A1[u] = q1[0]; B1[u] = q1[kChunk / 2];
+          A2[u] = q2[0]; B2[u] = q2[kChunk / 2];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const double d0 = B0[u] - A0[u], d1 = B1[u] - A1[u], d2 = B2[u] - A2[u];
-          const double l0 = fma(f0[u], d0, A0[u]), l1 = fma(f1[u], d1, A1[u]), l2 = fma(f2[u], d2, A2[u]);
-          const double zeta = s_lig[l + u].w;
-          const double l01 = l0 * l1;
-          e = fma(zeta, l01 * l2, e);
+        for (int u = 0; u < 2; ++u) {
+          const double dx0 = B0[u].x - A0[u].x, dx1 = B1[u].x - A1[u].x, dx2 = B2[u].x - A2[u].x;
+          const double dy0 = B0[u].y - A0[u].y, dy1 = B1[u].y - A1[u].y, dy2 = B2[u].y - A2[u].y;
+          const double lx0 = fma(f0[u], dx0, A0[u].x), lx1 = fma(f1[u], dx1, A1[u].x), lx2 = fma(f2[u], dx2, A2[u].x);
+          const double ly0 = fma(f0[u], dy0, A0[u].y), ly1 = fma(f1[u], dy1, A1[u].y), ly2 = fma(f2[u], dy2, A2[u].y);
+          const double lx01 = lx0 * lx1, ly01 = ly0 * ly1;
+          e = fma(zeta[u], lx01 * lx2, e);
+          e = fma(zeta[u], ly01 * ly2, e);
           if (GRAD) {
-            const double zh = zeta * a.inv_h;
-            const double G0 = zh * (d0 * l1 * l2), G1 = zh * (l0 * d1 * l2), G2 = zh * (l01 * d2);
-            const double4 v = s_v[lp * L + l + u];
+            const double zh = zeta[u] * a.inv_h;
+            const double G0 = zh * (dx0 * lx1 * lx2 + dy0 * ly1 * ly2);
+            const double G1 = zh * (lx0 * dx1 * lx2 + ly0 * dy1 * ly2);
+            const double G2 = zh * (lx01 * dx2 + ly01 * dy2);
+            const double4 v = s_v[lp * L + la[u]];
             gt0 += G0; gt1 += G1; gt2 += G2;
             gw0 += v.y * G2 - v.z * G1;
             gw1 += v.z * G0 - v.x * G2;
             gw2 += v.x * G1 - v.y * G0;
           }
-        }
-      }
-      for (; l < L; ++l) {
-        const GridPt g = pts[l];
-        const double* q0 = F0 + (int64_t)g.i0 * kChunk;
-        const double* q1 = F1 + (int64_t)g.i1 * kChunk;
-        const double* q2 = F2 + (int64_t)g.i2 * kChunk;
-        const double A0 = q0[0], B0 = q0[kChunk], A1 = q1[0], B1 = q1[kChunk], A2 = q2[0], B2 = q2[kChunk];
-        const double d0 = B0 - A0, d1 = B1 - A1, d2 = B2 - A2;
-        const double l0 = fma(g.f0, d0, A0), l1 = fma(g.f1, d1, A1), l2 = fma(g.f2, d2, A2);
-        const double zeta = s_lig[l].w;
-        const double l01 = l0 * l1;
-        e = fma(zeta, l01 * l2, e);
-        if (GRAD) {
-          const double zh = zeta * a.inv_h;
-          const double G0 = zh * (d0 * l1 * l2), G1 = zh * (l0 * d1 * l2), G2 = zh * (l01 * d2);
-          const double4 v = s_v[lp * L + l];
-          gt0 += G0; gt1 += G1; gt2 += G2;
-          gw0 += v.y * G2 - v.z * G1;
-          gw1 += v.z * G0 - v.x * G2;
-          gw2 += v.x * G1 - v.y * G0;
         }
       }
     }
