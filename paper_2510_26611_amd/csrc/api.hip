@@ -105,6 +105,20 @@ rsd_status Context::workspace(size_t bytes, void** out) {
   return RSD_OK;
 }
 
+rsd_status Context::aux_streams() {
+  for (int i = 0; i < 2; ++i) {
+    if (!aux_stream[i]) RSD_HIP(hipStreamCreateWithFlags(&aux_stream[i], hipStreamNonBlocking));
+    if (!aux_blas[i]) {
+      rocblas_handle h = nullptr;
+      RSD_CHECK(rocblas_create_handle(&h) == rocblas_status_success, RSD_E_HIP, "rocblas_create_handle failed");
+      aux_blas[i] = h;
+    }
+    RSD_CHECK(rocblas_set_stream((rocblas_handle)aux_blas[i], aux_stream[i]) == rocblas_status_success, RSD_E_HIP,
+              "rocblas_set_stream failed");
+  }
+  return RSD_OK;
+}
+
 rsd_status Context::timer_begin(const char* name, KernelTimer* t) {
   t->name = name;
   RSD_HIP(hipEventCreate(&t->start));
@@ -243,6 +257,11 @@ static void context_destroy(Context* ctx) {
   ctx->dev_free(ctx->ws, ctx->ws_bytes);
   ctx->ws = nullptr;
   if (ctx->blas) rocblas_destroy_handle((rocblas_handle)ctx->blas);
+  for (int i = 0; i < 2; ++i) {
+    if (ctx->aux_stream[i]) (void)hipStreamSynchronize(ctx->aux_stream[i]);
+    if (ctx->aux_blas[i]) rocblas_destroy_handle((rocblas_handle)ctx->aux_blas[i]);
+    if (ctx->aux_stream[i]) (void)hipStreamDestroy(ctx->aux_stream[i]);
+  }
   delete static_cast<rsd_context*>(ctx);
 }
 

@@ -562,16 +562,19 @@ struct DevBuf {
   double* p = nullptr;
   size_t bytes = 0;
   rsd_status alloc(Context* c, size_t n) {
+    release();
     ctx = c;
     bytes = sizeof(double) * (n ? n : 1);
     return c->dev_alloc((void**)&p, bytes);
   }
-  ~DevBuf() {   // work queued on the stream may still read the buffer
+  void release() {   // work queued on the context stream may still read the buffer
     if (p) {
       (void)hipStreamSynchronize(ctx->stream);
       ctx->dev_free(p, bytes);
+      p = nullptr;
     }
   }
+  ~DevBuf() { release(); }
 };
 
 inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -601,83 +604,179 @@ rsd_status check_info(Context* ctx, rocblas_int* d_info, int count, const char* 
   return RSD_OK;
 }
 
-// Dominant eigenvectors of the symmetric PSD Gram matrix G (n x n, row-major, upper tiles
-// filled) by randomized subspace iteration: Y = G Omega, one power step, Q = orth(Y)
-// (Householder QR), Rayleigh-Ritz on Q^T G Q.  The subspace of k columns is doubled until its
-// k-th Ritz value lies below eps^2 times the largest, with 16 columns of margin, so every
-// eigenvalue that the rank rule keeps is inside it.  Output: U (n x ldu, row-major, first r
-// columns), eigenvalues descending in lam.
-rsd_status subspace_eigvecs(Context* ctx, rocblas_handle hb, double* G, int n, double eps, uint64_t seed,
-                            rocblas_int* d_info, DevBuf* U, int* r_out, int* ldu_out, std::vector<double>* lam) {
-  hipStream_t s = ctx->stream;
-  RSD_TIMED_LAUNCH(ctx, "eig", (k_symmetrize<<<grid1d((int64_t)n * n), 256, 0, s>>>(G, n)));
-  int k = std::min(n, 128);
-  for (;;) {
-    DevBuf Om, Y, Z, T, W, E, tau;
-    RSD_TRY(Om.alloc(ctx, (size_t)n * k));
-    RSD_TRY(Y.alloc(ctx, (size_t)n * k));
-    RSD_TRY(Z.alloc(ctx, (size_t)n * k));
-    RSD_TRY(T.alloc(ctx, (size_t)k * k));
-    RSD_TRY(W.alloc(ctx, k));
-    RSD_TRY(E.alloc(ctx, k));
-    RSD_TRY(tau.alloc(ctx, k));
-    RSD_TIMED_LAUNCH(ctx, "eig", (k_random_fill<<<grid1d((int64_t)n * k), 256, 0, s>>>(Om.p, (int64_t)n * k, seed)));
-    auto qr = [&](double* A) -> rsd_status {   // A: column-major n x k -> orthonormal Q in place
-      RSD_CHECK(rocsolver_dgeqrf(hb, n, k, A, n, tau.p) == rocblas_status_success, RSD_E_HIP, "rocsolver_dgeqrf failed");
-      RSD_CHECK(rocsolver_dorgqr(hb, n, k, k, A, n, tau.p) == rocblas_status_success, RSD_E_HIP, "rocsolver_dorgqr failed");
-      return RSD_OK;
-    };
-    GemmShape g{};
-    g.split_stride = 0; g.accumulate = 0; g.tri = 0;
-    // Y^T = Omega^T G  (k x n row-major = n x k column-major)
-    g.M = k; g.N = n; g.K = n; g.kper = ((int64_t)n + TK - 1) / TK * TK; g.C = Y.p; g.ldc = n;
-    RSD_TRY(gemm(ctx, "eig", OpKM{Om.p, k, k}, OpKM{G, n, n}, g, 1));
-    KernelTimer kt;
-    if (ctx->timing) RSD_TRY(ctx->timer_begin("eig", &kt));
-    RSD_TRY(qr(Y.p));
-    if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
-    // one power step: Y^T = Q^T G, orthonormalise again
-    g.C = Z.p;
-    RSD_TRY(gemm(ctx, "eig", OpMK{Y.p, n, k}, OpKM{G, n, n}, g, 1));
-    if (ctx->timing) RSD_TRY(ctx->timer_begin("eig", &kt));
-    RSD_TRY(qr(Z.p));
-    if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
-    // Rayleigh-Ritz: W^T = Q^T G (k x n), T = Q^T G Q (k x k)
-    g.C = Y.p;
-    RSD_TRY(gemm(ctx, "eig", OpMK{Z.p, n, k}, OpKM{G, n, n}, g, 1));
-    GemmShape gt = g;
-    gt.M = k; gt.N = k; gt.K = n; gt.C = T.p; gt.ldc = k;
-    RSD_TRY(gemm(ctx, "eig", OpMK{Z.p, n, k}, OpMK{Y.p, n, k}, gt, 1));
-    if (ctx->timing) RSD_TRY(ctx->timer_begin("eig", &kt));
-    rocblas_status rs = rocsolver_dsyevd(hb, rocblas_evect_original, rocblas_fill_upper, k, T.p, k, W.p, E.p, d_info);
-    RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dsyevd failed (%d)", (int)rs);
-    if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
-    RSD_TRY(check_info(ctx, d_info, 1, "Ritz eigensolver"));
-    std::vector<double> w((size_t)k);
-    RSD_HIP(hipMemcpy(w.data(), W.p, sizeof(double) * k, hipMemcpyDeviceToHost));
-    const double lmax = w[k - 1];
-    RSD_CHECK(lmax > 0.0 && std::isfinite(lmax), RSD_E_NUMERIC, "Gram matrix has no positive eigenvalue");
-    int r = 0;
-    for (int i = k - 1; i >= 0 && w[i] >= eps * eps * lmax; --i) ++r;
-    if (r > k - 16 && k < n) {
-      k = std::min(n, 2 * k);
-      continue;
+// Dominant eigenvectors of the three modes' symmetric PSD Gram matrices G_d (n x n, row-major
+// and exactly symmetric), by randomized subspace iteration: Y = G Omega with k deterministic
+// test vectors, an orthonormal basis Q of Y (Householder QR), one power step Q <- orth(G Q),
+// then Rayleigh-Ritz on Q^T G Q (k x k).  Eigenvalues >= eps^2 * the largest are kept; if
+// fewer than 16 of the k Ritz values fall below that cut, k is doubled and the mode is redone.
+// The three modes run on three streams (the context stream and two auxiliary ones, each with
+// its own rocBLAS handle): their QR and small eigensolver calls are chains of short launches,
+// which then overlap.  The host synchronises once per pass to read the Ritz values.
+rsd_status subspace_eigvecs3(Context* ctx, rocblas_handle hb, double* G3, int n, double eps, rocblas_int* d_info,
+                             DevBuf U[3], int r_out[3], int ldu_out[3]) {
+  hipStream_t main = ctx->stream;
+  RSD_TRY(ctx->aux_streams());
+  hipStream_t st[3] = {main, ctx->aux_stream[0], ctx->aux_stream[1]};
+  rocblas_handle hbs[3] = {hb, (rocblas_handle)ctx->aux_blas[0], (rocblas_handle)ctx->aux_blas[1]};
+  const int64_t nn = (int64_t)n * n;
+  for (int d = 0; d < 3; ++d)
+    RSD_TIMED_LAUNCH(ctx, "eig", (k_symmetrize<<<grid1d(nn), 256, 0, main>>>(G3 + d * nn, n)));
+  hipEvent_t ready = nullptr, done[2] = {nullptr, nullptr};
+  struct Events {
+    hipEvent_t* e[3];
+    ~Events() {
+      for (auto* x : e)
+        if (*x) (void)hipEventDestroy(*x);
     }
-    RSD_CHECK(r >= 1 && r <= 1024, RSD_E_UNSUPPORTED, "rank %d outside [1, 1024]", r);
-    const int ldu = ((r + 7) / 8) * 8;
-    DevBuf Vsel;
-    RSD_TRY(Vsel.alloc(ctx, (size_t)k * ldu));
-    RSD_TIMED_LAUNCH(ctx, "eig", (k_take_eigvecs<<<grid1d((int64_t)k * ldu), 256, 0, s>>>(T.p, k, r, Vsel.p, ldu)));
-    RSD_TRY(U->alloc(ctx, (size_t)n * ldu));
-    GemmShape gu = g;
-    gu.M = n; gu.N = r; gu.K = k; gu.kper = ((int64_t)k + TK - 1) / TK * TK; gu.C = U->p; gu.ldc = ldu;
-    RSD_TRY(gemm(ctx, "eig", OpKM{Z.p, n, n}, OpKM{Vsel.p, ldu, r}, gu, 1));
-    lam->assign(w.rbegin(), w.rend());
-    *r_out = r;
-    *ldu_out = ldu;
-    RSD_HIP(hipStreamSynchronize(s));
-    return RSD_OK;
+  } evguard{{&ready, &done[0], &done[1]}};
+  RSD_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  RSD_HIP(hipEventCreateWithFlags(&done[0], hipEventDisableTiming));
+  RSD_HIP(hipEventCreateWithFlags(&done[1], hipEventDisableTiming));
+  RSD_HIP(hipEventRecord(ready, main));
+  RSD_HIP(hipStreamWaitEvent(st[1], ready, 0));
+  RSD_HIP(hipStreamWaitEvent(st[2], ready, 0));
+  struct Mode {
+    int k = 0;
+    bool finished = false;
+    DevBuf Om, Y, Z, T, W, E, tau;
+  } m[3];
+  for (int d = 0; d < 3; ++d) m[d].k = std::min(n, 128);
+  struct StreamGuard {   // issue a mode's work on its stream; the context stream comes back afterwards
+    Context* c;
+    hipStream_t saved;
+    ~StreamGuard() { c->stream = saved; }
+  } sg{ctx, main};
+  rsd_status st_all = RSD_OK;
+  for (int pass = 0; pass < 8 && st_all == RSD_OK; ++pass) {
+    bool any = false;
+    for (int d = 0; d < 3; ++d) {
+      Mode& md = m[d];
+      if (md.finished) continue;
+      any = true;
+      ctx->stream = st[d];
+      const int k = md.k;
+      auto issue = [&]() -> rsd_status {
+        RSD_TRY(md.Om.alloc(ctx, (size_t)n * k));
+        RSD_TRY(md.Y.alloc(ctx, (size_t)n * k));
+        RSD_TRY(md.Z.alloc(ctx, (size_t)n * k));
+        RSD_TRY(md.T.alloc(ctx, (size_t)k * k));
+        RSD_TRY(md.W.alloc(ctx, k));
+        RSD_TRY(md.E.alloc(ctx, k));
+        RSD_TRY(md.tau.alloc(ctx, k));
+        double* G = G3 + d * nn;
+        RSD_TIMED_LAUNCH(ctx, "eig", (k_random_fill<<<grid1d((int64_t)n * k), 256, 0, st[d]>>>(
+                                         md.Om.p, (int64_t)n * k, 0x5EEDull + (uint64_t)d)));
+        auto qr = [&](double* A) -> rsd_status {   // A: column-major n x k -> orthonormal Q in place
+          KernelTimer kt;
+          if (ctx->timing) RSD_TRY(ctx->timer_begin("eig", &kt));
+          RSD_CHECK(rocsolver_dgeqrf(hbs[d], n, k, A, n, md.tau.p) == rocblas_status_success, RSD_E_HIP,
+                    "rocsolver_dgeqrf failed");
+          RSD_CHECK(rocsolver_dorgqr(hbs[d], n, k, k, A, n, md.tau.p) == rocblas_status_success, RSD_E_HIP,
+                    "rocsolver_dorgqr failed");
+          if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+          return RSD_OK;
+        };
+        GemmShape g{};
+        g.split_stride = 0; g.accumulate = 0; g.tri = 0;
+        // Y^T = Omega^T G  (k x n row-major = n x k column-major)
+        g.M = k; g.N = n; g.K = n; g.kper = ((int64_t)n + TK - 1) / TK * TK; g.C = md.Y.p; g.ldc = n;
+        RSD_TRY(gemm(ctx, "eig", OpKM{md.Om.p, k, k}, OpKM{G, n, n}, g, 1));
+        RSD_TRY(qr(md.Y.p));
+        // one power step: Z^T = Q^T G, orthonormalise again
+        g.C = md.Z.p;
+        RSD_TRY(gemm(ctx, "eig", OpMK{md.Y.p, n, k}, OpKM{G, n, n}, g, 1));
+        RSD_TRY(qr(md.Z.p));
+        // Rayleigh-Ritz: Y^T = Q^T G (k x n), T = Q^T G Q (k x k)
+        g.C = md.Y.p;
+        RSD_TRY(gemm(ctx, "eig", OpMK{md.Z.p, n, k}, OpKM{G, n, n}, g, 1));
+        GemmShape gt = g;
+        gt.M = k; gt.N = k; gt.K = n; gt.C = md.T.p; gt.ldc = k;
+        RSD_TRY(gemm(ctx, "eig", OpMK{md.Z.p, n, k}, OpMK{md.Y.p, n, k}, gt, 1));
+        KernelTimer kt;
+        if (ctx->timing) RSD_TRY(ctx->timer_begin("eig", &kt));
+        const rocblas_status rs = rocsolver_dsyevd(hbs[d], rocblas_evect_original, rocblas_fill_upper, k, md.T.p, k,
+                                                   md.W.p, md.E.p, d_info + d);
+        RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dsyevd failed (%d)", (int)rs);
+        if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+        return RSD_OK;
+      };
+      st_all = issue();
+      ctx->stream = main;
+      if (st_all != RSD_OK) break;
+    }
+    if (!any || st_all != RSD_OK) break;
+    // read every unfinished mode's Ritz values; finish the modes whose subspace was large enough
+    for (int d = 0; d < 3 && st_all == RSD_OK; ++d) {
+      Mode& md = m[d];
+      if (md.finished) continue;
+      const int k = md.k;
+      std::vector<double> w((size_t)k);
+      rocblas_int info = 0;
+      hipError_t e = hipMemcpyAsync(&info, d_info + d, sizeof(info), hipMemcpyDeviceToHost, st[d]);
+      if (e == hipSuccess) e = hipMemcpyAsync(w.data(), md.W.p, sizeof(double) * k, hipMemcpyDeviceToHost, st[d]);
+      if (e == hipSuccess) e = hipStreamSynchronize(st[d]);
+      if (e != hipSuccess) {
+        set_error("Ritz values: %s", hipGetErrorString(e));
+        st_all = RSD_E_HIP;
+        break;
+      }
+      if (info != 0) {
+        set_error("Ritz eigensolver of mode %d did not converge (info %d)", d, (int)info);
+        st_all = RSD_E_NUMERIC;
+        break;
+      }
+      const double lmax = w[k - 1];
+      if (!(lmax > 0.0 && std::isfinite(lmax))) {
+        set_error("Gram matrix of mode %d has no positive eigenvalue", d);
+        st_all = RSD_E_NUMERIC;
+        break;
+      }
+      int r = 0;
+      for (int i = k - 1; i >= 0 && w[i] >= eps * eps * lmax; --i) ++r;
+      if (r > k - 16 && k < n) {
+        md.k = std::min(n, 2 * k);   // redo this mode with a larger subspace on the next pass
+        continue;
+      }
+      if (r < 1 || r > 1024) {
+        set_error("mode-%d rank %d outside [1, 1024]", d, r);
+        st_all = RSD_E_UNSUPPORTED;
+        break;
+      }
+      const int ldu = ((r + 7) / 8) * 8;
+      ctx->stream = st[d];
+      auto finish = [&]() -> rsd_status {
+        DevBuf Vsel;
+        RSD_TRY(Vsel.alloc(ctx, (size_t)k * ldu));
+        RSD_TIMED_LAUNCH(ctx, "eig", (k_take_eigvecs<<<grid1d((int64_t)k * ldu), 256, 0, st[d]>>>(md.T.p, k, r,
+                                                                                                   Vsel.p, ldu)));
+        RSD_TRY(U[d].alloc(ctx, (size_t)n * ldu));
+        GemmShape gu{};
+        gu.split_stride = 0; gu.accumulate = 0; gu.tri = 0;
+        gu.M = n; gu.N = r; gu.K = k; gu.kper = ((int64_t)k + TK - 1) / TK * TK; gu.C = U[d].p; gu.ldc = ldu;
+        RSD_TRY(gemm(ctx, "eig", OpKM{md.Z.p, n, n}, OpKM{Vsel.p, ldu, r}, gu, 1));
+        RSD_HIP(hipStreamSynchronize(st[d]));   // Vsel and the mode's buffers are released next
+        return RSD_OK;
+      };
+      st_all = finish();
+      ctx->stream = main;
+      r_out[d] = r;
+      ldu_out[d] = ldu;
+      md.finished = true;
+    }
   }
+  // the context stream continues after the auxiliary streams' work
+  (void)hipEventRecord(done[0], st[1]);
+  (void)hipEventRecord(done[1], st[2]);
+  (void)hipStreamWaitEvent(main, done[0], 0);
+  (void)hipStreamWaitEvent(main, done[1], 0);
+  if (st_all != RSD_OK) {
+    (void)hipStreamSynchronize(st[1]);
+    (void)hipStreamSynchronize(st[2]);
+    return st_all;
+  }
+  for (int d = 0; d < 3; ++d)
+    RSD_CHECK(m[d].finished, RSD_E_NUMERIC, "subspace iteration of mode %d did not settle", d);
+  return RSD_OK;
 }
 
 }  // namespace
@@ -794,12 +893,9 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
     RSD_TRY(check_info(ctx, d_info, 3, "symmetric eigensolver"));
     RSD_HIP(hipMemcpy(lam3.data(), W3.p, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
   }
+  if (subspace) RSD_TRY(subspace_eigvecs3(ctx, hb, G3.p, n, eps, d_info, U, r, ldu));
   for (int d = 0; d < 3; ++d) {
-    if (subspace) {
-      std::vector<double> lam;
-      RSD_TRY(subspace_eigvecs(ctx, hb, G3.p + d * nn, n, eps, 0x5EEDull + (uint64_t)d, d_info, &U[d], &r[d],
-                               &ldu[d], &lam));
-    } else {
+    if (!subspace) {
       const double* lam = lam3.data() + (size_t)d * n;
       const double lmax = lam[n - 1];
       RSD_CHECK(lmax > 0.0 && std::isfinite(lmax), RSD_E_NUMERIC, "Gram matrix of mode %d has no positive eigenvalue",

@@ -81,6 +81,10 @@ struct Context {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   void* blas = nullptr;        // rocblas_handle for the eigen/SVD steps of the build (lazy)
+  // two more streams (default priority) and their rocblas handles: the build runs the three
+  // modes' eigensolvers concurrently on the context stream and these (lazy)
+  hipStream_t aux_stream[2] = {nullptr, nullptr};
+  void* aux_blas[2] = {nullptr, nullptr};
   int live_tensors = 0;        // tensors made with this context and not yet freed
   bool closing = false;        // rsd_context_free was called; released with the last tensor
   // tuning options (rsd_context_set_option)
@@ -109,6 +113,7 @@ struct Context {
   void block_release(void* p, size_t bytes);
   void block_trim();
   rsd_status workspace(size_t bytes, void** out);
+  rsd_status aux_streams();
   rsd_status timer_begin(const char* name, KernelTimer* t);
   rsd_status timer_end(KernelTimer* t);
   rsd_status collect_timers();
