@@ -208,7 +208,18 @@ struct PairT<true> {
 template <bool GRAD, bool LONG>
 __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4* __restrict__ s_lig,
                            double4* __restrict__ s_y, typename PairT<GRAD>::type* __restrict__ q,
-                           int* __restrict__ rowoff, int* __restrict__ rowstart, const int lane);
+                           int* __restrict__ rowoff, int* __restrict__ rowstart, const double* __restrict__ s_tab,
+                           const int lane);
+
+// The short-range table (t_k^2 then w_k, kMaxTerms each) staged in LDS: the pair loop reads it
+// once per term, and from global memory every read would be a full round trip (the compiler
+// cannot prove the table is not written by the kernel, so it uses vector loads).
+__device__ __forceinline__ void stage_short_table(const ScoreParams& a, double* __restrict__ s_tab) {
+  for (int i = threadIdx.x; i < kMaxTerms; i += blockDim.x) {
+    s_tab[i] = a.t2[i];
+    s_tab[kMaxTerms + i] = a.w[i];
+  }
+}
 
 template <bool GRAD, bool LONG>
 __global__ __launch_bounds__(256) void k_score(const ScoreParams a) {
@@ -224,19 +235,22 @@ __global__ __launch_bounds__(256) void k_score(const ScoreParams a) {
   Pair* q = (Pair*)(tail) + (size_t)wv * kQueue;
   int* rowoff = (int*)(tail + sizeof(Pair) * kQueue * W) + wv * 128;
   int* rowstart = rowoff + 64;
+  double* s_tab = (double*)(tail + sizeof(Pair) * kQueue * W + sizeof(int) * 128 * W);
 
   for (int i = threadIdx.x; i < L; i += blockDim.x) s_lig[i] = a.lig[i];
+  stage_short_table(a, s_tab);
   __syncthreads();
   const int64_t p = (int64_t)blockIdx.x * W + wv;
   if (p >= a.P) return;    // whole wavefront leaves; no block barrier follows
-  score_pose<GRAD, LONG>(a, p, s_lig, s_y, q, rowoff, rowstart, lane);
+  score_pose<GRAD, LONG>(a, p, s_lig, s_y, q, rowoff, rowstart, s_tab, lane);
 }
 
 // One pose on one wavefront: A1, A3, A4 (and A2 when LONG), A5.
 template <bool GRAD, bool LONG>
 __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4* __restrict__ s_lig,
                            double4* __restrict__ s_y, typename PairT<GRAD>::type* __restrict__ q,
-                           int* __restrict__ rowoff, int* __restrict__ rowstart, const int lane) {
+                           int* __restrict__ rowoff, int* __restrict__ rowstart, const double* __restrict__ s_tab,
+                           const int lane) {
   using Pair = typename PairT<GRAD>::type;
   const int L = a.L;
   // ---- A1: pose frame and atom positions
@@ -344,11 +358,12 @@ __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4*
       if (lane < m) {
         const Pair e = q[(qh + lane) & (kQueue - 1)];
         double gs = 0.0, dg = 0.0;
+#pragma unroll 2
         for (int k = 0; k < a.S; ++k) {
-          const double t2 = a.t2[k];
+          const double t2 = s_tab[k], wk = s_tab[kMaxTerms + k];
           const double ex = exp(-(t2 * e.d2));
-          gs = fma(a.w[k], ex, gs);
-          if (GRAD) dg = fma(a.w[k] * (-2.0 * t2), ex, dg);
+          gs = fma(wk, ex, gs);
+          if (GRAD) dg = fma(wk * (-2.0 * t2), ex, dg);
         }
         eS = fma(e.zz, gs, eS);
         if constexpr (GRAD) {
@@ -715,11 +730,13 @@ __global__ __launch_bounds__(256) void k_batch_short(const BatchDesc* __restrict
   PairE* q = (PairE*)(tail) + (size_t)wv * kQueue;
   int* rowoff = (int*)(tail + sizeof(PairE) * kQueue * W) + wv * 128;
   int* rowstart = rowoff + 64;
+  double* s_tab = (double*)(tail + sizeof(PairE) * kQueue * W + sizeof(int) * 128 * W);
   for (int i = threadIdx.x; i < L; i += blockDim.x) s_lig[i] = a.lig[i];
+  stage_short_table(a, s_tab);
   __syncthreads();
   const int64_t p = (blk - d[r].short_base) * W + wv;
   if (p >= a.P) return;
-  score_pose<false, false>(a, p, s_lig, s_y, q, rowoff, rowstart, lane);
+  score_pose<false, false>(a, p, s_lig, s_y, q, rowoff, rowstart, s_tab, lane);
 }
 
 // Requests [first, first + nreq) of one ligand-size bucket (LDS sized for that bucket).  Each
@@ -791,7 +808,8 @@ ScoreParams make_score_params(const Tensor* t, const ScoreIO& io, const double4*
 
 size_t short_lds(int L, int W, bool grad) {
   const size_t pair_bytes = grad ? sizeof(PairG) : sizeof(PairE);
-  return sizeof(double4) * (size_t)L * (1 + W) + (size_t)W * (pair_bytes * kQueue + 128 * sizeof(int));
+  return sizeof(double4) * (size_t)L * (1 + W) + (size_t)W * (pair_bytes * kQueue + 128 * sizeof(int)) +
+         2 * kMaxTerms * sizeof(double);
 }
 
 constexpr size_t kLdsDefault = 64 * 1024;   // dynamic LDS a kernel gets without asking
