@@ -92,19 +92,28 @@ def quat_valid(q: np.ndarray, t: np.ndarray) -> np.ndarray:
     return fin & (np.abs(qq - 1.0) <= QUAT_TOL)
 
 
-def long_range(F, n: int, b: float, y: np.ndarray, want_grad: bool = False):
+def long_range(F, n: int, b: float, y: np.ndarray, want_grad: bool = False, grid_spec=None):
     """Trilinear evaluation of the canonical tensor sum_p F1[:,p] x F2[:,p] x F3[:,p] (Lemma 3.3).
 
     y: (Q, 3) points.  Returns (value, in_domain, abs_scale, grad, grad_abs) per point;
     value/grad are NaN where the point is outside the grid.
-    Row i_d = min(floor(s_d), n-2) and weight f_d = s_d - i_d; the mode-d factor row
+    Row i_d = min(floor(s_d), n_d-2) and weight f_d = s_d - i_d; the mode-d factor row
     is (1-f_d) F_d[i_d] + f_d F_d[i_d+1]; its derivative (F_d[i_d+1]-F_d[i_d]) inv_h
     is the one-sided difference of eq. 3.12 inside the cell.
+    grid_spec = (X0s, inv_h, ns): per-mode origins and row counts (a tensor restricted to a
+    sub-box); default: the n-point grid on [-b, b] in every mode.
     """
-    _, X0, inv_h, _ = _tensor.grid(n, b)
+    if grid_spec is None:
+        _, X0, inv_h, _ = _tensor.grid(n, b)
+        X0s = np.full(3, X0)
+        ns = np.full(3, n, dtype=np.int64)
+    else:
+        X0s, inv_h, ns = grid_spec
+        X0s = np.asarray(X0s, dtype=np.float64)
+        ns = np.asarray(ns, dtype=np.int64)
     y = np.atleast_2d(y)
-    s = (y - X0) * inv_h
-    inside = np.all((s >= 0.0) & (s <= n - 1), axis=1)
+    s = (y - X0s[None, :]) * inv_h
+    inside = np.all((s >= 0.0) & (s <= (ns - 1)[None, :]), axis=1)
     Q = y.shape[0]
     val = np.full(Q, np.nan)
     scale = np.zeros(Q)
@@ -114,7 +123,7 @@ def long_range(F, n: int, b: float, y: np.ndarray, want_grad: bool = False):
     if ok.size == 0:
         return val, inside, scale, grad, gabs
     so = s[ok]
-    i = np.minimum(np.floor(so), n - 2).astype(np.int64)
+    i = np.minimum(np.floor(so), (ns - 2)[None, :]).astype(np.int64)
     f = so - i
     lerp, alerp, dl, adl = [], [], [], []
     for d in range(3):
@@ -181,7 +190,7 @@ def short_range(atoms, z, t_short, w_short, r_cut, y, want_grad: bool = False):
 
 
 def score(F, n, b, atoms, z, t_short, w_short, r_cut, lig_charges, lig_positions,
-          quats, trans, vdw_min, want_grad: bool = False, pose_chunk: int = 16):
+          quats, trans, vdw_min, want_grad: bool = False, pose_chunk: int = 16, grid_spec=None):
     """Score P poses (Algorithm PLIE with the short-range term and the vdW flag).
 
     Returns a dict with E, E_long (P,), flags (P,) uint8, counts (P,) int32,
@@ -215,7 +224,7 @@ def score(F, n, b, atoms, z, t_short, w_short, r_cut, lig_charges, lig_positions
         v = rotate(R, u)                                  # (Pc, L, 3) = R u
         y = v + trans[idx][:, None, :]
         pts = y.reshape(-1, 3)
-        lv, inside, lsc, lg, lga = long_range(F, n, b, pts, want_grad)
+        lv, inside, lsc, lg, lga = long_range(F, n, b, pts, want_grad, grid_spec)
         sv, cnt, md2, ssc, sg, sga = short_range(atoms, z, t_short, w_short, r_cut, pts, want_grad)
         Pc = idx.size
         inside = inside.reshape(Pc, L).all(axis=1)
