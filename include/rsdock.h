@@ -184,8 +184,31 @@ rsd_status rsd_batch_create(rsd_context* ctx, const rsd_request* requests, int32
 rsd_status rsd_batch_run(rsd_batch* batch);
 void rsd_batch_free(rsd_batch* batch);
 
+/* The long-range tensor restricted to a sub-box and rank-reduced (Sec. 3.3, scheme (C), the
+ * hybrid: the global tensor is computed once and its rank is reduced separately in each box
+ * that accompanies the ligand; Table 3.1 shows ranks far below the global ones).
+ * The new tensor keeps the grid rows of `src` that trilinear evaluation inside the box
+ * [lo, hi] (Angstrom, per axis) can reach: rows floor((lo_d - X0)/h) .. floor((hi_d - X0)/h) + 1
+ * of mode d, clipped to the grid, so its modes have their own origin and row count (see
+ * rsd_tensor_grid) and the same mesh h.  The restricted canonical tensor is exact there; its
+ * rank is then reduced by the build's RHOSVD steps at relative accuracy `eps` (explicit
+ * unit-norm factor columns, weights = products of the column norms).  The protein atoms,
+ * cell list and short-range table are copied, so scoring works as with any tensor; poses
+ * with an atom outside the kept rows are flagged out of domain.  The result belongs to
+ * `ctx` and is independent of `src` (which may be freed).  Restricted tensors cannot be
+ * saved.  Errors: RSD_E_INVALID for a NULL argument, lo >= hi, non-finite bounds, a box that
+ * misses the grid, or eps outside (0, 1); RSD_E_OOM beyond the budget. */
+rsd_status rsd_tensor_restrict(rsd_context* ctx, const rsd_tensor* src, const double lo[3], const double hi[3],
+                               double eps, rsd_tensor** out);
+
+/* Per-mode grid of a tensor: origin X0[d] (Angstrom), row count rows[d] and the mesh h.
+ * For tensors from rsd_build_rs_tensor / rsd_tensor_import every mode has X0 = -b + h and
+ * rows = n.  Any output pointer may be NULL. */
+rsd_status rsd_tensor_grid(const rsd_tensor* t, double X0[3], int32_t rows[3], double* h);
+
 /* Tensor metadata: grid size, canonical rank R, Tucker ranks (0 for imported tensors)
- * and resident device bytes.  Any output pointer may be NULL. */
+ * and resident device bytes.  Any output pointer may be NULL.  For a restricted tensor, n
+ * is the largest row count of its modes (the factor layout's rows). */
 rsd_status rsd_tensor_query(const rsd_tensor* t, int32_t* n, int64_t* R, int32_t ranks[3],
                             size_t* bytes);
 

@@ -29,6 +29,7 @@ EXPORTED = [
     "rsd_score_poses", "rsd_tensor_query", "rsd_tensor_export", "rsd_tensor_save",
     "rsd_tensor_load", "rsd_tensor_free", "rsd_context_set_timing", "rsd_kernel_time",
     "rsd_context_set_option", "rsd_batch_create", "rsd_batch_run", "rsd_batch_free", "rsd_autotune",
+    "rsd_tensor_restrict", "rsd_tensor_grid",
 ]
 
 
@@ -82,6 +83,8 @@ def _declare(lib: C.CDLL) -> C.CDLL:
         "rsd_batch_run": (st, [_P]),
         "rsd_batch_free": (None, [_P]),
         "rsd_autotune": (st, [_P, _P, _P, _P, _I64, _P, _P, _I64, _D, _I32, C.POINTER(TuneReport)]),
+        "rsd_tensor_restrict": (st, [_P, _P, C.POINTER(_D), C.POINTER(_D), _D, C.POINTER(_P)]),
+        "rsd_tensor_grid": (st, [_P, C.POINTER(_D), C.POINTER(_I32), C.POINTER(_D)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -217,6 +217,10 @@ static rsd_status tensor_common(Context* ctx, Tensor* t, int32_t n, double b, co
   t->n = n;
   t->b = b;
   grid_constants(n, b, &t->h, &t->X0, &t->inv_h);
+  for (int d = 0; d < 3; ++d) {
+    t->X0m[d] = t->X0;
+    t->nm[d] = n;
+  }
   t->sp = *sp;
   t->N = (int64_t)z.size();
   t->host_charges = std::move(z);
@@ -434,6 +438,84 @@ static rsd_status make_tensor(rsd_context* ctx, const double* const F[3], int64_
   return RSD_OK;
 }
 
+rsd_status rsd_tensor_restrict(rsd_context* ctx, const rsd_tensor* src, const double lo[3], const double hi[3],
+                               double eps, rsd_tensor** out) {
+  clear_error();
+  RSD_CHECK(out != nullptr, RSD_E_INVALID, "out is NULL");
+  *out = nullptr;
+  RSD_CHECK(ctx != nullptr && !ctx->closing, RSD_E_INVALID, "ctx is NULL or freed");
+  RSD_CHECK(src != nullptr && lo != nullptr && hi != nullptr, RSD_E_INVALID, "NULL argument");
+  RSD_CHECK(src->ctx->device == ctx->device, RSD_E_INVALID, "tensor lives on another device");
+  RSD_CHECK(std::isfinite(eps) && eps > 0 && eps < 1, RSD_E_INVALID, "eps must be in (0, 1)");
+  for (int d = 0; d < 3; ++d) {
+    RSD_CHECK(std::isfinite(lo[d]) && std::isfinite(hi[d]) && lo[d] < hi[d], RSD_E_INVALID,
+              "box axis %d: need finite lo < hi", d);
+    RSD_CHECK(hi[d] >= src->X0m[d] && lo[d] <= src->X0m[d] + (src->nm[d] - 1) * src->h, RSD_E_INVALID,
+              "box axis %d misses the grid", d);
+  }
+  RSD_HIP(hipSetDevice(ctx->device));
+  rsd_sinc_params sp = src->sp;
+  sp.eps = eps;
+  rsd_tensor* t = new (std::nothrow) rsd_tensor();
+  RSD_CHECK(t != nullptr, RSD_E_OOM, "host allocation failed");
+  t->ctx = ctx;
+  ctx->live_tensors += 1;
+  double* d_z = nullptr;
+  double* d_pos = nullptr;
+  std::vector<double> z = src->host_charges, pos = src->host_positions;
+  const int64_t N = (int64_t)z.size();
+  rsd_status st = tensor_common(ctx, t, src->n, src->b, &sp, std::move(z), std::move(pos), &d_z, &d_pos);
+  int i_lo[3] = {0, 0, 0};
+  if (st == RSD_OK) {
+    // rows of the source grid that evaluation inside [lo, hi] reaches (the source may itself be
+    // restricted: its mode d starts at row offset (X0m[d] - X0) / h of the full grid)
+    int nmax = 0;
+    for (int d = 0; d < 3; ++d) {
+      int a = (int)std::floor((lo[d] - src->X0m[d]) * src->inv_h);
+      int c = (int)std::floor((hi[d] - src->X0m[d]) * src->inv_h) + 1;
+      a = std::min(std::max(a, 0), src->nm[d] - 2);
+      c = std::min(std::max(c, a + 1), src->nm[d] - 1);
+      i_lo[d] = a;
+      t->nm[d] = c - a + 1;
+      t->X0m[d] = src->X0m[d] + (double)a * src->h;
+      nmax = std::max(nmax, t->nm[d]);
+    }
+    if (!src->restricted)   // rows of the full grid: origins as the grid nodes -b + (i + 1) h
+      for (int d = 0; d < 3; ++d) t->X0m[d] = -src->b + (double)(i_lo[d] + 1) * src->h;
+    t->n = nmax;
+    t->restricted = true;
+    st = restrict_factors(ctx, src, t, i_lo);
+  }
+  if (st == RSD_OK) {
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+      set_error("hipStreamSynchronize: %s", hipGetErrorString(e));
+      st = RSD_E_HIP;
+    }
+  }
+  ctx->dev_free(d_z, sizeof(double) * (size_t)(N ? N : 1));
+  ctx->dev_free(d_pos, sizeof(double) * 3 * (size_t)(N ? N : 1));
+  if (st != RSD_OK) {
+    std::string keep = g_err;
+    tensor_release(t);
+    g_err = keep;
+    return st;
+  }
+  *out = t;
+  return RSD_OK;
+}
+
+rsd_status rsd_tensor_grid(const rsd_tensor* t, double X0[3], int32_t rows[3], double* h) {
+  clear_error();
+  RSD_CHECK(t != nullptr, RSD_E_INVALID, "tensor is NULL");
+  for (int d = 0; d < 3; ++d) {
+    if (X0) X0[d] = t->X0m[d];
+    if (rows) rows[d] = t->nm[d];
+  }
+  if (h) *h = t->h;
+  return RSD_OK;
+}
+
 rsd_status rsd_build_rs_tensor(rsd_context* ctx, const double* charges, const double* positions, int64_t N,
                                int32_t n, double b, const rsd_sinc_params* sp, uint32_t mem_flags,
                                rsd_tensor** out) {
@@ -646,6 +728,7 @@ struct FileHeader {
 rsd_status rsd_tensor_save(const rsd_tensor* t, const char* path) {
   clear_error();
   RSD_CHECK(t != nullptr && path != nullptr, RSD_E_INVALID, "tensor or path is NULL");
+  RSD_CHECK(!t->restricted, RSD_E_UNSUPPORTED, "a tensor restricted to a sub-box cannot be saved");
   const size_t nR = (size_t)t->n * (size_t)t->R;
   std::vector<double> F(3 * nR);
   if (t->R > 0) RSD_TRY(rsd_tensor_export(t, F.data(), F.data() + nR, F.data() + 2 * nR));

@@ -158,6 +158,50 @@ struct OpGauss {              // element (k = grid row i, m = column c) = exp(-t
   }
 };
 
+// ----------------------------------------------------------------- restriction to a sub-box
+// Rows i0 .. i0 + rows - 1 of one mode of a chunked factor table as a row-major matrix:
+// A[i * R + p] = F[chunk p / kChunk][row i0 + i][p % kChunk].
+__global__ void k_take_rows(const double* __restrict__ F, int n_src, int64_t R, int i0, int rows,
+                            double* __restrict__ A) {
+  const int64_t total = (int64_t)rows * R;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / R);
+    const int64_t p = e % R;
+    A[e] = F[((p / kChunk) * n_src + i0 + i) * kChunk + p % kChunk];
+  }
+}
+
+// Column norms nu[p] = ||A[:, p]|| of a row-major rows x R matrix, one thread per column.
+__global__ void k_row_colnorms(const double* __restrict__ A, int rows, int64_t R, double* __restrict__ nu) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < R; p += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < rows; ++i) {
+      const double v = A[(int64_t)i * R + p];
+      s = fma(v, v, s);
+    }
+    nu[p] = sqrt(s);
+  }
+}
+
+// Term weights xi[p] = nu1 nu2 nu3; a term with a zero column in any mode is zero (xi = 0).
+__global__ void k_local_weights(const double* __restrict__ nu0, const double* __restrict__ nu1,
+                                const double* __restrict__ nu2, int64_t R, double* __restrict__ xi) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < R; p += (int64_t)gridDim.x * blockDim.x) {
+    const bool live = nu0[p] > 0.0 && nu1[p] > 0.0 && nu2[p] > 0.0;
+    xi[p] = live ? nu0[p] * nu1[p] * nu2[p] : 0.0;
+  }
+}
+
+// Unit-norm columns: A[i][p] /= nu[p]; the columns of zero terms are set to zero in every mode.
+__global__ void k_normalize_cols(double* __restrict__ A, int rows, int64_t R, const double* __restrict__ nu,
+                                 const double* __restrict__ xi) {
+  const int64_t total = (int64_t)rows * R;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e % R;
+    A[e] = xi[p] != 0.0 ? A[e] / nu[p] : 0.0;
+  }
+}
+
 // ----------------------------------------------------------------- FP64 MFMA GEMM
 // C[split][m][n] (+)= sum_{k in split} A(k, m) * B(k, n) for one 64 x 64 tile per workgroup.
 // Four wavefronts, each a 32 x 32 sub-tile of 2 x 2 v_mfma_f64_16x16x4 blocks.
@@ -427,9 +471,10 @@ __global__ void k_core_slices(const double* __restrict__ beta, int r1, int r2, i
   }
 }
 
-// F[chunk][i][j] = sum_a U[i * ldu + a] * V[a * R + p] with p = chunk * kChunk + j (zero for p >= R).
+// F[chunk][i][j] = sum_a U[i * ldu + a] * V[a * R + p] with p = chunk * kChunk + j (zero for p >= R
+// and for layout rows i >= rows, the rows U has).
 __global__ void k_assemble(const double* __restrict__ U, int ldu, int r, const double* __restrict__ V, int64_t R,
-                           int n, int nchunk, double* __restrict__ F) {
+                           int n, int rows, int nchunk, double* __restrict__ F) {
   const int64_t total = (int64_t)nchunk * n * kChunk;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int j = (int)(e % kChunk);
@@ -437,7 +482,7 @@ __global__ void k_assemble(const double* __restrict__ U, int ldu, int r, const d
     const int i = (int)(rest % n);
     const int64_t p = (rest / n) * kChunk + j;
     double s = 0.0;
-    if (p < R) {
+    if (p < R && i < rows) {   // U has `rows` rows; the layout's rows beyond them stay zero
       const double* u = U + (int64_t)i * ldu;
       for (int a = 0; a < r; ++a) s = fma(u[a], V[(int64_t)a * R + p], s);
     }
@@ -781,6 +826,189 @@ rsd_status subspace_eigvecs3(Context* ctx, rocblas_handle hb, double* G3, int n,
 
 }  // namespace
 
+// Steps 4-5 shared by the build and the restriction to a sub-box: the Tucker core
+// beta[(a*r2 + b)][c] = sum_col xi_col B1[col][a] B2[col][b] B3[col][c] (Bt_d = B_d^T, C columns),
+// the slice SVDs, and the canonical factors F_d = U_d V_d written into t's chunked layout
+// (mode d has t->nm[d] rows; rows beyond it, up to t->n, are zero).
+rsd_status tucker_canonical(Context* ctx, Tensor* t, DevBuf Bt[3], DevBuf U[3], const int r[3], const int ldu[3],
+                            const double* xi, int64_t C, rocblas_handle hb, rocblas_int* d_info) {
+  hipStream_t s = ctx->stream;
+  const double eps = t->sp.eps;
+  const int n = t->n;
+  const int M12 = r[0] * r[1];
+  const int tiles = div_up(M12, TM) * div_up(r[2], TN);
+  const int csplit = std::max(1, std::min(64, div_up(1024, tiles)));
+  DevBuf Cpart, beta;
+  RSD_TRY(Cpart.alloc(ctx, (size_t)csplit * M12 * r[2]));
+  RSD_TRY(beta.alloc(ctx, (size_t)M12 * r[2]));
+  OpKhatriRao kr{Bt[0].p, Bt[1].p, ldu[0], ldu[1], r[1], M12, {}, {}};
+  OpKMScaled b3{Bt[2].p, xi, ldu[2], r[2]};
+  {
+    GemmShape g{};
+    g.M = M12; g.N = r[2]; g.K = C;
+    g.kper = (int64_t)div_up(C, (int64_t)csplit * TK) * TK;
+    g.C = Cpart.p; g.ldc = r[2]; g.split_stride = (int64_t)M12 * r[2]; g.accumulate = 0; g.tri = 0;
+    RSD_TRY(gemm(ctx, "core", kr, b3, g, csplit));
+    RSD_TIMED_LAUNCH(ctx, "core", (k_reduce_splits<<<grid1d((int64_t)M12 * r[2]), 256, 0, s>>>(
+                                      Cpart.p, csplit, (int64_t)M12 * r[2], M12, r[2], r[2], beta.p, r[2])));
+  }
+
+  // 5. Tucker -> canonical: SVD of the mode-3 slices (r1 x r2, column-major)
+  const int r1 = r[0], r2 = r[1], r3 = r[2];
+  const bool jacobi = ctx->opt_t2c == 2 ? false : (ctx->opt_t2c == 1 || (int64_t)r1 * r2 <= kJacobiMaxElems);
+  RSD_CHECK(!jacobi || (int64_t)r1 * r2 <= kJacobiMaxElems, RSD_E_UNSUPPORTED, "core slice too large for LDS");
+  const int ns = jacobi ? r2 : std::min(r1, r2);      // singular values per slice
+  DevBuf S, Sv, Uv, Vv, Ev;
+  RSD_TRY(S.alloc(ctx, (size_t)r1 * r2 * r3));
+  RSD_TRY(Sv.alloc(ctx, (size_t)ns * r3));
+  RSD_TRY(Uv.alloc(ctx, (size_t)r1 * ns * r3));
+  RSD_TRY(Vv.alloc(ctx, (size_t)ns * r2 * r3));
+  RSD_TRY(Ev.alloc(ctx, (size_t)ns * r3));
+  RSD_TIMED_LAUNCH(ctx, "t2c", (k_core_slices<<<grid1d((int64_t)r1 * r2 * r3), 256, 0, s>>>(beta.p, r1, r2, r3,
+                                                                                            r3, S.p)));
+  RSD_CHECK(r3 <= 1024, RSD_E_UNSUPPORTED, "too many core slices");
+  if (jacobi) {
+    RSD_HIP(hipFuncSetAttribute((const void*)k_jacobi_svd, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(double) * (size_t)r1 * r2)));
+    const double skip_rel2 = std::max(1e-3 * eps * 1e-3 * eps, 1e-30);
+    RSD_TIMED_LAUNCH(ctx, "t2c", (k_jacobi_svd<<<r3, 256, sizeof(double) * (size_t)r1 * r2, s>>>(
+                                     S.p, r1, r2, skip_rel2, Sv.p, Uv.p, Vv.p, (int*)d_info)));
+    std::vector<int> sw((size_t)r3);
+    RSD_HIP(hipMemcpyAsync(sw.data(), d_info, sizeof(int) * r3, hipMemcpyDeviceToHost, s));
+    RSD_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < r3; ++c)
+      RSD_CHECK(sw[c] < kJacobiMaxSweeps, RSD_E_NUMERIC, "Jacobi SVD of core slice %d did not converge", c);
+  } else {
+    KernelTimer kt;
+    if (ctx->timing) RSD_TRY(ctx->timer_begin("t2c", &kt));
+    rocblas_status rs = rocsolver_dgesvd_strided_batched(
+        hb, rocblas_svect_singular, rocblas_svect_singular, r1, r2, S.p, r1, (rocblas_stride)r1 * r2, Sv.p,
+        (rocblas_stride)ns, Uv.p, r1, (rocblas_stride)r1 * ns, Vv.p, ns, (rocblas_stride)ns * r2, Ev.p,
+        (rocblas_stride)ns, rocblas_outofplace, d_info, r3);
+    RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dgesvd_strided_batched failed (%d)", (int)rs);
+    if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+    RSD_TRY(check_info(ctx, d_info, r3, "slice SVD"));
+  }
+  std::vector<double> sv((size_t)ns * r3), uv((size_t)r1 * ns * r3), vv((size_t)ns * r2 * r3);
+  RSD_HIP(hipMemcpy(sv.data(), Sv.p, sizeof(double) * sv.size(), hipMemcpyDeviceToHost));
+  RSD_HIP(hipMemcpy(uv.data(), Uv.p, sizeof(double) * uv.size(), hipMemcpyDeviceToHost));
+  RSD_HIP(hipMemcpy(vv.data(), Vv.p, sizeof(double) * vv.size(), hipMemcpyDeviceToHost));
+  double smax = 0.0;
+  for (double x : sv) smax = std::max(smax, x);
+  std::vector<std::pair<int, int>> kept;
+  for (int c = 0; c < r3; ++c)
+    for (int q = 0; q < ns; ++q)
+      if (sv[(size_t)c * ns + q] >= eps * smax && sv[(size_t)c * ns + q] > 0.0) kept.emplace_back(c, q);
+  const int64_t R = (int64_t)kept.size();
+  RSD_CHECK(R <= ((int64_t)1 << 20), RSD_E_UNSUPPORTED, "canonical rank %lld too large", (long long)R);
+  // V_d (r_d x R) on the host: columns p = s*u (mode 1), v (mode 2), e_c (mode 3)
+  std::vector<double> V1((size_t)r1 * R), V2((size_t)r2 * R), V3((size_t)r3 * R, 0.0);
+  for (int64_t p = 0; p < R; ++p) {
+    const int c = kept[p].first, q = kept[p].second;
+    const double sq = sv[(size_t)c * ns + q];
+    for (int a = 0; a < r1; ++a) V1[(size_t)a * R + p] = sq * uv[(size_t)c * r1 * ns + (size_t)q * r1 + a];
+    for (int bb = 0; bb < r2; ++bb) V2[(size_t)bb * R + p] = vv[(size_t)c * ns * r2 + (size_t)bb * ns + q];
+    V3[(size_t)c * R + p] = 1.0;
+  }
+  RSD_TRY(alloc_factors(ctx, t, R));
+  if (R == 0) return RSD_OK;
+  const int64_t mode = (int64_t)t->nchunk * n * kChunk;
+  const std::vector<double>* Vh[3] = {&V1, &V2, &V3};
+  for (int d = 0; d < 3; ++d) {
+    DevBuf Vd;
+    RSD_TRY(Vd.alloc(ctx, Vh[d]->size()));
+    RSD_HIP(hipMemcpyAsync(Vd.p, Vh[d]->data(), sizeof(double) * Vh[d]->size(), hipMemcpyHostToDevice, s));
+    RSD_TIMED_LAUNCH(ctx, "assemble", (k_assemble<<<grid1d(mode), 256, 0, s>>>(U[d].p, ldu[d], r[d], Vd.p, R, n,
+                                                                               t->nm[d], t->nchunk, t->F + d * mode)));
+    RSD_HIP(hipStreamSynchronize(s));
+  }
+  return RSD_OK;
+}
+
+// The tensor restricted to a sub-box and rank-reduced (scheme (C) of Sec. 3.3): the rows
+// i_lo[d] .. i_lo[d] + t->nm[d] - 1 of src's factors form the restricted canonical tensor,
+// whose rank is reduced by the same RHOSVD steps as the build: unit-norm columns with the
+// products of the norms as weights, the Gram matrix of each mode (rows x rows, small), its
+// eigenvectors above eps^2 times the largest eigenvalue, the projection, then steps 4-5.
+rsd_status restrict_factors(Context* ctx, const Tensor* src, Tensor* t, const int i_lo[3]) {
+  const int64_t R = src->R;
+  if (R == 0) return alloc_factors(ctx, t, 0);
+  hipStream_t s = ctx->stream;
+  const double eps = t->sp.eps;
+  if (!ctx->blas) {
+    rocblas_handle hnew = nullptr;
+    RSD_CHECK(rocblas_create_handle(&hnew) == rocblas_status_success, RSD_E_HIP, "rocblas_create_handle failed");
+    ctx->blas = hnew;
+  }
+  rocblas_handle hb = (rocblas_handle)ctx->blas;
+  RSD_CHECK(rocblas_set_stream(hb, s) == rocblas_status_success, RSD_E_HIP, "rocblas_set_stream failed");
+  rocblas_int* d_info = nullptr;
+  RSD_TRY(ctx->dev_alloc((void**)&d_info, 4096));
+  struct InfoGuard {
+    Context* c;
+    void* p;
+    ~InfoGuard() { c->dev_free(p, 4096); }
+  } ig{ctx, d_info};
+  const int64_t src_mode = (int64_t)src->nchunk * src->n * kChunk;
+  DevBuf A[3], nu[3], xi, U[3], Bt[3], G, W, E;
+  for (int d = 0; d < 3; ++d) {
+    const int rows = t->nm[d];
+    RSD_TRY(A[d].alloc(ctx, (size_t)rows * R));
+    RSD_TRY(nu[d].alloc(ctx, (size_t)R));
+    RSD_TIMED_LAUNCH(ctx, "restrict", (k_take_rows<<<grid1d((int64_t)rows * R), 256, 0, s>>>(
+                                          src->F + d * src_mode, src->n, R, i_lo[d], rows, A[d].p)));
+    RSD_TIMED_LAUNCH(ctx, "restrict", (k_row_colnorms<<<grid1d(R), 256, 0, s>>>(A[d].p, rows, R, nu[d].p)));
+  }
+  RSD_TRY(xi.alloc(ctx, (size_t)R));
+  RSD_TIMED_LAUNCH(ctx, "restrict", (k_local_weights<<<grid1d(R), 256, 0, s>>>(nu[0].p, nu[1].p, nu[2].p, R, xi.p)));
+  for (int d = 0; d < 3; ++d)
+    RSD_TIMED_LAUNCH(ctx, "restrict", (k_normalize_cols<<<grid1d((int64_t)t->nm[d] * R), 256, 0, s>>>(
+                                          A[d].p, t->nm[d], R, nu[d].p, xi.p)));
+  const int nmax = t->n;
+  RSD_TRY(G.alloc(ctx, (size_t)nmax * nmax));
+  RSD_TRY(W.alloc(ctx, (size_t)nmax));
+  RSD_TRY(E.alloc(ctx, (size_t)nmax));
+  int r[3] = {0, 0, 0}, ldu[3] = {0, 0, 0};
+  for (int d = 0; d < 3; ++d) {
+    const int rows = t->nm[d];
+    // Gram[i][j] = sum_p A[i][p] A[j][p]
+    GemmShape g{};
+    g.M = rows; g.N = rows; g.K = R; g.kper = (R + TK - 1) / TK * TK;
+    g.C = G.p; g.ldc = rows; g.split_stride = 0; g.accumulate = 0; g.tri = 0;
+    RSD_TRY(gemm(ctx, "restrict", OpMK{A[d].p, (int)R, rows}, OpMK{A[d].p, (int)R, rows}, g, 1));
+    KernelTimer kt;
+    if (ctx->timing) RSD_TRY(ctx->timer_begin("restrict", &kt));
+    const rocblas_status rs = rocsolver_dsyevd(hb, rocblas_evect_original, rocblas_fill_upper, rows, G.p, rows, W.p,
+                                               E.p, d_info);
+    RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dsyevd failed (%d)", (int)rs);
+    if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+    RSD_TRY(check_info(ctx, d_info, 1, "symmetric eigensolver"));
+    std::vector<double> w((size_t)rows);
+    RSD_HIP(hipMemcpy(w.data(), W.p, sizeof(double) * rows, hipMemcpyDeviceToHost));
+    const double lmax = w[rows - 1];
+    RSD_CHECK(lmax > 0.0 && std::isfinite(lmax), RSD_E_NUMERIC, "restricted mode %d has no positive eigenvalue", d);
+    int rd = 0;
+    for (int i = rows - 1; i >= 0 && w[i] >= eps * eps * lmax; --i) ++rd;
+    RSD_CHECK(rd >= 1 && rd <= 1024, RSD_E_UNSUPPORTED, "mode-%d rank %d outside [1, 1024]", d, rd);
+    r[d] = rd;
+    ldu[d] = ((rd + 7) / 8) * 8;
+    RSD_TRY(U[d].alloc(ctx, (size_t)rows * ldu[d]));
+    RSD_TIMED_LAUNCH(ctx, "restrict", (k_take_eigvecs<<<grid1d((int64_t)rows * ldu[d]), 256, 0, s>>>(
+                                          G.p, rows, rd, U[d].p, ldu[d])));
+    // B_d^T[p][a] = sum_i A[i][p] U[i][a]
+    RSD_TRY(Bt[d].alloc(ctx, (size_t)R * ldu[d]));
+    GemmShape gp{};
+    gp.M = (int)R; gp.N = rd; gp.K = rows; gp.kper = ((rows + TK - 1) / TK) * TK;
+    gp.C = Bt[d].p; gp.ldc = ldu[d]; gp.split_stride = 0; gp.accumulate = 0; gp.tri = 0;
+    RSD_TRY(gemm(ctx, "restrict", OpKM{A[d].p, (int)R, (int)R}, OpKM{U[d].p, ldu[d], rd}, gp, 1));
+    RSD_HIP(hipStreamSynchronize(s));   // G is reused by the next mode
+  }
+  t->ranks[0] = r[0];
+  t->ranks[1] = r[1];
+  t->ranks[2] = r[2];
+  return tucker_canonical(ctx, t, Bt, U, r, ldu, xi.p, R, hb, d_info);
+}
+
 rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const double* d_pos) {
   const int n = t->n;
   const int K = t->sp.K_long;
@@ -930,94 +1158,7 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
   RSD_TRY(xi.alloc(ctx, (size_t)C));
   RSD_TIMED_LAUNCH(ctx, "core", (k_weights<<<grid1d(C), 256, 0, s>>>(d_z, wd.p, K, C, nu[0].p, nu[1].p, nu[2].p,
                                                                      xi.p)));
-  const int M12 = r[0] * r[1];
-  const int tiles = div_up(M12, TM) * div_up(r[2], TN);
-  const int csplit = std::max(1, std::min(64, div_up(1024, tiles)));
-  DevBuf Cpart, beta;
-  RSD_TRY(Cpart.alloc(ctx, (size_t)csplit * M12 * r[2]));
-  RSD_TRY(beta.alloc(ctx, (size_t)M12 * r[2]));
-  OpKhatriRao kr{Bt[0].p, Bt[1].p, ldu[0], ldu[1], r[1], M12, {}, {}};
-  OpKMScaled b3{Bt[2].p, xi.p, ldu[2], r[2]};
-  {
-    GemmShape g{};
-    g.M = M12; g.N = r[2]; g.K = C;
-    g.kper = (int64_t)div_up(C, (int64_t)csplit * TK) * TK;
-    g.C = Cpart.p; g.ldc = r[2]; g.split_stride = (int64_t)M12 * r[2]; g.accumulate = 0; g.tri = 0;
-    RSD_TRY(gemm(ctx, "core", kr, b3, g, csplit));
-    RSD_TIMED_LAUNCH(ctx, "core", (k_reduce_splits<<<grid1d((int64_t)M12 * r[2]), 256, 0, s>>>(
-                                      Cpart.p, csplit, (int64_t)M12 * r[2], M12, r[2], r[2], beta.p, r[2])));
-  }
-
-  // 5. Tucker -> canonical: SVD of the mode-3 slices (r1 x r2, column-major)
-  const int r1 = r[0], r2 = r[1], r3 = r[2];
-  const bool jacobi = ctx->opt_t2c == 2 ? false : (ctx->opt_t2c == 1 || (int64_t)r1 * r2 <= kJacobiMaxElems);
-  RSD_CHECK(!jacobi || (int64_t)r1 * r2 <= kJacobiMaxElems, RSD_E_UNSUPPORTED, "core slice too large for LDS");
-  const int ns = jacobi ? r2 : std::min(r1, r2);      // singular values per slice
-  DevBuf S, Sv, Uv, Vv, Ev;
-  RSD_TRY(S.alloc(ctx, (size_t)r1 * r2 * r3));
-  RSD_TRY(Sv.alloc(ctx, (size_t)ns * r3));
-  RSD_TRY(Uv.alloc(ctx, (size_t)r1 * ns * r3));
-  RSD_TRY(Vv.alloc(ctx, (size_t)ns * r2 * r3));
-  RSD_TRY(Ev.alloc(ctx, (size_t)ns * r3));
-  RSD_TIMED_LAUNCH(ctx, "t2c", (k_core_slices<<<grid1d((int64_t)r1 * r2 * r3), 256, 0, s>>>(beta.p, r1, r2, r3,
-                                                                                            r3, S.p)));
-  RSD_CHECK(r3 <= 1024, RSD_E_UNSUPPORTED, "too many core slices");
-  if (jacobi) {
-    RSD_HIP(hipFuncSetAttribute((const void*)k_jacobi_svd, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(sizeof(double) * (size_t)r1 * r2)));
-    const double skip_rel2 = std::max(1e-3 * eps * 1e-3 * eps, 1e-30);
-    RSD_TIMED_LAUNCH(ctx, "t2c", (k_jacobi_svd<<<r3, 256, sizeof(double) * (size_t)r1 * r2, s>>>(
-                                     S.p, r1, r2, skip_rel2, Sv.p, Uv.p, Vv.p, (int*)d_info)));
-    std::vector<int> sw((size_t)r3);
-    RSD_HIP(hipMemcpyAsync(sw.data(), d_info, sizeof(int) * r3, hipMemcpyDeviceToHost, s));
-    RSD_HIP(hipStreamSynchronize(s));
-    for (int c = 0; c < r3; ++c)
-      RSD_CHECK(sw[c] < kJacobiMaxSweeps, RSD_E_NUMERIC, "Jacobi SVD of core slice %d did not converge", c);
-  } else {
-    KernelTimer kt;
-    if (ctx->timing) RSD_TRY(ctx->timer_begin("t2c", &kt));
-    rocblas_status rs = rocsolver_dgesvd_strided_batched(
-        hb, rocblas_svect_singular, rocblas_svect_singular, r1, r2, S.p, r1, (rocblas_stride)r1 * r2, Sv.p,
-        (rocblas_stride)ns, Uv.p, r1, (rocblas_stride)r1 * ns, Vv.p, ns, (rocblas_stride)ns * r2, Ev.p,
-        (rocblas_stride)ns, rocblas_outofplace, d_info, r3);
-    RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dgesvd_strided_batched failed (%d)", (int)rs);
-    if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
-    RSD_TRY(check_info(ctx, d_info, r3, "slice SVD"));
-  }
-  std::vector<double> sv((size_t)ns * r3), uv((size_t)r1 * ns * r3), vv((size_t)ns * r2 * r3);
-  RSD_HIP(hipMemcpy(sv.data(), Sv.p, sizeof(double) * sv.size(), hipMemcpyDeviceToHost));
-  RSD_HIP(hipMemcpy(uv.data(), Uv.p, sizeof(double) * uv.size(), hipMemcpyDeviceToHost));
-  RSD_HIP(hipMemcpy(vv.data(), Vv.p, sizeof(double) * vv.size(), hipMemcpyDeviceToHost));
-  double smax = 0.0;
-  for (double x : sv) smax = std::max(smax, x);
-  std::vector<std::pair<int, int>> kept;
-  for (int c = 0; c < r3; ++c)
-    for (int q = 0; q < ns; ++q)
-      if (sv[(size_t)c * ns + q] >= eps * smax && sv[(size_t)c * ns + q] > 0.0) kept.emplace_back(c, q);
-  const int64_t R = (int64_t)kept.size();
-  RSD_CHECK(R <= ((int64_t)1 << 20), RSD_E_UNSUPPORTED, "canonical rank %lld too large", (long long)R);
-  // V_d (r_d x R) on the host: columns p = s*u (mode 1), v (mode 2), e_c (mode 3)
-  std::vector<double> V1((size_t)r1 * R), V2((size_t)r2 * R), V3((size_t)r3 * R, 0.0);
-  for (int64_t p = 0; p < R; ++p) {
-    const int c = kept[p].first, q = kept[p].second;
-    const double sq = sv[(size_t)c * ns + q];
-    for (int a = 0; a < r1; ++a) V1[(size_t)a * R + p] = sq * uv[(size_t)c * r1 * ns + (size_t)q * r1 + a];
-    for (int bb = 0; bb < r2; ++bb) V2[(size_t)bb * R + p] = vv[(size_t)c * ns * r2 + (size_t)bb * ns + q];
-    V3[(size_t)c * R + p] = 1.0;
-  }
-  RSD_TRY(alloc_factors(ctx, t, R));
-  if (R == 0) return RSD_OK;
-  const int64_t mode = (int64_t)t->nchunk * n * kChunk;
-  const std::vector<double>* Vh[3] = {&V1, &V2, &V3};
-  for (int d = 0; d < 3; ++d) {
-    DevBuf Vd;
-    RSD_TRY(Vd.alloc(ctx, Vh[d]->size()));
-    RSD_HIP(hipMemcpyAsync(Vd.p, Vh[d]->data(), sizeof(double) * Vh[d]->size(), hipMemcpyHostToDevice, s));
-    RSD_TIMED_LAUNCH(ctx, "assemble", (k_assemble<<<grid1d(mode), 256, 0, s>>>(U[d].p, ldu[d], r[d], Vd.p, R, n,
-                                                                               t->nchunk, t->F + d * mode)));
-    RSD_HIP(hipStreamSynchronize(s));
-  }
-  return RSD_OK;
+  return tucker_canonical(ctx, t, Bt, U, r, ldu, xi.p, C, hb, d_info);
 }
 
 }  // namespace rsd

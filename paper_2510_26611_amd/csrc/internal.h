@@ -132,8 +132,13 @@ struct Context {
 // ---------------------------------------------------------------- tensor
 struct Tensor {
   Context* ctx = nullptr;
-  int n = 0;
+  int n = 0;                   // factor rows in the layout (the largest of nm[])
   double b = 0, h = 0, X0 = 0, inv_h = 0;
+  // per-mode grid: origin and row count (all X0 and n, except for a tensor restricted to a
+  // sub-box, whose modes start at different nodes and may have different lengths)
+  double X0m[3] = {0, 0, 0};
+  int nm[3] = {0, 0, 0};
+  bool restricted = false;
   int64_t R = 0;
   int nchunk = 0;              // ceil(R / kChunk); the kernels handle nchunk == 0
   int ranks[3] = {0, 0, 0};
@@ -192,6 +197,7 @@ void batch_free(Batch* b);
 rsd_status alloc_factors(Context* ctx, Tensor* t, int64_t R);
 // rank reduction on the device (build.hip)
 rsd_status build_factors(Context* ctx, Tensor* t, const double* d_charges, const double* d_positions);
+rsd_status restrict_factors(Context* ctx, const Tensor* src, Tensor* t, const int i_lo[3]);
 
 }  // namespace rsd
 

@@ -44,8 +44,10 @@ struct ScoreParams {
   const double* __restrict__ F;
   int64_t mode_stride;        // nchunk * n * kChunk
   int64_t chunk_stride;       // n * kChunk
-  int n, nchunk;
-  double X0, inv_h, smax;     // smax = n - 1
+  int nchunk;
+  double X0[3], smax[3];      // per mode: origin and last row (n_d - 1)
+  int nm2[3];                 // per mode: last lerp row n_d - 2
+  double inv_h;
   const double4* __restrict__ atoms;
   const int* __restrict__ cell_start;
   CellGrid cells;
@@ -277,8 +279,8 @@ __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4*
     const double4 u = s_lig[l];
     const double3 y = place(R, tv, u);
     s_y[l] = make_double4(y.x, y.y, y.z, u.w);
-    const bool in = in_grid(y.x, a.X0, a.inv_h, a.smax) && in_grid(y.y, a.X0, a.inv_h, a.smax) &&
-                    in_grid(y.z, a.X0, a.inv_h, a.smax);
+    const bool in = in_grid(y.x, a.X0[0], a.inv_h, a.smax[0]) && in_grid(y.y, a.X0[1], a.inv_h, a.smax[1]) &&
+                    in_grid(y.z, a.X0[2], a.inv_h, a.smax[2]);
     out_of_domain |= !in;
   }
   const bool dom = __ballot(out_of_domain) == 0ull;
@@ -291,7 +293,6 @@ __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4*
   // owns columns 2j and 2j+1 of every chunk and loads them from rows i and i+1 as 16-byte
   // loads (twice the bytes per lane of 8-byte loads through the same return path).
   if (LONG && dom && a.nchunk > 0) {
-    const int nm2 = a.n - 2;
     const int64_t cs = a.chunk_stride / 2;                 // in double2
     const int half = lane >> 5, col2 = lane & 31;
     for (int l = 0; l < L; l += 2) {
@@ -299,8 +300,9 @@ __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4*
       const int la = lx < L ? lx : L - 1;                  // a missing partner repeats atom L-1 with no charge
       const double4 y = s_y[la];
       const double zeta = lx < L ? y.w : 0.0;
-      const double s0 = (y.x - a.X0) * a.inv_h, s1 = (y.y - a.X0) * a.inv_h, s2 = (y.z - a.X0) * a.inv_h;
-      const int i0 = min((int)floor(s0), nm2), i1 = min((int)floor(s1), nm2), i2 = min((int)floor(s2), nm2);
+      const double s0 = (y.x - a.X0[0]) * a.inv_h, s1 = (y.y - a.X0[1]) * a.inv_h, s2 = (y.z - a.X0[2]) * a.inv_h;
+      const int i0 = min((int)floor(s0), a.nm2[0]), i1 = min((int)floor(s1), a.nm2[1]);
+      const int i2 = min((int)floor(s2), a.nm2[2]);
       const double f0 = s0 - (double)i0, f1 = s1 - (double)i1, f2 = s2 - (double)i2;
       const double2* p0 = (const double2*)(a.F + (int64_t)i0 * kChunk) + col2;
       const double2* p1 = (const double2*)(a.F + a.mode_stride + (int64_t)i1 * kChunk) + col2;
@@ -490,8 +492,10 @@ __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4*
 struct LongParams {
   const double* __restrict__ F;
   int64_t mode_stride, chunk_stride;
-  int n, nchunk;
-  double X0, inv_h, smax;
+  int nchunk;
+  double X0[3], smax[3];         // per mode: origin and last row (n_d - 1)
+  int nm2[3];                    // per mode: last lerp row n_d - 2
+  double inv_h;
   const double4* __restrict__ lig;
   int L;
   const double* __restrict__ quats;
@@ -535,7 +539,6 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
   for (int i = tid; i < L; i += 256) s_lig[i] = a.lig[i];
   for (int i = tid; i < PB; i += 256) s_bad[i] = 0;
   __syncthreads();
-  const int nm2 = a.n - 2;
   for (int e = tid; e < PB * L; e += 256) {
     const int lp = e / L, l = e - lp * L;
     const int64_t p = p0 + lp;
@@ -545,12 +548,13 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
       double R[9], tv[3];
       if (pose_frame(a.quats + 4 * p, a.trans + 3 * p, R, tv)) {
         const double3 y = place(R, tv, s_lig[l]);
-        if (in_grid(y.x, a.X0, a.inv_h, a.smax) && in_grid(y.y, a.X0, a.inv_h, a.smax) &&
-            in_grid(y.z, a.X0, a.inv_h, a.smax)) {
-          const double s0 = (y.x - a.X0) * a.inv_h, s1 = (y.y - a.X0) * a.inv_h, s2 = (y.z - a.X0) * a.inv_h;
-          g.i0 = min((int)floor(s0), nm2);
-          g.i1 = min((int)floor(s1), nm2);
-          g.i2 = min((int)floor(s2), nm2);
+        if (in_grid(y.x, a.X0[0], a.inv_h, a.smax[0]) && in_grid(y.y, a.X0[1], a.inv_h, a.smax[1]) &&
+            in_grid(y.z, a.X0[2], a.inv_h, a.smax[2])) {
+          const double s0 = (y.x - a.X0[0]) * a.inv_h, s1 = (y.y - a.X0[1]) * a.inv_h;
+          const double s2 = (y.z - a.X0[2]) * a.inv_h;
+          g.i0 = min((int)floor(s0), a.nm2[0]);
+          g.i1 = min((int)floor(s1), a.nm2[1]);
+          g.i2 = min((int)floor(s2), a.nm2[2]);
           g.f0 = s0 - (double)g.i0;
           g.f1 = s1 - (double)g.i1;
           g.f2 = s2 - (double)g.i2;
@@ -775,11 +779,13 @@ ScoreParams make_score_params(const Tensor* t, const ScoreIO& io, const double4*
   a.F = t->F;
   a.chunk_stride = (int64_t)t->n * kChunk;
   a.mode_stride = (int64_t)t->nchunk * a.chunk_stride;
-  a.n = t->n;
   a.nchunk = t->nchunk;
-  a.X0 = t->X0;
+  for (int d = 0; d < 3; ++d) {
+    a.X0[d] = t->X0m[d];
+    a.smax[d] = (double)(t->nm[d] - 1);
+    a.nm2[d] = t->nm[d] - 2;
+  }
   a.inv_h = t->inv_h;
-  a.smax = (double)(t->n - 1);
   a.atoms = t->atoms;
   a.cell_start = t->cell_start;
   a.cells = t->cells;
@@ -840,11 +846,13 @@ LongParams make_long_params(const Tensor* t, const ScoreIO& io, const double4* l
   lp.F = t->F;
   lp.chunk_stride = (int64_t)t->n * kChunk;
   lp.mode_stride = (int64_t)t->nchunk * lp.chunk_stride;
-  lp.n = t->n;
   lp.nchunk = t->nchunk;
-  lp.X0 = t->X0;
+  for (int d = 0; d < 3; ++d) {
+    lp.X0[d] = t->X0m[d];
+    lp.smax[d] = (double)(t->nm[d] - 1);
+    lp.nm2[d] = t->nm[d] - 2;
+  }
   lp.inv_h = t->inv_h;
-  lp.smax = (double)(t->n - 1);
   lp.lig = lig;
   lp.L = io.L;
   lp.quats = io.quats;

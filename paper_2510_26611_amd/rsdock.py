@@ -144,6 +144,21 @@ class Tensor:
     def save(self, path: str) -> None:
         _check(_lib.lib().rsd_tensor_save(self.handle, str(path).encode()))
 
+    def grid(self):
+        """rsd_tensor_grid: per-mode origins X0, row counts and the mesh h."""
+        X0, rows, h = (C.c_double * 3)(), (C.c_int32 * 3)(), C.c_double()
+        _check(_lib.lib().rsd_tensor_grid(self.handle, X0, rows, C.byref(h)))
+        return dict(X0=tuple(X0), rows=tuple(rows), h=h.value)
+
+    def restrict(self, lo, hi, eps: float, ctx: "Context" = None) -> "Tensor":
+        """rsd_tensor_restrict: this tensor on the sub-box [lo, hi], rank-reduced at eps (Sec. 3.3, scheme (C))."""
+        ctx = ctx or self.ctx
+        lo3 = (C.c_double * 3)(*[float(x) for x in lo])
+        hi3 = (C.c_double * 3)(*[float(x) for x in hi])
+        out = C.c_void_p()
+        _check(_lib.lib().rsd_tensor_restrict(ctx.handle, self.handle, lo3, hi3, float(eps), C.byref(out)))
+        return Tensor(ctx, out)
+
     def free(self) -> None:
         if getattr(self, "handle", None):
             _lib.lib().rsd_tensor_free(self.handle)
