@@ -89,10 +89,11 @@ def main() -> int:
     ap.add_argument("--score-mode", type=int, default=0, help="0 automatic, 1 fused per-pose, 2 chunk-major")
     ap.add_argument("--no-autotune", action="store_true", help="skip the launch-shape tuner before timing")
     ap.add_argument("--tune-poses", type=int, default=16384, help="poses of the tuner's sample")
-    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"],
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "site"],
                     help="cfg2 (default): one 5,000-atom protein, 1e6 poses; cfg1: 200 atoms, 128 poses; "
                          "cfg3: 64 protein/ligand pairs batched; cfg4: 10,000 atoms, 65,536 poses with gradients; "
-                         "cfg5: serving 8 resident proteins under Poisson arrivals")
+                         "cfg5: serving 8 resident proteins under Poisson arrivals; site: 1e6 poses at one site of "
+                         "the cfg2 protein scored with the global tensor and with the tensor restricted to a box")
     ap.add_argument("--pairs", type=int, default=64, help="cfg3: number of protein/ligand pairs")
     ap.add_argument("--requests", type=int, default=100, help="cfg5: arrivals in the served trace")
     ap.add_argument("--rate", type=float, default=200.0, help="cfg5: offered requests per second")
@@ -132,6 +133,8 @@ def main() -> int:
         return run_batched(args, rs, configs, torch, np, dev)
     if args.workload == "cfg5":
         return run_serving(args, rs, configs, torch, np)
+    if args.workload == "site":
+        return run_site(args, rs, configs, torch, np, dev)
     cfg = {"cfg1": configs.CONFIG1, "cfg2": configs.CONFIG2, "cfg4": configs.CONFIG4}[args.workload]
     want_grad = args.workload == "cfg4"
     P = args.poses or cfg.P
@@ -323,6 +326,98 @@ def run_batched(args, rs, configs, torch, np, dev) -> int:
     batch.free()
     for t in tensors:
         t.free()
+    ctx.close()
+    return 0
+
+
+def run_site(args, rs, configs, torch, np, dev) -> int:
+    """A docking scan at one site (Sec. 3.3, schemes (B)/(C)): 1,000 translations within 2 A of a
+    point 5 A outside the 5,000-atom protein, 1,000 rotations each.  Step A scores them with the
+    global RS tensor; step B restricts the tensor to the 16 A box around the site (rank
+    reduction included in the step) and scores them with the local tensor."""
+    from workloads import generators as gen
+    cfg = configs.CONFIG2
+    wl = configs.make(cfg, P=1)
+    T, Q = 1000, 1000
+    site = np.array([cfg.pose_r_in, 0.0, 0.0])
+    half = cfg.ligand_radius + 2.0
+    dirs = gen.directions(gen.rng(6, 6), T)
+    rad = 2.0 * np.cbrt(gen.rng(6, 7).random(T))
+    centres = site[None, :] + dirs * rad[:, None]
+    quats = gen.unit_quaternions(gen.rng(6, 5), T * Q)
+    trans = np.repeat(centres, Q, axis=0)                        # translation-major: 1,000 rotations per site point
+    P = T * Q
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    d_lz, d_lx, d_q, d_t = to(wl.ligand_charges), to(wl.ligand_positions), to(quats), to(trans)
+    ctx = rs.Context(0)
+    tg = rs.build_rs_tensor(ctx, to(wl.protein_charges), to(wl.protein_positions), cfg.n, cfg.b,
+                            rs.Sinc.from_config(cfg))
+    out = {k: dict(E=torch.empty(P, dtype=torch.float64, device=dev), flags=torch.empty(P, dtype=torch.uint8, device=dev),
+                   counts=torch.empty(P, dtype=torch.int32, device=dev)) for k in ("global", "local")}
+    m = min(P, args.tune_poses)
+    tune = {"global": ctx.autotune(tg, d_lz, d_lx, d_q[:m], d_t[:m], cfg.sigma)}
+    tl0 = tg.restrict(site - half, site + half, cfg.eps)
+    tune["local"] = ctx.autotune(tl0, d_lz, d_lx, d_q[:m], d_t[:m], cfg.sigma)
+    tl0.free()
+
+    def step_global():
+        rs.score_poses(ctx, tg, d_lz, d_lx, d_q, d_t, cfg.sigma, out=out["global"])
+
+    info = {}
+
+    def step_local():
+        tl = tg.restrict(site - half, site + half, cfg.eps)
+        info.update(tl.query())
+        info["rows"] = list(tl.grid()["rows"])
+        rs.score_poses(ctx, tl, d_lz, d_lx, d_q, d_t, cfg.sigma, out=out["local"])
+        tl.free()
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    ms_glob = timed(step_global) * 1e3
+    ctx.set_timing(True)
+    ms_loc = timed(step_local) * 1e3
+    kt = {k: ctx.kernel_time(k) for k in ("restrict", "core", "t2c", "assemble", "cells", "long", "short", "score")}
+    ctx.set_timing(False)
+    fg, fl = out["global"]["flags"].cpu().numpy(), out["local"]["flags"].cpu().numpy()
+    cg, cl = out["global"]["counts"].cpu().numpy(), out["local"]["counts"].cpu().numpy()
+    Eg, El = out["global"]["E"].cpu().numpy(), out["local"]["E"].cpu().numpy()
+    ok = (fl & 2) != 0
+    Rg = tg.query()["R"]
+    dom = "long" if kt["long"][0] else "score"          # chunk-major or fused, whichever the tuner chose
+    long_ms = kt[dom][1] / max(kt[dom][0], 1)
+    alg = P * (48.0 * cfg.L * info["R"] + 56)
+    res = {
+        "metric": METRIC, "value": P / (ms_loc / 1e3), "unit": "poses/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_loc, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "site-scan-cfg2-protein", "poses": P, "site_points": T, "rotations_per_point": Q,
+                   "box_half_width_A": half, "canonical_rank_global": Rg, "canonical_rank_local": info["R"],
+                   "local_grid_rows": info["rows"],
+                   "parallelism": "single GPU, data-parallel over poses"},
+        "global_tensor_poses_per_s": P / (ms_glob / 1e3), "global_ms": ms_glob,
+        "local_ms_including_restriction": ms_loc,
+        "restriction_ms": sum(kt[k][1] for k in ("restrict", "core", "t2c", "assemble", "cells")) / args.steps,
+        "roofline": {"kernel": dom, "kernel_ms": long_ms, "bound": "hbm", "achieved": alg / (long_ms / 1e3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / (long_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None},
+        "autotune": tune,
+        "in_box_fraction": float(np.mean(ok)),
+        "flags_equal_in_box": bool(np.array_equal(fg[ok], fl[ok])), "counts_equal": bool(np.array_equal(cg, cl)),
+        "max_abs_dE_in_box": float(np.max(np.abs(Eg[ok] - El[ok]))) if ok.any() else None,
+        "max_abs_E_in_box": float(np.max(np.abs(Eg[ok]))) if ok.any() else None,
+        "breakdown": {k: {"launches": v[0], "ms_per_step": v[1] / args.steps} for k, v in kt.items() if v[0]},
+    }
+    print(json.dumps(res), flush=True)
+    tg.free()
     ctx.close()
     return 0
 
