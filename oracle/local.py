@@ -85,3 +85,12 @@ def recompress(F, eps):
     bound = xi_norm * sum(float(np.sqrt(np.sum(sing[d][ranks[d]:] ** 2))) for d in range(3))
     tk = _rhosvd.TuckerResult(U=U, sing=sing, ranks=tuple(ranks), core=core, xi_norm=xi_norm, bound=bound)
     return tk, _rhosvd.tucker_to_canonical(tk, eps)
+
+
+def combine(F_list, eps):
+    """The long-range tensor of a complex of molecules (eq. 5.1 sums their potentials): the
+    canonical factors of tensors on one grid are concatenated (a sum of canonical tensors is
+    the canonical tensor of all their terms) and the rank of the sum is reduced as in
+    `recompress` (the add-and-compress of Sec. 5)."""
+    F = [np.concatenate([np.asarray(Fi[d], dtype=np.float64) for Fi in F_list], axis=1) for d in range(3)]
+    return F, recompress(F, eps)

@@ -95,3 +95,37 @@ def test_scoring_in_the_box_matches_the_global_tensor(glob):
     bound = np.sum(np.abs(zeta)) * (tk.bound + rc.dropped_fro)
     assert np.max(np.abs(loc["E"] - ref["E"])) <= bound
 
+
+
+def test_complex_of_two_molecules_is_the_sum():
+    """Eq. 5.1: a ligand scored against a complex gets the sum of its energies against each
+    molecule (long range by linearity, short range and counts over the union of the atoms);
+    add-and-compress keeps the sum within the RHOSVD bound."""
+    pa = gen.ball_points(gen.rng(11, 1), 120, 9.0) + np.array([-9.0, 0.0, 0.0])
+    pb = gen.ball_points(gen.rng(12, 1), 90, 8.0) + np.array([9.0, 2.0, 0.0])
+    za = gen.charges(gen.rng(11, 2), 120, 0.3, True)
+    zb = gen.charges(gen.rng(12, 2), 90, 0.3, True)
+    _, ca = rhosvd.build(za, pa, TL, WL, N_GRID, B_BOX, 1e-8)
+    _, cb = rhosvd.build(zb, pb, TL, WL, N_GRID, B_BOX, 1e-8)
+    Fsum, (tk, cc) = local.combine([ca.F, cb.F], 1e-8)
+    assert Fsum[0].shape[1] == ca.R + cb.R and cc.R < ca.R + cb.R
+    idx = np.random.default_rng(2).integers(0, N_GRID, size=(3000, 3))
+    at = lambda F: np.sum(F[0][idx[:, 0]] * F[1][idx[:, 1]] * F[2][idx[:, 2]], axis=1)  # noqa: E731
+    exact = at(ca.F) + at(cb.F)
+    assert np.max(np.abs(at(Fsum) - exact)) <= 1e-14 * np.max(np.abs(exact))
+    assert np.max(np.abs(at(cc.F) - exact)) <= tk.bound + cc.dropped_fro
+    # energies: complex = molecule A + molecule B (long range to the truncation, the rest exactly)
+    (_, _), (ts, ws) = sinc.split(T, W, K)
+    r_cut = 43.836027469049675
+    lig = gen.ball_points(gen.rng(13, 3), 10, 3.5)
+    zeta = gen.charges(gen.rng(13, 4), 10, 0.3, False)
+    q = gen.unit_quaternions(gen.rng(13, 5), 32)
+    t = np.array([0.0, 14.0, 0.0])[None, :] + gen.sphere_translations(gen.rng(13, 6), 32, 2.0)
+    ea = score.score(ca.F, N_GRID, B_BOX, pa, za, ts, ws, r_cut, zeta, lig, q, t, 2.5)
+    eb = score.score(cb.F, N_GRID, B_BOX, pb, zb, ts, ws, r_cut, zeta, lig, q, t, 2.5)
+    ec = score.score(cc.F, N_GRID, B_BOX, np.vstack([pa, pb]), np.concatenate([za, zb]), ts, ws, r_cut, zeta, lig,
+                     q, t, 2.5)
+    assert np.array_equal(ec["counts"], ea["counts"] + eb["counts"])
+    assert np.array_equal(ec["flags"] & 1, (ea["flags"] & 1) & (eb["flags"] & 1))
+    bound = np.sum(np.abs(zeta)) * (tk.bound + cc.dropped_fro) + 1e-12
+    assert np.max(np.abs(ec["E"] - (ea["E"] + eb["E"]))) <= bound
