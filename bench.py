@@ -29,14 +29,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "long_cfg2_traffic.json")
 SCORE_SRC = os.path.join(ROOT, "paper_2510_26611_amd", "csrc", "score.hip")
 
 
-KERNEL_END = "// E = sum_c part[c]"   # the long-range kernel and everything it uses precede this line
+# The source the counters measured: the pose-transform helpers and the long-range kernel.
+KERNEL_REGIONS = (("// Rotation matrix of q = (w, x, y, z)", "// Two columns of one chunk for one atom"),
+                  ("struct LongParams {", "// E = sum_c part[c]"))
 
 
 def _src_hash() -> str:
-    """Hash of the scoring source up to the end of the long-range kernel (the code the counters measured)."""
+    """Hash of the scoring source regions that define the long-range kernel."""
     with open(SCORE_SRC, encoding="utf-8") as f:
         text = f.read()
-    return hashlib.sha256(text[:text.index(KERNEL_END)].encode()).hexdigest()[:16]
+    parts = [text[text.index(a):text.index(b)] for a, b in KERNEL_REGIONS]
+    return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
 
 
 def _traffic(launch_poses: int):
