@@ -48,7 +48,7 @@ typedef enum {
   RSD_E_OOM = -2,         /* device allocation failed or the context's HBM budget is exceeded */
   RSD_E_HIP = -3,         /* a HIP runtime call failed */
   RSD_E_NUMERIC = -4,     /* the rank reduction did not converge */
-  RSD_E_UNSUPPORTED = -5, /* a size beyond what the kernels support */
+  RSD_E_UNSUPPORTED = -5, /* a size, or a combination of inputs, the library does not support */
   RSD_E_IO = -6           /* file could not be read or written, or is not a tensor file */
 } rsd_status;
 
@@ -200,6 +200,67 @@ void rsd_batch_free(rsd_batch* batch);
  * misses the grid, or eps outside (0, 1); RSD_E_OOM beyond the budget. */
 rsd_status rsd_tensor_restrict(rsd_context* ctx, const rsd_tensor* src, const double lo[3], const double hi[3],
                                double eps, rsd_tensor** out);
+
+/* The potential of a complex of molecules M_1..M_m (eq. 5.1: a molecule of the complex, or a
+ * ligand, is scored against the sum of the other molecules' potentials), built by the
+ * add-and-compress of Algorithm TEP, step 4: the canonical factors of `count` tensors on one
+ * grid are put side by side (the canonical tensor of the sum has all their terms) and that
+ * sum's rank is reduced by the build's RHOSVD steps at relative accuracy `eps`, exactly as in
+ * rsd_tensor_restrict.  The short-range part and the van der Waals test use the union of the
+ * molecules' atoms (the sources' atoms in order).  The long-range error is at most the sum of
+ * the sources' errors plus the truncation at eps.  The same call builds one large molecule in
+ * pieces (rsd_build_rs_tensor on chunks of its atoms, then one combine).
+ * Requirements: 1 <= count <= 4096; every source on ctx's device, with the same grid (n, b,
+ * per-mode origins and row counts: all from the build/import, or all restrictions to the same
+ * box) and the same sinc parameters apart from eps.  The result belongs to `ctx` and does not
+ * reference the sources.  Errors: RSD_E_INVALID for a NULL argument, a bad count or eps
+ * outside (0, 1); RSD_E_UNSUPPORTED for sources on different grids or quadratures; RSD_E_OOM
+ * beyond the budget. */
+rsd_status rsd_tensor_combine(rsd_context* ctx, const rsd_tensor* const* tensors, int32_t count, double eps,
+                              rsd_tensor** out);
+
+/* ---- posing search (Algorithm PPIEM, steps A2-A6) ----
+ * The search scans a grid of orbit directions u_i (positions of the ligand centre around the
+ * protein centre x_P) times orientations q_k of the ligand about its own centre; each pose
+ * sits at first contact (step A3) and is scored by rsd_score_poses (steps A4-A5); the lowest
+ * energy per orbit position and the local minima over the orbit grid follow (step A6).  The
+ * arrays of these calls are DEVICE pointers (HBM), laid out orbit-major: entry u * Q + q. */
+
+/* Step A2: the protein's geometric centre x_P, the unweighted mean of its atom positions,
+ * summed in index order and divided by N.  RSD_E_INVALID for a tensor without atoms. */
+rsd_status rsd_tensor_centre(const rsd_tensor* t, double centre[3]);
+
+/* Step A3, radial approach.  For orbit direction u (unit, dirs[3u..3u+2]) and orientation q
+ * (unit quaternion, quats[4q..4q+3]) the ligand centre moves along x_P + rho u; coming in from
+ * far away, the first contact with the van der Waals distance is at
+ *   rho* = max over protein-ligand pairs of the larger root of |rho u + w|^2 = sigma^2,
+ *   w = centre + R(q) (x_l - c) - x_m,
+ * after which every larger rho keeps all pairs at >= sigma (the root formula is exact; the
+ * device evaluates it in FP64).  Outputs, for entry o = u * Q + q:
+ *   rho[o]            rho*; -inf if the line never comes within sigma of the protein; NaN
+ *                     for an invalid quaternion (| |q|^2 - 1 | > 1e-12 or non-finite);
+ *   pose_quats[4o..]  q (copied);
+ *   pose_trans[3o..]  centre + (rho* + gap) u, NaN where rho* is not finite -- ready for
+ *                     rsd_score_poses with RSD_MEM_DEVICE (NaN poses are flagged invalid).
+ * Inputs: lig_positions [L*3], dirs [U*3], quats [Q*4] on the device; centre[3] on the host
+ * (normally rsd_tensor_centre); sigma > 0, gap >= 0 (a gap of 1e-6 A keeps the contact poses
+ * strictly admissible).  Enqueued on the context stream, not synchronised.  Errors:
+ * RSD_E_INVALID (NULL, sizes, non-finite sigma/gap/centre), RSD_E_UNSUPPORTED (L). */
+rsd_status rsd_contact_poses(rsd_context* ctx, const rsd_tensor* t, const double* lig_positions, int64_t L,
+                             const double* dirs, int64_t U, const double* quats, int64_t Q, const double centre[3],
+                             double sigma, double gap, double* rho, double* pose_quats, double* pose_trans);
+
+/* Step A6.  For each orbit position u: best_rotation[u] = the orientation q with the lowest
+ * energies[u*Q + q] among poses with the accept bit (flags & 1; the lowest q on ties), -1 if
+ * none, and best_energy[u] its energy (+inf if none); is_minimum[u] = 1 when u has an
+ * accepted pose and best_energy[u] <= best_energy[v] for every neighbour v, listed in CSR
+ * form: nbr_index[nbr_offsets[u] .. nbr_offsets[u+1]-1] (indices in [0, U)).  All arrays on
+ * the device.  The neighbour lists are read back and checked first (one synchronisation);
+ * the kernels are then enqueued on the context stream.  Errors: RSD_E_INVALID (NULL, sizes,
+ * offsets not starting at 0 or decreasing, an index outside [0, U)). */
+rsd_status rsd_orbit_minima(rsd_context* ctx, const double* energies, const uint8_t* flags, int64_t U, int64_t Q,
+                            const int32_t* nbr_offsets, const int32_t* nbr_index, int32_t* best_rotation,
+                            double* best_energy, uint8_t* is_minimum);
 
 /* Per-mode grid of a tensor: origin X0[d] (Angstrom), row count rows[d] and the mesh h.
  * For tensors from rsd_build_rs_tensor / rsd_tensor_import every mode has X0 = -b + h and

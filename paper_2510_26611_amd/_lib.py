@@ -29,7 +29,8 @@ EXPORTED = [
     "rsd_score_poses", "rsd_tensor_query", "rsd_tensor_export", "rsd_tensor_save",
     "rsd_tensor_load", "rsd_tensor_free", "rsd_context_set_timing", "rsd_kernel_time",
     "rsd_context_set_option", "rsd_batch_create", "rsd_batch_run", "rsd_batch_free", "rsd_autotune",
-    "rsd_tensor_restrict", "rsd_tensor_grid",
+    "rsd_tensor_restrict", "rsd_tensor_grid", "rsd_tensor_combine",
+    "rsd_tensor_centre", "rsd_contact_poses", "rsd_orbit_minima",
 ]
 
 
@@ -84,6 +85,11 @@ def _declare(lib: C.CDLL) -> C.CDLL:
         "rsd_batch_free": (None, [_P]),
         "rsd_autotune": (st, [_P, _P, _P, _P, _I64, _P, _P, _I64, _D, _I32, C.POINTER(TuneReport)]),
         "rsd_tensor_restrict": (st, [_P, _P, C.POINTER(_D), C.POINTER(_D), _D, C.POINTER(_P)]),
+        "rsd_tensor_combine": (st, [_P, _P, C.c_int32, _D, C.POINTER(_P)]),
+        "rsd_tensor_centre": (st, [_P, C.POINTER(_D)]),
+        "rsd_contact_poses": (st, [_P, _P, _P, C.c_int64, _P, C.c_int64, _P, C.c_int64, C.POINTER(_D), _D, _D, _P,
+                                   _P, _P]),
+        "rsd_orbit_minima": (st, [_P, _P, _P, C.c_int64, C.c_int64, _P, _P, _P, _P, _P]),
         "rsd_tensor_grid": (st, [_P, C.POINTER(_D), C.POINTER(_I32), C.POINTER(_D)]),
     }
     for name, (res, args) in sig.items():

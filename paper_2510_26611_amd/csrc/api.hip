@@ -467,6 +467,10 @@ rsd_status rsd_tensor_restrict(rsd_context* ctx, const rsd_tensor* src, const do
   rsd_status st = tensor_common(ctx, t, src->n, src->b, &sp, std::move(z), std::move(pos), &d_z, &d_pos);
   int i_lo[3] = {0, 0, 0};
   if (st == RSD_OK) {
+    // the mesh is the source's (a restricted source's n is its largest row count, not the grid's)
+    t->h = src->h;
+    t->inv_h = src->inv_h;
+    t->X0 = src->X0;
     // rows of the source grid that evaluation inside [lo, hi] reaches (the source may itself be
     // restricted: its mode d starts at row offset (X0m[d] - X0) / h of the full grid)
     int nmax = 0;
@@ -484,7 +488,8 @@ rsd_status rsd_tensor_restrict(rsd_context* ctx, const rsd_tensor* src, const do
       for (int d = 0; d < 3; ++d) t->X0m[d] = -src->b + (double)(i_lo[d] + 1) * src->h;
     t->n = nmax;
     t->restricted = true;
-    st = restrict_factors(ctx, src, t, i_lo);
+    const Tensor* one = src;
+    st = reduce_factors(ctx, &one, 1, t, i_lo);
   }
   if (st == RSD_OK) {
     hipError_t e = hipStreamSynchronize(ctx->stream);
@@ -503,6 +508,144 @@ rsd_status rsd_tensor_restrict(rsd_context* ctx, const rsd_tensor* src, const do
   }
   *out = t;
   return RSD_OK;
+}
+
+rsd_status rsd_tensor_combine(rsd_context* ctx, const rsd_tensor* const* tensors, int32_t count, double eps,
+                              rsd_tensor** out) {
+  clear_error();
+  RSD_CHECK(out != nullptr, RSD_E_INVALID, "out is NULL");
+  *out = nullptr;
+  RSD_CHECK(ctx != nullptr && !ctx->closing, RSD_E_INVALID, "ctx is NULL or freed");
+  RSD_CHECK(tensors != nullptr, RSD_E_INVALID, "tensors is NULL");
+  RSD_CHECK(count >= 1 && count <= 4096, RSD_E_INVALID, "count %d outside [1, 4096]", (int)count);
+  RSD_CHECK(std::isfinite(eps) && eps > 0 && eps < 1, RSD_E_INVALID, "eps must be in (0, 1)");
+  const rsd_tensor* s0 = tensors[0];
+  RSD_CHECK(s0 != nullptr, RSD_E_INVALID, "tensor 0 is NULL");
+  std::vector<const Tensor*> src((size_t)count);
+  size_t atoms = 0;
+  for (int k = 0; k < count; ++k) {
+    const rsd_tensor* sk = tensors[k];
+    RSD_CHECK(sk != nullptr, RSD_E_INVALID, "tensor %d is NULL", k);
+    RSD_CHECK(sk->ctx->device == ctx->device, RSD_E_INVALID, "tensor %d lives on another device", k);
+    RSD_CHECK(sk->n == s0->n && sk->b == s0->b && sk->h == s0->h && sk->restricted == s0->restricted,
+              RSD_E_UNSUPPORTED, "tensor %d is on another grid", k);
+    for (int d = 0; d < 3; ++d)
+      RSD_CHECK(sk->X0m[d] == s0->X0m[d] && sk->nm[d] == s0->nm[d], RSD_E_UNSUPPORTED,
+                "tensor %d covers other rows of mode %d", k, d);
+    RSD_CHECK(sk->sp.M == s0->sp.M && sk->sp.K_long == s0->sp.K_long && sk->sp.h_M == s0->sp.h_M &&
+                  sk->sp.L_s == s0->sp.L_s && sk->sp.r_cut == s0->sp.r_cut,
+              RSD_E_UNSUPPORTED, "tensor %d has other sinc parameters", k);
+    src[k] = sk;
+    atoms += sk->host_charges.size();
+  }
+  RSD_HIP(hipSetDevice(ctx->device));
+  rsd_sinc_params sp = s0->sp;
+  sp.eps = eps;
+  std::vector<double> z, pos;
+  z.reserve(atoms);
+  pos.reserve(3 * atoms);
+  for (const Tensor* sk : src) {
+    z.insert(z.end(), sk->host_charges.begin(), sk->host_charges.end());
+    pos.insert(pos.end(), sk->host_positions.begin(), sk->host_positions.end());
+  }
+  rsd_tensor* t = new (std::nothrow) rsd_tensor();
+  RSD_CHECK(t != nullptr, RSD_E_OOM, "host allocation failed");
+  t->ctx = ctx;
+  ctx->live_tensors += 1;
+  double* d_z = nullptr;
+  double* d_pos = nullptr;
+  const int64_t N = (int64_t)z.size();
+  rsd_status st = tensor_common(ctx, t, s0->n, s0->b, &sp, std::move(z), std::move(pos), &d_z, &d_pos);
+  if (st == RSD_OK) {
+    t->h = s0->h;
+    t->inv_h = s0->inv_h;
+    t->X0 = s0->X0;
+    for (int d = 0; d < 3; ++d) {
+      t->X0m[d] = s0->X0m[d];
+      t->nm[d] = s0->nm[d];
+    }
+    t->restricted = s0->restricted;
+    const int i_lo[3] = {0, 0, 0};
+    st = reduce_factors(ctx, src.data(), count, t, i_lo);
+  }
+  if (st == RSD_OK) {
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+      set_error("hipStreamSynchronize: %s", hipGetErrorString(e));
+      st = RSD_E_HIP;
+    }
+  }
+  ctx->dev_free(d_z, sizeof(double) * (size_t)(N ? N : 1));
+  ctx->dev_free(d_pos, sizeof(double) * 3 * (size_t)(N ? N : 1));
+  if (st != RSD_OK) {
+    std::string keep = g_err;
+    tensor_release(t);
+    g_err = keep;
+    return st;
+  }
+  *out = t;
+  return RSD_OK;
+}
+
+rsd_status rsd_tensor_centre(const rsd_tensor* t, double centre[3]) {
+  clear_error();
+  RSD_CHECK(t != nullptr && centre != nullptr, RSD_E_INVALID, "NULL argument");
+  RSD_CHECK(t->N > 0, RSD_E_INVALID, "the tensor has no atoms");
+  double c[3] = {0.0, 0.0, 0.0};
+  for (int64_t m = 0; m < t->N; ++m)
+    for (int d = 0; d < 3; ++d) c[d] = c[d] + t->host_positions[3 * m + d];
+  for (int d = 0; d < 3; ++d) centre[d] = c[d] / (double)t->N;
+  return RSD_OK;
+}
+
+rsd_status rsd_contact_poses(rsd_context* ctx, const rsd_tensor* t, const double* lig_positions, int64_t L,
+                             const double* dirs, int64_t U, const double* quats, int64_t Q, const double centre[3],
+                             double sigma, double gap, double* rho, double* pose_quats, double* pose_trans) {
+  clear_error();
+  RSD_CHECK(ctx != nullptr && t != nullptr && centre != nullptr, RSD_E_INVALID, "NULL argument");
+  RSD_CHECK(!ctx->closing, RSD_E_INVALID, "context has been freed");
+  RSD_CHECK(t->ctx->device == ctx->device, RSD_E_INVALID, "tensor lives on another device");
+  RSD_CHECK(L >= 1 && L <= kMaxLigand, RSD_E_UNSUPPORTED, "L=%lld outside [1, %d]", (long long)L, kMaxLigand);
+  RSD_CHECK(U >= 0 && Q >= 0 && (U == 0 || Q <= ((int64_t)1 << 33) / U), RSD_E_INVALID, "U=%lld, Q=%lld out of range",
+            (long long)U, (long long)Q);
+  RSD_CHECK(std::isfinite(sigma) && sigma > 0, RSD_E_INVALID, "sigma must be finite and > 0");
+  RSD_CHECK(std::isfinite(gap) && gap >= 0, RSD_E_INVALID, "gap must be finite and >= 0");
+  for (int d = 0; d < 3; ++d) RSD_CHECK(std::isfinite(centre[d]), RSD_E_INVALID, "centre is not finite");
+  if (U == 0 || Q == 0) return RSD_OK;
+  RSD_CHECK(lig_positions && dirs && quats && rho && pose_quats && pose_trans, RSD_E_INVALID, "NULL array");
+  RSD_HIP(hipSetDevice(ctx->device));
+  return launch_contact(ctx, t, lig_positions, (int)L, dirs, U, quats, Q, centre, sigma, gap, rho, pose_quats,
+                        pose_trans);
+}
+
+rsd_status rsd_orbit_minima(rsd_context* ctx, const double* energies, const uint8_t* flags, int64_t U, int64_t Q,
+                            const int32_t* nbr_offsets, const int32_t* nbr_index, int32_t* best_rotation,
+                            double* best_energy, uint8_t* is_minimum) {
+  clear_error();
+  RSD_CHECK(ctx != nullptr && !ctx->closing, RSD_E_INVALID, "ctx is NULL or freed");
+  RSD_CHECK(U >= 0 && Q >= 1 && Q <= 0x7fffffff && (U == 0 || Q <= ((int64_t)1 << 33) / U), RSD_E_INVALID,
+            "U=%lld, Q=%lld out of range", (long long)U, (long long)Q);
+  if (U == 0) return RSD_OK;
+  RSD_CHECK(energies && flags && nbr_offsets && nbr_index && best_rotation && best_energy && is_minimum,
+            RSD_E_INVALID, "NULL array");
+  RSD_HIP(hipSetDevice(ctx->device));
+  // the neighbour lists steer device reads: check them on the host first
+  std::vector<int32_t> off((size_t)U + 1);
+  RSD_HIP(hipMemcpyAsync(off.data(), nbr_offsets, sizeof(int32_t) * off.size(), hipMemcpyDeviceToHost, ctx->stream));
+  RSD_HIP(hipStreamSynchronize(ctx->stream));
+  RSD_CHECK(off[0] == 0, RSD_E_INVALID, "nbr_offsets[0] must be 0");
+  for (int64_t u = 0; u < U; ++u)
+    RSD_CHECK(off[u + 1] >= off[u], RSD_E_INVALID, "nbr_offsets decrease at %lld", (long long)u);
+  if (off[U] > 0) {
+    std::vector<int32_t> idx((size_t)off[U]);
+    RSD_HIP(hipMemcpyAsync(idx.data(), nbr_index, sizeof(int32_t) * idx.size(), hipMemcpyDeviceToHost, ctx->stream));
+    RSD_HIP(hipStreamSynchronize(ctx->stream));
+    for (size_t k = 0; k < idx.size(); ++k)
+      RSD_CHECK(idx[k] >= 0 && idx[k] < U, RSD_E_INVALID, "nbr_index[%zu] = %d outside [0, %lld)", k, (int)idx[k],
+                (long long)U);
+  }
+  return launch_orbit_minima(ctx, energies, flags, U, Q, nbr_offsets, nbr_index, best_rotation, best_energy,
+                             is_minimum);
 }
 
 rsd_status rsd_tensor_grid(const rsd_tensor* t, double X0[3], int32_t rows[3], double* h) {

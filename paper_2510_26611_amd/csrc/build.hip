@@ -158,16 +158,17 @@ struct OpGauss {              // element (k = grid row i, m = column c) = exp(-t
   }
 };
 
-// ----------------------------------------------------------------- restriction to a sub-box
-// Rows i0 .. i0 + rows - 1 of one mode of a chunked factor table as a row-major matrix:
-// A[i * R + p] = F[chunk p / kChunk][row i0 + i][p % kChunk].
+// ----------------------------------------------------------------- rank reduction of explicit factors
+// Rows i0 .. i0 + rows - 1 of one mode of a chunked factor table (R columns) as columns
+// col0 .. col0 + R - 1 of a row-major matrix with ldA columns:
+// A[i * ldA + col0 + p] = F[chunk p / kChunk][row i0 + i][p % kChunk].
 __global__ void k_take_rows(const double* __restrict__ F, int n_src, int64_t R, int i0, int rows,
-                            double* __restrict__ A) {
+                            double* __restrict__ A, int64_t ldA, int64_t col0) {
   const int64_t total = (int64_t)rows * R;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / R);
     const int64_t p = e % R;
-    A[e] = F[((p / kChunk) * n_src + i0 + i) * kChunk + p % kChunk];
+    A[(int64_t)i * ldA + col0 + p] = F[((p / kChunk) * n_src + i0 + i) * kChunk + p % kChunk];
   }
 }
 
@@ -427,6 +428,16 @@ __global__ void k_take_eigvecs(const double* __restrict__ Z, int n, int r, doubl
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / ldu), a = (int)(e % ldu);
     U[e] = a < r ? Z[(int64_t)(n - 1 - a) * n + i] : 0.0;
+  }
+}
+
+// The upper triangle of the leading k x k block of a column-major matrix (ld lda) into a
+// column-major k x k matrix, zeros below the diagonal.
+__global__ void k_upper_copy(const double* __restrict__ X, int64_t lda, int k, double* __restrict__ Rb) {
+  const int64_t total = (int64_t)k * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e % k), j = (int)(e / k);
+    Rb[e] = a <= j ? X[(int64_t)j * lda + a] : 0.0;
   }
 }
 
@@ -925,14 +936,112 @@ rsd_status tucker_canonical(Context* ctx, Tensor* t, DevBuf Bt[3], DevBuf U[3], 
   return RSD_OK;
 }
 
-// The tensor restricted to a sub-box and rank-reduced (scheme (C) of Sec. 3.3): the rows
-// i_lo[d] .. i_lo[d] + t->nm[d] - 1 of src's factors form the restricted canonical tensor,
-// whose rank is reduced by the same RHOSVD steps as the build: unit-norm columns with the
-// products of the norms as weights, the Gram matrix of each mode (rows x rows, small), its
-// eigenvectors above eps^2 times the largest eigenvalue, the projection, then steps 4-5.
-rsd_status restrict_factors(Context* ctx, const Tensor* src, Tensor* t, const int i_lo[3]) {
-  const int64_t R = src->R;
+// Dominant left singular vectors of an explicit rows x R matrix A (row-major), with the
+// singular values computed from A itself rather than from A A^T: the Gram matrix squares the
+// spectrum, and at eps = 1e-8 its eigenvalue cut eps^2 lies at the rounding level of FP64,
+// where the exactly low-rank modes of canonical factors (mode 3 of a factor set made by the
+// canonical -> Tucker -> canonical step has only r3 distinct columns) pass noise as rank.
+// Randomized range finder: Q = orth(A Omega) with k test vectors and one power step
+// Q <- orth(A (A^T Q)); then B = Q^T A (k x R), B^T = Q_b R_b (Householder QR), the SVD of
+// the k x k factor R_b (its right singular vectors are B's left ones), U = Q V.  When
+// k = min(rows, R) the range is captured exactly and the power step is skipped.  Singular
+// values >= eps * the largest are kept; if fewer than 16 of the k fall below that cut and
+// k < min(rows, R), k is doubled and the mode is redone.  U is rows x ldu, row-major.
+static rsd_status left_basis(Context* ctx, rocblas_handle hb, const double* A, int rows, int64_t R, double eps,
+                             rocblas_int* d_info, uint64_t seed, DevBuf* U, int* r_out, int* ldu_out) {
+  hipStream_t s = ctx->stream;
+  const int kmax = (int)std::min<int64_t>(rows, R);
+  int k = std::min(kmax, rows <= 256 ? kmax : 128);
+  for (;;) {
+    const bool exact = k == kmax;
+    DevBuf Om, Y, W, Rb, Sv, VT, E, tau;
+    RSD_TRY(Om.alloc(ctx, (size_t)R * k));
+    RSD_TRY(Y.alloc(ctx, (size_t)rows * k));
+    RSD_TRY(W.alloc(ctx, (size_t)R * k));
+    RSD_TRY(Rb.alloc(ctx, (size_t)k * k));
+    RSD_TRY(Sv.alloc(ctx, (size_t)k));
+    RSD_TRY(VT.alloc(ctx, (size_t)k * k));
+    RSD_TRY(E.alloc(ctx, (size_t)k));
+    RSD_TRY(tau.alloc(ctx, (size_t)k));
+    auto qr = [&](double* X, int m, int64_t ld, bool form_q) -> rsd_status {   // column-major m x k
+      KernelTimer kt;
+      if (ctx->timing) RSD_TRY(ctx->timer_begin("restrict", &kt));
+      RSD_CHECK(rocsolver_dgeqrf(hb, m, k, X, (rocblas_int)ld, tau.p) == rocblas_status_success, RSD_E_HIP,
+                "rocsolver_dgeqrf failed");
+      if (form_q)
+        RSD_CHECK(rocsolver_dorgqr(hb, m, k, k, X, (rocblas_int)ld, tau.p) == rocblas_status_success, RSD_E_HIP,
+                  "rocsolver_dorgqr failed");
+      if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+      return RSD_OK;
+    };
+    GemmShape g{};
+    g.split_stride = 0; g.accumulate = 0; g.tri = 0;
+    RSD_TIMED_LAUNCH(ctx, "restrict", (k_random_fill<<<grid1d(R * k), 256, 0, s>>>(Om.p, R * k, seed)));
+    // Y = A Omega as Y^T (k x rows row-major = rows x k column-major)
+    g.M = k; g.N = rows; g.K = R; g.kper = (R + TK - 1) / TK * TK; g.C = Y.p; g.ldc = rows;
+    RSD_TRY(gemm(ctx, "restrict", OpKM{Om.p, k, k}, OpMK{A, R, rows}, g, 1));
+    RSD_TRY(qr(Y.p, rows, rows, true));
+    if (!exact) {
+      // W = A^T Q (R x k row-major), then Y^T = W^T A^T and orthonormalise again
+      g.M = (int)R; g.N = k; g.K = rows; g.kper = ((int64_t)rows + TK - 1) / TK * TK; g.C = W.p; g.ldc = k;
+      RSD_TRY(gemm(ctx, "restrict", OpKM{A, R, (int)R}, OpMK{Y.p, rows, k}, g, 1));
+      g.M = k; g.N = rows; g.K = R; g.kper = (R + TK - 1) / TK * TK; g.C = Y.p; g.ldc = rows;
+      RSD_TRY(gemm(ctx, "restrict", OpKM{W.p, k, k}, OpMK{A, R, rows}, g, 1));
+      RSD_TRY(qr(Y.p, rows, rows, true));
+    }
+    // B^T = A^T Q as a column-major R x k matrix (k x R row-major), its R factor, and the SVD
+    RSD_CHECK(div_up(R, TN) <= 65535, RSD_E_UNSUPPORTED, "too many columns (%lld) for the projection",
+              (long long)R);
+    g.M = k; g.N = (int)R; g.K = rows; g.kper = ((int64_t)rows + TK - 1) / TK * TK; g.C = W.p; g.ldc = R;
+    RSD_TRY(gemm(ctx, "restrict", OpMK{Y.p, rows, k}, OpKM{A, R, (int)R}, g, 1));
+    RSD_TRY(qr(W.p, (int)R, R, false));
+    RSD_TIMED_LAUNCH(ctx, "restrict", (k_upper_copy<<<grid1d((int64_t)k * k), 256, 0, s>>>(W.p, R, k, Rb.p)));
+    {
+      KernelTimer kt;
+      if (ctx->timing) RSD_TRY(ctx->timer_begin("restrict", &kt));
+      const rocblas_status rs = rocsolver_dgesvd(hb, rocblas_svect_none, rocblas_svect_singular, k, k, Rb.p, k, Sv.p,
+                                                 nullptr, 1, VT.p, k, E.p, rocblas_outofplace, d_info);
+      RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dgesvd failed (%d)", (int)rs);
+      if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+    }
+    RSD_TRY(check_info(ctx, d_info, 1, "singular value decomposition"));
+    std::vector<double> sv((size_t)k);
+    RSD_HIP(hipMemcpy(sv.data(), Sv.p, sizeof(double) * k, hipMemcpyDeviceToHost));
+    RSD_CHECK(sv[0] > 0.0 && std::isfinite(sv[0]), RSD_E_NUMERIC, "factor matrix has no positive singular value");
+    int r = 0;
+    while (r < k && sv[r] >= eps * sv[0]) ++r;
+    if (r > k - 16 && k < kmax) {
+      k = std::min(kmax, 2 * k);
+      continue;
+    }
+    RSD_CHECK(r >= 1 && r <= 1024, RSD_E_UNSUPPORTED, "mode rank %d outside [1, 1024]", r);
+    const int ldu = ((r + 7) / 8) * 8;
+    RSD_TRY(U->alloc(ctx, (size_t)rows * ldu));
+    RSD_HIP(hipMemsetAsync(U->p, 0, U->bytes, s));   // columns r .. ldu - 1 stay zero
+    // U[i][a] = sum_j Q[i][j] V[j][a],  V[j][a] = VT[a + j k]
+    g.M = rows; g.N = r; g.K = k; g.kper = ((int64_t)k + TK - 1) / TK * TK; g.C = U->p; g.ldc = ldu;
+    RSD_TRY(gemm(ctx, "restrict", OpKM{Y.p, rows, rows}, OpKM{VT.p, k, r}, g, 1));
+    *r_out = r;
+    *ldu_out = ldu;
+    RSD_HIP(hipStreamSynchronize(s));   // the local buffers are released on return
+    return RSD_OK;
+  }
+}
+
+// Rank reduction of a canonical tensor given by explicit factors: the rows i_lo[d] ..
+// i_lo[d] + t->nm[d] - 1 of the factors of src[0..nsrc-1], side by side (the sum of those
+// canonical tensors), reduced by the same RHOSVD steps as the build.  With one source and a
+// sub-box this is the restriction of scheme (C) in Sec. 3.3; with several sources on one grid
+// it is the sum of their potentials (eq. 5.1) followed by the rank reduction (the
+// add-and-compress of Algorithm TEP, step 4).  Steps: unit-norm columns with the products of
+// the norms as weights, the Gram matrix of each mode (rows x rows), its eigenvectors above
+// eps^2 times the largest eigenvalue (dense solver for small grids, the build's subspace
+// iteration for large ones), the projection, then steps 4-5 (tucker_canonical).
+rsd_status reduce_factors(Context* ctx, const Tensor* const* src, int nsrc, Tensor* t, const int i_lo[3]) {
+  int64_t R = 0;
+  for (int k = 0; k < nsrc; ++k) R += src[k]->R;
   if (R == 0) return alloc_factors(ctx, t, 0);
+  RSD_CHECK(R < ((int64_t)1 << 31), RSD_E_UNSUPPORTED, "too many columns (%lld) to reduce", (long long)R);
   hipStream_t s = ctx->stream;
   const double eps = t->sp.eps;
   if (!ctx->blas) {
@@ -949,14 +1058,20 @@ rsd_status restrict_factors(Context* ctx, const Tensor* src, Tensor* t, const in
     void* p;
     ~InfoGuard() { c->dev_free(p, 4096); }
   } ig{ctx, d_info};
-  const int64_t src_mode = (int64_t)src->nchunk * src->n * kChunk;
-  DevBuf A[3], nu[3], xi, U[3], Bt[3], G, W, E;
+  DevBuf A[3], nu[3], xi, U[3], Bt[3];
   for (int d = 0; d < 3; ++d) {
     const int rows = t->nm[d];
     RSD_TRY(A[d].alloc(ctx, (size_t)rows * R));
     RSD_TRY(nu[d].alloc(ctx, (size_t)R));
-    RSD_TIMED_LAUNCH(ctx, "restrict", (k_take_rows<<<grid1d((int64_t)rows * R), 256, 0, s>>>(
-                                          src->F + d * src_mode, src->n, R, i_lo[d], rows, A[d].p)));
+    int64_t col0 = 0;
+    for (int k = 0; k < nsrc; ++k) {
+      const Tensor* sk = src[k];
+      if (sk->R == 0) continue;
+      const int64_t sm = (int64_t)sk->nchunk * sk->n * kChunk;
+      RSD_TIMED_LAUNCH(ctx, "restrict", (k_take_rows<<<grid1d((int64_t)rows * sk->R), 256, 0, s>>>(
+                                            sk->F + d * sm, sk->n, sk->R, i_lo[d], rows, A[d].p, R, col0)));
+      col0 += sk->R;
+    }
     RSD_TIMED_LAUNCH(ctx, "restrict", (k_row_colnorms<<<grid1d(R), 256, 0, s>>>(A[d].p, rows, R, nu[d].p)));
   }
   RSD_TRY(xi.alloc(ctx, (size_t)R));
@@ -964,44 +1079,17 @@ rsd_status restrict_factors(Context* ctx, const Tensor* src, Tensor* t, const in
   for (int d = 0; d < 3; ++d)
     RSD_TIMED_LAUNCH(ctx, "restrict", (k_normalize_cols<<<grid1d((int64_t)t->nm[d] * R), 256, 0, s>>>(
                                           A[d].p, t->nm[d], R, nu[d].p, xi.p)));
-  const int nmax = t->n;
-  RSD_TRY(G.alloc(ctx, (size_t)nmax * nmax));
-  RSD_TRY(W.alloc(ctx, (size_t)nmax));
-  RSD_TRY(E.alloc(ctx, (size_t)nmax));
   int r[3] = {0, 0, 0}, ldu[3] = {0, 0, 0};
+  for (int d = 0; d < 3; ++d)
+    RSD_TRY(left_basis(ctx, hb, A[d].p, t->nm[d], R, eps, d_info, 0x5EEDull + (uint64_t)d, &U[d], &r[d], &ldu[d]));
   for (int d = 0; d < 3; ++d) {
-    const int rows = t->nm[d];
-    // Gram[i][j] = sum_p A[i][p] A[j][p]
-    GemmShape g{};
-    g.M = rows; g.N = rows; g.K = R; g.kper = (R + TK - 1) / TK * TK;
-    g.C = G.p; g.ldc = rows; g.split_stride = 0; g.accumulate = 0; g.tri = 0;
-    RSD_TRY(gemm(ctx, "restrict", OpMK{A[d].p, (int)R, rows}, OpMK{A[d].p, (int)R, rows}, g, 1));
-    KernelTimer kt;
-    if (ctx->timing) RSD_TRY(ctx->timer_begin("restrict", &kt));
-    const rocblas_status rs = rocsolver_dsyevd(hb, rocblas_evect_original, rocblas_fill_upper, rows, G.p, rows, W.p,
-                                               E.p, d_info);
-    RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dsyevd failed (%d)", (int)rs);
-    if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
-    RSD_TRY(check_info(ctx, d_info, 1, "symmetric eigensolver"));
-    std::vector<double> w((size_t)rows);
-    RSD_HIP(hipMemcpy(w.data(), W.p, sizeof(double) * rows, hipMemcpyDeviceToHost));
-    const double lmax = w[rows - 1];
-    RSD_CHECK(lmax > 0.0 && std::isfinite(lmax), RSD_E_NUMERIC, "restricted mode %d has no positive eigenvalue", d);
-    int rd = 0;
-    for (int i = rows - 1; i >= 0 && w[i] >= eps * eps * lmax; --i) ++rd;
-    RSD_CHECK(rd >= 1 && rd <= 1024, RSD_E_UNSUPPORTED, "mode-%d rank %d outside [1, 1024]", d, rd);
-    r[d] = rd;
-    ldu[d] = ((rd + 7) / 8) * 8;
-    RSD_TRY(U[d].alloc(ctx, (size_t)rows * ldu[d]));
-    RSD_TIMED_LAUNCH(ctx, "restrict", (k_take_eigvecs<<<grid1d((int64_t)rows * ldu[d]), 256, 0, s>>>(
-                                          G.p, rows, rd, U[d].p, ldu[d])));
     // B_d^T[p][a] = sum_i A[i][p] U[i][a]
+    const int rows = t->nm[d];
     RSD_TRY(Bt[d].alloc(ctx, (size_t)R * ldu[d]));
     GemmShape gp{};
-    gp.M = (int)R; gp.N = rd; gp.K = rows; gp.kper = ((rows + TK - 1) / TK) * TK;
+    gp.M = (int)R; gp.N = r[d]; gp.K = rows; gp.kper = ((rows + TK - 1) / TK) * TK;
     gp.C = Bt[d].p; gp.ldc = ldu[d]; gp.split_stride = 0; gp.accumulate = 0; gp.tri = 0;
-    RSD_TRY(gemm(ctx, "restrict", OpKM{A[d].p, (int)R, (int)R}, OpKM{U[d].p, ldu[d], rd}, gp, 1));
-    RSD_HIP(hipStreamSynchronize(s));   // G is reused by the next mode
+    RSD_TRY(gemm(ctx, "restrict", OpKM{A[d].p, (int)R, (int)R}, OpKM{U[d].p, ldu[d], r[d]}, gp, 1));
   }
   t->ranks[0] = r[0];
   t->ranks[1] = r[1];

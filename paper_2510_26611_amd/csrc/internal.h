@@ -186,6 +186,13 @@ struct ScoreIO {
 };
 rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io);
 rsd_status autotune(Context* ctx, const Tensor* t, const ScoreIO& io, rsd_tune_report* rep);
+// posing search (score.hip)
+rsd_status launch_contact(Context* ctx, const Tensor* t, const double* lig_positions, int L, const double* dirs,
+                          int64_t U, const double* quats, int64_t Q, const double xP[3], double sigma, double gap,
+                          double* rho, double* pose_q, double* pose_t);
+rsd_status launch_orbit_minima(Context* ctx, const double* E, const uint8_t* flags, int64_t U, int64_t Q,
+                               const int32_t* off, const int32_t* idx, int32_t* best_q, double* best_e,
+                               uint8_t* is_min);
 
 // many requests per launch (score.hip)
 struct Batch;
@@ -197,7 +204,7 @@ void batch_free(Batch* b);
 rsd_status alloc_factors(Context* ctx, Tensor* t, int64_t R);
 // rank reduction on the device (build.hip)
 rsd_status build_factors(Context* ctx, Tensor* t, const double* d_charges, const double* d_positions);
-rsd_status restrict_factors(Context* ctx, const Tensor* src, Tensor* t, const int i_lo[3]);
+rsd_status reduce_factors(Context* ctx, const Tensor* const* src, int nsrc, Tensor* t, const int i_lo[3]);
 
 }  // namespace rsd
 

@@ -204,6 +204,16 @@ def tensor_import(ctx: Context, F, n: int, b: float, sinc: Sinc, charges, positi
     return Tensor(ctx, out)
 
 
+def tensor_combine(ctx: Context, tensors, eps: float) -> Tensor:
+    """rsd_tensor_combine: the potential of a complex of molecules (eq. 5.1), the sum of the
+    tensors' canonical terms rank-reduced at eps (add-and-compress); atoms are the union."""
+    tensors = list(tensors)
+    arr = (C.c_void_p * len(tensors))(*[t.handle for t in tensors])
+    out = C.c_void_p()
+    _check(_lib.lib().rsd_tensor_combine(ctx.handle, arr, len(tensors), float(eps), C.byref(out)))
+    return Tensor(ctx, out)
+
+
 def tensor_load(ctx: Context, path: str) -> Tensor:
     out = C.c_void_p()
     _check(_lib.lib().rsd_tensor_load(ctx.handle, str(path).encode(), C.byref(out)))

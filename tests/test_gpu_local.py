@@ -162,3 +162,28 @@ def test_cfg2_site_restriction_full_size(env):
     assert tl.query()["R"] * 4 < tg.query()["R"]
     tl.free()
     tg.free()
+
+
+def test_restriction_of_a_restriction(env):
+    """A local tensor restricted again keeps the source's mesh: the same rows and origins as the
+    direct restriction of the global tensor to the inner box, and the same values to the
+    truncation level."""
+    rs, torch, ctx, cfg, wl, F, t = env
+    site = np.array([18.0, 0.0, 0.0])
+    outer = t.restrict(site - 7.0, site + 7.0, 1e-10)
+    inner = outer.restrict(site - 3.0, site + 3.0, 1e-8)
+    direct = t.restrict(site - 3.0, site + 3.0, 1e-8)
+    g_i, g_d = inner.grid(), direct.grid()
+    assert g_i["h"] == t.grid()["h"] == outer.grid()["h"]
+    assert g_i["rows"] == g_d["rows"] and np.array_equal(np.array(g_i["X0"]), np.array(g_d["X0"]))
+    ref = olocal.restrict(F, cfg.n, cfg.b, site - 3.0, site + 3.0)
+    rows = np.array(g_i["rows"])
+    idx = np.random.default_rng(4).integers(0, rows, size=(4000, 3))
+    at = lambda G: np.sum(G[0][idx[:, 0]] * G[1][idx[:, 1]] * G[2][idx[:, 2]], axis=1)  # noqa: E731
+    exact = at(ref.F)
+    e_i = np.max(np.abs(at(_local_factors(inner, g_i)) - exact))
+    e_d = np.max(np.abs(at(_local_factors(direct, g_d)) - exact))
+    print(f"inner of outer: R {inner.query()['R']} err {e_i:.3e} | direct R {direct.query()['R']} err {e_d:.3e}")
+    assert e_i <= 10.0 * max(e_d, 1e-8 * np.max(np.abs(exact)))
+    for x in (outer, inner, direct):
+        x.free()
