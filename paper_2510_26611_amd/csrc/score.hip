@@ -535,6 +535,7 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
   GridPt* s_pt = (GridPt*)(smem + L);
   double4* s_v = (double4*)(s_pt + PB * L);    // GRAD: R u_l per point
   int* s_bad = (int*)(GRAD ? (void*)(s_v + PB * L) : (void*)s_v);
+  double* s_out = (double*)(s_bad + PB);        // the block's PB x S results, stored together at the end
   const int tid = threadIdx.x;
   for (int i = tid; i < L; i += 256) s_lig[i] = a.lig[i];
   for (int i = tid; i < PB; i += 256) s_bad[i] = 0;
@@ -631,13 +632,19 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
       gw0 = wave_sum(gw0); gw1 = wave_sum(gw1); gw2 = wave_sum(gw2);
     }
     if (lane == 0) {
-      double* o = a.part + ((int64_t)c * a.P + p) * S;
+      double* o = s_out + lp * S;
       o[0] = e;
       if (GRAD) {
         o[1] = gt0; o[2] = gt1; o[3] = gt2; o[4] = gw0; o[5] = gw1; o[6] = gw2;
       }
     }
   }
+  // One contiguous store of the block's results: single 8-byte stores from four wavefronts at
+  // different times leave partial cache lines, each written back to HBM on its own.
+  __syncthreads();
+  const int np = (int)(a.P - p0 < PB ? a.P - p0 : PB);
+  double* out = a.part + ((int64_t)c * a.P + p0) * S;
+  for (int i = tid; i < np * S; i += 256) out[i] = s_out[i];
 }
 
 // E = sum_c part[c] + short part for poses in the grid; NaN otherwise (invalid poses keep
@@ -832,7 +839,7 @@ rsd_status allow_lds(const void* kernel, size_t bytes) {
 size_t long_lds(int L, int ppw, bool grad) {
   const int PB = 4 * ppw;
   return sizeof(double4) * (size_t)L + (size_t)PB * L * (sizeof(GridPt) + (grad ? sizeof(double4) : 0)) +
-         sizeof(int) * (size_t)PB;
+         sizeof(int) * (size_t)PB + sizeof(double) * (size_t)PB * (grad ? 7 : 1);
 }
 
 int pick_ppw(int L, bool grad, int want) {
@@ -1210,6 +1217,202 @@ void batch_free(Batch* b) {
   }
   b->ctx->block_release(b->mem, b->bytes);
   delete b;
+}
+
+// ---------------------------------------------------------------- posing search (Algorithm PPIEM)
+// Step A3, radial approach.  The ligand, rotated by q about its centre, has its centre at
+// x_P + rho u.  For the pair (ligand atom l, protein atom m) with a = x_P + R(q) u_l and
+// w = a - x_m, |rho u + w| = sigma at rho = -(u.w) +- sqrt((u.w)^2 - (|w|^2 - sigma^2)), and
+// the pair is closer than sigma between the roots; the first contact when moving in from far
+// away is rho* = the largest root over all pairs (-inf if no pair has a real root).
+// One workgroup takes one orbit direction u and cpb orientations; tpc threads share each
+// orientation's ligand atoms.  Only protein atoms within sigma + (ligand radius) of the line
+// x_P + rho u can have a real root with any ligand atom; each tile of protein atoms is
+// filtered against that cylinder and compacted in LDS, and every thread then runs over the
+// survivors.  A root is taken (with its square root) only when it can beat the thread's best:
+// -b + sqrt(disc) > best  <=>  disc >= 0 and (best + b < 0 or disc > (best + b)^2).
+struct ContactParams {
+  const double4* __restrict__ atoms;   // protein atoms (x, y, z, charge)
+  int64_t N;
+  const double4* __restrict__ lig;     // centred ligand (k_ligand_prep)
+  const double* __restrict__ rlig;     // its radius
+  int L;
+  const double* __restrict__ dirs;
+  const double* __restrict__ quats;
+  int64_t U, Q;
+  double xP[3];
+  double sigma, gap;
+  int tpc, cpb;
+  int64_t qblocks;
+  double* __restrict__ rho;
+  double* __restrict__ pose_q;
+  double* __restrict__ pose_t;
+};
+
+constexpr int kContactTile = 1024;   // protein atoms filtered per pass
+
+__global__ __launch_bounds__(256) void k_contact(const ContactParams a) {
+  __shared__ double4 s_at[kContactTile];
+  __shared__ double s_best[256];
+  __shared__ int s_cnt;
+  const int tid = threadIdx.x;
+  const int64_t ui = (int64_t)blockIdx.x / a.qblocks;
+  const int64_t qb = (int64_t)blockIdx.x % a.qblocks;
+  const double ux = a.dirs[3 * ui], uy = a.dirs[3 * ui + 1], uz = a.dirs[3 * ui + 2];
+  const int j = tid / a.tpc, lt = tid - (tid / a.tpc) * a.tpc;
+  const int64_t q = qb * a.cpb + j;
+  const bool active = j < a.cpb && q < a.Q;
+  double R[9], t[3];
+  bool valid = false;
+  if (active) valid = pose_frame(a.quats + 4 * q, a.xP, R, t);
+  const double rc = a.sigma + a.rlig[0] + 1e-3;   // the cylinder radius, with a margin for rounding
+  const double rc2 = rc * rc;
+  const double s2 = a.sigma * a.sigma;
+  double best = -INFINITY;
+  const int nl = (a.L + a.tpc - 1) / a.tpc;
+  for (int il = 0; il < nl; ++il) {
+    const int l = lt + il * a.tpc;
+    const bool has = active && valid && l < a.L;
+    double3 y = make_double3(0.0, 0.0, 0.0);
+    if (has) y = place(R, t, a.lig[l]);
+    for (int64_t m0 = 0; m0 < a.N; m0 += kContactTile) {
+      if (tid == 0) s_cnt = 0;
+      __syncthreads();
+      for (int k = tid; k < kContactTile; k += 256) {
+        const int64_t m = m0 + k;
+        if (m < a.N) {
+          const double4 p = a.atoms[m];
+          const double dx = p.x - a.xP[0], dy = p.y - a.xP[1], dz = p.z - a.xP[2];
+          const double pr = fma(ux, dx, fma(uy, dy, uz * dz));
+          const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+          if (d2 - pr * pr <= rc2) s_at[atomicAdd(&s_cnt, 1)] = p;
+        }
+      }
+      __syncthreads();
+      const int cnt = s_cnt;
+      if (has) {
+        for (int k = 0; k < cnt; ++k) {
+          const double4 p = s_at[k];
+          const double wx = y.x - p.x, wy = y.y - p.y, wz = y.z - p.z;
+          const double bu = fma(ux, wx, fma(uy, wy, uz * wz));
+          const double ww = fma(wx, wx, fma(wy, wy, wz * wz));
+          const double disc = fma(bu, bu, s2 - ww);
+          const double g = best + bu;
+          if (disc >= 0.0 && (g < 0.0 || disc > g * g)) best = fmax(best, sqrt(disc) - bu);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  s_best[tid] = best;
+  __syncthreads();
+  if (active && lt == 0) {
+    double r = -INFINITY;
+    for (int k = 0; k < a.tpc; ++k) r = fmax(r, s_best[j * a.tpc + k]);
+    const int64_t o = ui * a.Q + q;
+    if (!valid) r = NAN;
+    a.rho[o] = r;
+    const bool placed = valid && r > -INFINITY;
+    const double rr = r + a.gap;
+    a.pose_t[3 * o + 0] = placed ? fma(rr, ux, a.xP[0]) : NAN;
+    a.pose_t[3 * o + 1] = placed ? fma(rr, uy, a.xP[1]) : NAN;
+    a.pose_t[3 * o + 2] = placed ? fma(rr, uz, a.xP[2]) : NAN;
+    for (int c = 0; c < 4; ++c) a.pose_q[4 * o + c] = a.quats[4 * q + c];
+  }
+}
+
+// Step A6, first half: for each orbit position the lowest energy over its accepted poses
+// (lowest orientation index on ties); -1 / +inf when none is accepted.  One wavefront each.
+__global__ __launch_bounds__(256) void k_orbit_best(const double* __restrict__ E, const uint8_t* __restrict__ flags,
+                                                    int64_t U, int64_t Q, int32_t* __restrict__ best_q,
+                                                    double* __restrict__ best_e) {
+  const int lane = threadIdx.x & 63;
+  const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (u >= U) return;
+  double be = INFINITY;
+  int64_t bq = -1;
+  for (int64_t q = lane; q < Q; q += 64) {
+    const int64_t o = u * Q + q;
+    const double e = E[o];
+    if ((flags[o] & 1) && e < be) {   // lanes visit increasing q: strict < keeps the lowest index
+      be = e;
+      bq = q;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double oe = __shfl_xor(be, off, 64);
+    const int64_t oq = __shfl_xor(bq, off, 64);
+    if (oq >= 0 && (bq < 0 || oe < be || (oe == be && oq < bq))) {
+      be = oe;
+      bq = oq;
+    }
+  }
+  if (lane == 0) {
+    best_q[u] = (int32_t)bq;
+    best_e[u] = be;
+  }
+}
+
+// Step A6, second half: an orbit position with an accepted pose is a minimum when its value is
+// not larger than any neighbour's (CSR neighbour lists over the orbit positions).
+__global__ void k_orbit_local(const int32_t* __restrict__ best_q, const double* __restrict__ best_e, int64_t U,
+                              const int32_t* __restrict__ off, const int32_t* __restrict__ idx,
+                              uint8_t* __restrict__ is_min) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < U; u += (int64_t)gridDim.x * blockDim.x) {
+    bool m = best_q[u] >= 0;
+    for (int32_t k = off[u]; m && k < off[u + 1]; ++k) m = best_e[u] <= best_e[idx[k]];
+    is_min[u] = m ? 1 : 0;
+  }
+}
+
+rsd_status launch_contact(Context* ctx, const Tensor* t, const double* lig_positions, int L, const double* dirs,
+                          int64_t U, const double* quats, int64_t Q, const double xP[3], double sigma, double gap,
+                          double* rho, double* pose_q, double* pose_t) {
+  hipStream_t s = ctx->stream;
+  void* ws = nullptr;
+  const size_t bytes = sizeof(double4) * (size_t)L + 256 + sizeof(double) * (size_t)L;
+  RSD_TRY(ctx->workspace(bytes, &ws));
+  double4* lig = (double4*)ws;
+  double* rl = (double*)((char*)ws + sizeof(double4) * (size_t)L);
+  double* zero = rl + 32;   // charges are not needed here
+  RSD_HIP(hipMemsetAsync(zero, 0, sizeof(double) * (size_t)L, s));
+  RSD_TIMED_LAUNCH(ctx, "ligand_prep", (k_ligand_prep<<<1, 64, 0, s>>>(lig_positions, zero, L, lig, rl)));
+  ContactParams a{};
+  a.atoms = t->atoms;
+  a.N = t->N;
+  a.lig = lig;
+  a.rlig = rl;
+  a.L = L;
+  a.dirs = dirs;
+  a.quats = quats;
+  a.U = U;
+  a.Q = Q;
+  for (int d = 0; d < 3; ++d) a.xP[d] = xP[d];
+  a.sigma = sigma;
+  a.gap = gap;
+  a.tpc = L <= 256 ? L : 256;
+  a.cpb = 256 / a.tpc;
+  a.qblocks = (Q + a.cpb - 1) / a.cpb;
+  a.rho = rho;
+  a.pose_q = pose_q;
+  a.pose_t = pose_t;
+  const int64_t blocks = U * a.qblocks;
+  RSD_CHECK(blocks <= 0x7fffffffLL, RSD_E_UNSUPPORTED, "too many orbit positions x orientations");
+  RSD_TIMED_LAUNCH(ctx, "contact", (k_contact<<<(unsigned)blocks, 256, 0, s>>>(a)));
+  return RSD_OK;
+}
+
+rsd_status launch_orbit_minima(Context* ctx, const double* E, const uint8_t* flags, int64_t U, int64_t Q,
+                               const int32_t* off, const int32_t* idx, int32_t* best_q, double* best_e,
+                               uint8_t* is_min) {
+  hipStream_t s = ctx->stream;
+  const int64_t b1 = (U + 3) / 4;
+  RSD_CHECK(b1 <= 0x7fffffffLL, RSD_E_UNSUPPORTED, "too many orbit positions");
+  RSD_TIMED_LAUNCH(ctx, "minima", (k_orbit_best<<<(unsigned)b1, 256, 0, s>>>(E, flags, U, Q, best_q, best_e)));
+  const unsigned b2 = (unsigned)std::min<int64_t>((U + 255) / 256, 65536);
+  RSD_TIMED_LAUNCH(ctx, "minima", (k_orbit_local<<<b2, 256, 0, s>>>(best_q, best_e, U, off, idx, is_min)));
+  return RSD_OK;
 }
 
 }  // namespace rsd
