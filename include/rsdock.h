@@ -292,6 +292,9 @@ void rsd_tensor_free(rsd_tensor* t);
  *                     iteration for n >= 1024), 1 dense batched eigensolver, 2 subspace iteration
  *   "t2c_solver"      SVD of the Tucker core slices in the build: 0 automatic, 1 one-sided
  *                     Jacobi with the slice in LDS, 2 rocSOLVER gesvd
+ *   "svd_solver"      the k x k SVD inside the rank reduction of explicit factors
+ *                     (rsd_tensor_restrict, rsd_tensor_combine): 0 automatic, 1 rocSOLVER gesvd,
+ *                     2 rocSOLVER gesdd (divide and conquer), 3 rocSOLVER gesvdj (Jacobi)
  *   "gram_solver"     Gram matrices of the side matrices in the build: 0 automatic (1),
  *                     1 Toeplitz-times-Hankel form of the uniform grid (O(n N K + n^2 K)),
  *                     2 dense product of the generated side matrix on matrix cores (O(n^2 N K))

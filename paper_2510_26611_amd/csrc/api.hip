@@ -1015,6 +1015,11 @@ rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t va
     ctx->opt_use_tuning = (int)value;
     return RSD_OK;
   }
+  if (std::strcmp(name, "svd_solver") == 0) {
+    RSD_CHECK(value >= 0 && value <= 3, RSD_E_INVALID, "svd_solver must be 0, 1, 2 or 3");
+    ctx->opt_svd = (int)value;
+    return RSD_OK;
+  }
   if (std::strcmp(name, "gram_solver") == 0) {
     RSD_CHECK(value >= 0 && value <= 2, RSD_E_INVALID, "gram_solver must be 0, 1 or 2");
     ctx->opt_gram = (int)value;

@@ -936,96 +936,222 @@ rsd_status tucker_canonical(Context* ctx, Tensor* t, DevBuf Bt[3], DevBuf U[3], 
   return RSD_OK;
 }
 
-// Dominant left singular vectors of an explicit rows x R matrix A (row-major), with the
-// singular values computed from A itself rather than from A A^T: the Gram matrix squares the
-// spectrum, and at eps = 1e-8 its eigenvalue cut eps^2 lies at the rounding level of FP64,
-// where the exactly low-rank modes of canonical factors (mode 3 of a factor set made by the
-// canonical -> Tucker -> canonical step has only r3 distinct columns) pass noise as rank.
-// Randomized range finder: Q = orth(A Omega) with k test vectors and one power step
-// Q <- orth(A (A^T Q)); then B = Q^T A (k x R), B^T = Q_b R_b (Householder QR), the SVD of
-// the k x k factor R_b (its right singular vectors are B's left ones), U = Q V.  When
-// k = min(rows, R) the range is captured exactly and the power step is skipped.  Singular
-// values >= eps * the largest are kept; if fewer than 16 of the k fall below that cut and
-// k < min(rows, R), k is doubled and the mode is redone.  U is rows x ldu, row-major.
-static rsd_status left_basis(Context* ctx, rocblas_handle hb, const double* A, int rows, int64_t R, double eps,
-                             rocblas_int* d_info, uint64_t seed, DevBuf* U, int* r_out, int* ldu_out) {
-  hipStream_t s = ctx->stream;
-  const int kmax = (int)std::min<int64_t>(rows, R);
-  int k = std::min(kmax, rows <= 256 ? kmax : 128);
-  for (;;) {
-    const bool exact = k == kmax;
-    DevBuf Om, Y, W, Rb, Sv, VT, E, tau;
-    RSD_TRY(Om.alloc(ctx, (size_t)R * k));
-    RSD_TRY(Y.alloc(ctx, (size_t)rows * k));
-    RSD_TRY(W.alloc(ctx, (size_t)R * k));
-    RSD_TRY(Rb.alloc(ctx, (size_t)k * k));
-    RSD_TRY(Sv.alloc(ctx, (size_t)k));
-    RSD_TRY(VT.alloc(ctx, (size_t)k * k));
-    RSD_TRY(E.alloc(ctx, (size_t)k));
-    RSD_TRY(tau.alloc(ctx, (size_t)k));
-    auto qr = [&](double* X, int m, int64_t ld, bool form_q) -> rsd_status {   // column-major m x k
+// Dominant left singular vectors of explicit rows x R matrices A_d (row-major, one per mode),
+// with the singular values computed from A itself rather than from A A^T: the Gram matrix
+// squares the spectrum, and at eps = 1e-8 its eigenvalue cut eps^2 lies at the rounding level
+// of FP64, where the exactly low-rank modes of canonical factors (mode 3 of a factor set made
+// by the canonical -> Tucker -> canonical step has only r3 distinct columns) pass noise as rank.
+//   rows <= R and rows <= 96: B = A itself (Q = I): A^T = Q_b R_b (Householder QR of the
+//     column-major R x rows view of A), the SVD of the rows x rows factor R_b, whose right
+//     singular vectors are A's left ones.
+//   otherwise a randomized range finder: Q = orth(A Omega) with k = 64 test vectors (128 above
+//     1024 rows) and one power step Q <- orth(A (A^T Q)) (skipped when k = min(rows, R)
+//     captures the range exactly), B = Q^T A, B^T = Q_b R_b, the SVD of R_b, U = Q V.  If
+//     fewer than 16 of the k singular values fall below the cut and k < min(rows, R), k is
+//     doubled and the mode is redone.
+// Singular values >= eps * the largest are kept.  The three modes run on three streams (the
+// context stream and two auxiliary ones with their own rocBLAS handles), since their QR and
+// SVD calls are chains of short launches; the host synchronises once per pass to read the
+// singular values.  U_d is rows_d x ldu_d, row-major, zero beyond column r_d.
+__global__ void k_vt_rows(const double* __restrict__ VT, int k, int rows, int r, double* __restrict__ U, int ldu) {
+  const int64_t total = (int64_t)rows * ldu;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / ldu), a = (int)(e % ldu);
+    U[e] = a < r ? VT[(int64_t)i * k + a] : 0.0;   // U[i][a] = V[i][a] = VT[a + i k]
+  }
+}
+
+static rsd_status left_basis3(Context* ctx, rocblas_handle hb, double* const A[3], const int rows[3], int64_t R,
+                              double eps, rocblas_int* d_info, DevBuf U[3], int r_out[3], int ldu_out[3]) {
+  hipStream_t main = ctx->stream;
+  RSD_TRY(ctx->aux_streams());
+  hipStream_t st[3] = {main, ctx->aux_stream[0], ctx->aux_stream[1]};
+  rocblas_handle hbs[3] = {hb, (rocblas_handle)ctx->aux_blas[0], (rocblas_handle)ctx->aux_blas[1]};
+  hipEvent_t ready = nullptr, done[2] = {nullptr, nullptr};
+  struct Events {
+    hipEvent_t* e[3];
+    ~Events() {
+      for (auto* x : e)
+        if (*x) (void)hipEventDestroy(*x);
+    }
+  } evguard{{&ready, &done[0], &done[1]}};
+  RSD_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  RSD_HIP(hipEventCreateWithFlags(&done[0], hipEventDisableTiming));
+  RSD_HIP(hipEventCreateWithFlags(&done[1], hipEventDisableTiming));
+  RSD_HIP(hipEventRecord(ready, main));
+  RSD_HIP(hipStreamWaitEvent(st[1], ready, 0));
+  RSD_HIP(hipStreamWaitEvent(st[2], ready, 0));
+  struct Mode {
+    int k = 0, kmax = 0;
+    bool direct = false, finished = false;
+    DevBuf Om, Y, W, Rb, Sv, VT, E, tau, Ul;
+  } m[3];
+  for (int d = 0; d < 3; ++d) {
+    m[d].kmax = (int)std::min<int64_t>(rows[d], R);
+    m[d].direct = rows[d] <= R && rows[d] <= 96;
+    m[d].k = m[d].kmax <= 96 ? m[d].kmax : std::min(m[d].kmax, rows[d] > 1024 ? 128 : 64);
+  }
+  struct StreamGuard {   // a mode's work is issued on its stream; the context stream comes back afterwards
+    Context* c;
+    hipStream_t saved;
+    ~StreamGuard() { c->stream = saved; }
+  } sg{ctx, main};
+  const int solver = ctx->opt_svd == 0 ? 3 : ctx->opt_svd;
+  auto issue = [&](int d) -> rsd_status {
+    Mode& md = m[d];
+    const int k = md.k, nr = rows[d];
+    const bool exact = k == md.kmax;
+    hipStream_t s = st[d];
+    RSD_TRY(md.W.alloc(ctx, (size_t)R * k));
+    RSD_TRY(md.Rb.alloc(ctx, (size_t)k * k));
+    RSD_TRY(md.Sv.alloc(ctx, (size_t)k));
+    RSD_TRY(md.VT.alloc(ctx, (size_t)k * k));
+    RSD_TRY(md.E.alloc(ctx, (size_t)k));
+    RSD_TRY(md.tau.alloc(ctx, (size_t)k));
+    auto qr = [&](double* X, int mrows, int64_t ld, bool form_q) -> rsd_status {   // column-major mrows x k
       KernelTimer kt;
-      if (ctx->timing) RSD_TRY(ctx->timer_begin("restrict", &kt));
-      RSD_CHECK(rocsolver_dgeqrf(hb, m, k, X, (rocblas_int)ld, tau.p) == rocblas_status_success, RSD_E_HIP,
+      if (ctx->timing) RSD_TRY(ctx->timer_begin("qr", &kt));
+      RSD_CHECK(rocsolver_dgeqrf(hbs[d], mrows, k, X, (rocblas_int)ld, md.tau.p) == rocblas_status_success, RSD_E_HIP,
                 "rocsolver_dgeqrf failed");
       if (form_q)
-        RSD_CHECK(rocsolver_dorgqr(hb, m, k, k, X, (rocblas_int)ld, tau.p) == rocblas_status_success, RSD_E_HIP,
-                  "rocsolver_dorgqr failed");
+        RSD_CHECK(rocsolver_dorgqr(hbs[d], mrows, k, k, X, (rocblas_int)ld, md.tau.p) == rocblas_status_success,
+                  RSD_E_HIP, "rocsolver_dorgqr failed");
       if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
       return RSD_OK;
     };
     GemmShape g{};
     g.split_stride = 0; g.accumulate = 0; g.tri = 0;
-    RSD_TIMED_LAUNCH(ctx, "restrict", (k_random_fill<<<grid1d(R * k), 256, 0, s>>>(Om.p, R * k, seed)));
-    // Y = A Omega as Y^T (k x rows row-major = rows x k column-major)
-    g.M = k; g.N = rows; g.K = R; g.kper = (R + TK - 1) / TK * TK; g.C = Y.p; g.ldc = rows;
-    RSD_TRY(gemm(ctx, "restrict", OpKM{Om.p, k, k}, OpMK{A, R, rows}, g, 1));
-    RSD_TRY(qr(Y.p, rows, rows, true));
-    if (!exact) {
-      // W = A^T Q (R x k row-major), then Y^T = W^T A^T and orthonormalise again
-      g.M = (int)R; g.N = k; g.K = rows; g.kper = ((int64_t)rows + TK - 1) / TK * TK; g.C = W.p; g.ldc = k;
-      RSD_TRY(gemm(ctx, "restrict", OpKM{A, R, (int)R}, OpMK{Y.p, rows, k}, g, 1));
-      g.M = k; g.N = rows; g.K = R; g.kper = (R + TK - 1) / TK * TK; g.C = Y.p; g.ldc = rows;
-      RSD_TRY(gemm(ctx, "restrict", OpKM{W.p, k, k}, OpMK{A, R, rows}, g, 1));
-      RSD_TRY(qr(Y.p, rows, rows, true));
+    if (md.direct) {
+      // B^T = A^T: the column-major R x rows view of A, copied (A is needed for the projection)
+      RSD_HIP(hipMemcpyAsync(md.W.p, A[d], sizeof(double) * (size_t)R * nr, hipMemcpyDeviceToDevice, s));
+    } else {
+      RSD_TRY(md.Om.alloc(ctx, (size_t)R * k));
+      RSD_TRY(md.Y.alloc(ctx, (size_t)nr * k));
+      RSD_TIMED_LAUNCH(ctx, "restrict", (k_random_fill<<<grid1d(R * k), 256, 0, s>>>(md.Om.p, R * k,
+                                                                                      0x5EEDull + (uint64_t)d)));
+      // Y = A Omega as Y^T (k x rows row-major = rows x k column-major)
+      g.M = k; g.N = nr; g.K = R; g.kper = (R + TK - 1) / TK * TK; g.C = md.Y.p; g.ldc = nr;
+      RSD_TRY(gemm(ctx, "restrict", OpKM{md.Om.p, k, k}, OpMK{A[d], R, nr}, g, 1));
+      RSD_TRY(qr(md.Y.p, nr, nr, true));
+      if (!exact) {
+        // W = A^T Q (R x k row-major), then Y^T = W^T A^T and orthonormalise again
+        g.M = (int)R; g.N = k; g.K = nr; g.kper = ((int64_t)nr + TK - 1) / TK * TK; g.C = md.W.p; g.ldc = k;
+        RSD_TRY(gemm(ctx, "restrict", OpKM{A[d], R, (int)R}, OpMK{md.Y.p, nr, k}, g, 1));
+        g.M = k; g.N = nr; g.K = R; g.kper = (R + TK - 1) / TK * TK; g.C = md.Y.p; g.ldc = nr;
+        RSD_TRY(gemm(ctx, "restrict", OpKM{md.W.p, k, k}, OpMK{A[d], R, nr}, g, 1));
+        RSD_TRY(qr(md.Y.p, nr, nr, true));
+      }
+      // B^T = A^T Q as a column-major R x k matrix (k x R row-major)
+      RSD_CHECK(div_up(R, TN) <= 65535, RSD_E_UNSUPPORTED, "too many columns (%lld) for the projection",
+                (long long)R);
+      g.M = k; g.N = (int)R; g.K = nr; g.kper = ((int64_t)nr + TK - 1) / TK * TK; g.C = md.W.p; g.ldc = R;
+      RSD_TRY(gemm(ctx, "restrict", OpMK{md.Y.p, nr, k}, OpKM{A[d], R, (int)R}, g, 1));
     }
-    // B^T = A^T Q as a column-major R x k matrix (k x R row-major), its R factor, and the SVD
-    RSD_CHECK(div_up(R, TN) <= 65535, RSD_E_UNSUPPORTED, "too many columns (%lld) for the projection",
-              (long long)R);
-    g.M = k; g.N = (int)R; g.K = rows; g.kper = ((int64_t)rows + TK - 1) / TK * TK; g.C = W.p; g.ldc = R;
-    RSD_TRY(gemm(ctx, "restrict", OpMK{Y.p, rows, k}, OpKM{A, R, (int)R}, g, 1));
-    RSD_TRY(qr(W.p, (int)R, R, false));
-    RSD_TIMED_LAUNCH(ctx, "restrict", (k_upper_copy<<<grid1d((int64_t)k * k), 256, 0, s>>>(W.p, R, k, Rb.p)));
-    {
-      KernelTimer kt;
-      if (ctx->timing) RSD_TRY(ctx->timer_begin("restrict", &kt));
-      const rocblas_status rs = rocsolver_dgesvd(hb, rocblas_svect_none, rocblas_svect_singular, k, k, Rb.p, k, Sv.p,
-                                                 nullptr, 1, VT.p, k, E.p, rocblas_outofplace, d_info);
-      RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dgesvd failed (%d)", (int)rs);
-      if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+    RSD_TRY(qr(md.W.p, (int)R, R, false));
+    RSD_TIMED_LAUNCH(ctx, "restrict", (k_upper_copy<<<grid1d((int64_t)k * k), 256, 0, s>>>(md.W.p, R, k, md.Rb.p)));
+    KernelTimer kt;
+    if (ctx->timing) RSD_TRY(ctx->timer_begin("svd", &kt));
+    rocblas_status rs = rocblas_status_success;
+    if (solver == 1) {
+      rs = rocsolver_dgesvd(hbs[d], rocblas_svect_none, rocblas_svect_singular, k, k, md.Rb.p, k, md.Sv.p, nullptr, 1,
+                            md.VT.p, k, md.E.p, rocblas_outofplace, d_info + d);
+    } else if (solver == 2) {
+      RSD_TRY(md.Ul.alloc(ctx, (size_t)k * k));
+      rs = rocsolver_dgesdd(hbs[d], rocblas_svect_singular, rocblas_svect_singular, k, k, md.Rb.p, k, md.Sv.p,
+                            md.Ul.p, k, md.VT.p, k, d_info + d);
+    } else {
+      rs = rocsolver_dgesvdj(hbs[d], rocblas_svect_none, rocblas_svect_singular, k, k, md.Rb.p, k, 0.0, md.E.p, 100,
+                             d_info + 3 + d, md.Sv.p, nullptr, 1, md.VT.p, k, d_info + d);
     }
-    RSD_TRY(check_info(ctx, d_info, 1, "singular value decomposition"));
-    std::vector<double> sv((size_t)k);
-    RSD_HIP(hipMemcpy(sv.data(), Sv.p, sizeof(double) * k, hipMemcpyDeviceToHost));
-    RSD_CHECK(sv[0] > 0.0 && std::isfinite(sv[0]), RSD_E_NUMERIC, "factor matrix has no positive singular value");
-    int r = 0;
-    while (r < k && sv[r] >= eps * sv[0]) ++r;
-    if (r > k - 16 && k < kmax) {
-      k = std::min(kmax, 2 * k);
-      continue;
-    }
-    RSD_CHECK(r >= 1 && r <= 1024, RSD_E_UNSUPPORTED, "mode rank %d outside [1, 1024]", r);
-    const int ldu = ((r + 7) / 8) * 8;
-    RSD_TRY(U->alloc(ctx, (size_t)rows * ldu));
-    RSD_HIP(hipMemsetAsync(U->p, 0, U->bytes, s));   // columns r .. ldu - 1 stay zero
-    // U[i][a] = sum_j Q[i][j] V[j][a],  V[j][a] = VT[a + j k]
-    g.M = rows; g.N = r; g.K = k; g.kper = ((int64_t)k + TK - 1) / TK * TK; g.C = U->p; g.ldc = ldu;
-    RSD_TRY(gemm(ctx, "restrict", OpKM{Y.p, rows, rows}, OpKM{VT.p, k, r}, g, 1));
-    *r_out = r;
-    *ldu_out = ldu;
-    RSD_HIP(hipStreamSynchronize(s));   // the local buffers are released on return
+    RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocSOLVER SVD (%d) failed (%d)", solver, (int)rs);
+    if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
     return RSD_OK;
+  };
+  auto finish = [&](int d, int r, int ldu) -> rsd_status {
+    Mode& md = m[d];
+    const int k = md.k, nr = rows[d];
+    hipStream_t s = st[d];
+    RSD_TRY(U[d].alloc(ctx, (size_t)nr * ldu));
+    if (md.direct) {
+      RSD_TIMED_LAUNCH(ctx, "restrict", (k_vt_rows<<<grid1d((int64_t)nr * ldu), 256, 0, s>>>(md.VT.p, k, nr, r,
+                                                                                                U[d].p, ldu)));
+    } else {
+      RSD_HIP(hipMemsetAsync(U[d].p, 0, U[d].bytes, s));   // columns r .. ldu - 1 stay zero
+      // U[i][a] = sum_j Q[i][j] V[j][a],  V[j][a] = VT[a + j k]
+      GemmShape g{};
+      g.split_stride = 0; g.accumulate = 0; g.tri = 0;
+      g.M = nr; g.N = r; g.K = k; g.kper = ((int64_t)k + TK - 1) / TK * TK; g.C = U[d].p; g.ldc = ldu;
+      RSD_TRY(gemm(ctx, "restrict", OpKM{md.Y.p, nr, nr}, OpKM{md.VT.p, k, r}, g, 1));
+    }
+    return RSD_OK;
+  };
+  rsd_status st_all = RSD_OK;
+  for (int pass = 0; pass < 8 && st_all == RSD_OK; ++pass) {
+    bool any = false;
+    for (int d = 0; d < 3 && st_all == RSD_OK; ++d) {
+      if (m[d].finished) continue;
+      any = true;
+      ctx->stream = st[d];
+      st_all = issue(d);
+      ctx->stream = main;
+    }
+    if (!any || st_all != RSD_OK) break;
+    for (int d = 0; d < 3 && st_all == RSD_OK; ++d) {
+      Mode& md = m[d];
+      if (md.finished) continue;
+      const int k = md.k;
+      std::vector<double> sv((size_t)k);
+      rocblas_int info = 0;
+      hipError_t e = hipMemcpyAsync(&info, d_info + d, sizeof(info), hipMemcpyDeviceToHost, st[d]);
+      if (e == hipSuccess) e = hipMemcpyAsync(sv.data(), md.Sv.p, sizeof(double) * k, hipMemcpyDeviceToHost, st[d]);
+      if (e == hipSuccess) e = hipStreamSynchronize(st[d]);
+      if (e != hipSuccess) {
+        set_error("singular values: %s", hipGetErrorString(e));
+        st_all = RSD_E_HIP;
+        break;
+      }
+      if (info != 0) {
+        set_error("SVD of mode %d did not converge (info %d)", d, (int)info);
+        st_all = RSD_E_NUMERIC;
+        break;
+      }
+      // rocSOLVER returns the singular values in decreasing order
+      if (!(sv[0] > 0.0 && std::isfinite(sv[0]))) {
+        set_error("factor matrix of mode %d has no positive singular value", d);
+        st_all = RSD_E_NUMERIC;
+        break;
+      }
+      int r = 0;
+      while (r < k && sv[r] >= eps * sv[0]) ++r;
+      if (r > k - 16 && k < md.kmax) {
+        md.k = std::min(md.kmax, 2 * k);   // redo this mode with more test vectors on the next pass
+        continue;
+      }
+      if (r < 1 || r > 1024) {
+        set_error("mode-%d rank %d outside [1, 1024]", d, r);
+        st_all = RSD_E_UNSUPPORTED;
+        break;
+      }
+      const int ldu = ((r + 7) / 8) * 8;
+      ctx->stream = st[d];
+      st_all = finish(d, r, ldu);
+      ctx->stream = main;
+      r_out[d] = r;
+      ldu_out[d] = ldu;
+      md.finished = true;
+    }
   }
+  // the context stream continues after the auxiliary streams' work; the modes' buffers are
+  // released on return, after every stream has finished with them
+  (void)hipEventRecord(done[0], st[1]);
+  (void)hipEventRecord(done[1], st[2]);
+  (void)hipStreamWaitEvent(main, done[0], 0);
+  (void)hipStreamWaitEvent(main, done[1], 0);
+  for (int d = 0; d < 3; ++d) (void)hipStreamSynchronize(st[d]);
+  RSD_TRY(st_all);
+  for (int d = 0; d < 3; ++d)
+    RSD_CHECK(m[d].finished, RSD_E_NUMERIC, "rank reduction of mode %d did not settle", d);
+  return RSD_OK;
 }
 
 // Rank reduction of a canonical tensor given by explicit factors: the rows i_lo[d] ..
@@ -1080,8 +1206,8 @@ rsd_status reduce_factors(Context* ctx, const Tensor* const* src, int nsrc, Tens
     RSD_TIMED_LAUNCH(ctx, "restrict", (k_normalize_cols<<<grid1d((int64_t)t->nm[d] * R), 256, 0, s>>>(
                                           A[d].p, t->nm[d], R, nu[d].p, xi.p)));
   int r[3] = {0, 0, 0}, ldu[3] = {0, 0, 0};
-  for (int d = 0; d < 3; ++d)
-    RSD_TRY(left_basis(ctx, hb, A[d].p, t->nm[d], R, eps, d_info, 0x5EEDull + (uint64_t)d, &U[d], &r[d], &ldu[d]));
+  double* const Ap[3] = {A[0].p, A[1].p, A[2].p};
+  RSD_TRY(left_basis3(ctx, hb, Ap, t->nm, R, eps, d_info, U, r, ldu));
   for (int d = 0; d < 3; ++d) {
     // B_d^T[p][a] = sum_i A[i][p] U[i][a]
     const int rows = t->nm[d];
