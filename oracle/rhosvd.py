@@ -59,8 +59,9 @@ def _left_svd(A: np.ndarray):
     return U, s
 
 
-def rhosvd(charges, positions, t_long, w_long, n, b, eps, col_chunk: int = 8192) -> TuckerResult:
-    """Canonical-to-Tucker transform of the long-range sum (steps 1-3 above)."""
+def rhosvd(charges, positions, t_long, w_long, n, b, eps, col_chunk: int = 8192, galerkin: bool = False) -> TuckerResult:
+    """Canonical-to-Tucker transform of the long-range sum (steps 1-3 above); galerkin=True
+    takes the cell-average factors of eq. 2.1 instead of collocated ones."""
     charges = np.asarray(charges, dtype=np.float64)
     positions = np.asarray(positions, dtype=np.float64)
     N = positions.shape[0]
@@ -68,7 +69,10 @@ def rhosvd(charges, positions, t_long, w_long, n, b, eps, col_chunk: int = 8192)
     _, _, _, nodes = _tensor.grid(n, b)
     U, sing, ranks, B, norms = [], [], [], [], []
     for d in range(3):
-        G = _tensor.factor_columns(positions[:, d], t_long, nodes).reshape(n, N * K)
+        if galerkin:
+            G = _tensor.galerkin_columns(positions[:, d], t_long, nodes, (2.0 * b) / n).reshape(n, N * K)
+        else:
+            G = _tensor.factor_columns(positions[:, d], t_long, nodes).reshape(n, N * K)
         nrm = np.sqrt(np.sum(G * G, axis=0))
         G /= np.where(nrm > 0.0, nrm, 1.0)[None, :]
         Ud, sd = _left_svd(G)
@@ -115,9 +119,9 @@ def tucker_to_canonical(tk: TuckerResult, eps) -> CanonicalResult:
     return CanonicalResult(F=F, R=F[0].shape[1], dropped_fro=float(np.sqrt(dropped)))
 
 
-def build(charges, positions, t_long, w_long, n, b, eps):
+def build(charges, positions, t_long, w_long, n, b, eps, galerkin: bool = False):
     """Algorithm TEP steps 3-5: the rank-reduced canonical long-range tensor."""
-    tk = rhosvd(charges, positions, t_long, w_long, n, b, eps)
+    tk = rhosvd(charges, positions, t_long, w_long, n, b, eps, galerkin=galerkin)
     return tk, tucker_to_canonical(tk, eps)
 
 

@@ -34,6 +34,24 @@ def factor_columns(coord: np.ndarray, t_long: np.ndarray, nodes: np.ndarray) -> 
     return np.exp(-(t_long * t_long)[None, None, :] * (diff * diff)[:, :, None])
 
 
+def galerkin_columns(coord: np.ndarray, t_long: np.ndarray, nodes: np.ndarray, h: float) -> np.ndarray:
+    """1-D Galerkin factors of eq. 2.1 (projection onto piecewise-constant basis functions),
+    normalised as cell averages so that they approximate the same potential values as the
+    collocated factors: G[j, m, k] = (1/h) int_{X_j - h/2}^{X_j + h/2} exp(-t_k^2 (x - x_m)^2) dx
+      = sqrt(pi) / (2 t_k h) * (erf(t_k (X_j + h/2 - x_m)) - erf(t_k (X_j - h/2 - x_m))),
+    and 1 for t_k = 0.  Where both arguments share a sign the difference is taken of erfc
+    values, which keeps the digits of the tails.  Returns (n, N, K) float64."""
+    from scipy.special import erf, erfc
+    diff = (nodes[:, None] - coord[None, :])[:, :, None]                 # X_j - x_m
+    t = np.asarray(t_long, dtype=np.float64)[None, None, :]
+    u1 = t * (diff - 0.5 * h)
+    u2 = t * (diff + 0.5 * h)
+    d = np.where(u1 >= 0.0, erfc(u1) - erfc(u2), np.where(u2 <= 0.0, erfc(-u2) - erfc(-u1), erf(u2) - erf(u1)))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        g = np.sqrt(np.pi) / (2.0 * t * h) * d
+    return np.where(t > 0.0, g, 1.0)
+
+
 def long_range_at_nodes(charges, positions, t_long, w_long, n, b, idx):
     """Uncompressed long-range tensor T0 at grid multi-indices idx (Q, 3) (eq. 2.6).
 

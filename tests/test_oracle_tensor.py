@@ -1,4 +1,6 @@
 """Pins of the oracle's grid, separable factors and RHOSVD (eqs. 2.1-2.6, Algorithm TEP)."""
+import math
+
 import numpy as np
 import pytest
 
@@ -108,3 +110,57 @@ def test_rank_nearly_independent_of_cluster_size():
         Rs.append(rhosvd.tucker_to_canonical(tk, 1e-8).R)
     assert max(ranks) <= min(ranks) + 2
     assert max(Rs) <= 1.25 * min(Rs)
+
+
+def test_galerkin_columns_are_cell_averages():
+    """Eq. 2.1's piecewise-constant projection as cell averages: against adaptive quadrature of
+    the Gaussian over each cell, for wide, narrow and constant (t = 0) terms, centres on and off
+    the cell and far out in the tail."""
+    from scipy.integrate import quad
+    n, b = 64, 8.0
+    h, _, _, nodes = tensor.grid(n, b)
+    t_long = np.array([0.0, 1e-4, 0.03, 0.4, 2.5, 9.0])
+    coord = np.array([0.0, 0.1234, -3.3, 7.9])
+    G = tensor.galerkin_columns(coord, t_long, nodes, h)
+    for j in (0, 5, 31, 32, 40, 63):
+        for m, x in enumerate(coord):
+            for k, t in enumerate(t_long):
+                f = lambda s: math.exp(-(t * (s - x)) ** 2)  # noqa: E731
+                ref = quad(f, nodes[j] - h / 2, nodes[j] + h / 2, epsabs=0.0, epsrel=1e-13, limit=200)[0] / h
+                assert G[j, m, k] == pytest.approx(ref, rel=1e-10, abs=1e-300)
+
+
+def test_galerkin_minus_collocation_is_second_order():
+    """The cell average exceeds the node value by f''(X) h^2 / 24 + O(h^4): halving h quarters the
+    difference, and the leading term matches."""
+    t = np.array([0.3])
+    x = np.array([0.37])
+    diffs = []
+    for n in (32, 64, 128):
+        h, _, _, nodes = tensor.grid(n, 8.0)
+        g = tensor.galerkin_columns(x, t, nodes, h)[:, 0, 0]
+        c = tensor.factor_columns(x, t, nodes)[:, 0, 0]
+        a = t[0] * (nodes - x[0])
+        lead = (4.0 * a * a - 2.0) * np.exp(-a * a) * (t[0] * h) ** 2 / 24.0
+        assert np.max(np.abs(g - c - lead)) <= 0.1 * np.max(np.abs(lead)) + 1e-15
+        diffs.append(np.max(np.abs(g - c)))
+    assert 3.5 < diffs[0] / diffs[1] < 4.5 and 3.5 < diffs[1] / diffs[2] < 4.5
+
+
+def test_galerkin_build_within_the_rhosvd_bound():
+    """RHOSVD of the Galerkin side matrices: the canonical tensor against the uncompressed
+    Galerkin sum at sampled nodes, within the bound of the truncation."""
+    n, b = 64, 12.0
+    pos = gen.ball_points(gen.rng(90, 1), 30, 6.0)
+    z = gen.charges(gen.rng(90, 2), 30, 0.3, True)
+    tk, can = rhosvd.build(z, pos, TL, WL, n, b, 1e-8, galerkin=True)
+    h, _, _, nodes = tensor.grid(n, b)
+    G = [tensor.galerkin_columns(pos[:, d], TL, nodes, h) for d in range(3)]     # (n, N, K)
+    idx = np.random.default_rng(4).integers(0, n, size=(400, 3))
+    exact = np.einsum("m,k,qmk,qmk,qmk->q", z, WL, G[0][idx[:, 0]], G[1][idx[:, 1]], G[2][idx[:, 2]])
+    approx = np.sum(can.F[0][idx[:, 0]] * can.F[1][idx[:, 1]] * can.F[2][idx[:, 2]], axis=1)
+    assert np.max(np.abs(approx - exact)) <= tk.bound + can.dropped_fro
+    # and it differs from the collocated build by the O(h^2) cell-average correction only
+    _, col = rhosvd.build(z, pos, TL, WL, n, b, 1e-8)
+    colv = np.sum(col.F[0][idx[:, 0]] * col.F[1][idx[:, 1]] * col.F[2][idx[:, 2]], axis=1)
+    assert 0 < np.max(np.abs(approx - colv)) <= 0.05 * np.max(np.abs(colv))
