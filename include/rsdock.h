@@ -219,6 +219,18 @@ rsd_status rsd_tensor_restrict(rsd_context* ctx, const rsd_tensor* src, const do
 rsd_status rsd_tensor_combine(rsd_context* ctx, const rsd_tensor* const* tensors, int32_t count, double eps,
                               rsd_tensor** out);
 
+/* The electrostatic energy of the molecule itself from its own tensor (Prop. 3.2, eqs. 3.8-3.9):
+ *   E_long  = 1/2 sum_j z_j (P_l(x_j) - z_j sum_{k < K_long} w_k),
+ * the long-range potential at each atom (trilinear, as in scoring) minus the atom's own
+ * long-range term (its charge times the long-range reference kernel at distance zero), and
+ *   E_short = 1/2 sum_j z_j sum_{m != j, d^2 < r_c^2} z_m sum_{k >= K_long} w_k exp(-t_k^2 d^2),
+ * the short-range pairs, which the proposition assumes to vanish (all pair distances beyond
+ * the short-range support); E_long + E_short approximates 1/2 sum_{j != m} z_j z_m / d_jm.
+ * Host outputs; synchronises the context stream.  The short-range sum runs over all atom
+ * pairs (O(N^2), no cell list).  Errors: RSD_E_INVALID (NULL), RSD_E_UNSUPPORTED for a
+ * restricted tensor. */
+rsd_status rsd_self_energy(rsd_context* ctx, const rsd_tensor* t, double* E_long, double* E_short);
+
 /* ---- posing search (Algorithm PPIEM, steps A2-A6) ----
  * The search scans a grid of orbit directions u_i (positions of the ligand centre around the
  * protein centre x_P) times orientations q_k of the ligand about its own centre; each pose
@@ -292,6 +304,10 @@ void rsd_tensor_free(rsd_tensor* t);
  *                     iteration for n >= 1024), 1 dense batched eigensolver, 2 subspace iteration
  *   "t2c_solver"      SVD of the Tucker core slices in the build: 0 automatic, 1 one-sided
  *                     Jacobi with the slice in LDS, 2 rocSOLVER gesvd
+ *   "factors"         1-D factors of rsd_build_rs_tensor: 0 (default) the Gaussians collocated
+ *                     at the grid nodes; 1 their averages over the grid cells, i.e. the
+ *                     projection onto piecewise-constant basis functions of eq. 2.1 (the Gram
+ *                     matrices are then formed densely on the matrix cores)
  *   "svd_solver"      the k x k SVD inside the rank reduction of explicit factors
  *                     (rsd_tensor_restrict, rsd_tensor_combine): 0 automatic, 1 rocSOLVER gesvd,
  *                     2 rocSOLVER gesdd (divide and conquer), 3 rocSOLVER gesvdj (Jacobi)

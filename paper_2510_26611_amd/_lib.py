@@ -31,6 +31,7 @@ EXPORTED = [
     "rsd_context_set_option", "rsd_batch_create", "rsd_batch_run", "rsd_batch_free", "rsd_autotune",
     "rsd_tensor_restrict", "rsd_tensor_grid", "rsd_tensor_combine",
     "rsd_tensor_centre", "rsd_contact_poses", "rsd_orbit_minima",
+    "rsd_self_energy",
 ]
 
 
@@ -87,6 +88,7 @@ def _declare(lib: C.CDLL) -> C.CDLL:
         "rsd_tensor_restrict": (st, [_P, _P, C.POINTER(_D), C.POINTER(_D), _D, C.POINTER(_P)]),
         "rsd_tensor_combine": (st, [_P, _P, C.c_int32, _D, C.POINTER(_P)]),
         "rsd_tensor_centre": (st, [_P, C.POINTER(_D)]),
+        "rsd_self_energy": (st, [_P, _P, C.POINTER(_D), C.POINTER(_D)]),
         "rsd_contact_poses": (st, [_P, _P, _P, C.c_int64, _P, C.c_int64, _P, C.c_int64, C.POINTER(_D), _D, _D, _P,
                                    _P, _P]),
         "rsd_orbit_minima": (st, [_P, _P, _P, C.c_int64, C.c_int64, _P, _P, _P, _P, _P]),

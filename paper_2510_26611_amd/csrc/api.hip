@@ -414,6 +414,7 @@ static rsd_status make_tensor(rsd_context* ctx, const double* const F[3], int64_
   rsd_status st = tensor_common(ctx, t, n, b, sp, std::move(z), std::move(pos), &d_z, &d_pos);
   if (st == RSD_OK) {
     if (build) {
+      t->galerkin = ctx->opt_factors == 1;
       st = build_factors(ctx, t, d_z, d_pos);
     } else {
       st = import_factors(ctx, t, F, R, dev);
@@ -585,6 +586,20 @@ rsd_status rsd_tensor_combine(rsd_context* ctx, const rsd_tensor* const* tensors
   }
   *out = t;
   return RSD_OK;
+}
+
+rsd_status rsd_self_energy(rsd_context* ctx, const rsd_tensor* t, double* E_long, double* E_short) {
+  clear_error();
+  RSD_CHECK(ctx != nullptr && t != nullptr && E_long != nullptr && E_short != nullptr, RSD_E_INVALID,
+            "NULL argument");
+  RSD_CHECK(!ctx->closing, RSD_E_INVALID, "context has been freed");
+  RSD_CHECK(t->ctx->device == ctx->device, RSD_E_INVALID, "tensor lives on another device");
+  RSD_CHECK(!t->restricted, RSD_E_UNSUPPORTED, "a restricted tensor does not cover the molecule's atoms");
+  *E_long = 0.0;
+  *E_short = 0.0;
+  if (t->N == 0) return RSD_OK;
+  RSD_HIP(hipSetDevice(ctx->device));
+  return launch_self_energy(ctx, t, E_long, E_short);
 }
 
 rsd_status rsd_tensor_centre(const rsd_tensor* t, double centre[3]) {
@@ -1013,6 +1028,11 @@ rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t va
   if (std::strcmp(name, "use_tuning") == 0) {
     RSD_CHECK(value == 0 || value == 1, RSD_E_INVALID, "use_tuning must be 0 or 1");
     ctx->opt_use_tuning = (int)value;
+    return RSD_OK;
+  }
+  if (std::strcmp(name, "factors") == 0) {
+    RSD_CHECK(value == 0 || value == 1, RSD_E_INVALID, "factors must be 0 or 1");
+    ctx->opt_factors = (int)value;
     return RSD_OK;
   }
   if (std::strcmp(name, "svd_solver") == 0) {

@@ -124,13 +124,46 @@ struct OpKhatriRao {          // element (k, m = a*r2 + b) = P1[k*ld1 + a] * P2[
   }
 };
 
-struct OpGauss {              // element (k = grid row i, m = column c) = exp(-t_c^2 (X_i - x_c)^2) / nu_c
+// One entry of a 1-D factor column at offset dx = X_i - x_m from the atom: the collocated
+// Gaussian exp(-t^2 dx^2), or with gal != 0 its average over the cell [X_i - h/2, X_i + h/2]
+// (eq. 2.1's piecewise-constant projection):
+//   sqrt(pi) / (2 t h) (erf(t (dx + h/2)) - erf(t (dx - h/2))),
+// with the difference taken of erfc values where both arguments share a sign.  For t h < 0.01
+// the erf difference would cancel most of its digits; there the average is the series
+// f + f2 (t h)^2 / 24 + f4 (t h)^4 / 1920 in a = t dx, with f = exp(-a^2) and f2, f4 its second
+// and fourth derivatives; the next term is below 4e-16 relative.
+__device__ __forceinline__ double gauss_entry(double t2, double dx, double h, int gal) {
+  if (!gal) return exp(-(t2 * (dx * dx)));
+  const double t = sqrt(t2);
+  const double th = t * h;
+  if (th < 0.01) {
+    const double a = t * dx, a2 = a * a;
+    const double e = exp(-a2);
+    const double f2 = (4.0 * a2 - 2.0) * e;
+    const double f4 = ((16.0 * a2 - 48.0) * a2 + 12.0) * e;
+    const double s2 = th * th;
+    return e + s2 * (f2 / 24.0 + s2 * (f4 / 1920.0));
+  }
+  const double u1 = t * (dx - 0.5 * h), u2 = t * (dx + 0.5 * h);
+  double d;
+  if (u1 >= 0.0) {
+    d = erfc(u1) - erfc(u2);
+  } else if (u2 <= 0.0) {
+    d = erfc(-u2) - erfc(-u1);
+  } else {
+    d = erf(u2) - erf(u1);
+  }
+  return 0.886226925452758 / th * d;   // sqrt(pi) / 2 = 0.886226925452758...
+}
+
+struct OpGauss {              // element (k = grid row i, m = column c) = g_c(X_i - x_c) / nu_c (gauss_entry)
   const double* __restrict__ pos;    // N x 3
   const double* __restrict__ t2;     // K_long
   const double* __restrict__ inv_nu; // columns
   int K, d, n;
   double b, h;
   int dim;                           // number of columns
+  int gal;                           // Galerkin (cell-average) entries
   double x_[8], t2_[8], s_[8];
   __device__ void setup(int m0) {
     const int c = (threadIdx.x & 7) * 8;
@@ -153,7 +186,7 @@ struct OpGauss {              // element (k = grid row i, m = column c) = exp(-t
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const double dx = X - x_[j];
-      s[kk * LDT + c + j] = (i < k1) ? exp(-(t2_[j] * (dx * dx))) * s_[j] : 0.0;
+      s[kk * LDT + c + j] = (i < k1) ? gauss_entry(t2_[j], dx, h, gal) * s_[j] : 0.0;
     }
   }
 };
@@ -295,7 +328,7 @@ __global__ void k_reduce_splits(const double* __restrict__ part, int splits, int
 // Column norms nu_c = ||g_c|| of columns c in [c0, c1) of mode d (one wavefront per column).
 __global__ void k_col_norms(const double* __restrict__ pos, const double* __restrict__ t2, int K, int d, int n,
                             double b, double h, int64_t c0, int64_t c1, double* __restrict__ nu,
-                            double* __restrict__ inv_nu) {
+                            double* __restrict__ inv_nu, int gal) {
   const int lane = threadIdx.x & 63;
   const int64_t c = c0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (c >= c1) return;
@@ -304,7 +337,7 @@ __global__ void k_col_norms(const double* __restrict__ pos, const double* __rest
   double s = 0.0;
   for (int i = lane; i < n; i += 64) {
     const double dx = (-b + (double)(i + 1) * h) - x;
-    const double g = exp(-(tt * (dx * dx)));
+    const double g = gauss_entry(tt, dx, h, gal);
     s = fma(g, g, s);
   }
 #pragma unroll
@@ -319,14 +352,14 @@ __global__ void k_col_norms(const double* __restrict__ pos, const double* __rest
 // Normalised side-matrix chunk: A[(c - c0) * n + i] = g_c[i] / nu_c  (column-contiguous).
 __global__ void k_gen_columns(const double* __restrict__ pos, const double* __restrict__ t2, int K, int d, int n,
                               double b, double h, int64_t c0, int64_t c1, const double* __restrict__ inv_nu,
-                              double* __restrict__ A) {
+                              double* __restrict__ A, int gal) {
   const int64_t total = (c1 - c0) * (int64_t)n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = c0 + e / n;
     const int i = (int)(e % n);
     const double x = pos[3 * (c / K) + d];
     const double dx = (-b + (double)(i + 1) * h) - x;
-    A[e] = exp(-(t2[c % K] * (dx * dx))) * inv_nu[c];
+    A[e] = gauss_entry(t2[c % K], dx, h, gal) * inv_nu[c];
   }
 }
 
@@ -1255,7 +1288,9 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
   rocblas_handle hb = (rocblas_handle)ctx->blas;
   RSD_CHECK(rocblas_set_stream(hb, s) == rocblas_status_success, RSD_E_HIP, "rocblas_set_stream failed");
 
-  const bool dense_gram = ctx->opt_gram == 2;
+  // Galerkin factors have no Toeplitz-times-Hankel Gram: they take the dense product
+  const int gal = t->galerkin ? 1 : 0;
+  const bool dense_gram = ctx->opt_gram == 2 || gal;
   // dense form: column chunks of the side matrix, at most ~1 GiB each
   const int64_t max_cols = std::max<int64_t>(TK, ((int64_t)1 << 27) / n / TK * TK);
   const int64_t chunk_cols = std::min<int64_t>(C, max_cols);
@@ -1295,7 +1330,7 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
     RSD_TIMED_LAUNCH(ctx, "gram", (k_gram_toeplitz<<<grid1d((int64_t)K * n), 256, 0, s>>>(t2d.p, K, n, h, Ttab.p)));
   for (int d = 0; d < 3; ++d) {
     RSD_TIMED_LAUNCH(ctx, "gen", (k_col_norms<<<div_up(C, 4), 256, 0, s>>>(d_pos, t2d.p, K, d, n, b, h, 0, C,
-                                                                             nu[d].p, inv_nu[d].p)));
+                                                                             nu[d].p, inv_nu[d].p, gal)));
     if (!dense_gram) {
       const dim3 gh((unsigned)div_up(2 * (int64_t)n - 1, 256), (unsigned)K);
       RSD_TIMED_LAUNCH(ctx, "gram", (k_gram_hankel<<<gh, 256, 0, s>>>(d_pos, t2d.p, inv_nu[d].p, K, d, n, b, h, N,
@@ -1308,7 +1343,7 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
     for (int64_t c0 = 0; c0 < C; c0 += chunk_cols) {
       const int64_t c1 = std::min(C, c0 + chunk_cols);
       RSD_TIMED_LAUNCH(ctx, "gen", (k_gen_columns<<<grid1d((c1 - c0) * n), 256, 0, s>>>(
-                                       d_pos, t2d.p, K, d, n, b, h, c0, c1, inv_nu[d].p, Abuf.p)));
+                                       d_pos, t2d.p, K, d, n, b, h, c0, c1, inv_nu[d].p, Abuf.p, gal)));
       OpKM op{Abuf.p, n, n};
       GemmShape g{};
       g.M = n; g.N = n; g.K = c1 - c0;
@@ -1357,6 +1392,7 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
     OpGauss ga{};
     ga.pos = d_pos; ga.t2 = t2d.p; ga.inv_nu = inv_nu[d].p; ga.K = K; ga.d = d; ga.n = n; ga.b = b; ga.h = h;
     ga.dim = (int)C;
+    ga.gal = gal;
     OpKM ub{U[d].p, ldu[d], rd};
     GemmShape g{};
     g.M = (int)C; g.N = rd; g.K = n; g.kper = ((n + TK - 1) / TK) * TK;

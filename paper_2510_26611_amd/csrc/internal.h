@@ -93,6 +93,7 @@ struct Context {
   int opt_t2c = 0;             // core slice SVDs: 0 auto, 1 Jacobi in LDS, 2 rocSOLVER
   int opt_eig = 0;             // Gram eigenvectors: 0 auto, 1 dense batched eigensolver, 2 subspace iteration
   int opt_svd = 0;             // small SVD of explicit-factor rank reduction: 0 auto, 1 gesvd, 2 gesdd, 3 Jacobi
+  int opt_factors = 0;         // build factors: 0 collocation at the nodes, 1 Galerkin cell averages
   int opt_gram = 0;            // Gram matrices: 0 auto, 1 Toeplitz x Hankel form, 2 dense matrix-core product
   int opt_short_waves = 0;     // short-range kernel: wavefronts per workgroup (0 = automatic)
   int opt_use_tuning = 1;      // apply shapes recorded by rsd_autotune to automatic calls
@@ -140,6 +141,7 @@ struct Tensor {
   double X0m[3] = {0, 0, 0};
   int nm[3] = {0, 0, 0};
   bool restricted = false;
+  bool galerkin = false;       // built from cell-average (Galerkin) factors
   int64_t R = 0;
   int nchunk = 0;              // ceil(R / kChunk); the kernels handle nchunk == 0
   int ranks[3] = {0, 0, 0};
@@ -187,6 +189,8 @@ struct ScoreIO {
 };
 rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io);
 rsd_status autotune(Context* ctx, const Tensor* t, const ScoreIO& io, rsd_tune_report* rep);
+// a molecule's own energy (score.hip)
+rsd_status launch_self_energy(Context* ctx, const Tensor* t, double* E_long, double* E_short);
 // posing search (score.hip)
 rsd_status launch_contact(Context* ctx, const Tensor* t, const double* lig_positions, int L, const double* dirs,
                           int64_t U, const double* quats, int64_t Q, const double xP[3], double sigma, double gap,

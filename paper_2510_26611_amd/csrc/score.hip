@@ -1415,4 +1415,159 @@ rsd_status launch_orbit_minima(Context* ctx, const double* E, const uint8_t* fla
   return RSD_OK;
 }
 
+// ---------------------------------------------------------------- a molecule's own energy (Prop. 3.2)
+// E_long = 1/2 sum_j z_j (P_l(x_j) - z_j W0), W0 = sum_{k < K_long} w_k (the long-range reference
+// kernel at distance zero: the atom's own long-range term), with P_l the trilinear value of the
+// tensor at x_j; E_short = 1/2 sum_j z_j sum_{m != j, d^2 < r_c^2} z_m sum_{k >= K_long} w_k
+// exp(-t_k^2 d^2).  Per-atom terms go to e_long[j], e_short[j] and are summed by one workgroup
+// in a fixed order, so the result does not depend on scheduling.
+struct SelfParams {
+  const double* __restrict__ F;
+  int64_t mode_stride, chunk_stride;
+  int nchunk;
+  double X0[3];
+  int nm2[3];
+  double inv_h, W0;
+  const double4* __restrict__ atoms;
+  int64_t N;
+  const double* __restrict__ tab;     // short-range t_k^2 [kMaxTerms], then w_k [kMaxTerms]
+  int S;
+  double rc2;
+  double* __restrict__ e_long;
+  double* __restrict__ e_short;
+};
+
+// one wavefront per atom: lane l owns column l of every rank chunk
+__global__ __launch_bounds__(256) void k_self_long(const SelfParams a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= a.N) return;
+  const double4 x = a.atoms[j];
+  const double xs[3] = {x.x, x.y, x.z};
+  int i[3];
+  double f[3];
+  for (int d = 0; d < 3; ++d) {
+    const double sd = (xs[d] - a.X0[d]) * a.inv_h;
+    int id = (int)floor(sd);
+    id = id < 0 ? 0 : (id > a.nm2[d] ? a.nm2[d] : id);
+    i[d] = id;
+    f[d] = sd - (double)id;
+  }
+  double v = 0.0;
+  for (int c = 0; c < a.nchunk; ++c) {
+    const double* base = a.F + (int64_t)c * a.chunk_stride + lane;
+    double prod = 1.0;
+    for (int d = 0; d < 3; ++d) {
+      const double* row = base + d * a.mode_stride + (int64_t)i[d] * kChunk;
+      const double lo = row[0], hi = row[kChunk];
+      prod *= fma(f[d], hi - lo, lo);
+    }
+    v += prod;
+  }
+  v = wave_sum(v);
+  if (lane == 0) a.e_long[j] = x.w * (v - x.w * a.W0);
+}
+
+// one thread per atom, protein atoms staged through LDS in tiles of 256
+__global__ __launch_bounds__(256) void k_self_short(const SelfParams a) {
+  __shared__ double4 s_at[256];
+  __shared__ double s_tab[2 * kMaxTerms];
+  const int tid = threadIdx.x;
+  for (int k = tid; k < 2 * kMaxTerms; k += 256) s_tab[k] = a.tab[k];
+  const int64_t j = (int64_t)blockIdx.x * 256 + tid;
+  const double4 x = j < a.N ? a.atoms[j] : make_double4(0.0, 0.0, 0.0, 0.0);
+  double acc = 0.0;
+  for (int64_t m0 = 0; m0 < a.N; m0 += 256) {
+    __syncthreads();
+    if (m0 + tid < a.N) s_at[tid] = a.atoms[m0 + tid];
+    __syncthreads();
+    const int cnt = (int)(a.N - m0 < 256 ? a.N - m0 : 256);
+    if (j < a.N) {
+      for (int k = 0; k < cnt; ++k) {
+        if (m0 + k == j) continue;
+        const double4 p = s_at[k];
+        const double dx = x.x - p.x, dy = x.y - p.y, dz = x.z - p.z;
+        const double d2 = (dx * dx + dy * dy) + dz * dz;
+        if (d2 < a.rc2) {
+          double g = 0.0;
+          for (int q = 0; q < a.S; ++q) g = fma(s_tab[kMaxTerms + q], exp(-(s_tab[q] * d2)), g);
+          acc = fma(p.w, g, acc);
+        }
+      }
+    }
+  }
+  if (j < a.N) a.e_short[j] = x.w * acc;
+}
+
+// out[0] = 1/2 sum e_long, out[1] = 1/2 sum e_short: strided partial sums, then a fixed tree
+__global__ __launch_bounds__(1024) void k_self_sum(const double* __restrict__ e_long,
+                                                   const double* __restrict__ e_short, int64_t N,
+                                                   double* __restrict__ out) {
+  __shared__ double s[2][1024];
+  const int tid = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int64_t j = tid; j < N; j += 1024) {
+    a += e_long[j];
+    b += e_short[j];
+  }
+  s[0][tid] = a;
+  s[1][tid] = b;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (tid < w) {
+      s[0][tid] += s[0][tid + w];
+      s[1][tid] += s[1][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = 0.5 * s[0][0];
+    out[1] = 0.5 * s[1][0];
+  }
+}
+
+rsd_status launch_self_energy(Context* ctx, const Tensor* t, double* E_long, double* E_short) {
+  hipStream_t s = ctx->stream;
+  const int64_t N = t->N;
+  void* ws = nullptr;
+  RSD_TRY(ctx->workspace(sizeof(double) * (size_t)(2 * N + 2), &ws));
+  double* e = (double*)ws;
+  SelfParams a{};
+  a.F = t->F;
+  a.chunk_stride = (int64_t)t->n * kChunk;
+  a.mode_stride = (int64_t)t->nchunk * a.chunk_stride;
+  a.nchunk = t->nchunk;
+  for (int d = 0; d < 3; ++d) {
+    a.X0[d] = t->X0m[d];
+    a.nm2[d] = t->nm[d] - 2;
+  }
+  a.inv_h = t->inv_h;
+  double tk[kMaxTerms], wk[kMaxTerms];
+  sinc_table(t->sp, tk, wk);
+  double W0 = 0.0;
+  for (int k = 0; k < t->sp.K_long; ++k) W0 += wk[k];
+  a.W0 = W0;
+  a.atoms = t->atoms;
+  a.N = N;
+  a.tab = t->short_tab;
+  a.S = t->shrt.S;
+  a.rc2 = t->sp.r_cut * t->sp.r_cut;
+  a.e_long = e;
+  a.e_short = e + N;
+  RSD_CHECK((N + 3) / 4 <= 0x7fffffffLL, RSD_E_UNSUPPORTED, "too many atoms");
+  if (t->nchunk > 0) {
+    RSD_TIMED_LAUNCH(ctx, "self", (k_self_long<<<(unsigned)((N + 3) / 4), 256, 0, s>>>(a)));
+  } else {
+    RSD_HIP(hipMemsetAsync(a.e_long, 0, sizeof(double) * (size_t)N, s));
+  }
+  RSD_TIMED_LAUNCH(ctx, "self", (k_self_short<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(a)));
+  RSD_TIMED_LAUNCH(ctx, "self", (k_self_sum<<<1, 1024, 0, s>>>(a.e_long, a.e_short, N, e + 2 * N)));
+  double out[2];
+  RSD_HIP(hipMemcpyAsync(out, e + 2 * N, sizeof(out), hipMemcpyDeviceToHost, s));
+  RSD_HIP(hipStreamSynchronize(s));
+  *E_long = out[0];
+  *E_short = out[1];
+  return RSD_OK;
+}
+
 }  // namespace rsd

@@ -159,6 +159,13 @@ class Tensor:
         _check(_lib.lib().rsd_tensor_restrict(ctx.handle, self.handle, lo3, hi3, float(eps), C.byref(out)))
         return Tensor(ctx, out)
 
+    def self_energy(self, ctx: "Context" = None):
+        """rsd_self_energy: (E_long, E_short) of the molecule itself (Prop. 3.2)."""
+        ctx = ctx or self.ctx
+        el, es = C.c_double(), C.c_double()
+        _check(_lib.lib().rsd_self_energy(ctx.handle, self.handle, C.byref(el), C.byref(es)))
+        return el.value, es.value
+
     def free(self) -> None:
         if getattr(self, "handle", None):
             _lib.lib().rsd_tensor_free(self.handle)
