@@ -91,6 +91,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--score-mode", type=int, default=0, help="0 automatic, 1 fused per-pose, 2 chunk-major")
     ap.add_argument("--no-autotune", action="store_true", help="skip the launch-shape tuner before timing")
+    ap.add_argument("--overlap", type=int, default=0, choices=[0, 1],
+                    help="1: the short-range kernel runs on a second stream beside the long-range one")
     ap.add_argument("--tune-poses", type=int, default=16384, help="poses of the tuner's sample")
     ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "site", "ppiem"],
                     help="cfg2 (default): one 5,000-atom protein, 1e6 poses; cfg1: 200 atoms, 128 poses; "
@@ -148,6 +150,7 @@ def main() -> int:
     stream = torch.cuda.current_stream(dev)
     ctx = rs.Context(0, stream=stream.cuda_stream)
     ctx.set_option("score_mode", args.score_mode)
+    ctx.set_option("overlap", args.overlap)
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     d_z, d_x = to(wl.protein_charges), to(wl.protein_positions)
     d_lz, d_lx, d_q, d_t = to(wl.ligand_charges), to(wl.ligand_positions), to(wl.quats), to(wl.trans)
@@ -221,7 +224,7 @@ def main() -> int:
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic},
         "breakdown": {k: {"launches": v[0], "ms_per_step": v[1] / args.steps} for k, v in kt.items() if v[0]},
-        "autotune": tune,
+        "autotune": tune, "short_range_on_second_stream": bool(args.overlap),
         "score_host_arrays_poses_per_s": P / host_io_s,
         "score_only_poses_per_s": P / (score_ms / 1e3),
         "accept_fraction": float(np.mean(flags & 1)),
@@ -356,6 +359,7 @@ def run_site(args, rs, configs, torch, np, dev) -> int:
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     d_lz, d_lx, d_q, d_t = to(wl.ligand_charges), to(wl.ligand_positions), to(quats), to(trans)
     ctx = rs.Context(0)
+    ctx.set_option("overlap", args.overlap)
     tg = rs.build_rs_tensor(ctx, to(wl.protein_charges), to(wl.protein_positions), cfg.n, cfg.b,
                             rs.Sinc.from_config(cfg))
     out = {k: dict(E=torch.empty(P, dtype=torch.float64, device=dev), flags=torch.empty(P, dtype=torch.uint8, device=dev),
@@ -391,7 +395,8 @@ def run_site(args, rs, configs, torch, np, dev) -> int:
     ms_glob = timed(step_global) * 1e3
     ctx.set_timing(True)
     ms_loc = timed(step_local) * 1e3
-    kt = {k: ctx.kernel_time(k) for k in ("restrict", "core", "t2c", "assemble", "cells", "long", "short", "score")}
+    kt = {k: ctx.kernel_time(k) for k in ("restrict", "qr", "svd", "core", "t2c", "assemble", "cells", "long", "short",
+                                          "score")}
     ctx.set_timing(False)
     fg, fl = out["global"]["flags"].cpu().numpy(), out["local"]["flags"].cpu().numpy()
     cg, cl = out["global"]["counts"].cpu().numpy(), out["local"]["counts"].cpu().numpy()
@@ -411,11 +416,12 @@ def run_site(args, rs, configs, torch, np, dev) -> int:
                    "parallelism": "single GPU, data-parallel over poses"},
         "global_tensor_poses_per_s": P / (ms_glob / 1e3), "global_ms": ms_glob,
         "local_ms_including_restriction": ms_loc,
-        "restriction_ms": sum(kt[k][1] for k in ("restrict", "core", "t2c", "assemble", "cells")) / args.steps,
+        "restriction_kernels_ms": sum(kt[k][1] for k in ("restrict", "qr", "svd", "core", "t2c", "assemble", "cells"))
+        / args.steps,
         "roofline": {"kernel": dom, "kernel_ms": long_ms, "bound": "hbm", "achieved": alg / (long_ms / 1e3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / (long_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                      "traffic": None},
-        "autotune": tune,
+        "autotune": tune, "short_range_on_second_stream": bool(args.overlap),
         "in_box_fraction": float(np.mean(ok)),
         "flags_equal_in_box": bool(np.array_equal(fg[ok], fl[ok])), "counts_equal": bool(np.array_equal(cg, cl)),
         "max_abs_dE_in_box": float(np.max(np.abs(Eg[ok] - El[ok]))) if ok.any() else None,
@@ -446,6 +452,7 @@ def run_ppiem(args, rs, configs, torch, np, dev) -> int:
     d_lz, d_lx, d_dirs, d_q = to(wl.ligand_charges), to(wl.ligand_positions), to(dirs), to(quats)
     d_off, d_idx = to(off.astype(np.int32)), to(idx.astype(np.int32))
     ctx = rs.Context(0)
+    ctx.set_option("overlap", args.overlap)
     t = rs.build_rs_tensor(ctx, to(wl.protein_charges), to(wl.protein_positions), cfg.n, cfg.b, rs.Sinc.from_config(cfg))
     centre = ppiem.tensor_centre(t)
     cp0 = ppiem.contact_poses(ctx, t, d_lx, d_dirs, d_q, cfg.sigma, centre=centre)
@@ -498,7 +505,7 @@ def run_ppiem(args, rs, configs, torch, np, dev) -> int:
                    "protein_atoms": cfg.N, "ligand_atoms": cfg.L, "grid_n": cfg.n, "canonical_rank": R,
                    "parallelism": "single GPU, data-parallel over poses"},
         "roofline": roof,
-        "autotune": tune,
+        "autotune": tune, "short_range_on_second_stream": bool(args.overlap),
         "contact_ms": kt["contact"][1] / args.steps,
         "rho_range_A": [float(np.min(rho)), float(np.max(rho))],
         "accept_fraction": float(np.mean(fl & 1)),

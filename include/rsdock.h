@@ -316,6 +316,10 @@ void rsd_tensor_free(rsd_tensor* t);
  *                     2 dense product of the generated side matrix on matrix cores (O(n^2 N K))
  *   "short_waves"     wavefronts (poses) per workgroup of the short-range kernel: 0 automatic,
  *                     1, 2 or 4 (must fit 64 KB of LDS for the ligand)
+ *   "overlap"         1: in chunk-major scoring the short-range kernel runs on a second stream
+ *                     of the context beside the long-range kernel (joined before the results
+ *                     are combined); 0 (default): one stream.  The long-range gathers slow
+ *                     down by about as much as the short range saves, so the default is off
  *   "use_tuning"      1 (default): calls whose three launch-shape options above are automatic
  *                     take the shape rsd_autotune recorded for their workload; 0: ignore it
  * Errors: RSD_E_INVALID for an unknown name or value. */

@@ -261,6 +261,8 @@ static void context_destroy(Context* ctx) {
   ctx->dev_free(ctx->ws, ctx->ws_bytes);
   ctx->ws = nullptr;
   if (ctx->blas) rocblas_destroy_handle((rocblas_handle)ctx->blas);
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   for (int i = 0; i < 2; ++i) {
     if (ctx->aux_stream[i]) (void)hipStreamSynchronize(ctx->aux_stream[i]);
     if (ctx->aux_blas[i]) rocblas_destroy_handle((rocblas_handle)ctx->aux_blas[i]);
@@ -1028,6 +1030,11 @@ rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t va
   if (std::strcmp(name, "use_tuning") == 0) {
     RSD_CHECK(value == 0 || value == 1, RSD_E_INVALID, "use_tuning must be 0 or 1");
     ctx->opt_use_tuning = (int)value;
+    return RSD_OK;
+  }
+  if (std::strcmp(name, "overlap") == 0) {
+    RSD_CHECK(value == 0 || value == 1, RSD_E_INVALID, "overlap must be 0 or 1");
+    ctx->opt_overlap = (int)value;
     return RSD_OK;
   }
   if (std::strcmp(name, "factors") == 0) {

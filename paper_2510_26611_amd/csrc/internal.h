@@ -85,6 +85,7 @@ struct Context {
   // modes' eigensolvers concurrently on the context stream and these (lazy)
   hipStream_t aux_stream[2] = {nullptr, nullptr};
   void* aux_blas[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;   // scoring: short range on aux_stream[0] (lazy)
   int live_tensors = 0;        // tensors made with this context and not yet freed
   bool closing = false;        // rsd_context_free was called; released with the last tensor
   // tuning options (rsd_context_set_option)
@@ -97,6 +98,7 @@ struct Context {
   int opt_gram = 0;            // Gram matrices: 0 auto, 1 Toeplitz x Hankel form, 2 dense matrix-core product
   int opt_short_waves = 0;     // short-range kernel: wavefronts per workgroup (0 = automatic)
   int opt_use_tuning = 1;      // apply shapes recorded by rsd_autotune to automatic calls
+  int opt_overlap = 0;         // chunk-major scoring: short range on a second stream beside the long range
   // launch shapes recorded by rsd_autotune: (n, nchunk, N, L, grad) -> (mode, ppw, short waves)
   std::map<std::tuple<int, int, int64_t, int, int>, std::array<int, 3>> tuned;
   bool timing = false;

@@ -939,14 +939,45 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   const size_t lds2 = long_lds(L, ppw, grad);
   const unsigned gc = (unsigned)std::min<int64_t>((P + 255) / 256, 65536);
   RSD_TRY(allow_lds(grad ? (const void*)k_long<true> : (const void*)k_long<false>, lds2));
+  // The short-range kernel (FP64 ALU) and the long-range gathers (bound by the L2 return
+  // path) use different units: with overlap on, the short range runs on a second stream
+  // beside the long range, forked after the ligand preparation and joined before the
+  // combine.
+  hipStream_t s_short = s;
+  if (ctx->opt_overlap) {
+    RSD_TRY(ctx->aux_streams());
+    if (!ctx->ev_fork) RSD_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    if (!ctx->ev_join) RSD_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    s_short = ctx->aux_stream[0];
+    RSD_HIP(hipEventRecord(ctx->ev_fork, s));
+    RSD_HIP(hipStreamWaitEvent(s_short, ctx->ev_fork, 0));
+  }
+  {
+    struct StreamGuard {   // the timer of the short-range launch records on its stream
+      Context* c;
+      hipStream_t saved;
+      ~StreamGuard() { c->stream = saved; }
+    } sg{ctx, s};
+    ctx->stream = s_short;
+    if (grad) {
+      RSD_TIMED_LAUNCH(ctx, "short", (k_score<true, false><<<g1, b1, lds1, s_short>>>(a)));
+    } else {
+      RSD_TIMED_LAUNCH(ctx, "short", (k_score<false, false><<<g1, b1, lds1, s_short>>>(a)));
+    }
+  }
   if (grad) {
-    RSD_TIMED_LAUNCH(ctx, "short", (k_score<true, false><<<g1, b1, lds1, s>>>(a)));
     RSD_TIMED_LAUNCH(ctx, "long", (k_long<true><<<g2, 256, lds2, s>>>(lp)));
+  } else {
+    RSD_TIMED_LAUNCH(ctx, "long", (k_long<false><<<g2, 256, lds2, s>>>(lp)));
+  }
+  if (s_short != s) {
+    RSD_HIP(hipEventRecord(ctx->ev_join, s_short));
+    RSD_HIP(hipStreamWaitEvent(s, ctx->ev_join, 0));
+  }
+  if (grad) {
     RSD_TIMED_LAUNCH(ctx, "combine", (k_combine<true><<<gc, 256, 0, s>>>(lp.part, t->nchunk, P, a.es, a.gs, io.flags,
                                                                            io.E, io.El, io.grads)));
   } else {
-    RSD_TIMED_LAUNCH(ctx, "short", (k_score<false, false><<<g1, b1, lds1, s>>>(a)));
-    RSD_TIMED_LAUNCH(ctx, "long", (k_long<false><<<g2, 256, lds2, s>>>(lp)));
     RSD_TIMED_LAUNCH(ctx, "combine", (k_combine<false><<<gc, 256, 0, s>>>(lp.part, t->nchunk, P, a.es, a.gs,
                                                                             io.flags, io.E, io.El, nullptr)));
   }

@@ -98,3 +98,24 @@ def test_autotune_argument_errors(env):
     assert e.value.code == -1
     with pytest.raises(rs.RsdError):
         ctx.set_option("short_waves", 3)
+
+
+@pytest.mark.parametrize("grads", [False, True])
+def test_short_range_on_a_second_stream_is_bitwise_the_same(env, grads):
+    """Option overlap: the short-range kernel on a second stream, joined before the combine,
+    gives the same bits as one stream (same kernels, same inputs), and stays at parity."""
+    rs, torch, ctx, cfg, wl, F, t, dev = env
+    ctx.set_option("score_mode", 2)
+    try:
+        ctx.set_option("overlap", 0)
+        one = _score(rs, torch, ctx, t, dev, cfg.sigma, grads)
+        ctx.set_option("overlap", 1)
+        two = _score(rs, torch, ctx, t, dev, cfg.sigma, grads)
+        again = _score(rs, torch, ctx, t, dev, cfg.sigma, grads)
+    finally:
+        ctx.set_option("overlap", 0)
+        ctx.set_option("score_mode", 0)
+    for k in one:
+        assert np.array_equal(one[k], two[k], equal_nan=True), k
+        assert np.array_equal(two[k], again[k], equal_nan=True), k
+    assert_parity(two, oracle_score(cfg, wl, F, wl.quats, wl.trans, grad=grads), grad=grads, label="overlap")
