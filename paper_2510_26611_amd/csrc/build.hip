@@ -578,36 +578,42 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* __restrict__ S
   for (; sweep < kJacobiMaxSweeps && n > 1; ++sweep) {
     if (tid == 0) s_rot = 0;
     __syncthreads();
+    // four lanes per column pair, each over every fourth row (loads unrolled so that several
+    // are in flight), the three sums combined within the quad: a 64-lane reduction per pair
+    // or one lane per pair leaves each round waiting on LDS latency
     for (int round = 0; round < np - 1; ++round) {
-      for (int k = wv; k < np / 2; k += 4) {
+      for (int k4 = tid; k4 < (np / 2) * 4; k4 += 256) {
+        const int k = k4 >> 2, part = k4 & 3;
         const int pa = rr_player(k, round, np), pb = rr_player(np - 1 - k, round, np);
         const int p = min(pa, pb), q = max(pa, pb);
         if (q >= n) continue;
         double* ap = sA + p * m;
         double* aq = sA + q * m;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int row = lane; row < m; row += 64) {
+#pragma unroll 8
+        for (int row = part; row < m; row += 4) {
           const double x = ap[row], y = aq[row];
           al = fma(x, x, al);
           be = fma(y, y, be);
           ga = fma(x, y, ga);
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          al += __shfl_xor(al, off, 64);
-          be += __shfl_xor(be, off, 64);
-          ga += __shfl_xor(ga, off, 64);
-        }
+        al += __shfl_xor(al, 1, 64);
+        be += __shfl_xor(be, 1, 64);
+        ga += __shfl_xor(ga, 1, 64);
+        al += __shfl_xor(al, 2, 64);
+        be += __shfl_xor(be, 2, 64);
+        ga += __shfl_xor(ga, 2, 64);
         if (ga != 0.0 && fmin(al, be) > skip && fabs(ga) > tol * sqrt(al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-          for (int row = lane; row < m; row += 64) {
+#pragma unroll 8
+          for (int row = part; row < m; row += 4) {
             const double x = ap[row], y = aq[row];
             ap[row] = cs * x - sn * y;
             aq[row] = sn * x + cs * y;
           }
-          if (lane == 0) s_rot = 1;
+          s_rot = 1;
         }
       }
       __syncthreads();
@@ -639,6 +645,7 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* __restrict__ S
     const double* scol = Sc + (int64_t)bcol * m;
     const double* u = sA + q * m;
     double w = 0.0;
+#pragma unroll 8
     for (int a = 0; a < m; ++a) w = fma(scol[a], u[a], w);
     const double sq = sv[(int64_t)c * n + q];
     vt[(int64_t)c * n * n + q + (int64_t)bcol * n] = sq > 0.0 ? w / sq : 0.0;
