@@ -209,6 +209,86 @@ static rsd_status check_protein(const std::vector<double>& z, const std::vector<
   return RSD_OK;
 }
 
+// The short-range kernel g(x) = sum_k w_k exp(-t_k^2 x), x = d^2, as piecewise polynomials:
+// intervals of width d1 = 0.5 / t_max^2 on [0, x1) and of width d2 = 0.5 / t_c^2 on [x1, r_c^2],
+// where x1 = 25 A^2 and t_c^2 is the largest t_k^2 whose term can still reach e^-45 of the
+// widest one beyond x1 (the others are below 1e-18 of g there).  On each interval g is
+// interpolated at the 8 Chebyshev points (values in long double), and the interpolant is
+// stored as monomial coefficients in s in [-1, 1].  With t^2 times the width at most 1/2 the
+// interpolation error of every term is below about 3e-12 of its size; the table is checked
+// against the exact sum at 16 points per interval and discarded (the kernels then evaluate
+// the exponentials) if any relative error exceeds 1e-11, or if it would exceed 8 MB.
+static bool build_short_poly(const ShortTable& st, double rc2, std::vector<double>* coef, int* n1, double* x1,
+                             double* d1, double* d2) {
+  coef->clear();
+  if (st.S <= 0 || !(rc2 > 0.0)) return false;
+  double amax = 0.0, amin = st.t2[0];
+  for (int k = 0; k < st.S; ++k) {
+    amax = std::max(amax, st.t2[k]);
+    amin = std::min(amin, st.t2[k]);
+  }
+  if (!(amax > 0.0)) return false;
+  const double X1 = std::min(25.0, rc2);
+  double ac = amin;
+  for (int k = 0; k < st.S; ++k)
+    if ((st.t2[k] - amin) * X1 <= 45.0) ac = std::max(ac, st.t2[k]);
+  *x1 = X1;
+  *d1 = 0.5 / amax;
+  *d2 = 0.5 / std::max(ac, 1e-300);
+  *n1 = (int)std::ceil(X1 / *d1);
+  const double n2d = rc2 > X1 ? std::ceil((rc2 - X1) / *d2) + 1.0 : 0.0;
+  const double total = (double)*n1 + n2d;
+  if (total * kPolyCoef * sizeof(double) > 8.0 * 1024 * 1024) return false;
+  const int n = (int)total;
+  coef->resize((size_t)n * kPolyCoef);
+  auto g = [&](double x) {   // terms in double, summed in long double
+    long double s = 0.0L;
+    for (int k = 0; k < st.S; ++k) s += (long double)(st.w[k] * std::exp(-st.t2[k] * x));
+    return s;
+  };
+  // Chebyshev polynomials T_0..T_7 in the power basis
+  long double T[kPolyCoef][kPolyCoef] = {};
+  T[0][0] = 1.0L;
+  T[1][1] = 1.0L;
+  for (int m = 2; m < kPolyCoef; ++m)
+    for (int j = 0; j < kPolyCoef; ++j) T[m][j] = (j > 0 ? 2.0L * T[m - 1][j - 1] : 0.0L) - T[m - 2][j];
+  const long double pi = 3.141592653589793238462643383279502884L;
+  long double node[kPolyCoef], cosm[kPolyCoef][kPolyCoef];
+  for (int j = 0; j < kPolyCoef; ++j) {
+    node[j] = std::cos(pi * (j + 0.5L) / kPolyCoef);
+    for (int m = 0; m < kPolyCoef; ++m) cosm[m][j] = std::cos(pi * m * (j + 0.5L) / kPolyCoef);
+  }
+  double worst = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double a = i < *n1 ? i * *d1 : X1 + (i - *n1) * *d2;
+    const double w = i < *n1 ? *d1 : *d2;
+    long double f[kPolyCoef], c[kPolyCoef];
+    for (int j = 0; j < kPolyCoef; ++j) f[j] = g((double)((long double)a + (long double)w * (node[j] + 1.0L) * 0.5L));
+    for (int m = 0; m < kPolyCoef; ++m) {
+      long double sm = 0.0L;
+      for (int j = 0; j < kPolyCoef; ++j) sm += f[j] * cosm[m][j];
+      c[m] = sm * 2.0L / kPolyCoef;
+    }
+    c[0] *= 0.5L;
+    long double p[kPolyCoef] = {};
+    for (int m = 0; m < kPolyCoef; ++m)
+      for (int j = 0; j < kPolyCoef; ++j) p[j] += c[m] * T[m][j];
+    for (int j = 0; j < kPolyCoef; ++j) (*coef)[(size_t)i * kPolyCoef + j] = (double)p[j];
+    for (int q = 0; q < 16; ++q) {   // check at points spread over the interval
+      const double s = -1.0 + 2.0 * (q + 0.5) / 16.0;
+      double v = (*coef)[(size_t)i * kPolyCoef + kPolyCoef - 1];
+      for (int j = kPolyCoef - 2; j >= 0; --j) v = std::fma(v, s, (*coef)[(size_t)i * kPolyCoef + j]);
+      const long double ex = g(a + w * (s + 1.0) * 0.5);
+      if (ex > 0.0L) worst = std::max(worst, (double)std::fabs(((long double)v - ex) / ex));
+    }
+  }
+  if (!(worst <= 1e-11)) {
+    coef->clear();
+    return false;
+  }
+  return true;
+}
+
 // Create the tensor shell: grid constants, short-range table, protein copies, cell list.
 static rsd_status tensor_common(Context* ctx, Tensor* t, int32_t n, double b, const rsd_sinc_params* sp,
                                 std::vector<double>&& z, std::vector<double>&& pos, double** d_z,
@@ -237,6 +317,30 @@ static rsd_status tensor_common(Context* ctx, Tensor* t, int32_t n, double b, co
   }
   RSD_TRY(ctx->dev_alloc((void**)&t->short_tab, sizeof(tab)));
   RSD_HIP(hipMemcpy(t->short_tab, tab, sizeof(tab), hipMemcpyHostToDevice));
+  if (ctx->opt_short_poly) {
+    // one table per quadrature and cutoff, kept by the context and shared by its tensors
+    const auto key = std::make_tuple(sp->M, sp->K_long, sp->h_M, sp->L_s, sp->r_cut);
+    auto it = ctx->poly_cache.find(key);
+    if (it == ctx->poly_cache.end()) {
+      Context::Poly pc{};
+      std::vector<double> coef;
+      double d1 = 0.0, d2 = 0.0;
+      if (build_short_poly(t->shrt, sp->r_cut * sp->r_cut, &coef, &pc.n1, &pc.x1, &d1, &d2)) {
+        pc.inv_d1 = 1.0 / d1;
+        pc.inv_d2 = 1.0 / d2;
+        pc.bytes = sizeof(double) * coef.size();
+        RSD_TRY(ctx->dev_alloc((void**)&pc.p, pc.bytes));
+        RSD_HIP(hipMemcpy(pc.p, coef.data(), pc.bytes, hipMemcpyHostToDevice));
+      }
+      it = ctx->poly_cache.emplace(key, pc).first;
+    }
+    const Context::Poly& pc = it->second;
+    t->short_poly = pc.p;
+    t->poly_n1 = pc.n1;
+    t->poly_x1 = pc.x1;
+    t->poly_inv_d1 = pc.inv_d1;
+    t->poly_inv_d2 = pc.inv_d2;
+  }
   // device copies of the protein (freed by the caller of tensor_common)
   const size_t N = (size_t)t->N;
   RSD_TRY(ctx->dev_alloc((void**)d_z, sizeof(double) * (N ? N : 1)));
@@ -258,6 +362,9 @@ static void context_destroy(Context* ctx) {
   }
   ctx->pending.clear();
   ctx->block_trim();
+  for (auto& kv : ctx->poly_cache)
+    if (kv.second.p) ctx->dev_free(kv.second.p, kv.second.bytes);
+  ctx->poly_cache.clear();
   ctx->dev_free(ctx->ws, ctx->ws_bytes);
   ctx->ws = nullptr;
   if (ctx->blas) rocblas_destroy_handle((rocblas_handle)ctx->blas);
@@ -1030,6 +1137,11 @@ rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t va
   if (std::strcmp(name, "use_tuning") == 0) {
     RSD_CHECK(value == 0 || value == 1, RSD_E_INVALID, "use_tuning must be 0 or 1");
     ctx->opt_use_tuning = (int)value;
+    return RSD_OK;
+  }
+  if (std::strcmp(name, "short_poly") == 0) {
+    RSD_CHECK(value == 0 || value == 1, RSD_E_INVALID, "short_poly must be 0 or 1");
+    ctx->opt_short_poly = (int)value;
     return RSD_OK;
   }
   if (std::strcmp(name, "overlap") == 0) {

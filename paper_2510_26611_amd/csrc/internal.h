@@ -49,6 +49,7 @@ void clear_error();
 // kChunk doubles of one row are one contiguous 512-byte segment and rows i and
 // i+1 of a chunk are adjacent.  Columns beyond R are zero.
 constexpr int kChunk = 64;
+constexpr int kPolyCoef = 8;       // coefficients per interval of the short-range polynomial table
 constexpr int kMaxTerms = 64;   // M + 1 <= 64
 constexpr int kMaxLigand = 896;   // keeps one wave's LDS within 64 KB
 
@@ -99,6 +100,7 @@ struct Context {
   int opt_short_waves = 0;     // short-range kernel: wavefronts per workgroup (0 = automatic)
   int opt_use_tuning = 1;      // apply shapes recorded by rsd_autotune to automatic calls
   int opt_overlap = 0;         // chunk-major scoring: short range on a second stream beside the long range
+  int opt_short_poly = 1;      // tensors made with this context carry the short-range polynomial table
   // launch shapes recorded by rsd_autotune: (n, nchunk, N, L, grad) -> (mode, ppw, short waves)
   std::map<std::tuple<int, int, int64_t, int, int>, std::array<int, 3>> tuned;
   bool timing = false;
@@ -110,6 +112,15 @@ struct Context {
   // first), so releasing needs no device-wide wait as hipFree would.  Cached blocks count as
   // in use and are freed when an allocation would exceed the budget or fail.
   std::vector<std::pair<void*, size_t>> block_cache;
+
+  // short-range polynomial tables by (M, K_long, h_M, L_s, r_cut), shared by the tensors
+  struct Poly {
+    double* p = nullptr;
+    size_t bytes = 0;
+    int n1 = 0;
+    double x1 = 0.0, inv_d1 = 0.0, inv_d2 = 0.0;
+  };
+  std::map<std::tuple<int, int, double, double, double>, Poly> poly_cache;
 
   rsd_status dev_alloc(void** p, size_t bytes);
   void dev_free(void* p, size_t bytes);
@@ -157,6 +168,12 @@ struct Tensor {
   CellGrid cells{};
   double* short_tab = nullptr; // device copy of ShortTable t2[], w[] (2 * kMaxTerms)
   ShortTable shrt{};
+  // the short-range kernel g(x) = sum_k w_k exp(-t_k^2 x) as piecewise polynomials in x = d^2
+  // (kPolyCoef monomial coefficients per interval on [-1, 1]); owned by the context's cache,
+  // null when not built
+  double* short_poly = nullptr;
+  int poly_n1 = 0;             // intervals of width poly_d1 on [0, poly_x1), then of width poly_d2
+  double poly_x1 = 0.0, poly_inv_d1 = 0.0, poly_inv_d2 = 0.0;
   std::vector<double> host_charges;    // kept for save/load
   std::vector<double> host_positions;
   size_t bytes() const;

@@ -40,6 +40,8 @@ struct PairG {                // queued pair with what the gradient needs
   int l, pad;
 };
 
+static_assert(kPolyCoef == 8, "the short-range table lookup reads two double4 per interval");
+
 struct ScoreParams {
   const double* __restrict__ F;
   int64_t mode_stride;        // nchunk * n * kChunk
@@ -55,6 +57,9 @@ struct ScoreParams {
   const double* __restrict__ t2;   // short-range t_k^2
   const double* __restrict__ w;    // short-range weights
   int S;
+  const double* __restrict__ poly; // short-range polynomial table (energies only), or null
+  double poly_x1, poly_inv_d1, poly_inv_d2;
+  int poly_n1;
   double rc2, sig2, reach;          // reach = max(r_cut, vdw_min)
   const double4* __restrict__ lig;  // centred ligand (u_x, u_y, u_z, zeta)
   const double* __restrict__ rlig;  // max_l |u_l|
@@ -360,12 +365,30 @@ __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4*
       if (lane < m) {
         const Pair e = q[(qh + lane) & (kQueue - 1)];
         double gs = 0.0, dg = 0.0;
+        if (!GRAD && a.poly) {
+          // g(d^2) from the polynomial table: interval and position s in [-1, 1]
+          const bool near = e.d2 < a.poly_x1;
+          const double xs = near ? e.d2 * a.poly_inv_d1 : (e.d2 - a.poly_x1) * a.poly_inv_d2;
+          const int ii = (int)xs;
+          const double sv = 2.0 * (xs - (double)ii) - 1.0;
+          const double4* c = reinterpret_cast<const double4*>(a.poly + (int64_t)(near ? ii : a.poly_n1 + ii) * kPolyCoef);
+          const double4 c0 = c[0], c1 = c[1];
+          double v = c1.w;
+          v = fma(v, sv, c1.z);
+          v = fma(v, sv, c1.y);
+          v = fma(v, sv, c1.x);
+          v = fma(v, sv, c0.w);
+          v = fma(v, sv, c0.z);
+          v = fma(v, sv, c0.y);
+          gs = fma(v, sv, c0.x);
+        } else {
 #pragma unroll 2
-        for (int k = 0; k < a.S; ++k) {
-          const double t2 = s_tab[k], wk = s_tab[kMaxTerms + k];
-          const double ex = exp(-(t2 * e.d2));
-          gs = fma(wk, ex, gs);
-          if (GRAD) dg = fma(wk * (-2.0 * t2), ex, dg);
+          for (int k = 0; k < a.S; ++k) {
+            const double t2 = s_tab[k], wk = s_tab[kMaxTerms + k];
+            const double ex = exp(-(t2 * e.d2));
+            gs = fma(wk, ex, gs);
+            if (GRAD) dg = fma(wk * (-2.0 * t2), ex, dg);
+          }
         }
         eS = fma(e.zz, gs, eS);
         if constexpr (GRAD) {
@@ -800,6 +823,11 @@ ScoreParams make_score_params(const Tensor* t, const ScoreIO& io, const double4*
   a.t2 = t->short_tab;
   a.w = t->short_tab + kMaxTerms;
   a.S = t->shrt.S;
+  a.poly = t->short_poly;
+  a.poly_x1 = t->poly_x1;
+  a.poly_inv_d1 = t->poly_inv_d1;
+  a.poly_inv_d2 = t->poly_inv_d2;
+  a.poly_n1 = t->poly_n1;
   a.rc2 = t->sp.r_cut * t->sp.r_cut;
   a.sig2 = io.vdw_min * io.vdw_min;
   a.reach = t->sp.r_cut > io.vdw_min ? t->sp.r_cut : io.vdw_min;

@@ -257,3 +257,30 @@ class _ClosedCtx:
 
     def __init__(self, c):
         self.handle = c._raw
+
+
+def test_short_range_table_and_exponentials_agree(rs, ctx, cfg1):
+    """Energy-only scoring evaluates the short-range Gaussians from the context's piecewise
+    polynomial table; a context with option short_poly = 0 evaluates the exponentials.  Both
+    meet the bar against the oracle, with the same flags and counts."""
+    cfg, wl, F, t = cfg1
+    import torch
+    c0 = rs.Context(0)
+    c0.set_option("short_poly", 0)
+    t0 = rs.tensor_import(c0, F, cfg.n, cfg.b, rs.Sinc.from_config(cfg), wl.protein_charges, wl.protein_positions)
+    q1, t1 = near_threshold_poses(cfg, wl, wl.quats, wl.trans * (15.5 / 18.0), cfg.r_cut * 0.5, 24)
+    q = np.concatenate([wl.quats, q1])
+    tr = np.concatenate([wl.trans, t1])
+    ref = oracle_score(cfg, wl, F, q, tr)
+    for mode in (1, 2):
+        a = _run(rs, ctx, t, wl, q, tr, cfg.sigma, grad=False, mode=mode)
+        b = _run(rs, c0, t0, wl, q, tr, cfg.sigma, grad=False, mode=mode)
+        wa = assert_parity(a, ref, label=f"table, mode {mode}")
+        wb = assert_parity(b, ref, label=f"exponentials, mode {mode}")
+        assert np.array_equal(a["flags"], b["flags"]) and np.array_equal(a["counts"], b["counts"])
+        print(f"mode {mode}: worst error table {wa:.3g}, exponentials {wb:.3g} x tolerance")
+    ctx.set_option("score_mode", 0)
+    c0.set_option("score_mode", 0)
+    t0.free()
+    c0.close()
+    torch.cuda.synchronize()
