@@ -316,6 +316,11 @@ void rsd_tensor_free(rsd_tensor* t);
  *                     2 dense product of the generated side matrix on matrix cores (O(n^2 N K))
  *   "short_waves"     wavefronts (poses) per workgroup of the short-range kernel: 0 automatic,
  *                     1, 2 or 4 (must fit 64 KB of LDS for the ligand)
+ *   "short_poly"      1 (default): tensors made afterwards with this context evaluate the
+ *                     short-range Gaussian sum of energy-only scoring from a table of degree-7
+ *                     Chebyshev interpolants in d^2 (one per quadrature and cutoff, kept by the
+ *                     context; checked on the host to 1e-11 relative, else not used); gradient
+ *                     calls and 0 evaluate the exponentials
  *   "overlap"         1: in chunk-major scoring the short-range kernel runs on a second stream
  *                     of the context beside the long-range kernel (joined before the results
  *                     are combined); 0 (default): one stream.  The long-range gathers slow
