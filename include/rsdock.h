@@ -316,6 +316,10 @@ void rsd_tensor_free(rsd_tensor* t);
  *                     2 dense product of the generated side matrix on matrix cores (O(n^2 N K))
  *   "short_waves"     wavefronts (poses) per workgroup of the short-range kernel: 0 automatic,
  *                     1, 2 or 4 (must fit 64 KB of LDS for the ligand)
+ *   "shared_mode3"    1 (default): for tensors made by the build, a restriction or a combine,
+ *                     whose mode-3 factor columns are copies of the r_3 columns of U_3, the
+ *                     chunk-major energy kernel lerps each chunk's few distinct U_3 columns once
+ *                     per atom (same values, fewer gathers); 0: gather every mode-3 column
  *   "short_poly"      1 (default): tensors made afterwards with this context evaluate the
  *                     short-range Gaussian sum of energy-only scoring from a table of degree-7
  *                     Chebyshev interpolants in d^2 (one per quadrature and cutoff, kept by the

@@ -150,7 +150,8 @@ rsd_status Context::collect_timers() {
 }
 
 size_t Tensor::bytes() const {
-  return F_bytes + cell_bytes + sizeof(double4) * (size_t)(N > 0 ? N : 1) + sizeof(double) * 2 * kMaxTerms;
+  return F_bytes + cell_bytes + sizeof(double4) * (size_t)(N > 0 ? N : 1) + sizeof(double) * 2 * kMaxTerms +
+         (U3 ? sizeof(double) * (size_t)nm[2] * u3_ld + sizeof(int) * (size_t)R : 0);
 }
 
 void sinc_table(const rsd_sinc_params& sp, double* t, double* w) {
@@ -388,6 +389,8 @@ static void tensor_release(Tensor* t) {
     c->dev_free(t->atoms, sizeof(double4) * (size_t)(t->N > 0 ? t->N : 1));
     c->dev_free(t->cell_start, t->cell_bytes);
     c->dev_free(t->short_tab, sizeof(double) * 2 * kMaxTerms);
+    if (t->U3) c->dev_free(t->U3, sizeof(double) * (size_t)t->nm[2] * t->u3_ld);
+    if (t->slice) c->dev_free(t->slice, sizeof(int) * (size_t)t->R);
     c->live_tensors -= 1;
   }
   delete static_cast<rsd_tensor*>(t);
@@ -1137,6 +1140,11 @@ rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t va
   if (std::strcmp(name, "use_tuning") == 0) {
     RSD_CHECK(value == 0 || value == 1, RSD_E_INVALID, "use_tuning must be 0 or 1");
     ctx->opt_use_tuning = (int)value;
+    return RSD_OK;
+  }
+  if (std::strcmp(name, "shared_mode3") == 0) {
+    RSD_CHECK(value == 0 || value == 1, RSD_E_INVALID, "shared_mode3 must be 0 or 1");
+    ctx->opt_shared_mode3 = (int)value;
     return RSD_OK;
   }
   if (std::strcmp(name, "short_poly") == 0) {

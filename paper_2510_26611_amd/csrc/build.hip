@@ -963,6 +963,17 @@ rsd_status tucker_canonical(Context* ctx, Tensor* t, DevBuf Bt[3], DevBuf U[3], 
   }
   RSD_TRY(alloc_factors(ctx, t, R));
   if (R == 0) return RSD_OK;
+  // keep U_3 and the column -> slice map: the scoring kernels lerp a chunk's few distinct
+  // mode-3 columns once per atom instead of gathering all of them
+  {
+    std::vector<int> sl((size_t)R);
+    for (int64_t p = 0; p < R; ++p) sl[(size_t)p] = kept[(size_t)p].first;
+    RSD_TRY(ctx->dev_alloc((void**)&t->U3, sizeof(double) * (size_t)t->nm[2] * ldu[2]));
+    RSD_TRY(ctx->dev_alloc((void**)&t->slice, sizeof(int) * (size_t)R));
+    t->u3_ld = ldu[2];
+    RSD_HIP(hipMemcpyAsync(t->U3, U[2].p, sizeof(double) * (size_t)t->nm[2] * ldu[2], hipMemcpyDeviceToDevice, s));
+    RSD_HIP(hipMemcpy(t->slice, sl.data(), sizeof(int) * (size_t)R, hipMemcpyHostToDevice));
+  }
   const int64_t mode = (int64_t)t->nchunk * n * kChunk;
   const std::vector<double>* Vh[3] = {&V1, &V2, &V3};
   for (int d = 0; d < 3; ++d) {

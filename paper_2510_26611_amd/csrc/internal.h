@@ -101,6 +101,7 @@ struct Context {
   int opt_use_tuning = 1;      // apply shapes recorded by rsd_autotune to automatic calls
   int opt_overlap = 0;         // chunk-major scoring: short range on a second stream beside the long range
   int opt_short_poly = 1;      // tensors made with this context carry the short-range polynomial table
+  int opt_shared_mode3 = 1;    // chunk-major scoring lerps a chunk's distinct U_3 columns once per atom
   // launch shapes recorded by rsd_autotune: (n, nchunk, N, L, grad) -> (mode, ppw, short waves)
   std::map<std::tuple<int, int, int64_t, int, int>, std::array<int, 3>> tuned;
   bool timing = false;
@@ -168,6 +169,11 @@ struct Tensor {
   CellGrid cells{};
   double* short_tab = nullptr; // device copy of ShortTable t2[], w[] (2 * kMaxTerms)
   ShortTable shrt{};
+  // made by the canonical -> Tucker -> canonical step: column p of F_3 is column slice[p] of
+  // U_3 (nm[2] rows, leading dimension u3_ld); null for imported or loaded tensors
+  double* U3 = nullptr;
+  int* slice = nullptr;
+  int u3_ld = 0;
   // the short-range kernel g(x) = sum_k w_k exp(-t_k^2 x) as piecewise polynomials in x = d^2
   // (kPolyCoef monomial coefficients per interval on [-1, 1]); owned by the context's cache,
   // null when not built

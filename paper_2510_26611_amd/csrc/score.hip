@@ -528,15 +528,33 @@ struct LongParams {
   int64_t nblk;                  // pose blocks of 4 * ppw poses
   int64_t items, per_xcd;
   double* __restrict__ part;     // [nchunk][P][S], S = 1 (energy) or 7 (energy, dE/dt, dE/domega)
+  // tensors made by the canonical -> Tucker -> canonical step: column p of F_3 is column
+  // slice[p] of U_3, so a chunk's mode-3 lerps take only a few distinct values per atom
+  const double* __restrict__ U3; // rows x u3_ld, or null
+  const int* __restrict__ slice; // [R]
+  int u3_ld;
+  int64_t R;
 };
+
+constexpr int kSlots = 4;        // distinct mode-3 columns per chunk served from LDS
 
 struct GridPt {                  // one ligand atom of one pose: grid rows and weights
   double f0, f1, f2;
   int i0, i1, i2, pad;
 };
 
-template <bool GRAD>
+template <bool GRAD, bool U3>
 __device__ void long_item(const LongParams& a, const int c, const int64_t p0, double4* smem);
+
+// The chunk's columns map to the U_3 columns clo .. clo + nsl - 1 (a contiguous range: the
+// terms are grouped by core slice); with nsl <= kSlots the mode-3 lerps come from LDS.
+__device__ __forceinline__ bool chunk_slices(const LongParams& a, int c, int* clo) {
+  if (!a.U3) return false;
+  const int64_t p_first = (int64_t)c * kChunk;
+  const int64_t p_last = min(a.R, p_first + kChunk) - 1;
+  *clo = a.slice[p_first];
+  return a.slice[p_last] - *clo < kSlots;
+}
 
 template <bool GRAD>
 __global__ __launch_bounds__(256) void k_long(const LongParams a) {
@@ -545,11 +563,16 @@ __global__ __launch_bounds__(256) void k_long(const LongParams a) {
   if (j >= a.per_xcd) return;
   const int64_t item = (int64_t)(blockIdx.x & 7) * a.per_xcd + j;
   if (item >= a.items) return;
-  long_item<GRAD>(a, (int)(item / a.nblk), (item % a.nblk) * (4 * a.ppw), smem);
+  const int c = (int)(item / a.nblk);
+  int clo = 0;
+  if (!GRAD && chunk_slices(a, c, &clo))
+    long_item<false, true>(a, c, (item % a.nblk) * (4 * a.ppw), smem);
+  else
+    long_item<GRAD, false>(a, c, (item % a.nblk) * (4 * a.ppw), smem);
 }
 
 // Chunk c of the long-range sum for the poses [p0, p0 + 4*ppw); the whole workgroup calls it.
-template <bool GRAD>
+template <bool GRAD, bool U3>
 __device__ void long_item(const LongParams& a, const int c, const int64_t p0, double4* smem) {
   constexpr int S = GRAD ? 7 : 1;
   const int L = a.L;
@@ -559,6 +582,9 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
   double4* s_v = (double4*)(s_pt + PB * L);    // GRAD: R u_l per point
   int* s_bad = (int*)(GRAD ? (void*)(s_v + PB * L) : (void*)s_v);
   double* s_out = (double*)(s_bad + PB);        // the block's PB x S results, stored together at the end
+  double* s_l3 = s_out + PB * S;                // U3: per atom kSlots mode-3 lerps
+  int clo = 0;
+  if (U3) chunk_slices(a, c, &clo);
   const int tid = threadIdx.x;
   for (int i = tid; i < L; i += 256) s_lig[i] = a.lig[i];
   for (int i = tid; i < PB; i += 256) s_bad[i] = 0;
@@ -584,6 +610,15 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
           g.f2 = s2 - (double)g.i2;
           ok = true;
           if (GRAD) s_v[e] = make_double4(y.x - tv[0], y.y - tv[1], y.z - tv[2], 0.0);
+          if (U3) {   // the mode-3 lerps of the chunk's distinct U_3 columns (as F_3 would give)
+            const double* r0 = a.U3 + (int64_t)g.i2 * a.u3_ld + clo;
+            const double* r1 = r0 + a.u3_ld;
+#pragma unroll
+            for (int q = 0; q < kSlots; ++q) {
+              const int cq = clo + q < a.u3_ld ? q : 0;
+              s_l3[e * kSlots + q] = fma(g.f2, r1[cq] - r0[cq], r0[cq]);
+            }
+          }
         }
       }
     }
@@ -592,6 +627,13 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
   }
   __syncthreads();
   const int lane = tid & 63, wv = tid >> 6;
+  // U3: this lane's two columns as slots of the chunk's mode-3 columns
+  int slot0 = 0, slot1 = 0;
+  if (U3) {
+    const int64_t pc = (int64_t)c * kChunk + 2 * (lane & 31);
+    slot0 = pc < a.R ? a.slice[pc] - clo : 0;
+    slot1 = pc + 1 < a.R ? a.slice[pc + 1] - clo : 0;
+  }
   // The two half-wavefronts take two different atoms; lane j of a half owns columns 2j and
   // 2j+1 of the chunk and loads them from rows i and i+1 as 16-byte loads.  The return path
   // from L2 moves a fixed number of lanes per clock, so 16 instead of 8 bytes per lane nearly
@@ -610,7 +652,7 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
       const GridPt* pts = s_pt + lp * L;
       for (int l0 = 0; l0 < L; l0 += 4) {
         double2 A0[2], B0[2], A1[2], B1[2], A2[2], B2[2];
-        double f0[2], f1[2], f2[2], zeta[2];
+        double f0[2], f1[2], f2[2], zeta[2], l3x[2], l3y[2];
         int la[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -621,17 +663,26 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
           f0[u] = g.f0; f1[u] = g.f1; f2[u] = g.f2;
           const double2* q0 = (const double2*)(F0 + (int64_t)g.i0 * kChunk);
           const double2* q1 = (const double2*)(F1 + (int64_t)g.i1 * kChunk);
-          const double2* q2 = (const double2*)(F2 + (int64_t)g.i2 * kChunk);
           A0[u] = q0[0]; B0[u] = q0[kChunk / 2];
           A1[u] = q1[0]; B1[u] = q1[kChunk / 2];
-          A2[u] = q2[0]; B2[u] = q2[kChunk / 2];
+          if constexpr (U3) {
+            const double* l3 = s_l3 + (lp * L + la[u]) * kSlots;
+            l3x[u] = l3[slot0];
+            l3y[u] = l3[slot1];
+          } else {
+            const double2* q2 = (const double2*)(F2 + (int64_t)g.i2 * kChunk);
+            A2[u] = q2[0]; B2[u] = q2[kChunk / 2];
+          }
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          const double dx0 = B0[u].x - A0[u].x, dx1 = B1[u].x - A1[u].x, dx2 = B2[u].x - A2[u].x;
-          const double dy0 = B0[u].y - A0[u].y, dy1 = B1[u].y - A1[u].y, dy2 = B2[u].y - A2[u].y;
-          const double lx0 = fma(f0[u], dx0, A0[u].x), lx1 = fma(f1[u], dx1, A1[u].x), lx2 = fma(f2[u], dx2, A2[u].x);
-          const double ly0 = fma(f0[u], dy0, A0[u].y), ly1 = fma(f1[u], dy1, A1[u].y), ly2 = fma(f2[u], dy2, A2[u].y);
+          const double dx0 = B0[u].x - A0[u].x, dx1 = B1[u].x - A1[u].x;
+          const double dy0 = B0[u].y - A0[u].y, dy1 = B1[u].y - A1[u].y;
+          const double dx2 = U3 ? 0.0 : B2[u].x - A2[u].x, dy2 = U3 ? 0.0 : B2[u].y - A2[u].y;
+          const double lx0 = fma(f0[u], dx0, A0[u].x), lx1 = fma(f1[u], dx1, A1[u].x);
+          const double lx2 = U3 ? l3x[u] : fma(f2[u], dx2, A2[u].x);
+          const double ly0 = fma(f0[u], dy0, A0[u].y), ly1 = fma(f1[u], dy1, A1[u].y);
+          const double ly2 = U3 ? l3y[u] : fma(f2[u], dy2, A2[u].y);
           const double lx01 = lx0 * lx1, ly01 = ly0 * ly1;
           e = fma(zeta[u], lx01 * lx2, e);
           e = fma(zeta[u], ly01 * ly2, e);
@@ -786,7 +837,12 @@ __global__ __launch_bounds__(256) void k_batch_long(const BatchDesc* __restrict_
   if (jl >= lp.per_xcd) return;
   const int64_t item = (int64_t)(blockIdx.x & 7) * lp.per_xcd + jl;
   if (item >= lp.items) return;
-  long_item<false>(lp, (int)(item / lp.nblk), (item % lp.nblk) * (4 * lp.ppw), smem);
+  const int c = (int)(item / lp.nblk);
+  int clo = 0;
+  if (chunk_slices(lp, c, &clo))
+    long_item<false, true>(lp, c, (item % lp.nblk) * (4 * lp.ppw), smem);
+  else
+    long_item<false, false>(lp, c, (item % lp.nblk) * (4 * lp.ppw), smem);
 }
 
 __global__ void k_batch_combine(const BatchDesc* __restrict__ d, int nreq, int64_t poses) {
@@ -864,19 +920,28 @@ rsd_status allow_lds(const void* kernel, size_t bytes) {
   return RSD_OK;
 }
 
-size_t long_lds(int L, int ppw, bool grad) {
+size_t long_lds(int L, int ppw, bool grad, bool u3) {
   const int PB = 4 * ppw;
   return sizeof(double4) * (size_t)L + (size_t)PB * L * (sizeof(GridPt) + (grad ? sizeof(double4) : 0)) +
-         sizeof(int) * (size_t)PB + sizeof(double) * (size_t)PB * (grad ? 7 : 1);
+         sizeof(int) * (size_t)PB + sizeof(double) * (size_t)PB * (grad ? 7 : 1) +
+         (grad || !u3 ? 0 : sizeof(double) * (size_t)PB * L * kSlots);
 }
 
-int pick_ppw(int L, bool grad, int want) {
+int pick_ppw(int L, bool grad, bool u3, int want) {
   int ppw = want > 0 ? want : 4;
-  while (ppw > 1 && long_lds(L, ppw, grad) > 48 * 1024) --ppw;
+  while (ppw > 1 && long_lds(L, ppw, grad, u3) > 64 * 1024) --ppw;
   return ppw;
 }
 
-LongParams make_long_params(const Tensor* t, const ScoreIO& io, const double4* lig, int ppw, double* part) {
+// Whether the chunk-major kernel serves the tensor's mode-3 lerps from LDS: the tensor keeps
+// U_3, the option is on, and the extra LDS still fits at the poses per wavefront it gets.
+bool use_u3(const Context* ctx, const Tensor* t, int L, bool grad, int ppw_want) {
+  if (grad || !t->U3 || !ctx->opt_shared_mode3) return false;
+  return long_lds(L, pick_ppw(L, grad, true, ppw_want), grad, true) <= kLdsMax;
+}
+
+LongParams make_long_params(const Tensor* t, const ScoreIO& io, const double4* lig, int ppw, double* part,
+                            bool shared_mode3) {
   LongParams lp{};
   lp.F = t->F;
   lp.chunk_stride = (int64_t)t->n * kChunk;
@@ -898,6 +963,10 @@ LongParams make_long_params(const Tensor* t, const ScoreIO& io, const double4* l
   lp.items = lp.nblk * t->nchunk;
   lp.per_xcd = (lp.items + 7) / 8;
   lp.part = part;
+  lp.U3 = shared_mode3 ? t->U3 : nullptr;
+  lp.slice = t->slice;
+  lp.u3_ld = t->u3_ld;
+  lp.R = t->R;
   return lp;
 }
 
@@ -925,8 +994,9 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
 
   // long-range mode: fused (one wavefront does the whole pose) or chunk-major (k_long)
   const int S = grad ? 7 : 1;
-  const int ppw = pick_ppw(L, grad, ppw_want);
-  bool split = t->nchunk > 0 && long_lds(L, ppw, grad) <= kLdsMax;
+  const bool u3 = use_u3(ctx, t, L, grad, ppw_want);
+  const int ppw = pick_ppw(L, grad, u3, ppw_want);
+  bool split = t->nchunk > 0 && long_lds(L, ppw, grad, u3) <= kLdsMax;
   if (mode == 1) split = false;
   if (mode == 0 && (t->nchunk < 2 || P < 256)) split = false;
 
@@ -961,10 +1031,10 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
     }
     return RSD_OK;
   }
-  const LongParams lp = make_long_params(t, io, lig, ppw, (double*)(w8 + off_part));
+  const LongParams lp = make_long_params(t, io, lig, ppw, (double*)(w8 + off_part), u3);
   RSD_CHECK(lp.per_xcd * 8 <= 0x7fffffffLL, RSD_E_UNSUPPORTED, "too many poses in one call");
   const dim3 g2((unsigned)(lp.per_xcd * 8));
-  const size_t lds2 = long_lds(L, ppw, grad);
+  const size_t lds2 = long_lds(L, ppw, grad, u3);
   const unsigned gc = (unsigned)std::min<int64_t>((P + 255) / 256, 65536);
   RSD_TRY(allow_lds(grad ? (const void*)k_long<true> : (const void*)k_long<false>, lds2));
   // The short-range kernel (FP64 ALU) and the long-range gathers (bound by the L2 return
@@ -1055,7 +1125,9 @@ rsd_status autotune(Context* ctx, const Tensor* t, const ScoreIO& io, rsd_tune_r
       cand.push_back({1, 0, W, 0.0});
       if (t->nchunk == 0) continue;
       for (int ppw = 1; ppw <= 4; ++ppw)
-        if (pick_ppw(L, grad, ppw) == ppw && long_lds(L, ppw, grad) <= kLdsMax) cand.push_back({2, ppw, W, 0.0});
+        if (pick_ppw(L, grad, use_u3(ctx, t, L, grad, ppw), ppw) == ppw &&
+            long_lds(L, ppw, grad, use_u3(ctx, t, L, grad, ppw)) <= kLdsMax)
+          cand.push_back({2, ppw, W, 0.0});
     }
     for (auto& c : cand) RSD_TRY(time_shape(c.mode, c.ppw, c.W, &c.ms));
     return RSD_OK;
@@ -1132,7 +1204,7 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
   b->ctx = ctx;
   b->nreq = nreq;
   std::vector<int64_t> off_lig(nreq), off_es(nreq), off_part(nreq);
-  std::vector<int> ppw(nreq);
+  std::vector<int> ppw(nreq), u3(nreq);
   int64_t nlig = 0, nes = 0, npart = 0;
   for (int k = 0; k < nreq; ++k) {
     const rsd_request& q = req_in[order[k]];
@@ -1145,7 +1217,8 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     npart += (int64_t)t->nchunk * q.P;
     int mode_k = ctx->opt_score_mode, ppw_k = ctx->opt_poses_per_wave, w_k = ctx->opt_short_waves;
     tuned_shape(ctx, t, (int)q.L, false, q.P, &mode_k, &ppw_k, &w_k);
-    ppw[k] = pick_ppw((int)q.L, false, ppw_k);
+    u3[k] = use_u3(ctx, t, (int)q.L, false, ppw_k) ? 1 : 0;
+    ppw[k] = pick_ppw((int)q.L, false, u3[k] != 0, ppw_k);
   }
   const size_t sz_desc = sizeof(BatchDesc) * (size_t)nreq;
   const size_t o_lig = (sz_desc + 255) / 256 * 256;
@@ -1182,7 +1255,7 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     double* es = (double*)(m + o_es) + off_es[k];
     double* part = (double*)(m + o_part) + off_part[k];
     h[k].sp = make_score_params(t, io, lig, rlig, es, nullptr);
-    h[k].lp = make_long_params(t, io, lig, ppw[k], part);
+    h[k].lp = make_long_params(t, io, lig, ppw[k], part, u3[k] != 0);
     h[k].lig_pos = q.lig_positions;
     h[k].lig_z = q.lig_charges;
     h[k].pose_base = pb;
@@ -1203,7 +1276,7 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
       sb += (h[i].sp.P + bu.W - 1) / bu.W;
       h[i].xcd_base = xb;
       xb += h[i].lp.per_xcd;
-      bu.lds_long = std::max(bu.lds_long, long_lds(h[i].lp.L, ppw[i], false));
+      bu.lds_long = std::max(bu.lds_long, long_lds(h[i].lp.L, ppw[i], false, u3[i] != 0));
     }
     bu.blocks = sb;
     bu.long_slots = xb;

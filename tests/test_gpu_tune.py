@@ -119,3 +119,41 @@ def test_short_range_on_a_second_stream_is_bitwise_the_same(env, grads):
         assert np.array_equal(one[k], two[k], equal_nan=True), k
         assert np.array_equal(two[k], again[k], equal_nan=True), k
     assert_parity(two, oracle_score(cfg, wl, F, wl.quats, wl.trans, grad=grads), grad=grads, label="overlap")
+
+
+def test_shared_mode3_columns_bitwise(env):
+    """Tensors made by the canonical -> Tucker -> canonical step keep U_3: the chunk-major energy
+    kernel lerps a chunk's distinct U_3 columns once per atom.  The values are the same as the
+    gathered F_3 columns, so option shared_mode3 gives the same bits on and off, alone and in a
+    batch, for a built, a restricted and a combined tensor."""
+    rs, torch, ctx, cfg, wl, F, t, dev = env
+    tb = rs.build_rs_tensor(ctx, wl.protein_charges, wl.protein_positions, cfg.n, cfg.b, rs.Sinc.from_config(cfg))
+    site = np.array([18.0, 0.0, 0.0])
+    tl = tb.restrict(site - 8.0, site + 8.0, 1e-8)
+    tc = rs.tensor_combine(ctx, [tb, tb], 1e-8)
+    qs = dev["q"].clone()
+    ts = dev["t"].clone()
+    ts[:1500] = torch.from_numpy(site[None, :] + gen.sphere_translations(gen.rng(73, 6), 1500, 2.0)).cuda()
+    ctx.set_option("score_mode", 2)
+    try:
+        for tt in (tb, tl, tc):
+            out = {}
+            for opt in (0, 1):
+                ctx.set_option("shared_mode3", opt)
+                o = rs.score_poses(ctx, tt, dev["z"], dev["x"], qs, ts, cfg.sigma)
+                torch.cuda.synchronize()
+                out[opt] = {k: v.cpu().numpy() for k, v in o.items()}
+            for k in out[0]:
+                assert np.array_equal(out[0][k], out[1][k], equal_nan=True), k
+            b = rs.Batch(ctx, [dict(tensor=tt, lig_charges=dev["z"], lig_positions=dev["x"], quats=qs, trans=ts,
+                                    vdw_min=cfg.sigma)])
+            b.run()
+            torch.cuda.synchronize()
+            for k, v in b.outputs()[0].items():
+                assert np.array_equal(v.cpu().numpy(), out[1][k], equal_nan=True), k
+            b.free()
+    finally:
+        ctx.set_option("shared_mode3", 1)
+        ctx.set_option("score_mode", 0)
+    for tt in (tl, tc, tb):
+        tt.free()
