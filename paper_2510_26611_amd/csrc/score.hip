@@ -22,7 +22,10 @@
 // IEEE FP64 implementation that follows the same order.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -775,6 +778,49 @@ struct BatchDesc {
   int64_t xcd_base;     // first long-range slot of the request on every XCD, within its bucket
 };
 
+// Pointers read from the request table are generic to the compiler, which then emits flat
+// loads and stores (slower, and they wait on the LDS counter too) for everything they reach.
+// They point at device (global) memory or are null, and they are the same in every lane:
+// passing the bits through an empty asm and back through the global address space keeps the
+// compiler from folding the round trip away, so it emits global loads and stores as it does
+// for pointers passed as kernel arguments.
+template <class T>
+__device__ __forceinline__ T* global_ptr(T* p) {
+  uint64_t v = (uint64_t)(uintptr_t)p;
+  asm("" : "+s"(v));
+  return (T*)(__attribute__((address_space(1))) T*)v;
+}
+
+__device__ __forceinline__ void make_global(LongParams& a) {
+  a.F = global_ptr(a.F);
+  a.lig = global_ptr(a.lig);
+  a.quats = global_ptr(a.quats);
+  a.trans = global_ptr(a.trans);
+  a.part = global_ptr(a.part);
+  a.U3 = global_ptr(a.U3);
+  a.slice = global_ptr(a.slice);
+}
+
+__device__ __forceinline__ void make_global(ScoreParams& a) {
+  a.F = global_ptr(a.F);
+  a.atoms = global_ptr(a.atoms);
+  a.cell_start = global_ptr(a.cell_start);
+  a.t2 = global_ptr(a.t2);
+  a.w = global_ptr(a.w);
+  a.poly = global_ptr(a.poly);
+  a.lig = global_ptr(a.lig);
+  a.rlig = global_ptr(a.rlig);
+  a.quats = global_ptr(a.quats);
+  a.trans = global_ptr(a.trans);
+  a.E = global_ptr(a.E);
+  a.El = global_ptr(a.El);
+  a.flags = global_ptr(a.flags);
+  a.counts = global_ptr(a.counts);
+  a.grads = global_ptr(a.grads);
+  a.es = global_ptr(a.es);
+  a.gs = global_ptr(a.gs);
+}
+
 // last request r with key(r) <= x (requests with nothing to do share the next one's key)
 template <class Key>
 __device__ __forceinline__ int find_request(const BatchDesc* __restrict__ d, int nreq, int64_t x, Key key) {
@@ -804,7 +850,8 @@ __global__ __launch_bounds__(256) void k_batch_short(const BatchDesc* __restrict
   const BatchDesc* d = dall + first;
   const int64_t blk = blockIdx.x;
   const int r = find_request_uniform(d, nreq, blk, [](const BatchDesc& x) { return x.short_base; });
-  const ScoreParams a = d[r].sp;   // by value: the fields then stay in registers inside the loops
+  ScoreParams a = d[r].sp;   // by value: the fields then stay in registers inside the loops
+  make_global(a);
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int W = blockDim.x >> 6;
@@ -832,7 +879,8 @@ __global__ __launch_bounds__(256) void k_batch_long(const BatchDesc* __restrict_
   const BatchDesc* d = dall + first;
   const int64_t j = blockIdx.x >> 3;
   const int r = find_request_uniform(d, nreq, j, [](const BatchDesc& x) { return x.xcd_base; });
-  const LongParams lp = d[r].lp;
+  LongParams lp = d[r].lp;
+  make_global(lp);
   const int64_t jl = j - d[r].xcd_base;
   if (jl >= lp.per_xcd) return;
   const int64_t item = (int64_t)(blockIdx.x & 7) * lp.per_xcd + jl;
@@ -912,11 +960,21 @@ size_t short_lds(int L, int W, bool grad) {
 constexpr size_t kLdsDefault = 64 * 1024;   // dynamic LDS a kernel gets without asking
 constexpr size_t kLdsMax = 160 * 1024;       // LDS of one gfx950 compute unit
 
-// Dynamic LDS beyond the default must be allowed per kernel function.
+// Dynamic LDS beyond the default must be allowed per kernel function (on the current device).
+// The allowance only ever grows, so a launch prepared earlier (a batch built before another
+// one with smaller needs) stays within it.
 rsd_status allow_lds(const void* kernel, size_t bytes) {
   if (bytes <= kLdsDefault) return RSD_OK;
   RSD_CHECK(bytes <= kLdsMax, RSD_E_UNSUPPORTED, "kernel needs %zu bytes of LDS", bytes);
+  int dev = 0;
+  RSD_HIP(hipGetDevice(&dev));
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, size_t> allowed;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& cur = allowed[{dev, kernel}];
+  if (bytes <= cur) return RSD_OK;
   RSD_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  cur = bytes;
   return RSD_OK;
 }
 
@@ -1164,19 +1222,26 @@ struct Batch {
   void* mem = nullptr;
   size_t bytes = 0;
   BatchDesc* d = nullptr;
-  struct Bucket {
-    int first, count, W;
-    size_t lds, lds_long;
-    int64_t blocks, long_slots;
+  struct Launch {          // one launch over the table range [first, first + count)
+    int first, count, W;   // W: wavefronts per workgroup (short range)
+    size_t lds;
+    int64_t units;         // workgroups (short range) or work-list slots per XCD (long range)
   };
-  std::vector<Bucket> buckets;   // short- and long-range launches, one pair per ligand-size class
+  std::vector<Launch> shorts, longs;
   int64_t poses = 0;
   std::vector<BatchDesc> host_table;   // source of the (asynchronous) table upload
   hipEvent_t uploaded = nullptr;       // recorded after the upload: host_table may go once it completes
 };
 
-// ligand-size classes of the launches (LDS, hence occupancy, depends on L)
-static int ligand_bucket(int64_t L) { return L <= 32 ? 0 : L <= 64 ? 1 : L <= 128 ? 2 : L <= 256 ? 3 : 4; }
+// Work-group slots per CU that a launch's LDS leaves, capped by the wavefronts a CU holds.
+// LDS goes to workgroups in granules of 1,280 bytes: a launch of 53,808 bytes per group fits
+// two groups per CU, not three (measured as a 5 % slower batch when such a request set the
+// launch's size for requests of 41-53 KB).
+constexpr size_t kLdsGranule = 1280;
+static int lds_occupancy(size_t lds, int waves_per_group) {
+  const size_t g = (std::max<size_t>(lds, 1) + kLdsGranule - 1) / kLdsGranule * kLdsGranule;
+  return (int)std::min<size_t>(kLdsMax / g, (size_t)(32 / waves_per_group));
+}
 
 rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, Batch** out) {
   *out = nullptr;
@@ -1194,17 +1259,47 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
                            q.counts),
               RSD_E_INVALID, "request %d: NULL pointer", r);
   }
-  // table order: by ligand-size bucket (stable), so each short-range launch covers a contiguous range
+  // Each request's launch shape as a call of its own would take it.  A launch's LDS is the
+  // largest any of its requests needs, so requests are grouped by the occupancy their own LDS
+  // allows: none then runs with fewer workgroups per CU than it would alone.
+  struct Shape {
+    int ppw, u3, W, occ_s, occ_l;
+    size_t lds_s, lds_l;
+  };
+  std::vector<Shape> shp((size_t)nreq);
+  for (int r = 0; r < nreq; ++r) {
+    const rsd_request& q = req_in[r];
+    const Tensor* t = static_cast<const Tensor*>(q.tensor);
+    const int L = (int)q.L;
+    int mode_k = ctx->opt_score_mode, ppw_k = ctx->opt_poses_per_wave, w_k = ctx->opt_short_waves;
+    tuned_shape(ctx, t, L, false, q.P, &mode_k, &ppw_k, &w_k);
+    Shape& x = shp[r];
+    x.u3 = use_u3(ctx, t, L, false, ppw_k) ? 1 : 0;
+    x.ppw = pick_ppw(L, false, x.u3 != 0, ppw_k);
+    x.W = w_k > 0 ? std::min(w_k, 4) : 4;
+    while (x.W > 1 && short_lds(L, x.W, false) > kLdsDefault) x.W >>= 1;
+    x.lds_s = short_lds(L, x.W, false);
+    x.lds_l = long_lds(L, x.ppw, false, x.u3 != 0);
+    RSD_CHECK(x.lds_s <= kLdsDefault && x.lds_l <= kLdsMax, RSD_E_UNSUPPORTED,
+              "request %d: ligand of %d atoms needs too much LDS", r, L);
+    x.occ_s = lds_occupancy(x.lds_s, x.W);
+    x.occ_l = lds_occupancy(x.lds_l, 4);
+  }
+  // table order: long-range occupancy, then the short-range shape (stable), so that every
+  // launch covers a contiguous range and the heavier long-range kernel gets the fewest launches
   std::vector<int> order((size_t)nreq);
   for (int r = 0; r < nreq; ++r) order[r] = r;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return ligand_bucket(req_in[x].L) < ligand_bucket(req_in[y].L); });
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const Shape &a = shp[x], &c = shp[y];
+    if (a.occ_l != c.occ_l) return a.occ_l > c.occ_l;
+    if (a.W != c.W) return a.W > c.W;
+    return a.occ_s > c.occ_s;
+  });
   Batch* b = new (std::nothrow) Batch();
   RSD_CHECK(b != nullptr, RSD_E_OOM, "host allocation failed");
   b->ctx = ctx;
   b->nreq = nreq;
   std::vector<int64_t> off_lig(nreq), off_es(nreq), off_part(nreq);
-  std::vector<int> ppw(nreq), u3(nreq);
   int64_t nlig = 0, nes = 0, npart = 0;
   for (int k = 0; k < nreq; ++k) {
     const rsd_request& q = req_in[order[k]];
@@ -1215,10 +1310,6 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     nes += q.P;
     off_part[k] = npart;
     npart += (int64_t)t->nchunk * q.P;
-    int mode_k = ctx->opt_score_mode, ppw_k = ctx->opt_poses_per_wave, w_k = ctx->opt_short_waves;
-    tuned_shape(ctx, t, (int)q.L, false, q.P, &mode_k, &ppw_k, &w_k);
-    u3[k] = use_u3(ctx, t, (int)q.L, false, ppw_k) ? 1 : 0;
-    ppw[k] = pick_ppw((int)q.L, false, u3[k] != 0, ppw_k);
   }
   const size_t sz_desc = sizeof(BatchDesc) * (size_t)nreq;
   const size_t o_lig = (sz_desc + 255) / 256 * 256;
@@ -1255,49 +1346,56 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     double* es = (double*)(m + o_es) + off_es[k];
     double* part = (double*)(m + o_part) + off_part[k];
     h[k].sp = make_score_params(t, io, lig, rlig, es, nullptr);
-    h[k].lp = make_long_params(t, io, lig, ppw[k], part, u3[k] != 0);
+    h[k].lp = make_long_params(t, io, lig, shp[order[k]].ppw, part, shp[order[k]].u3 != 0);
     h[k].lig_pos = q.lig_positions;
     h[k].lig_z = q.lig_charges;
     h[k].pose_base = pb;
     pb += q.P;
   }
-  // ligand-size buckets: one short-range and one long-range launch each, LDS sized per bucket
-  for (int k = 0; k < nreq;) {
-    const int bk = ligand_bucket(req_in[order[k]].L);
+  // launches: maximal runs of the table with one short-range shape, and with one long-range
+  // occupancy; each launch's LDS is the largest its requests need
+  rsd_status lst = RSD_OK;
+  size_t lds_long_max = 0;
+  for (int k = 0; k < nreq && lst == RSD_OK;) {
+    const Shape& s0 = shp[order[k]];
+    Batch::Launch la{k, 0, s0.W, 0, 0};
     int e = k;
-    int maxL = 1;
-    while (e < nreq && ligand_bucket(req_in[order[e]].L) == bk) maxL = std::max(maxL, (int)req_in[order[e++]].L);
-    Batch::Bucket bu{k, e - k, 4, 0, 0, 0, 0};
-    while (bu.W > 1 && short_lds(maxL, bu.W, false) > 64 * 1024) bu.W >>= 1;
-    bu.lds = short_lds(maxL, bu.W, false);
-    int64_t sb = 0, xb = 0;
-    for (int i = k; i < e; ++i) {
-      h[i].short_base = sb;
-      sb += (h[i].sp.P + bu.W - 1) / bu.W;
-      h[i].xcd_base = xb;
-      xb += h[i].lp.per_xcd;
-      bu.lds_long = std::max(bu.lds_long, long_lds(h[i].lp.L, ppw[i], false, u3[i] != 0));
+    for (; e < nreq && shp[order[e]].W == s0.W && shp[order[e]].occ_s == s0.occ_s; ++e) {
+      h[e].short_base = la.units;
+      la.units += (h[e].sp.P + la.W - 1) / la.W;
+      la.lds = std::max(la.lds, shp[order[e]].lds_s);
     }
-    bu.blocks = sb;
-    bu.long_slots = xb;
-    rsd_status lst = RSD_OK;
-    if (bu.lds > kLdsDefault) {
-      set_error("ligand of %d atoms needs too much LDS", maxL);
-      lst = RSD_E_UNSUPPORTED;
-    } else {
-      lst = allow_lds((const void*)k_batch_long, bu.lds_long);
-    }
-    if (lst == RSD_OK && (sb > 0x7fffffffLL || xb * 8 > 0x7fffffffLL)) {
+    la.count = e - k;
+    if (la.units > 0x7fffffffLL) {
       set_error("batch too large for one launch");
       lst = RSD_E_UNSUPPORTED;
     }
-    if (lst != RSD_OK) {
-      ctx->block_release(b->mem, b->bytes);
-      delete b;
-      return lst;
-    }
-    if (sb > 0 || xb > 0) b->buckets.push_back(bu);
+    if (la.units > 0) b->shorts.push_back(la);
     k = e;
+  }
+  for (int k = 0; k < nreq && lst == RSD_OK;) {
+    const int occ = shp[order[k]].occ_l;
+    Batch::Launch la{k, 0, 4, 0, 0};
+    int e = k;
+    for (; e < nreq && shp[order[e]].occ_l == occ; ++e) {
+      h[e].xcd_base = la.units;
+      la.units += h[e].lp.per_xcd;
+      la.lds = std::max(la.lds, shp[order[e]].lds_l);
+    }
+    la.count = e - k;
+    if (la.units * 8 > 0x7fffffffLL) {
+      set_error("batch too large for one launch");
+      lst = RSD_E_UNSUPPORTED;
+    }
+    lds_long_max = std::max(lds_long_max, la.lds);
+    if (la.units > 0) b->longs.push_back(la);
+    k = e;
+  }
+  if (lst == RSD_OK) lst = allow_lds((const void*)k_batch_long, lds_long_max);
+  if (lst != RSD_OK) {
+    ctx->block_release(b->mem, b->bytes);
+    delete b;
+    return lst;
   }
   b->poses = pb;
   b->d = (BatchDesc*)m;
@@ -1324,16 +1422,12 @@ rsd_status batch_run(Batch* b) {
   hipStream_t s = ctx->stream;
   if (b->poses == 0) return RSD_OK;
   RSD_TIMED_LAUNCH(ctx, "ligand_prep", (k_batch_prep<<<b->nreq, 64, 0, s>>>(b->d)));
-  for (const auto& bu : b->buckets) {
-    if (bu.blocks > 0)
-      RSD_TIMED_LAUNCH(ctx, "short", (k_batch_short<<<(unsigned)bu.blocks, 64 * bu.W, bu.lds, s>>>(
-                                         b->d, bu.first, bu.count)));
-  }
-  for (const auto& bu : b->buckets) {
-    if (bu.long_slots > 0)
-      RSD_TIMED_LAUNCH(ctx, "long", (k_batch_long<<<(unsigned)(bu.long_slots * 8), 256, bu.lds_long, s>>>(
-                                        b->d, bu.first, bu.count)));
-  }
+  for (const auto& la : b->shorts)
+    RSD_TIMED_LAUNCH(ctx, "short", (k_batch_short<<<(unsigned)la.units, 64 * la.W, la.lds, s>>>(
+                                       b->d, la.first, la.count)));
+  for (const auto& la : b->longs)
+    RSD_TIMED_LAUNCH(ctx, "long", (k_batch_long<<<(unsigned)(la.units * 8), 256, la.lds, s>>>(
+                                      b->d, la.first, la.count)));
   const unsigned gc = (unsigned)std::min<int64_t>((b->poses + 255) / 256, 65536);
   RSD_TIMED_LAUNCH(ctx, "combine", (k_batch_combine<<<gc, 256, 0, s>>>(b->d, b->nreq, b->poses)));
   return RSD_OK;

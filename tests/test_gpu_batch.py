@@ -138,6 +138,31 @@ def test_batch_graph_replays_match_eager(env):
     b.free()
 
 
+def test_batch_made_before_a_smaller_one_still_runs(env):
+    """Two batches whose long-range launches need more LDS than the default, the larger made
+    first: running it after the second was made still works and matches the request alone."""
+    rs, ctx, torch, T = env
+    big, mid = _requests(torch, T, 300)[-1], None
+    lig = gen.ball_points(gen.rng(95, 3), 400, 1.2 * 400 ** (1 / 3))
+    zeta = gen.charges(gen.rng(95, 4), 400, 0.3, False)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    mid = dict(big, lig_charges=d(zeta), lig_positions=d(lig))
+    for r in (big, mid):
+        r["out"] = _mk_out(torch, r["quats"].shape[0])
+    b1 = rs.Batch(ctx, [big])
+    b2 = rs.Batch(ctx, [mid])
+    b1.run()
+    b2.run()
+    torch.cuda.synchronize()
+    for r in (big, mid):
+        got = {k: v.cpu().numpy() for k, v in r["out"].items()}
+        ref = _alone(rs, ctx, torch, r)
+        for k in ("E", "E_long", "flags", "counts"):
+            assert np.array_equal(got[k], ref[k], equal_nan=True), k
+    b1.free()
+    b2.free()
+
+
 def test_batch_argument_errors(env):
     rs, ctx, torch, T = env
     reqs = _requests(torch, T, 11)[:2]
