@@ -46,7 +46,7 @@ struct OpKM {                 // element (k, m) = p[k * ld + m]
   int64_t ld;
   int dim;
   __device__ void setup(int) {}
-  __device__ void fill(double* s, int64_t k0, int64_t k1, int m0) const {
+  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
     const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
     const int64_t k = k0 + kk;
     double v[8];
@@ -63,7 +63,7 @@ struct OpKM {                 // element (k, m) = p[k * ld + m]
       for (int j = 0; j < 8; ++j) v[j] = (k < k1 && m0 + c + j < dim) ? p[k * ld + m0 + c + j] : 0.0;
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) s[kk * LDT + c + j] = v[j];
+    for (int j = 0; j < 8; ++j) s[kk * sld + c + j] = v[j];
   }
 };
 
@@ -72,13 +72,13 @@ struct OpMK {                 // element (k, m) = p[m * ld + k]  (each m-row con
   int64_t ld;
   int dim;
   __device__ void setup(int) {}
-  __device__ void fill(double* s, int64_t k0, int64_t k1, int m0) const {
+  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
     const int t = threadIdx.x, mm = t >> 2, kk = (t & 3) * 8;
     const int m = m0 + mm;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int64_t k = k0 + kk + j;
-      s[(kk + j) * LDT + mm] = (m < dim && k < k1) ? p[(int64_t)m * ld + k] : 0.0;
+      s[(kk + j) * sld + mm] = (m < dim && k < k1) ? p[(int64_t)m * ld + k] : 0.0;
     }
   }
 };
@@ -89,13 +89,13 @@ struct OpKMScaled {           // element (k, m) = p[k * ld + m] * scale[k]
   int64_t ld;
   int dim;
   __device__ void setup(int) {}
-  __device__ void fill(double* s, int64_t k0, int64_t k1, int m0) const {
+  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
     const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
     const int64_t k = k0 + kk;
     const double sc = k < k1 ? scale[k] : 0.0;
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-      s[kk * LDT + c + j] = (k < k1 && m0 + c + j < dim) ? p[k * ld + m0 + c + j] * sc : 0.0;
+      s[kk * sld + c + j] = (k < k1 && m0 + c + j < dim) ? p[k * ld + m0 + c + j] * sc : 0.0;
   }
 };
 
@@ -115,12 +115,12 @@ struct OpKhatriRao {          // element (k, m = a*r2 + b) = P1[k*ld1 + a] * P2[
       b_[j] = m < dim ? m % r2 : 0;
     }
   }
-  __device__ void fill(double* s, int64_t k0, int64_t k1, int m0) const {
+  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
     const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
     const int64_t k = k0 + kk;
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-      s[kk * LDT + c + j] = (k < k1 && m0 + c + j < dim) ? P1[k * ld1 + a_[j]] * P2[k * ld2 + b_[j]] : 0.0;
+      s[kk * sld + c + j] = (k < k1 && m0 + c + j < dim) ? P1[k * ld1 + a_[j]] * P2[k * ld2 + b_[j]] : 0.0;
   }
 };
 
@@ -156,6 +156,9 @@ __device__ __forceinline__ double gauss_entry(double t2, double dx, double h, in
   return 0.886226925452758 / th * d;   // sqrt(pi) / 2 = 0.886226925452758...
 }
 
+// GAL selects the cell-average entries at compile time: their erf code would otherwise set the
+// register budget of the projection for the collocated entries too.
+template <bool GAL>
 struct OpGauss {              // element (k = grid row i, m = column c) = g_c(X_i - x_c) / nu_c (gauss_entry)
   const double* __restrict__ pos;    // N x 3
   const double* __restrict__ t2;     // K_long
@@ -163,7 +166,6 @@ struct OpGauss {              // element (k = grid row i, m = column c) = g_c(X_
   int K, d, n;
   double b, h;
   int dim;                           // number of columns
-  int gal;                           // Galerkin (cell-average) entries
   double x_[8], t2_[8], s_[8];
   __device__ void setup(int m0) {
     const int c = (threadIdx.x & 7) * 8;
@@ -179,14 +181,14 @@ struct OpGauss {              // element (k = grid row i, m = column c) = g_c(X_
       }
     }
   }
-  __device__ void fill(double* s, int64_t k0, int64_t k1, int m0) const {
+  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
     const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
     const int64_t i = k0 + kk;
     const double X = -b + (double)(i + 1) * h;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const double dx = X - x_[j];
-      s[kk * LDT + c + j] = (i < k1) ? gauss_entry(t2_[j], dx, h, gal) * s_[j] : 0.0;
+      s[kk * sld + c + j] = (i < k1) ? gauss_entry(t2_[j], dx, h, GAL ? 1 : 0) * s_[j] : 0.0;
     }
   }
 };
@@ -280,8 +282,8 @@ __global__ __launch_bounds__(256) void k_gemm(AOp A, BOp B, const GemmShape g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
   for (int64_t kb = k0; kb < k1; kb += TK) {
-    A.fill(sA, kb, k1, m0);
-    B.fill(sB, kb, k1, n0);
+    A.fill(sA, LDT, kb, k1, m0);
+    B.fill(sB, LDT, kb, k1, n0);
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
@@ -310,6 +312,58 @@ __global__ __launch_bounds__(256) void k_gemm(AOp A, BOp B, const GemmShape g) {
           *c = g.accumulate ? *c + acc[i][j][v] : acc[i][j][v];
         }
       }
+}
+
+// The same product for N <= 80 in one 64 x 80 tile per workgroup.  Wavefront w takes rows
+// 16w .. 16w+15 against all five 16-column blocks, so a narrow product (N = a Tucker rank)
+// is not split over two 64-column tiles of which the second is mostly padding, and an A tile
+// that is generated rather than loaded (the Gaussians) is made once instead of once per
+// column tile.  Each output element sums the same products in the same order as k_gemm.
+constexpr int TNW = 80;
+constexpr int LDTW = 2 * TN + 4;   // B tile: two 64-column fills, padded
+
+template <class AOp, class BOp>
+__global__ __launch_bounds__(256) void k_gemm_w(AOp A, BOp B, const GemmShape g) {
+  __shared__ double sA[TK * LDT];
+  __shared__ double sB[TK * LDTW];
+  const int m0 = blockIdx.x * TM;
+  const int64_t k0 = (int64_t)blockIdx.z * g.kper;
+  const int64_t k1 = min(g.K, k0 + g.kper);
+  BOp B1 = B;
+  A.setup(m0);
+  B.setup(0);
+  B1.setup(TN);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  d4v acc[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) acc[j] = d4v{0.0, 0.0, 0.0, 0.0};
+  for (int64_t kb = k0; kb < k1; kb += TK) {
+    A.fill(sA, LDT, kb, k1, m0);
+    B.fill(sB, LDTW, kb, k1, 0);
+    B1.fill(sB + TN, LDTW, kb, k1, TN);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      const double a = sA[(kk + lk) * LDT + 16 * w + lr];
+#pragma unroll
+      for (int j = 0; j < 5; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sB[(kk + lk) * LDTW + 16 * j + lr], acc[j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* C = g.C + (int64_t)blockIdx.z * g.split_stride;
+#pragma unroll
+  for (int j = 0; j < 5; ++j)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int m = m0 + 16 * w + 4 * v + lk;
+      const int n = 16 * j + lr;
+      if (m < g.M && n < g.N) {
+        double* c = C + (int64_t)m * g.ldc + n;
+        *c = g.accumulate ? *c + acc[j][v] : acc[j][v];
+      }
+    }
 }
 
 // Sum split slices: out[m*ldo + n] = sum_s part[s*stride + m*ldp + n].
@@ -686,6 +740,11 @@ rsd_status gemm(Context* ctx, const char* name, const AOp& A, const BOp& B, Gemm
     RSD_CHECK(div_up(g.N, TN) <= 65535 && splits <= 65535, RSD_E_UNSUPPORTED, "%s: product shape exceeds the launch grid",
               name);
     grid = dim3((unsigned)div_up(g.M, TM), (unsigned)div_up(g.N, TN), (unsigned)splits);
+    if (g.N <= TNW) {   // one column tile
+      grid.y = 1;
+      RSD_TIMED_LAUNCH(ctx, name, (k_gemm_w<AOp, BOp><<<grid, 256, 0, ctx->stream>>>(A, B, g)));
+      return RSD_OK;
+    }
   }
   RSD_TIMED_LAUNCH(ctx, name, (k_gemm<AOp, BOp><<<grid, 256, 0, ctx->stream>>>(A, B, g)));
   return RSD_OK;
@@ -1407,15 +1466,16 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
     const int rd = r[d];
     // 3. projection B_d^T[c][a] = sum_i A(i, c) U[i][a], side-matrix columns regenerated in LDS
     RSD_TRY(Bt[d].alloc(ctx, (size_t)C * ldu[d]));
-    OpGauss ga{};
-    ga.pos = d_pos; ga.t2 = t2d.p; ga.inv_nu = inv_nu[d].p; ga.K = K; ga.d = d; ga.n = n; ga.b = b; ga.h = h;
-    ga.dim = (int)C;
-    ga.gal = gal;
-    OpKM ub{U[d].p, ldu[d], rd};
-    GemmShape g{};
-    g.M = (int)C; g.N = rd; g.K = n; g.kper = ((n + TK - 1) / TK) * TK;
-    g.C = Bt[d].p; g.ldc = ldu[d]; g.split_stride = 0; g.accumulate = 0; g.tri = 0;
-    RSD_TRY(gemm(ctx, "project", ga, ub, g, 1));
+    auto project = [&](auto ga) -> rsd_status {
+      ga.pos = d_pos; ga.t2 = t2d.p; ga.inv_nu = inv_nu[d].p; ga.K = K; ga.d = d; ga.n = n; ga.b = b; ga.h = h;
+      ga.dim = (int)C;
+      OpKM ub{U[d].p, ldu[d], rd};
+      GemmShape g{};
+      g.M = (int)C; g.N = rd; g.K = n; g.kper = ((n + TK - 1) / TK) * TK;
+      g.C = Bt[d].p; g.ldc = ldu[d]; g.split_stride = 0; g.accumulate = 0; g.tri = 0;
+      return gemm(ctx, "project", ga, ub, g, 1);
+    };
+    RSD_TRY(gal ? project(OpGauss<true>{}) : project(OpGauss<false>{}));
   }
   t->ranks[0] = r[0];
   t->ranks[1] = r[1];
