@@ -31,7 +31,7 @@ rsd_status Context::dev_alloc(void** p, size_t bytes) {
   RSD_CHECK(budget == 0 || in_use + bytes <= budget, RSD_E_OOM,
             "HBM budget exceeded: %zu in use + %zu requested > %zu", in_use, bytes, budget);
   hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess && !block_cache.empty()) {
+  if (e != hipSuccess && (!block_cache.empty() || !scratch_cache.empty())) {
     (void)hipGetLastError();
     block_trim();
     e = hipMalloc(p, bytes);
@@ -83,10 +83,52 @@ void Context::block_release(void* p, size_t bytes) {
 }
 
 void Context::block_trim() {
-  if (block_cache.empty()) return;
+  if (block_cache.empty() && scratch_cache.empty()) return;
   (void)hipStreamSynchronize(stream);
   for (auto& b : block_cache) dev_free(b.first, b.second);
   block_cache.clear();
+  for (auto& b : scratch_cache) dev_free(b.first, b.second);
+  scratch_cache.clear();
+}
+
+rsd_status Context::scratch_get(void** p, size_t bytes) {
+  const size_t want = bytes == 0 ? 8 : bytes;
+  int best = -1;
+  for (int i = 0; i < (int)scratch_cache.size(); ++i) {
+    const size_t have = scratch_cache[i].second;
+    if (have >= want && have <= want + want / 4 + (1u << 20) && (best < 0 || have < scratch_cache[best].second))
+      best = i;
+  }
+  if (best >= 0) {
+    *p = scratch_cache[best].first;
+    scratch_live.push_back(scratch_cache[best]);
+    scratch_cache.erase(scratch_cache.begin() + best);
+    return RSD_OK;
+  }
+  RSD_TRY(dev_alloc(p, want));
+  scratch_live.emplace_back(*p, want);
+  return RSD_OK;
+}
+
+void Context::scratch_end() {
+  if (scratch_live.empty()) return;
+  (void)hipStreamSynchronize(stream);   // the call's streams have joined this one
+  for (auto& b : scratch_live) scratch_cache.push_back(b);
+  scratch_live.clear();
+  // keep at most 96 blocks and 4 GiB: small builds then reuse everything, while the Gram
+  // matrices of a large grid (3 n^2 doubles) are not held between calls
+  size_t total = 0;
+  for (auto& b : scratch_cache) total += b.second;
+  while (scratch_cache.size() > 96 || total > ((size_t)4 << 30)) {
+    int drop = 0;   // the smallest while over the count, else the largest
+    for (int i = 1; i < (int)scratch_cache.size(); ++i) {
+      const bool smaller = scratch_cache[i].second < scratch_cache[drop].second;
+      if (scratch_cache.size() > 96 ? smaller : !smaller) drop = i;
+    }
+    total -= scratch_cache[drop].second;
+    dev_free(scratch_cache[drop].first, scratch_cache[drop].second);
+    scratch_cache.erase(scratch_cache.begin() + drop);
+  }
 }
 
 rsd_status Context::workspace(size_t bytes, void** out) {
@@ -362,6 +404,7 @@ static void context_destroy(Context* ctx) {
     (void)hipEventDestroy(t.stop);
   }
   ctx->pending.clear();
+  ctx->scratch_end();
   ctx->block_trim();
   for (auto& kv : ctx->poly_cache)
     if (kv.second.p) ctx->dev_free(kv.second.p, kv.second.bytes);

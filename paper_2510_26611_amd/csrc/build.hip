@@ -707,24 +707,23 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* __restrict__ S
 }
 
 // ----------------------------------------------------------------- host helpers
+// A scratch buffer of a build or rank reduction, drawn from the context's scratch cache.  Its
+// block stays with the call (queued work may still use it) and returns to the cache when
+// the call's ScratchScope ends; releasing a DevBuf only forgets the pointer.
 struct DevBuf {
-  Context* ctx = nullptr;
   double* p = nullptr;
   size_t bytes = 0;
   rsd_status alloc(Context* c, size_t n) {
-    release();
-    ctx = c;
     bytes = sizeof(double) * (n ? n : 1);
-    return c->dev_alloc((void**)&p, bytes);
+    return c->scratch_get((void**)&p, bytes);
   }
-  void release() {   // work queued on the context stream may still read the buffer
-    if (p) {
-      (void)hipStreamSynchronize(ctx->stream);
-      ctx->dev_free(p, bytes);
-      p = nullptr;
-    }
-  }
-  ~DevBuf() { release(); }
+};
+
+// Declared first in an entry function, so that it ends last: one wait for the context
+// stream, then every scratch block of the call goes back to the cache.
+struct ScratchScope {
+  Context* c;
+  ~ScratchScope() { c->scratch_end(); }
 };
 
 inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -908,9 +907,7 @@ rsd_status subspace_eigvecs3(Context* ctx, rocblas_handle hb, double* G3, int n,
         GemmShape gu{};
         gu.split_stride = 0; gu.accumulate = 0; gu.tri = 0;
         gu.M = n; gu.N = r; gu.K = k; gu.kper = ((int64_t)k + TK - 1) / TK * TK; gu.C = U[d].p; gu.ldc = ldu;
-        RSD_TRY(gemm(ctx, "eig", OpKM{md.Z.p, n, n}, OpKM{Vsel.p, ldu, r}, gu, 1));
-        RSD_HIP(hipStreamSynchronize(st[d]));   // Vsel and the mode's buffers are released next
-        return RSD_OK;
+        return gemm(ctx, "eig", OpKM{md.Z.p, n, n}, OpKM{Vsel.p, ldu, r}, gu, 1);
       };
       st_all = finish();
       ctx->stream = main;
@@ -1041,8 +1038,8 @@ rsd_status tucker_canonical(Context* ctx, Tensor* t, DevBuf Bt[3], DevBuf U[3], 
     RSD_HIP(hipMemcpyAsync(Vd.p, Vh[d]->data(), sizeof(double) * Vh[d]->size(), hipMemcpyHostToDevice, s));
     RSD_TIMED_LAUNCH(ctx, "assemble", (k_assemble<<<grid1d(mode), 256, 0, s>>>(U[d].p, ldu[d], r[d], Vd.p, R, n,
                                                                                t->nm[d], t->nchunk, t->F + d * mode)));
-    RSD_HIP(hipStreamSynchronize(s));
   }
+  RSD_HIP(hipStreamSynchronize(s));   // the uploads read V1..V3, which go on return
   return RSD_OK;
 }
 
@@ -1274,6 +1271,7 @@ static rsd_status left_basis3(Context* ctx, rocblas_handle hb, double* const A[3
 // eps^2 times the largest eigenvalue (dense solver for small grids, the build's subspace
 // iteration for large ones), the projection, then steps 4-5 (tucker_canonical).
 rsd_status reduce_factors(Context* ctx, const Tensor* const* src, int nsrc, Tensor* t, const int i_lo[3]) {
+  ScratchScope scope{ctx};
   int64_t R = 0;
   for (int k = 0; k < nsrc; ++k) R += src[k]->R;
   if (R == 0) return alloc_factors(ctx, t, 0);
@@ -1288,12 +1286,7 @@ rsd_status reduce_factors(Context* ctx, const Tensor* const* src, int nsrc, Tens
   rocblas_handle hb = (rocblas_handle)ctx->blas;
   RSD_CHECK(rocblas_set_stream(hb, s) == rocblas_status_success, RSD_E_HIP, "rocblas_set_stream failed");
   rocblas_int* d_info = nullptr;
-  RSD_TRY(ctx->dev_alloc((void**)&d_info, 4096));
-  struct InfoGuard {
-    Context* c;
-    void* p;
-    ~InfoGuard() { c->dev_free(p, 4096); }
-  } ig{ctx, d_info};
+  RSD_TRY(ctx->scratch_get((void**)&d_info, 4096));
   DevBuf A[3], nu[3], xi, U[3], Bt[3];
   for (int d = 0; d < 3; ++d) {
     const int rows = t->nm[d];
@@ -1334,6 +1327,7 @@ rsd_status reduce_factors(Context* ctx, const Tensor* const* src, int nsrc, Tens
 }
 
 rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const double* d_pos) {
+  ScratchScope scope{ctx};
   const int n = t->n;
   const int K = t->sp.K_long;
   const int64_t N = t->N;
@@ -1391,12 +1385,7 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
   RSD_TRY(W3.alloc(ctx, 3 * (size_t)n));
   RSD_TRY(E3.alloc(ctx, 3 * (size_t)n));
   rocblas_int* d_info = nullptr;
-  RSD_TRY(ctx->dev_alloc((void**)&d_info, 4096));
-  struct InfoGuard {
-    Context* c;
-    void* p;
-    ~InfoGuard() { c->dev_free(p, 4096); }
-  } ig{ctx, d_info};
+  RSD_TRY(ctx->scratch_get((void**)&d_info, 4096));
 
   int r[3] = {0, 0, 0};
   int ldu[3] = {0, 0, 0};

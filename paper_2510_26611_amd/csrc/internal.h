@@ -114,6 +114,12 @@ struct Context {
   // in use and are freed when an allocation would exceed the budget or fail.
   std::vector<std::pair<void*, size_t>> block_cache;
 
+  // Scratch of the tensor builds and rank reductions (dozens of buffers per call).  Blocks
+  // handed out by scratch_get stay with the call until scratch_end, which waits for the
+  // context stream once and keeps them for the next call: no allocation, free or wait
+  // inside the call.  Cached blocks count as in use and go when the budget needs room.
+  std::vector<std::pair<void*, size_t>> scratch_cache, scratch_live;
+
   // short-range polynomial tables by (M, K_long, h_M, L_s, r_cut), shared by the tensors
   struct Poly {
     double* p = nullptr;
@@ -128,6 +134,8 @@ struct Context {
   rsd_status block_alloc(void** p, size_t* bytes);   // in: bytes wanted; out: size of the block handed out
   void block_release(void* p, size_t bytes);
   void block_trim();
+  rsd_status scratch_get(void** p, size_t bytes);
+  void scratch_end();
   rsd_status workspace(size_t bytes, void** out);
   rsd_status aux_streams();
   rsd_status timer_begin(const char* name, KernelTimer* t);
