@@ -1452,10 +1452,15 @@ void batch_free(Batch* b) {
 // the pair is closer than sigma between the roots; the first contact when moving in from far
 // away is rho* = the largest root over all pairs (-inf if no pair has a real root).
 // One workgroup takes one orbit direction u and cpb orientations; tpc threads share each
-// orientation's ligand atoms.  Only protein atoms within sigma + (ligand radius) of the line
-// x_P + rho u can have a real root with any ligand atom; each tile of protein atoms is
-// filtered against that cylinder and compacted in LDS, and every thread then runs over the
-// survivors.  A root is taken (with its square root) only when it can beat the thread's best:
+// orientation's ligand atoms.  A pair has a real root only when the protein atom lies within
+// sigma of the ligand atom's line y + rho u, i.e. when their projections onto the plane
+// normal to u are within sigma.  Each tile of protein atoms is filtered against the cylinder
+// of radius sigma + (ligand radius) about x_P + rho u (no ligand atom's line leaves it), and
+// the survivors are sorted in LDS by a 2-D bin of their projection.  A thread then visits
+// only the bins within sigma of its line's projection, row by row as contiguous ranges.
+// Every pair with a real root is examined with the same arithmetic as without the bins, and
+// the maximum does not depend on the order, so the radii are the same.  A root is taken
+// (with its square root) only when it can beat the thread's best:
 // -b + sqrt(disc) > best  <=>  disc >= 0 and (best + b < 0 or disc > (best + b)^2).
 struct ContactParams {
   const double4* __restrict__ atoms;   // protein atoms (x, y, z, charge)
@@ -1476,15 +1481,30 @@ struct ContactParams {
 };
 
 constexpr int kContactTile = 1024;   // protein atoms filtered per pass
+constexpr int kContactBins = 32;     // at most this many bins per axis of the projection plane
 
 __global__ __launch_bounds__(256) void k_contact(const ContactParams a) {
-  __shared__ double4 s_at[kContactTile];
+  __shared__ double4 s_at[kContactTile];                        // the tile's survivors, by bin
+  __shared__ int s_key[kContactTile];                           // bin of each tile atom, -1 if filtered
+  __shared__ int s_start[kContactBins * kContactBins + 1];      // first survivor of each bin
+  __shared__ int s_fill[kContactBins * kContactBins];
   __shared__ double s_best[256];
-  __shared__ int s_cnt;
   const int tid = threadIdx.x;
   const int64_t ui = (int64_t)blockIdx.x / a.qblocks;
   const int64_t qb = (int64_t)blockIdx.x % a.qblocks;
   const double ux = a.dirs[3 * ui], uy = a.dirs[3 * ui + 1], uz = a.dirs[3 * ui + 2];
+  // an orthonormal basis (e1, e2) of the plane normal to u
+  double e1x, e1y, e1z;
+  {
+    const double ax = fabs(ux), ay = fabs(uy), az = fabs(uz);
+    // u x (the coordinate axis least aligned with u)
+    if (ax <= ay && ax <= az) { e1x = 0.0; e1y = uz; e1z = -uy; }
+    else if (ay <= az)        { e1x = -uz; e1y = 0.0; e1z = ux; }
+    else                      { e1x = uy; e1y = -ux; e1z = 0.0; }
+    const double inv = 1.0 / sqrt(fma(e1x, e1x, fma(e1y, e1y, e1z * e1z)));
+    e1x *= inv; e1y *= inv; e1z *= inv;
+  }
+  const double e2x = uy * e1z - uz * e1y, e2y = uz * e1x - ux * e1z, e2z = ux * e1y - uy * e1x;
   const int j = tid / a.tpc, lt = tid - (tid / a.tpc) * a.tpc;
   const int64_t q = qb * a.cpb + j;
   const bool active = j < a.cpb && q < a.Q;
@@ -1494,37 +1514,84 @@ __global__ __launch_bounds__(256) void k_contact(const ContactParams a) {
   const double rc = a.sigma + a.rlig[0] + 1e-3;   // the cylinder radius, with a margin for rounding
   const double rc2 = rc * rc;
   const double s2 = a.sigma * a.sigma;
+  // bins: the square [-rc, rc]^2 of the plane in nb x nb cells of edge eb (at least sigma / 2)
+  const double eb = fmax(0.5 * a.sigma, 2.0 * rc / kContactBins);
+  const int nb = min(kContactBins, max(1, (int)ceil(2.0 * rc / eb)));
+  const double inv_eb = 1.0 / eb;
+  const double rs = a.sigma * (1.0 + 1e-9) + 1e-6;   // query radius about a line, with a margin
+  auto bin_of = [&](double c) { return min(nb - 1, max(0, (int)floor((c + rc) * inv_eb))); };
   double best = -INFINITY;
   const int nl = (a.L + a.tpc - 1) / a.tpc;
   for (int il = 0; il < nl; ++il) {
     const int l = lt + il * a.tpc;
     const bool has = active && valid && l < a.L;
     double3 y = make_double3(0.0, 0.0, 0.0);
-    if (has) y = place(R, t, a.lig[l]);
+    int bx0 = 0, bx1 = -1, by0 = 0, by1 = -1;
+    if (has) {
+      y = place(R, t, a.lig[l]);
+      const double dx = y.x - a.xP[0], dy = y.y - a.xP[1], dz = y.z - a.xP[2];
+      const double c1 = fma(e1x, dx, fma(e1y, dy, e1z * dz)), c2 = fma(e2x, dx, fma(e2y, dy, e2z * dz));
+      bx0 = bin_of(c1 - rs); bx1 = bin_of(c1 + rs);
+      by0 = bin_of(c2 - rs); by1 = bin_of(c2 + rs);
+    }
     for (int64_t m0 = 0; m0 < a.N; m0 += kContactTile) {
-      if (tid == 0) s_cnt = 0;
+      // bin of every atom of the tile within the cylinder
+      for (int k = tid; k < nb * nb; k += 256) s_fill[k] = 0;
       __syncthreads();
       for (int k = tid; k < kContactTile; k += 256) {
         const int64_t m = m0 + k;
+        int key = -1;
         if (m < a.N) {
           const double4 p = a.atoms[m];
           const double dx = p.x - a.xP[0], dy = p.y - a.xP[1], dz = p.z - a.xP[2];
           const double pr = fma(ux, dx, fma(uy, dy, uz * dz));
           const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
-          if (d2 - pr * pr <= rc2) s_at[atomicAdd(&s_cnt, 1)] = p;
+          if (d2 - pr * pr <= rc2) {
+            const double c1 = fma(e1x, dx, fma(e1y, dy, e1z * dz)), c2 = fma(e2x, dx, fma(e2y, dy, e2z * dz));
+            key = bin_of(c2) * nb + bin_of(c1);
+            atomicAdd(&s_fill[key], 1);
+          }
         }
+        s_key[k] = key;
       }
       __syncthreads();
-      const int cnt = s_cnt;
+      if (tid < 64) {   // exclusive scan of the bin counts (one wavefront)
+        int carry = 0;
+        for (int b0 = 0; b0 < nb * nb; b0 += 64) {
+          const int b = b0 + tid;
+          const int v = b < nb * nb ? s_fill[b] : 0;
+          int incl = v;
+#pragma unroll
+          for (int off = 1; off < 64; off <<= 1) {
+            const int w = __shfl_up(incl, off, 64);
+            if (tid >= off) incl += w;
+          }
+          if (b < nb * nb) {
+            s_start[b] = carry + incl - v;
+            s_fill[b] = carry + incl - v;
+          }
+          carry += __shfl(incl, 63, 64);
+        }
+        if (tid == 0) s_start[nb * nb] = carry;
+      }
+      __syncthreads();
+      for (int k = tid; k < kContactTile; k += 256) {
+        const int key = s_key[k];
+        if (key >= 0) s_at[atomicAdd(&s_fill[key], 1)] = a.atoms[m0 + k];
+      }
+      __syncthreads();
       if (has) {
-        for (int k = 0; k < cnt; ++k) {
-          const double4 p = s_at[k];
-          const double wx = y.x - p.x, wy = y.y - p.y, wz = y.z - p.z;
-          const double bu = fma(ux, wx, fma(uy, wy, uz * wz));
-          const double ww = fma(wx, wx, fma(wy, wy, wz * wz));
-          const double disc = fma(bu, bu, s2 - ww);
-          const double g = best + bu;
-          if (disc >= 0.0 && (g < 0.0 || disc > g * g)) best = fmax(best, sqrt(disc) - bu);
+        for (int by = by0; by <= by1; ++by) {
+          const int k1 = s_start[by * nb + bx1 + 1];
+          for (int k = s_start[by * nb + bx0]; k < k1; ++k) {
+            const double4 p = s_at[k];
+            const double wx = y.x - p.x, wy = y.y - p.y, wz = y.z - p.z;
+            const double bu = fma(ux, wx, fma(uy, wy, uz * wz));
+            const double ww = fma(wx, wx, fma(wy, wy, wz * wz));
+            const double disc = fma(bu, bu, s2 - ww);
+            const double g = best + bu;
+            if (disc >= 0.0 && (g < 0.0 || disc > g * g)) best = fmax(best, sqrt(disc) - bu);
+          }
         }
       }
       __syncthreads();
