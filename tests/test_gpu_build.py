@@ -84,6 +84,28 @@ def test_cfg1_build_within_rhosvd_bound(rs, ctx):
         assert np.array_equal(F1[d], F2[d])
 
 
+def test_reused_scratch_gives_the_same_tensor(rs, ctx):
+    """Builds and rank reductions take their scratch from a per-context cache.  A build after
+    others of different sizes (which leave other contents in the reused blocks) gives the
+    same tensor bit for bit, so no kernel reads scratch it has not written."""
+    c1, c2 = configs.CONFIG1, configs.CONFIG2
+    w1, w2 = configs.make(c1, P=1), configs.make(c2, P=1)
+    build = lambda c, w: rs.build_rs_tensor(ctx, w.protein_charges, w.protein_positions, c.n, c.b,  # noqa: E731
+                                            rs.Sinc.from_config(c))
+    ta = build(c1, w1)
+    Fa = ta.export()
+    tb = build(c2, w2)
+    loc = tb.restrict(np.array([15.0, -8.0, -8.0]), np.array([31.0, 8.0, 8.0]), c2.eps)
+    tc = build(c1, w1)
+    Fc = tc.export()
+    for d in range(3):
+        assert np.array_equal(Fa[d], Fc[d])
+    loc2 = tb.restrict(np.array([15.0, -8.0, -8.0]), np.array([31.0, 8.0, 8.0]), c2.eps)
+    assert all(np.array_equal(x, y) for x, y in zip(loc.export(), loc2.export()))
+    for t in (ta, tb, loc, tc, loc2):
+        t.free()
+
+
 @pytest.mark.timeout(900)
 def test_cfg2_build_within_rhosvd_bound(rs, ctx):
     _check_build(rs, ctx, configs.CONFIG2, 512, "cfg2")
