@@ -25,6 +25,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -362,11 +363,16 @@ __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4*
     const int ny = cy1 - cy0 + 1;
     const int nrows = ny * (cz1 - cz0 + 1);
     int qh = 0, qt = 0;   // ring head / tail (wave-uniform)
+    // The accept flag asks whether some pair is closer than sigma.  When sigma <= r_cut every
+    // such pair is queued, so the minimum is taken over the queued pairs in the drain instead
+    // of over every candidate test.
+    const bool mind_in_drain = a.sig2 <= a.rc2;
 
     auto drain = [&](int m) {   // evaluate queued pairs [qh, qh + m), m <= 64
       wave_sync();
       if (lane < m) {
         const Pair e = q[(qh + lane) & (kQueue - 1)];
+        if (mind_in_drain) mind = fmin(mind, e.d2);   // once per queued pair
         double gs = 0.0, dg = 0.0;
         if (!GRAD && a.poly) {
           // g(d^2) from the polynomial table: interval and position s in [-1, 1]
@@ -409,72 +415,79 @@ __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4*
       wave_sync();
     };
 
-    for (int rb = 0; rb < nrows; rb += 64) {
-      const int r = rb + lane;
-      int seg_start = 0, seg_len = 0;
-      if (r < nrows) {
-        const int cy = cy0 + r % ny, cz = cz0 + r / ny;
-        const double ylo = g.origin + cy * g.edge, yhi = ylo + g.edge;
-        const double zlo = g.origin + cz * g.edge, zhi = zlo + g.edge;
-        const double dy = fmax(fmax(ylo - ty, ty - yhi), 0.0);
-        const double dz = fmax(fmax(zlo - tz, tz - zhi), 0.0);
-        const double rem = Rc2 - (dy * dy + dz * dz);
-        if (rem >= 0.0) {
-          const double hw = sqrt(rem);
-          const int cx0 = cell_floor((tx - hw - g.origin) * g.inv_edge, g.dim);
-          const int cx1 = cell_floor((tx + hw - g.origin) * g.inv_edge, g.dim);
-          const int base = (cz * g.dim + cy) * g.dim;
-          seg_start = a.cell_start[base + cx0];
-          seg_len = a.cell_start[base + cx1 + 1] - seg_start;
-        }
-      }
-      // inclusive scan of the segment lengths across the wavefront
-      int incl = seg_len;
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const int v = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += v;
-      }
-      const int total = __shfl(incl, 63, 64);
-      rowoff[lane] = incl - seg_len;
-      rowstart[lane] = seg_start;
-      wave_sync();
-      for (int cb = 0; cb < total; cb += 64) {
-        const int k = cb + lane;
-        const bool act = k < total;
-        double4 at = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (act) {
-          int lo = 0, hi = 63;               // last row whose offset is <= k
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (rowoff[mid] <= k) lo = mid; else hi = mid - 1;
+    auto scan = [&](auto every) {   // every: the minimum over every test (sigma > r_cut)
+      for (int rb = 0; rb < nrows; rb += 64) {
+        const int r = rb + lane;
+        int seg_start = 0, seg_len = 0;
+        if (r < nrows) {
+          const int cy = cy0 + r % ny, cz = cz0 + r / ny;
+          const double ylo = g.origin + cy * g.edge, yhi = ylo + g.edge;
+          const double zlo = g.origin + cz * g.edge, zhi = zlo + g.edge;
+          const double dy = fmax(fmax(ylo - ty, ty - yhi), 0.0);
+          const double dz = fmax(fmax(zlo - tz, tz - zhi), 0.0);
+          const double rem = Rc2 - (dy * dy + dz * dz);
+          if (rem >= 0.0) {
+            const double hw = sqrt(rem);
+            const int cx0 = cell_floor((tx - hw - g.origin) * g.inv_edge, g.dim);
+            const int cx1 = cell_floor((tx + hw - g.origin) * g.inv_edge, g.dim);
+            const int base = (cz * g.dim + cy) * g.dim;
+            seg_start = a.cell_start[base + cx0];
+            seg_len = a.cell_start[base + cx1 + 1] - seg_start;
           }
-          at = a.atoms[rowstart[lo] + (k - rowoff[lo])];
         }
-        for (int l = 0; l < L; ++l) {
-          const double4 y = s_y[l];
-          const double dx = y.x - at.x, dy = y.y - at.y, dz = y.z - at.z;
-          const double d2 = (dx * dx + dy * dy) + dz * dz;     // ((dx^2 + dy^2) + dz^2), no fma
-          const bool hit = act && (d2 < a.rc2);
-          if (act) mind = fmin(mind, d2);
-          const uint64_t m = __ballot(hit);
-          if (m != 0ull) {
-            if (hit) {
-              Pair& e = q[(qt + lane_prefix(m)) & (kQueue - 1)];
-              e.d2 = d2;
-              e.zz = at.w * y.w;
-              if constexpr (GRAD) {
-                e.dx = dx; e.dy = dy; e.dz = dz; e.l = l;
-              }
-              ++cnt;
+        // inclusive scan of the segment lengths across the wavefront
+        int incl = seg_len;
+  #pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const int v = __shfl_up(incl, off, 64);
+          if (lane >= off) incl += v;
+        }
+        const int total = __shfl(incl, 63, 64);
+        rowoff[lane] = incl - seg_len;
+        rowstart[lane] = seg_start;
+        wave_sync();
+        for (int cb = 0; cb < total; cb += 64) {
+          const int k = cb + lane;
+          const bool act = k < total;
+          // a lane without a candidate takes an atom so far away that every test fails
+          double4 at = make_double4(1e300, 1e300, 1e300, 0.0);
+          if (act) {
+            int lo = 0, hi = 63;               // last row whose offset is <= k
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (rowoff[mid] <= k) lo = mid; else hi = mid - 1;
             }
-            qt += __popcll(m);
-            if (qt - qh >= 64) drain(64);
+            at = a.atoms[rowstart[lo] + (k - rowoff[lo])];
+          }
+          for (int l = 0; l < L; ++l) {
+            const double4 y = s_y[l];
+            const double dx = y.x - at.x, dy = y.y - at.y, dz = y.z - at.z;
+            const double d2 = (dx * dx + dy * dy) + dz * dz;     // ((dx^2 + dy^2) + dz^2), no fma
+            const bool hit = d2 < a.rc2;                          // +inf for a lane without a candidate
+            if constexpr (decltype(every)::value) mind = fmin(mind, d2);
+            const uint64_t m = __ballot(hit);
+            if (m != 0ull) {
+              if (hit) {
+                Pair& e = q[(qt + lane_prefix(m)) & (kQueue - 1)];
+                e.d2 = d2;
+                e.zz = at.w * y.w;
+                if constexpr (GRAD) {
+                  e.dx = dx; e.dy = dy; e.dz = dz; e.l = l;
+                }
+                ++cnt;
+              }
+              qt += __popcll(m);
+              if (qt - qh >= 64) drain(64);
+            }
           }
         }
+        wave_sync();
       }
-      wave_sync();
-    }
+    };
+    if (mind_in_drain)
+      scan(std::false_type{});
+    else
+      scan(std::true_type{});
     if (qt > qh) drain(qt - qh);
   }
 

@@ -11,7 +11,8 @@ import numpy as np
 import pytest
 
 sys.path.insert(0, os.path.dirname(__file__))
-from gpu_common import assert_parity, near_threshold_poses, oracle_factors, oracle_score  # noqa: E402
+from gpu_common import assert_parity, near_threshold_poses, oracle_factors, oracle_score, sinc_parts  # noqa: E402
+from oracle import score as oscore  # noqa: E402
 from workloads import configs, generators as gen  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -105,6 +106,30 @@ def test_cfg1_near_thresholds_and_edge_poses(rs, ctx, cfg1, mode):
     g = _run(rs, ctx, t, wl, q, tt, cfg.sigma, mode=mode)
     assert_parity(g, ref, grad=True, label="cfg1 thresholds")
     assert ref["flags"][-3] == 4 and ref["flags"][-4] == 4 and ref["flags"][-1] == 0
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_vdw_distance_beyond_the_cutoff(rs, ctx, cfg1, mode):
+    """vdw_min > r_cut: the accept flag then needs the minimum over every candidate pair, not
+    only over the pairs within the cutoff (a pose can be rejected with no pair counted)."""
+    cfg, wl, F, _ = cfg1
+    r_cut, vdw = 3.0, 4.5
+    t = rs.tensor_import(ctx, F, cfg.n, cfg.b, rs.Sinc(cfg.M, cfg.h_M, cfg.L_s, cfg.K_long, r_cut, cfg.eps),
+                         wl.protein_charges, wl.protein_positions)
+    tr = wl.trans * (15.5 / 18.0)   # poses that touch the protein
+    q1, t1 = near_threshold_poses(cfg, wl, wl.quats, tr, vdw, 24)
+    q = np.concatenate([q1, wl.quats[24:64]])
+    tt = np.concatenate([t1, tr[24:64]])
+    _, (ts, ws) = sinc_parts(cfg)
+    ref = oscore.score(F, cfg.n, cfg.b, wl.protein_positions, wl.protein_charges, ts, ws, r_cut, wl.ligand_charges,
+                       wl.ligand_positions, q, tt, vdw, want_grad=True)
+    g = _run(rs, ctx, t, wl, q, tt, vdw, mode=mode)
+    assert_parity(g, ref, grad=True, label="vdw beyond the cutoff")
+    rejected_uncounted = np.sum(((ref["flags"] & 3) == 2) & (ref["counts"] == 0))
+    print(f"{len(q)} poses: accepted {int(np.sum(ref['flags'] & 1))}, rejected with no pair within r_cut "
+          f"{int(rejected_uncounted)}")
+    assert rejected_uncounted > 0
+    t.free()
 
 
 @pytest.mark.parametrize("mode", [1, 2])
