@@ -325,6 +325,12 @@ void rsd_tensor_free(rsd_tensor* t);
  *                     Chebyshev interpolants in d^2 (one per quadrature and cutoff, kept by the
  *                     context; checked on the host to 1e-11 relative, else not used); gradient
  *                     calls and 0 evaluate the exponentials
+ *   "pose_order"      chunk-major long range: 0 automatic, 1 always, 2 never take the poses in
+ *                     spatial order (a counting sort of their translations by a Morton code of
+ *                     32^3 cells over the box, on the device).  On grids where one rank chunk's
+ *                     rows (3 x n x 512 bytes) exceed the 4 MiB L2 of an XCD (n >= 2731, the
+ *                     automatic choice) the gathers then reuse the L2; the results are those of
+ *                     input order bit for bit, each written to its own pose
  *   "overlap"         1: in chunk-major scoring the short-range kernel runs on a second stream
  *                     of the context beside the long-range kernel (joined before the results
  *                     are combined); 0 (default): one stream.  The long-range gathers slow

@@ -1195,6 +1195,11 @@ rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t va
     ctx->opt_short_poly = (int)value;
     return RSD_OK;
   }
+  if (std::strcmp(name, "pose_order") == 0) {
+    RSD_CHECK(value >= 0 && value <= 2, RSD_E_INVALID, "pose_order must be 0, 1 or 2");
+    ctx->opt_pose_order = (int)value;
+    return RSD_OK;
+  }
   if (std::strcmp(name, "overlap") == 0) {
     RSD_CHECK(value == 0 || value == 1, RSD_E_INVALID, "overlap must be 0 or 1");
     ctx->opt_overlap = (int)value;

@@ -100,6 +100,7 @@ struct Context {
   int opt_short_waves = 0;     // short-range kernel: wavefronts per workgroup (0 = automatic)
   int opt_use_tuning = 1;      // apply shapes recorded by rsd_autotune to automatic calls
   int opt_overlap = 0;         // chunk-major scoring: short range on a second stream beside the long range
+  int opt_pose_order = 0;      // chunk-major scoring: poses in spatial order (0 automatic, 1 always, 2 never)
   int opt_short_poly = 1;      // tensors made with this context carry the short-range polynomial table
   int opt_shared_mode3 = 1;    // chunk-major scoring lerps a chunk's distinct U_3 columns once per atom
   // launch shapes recorded by rsd_autotune: (n, nchunk, N, L, grad) -> (mode, ppw, short waves)

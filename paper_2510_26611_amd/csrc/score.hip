@@ -550,6 +550,9 @@ struct LongParams {
   const int* __restrict__ slice; // [R]
   int u3_ld;
   int64_t R;
+  // spatial order of the poses (or null): work slot i takes pose perm[i], and the partials
+  // of slot i are stored at i; the combination writes each result back to its pose
+  const int* __restrict__ perm;
 };
 
 constexpr int kSlots = 4;        // distinct mode-3 columns per chunk served from LDS
@@ -612,7 +615,8 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
     bool ok = false;
     if (p < a.P) {
       double R[9], tv[3];
-      if (pose_frame(a.quats + 4 * p, a.trans + 3 * p, R, tv)) {
+      const int64_t pi = a.perm ? (int64_t)a.perm[p] : p;
+      if (pose_frame(a.quats + 4 * pi, a.trans + 3 * pi, R, tv)) {
         const double3 y = place(R, tv, s_lig[l]);
         if (in_grid(y.x, a.X0[0], a.inv_h, a.smax[0]) && in_grid(y.y, a.X0[1], a.inv_h, a.smax[1]) &&
             in_grid(y.z, a.X0[2], a.inv_h, a.smax[2])) {
@@ -743,15 +747,17 @@ template <bool GRAD>
 __device__ __forceinline__ void combine_pose(const double* __restrict__ part, int nchunk, int64_t P,
                                              const double* __restrict__ es, const double* __restrict__ gs,
                                              const uint8_t* __restrict__ flags, double* __restrict__ E,
-                                             double* __restrict__ El, double* __restrict__ grads, int64_t p) {
+                                             double* __restrict__ El, double* __restrict__ grads, int64_t slot,
+                                             const int* __restrict__ perm) {
   constexpr int S = GRAD ? 7 : 1;
+  const int64_t p = perm ? (int64_t)perm[slot] : slot;   // the pose whose partials are at slot
   const bool dom = (flags[p] & RSD_FLAG_IN_DOMAIN) != 0;
   double acc[S];
 #pragma unroll
   for (int k = 0; k < S; ++k) acc[k] = 0.0;
   if (dom) {
     for (int c = 0; c < nchunk; ++c) {
-      const double* o = part + ((int64_t)c * P + p) * S;
+      const double* o = part + ((int64_t)c * P + slot) * S;
 #pragma unroll
       for (int k = 0; k < S; ++k) acc[k] += o[k];
     }
@@ -768,9 +774,79 @@ __device__ __forceinline__ void combine_pose(const double* __restrict__ part, in
 template <bool GRAD>
 __global__ void k_combine(const double* __restrict__ part, int nchunk, int64_t P, const double* __restrict__ es,
                           const double* __restrict__ gs, const uint8_t* __restrict__ flags, double* __restrict__ E,
-                          double* __restrict__ El, double* __restrict__ grads) {
+                          double* __restrict__ El, double* __restrict__ grads, const int* __restrict__ perm) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x)
+    combine_pose<GRAD>(part, nchunk, P, es, gs, flags, E, El, grads, i, perm);
+}
+
+// ---------------------------------------------------------------- spatial order of the poses
+// On a large grid one rank chunk's rows (3 x n x 512 bytes) exceed an XCD's L2, and poses in
+// input order touch rows all over it.  Ordering the poses by a Morton code of their
+// translation's cell (32 cells per axis over the box) makes the poses that an XCD works on
+// together touch a narrow band of rows.  A counting sort on the device (histogram, scan,
+// scatter; kernels only, so it can be captured in a HIP graph) gives the permutation; the
+// order within a cell is that of the atomics, which no result depends on.
+constexpr int kSortBits = 5;
+constexpr int kSortCells = 1 << (3 * kSortBits);
+
+__device__ __forceinline__ uint32_t spread_bits(uint32_t v) {   // bit b of v to bit 3b
+  uint32_t r = 0;
+#pragma unroll
+  for (int b = 0; b < kSortBits; ++b) r |= ((v >> b) & 1u) << (3 * b);
+  return r;
+}
+
+__device__ __forceinline__ int pose_cell(const double* __restrict__ t3, double lo, double inv_w) {
+  uint32_t c[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double x = (t3[d] - lo) * inv_w;   // NaN and out-of-box translations go to an edge cell
+    c[d] = x >= (double)((1 << kSortBits) - 1) ? (uint32_t)((1 << kSortBits) - 1) : x > 0.0 ? (uint32_t)x : 0u;
+  }
+  return (int)(spread_bits(c[0]) | spread_bits(c[1]) << 1 | spread_bits(c[2]) << 2);
+}
+
+__global__ void k_fill_int(int* __restrict__ a, int64_t n, int v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+__global__ void k_pose_hist(const double* __restrict__ trans, int64_t P, double lo, double inv_w,
+                            int* __restrict__ cell_of, int* __restrict__ hist) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+    const int c = pose_cell(trans + 3 * p, lo, inv_w);
+    cell_of[p] = c;
+    atomicAdd(&hist[c], 1);
+  }
+}
+
+// exclusive scan of the kSortCells counts in place, one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void k_cell_offsets(int* __restrict__ hist) {
+  __shared__ int s_part[1024];
+  constexpr int per = kSortCells / 1024;
+  const int t = threadIdx.x;
+  int sum = 0;
+  for (int k = 0; k < per; ++k) sum += hist[t * per + k];
+  s_part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {   // inclusive scan of the partial sums
+    const int v = t >= off ? s_part[t - off] : 0;
+    __syncthreads();
+    s_part[t] += v;
+    __syncthreads();
+  }
+  int run = s_part[t] - sum;
+  for (int k = 0; k < per; ++k) {
+    const int c = hist[t * per + k];
+    hist[t * per + k] = run;
+    run += c;
+  }
+}
+
+__global__ void k_pose_scatter(const int* __restrict__ cell_of, int64_t P, int* __restrict__ next,
+                               int* __restrict__ perm) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x)
-    combine_pose<GRAD>(part, nchunk, P, es, gs, flags, E, El, grads, p);
+    perm[atomicAdd(&next[cell_of[p]], 1)] = (int)p;
 }
 
 // ---------------------------------------------------------------- many requests per launch
@@ -812,6 +888,7 @@ __device__ __forceinline__ void make_global(LongParams& a) {
   a.part = global_ptr(a.part);
   a.U3 = global_ptr(a.U3);
   a.slice = global_ptr(a.slice);
+  a.perm = global_ptr(a.perm);
 }
 
 __device__ __forceinline__ void make_global(ScoreParams& a) {
@@ -911,7 +988,7 @@ __global__ void k_batch_combine(const BatchDesc* __restrict__ d, int nreq, int64
     const int r = find_request(d, nreq, g, [](const BatchDesc& x) { return x.pose_base; });
     const BatchDesc& x = d[r];
     combine_pose<false>(x.lp.part, x.lp.nchunk, x.sp.P, x.sp.es, nullptr, x.sp.flags, x.sp.E, x.sp.El, nullptr,
-                        g - x.pose_base);
+                        g - x.pose_base, x.lp.perm);
   }
 }
 
@@ -1041,6 +1118,35 @@ LongParams make_long_params(const Tensor* t, const ScoreIO& io, const double4* l
   return lp;
 }
 
+// Whether a call's long-range gathers take the poses in spatial order: option pose_order
+// (0 automatic, 1 always, 2 never); automatically when one rank chunk's rows (3 modes x n
+// rows x 64 columns) exceed the 4 MiB L2 of an XCD.
+bool sort_poses(const Context* ctx, const Tensor* t) {
+  if (ctx->opt_pose_order == 1) return true;
+  if (ctx->opt_pose_order == 2) return false;
+  return (size_t)3 * (size_t)t->n * kChunk * sizeof(double) > ((size_t)4 << 20);
+}
+
+// The permutation of P poses into spatial order (hist: kSortCells ints, cell_of and perm: P).
+rsd_status launch_pose_sort(Context* ctx, hipStream_t s, const Tensor* t, const double* trans, int64_t P, int* hist,
+                            int* cell_of, int* perm) {
+  const double lo = -t->b, inv_w = (double)(1 << kSortBits) / (2.0 * t->b);
+  const unsigned g = (unsigned)std::min<int64_t>((P + 255) / 256, 65536);
+  hipStream_t saved = ctx->stream;
+  ctx->stream = s;   // the timers record on the stream the sort runs on
+  rsd_status st = RSD_OK;
+  auto run = [&]() -> rsd_status {
+    RSD_TIMED_LAUNCH(ctx, "sort", (k_fill_int<<<kSortCells / 256, 256, 0, s>>>(hist, kSortCells, 0)));
+    RSD_TIMED_LAUNCH(ctx, "sort", (k_pose_hist<<<g, 256, 0, s>>>(trans, P, lo, inv_w, cell_of, hist)));
+    RSD_TIMED_LAUNCH(ctx, "sort", (k_cell_offsets<<<1, 1024, 0, s>>>(hist)));
+    RSD_TIMED_LAUNCH(ctx, "sort", (k_pose_scatter<<<g, 256, 0, s>>>(cell_of, P, hist, perm)));
+    return RSD_OK;
+  };
+  st = run();
+  ctx->stream = saved;
+  return st;
+}
+
 }  // namespace
 
 // Launch shape recorded by rsd_autotune for this workload, applied when the caller left all
@@ -1076,7 +1182,10 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   const size_t off_es = off_r + 256;
   const size_t off_gs = off_es + sizeof(double) * (size_t)(split ? P : 0);
   const size_t off_part = off_gs + sizeof(double) * (size_t)(split && grad ? 6 * P : 0);
-  const size_t total = off_part + sizeof(double) * (size_t)(split ? (int64_t)t->nchunk * P * S : 0);
+  const bool sorted = split && P > 1 && sort_poses(ctx, t);
+  // spatial order: cell histogram (kSortCells) | cell of each pose (P) | permutation (P)
+  const size_t off_sort = off_part + sizeof(double) * (size_t)(split ? (int64_t)t->nchunk * P * S : 0);
+  const size_t total = off_sort + sizeof(int) * (size_t)(sorted ? kSortCells + 2 * P : 0);
   void* ws = nullptr;
   RSD_TRY(ctx->workspace(total, &ws));
   char* w8 = (char*)ws;
@@ -1102,8 +1211,14 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
     }
     return RSD_OK;
   }
-  const LongParams lp = make_long_params(t, io, lig, ppw, (double*)(w8 + off_part), u3);
+  LongParams lp = make_long_params(t, io, lig, ppw, (double*)(w8 + off_part), u3);
   RSD_CHECK(lp.per_xcd * 8 <= 0x7fffffffLL, RSD_E_UNSUPPORTED, "too many poses in one call");
+  if (sorted) {
+    int* hist = (int*)(w8 + off_sort);
+    int* perm = hist + kSortCells + P;
+    RSD_TRY(launch_pose_sort(ctx, s, t, io.trans, P, hist, hist + kSortCells, perm));
+    lp.perm = perm;
+  }
   const dim3 g2((unsigned)(lp.per_xcd * 8));
   const size_t lds2 = long_lds(L, ppw, grad, u3);
   const unsigned gc = (unsigned)std::min<int64_t>((P + 255) / 256, 65536);
@@ -1145,10 +1260,10 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   }
   if (grad) {
     RSD_TIMED_LAUNCH(ctx, "combine", (k_combine<true><<<gc, 256, 0, s>>>(lp.part, t->nchunk, P, a.es, a.gs, io.flags,
-                                                                           io.E, io.El, io.grads)));
+                                                                           io.E, io.El, io.grads, lp.perm)));
   } else {
     RSD_TIMED_LAUNCH(ctx, "combine", (k_combine<false><<<gc, 256, 0, s>>>(lp.part, t->nchunk, P, a.es, a.gs,
-                                                                            io.flags, io.E, io.El, nullptr)));
+                                                                            io.flags, io.E, io.El, nullptr, lp.perm)));
   }
   return RSD_OK;
 }
@@ -1241,6 +1356,15 @@ struct Batch {
     int64_t units;         // workgroups (short range) or work-list slots per XCD (long range)
   };
   std::vector<Launch> shorts, longs;
+  struct Sort {            // a request whose poses the long range takes in spatial order
+    const Tensor* t;
+    const double* trans;
+    int64_t P;
+    int* perm;
+  };
+  std::vector<Sort> sorts;
+  int* sort_hist = nullptr;   // shared by the requests' sorts, which run one after another
+  int* sort_cell = nullptr;
   int64_t poses = 0;
   std::vector<BatchDesc> host_table;   // source of the (asynchronous) table upload
   hipEvent_t uploaded = nullptr;       // recorded after the upload: host_table may go once it completes
@@ -1313,7 +1437,8 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
   b->ctx = ctx;
   b->nreq = nreq;
   std::vector<int64_t> off_lig(nreq), off_es(nreq), off_part(nreq);
-  int64_t nlig = 0, nes = 0, npart = 0;
+  std::vector<int64_t> off_perm(nreq, -1);
+  int64_t nlig = 0, nes = 0, npart = 0, nperm = 0, maxsort = 0;
   for (int k = 0; k < nreq; ++k) {
     const rsd_request& q = req_in[order[k]];
     const Tensor* t = static_cast<const Tensor*>(q.tensor);
@@ -1323,13 +1448,22 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     nes += q.P;
     off_part[k] = npart;
     npart += (int64_t)t->nchunk * q.P;
+    if (q.P > 1 && t->nchunk > 0 && sort_poses(ctx, t)) {
+      off_perm[k] = nperm;
+      nperm += q.P;
+      maxsort = std::max<int64_t>(maxsort, q.P);
+    }
   }
   const size_t sz_desc = sizeof(BatchDesc) * (size_t)nreq;
   const size_t o_lig = (sz_desc + 255) / 256 * 256;
   const size_t o_r = o_lig + sizeof(double4) * (size_t)nlig;
   const size_t o_es = o_r + sizeof(double) * (size_t)nreq;
   const size_t o_part = o_es + sizeof(double) * (size_t)nes;
-  b->bytes = o_part + sizeof(double) * (size_t)npart;
+  // spatial order: the requests' permutations, then one histogram and cell array for all
+  const size_t o_perm = o_part + sizeof(double) * (size_t)npart;
+  const size_t o_hist = o_perm + sizeof(int) * (size_t)nperm;
+  const size_t o_cell = o_hist + sizeof(int) * (size_t)(nperm ? kSortCells : 0);
+  b->bytes = o_cell + sizeof(int) * (size_t)maxsort;
   rsd_status st = ctx->block_alloc(&b->mem, &b->bytes);
   if (st != RSD_OK) {
     delete b;
@@ -1360,6 +1494,11 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     double* part = (double*)(m + o_part) + off_part[k];
     h[k].sp = make_score_params(t, io, lig, rlig, es, nullptr);
     h[k].lp = make_long_params(t, io, lig, shp[order[k]].ppw, part, shp[order[k]].u3 != 0);
+    if (off_perm[k] >= 0) {
+      int* perm = (int*)(m + o_perm) + off_perm[k];
+      h[k].lp.perm = perm;
+      b->sorts.push_back({t, q.trans, q.P, perm});
+    }
     h[k].lig_pos = q.lig_positions;
     h[k].lig_z = q.lig_charges;
     h[k].pose_base = pb;
@@ -1412,6 +1551,10 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
   }
   b->poses = pb;
   b->d = (BatchDesc*)m;
+  if (nperm) {
+    b->sort_hist = (int*)(m + o_hist);
+    b->sort_cell = (int*)(m + o_cell);
+  }
   b->host_table = std::move(h);
   hipError_t e = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming);
   if (e == hipSuccess) e = hipMemcpyAsync(b->d, b->host_table.data(), sz_desc, hipMemcpyHostToDevice, ctx->stream);
@@ -1435,6 +1578,8 @@ rsd_status batch_run(Batch* b) {
   hipStream_t s = ctx->stream;
   if (b->poses == 0) return RSD_OK;
   RSD_TIMED_LAUNCH(ctx, "ligand_prep", (k_batch_prep<<<b->nreq, 64, 0, s>>>(b->d)));
+  for (const auto& so : b->sorts)
+    RSD_TRY(launch_pose_sort(ctx, s, so.t, so.trans, so.P, b->sort_hist, b->sort_cell, so.perm));
   for (const auto& la : b->shorts)
     RSD_TIMED_LAUNCH(ctx, "short", (k_batch_short<<<(unsigned)la.units, 64 * la.W, la.lds, s>>>(
                                        b->d, la.first, la.count)));

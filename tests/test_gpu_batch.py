@@ -73,8 +73,11 @@ def _mk_out(torch, P):
                 counts=torch.empty(P, dtype=torch.int32, device="cuda"))
 
 
-def test_batch_equals_alone_bitwise_and_oracle(env):
+@pytest.mark.parametrize("order", [0, 1])
+def test_batch_equals_alone_bitwise_and_oracle(env, order):
+    """order 1: every request's long range takes its poses in spatial order (option pose_order)."""
     rs, ctx, torch, T = env
+    ctx.set_option("pose_order", order)
     reqs = _requests(torch, T, 500)
     for r in reqs:
         r["out"] = _mk_out(torch, r["quats"].shape[0])
@@ -102,10 +105,13 @@ def test_batch_equals_alone_bitwise_and_oracle(env):
     got = {k: v.cpu().numpy() for k, v in rb["out"].items()}
     assert_parity(got, ref, label="batch request with 600 ligand atoms")
     b.free()
+    ctx.set_option("pose_order", 0)
 
 
-def test_batch_graph_replays_match_eager(env):
+@pytest.mark.parametrize("order", [0, 1])
+def test_batch_graph_replays_match_eager(env, order):
     rs, ctx, torch, T = env
+    ctx.set_option("pose_order", order)
     reqs = _requests(torch, T, 700)
     for r in reqs:
         r["out"] = _mk_out(torch, r["quats"].shape[0])
@@ -136,6 +142,7 @@ def test_batch_graph_replays_match_eager(env):
                 assert np.array_equal(got[k], refs[i][k], equal_nan=True), (rep, i, k)
     del graph
     b.free()
+    ctx.set_option("pose_order", 0)
 
 
 def test_batch_made_before_a_smaller_one_still_runs(env):

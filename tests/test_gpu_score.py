@@ -108,6 +108,25 @@ def test_cfg1_near_thresholds_and_edge_poses(rs, ctx, cfg1, mode):
     assert ref["flags"][-3] == 4 and ref["flags"][-4] == 4 and ref["flags"][-1] == 0
 
 
+@pytest.mark.parametrize("grad", [False, True])
+def test_spatial_pose_order_is_bitwise_input_order(rs, ctx, cfg1, grad):
+    """Option pose_order: the long range taking the poses in spatial order gives, pose for pose,
+    the results of input order (including invalid and out-of-grid poses)."""
+    cfg, wl, F, t = cfg1
+    q, tt = wl.quats.copy(), wl.trans.copy()
+    tt[-1] = [1e3, 0, 0]
+    q[-2] = [0.0, 0.0, 0.0, 0.0]
+    tt[-3, 1] = np.nan
+    out = {}
+    for order in (1, 2):
+        ctx.set_option("pose_order", order)
+        out[order] = _run(rs, ctx, t, wl, q, tt, cfg.sigma, grad=grad, mode=2)
+    ctx.set_option("pose_order", 0)
+    for k in out[1]:
+        assert np.array_equal(out[1][k], out[2][k], equal_nan=True), k
+    assert_parity(out[1], oracle_score(cfg, wl, F, q, tt, grad=grad), grad=grad, label="spatial order")
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_vdw_distance_beyond_the_cutoff(rs, ctx, cfg1, mode):
     """vdw_min > r_cut: the accept flag then needs the minimum over every candidate pair, not
