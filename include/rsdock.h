@@ -340,6 +340,23 @@ void rsd_tensor_free(rsd_tensor* t);
  * Errors: RSD_E_INVALID for an unknown name or value. */
 rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t value);
 
+/* The spatial order in which the chunk-major long-range kernels take poses on large grids
+ * (option "pose_order"), for a caller that splits a large request into parts scored at
+ * different times (a serving loop): parts cut from the ordered poses each cover a compact
+ * region, so their factor rows stay in the L2 (Algorithm PLIE's sum over poses is
+ * unchanged; each pose's result does not depend on the order).
+ *   t          the tensor the poses will be scored against (its box sets the cells)
+ *   quats [P*4] (may be NULL when quats_out is NULL), trans [P*3]   device arrays
+ *   perm [P]   out, device: perm[i] = the input index of the pose at position i; the order
+ *              sorts the poses by a Morton code of their translation's cell (32^3 cells over
+ *              the box), poses of one cell in no particular order
+ *   quats_out [P*4], trans_out [P*3]   out, device (or NULL): the poses in that order
+ *   sorted     out (or NULL): 1 if automatic scoring of this tensor sorts poses itself
+ * Asynchronous on the context stream.  Errors: RSD_E_INVALID (NULL arrays, P out of range). */
+rsd_status rsd_pose_order(rsd_context* ctx, const rsd_tensor* t, const double* quats,
+                          const double* trans, int64_t P, int32_t* perm, double* quats_out,
+                          double* trans_out, int32_t* sorted);
+
 /* Launch-shape tuner (the scoring kernels' tile parameters: poses per wavefront of the
  * rank-chunk-major long-range kernel, wavefronts per workgroup of the short-range kernel, and
  * chunk-major versus fused per-pose long-range evaluation).  Every candidate shape whose LDS
@@ -354,6 +371,7 @@ rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t va
  * chunk-major evaluation sum the ranks in different orders (both within the parity
  * tolerance).  Synchronises the context stream.  `report` may be NULL.
  * Errors: as rsd_score_poses; RSD_E_OOM if the scratch does not fit the budget. */
+
 typedef struct rsd_tune_report {
   int32_t score_mode;      /* chosen: 1 fused, 2 chunk-major */
   int32_t poses_per_wave;  /* chosen (chunk-major) */

@@ -978,6 +978,21 @@ rsd_status rsd_score_poses(rsd_context* ctx, const rsd_tensor* t, const double* 
   return st;
 }
 
+rsd_status rsd_pose_order(rsd_context* ctx, const rsd_tensor* t, const double* quats, const double* trans, int64_t P,
+                          int32_t* perm, double* quats_out, double* trans_out, int32_t* sorted) {
+  clear_error();
+  RSD_CHECK(ctx != nullptr && t != nullptr && !ctx->closing, RSD_E_INVALID, "ctx or tensor is NULL or freed");
+  RSD_CHECK(t->ctx->device == ctx->device, RSD_E_INVALID, "tensor lives on another device");
+  RSD_CHECK(P >= 0 && P <= ((int64_t)1 << 31) - 1, RSD_E_INVALID, "P=%lld out of range", (long long)P);
+  RSD_CHECK(P == 0 || (trans && perm), RSD_E_INVALID, "trans or perm is NULL");
+  RSD_CHECK(quats || !quats_out, RSD_E_INVALID, "quats_out needs quats");
+  RSD_HIP(hipSetDevice(ctx->device));
+  int flag = 0;
+  const rsd_status st = pose_order(ctx, t, quats, trans, P, perm, quats_out, trans_out, &flag);
+  if (sorted) *sorted = flag;
+  return st;
+}
+
 // ---------------------------------------------------------------- launch-shape tuner
 rsd_status rsd_autotune(rsd_context* ctx, const rsd_tensor* t, const double* lig_charges,
                         const double* lig_positions, int64_t L, const double* quats, const double* trans,

@@ -222,6 +222,10 @@ struct ScoreIO {
   double* grads;               // may be null
 };
 rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io);
+// rsd_pose_order (score.hip): the spatial order of the long-range kernels and the poses in it;
+// *sorted: whether automatic scoring of t sorts poses itself
+rsd_status pose_order(Context* ctx, const Tensor* t, const double* quats, const double* trans, int64_t P, int* perm,
+                      double* q_out, double* t_out, int* sorted);
 rsd_status autotune(Context* ctx, const Tensor* t, const ScoreIO& io, rsd_tune_report* rep);
 // a molecule's own energy (score.hip)
 rsd_status launch_self_energy(Context* ctx, const Tensor* t, double* E_long, double* E_short);

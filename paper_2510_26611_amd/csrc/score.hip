@@ -849,6 +849,18 @@ __global__ void k_pose_scatter(const int* __restrict__ cell_of, int64_t P, int* 
     perm[atomicAdd(&next[cell_of[p]], 1)] = (int)p;
 }
 
+// The poses in the order perm (rsd_pose_order).
+__global__ void k_pose_gather(const int* __restrict__ perm, int64_t P, const double* __restrict__ quats,
+                              const double* __restrict__ trans, double* __restrict__ q_out, double* __restrict__ t_out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = perm[i];
+    if (q_out)
+      for (int k = 0; k < 4; ++k) q_out[4 * i + k] = quats[4 * p + k];
+    if (t_out)
+      for (int k = 0; k < 3; ++k) t_out[3 * i + k] = trans[3 * p + k];
+  }
+}
+
 // ---------------------------------------------------------------- many requests per launch
 // A batch scores requests with different tensors, ligands and pose counts in four launches
 // (ligand frames, short-range, long-range, combine) for all of them.  Workgroups find their
@@ -1147,7 +1159,23 @@ rsd_status launch_pose_sort(Context* ctx, hipStream_t s, const Tensor* t, const 
   return st;
 }
 
+
 }  // namespace
+
+rsd_status pose_order(Context* ctx, const Tensor* t, const double* quats, const double* trans, int64_t P, int* perm,
+                      double* q_out, double* t_out, int* sorted) {
+  if (sorted) *sorted = sort_poses(ctx, t) ? 1 : 0;
+  if (P == 0) return RSD_OK;
+  void* ws = nullptr;
+  RSD_TRY(ctx->workspace(sizeof(int) * (size_t)(kSortCells + P), &ws));
+  int* hist = (int*)ws;
+  RSD_TRY(launch_pose_sort(ctx, ctx->stream, t, trans, P, hist, hist + kSortCells, perm));
+  if (q_out || t_out) {
+    const unsigned g = (unsigned)std::min<int64_t>((P + 255) / 256, 65536);
+    RSD_TIMED_LAUNCH(ctx, "sort", (k_pose_gather<<<g, 256, 0, ctx->stream>>>(perm, P, quats, trans, q_out, t_out)));
+  }
+  return RSD_OK;
+}
 
 // Launch shape recorded by rsd_autotune for this workload, applied when the caller left all
 // three shape options automatic.

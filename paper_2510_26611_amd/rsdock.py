@@ -197,6 +197,24 @@ def build_rs_tensor(ctx: Context, charges, positions, n: int, b: float, sinc: Si
     return Tensor(ctx, out)
 
 
+def pose_order(ctx: Context, tensor: Tensor, quats, trans):
+    """rsd_pose_order: (perm, quats in that order, trans in that order, whether automatic scoring
+    of this tensor sorts poses itself); device tensors in and out."""
+    import torch
+    qp, qk, qdev = _arr(quats)
+    tp, tk, tdev = _arr(trans)
+    if not (qdev and tdev):
+        raise TypeError("quats and trans must be device tensors")
+    P = int(tk.shape[0])
+    perm = torch.empty(P, dtype=torch.int32, device=tk.device)
+    q_out = torch.empty_like(qk)
+    t_out = torch.empty_like(tk)
+    flag = C.c_int32()
+    _check(_lib.lib().rsd_pose_order(ctx.handle, tensor.handle, qp, tp, P, C.c_void_p(perm.data_ptr()),
+                                     C.c_void_p(q_out.data_ptr()), C.c_void_p(t_out.data_ptr()), C.byref(flag)))
+    return perm, q_out, t_out, bool(flag.value)
+
+
 def tensor_import(ctx: Context, F, n: int, b: float, sinc: Sinc, charges, positions) -> Tensor:
     """rsd_tensor_import: resident tensor from given n x R factors (host arrays)."""
     Fs = [np.ascontiguousarray(f, dtype=np.float64) for f in F]

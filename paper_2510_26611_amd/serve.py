@@ -78,8 +78,9 @@ def validate(req: Request, proteins: dict) -> int:
 
 
 def request_bytes(req: Request) -> int:
-    """Device bytes a request holds from admission to completion (inputs and outputs)."""
-    return 8 * (4 * req.L + 7 * req.P) + req.P * (8 + 1 + 4)
+    """Device bytes a request holds from admission to completion: inputs and outputs, and at
+    most the spatial-order copies of its poses with their permutation and sort scratch."""
+    return 8 * (4 * req.L + 7 * req.P) + req.P * (8 + 1 + 4) + req.P * (7 * 8 + 4 + 4) + 4 * 32768 + 256
 
 
 def round_scratch_bytes(round_poses: int, nchunk: int, max_ligand: int = 896, slices: int = 64) -> int:
@@ -222,18 +223,31 @@ class Server:
     """Serve a trace of requests against resident tensors on one GPU."""
 
     def __init__(self, tensors: dict, hbm_budget_bytes: int, streams: int = 2, round_poses: int = 250_000,
-                 min_slice: int = 16_384, device: int = 0):
+                 min_slice: int = 16_384, device: int = 0, options: dict | None = None):
         import torch
         self.torch = torch
         self.tensors = tensors
         self.dev = torch.device(f"cuda:{device}")
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(streams)]
         self.ctxs = [rsdock.Context(device, stream=s.cuda_stream) for s in self.streams]
+        for c in self.ctxs:
+            for name, value in (options or {}).items():
+                c.set_option(name, value)
         nchunk = max(-(-t.query()["R"] // 64) for t in tensors.values())
         resident = sum(t.query()["bytes"] for t in tensors.values())
         self.sched = Scheduler(hbm_budget_bytes, resident, streams * round_scratch_bytes(round_poses, nchunk),
                                max_rounds=streams, round_poses=round_poses, min_slice=min_slice)
         self.last_compute = None
+        self._sorted = {}
+        self._k = 0
+
+    def _sorts(self, protein) -> bool:
+        """Whether the library scores this protein's poses in spatial order (no device work)."""
+        if protein not in self._sorted:
+            torch = self.torch
+            e = torch.empty((0, 4), dtype=torch.float64, device=self.dev)
+            self._sorted[protein] = rsdock.pose_order(self.ctxs[0], self.tensors[protein], e, e[:, :3])[3]
+        return self._sorted[protein]
 
     def _upload(self, r: Request) -> None:
         """Inputs to the device and output buffers (device + pinned host) for a newly admitted request."""
@@ -242,6 +256,16 @@ class Server:
                 for a in (r.lig_charges, r.lig_positions, r.quats, r.trans)]
         r._host_in = host
         r._dev = [h.to(dev, non_blocking=True) for h in host]
+        r._perm = None
+        if r.P > 1 and self._sorts(r.protein):
+            # slices of the request in the long-range kernels' spatial order: each slice then
+            # covers a compact part of the grid; results come back in that order and are put
+            # back in request order on the host at the end
+            perm, q, t, _ = rsdock.pose_order(self.ctxs[self._k], self.tensors[r.protein], r._dev[2], r._dev[3])
+            r._dev[2], r._dev[3] = q, t
+            r._perm = torch.empty(r.P, dtype=torch.int32, pin_memory=True)
+            r._perm.copy_(perm, non_blocking=True)
+            r._perm_dev = perm
         r._out = dict(E=torch.empty(r.P, dtype=torch.float64, device=dev),
                       flags=torch.empty(r.P, dtype=torch.uint8, device=dev),
                       counts=torch.empty(r.P, dtype=torch.int32, device=dev))
@@ -250,6 +274,7 @@ class Server:
     def _launch(self, slices: list, k: int) -> dict:
         torch = self.torch
         s = self.streams[k]
+        self._k = k
         with torch.cuda.stream(s):
             for r, off, _ in slices:
                 if off == 0:
@@ -304,8 +329,14 @@ class Server:
                     rd["batch"].free()
                     for r in self.sched.finish_round(rd["slices"]):
                         r.result = {key: v.numpy() for key, v in r._res.items()}
+                        if r._perm is not None:
+                            perm = r._perm.numpy()
+                            for key, v in r.result.items():
+                                back = np.empty_like(v)
+                                back[perm] = v
+                                r.result[key] = back
                         r.t_done = t_done
-                        r._dev = r._out = r._host_in = r._res = None
+                        r._dev = r._out = r._host_in = r._res = r._perm = r._perm_dev = None
                         finished += 1
                         if progress is not None:
                             progress(finished, len(trace))

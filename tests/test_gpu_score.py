@@ -127,6 +127,45 @@ def test_spatial_pose_order_is_bitwise_input_order(rs, ctx, cfg1, grad):
     assert_parity(out[1], oracle_score(cfg, wl, F, q, tt, grad=grad), grad=grad, label="spatial order")
 
 
+def _morton_cells(trans, b):
+    """Morton code of each translation's cell, 32 cells per axis over [-b, b) (x in bit 3k,
+    y in 3k+1, z in 3k+2); NaN and out-of-box coordinates clamp to the edge cells."""
+    x = (np.asarray(trans) + b) * (32.0 / (2.0 * b))
+    c = np.where(x >= 31.0, 31, np.where(x > 0.0, np.floor(np.nan_to_num(x, nan=0.0)), 0)).astype(np.int64)
+    code = np.zeros(len(c), dtype=np.int64)
+    for bit in range(5):
+        for d in range(3):
+            code |= ((c[:, d] >> bit) & 1) << (3 * bit + d)
+    return code
+
+
+def test_pose_order_call(rs, ctx, cfg1):
+    """rsd_pose_order: a permutation whose translations' Morton cells never decrease, and the
+    poses gathered in that order; the flag says whether automatic scoring sorts by itself."""
+    import torch
+    cfg, wl, F, t = cfg1
+    g = np.random.default_rng(31)
+    P = 5000
+    q = gen.unit_quaternions(gen.rng(31, 1), P)
+    tt = g.uniform(-1.2 * cfg.b, 1.2 * cfg.b, size=(P, 3))
+    tt[7] = [np.nan, 0.0, 1.0]
+    tt[8] = [-np.inf, np.inf, 0.0]
+    qd, td = torch.from_numpy(q).cuda(), torch.from_numpy(tt).cuda()
+    for order, want in ((0, False), (1, True), (2, False)):
+        ctx.set_option("pose_order", order)
+        perm, q2, t2, flag = rs.pose_order(ctx, t, qd, td)
+        assert flag == want
+        perm = perm.cpu().numpy()
+        assert np.array_equal(np.sort(perm), np.arange(P))
+        assert np.array_equal(q2.cpu().numpy(), q[perm])
+        assert np.array_equal(t2.cpu().numpy(), tt[perm], equal_nan=True)
+        assert np.all(np.diff(_morton_cells(tt[perm], cfg.b)) >= 0)
+    ctx.set_option("pose_order", 0)
+    e = torch.empty((0, 4), dtype=torch.float64, device="cuda")
+    perm, _, _, _ = rs.pose_order(ctx, t, e, e[:, :3])
+    assert perm.numel() == 0
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_vdw_distance_beyond_the_cutoff(rs, ctx, cfg1, mode):
     """vdw_min > r_cut: the accept flag then needs the minimum over every candidate pair, not

@@ -15,7 +15,9 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.timeout(600)
-def test_server_mix_equals_alone_under_budget():
+@pytest.mark.parametrize("pose_order", [0, 1])
+def test_server_mix_equals_alone_under_budget(pose_order):
+    """pose_order 1: every request is sliced in spatial order and put back in request order."""
     import torch
     assert torch.cuda.is_available()
     import paper_2510_26611_amd as rs
@@ -54,7 +56,8 @@ def test_server_mix_equals_alone_under_budget():
     # small rounds so that requests are split into slices; room for about four requests in flight
     scratch = 2 * serve.round_scratch_bytes(2000, nchunk)
     srv = serve.Server(tensors, hbm_budget_bytes=int(resident + scratch + 4 * mean_cost), round_poses=2000,
-                       min_slice=256)
+                       min_slice=256, options=dict(pose_order=pose_order))
+    assert all(srv._sorts(name) == (pose_order == 1) for name in tensors)
     stats = srv.run(trace)
     print(f"served {stats['served']} p50 {stats['latency_p50_s'] * 1e3:.2f} ms p99 {stats['latency_p99_s'] * 1e3:.2f} ms")
     assert stats["served"] == 40 and stats["rejected"] == 1
