@@ -349,10 +349,13 @@ rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t va
  *   quats [P*4] (may be NULL when quats_out is NULL), trans [P*3]   device arrays
  *   perm [P]   out, device: perm[i] = the input index of the pose at position i; the order
  *              sorts the poses by a Morton code of their translation's cell (32^3 cells over
- *              the box), poses of one cell in no particular order
+ *              the box; coordinates outside it or NaN clamp to the edge cells), poses of one
+ *              cell in no particular order
  *   quats_out [P*4], trans_out [P*3]   out, device (or NULL): the poses in that order
  *   sorted     out (or NULL): 1 if automatic scoring of this tensor sorts poses itself
- * Asynchronous on the context stream.  Errors: RSD_E_INVALID (NULL arrays, P out of range). */
+ * Asynchronous on the context stream (which it synchronises only when the context's
+ * workspace must grow to 4 * (32768 + P) bytes).  Errors: RSD_E_INVALID (NULL arrays, P out
+ * of range, a tensor of another device); RSD_E_OOM. */
 rsd_status rsd_pose_order(rsd_context* ctx, const rsd_tensor* t, const double* quats,
                           const double* trans, int64_t P, int32_t* perm, double* quats_out,
                           double* trans_out, int32_t* sorted);
