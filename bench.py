@@ -91,6 +91,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--score-mode", type=int, default=0, help="0 automatic, 1 fused per-pose, 2 chunk-major")
     ap.add_argument("--no-autotune", action="store_true", help="skip the launch-shape tuner before timing")
+    ap.add_argument("--pose-order", type=int, default=0, choices=[0, 1, 2],
+                    help="long range takes poses in spatial order: 0 automatic (large grids), 1 always, 2 never")
     ap.add_argument("--overlap", type=int, default=0, choices=[0, 1],
                     help="1: the short-range kernel runs on a second stream beside the long-range one")
     ap.add_argument("--tune-poses", type=int, default=16384, help="poses of the tuner's sample")
@@ -151,6 +153,7 @@ def main() -> int:
     ctx = rs.Context(0, stream=stream.cuda_stream)
     ctx.set_option("score_mode", args.score_mode)
     ctx.set_option("overlap", args.overlap)
+    ctx.set_option("pose_order", args.pose_order)
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     d_z, d_x = to(wl.protein_charges), to(wl.protein_positions)
     d_lz, d_lx, d_q, d_t = to(wl.ligand_charges), to(wl.ligand_positions), to(wl.quats), to(wl.trans)
@@ -360,6 +363,7 @@ def run_site(args, rs, configs, torch, np, dev) -> int:
     d_lz, d_lx, d_q, d_t = to(wl.ligand_charges), to(wl.ligand_positions), to(quats), to(trans)
     ctx = rs.Context(0)
     ctx.set_option("overlap", args.overlap)
+    ctx.set_option("pose_order", args.pose_order)
     tg = rs.build_rs_tensor(ctx, to(wl.protein_charges), to(wl.protein_positions), cfg.n, cfg.b,
                             rs.Sinc.from_config(cfg))
     out = {k: dict(E=torch.empty(P, dtype=torch.float64, device=dev), flags=torch.empty(P, dtype=torch.uint8, device=dev),
@@ -453,6 +457,7 @@ def run_ppiem(args, rs, configs, torch, np, dev) -> int:
     d_off, d_idx = to(off.astype(np.int32)), to(idx.astype(np.int32))
     ctx = rs.Context(0)
     ctx.set_option("overlap", args.overlap)
+    ctx.set_option("pose_order", args.pose_order)
     t = rs.build_rs_tensor(ctx, to(wl.protein_charges), to(wl.protein_positions), cfg.n, cfg.b, rs.Sinc.from_config(cfg))
     centre = ppiem.tensor_centre(t)
     cp0 = ppiem.contact_poses(ctx, t, d_lx, d_dirs, d_q, cfg.sigma, centre=centre)
