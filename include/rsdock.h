@@ -325,12 +325,13 @@ void rsd_tensor_free(rsd_tensor* t);
  *                     Chebyshev interpolants in d^2 (one per quadrature and cutoff, kept by the
  *                     context; checked on the host to 1e-11 relative, else not used); gradient
  *                     calls and 0 evaluate the exponentials
- *   "pose_order"      chunk-major long range: 0 automatic, 1 always, 2 never take the poses in
- *                     spatial order (a counting sort of their translations by a Morton code of
- *                     32^3 cells over the box, on the device).  On grids where one rank chunk's
- *                     rows (3 x n x 512 bytes) exceed the 4 MiB L2 of an XCD (n >= 2731, the
- *                     automatic choice) the gathers then reuse the L2; the results are those of
- *                     input order bit for bit, each written to its own pose
+ *   "pose_order"      chunk-major long range: 0 automatic (calls and batch requests of at least
+ *                     16384 poses), 1 always, 2 never take the poses in spatial order (a
+ *                     counting sort of their translations by a Morton code of 32^3 cells over
+ *                     the box, on the device).  Neighbouring poses then share factor rows within
+ *                     a workgroup and, on grids whose rank chunk (3 x n x 512 bytes) exceeds the
+ *                     4 MiB L2 of an XCD, within the L2; the results are those of input order
+ *                     bit for bit, each written to its own pose
  *   "overlap"         1: in chunk-major scoring the short-range kernel runs on a second stream
  *                     of the context beside the long-range kernel (joined before the results
  *                     are combined); 0 (default): one stream.  The long-range gathers slow
@@ -352,7 +353,7 @@ rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t va
  *              the box; coordinates outside it or NaN clamp to the edge cells), poses of one
  *              cell in no particular order
  *   quats_out [P*4], trans_out [P*3]   out, device (or NULL): the poses in that order
- *   sorted     out (or NULL): 1 if automatic scoring of this tensor sorts poses itself
+ *   sorted     out (or NULL): 1 if scoring these P poses on this context would sort them itself
  * Asynchronous on the context stream (which it synchronises only when the context's
  * workspace must grow to 4 * (32768 + P) bytes).  Errors: RSD_E_INVALID (NULL arrays, P out
  * of range, a tensor of another device); RSD_E_OOM. */

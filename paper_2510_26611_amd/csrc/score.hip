@@ -1130,13 +1130,16 @@ LongParams make_long_params(const Tensor* t, const ScoreIO& io, const double4* l
   return lp;
 }
 
-// Whether a call's long-range gathers take the poses in spatial order: option pose_order
-// (0 automatic, 1 always, 2 never); automatically when one rank chunk's rows (3 modes x n
-// rows x 64 columns) exceed the 4 MiB L2 of an XCD.
-bool sort_poses(const Context* ctx, const Tensor* t) {
+// Whether a call's long-range gathers take its P poses in spatial order: option pose_order
+// (0 automatic, 1 always, 2 never); automatically from kSortMinPoses poses on.  Neighbouring
+// poses then share factor rows within a wavefront and workgroup (and, on grids whose rank
+// chunk exceeds an XCD's L2, within the L2); the sort costs two passes over the translations.
+constexpr int64_t kSortMinPoses = 16384;
+bool sort_poses(const Context* ctx, const Tensor* t, int64_t P) {
+  if (P < 2 || t->nchunk == 0) return false;
   if (ctx->opt_pose_order == 1) return true;
   if (ctx->opt_pose_order == 2) return false;
-  return (size_t)3 * (size_t)t->n * kChunk * sizeof(double) > ((size_t)4 << 20);
+  return P >= kSortMinPoses;
 }
 
 // The permutation of P poses into spatial order (hist: kSortCells ints, cell_of and perm: P).
@@ -1164,7 +1167,7 @@ rsd_status launch_pose_sort(Context* ctx, hipStream_t s, const Tensor* t, const 
 
 rsd_status pose_order(Context* ctx, const Tensor* t, const double* quats, const double* trans, int64_t P, int* perm,
                       double* q_out, double* t_out, int* sorted) {
-  if (sorted) *sorted = sort_poses(ctx, t) ? 1 : 0;
+  if (sorted) *sorted = sort_poses(ctx, t, P) ? 1 : 0;
   if (P == 0) return RSD_OK;
   void* ws = nullptr;
   RSD_TRY(ctx->workspace(sizeof(int) * (size_t)(kSortCells + P), &ws));
@@ -1210,7 +1213,7 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   const size_t off_es = off_r + 256;
   const size_t off_gs = off_es + sizeof(double) * (size_t)(split ? P : 0);
   const size_t off_part = off_gs + sizeof(double) * (size_t)(split && grad ? 6 * P : 0);
-  const bool sorted = split && P > 1 && sort_poses(ctx, t);
+  const bool sorted = split && sort_poses(ctx, t, P);
   // spatial order: cell histogram (kSortCells) | cell of each pose (P) | permutation (P)
   const size_t off_sort = off_part + sizeof(double) * (size_t)(split ? (int64_t)t->nchunk * P * S : 0);
   const size_t total = off_sort + sizeof(int) * (size_t)(sorted ? kSortCells + 2 * P : 0);
@@ -1476,7 +1479,7 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     nes += q.P;
     off_part[k] = npart;
     npart += (int64_t)t->nchunk * q.P;
-    if (q.P > 1 && t->nchunk > 0 && sort_poses(ctx, t)) {
+    if (sort_poses(ctx, t, q.P)) {
       off_perm[k] = nperm;
       nperm += q.P;
       maxsort = std::max<int64_t>(maxsort, q.P);

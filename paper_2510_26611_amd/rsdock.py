@@ -198,8 +198,8 @@ def build_rs_tensor(ctx: Context, charges, positions, n: int, b: float, sinc: Si
 
 
 def pose_order(ctx: Context, tensor: Tensor, quats, trans):
-    """rsd_pose_order: (perm, quats in that order, trans in that order, whether automatic scoring
-    of this tensor sorts poses itself); device tensors in and out."""
+    """rsd_pose_order: (perm, quats in that order, trans in that order, whether scoring these
+    poses on this context would sort them itself); device tensors in and out."""
     import torch
     qp, qk, qdev = _arr(quats)
     tp, tk, tdev = _arr(trans)

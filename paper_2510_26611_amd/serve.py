@@ -238,16 +238,16 @@ class Server:
         self.sched = Scheduler(hbm_budget_bytes, resident, streams * round_scratch_bytes(round_poses, nchunk),
                                max_rounds=streams, round_poses=round_poses, min_slice=min_slice)
         self.last_compute = None
-        self._sorted = {}
+        self.pose_order = int((options or {}).get("pose_order", 0))
+        self.ordered = 0   # requests sliced in spatial order so far
         self._k = 0
 
-    def _sorts(self, protein) -> bool:
-        """Whether the library scores this protein's poses in spatial order (no device work)."""
-        if protein not in self._sorted:
-            torch = self.torch
-            e = torch.empty((0, 4), dtype=torch.float64, device=self.dev)
-            self._sorted[protein] = rsdock.pose_order(self.ctxs[0], self.tensors[protein], e, e[:, :3])[3]
-        return self._sorted[protein]
+    def _orders(self, r: Request) -> bool:
+        """Whether a request is sliced in spatial order: option pose_order 1 always, 2 never,
+        0 when it is large enough to be cut into several slices."""
+        if r.P < 2 or self.pose_order == 2:
+            return False
+        return self.pose_order == 1 or r.P >= 2 * self.sched.min_slice
 
     def _upload(self, r: Request) -> None:
         """Inputs to the device and output buffers (device + pinned host) for a newly admitted request."""
@@ -257,7 +257,7 @@ class Server:
         r._host_in = host
         r._dev = [h.to(dev, non_blocking=True) for h in host]
         r._perm = None
-        if r.P > 1 and self._sorts(r.protein):
+        if self._orders(r):
             # slices of the request in the long-range kernels' spatial order: each slice then
             # covers a compact part of the grid; results come back in that order and are put
             # back in request order on the host at the end
@@ -266,6 +266,7 @@ class Server:
             r._perm = torch.empty(r.P, dtype=torch.int32, pin_memory=True)
             r._perm.copy_(perm, non_blocking=True)
             r._perm_dev = perm
+            self.ordered += 1
         r._out = dict(E=torch.empty(r.P, dtype=torch.float64, device=dev),
                       flags=torch.empty(r.P, dtype=torch.uint8, device=dev),
                       counts=torch.empty(r.P, dtype=torch.int32, device=dev))

@@ -15,9 +15,10 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("pose_order", [0, 1])
+@pytest.mark.parametrize("pose_order", [0, 1, 2])
 def test_server_mix_equals_alone_under_budget(pose_order):
-    """pose_order 1: every request is sliced in spatial order and put back in request order."""
+    """Requests sliced in spatial order (pose_order 1: every request; 0: those of at least two
+    minimum slices; 2: none) come back in request order."""
     import torch
     assert torch.cuda.is_available()
     import paper_2510_26611_amd as rs
@@ -57,10 +58,11 @@ def test_server_mix_equals_alone_under_budget(pose_order):
     scratch = 2 * serve.round_scratch_bytes(2000, nchunk)
     srv = serve.Server(tensors, hbm_budget_bytes=int(resident + scratch + 4 * mean_cost), round_poses=2000,
                        min_slice=256, options=dict(pose_order=pose_order))
-    assert all(srv._sorts(name) == (pose_order == 1) for name in tensors)
     stats = srv.run(trace)
     print(f"served {stats['served']} p50 {stats['latency_p50_s'] * 1e3:.2f} ms p99 {stats['latency_p99_s'] * 1e3:.2f} ms")
     assert stats["served"] == 40 and stats["rejected"] == 1
+    want = {0: sum(r.P >= 512 for r in trace[:40]), 1: sum(r.P >= 2 for r in trace[:40]), 2: 0}[pose_order]
+    assert srv.ordered == want and (pose_order == 2 or want > 0)
     assert trace[-1].error == serve.E_UNKNOWN_PROTEIN
     assert np.isfinite(stats["latency_p99_s"])
     ctx.set_option("score_mode", 2)
