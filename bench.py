@@ -29,16 +29,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "long_cfg2_traffic.json")
 SCORE_SRC = os.path.join(ROOT, "paper_2510_26611_amd", "csrc", "score.hip")
 
 
-# The source the counters measured: the pose-transform helpers and the long-range kernel.
+# The source the counters measured: the pose-transform helpers, the long-range kernel and the
+# single-call launch sequence around it (which decides the pose order the kernel reads in).
 KERNEL_REGIONS = (("// Rotation matrix of q = (w, x, y, z)", "// Two columns of one chunk for one atom"),
-                  ("struct LongParams {", "// E = sum_c part[c]"))
+                  ("struct LongParams {", "// E = sum_c part[c]"),
+                  ("rsd_status launch_score(Context* ctx", "\n}\n"))
 
 
 def _src_hash() -> str:
     """Hash of the scoring source regions that define the long-range kernel."""
     with open(SCORE_SRC, encoding="utf-8") as f:
         text = f.read()
-    parts = [text[text.index(a):text.index(b)] for a, b in KERNEL_REGIONS]
+    parts = [text[text.index(a):text.index(b, text.index(a))] for a, b in KERNEL_REGIONS]
     return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
 
 

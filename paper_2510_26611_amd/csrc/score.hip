@@ -1216,7 +1216,9 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   const bool sorted = split && sort_poses(ctx, t, P);
   // spatial order: cell histogram (kSortCells) | cell of each pose (P) | permutation (P)
   const size_t off_sort = off_part + sizeof(double) * (size_t)(split ? (int64_t)t->nchunk * P * S : 0);
-  const size_t total = off_sort + sizeof(int) * (size_t)(sorted ? kSortCells + 2 * P : 0);
+  // the sorted poses' copies (quats then trans) after the sort's counts and permutation
+  const size_t off_spose = (off_sort + sizeof(int) * (size_t)(kSortCells + 2 * P) + 255) / 256 * 256;
+  const size_t total = sorted ? off_spose + sizeof(double) * 7 * (size_t)P : off_sort;
   void* ws = nullptr;
   RSD_TRY(ctx->workspace(total, &ws));
   char* w8 = (char*)ws;
@@ -1244,11 +1246,20 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   }
   LongParams lp = make_long_params(t, io, lig, ppw, (double*)(w8 + off_part), u3);
   RSD_CHECK(lp.per_xcd * 8 <= 0x7fffffffLL, RSD_E_UNSUPPORTED, "too many poses in one call");
+  const int* comb_perm = nullptr;   // slot -> pose of the long-range partials, when sorted
   if (sorted) {
     int* hist = (int*)(w8 + off_sort);
     int* perm = hist + kSortCells + P;
     RSD_TRY(launch_pose_sort(ctx, s, t, io.trans, P, hist, hist + kSortCells, perm));
-    lp.perm = perm;
+    // the long range reads the poses in sorted order from contiguous copies (one pass of
+    // scattered reads here instead of one per rank chunk); the combination maps slots back
+    double* q_sorted = (double*)(w8 + off_spose);
+    double* t_sorted = q_sorted + 4 * P;
+    const unsigned gs = (unsigned)std::min<int64_t>((P + 255) / 256, 65536);
+    RSD_TIMED_LAUNCH(ctx, "sort", (k_pose_gather<<<gs, 256, 0, s>>>(perm, P, lp.quats, lp.trans, q_sorted, t_sorted)));
+    lp.quats = q_sorted;
+    lp.trans = t_sorted;
+    comb_perm = perm;
   }
   const dim3 g2((unsigned)(lp.per_xcd * 8));
   const size_t lds2 = long_lds(L, ppw, grad, u3);
@@ -1291,10 +1302,10 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   }
   if (grad) {
     RSD_TIMED_LAUNCH(ctx, "combine", (k_combine<true><<<gc, 256, 0, s>>>(lp.part, t->nchunk, P, a.es, a.gs, io.flags,
-                                                                           io.E, io.El, io.grads, lp.perm)));
+                                                                           io.E, io.El, io.grads, comb_perm)));
   } else {
     RSD_TIMED_LAUNCH(ctx, "combine", (k_combine<false><<<gc, 256, 0, s>>>(lp.part, t->nchunk, P, a.es, a.gs,
-                                                                            io.flags, io.E, io.El, nullptr, lp.perm)));
+                                                                            io.flags, io.E, io.El, nullptr, comb_perm)));
   }
   return RSD_OK;
 }
