@@ -59,9 +59,11 @@ def _left_svd(A: np.ndarray):
     return U, s
 
 
-def rhosvd(charges, positions, t_long, w_long, n, b, eps, col_chunk: int = 8192, galerkin: bool = False) -> TuckerResult:
+def rhosvd(charges, positions, t_long, w_long, n, b, eps, col_chunk: int = 8192, galerkin: bool = False,
+           snapped: bool = False) -> TuckerResult:
     """Canonical-to-Tucker transform of the long-range sum (steps 1-3 above); galerkin=True
-    takes the cell-average factors of eq. 2.1 instead of collocated ones."""
+    takes the cell-average factors of eq. 2.1 instead of collocated ones; snapped=True builds
+    the columns by the shift-and-window transform of eq. 2.5 (charges at their nearest nodes)."""
     charges = np.asarray(charges, dtype=np.float64)
     positions = np.asarray(positions, dtype=np.float64)
     N = positions.shape[0]
@@ -69,7 +71,9 @@ def rhosvd(charges, positions, t_long, w_long, n, b, eps, col_chunk: int = 8192,
     _, _, _, nodes = _tensor.grid(n, b)
     U, sing, ranks, B, norms = [], [], [], [], []
     for d in range(3):
-        if galerkin:
+        if snapped:
+            G = _tensor.shifted_columns(positions[:, d], t_long, n, b, galerkin).reshape(n, N * K)
+        elif galerkin:
             G = _tensor.galerkin_columns(positions[:, d], t_long, nodes, (2.0 * b) / n).reshape(n, N * K)
         else:
             G = _tensor.factor_columns(positions[:, d], t_long, nodes).reshape(n, N * K)
@@ -119,9 +123,9 @@ def tucker_to_canonical(tk: TuckerResult, eps) -> CanonicalResult:
     return CanonicalResult(F=F, R=F[0].shape[1], dropped_fro=float(np.sqrt(dropped)))
 
 
-def build(charges, positions, t_long, w_long, n, b, eps, galerkin: bool = False):
+def build(charges, positions, t_long, w_long, n, b, eps, galerkin: bool = False, snapped: bool = False):
     """Algorithm TEP steps 3-5: the rank-reduced canonical long-range tensor."""
-    tk = rhosvd(charges, positions, t_long, w_long, n, b, eps, galerkin=galerkin)
+    tk = rhosvd(charges, positions, t_long, w_long, n, b, eps, galerkin=galerkin, snapped=snapped)
     return tk, tucker_to_canonical(tk, eps)
 
 

@@ -7,9 +7,10 @@ Long-range collective potential of the protein (eq. 2.6, Algorithm TEP steps 2-3
 
     T0[i1,i2,i3] = sum_m sum_{k in long} z_m w_k prod_d exp(-t_k^2 (X_{i_d} - x_{m,d})^2),
 
-a canonical tensor of rank N*K_long.  The build collocates the Gaussians at the
-true (off-grid) atom positions instead of shifting a reference tensor onto
-grid-snapped atoms (eq. 2.5); this is a reading recorded in the design notes.
+a canonical tensor of rank N*K_long.  The default build collocates the Gaussians at
+the true (off-grid) atom positions; the paper's own construction -- a reference tensor
+on a twice larger grid shifted onto each charge moved to its nearest node and windowed
+onto the grid (eq. 2.5) -- is `shifted_columns`, the snapped variant.
 """
 from __future__ import annotations
 
@@ -50,6 +51,44 @@ def galerkin_columns(coord: np.ndarray, t_long: np.ndarray, nodes: np.ndarray, h
     with np.errstate(divide="ignore", invalid="ignore"):
         g = np.sqrt(np.pi) / (2.0 * t * h) * d
     return np.where(t > 0.0, g, 1.0)
+
+
+def snap_to_nodes(coord: np.ndarray, n: int, b: float) -> np.ndarray:
+    """Index of the grid node nearest to each coordinate, the grid point a charge is moved to
+    before the reference tensor is shifted onto it (eq. 2.5): j = floor((x - X0)/h + 1/2),
+    clipped to [0, n-1] (a coordinate half-way between two nodes goes to the upper one)."""
+    _, X0, inv_h, _ = grid(n, b)
+    j = np.floor((np.asarray(coord, dtype=np.float64) - X0) * inv_h + 0.5)
+    return np.clip(j, 0, n - 1).astype(np.int64)
+
+
+def snapped_positions(positions: np.ndarray, n: int, b: float) -> np.ndarray:
+    """The atoms moved to their nearest grid nodes (every coordinate a node X_j)."""
+    _, _, _, nodes = grid(n, b)
+    return nodes[snap_to_nodes(positions, n, b)]
+
+
+def reference_vectors(t_long: np.ndarray, n: int, h: float, galerkin: bool = False) -> np.ndarray:
+    """1-D factors of the reference tensor on the twice larger grid (the single-charge kernel of
+    eq. 2.5, long-range terms): for term k, the Gaussian exp(-t_k^2 (o h)^2) at offsets o = -n..n-1
+    from the node that holds the charge (row o + n), or its cell average (eq. 2.1, normalised as in
+    `galerkin_columns`).  Returns (2n, K)."""
+    offsets = (np.arange(2 * n, dtype=np.float64) - n) * h
+    t_long = np.asarray(t_long, dtype=np.float64)
+    if galerkin:
+        return galerkin_columns(np.zeros(1), t_long, offsets, h)[:, 0, :]
+    return np.exp(-(t_long * t_long)[None, :] * (offsets * offsets)[:, None])
+
+
+def shifted_columns(coord: np.ndarray, t_long: np.ndarray, n: int, b: float, galerkin: bool = False) -> np.ndarray:
+    """Shift-and-window transform of the reference vectors (eq. 2.5): the charge m moves to its
+    nearest node j_m, the reference's centre is shifted there and the result is restricted to the
+    n grid nodes, G[i, m, k] = ref[i - j_m + n, k].  Returns (n, N, K)."""
+    h = (2.0 * b) / n
+    ref = reference_vectors(t_long, n, h, galerkin)
+    j = snap_to_nodes(coord, n, b)
+    rows = np.arange(n)[:, None] - j[None, :] + n          # (n, N), always in [1, 2n - 1]
+    return ref[rows]
 
 
 def long_range_at_nodes(charges, positions, t_long, w_long, n, b, idx):
