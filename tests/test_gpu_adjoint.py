@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 sys.path.insert(0, os.path.dirname(__file__))
-from gpu_common import oracle_factors, oracle_score, sinc_parts  # noqa: E402
+from gpu_common import assert_parity, near_threshold_poses, oracle_factors, oracle_score, sinc_parts  # noqa: E402
 from oracle import score as oscore, tensor as otensor  # noqa: E402
 from workloads import configs  # noqa: E402
 
@@ -208,3 +208,37 @@ def test_cfg4_projected_gradient_50_steps(env, cfg4):
         if ref["flags"][k] & 2:
             be = np.sum(zeta * pt_err[k * cfg.L:(k + 1) * cfg.L]) + 1e-9
             assert abs(out["E"][k] - ref["E"][k]) <= be
+
+
+@pytest.mark.timeout(900)
+def test_cfg4_parity_with_the_oracle_on_exported_factors(env, cfg4):
+    """Config 4 at its own size, in the launch shape the tuner picks for it: all 65,536 poses scored
+    with gradients in one call, then 512 seeded poses and poses placed on the sigma and r_c
+    thresholds against the oracle's energies and analytic gradients on the tensor's own factors
+    (PLIE, Sec. 3.4; eq. 3.12; eqs. 5.2-5.3): flags and counts bit-exact, E, E_long and all six
+    gradient components within 1e-10 of the per-pose summation scale."""
+    rs, ctx, torch = env
+    cfg, wl, t = cfg4
+    lz, lx, q, tr = _dev(torch, wl.ligand_charges, wl.ligand_positions, wl.quats, wl.trans)
+    tune = ctx.autotune(t, lz, lx, q[:16384], tr[:16384], cfg.sigma, grads=True)
+    print(f"cfg4 tuned shape: {tune}", flush=True)
+    out = rs.score_poses(ctx, t, lz, lx, q, tr, cfg.sigma, grads=True, energies_long=True)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    F = t.export()
+    sample = np.sort(np.random.default_rng(4004).choice(cfg.P, 512, replace=False))
+    ref = oracle_score(cfg, wl, F, wl.quats[sample], wl.trans[sample], grad=True)
+    sub = {k: v[sample] for k, v in got.items()}
+    worst = assert_parity(sub, ref, grad=True, label="cfg4 sample")
+    print(f"cfg4: R={F[0].shape[1]}, {len(sample)} sampled poses, worst energy error {worst:.3g} x tolerance, "
+          f"accepted {int(np.sum(ref['flags'] & 1))}", flush=True)
+    qs, ts_ = [], []
+    for target in (cfg.sigma, cfg.r_cut):
+        a, b = near_threshold_poses(cfg, wl, wl.quats[sample[:24]], wl.trans[sample[:24]], target, 24)
+        qs.append(a)
+        ts_.append(b)
+    qn, tn = np.concatenate(qs), np.concatenate(ts_)
+    outn = rs.score_poses(ctx, t, lz, lx, *_dev(torch, qn, tn), cfg.sigma, grads=True, energies_long=True)
+    torch.cuda.synchronize()
+    refn = oracle_score(cfg, wl, F, qn, tn, grad=True)
+    assert_parity({k: v.cpu().numpy() for k, v in outn.items()}, refn, grad=True, label="cfg4 near thresholds")

@@ -1,6 +1,7 @@
 """GPU test of the continuous-batching server: mixed requests over three resident tensors
 under a tight HBM budget, split into pose slices across rounds; every served result equals
-the same request scored alone."""
+the same request scored alone, and a sample of every served request matches the oracle on
+the tensors' own factors."""
 import os
 import sys
 
@@ -8,7 +9,8 @@ import numpy as np
 import pytest
 
 sys.path.insert(0, os.path.dirname(__file__))
-from gpu_common import oracle_factors  # noqa: E402
+from gpu_common import TOL, oracle_factors  # noqa: E402
+from oracle import score as oscore, sinc as osinc  # noqa: E402
 from workloads import configs, generators as gen  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -78,6 +80,26 @@ def test_server_mix_equals_alone_under_budget(pose_order):
                       f"flags {alone['flags'][diff[:3]]}")
                 bad.append((r.rid, k))
     assert not bad, bad
+    # served results against the oracle (PLIE, Sec. 3.4) on each tensor's own factors
+    sinc16 = osinc.split(*osinc.sinc_table(cfg.M, cfg.h_M, cfg.L_s), 16)[1]
+    ref_args = {"cfg1": (can.F, cfg.n, cfg.b, wl.protein_positions, wl.protein_charges,
+                         *osinc.split(*osinc.sinc_table(cfg.M, cfg.h_M, cfg.L_s), cfg.K_long)[1], cfg.r_cut),
+                "built": (tensors["built"].export(), 256, 30.0, pos, z, *sinc16, 9.5),
+                "rand": (tensors["rand"].export(), 96, 30.0, pos[:60] * 0.7, z[:60], *sinc16, 9.5)}
+    gs = np.random.default_rng(77)
+    checked = 0
+    for r in trace[:40]:
+        sample = np.sort(gs.choice(r.P, min(r.P, 24), replace=False))
+        ref = oscore.score(*ref_args[r.protein], r.lig_charges, r.lig_positions, r.quats[sample], r.trans[sample],
+                           r.vdw_min)
+        assert np.array_equal(r.result["flags"][sample], ref["flags"]), r.rid
+        assert np.array_equal(r.result["counts"][sample], ref["counts"]), r.rid
+        E = r.result["E"][sample]
+        assert np.array_equal(np.isnan(E), np.isnan(ref["E"])), r.rid
+        ok = ~np.isnan(ref["E"])
+        assert np.all(np.abs(E[ok] - ref["E"][ok]) <= TOL * ref["scale"][ok]), r.rid
+        checked += len(sample)
+    print(f"{checked} served poses at parity with the oracle")
     srv.close()
     for x in tensors.values():
         x.free()
