@@ -152,6 +152,25 @@ rsd_status rsd_score_poses(rsd_context* ctx, const rsd_tensor* tensor,
                            uint32_t mem_flags, double* energies, double* energies_long,
                            uint8_t* flags, int32_t* counts, double* grads);
 
+/* rsd_score_poses for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, results and
+ * validation as rsd_score_poses with RSD_DEVICE_PTRS (mem_flags must hold it: host arrays
+ * would need staging memory, RSD_E_INVALID otherwise).  The call allocates nothing: its
+ * scratch (ligand frame, short-range partial sums, per-chunk long-range partials, the pose
+ * sort) lives in one static 128 MiB array per GPU that the library holds from its first use
+ * on that GPU until the process ends.  The poses are scored in equal slices whose scratch
+ * fits the array (each pose's result does not depend on the slicing); a call whose single
+ * pose would not fit returns RSD_E_UNSUPPORTED.  Enqueues on the context stream and returns
+ * before completion; the context's timing option is ignored, and the short range always runs
+ * on the context stream (option overlap ignored).  Every call on one GPU shares its array:
+ * calls that can overlap on one GPU (contexts on different streams) race and must be ordered
+ * by the caller.  Errors: as rsd_score_poses. */
+rsd_status rsd_score_poses_noalloc(rsd_context* ctx, const rsd_tensor* tensor,
+                                   const double* lig_charges, const double* lig_positions, int64_t L,
+                                   const double* quats, const double* trans, int64_t P, double vdw_min,
+                                   uint32_t mem_flags, double* energies, double* energies_long,
+                                   uint8_t* flags, int32_t* counts, double* grads);
+
 /* Many requests per launch.  A request is one rsd_score_poses call with device pointers
  * and no gradients; the tensors may differ between requests but belong to one context.
  * rsd_batch_create validates the requests, allocates the batch's device scratch (per-request

@@ -31,7 +31,7 @@ EXPORTED = [
     "rsd_context_set_option", "rsd_batch_create", "rsd_batch_run", "rsd_batch_free", "rsd_autotune",
     "rsd_tensor_restrict", "rsd_tensor_grid", "rsd_tensor_combine",
     "rsd_tensor_centre", "rsd_contact_poses", "rsd_orbit_minima",
-    "rsd_self_energy", "rsd_pose_order",
+    "rsd_self_energy", "rsd_pose_order", "rsd_score_poses_noalloc",
 ]
 
 
@@ -74,6 +74,7 @@ def _declare(lib: C.CDLL) -> C.CDLL:
         "rsd_tensor_import": (st, [_P, _P, _P, _P, _I64, _I32, _D, C.POINTER(SincParams), _P, _P, _I64, _U32,
                                    C.POINTER(_P)]),
         "rsd_score_poses": (st, [_P, _P, _P, _P, _I64, _P, _P, _I64, _D, _U32, _P, _P, _P, _P, _P]),
+        "rsd_score_poses_noalloc": (st, [_P, _P, _P, _P, _I64, _P, _P, _I64, _D, _U32, _P, _P, _P, _P, _P]),
         "rsd_tensor_query": (st, [_P, C.POINTER(_I32), C.POINTER(_I64), C.POINTER(_I32), C.POINTER(_SZ)]),
         "rsd_tensor_export": (st, [_P, _P, _P, _P]),
         "rsd_tensor_save": (st, [_P, C.c_char_p]),

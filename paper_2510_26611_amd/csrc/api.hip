@@ -512,6 +512,11 @@ rsd_status rsd_context_create(int32_t device, void* hip_stream, size_t hbm_budge
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
   c->budget = hbm_budget_bytes;
+  const rsd_status st = noalloc_scratch_init(device);   // rsd_score_poses_noalloc's static scratch
+  if (st != RSD_OK) {
+    delete c;
+    return st;
+  }
   *out = c;
   return RSD_OK;
 }
@@ -884,6 +889,38 @@ rsd_status rsd_tensor_export(const rsd_tensor* t, double* F1, double* F2, double
 }
 
 void rsd_tensor_free(rsd_tensor* t) { tensor_release(t); }
+
+rsd_status rsd_score_poses_noalloc(rsd_context* ctx, const rsd_tensor* t, const double* lig_charges,
+                                   const double* lig_positions, int64_t L, const double* quats, const double* trans,
+                                   int64_t P, double vdw_min, uint32_t mem_flags, double* energies,
+                                   double* energies_long, uint8_t* flags, int32_t* counts, double* grads) {
+  clear_error();
+  RSD_CHECK(ctx != nullptr && t != nullptr, RSD_E_INVALID, "ctx or tensor is NULL");
+  RSD_CHECK(!ctx->closing, RSD_E_INVALID, "context has been freed");
+  RSD_CHECK(t->ctx->device == ctx->device, RSD_E_INVALID, "tensor lives on another device");
+  RSD_CHECK(is_device_ptrs(mem_flags), RSD_E_INVALID, "the allocation-free call takes device pointers only");
+  RSD_CHECK(L >= 1 && L <= kMaxLigand, RSD_E_UNSUPPORTED, "L=%lld outside [1, %d]", (long long)L, kMaxLigand);
+  RSD_CHECK(P >= 0 && P <= (int64_t)INT32_MAX, RSD_E_INVALID, "P=%lld out of range", (long long)P);
+  RSD_CHECK(std::isfinite(vdw_min) && vdw_min >= 0, RSD_E_INVALID, "vdw_min must be finite and >= 0");
+  RSD_CHECK(lig_charges && lig_positions, RSD_E_INVALID, "ligand pointers are NULL");
+  if (P == 0) return RSD_OK;
+  RSD_CHECK(quats && trans && energies && flags && counts, RSD_E_INVALID, "pose/output pointers are NULL");
+  RSD_HIP(hipSetDevice(ctx->device));
+  ScoreIO io{};
+  io.lig_charges = lig_charges;
+  io.lig_positions = lig_positions;
+  io.L = (int)L;
+  io.quats = quats;
+  io.trans = trans;
+  io.P = P;
+  io.vdw_min = vdw_min;
+  io.E = energies;
+  io.El = energies_long;
+  io.flags = flags;
+  io.counts = counts;
+  io.grads = grads;
+  return score_noalloc(ctx, t, io);
+}
 
 rsd_status rsd_score_poses(rsd_context* ctx, const rsd_tensor* t, const double* lig_charges,
                            const double* lig_positions, int64_t L, const double* quats, const double* trans,

@@ -221,7 +221,17 @@ struct ScoreIO {
   int32_t* counts;
   double* grads;               // may be null
 };
-rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io);
+// Enqueues the scoring of io.P poses.  Scratch comes from the context's growable workspace, or
+// from ext_ws (ext_bytes long, RSD_E_UNSUPPORTED if too small) when given; with need != nullptr
+// nothing is launched and *need receives the scratch bytes the call would use.
+rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io, void* ext_ws = nullptr,
+                        size_t ext_bytes = 0, size_t* need = nullptr);
+// rsd_score_poses_noalloc (score.hip): launch_score over pose slices whose scratch fits the
+// library's static per-device array; no device memory is allocated.
+rsd_status score_noalloc(Context* ctx, const Tensor* t, const ScoreIO& io);
+// Looks up (once per device, with that device current) the device address of the static
+// scratch array of score_noalloc.
+rsd_status noalloc_scratch_init(int device);
 // rsd_pose_order (score.hip): the spatial order of the long-range kernels and the poses in it;
 // *sorted: whether automatic scoring of t sorts poses itself
 rsd_status pose_order(Context* ctx, const Tensor* t, const double* quats, const double* trans, int64_t P, int* perm,

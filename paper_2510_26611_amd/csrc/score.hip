@@ -1191,8 +1191,12 @@ void tuned_shape(const Context* ctx, const Tensor* t, int L, bool grad, int64_t 
   *W = it->second[2];
 }
 
-rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
-  if (io.P == 0) return RSD_OK;
+rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io, void* ext_ws, size_t ext_bytes,
+                        size_t* need) {
+  if (io.P == 0) {
+    if (need) *need = 0;
+    return RSD_OK;
+  }
   const bool grad = io.grads != nullptr;
   const int L = io.L;
   const int64_t P = io.P;
@@ -1219,8 +1223,18 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   // the sorted poses' copies (quats then trans) after the sort's counts and permutation
   const size_t off_spose = (off_sort + sizeof(int) * (size_t)(kSortCells + 2 * P) + 255) / 256 * 256;
   const size_t total = sorted ? off_spose + sizeof(double) * 7 * (size_t)P : off_sort;
+  if (need) {   // size query only
+    *need = total;
+    return RSD_OK;
+  }
   void* ws = nullptr;
-  RSD_TRY(ctx->workspace(total, &ws));
+  if (ext_ws) {
+    RSD_CHECK(total <= ext_bytes, RSD_E_UNSUPPORTED, "scoring needs %zu bytes of scratch, %zu available", total,
+              ext_bytes);
+    ws = ext_ws;
+  } else {
+    RSD_TRY(ctx->workspace(total, &ws));
+  }
   char* w8 = (char*)ws;
   double4* lig = (double4*)w8;
   double* rlig = (double*)(w8 + off_r);
@@ -1270,7 +1284,7 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
   // beside the long range, forked after the ligand preparation and joined before the
   // combine.
   hipStream_t s_short = s;
-  if (ctx->opt_overlap) {
+  if (ctx->opt_overlap && !ext_ws) {   // (the second stream's set-up allocates)
     RSD_TRY(ctx->aux_streams());
     if (!ctx->ev_fork) RSD_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
     if (!ctx->ev_join) RSD_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
@@ -1308,6 +1322,89 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io) {
                                                                             io.flags, io.E, io.El, nullptr, comb_perm)));
   }
   return RSD_OK;
+}
+
+// ---------------------------------------------------------------- allocation-free scoring
+// The scratch of rsd_score_poses_noalloc: one static array in the code object, so each GPU the
+// library runs on holds its own copy from module load until the process ends.  In host code
+// `scratch` only stands in for the symbol; its device address on each GPU is looked up once,
+// with that GPU current, and every launch receives that address.
+constexpr size_t kNoAllocBytes = (size_t)128 << 20;
+__device__ __align__(256) char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+}  // namespace
+
+rsd_status noalloc_scratch_init(int device) {
+  RSD_CHECK(device >= 0 && device < kMaxDevices, RSD_E_UNSUPPORTED, "device %d beyond %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return RSD_OK;
+  int cur = -1;
+  RSD_HIP(hipGetDevice(&cur));
+  RSD_CHECK(cur == device, RSD_E_INVALID, "device %d is not current", device);
+  void* ptr = nullptr;
+  RSD_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  RSD_CHECK(ptr != nullptr, RSD_E_HIP, "no device address for the static scratch array");
+  g_noalloc_ptr[device] = ptr;
+  return RSD_OK;
+}
+
+// Scores io.P poses in equal slices whose scratch (the same layout launch_score uses) fits the
+// static array; a pose's result does not depend on the slice it falls in.  Nothing here or in
+// launch_score allocates when given the array: the second stream of the overlap option and the
+// timing events are left out.  Nothing in the scratch needs to start at zero (the sort clears
+// its own counts), so stale contents of an earlier call are harmless; calls that overlap on
+// one GPU share the array and race.
+rsd_status score_noalloc(Context* ctx, const Tensor* t, const ScoreIO& io) {
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    base = (ctx->device >= 0 && ctx->device < kMaxDevices) ? g_noalloc_ptr[ctx->device] : nullptr;
+  }
+  RSD_CHECK(base != nullptr, RSD_E_INVALID, "static scratch of device %d was not set up", ctx->device);
+  if (io.P == 0) return RSD_OK;
+  auto need_for = [&](int64_t P, size_t* bytes) -> rsd_status {
+    ScoreIO q = io;
+    q.P = P;
+    return launch_score(ctx, t, q, base, kNoAllocBytes, bytes);
+  };
+  size_t one = 0;
+  RSD_TRY(need_for(1, &one));
+  RSD_CHECK(one <= kNoAllocBytes, RSD_E_UNSUPPORTED,
+            "a single pose needs %zu bytes of scratch, more than the %zu of the static array", one, kNoAllocBytes);
+  // largest slice that fits (the scratch grows with the slice), then equal slices of at most that
+  int64_t lo = 1, hi = io.P;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    size_t b = 0;
+    RSD_TRY(need_for(mid, &b));
+    if (b <= kNoAllocBytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int64_t slices = (io.P + lo - 1) / lo;
+  const int64_t per = (io.P + slices - 1) / slices;
+  const bool saved_timing = ctx->timing;
+  ctx->timing = false;
+  rsd_status st = RSD_OK;
+  for (int64_t p0 = 0; p0 < io.P && st == RSD_OK; p0 += per) {
+    ScoreIO q = io;
+    q.P = std::min<int64_t>(per, io.P - p0);
+    q.quats = io.quats + 4 * p0;
+    q.trans = io.trans + 3 * p0;
+    q.E = io.E + p0;
+    q.El = io.El ? io.El + p0 : nullptr;
+    q.flags = io.flags + p0;
+    q.counts = io.counts + p0;
+    q.grads = io.grads ? io.grads + 6 * p0 : nullptr;
+    st = launch_score(ctx, t, q, base, kNoAllocBytes, nullptr);
+  }
+  ctx->timing = saved_timing;
+  return st;
 }
 
 // ---------------------------------------------------------------- launch-shape tuner

@@ -283,6 +283,25 @@ def score_poses(ctx: Context, tensor: Tensor, lig_charges, lig_positions, quats,
     return out
 
 
+def score_poses_noalloc(ctx: Context, tensor: Tensor, lig_charges, lig_positions, quats, trans, vdw_min: float,
+                        out: dict) -> dict:
+    """rsd_score_poses_noalloc: rsd_score_poses on device tensors with the library's static
+    scratch; `out` holds the caller's output tensors (E, flags, counts[, E_long][, grads])."""
+    args = [_arr(x) for x in (lig_charges, lig_positions, quats, trans)]
+    if not all(a[2] for a in args):
+        raise TypeError("score_poses_noalloc takes device tensors")
+    ep = _arr(out["E"])[0]
+    fp = _arr(out["flags"], np.uint8)[0]
+    cp = _arr(out["counts"], np.int32)[0]
+    elp = _arr(out["E_long"])[0] if "E_long" in out else None
+    gp = _arr(out["grads"])[0] if "grads" in out else None
+    _check(_lib.lib().rsd_score_poses_noalloc(ctx.handle, tensor.handle, args[0][0], args[1][0],
+                                              int(args[0][1].shape[0]), args[2][0], args[3][0],
+                                              int(args[2][1].shape[0]), float(vdw_min), RSD_DEVICE_PTRS, ep, elp,
+                                              fp, cp, gp))
+    return out
+
+
 class Batch:
     """rsd_batch: many requests (device tensors, energies only) scored by one set of launches.
 
