@@ -56,8 +56,12 @@ def _traffic(launch_poses: int):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(cfg, wl, sample: int):
-    """The oracle as it stands: its own tensor build, then scoring a bounded pose sample."""
+def cpu_baseline(cfg, wl, sample: int, F_gpu=None, gpu_out=None):
+    """The oracle as it stands: its own tensor build (timed), then scoring of a bounded pose sample.
+
+    With F_gpu (the factors of the tensor the timed steps scored) the sample is scored on those
+    factors, and the GPU's results of the timed run (gpu_out: E, flags, counts) are checked
+    against it: flags and counts bit-exact, energies within 1e-10 of the summation scale."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
@@ -67,20 +71,32 @@ def cpu_baseline(cfg, wl, sample: int):
     t0 = time.perf_counter()
     _, can = rhosvd.build(wl.protein_charges, wl.protein_positions, tl, wlong, cfg.n, cfg.b, cfg.eps)
     t_build = time.perf_counter() - t0
+    F = F_gpu if F_gpu is not None else can.F
     t0 = time.perf_counter()
-    score.score(can.F, cfg.n, cfg.b, wl.protein_positions, wl.protein_charges, ts, ws, cfg.r_cut,
-                wl.ligand_charges, wl.ligand_positions, wl.quats[:sample], wl.trans[:sample], cfg.sigma)
+    ref = score.score(F, cfg.n, cfg.b, wl.protein_positions, wl.protein_charges, ts, ws, cfg.r_cut,
+                      wl.ligand_charges, wl.ligand_positions, wl.quats[:sample], wl.trans[:sample], cfg.sigma)
     t_score = time.perf_counter() - t0
     per_pose = t_score / sample
     job = t_build + cfg.P * per_pose
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return {
+    res = {
         "value": cfg.P / job, "unit": "poses/s", "cores": threads, "kind": "oracle",
         "sample": (f"oracle tensor build ({t_build:.1f} s, counted once per job) + scoring of the first "
-                   f"{sample} poses ({t_score:.1f} s); value = {cfg.P} poses / (build + {cfg.P} x per-pose time); "
+                   f"{sample} poses ({t_score:.1f} s) on the factors of the tensor the GPU scored; "
+                   f"value = {cfg.P} poses / (build + {cfg.P} x per-pose time); "
                    f"cores = BLAS threads (the elementwise parts run on one thread)"),
         "oracle_build_s": t_build, "oracle_score_poses_per_s": 1.0 / per_pose,
     }
+    if gpu_out is not None:
+        E, flags, counts = (np.asarray(gpu_out[k][:sample]) for k in ("E", "flags", "counts"))
+        ok = ~np.isnan(ref["E"])
+        nan_ok = bool(np.array_equal(np.isnan(E), ~ok))
+        err = np.abs(E[ok] - ref["E"][ok]) / (1e-10 * ref["scale"][ok] + 1e-300)
+        res["parity"] = {"poses": sample, "flags_mismatch": int(np.sum(flags != ref["flags"])),
+                         "counts_mismatch": int(np.sum(counts != ref["counts"])), "nan_pattern_equal": nan_ok,
+                         "max_energy_error_over_tolerance": float(err.max()) if err.size else 0.0,
+                         "tolerance": "1e-10 x per-pose summation scale"}
+    return res
 
 
 def main() -> int:
@@ -110,11 +126,20 @@ def main() -> int:
     ap.add_argument("--hbm-budget-gib", type=float, default=48.0, help="cfg5: HBM for requests in flight")
     ap.add_argument("--round-poses", type=int, default=250_000, help="cfg5: poses per round, shared by the requests")
     ap.add_argument("--min-slice", type=int, default=16_384, help="cfg5: smallest pose slice of a request in a round")
-    ap.add_argument("--sweep", default="0.5,0.8,1.0,1.25", help="cfg5: offered rates as fractions of capacity")
-    ap.add_argument("--sweep-requests", type=int, default=24, help="cfg5: arrivals per sweep point")
+    ap.add_argument("--sweep", default="0.5,0.8", help="cfg5: offered rates as fractions of capacity")
+    ap.add_argument("--sweep-requests", type=int, default=200, help="cfg5: arrivals per sweep point")
+    ap.add_argument("--no-serving", dest="serving", action="store_false",
+                    help="cfg2: leave out the brief config-5 serving comparison of the default line")
+    ap.add_argument("--serving-requests", type=int, default=60,
+                    help="cfg2: arrivals per trace of the brief serving comparison")
+    ap.add_argument("--serve-policy", default="share", choices=["share", "small_first"],
+                    help="cfg5 and the brief serving comparison: how a round's poses are shared among requests")
     ap.add_argument("--dump-requests", default="", help="cfg5: write per-request times (CSV) to this file")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="only run a device copy of this many MiB (counter calibration) and exit")
+    ap.add_argument("--calibrate-gather", action="store_true",
+                    help="only time the long-range kernel's gather pattern alone (rsd_probe_gather) on chunks "
+                         "of 512..8192 rows and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -139,6 +164,15 @@ def main() -> int:
     import paper_2510_26611_amd as rs
     from workloads import configs
 
+    if args.calibrate_gather:
+        ctx = rs.Context(0)
+        rows = []
+        for n in (512, 1024, 2048, 4096, 8192):
+            r = rs.probe_gather(ctx, n, 256)
+            rows.append({"rows_per_chunk": n, "bytes_per_xcd": 2 * n * 512, **r})
+        ctx.close()
+        print(json.dumps({"gather_probe": rows}))
+        return 0
     if args.workload == "cfg3":
         return run_batched(args, rs, configs, torch, np, dev)
     if args.workload == "cfg5":
@@ -186,14 +220,21 @@ def main() -> int:
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # timed region: K whole jobs, no per-launch instrumentation
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # kernel attribution: the same K jobs again with HIP events around every launch
     ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kt = {k: ctx.kernel_time(k) for k in ("score", "long", "short", "combine", "ligand_prep", "cells", "gen",
+    wall_instr = time.perf_counter() - t0
+    kt = {k: ctx.kernel_time(k) for k in ("score", "long", "short", "combine", "ligand_prep", "sort", "cells", "gen",
                                            "gram", "eig", "project", "core", "t2c", "assemble")}
     ctx.set_timing(False)
     ms_step = wall / args.steps * 1e3
@@ -202,13 +243,45 @@ def main() -> int:
     dom_name = "long" if kt["long"][0] else "score"
     n_dom, ms_dom = kt[dom_name]
     dom_ms = ms_dom / max(n_dom, 1)
-    score_ms = sum(kt[k][1] for k in ("score", "long", "short", "combine", "ligand_prep")) / args.steps
+    score_ms = sum(kt[k][1] for k in ("score", "long", "short", "combine", "ligand_prep", "sort")) / args.steps
     alg_bytes = P * (48.0 * cfg.L * R + 56)           # two factor rows per mode per atom + pose inputs
-    achieved = alg_bytes / (dom_ms / 1e3) / 1e9
     traffic = _traffic(P) if args.workload == "cfg2" else None
     flags = out["flags"].cpu().numpy()
-    # the same scoring call with host arrays (PCIe upload and download inside the call)
+    # the roofline of the gathers: bytes the long-range kernel moves from L2 into the compute
+    # units (per atom and rank chunk: rows i and i+1 of modes 1-2, 512 bytes each, and of mode 3
+    # unless the chunk takes its mode-3 lerps from U_3, read as 2 x 4 values per atom), against the
+    # rate of the same gather pattern alone (rsd_probe_gather, measured here)
     t = rs.build_rs_tensor(ctx, d_z, d_x, cfg.n, cfg.b, sinc)
+    lay = t.layout()
+    nch, u3 = lay["nchunk"], lay["shared_mode3"]
+    moved = P * cfg.L * (u3 * (4 * 512 + 64) + (nch - u3) * 6 * 512)
+    pn = 2048                                          # 2 MB per XCD: the L2-resident ceiling
+    probe = rs.probe_gather(ctx, pn, 256)
+    flops = P * cfg.L * nch * 64 * 10.0                # per atom and column: two lerps, two products, one FMA
+    roof = {"kernel": dom_name, "kernel_ms": dom_ms}
+    if dom_name == "long":
+        achieved = moved / (dom_ms / 1e3) / 1e9
+        roof.update({"bound": "l2_gather", "achieved": achieved, "peak": probe["gbs"], "unit": "GB/s",
+                     "frac": achieved / probe["gbs"], "traffic": traffic,
+                     "bytes_per_launch": moved,
+                     "peak_source": (f"rsd_probe_gather on this GPU: the kernel's gather pattern alone (16-byte "
+                                     f"loads of rows i, i+1 of two modes per half-wavefront, {pn}-row chunks, "
+                                     f"one per XCD), {probe['bytes'] / 1e9:.2f} GB in {probe['ms']:.3f} ms"),
+                     "chunks": nch, "chunks_mode3_from_U3": u3})
+    else:
+        achieved = alg_bytes / (dom_ms / 1e3) / 1e9
+        roof.update({"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None})
+    roof["hbm_algorithmic"] = {"bytes_per_launch": alg_bytes, "GB_per_s": alg_bytes / (dom_ms / 1e3) / 1e9,
+                               "multiple_of_hbm_peak": alg_bytes / (dom_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                               "note": "48 L R bytes per pose (Lemma 3.3's two rows per mode per atom) over the "
+                                       "8 TB/s HBM peak; the factors stay in L2, so this multiple exceeds 1"}
+    roof["fp64_valu"] = {"tflops": flops / (dom_ms / 1e3) / 1e12, "peak_tflops": FP64_MFMA_PEAK_TFS,
+                         "frac": flops / (dom_ms / 1e3) / 1e12 / FP64_MFMA_PEAK_TFS}
+    F_gpu = None
+    if not args.no_cpu_baseline and args.workload == "cfg2":
+        F_gpu = t.export()
+    # the same scoring call with host arrays (PCIe upload and download inside the call)
     rs.score_poses(ctx, t, wl.ligand_charges, wl.ligand_positions, wl.quats[:4096], wl.trans[:4096], cfg.sigma,
                    grads=want_grad)
     torch.cuda.synchronize()
@@ -224,11 +297,9 @@ def main() -> int:
                    "box_b_A": cfg.b, "sinc_M": cfg.M, "K_long": cfg.K_long, "rhosvd_eps": cfg.eps,
                    "poses": P, "vdw_min_A": cfg.sigma, "canonical_rank": R, "tucker_ranks": list(info["ranks"]),
                    "parallelism": "single GPU, data-parallel over poses"},
-        "roofline": {"kernel": dom_name, "kernel_ms": dom_ms, "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic},
+        "roofline": roof,
         "breakdown": {k: {"launches": v[0], "ms_per_step": v[1] / args.steps} for k, v in kt.items() if v[0]},
+        "ms_per_step_with_kernel_events": wall_instr / args.steps * 1e3,
         "autotune": tune, "short_range_on_second_stream": bool(args.overlap),
         "score_host_arrays_poses_per_s": P / host_io_s,
         "score_only_poses_per_s": P / (score_ms / 1e3),
@@ -248,9 +319,16 @@ def main() -> int:
     if want_grad:
         res["metric"] = "poses scored/sec with energy + 6-DoF adjoint gradient at the oracle's tolerance"
     if not args.no_cpu_baseline and args.workload == "cfg2":
-        res["cpu_baseline"] = cpu_baseline(cfg, wl, args.cpu_sample)
+        res["cpu_baseline"] = cpu_baseline(cfg, wl, args.cpu_sample, F_gpu,
+                                           {k: v.cpu().numpy() for k, v in out.items()})
+    if args.serving and args.workload == "cfg2":
+        ctx.close()
+        ctx = None
+        torch.cuda.synchronize()
+        res["serving"] = serving_block(args, rs, configs, torch, np)
     print(json.dumps(res), flush=True)
-    ctx.close()
+    if ctx is not None:
+        ctx.close()
     return 0
 
 
@@ -299,24 +377,46 @@ def run_batched(args, rs, configs, torch, np, dev) -> int:
     per_request()
     kt_req = {k: ctx.kernel_time(k) for k in ("ligand_prep", "short", "long", "combine", "score")}
     ctx.set_timing(False)
-    batch = rs.Batch(ctx, reqs)
-    ms_batch = timed(batch.run) * 1e3
-    s = torch.cuda.Stream()
-    s.wait_stream(stream)
-    ctx.set_stream(s.cuda_stream)
-    with torch.cuda.stream(s):
+    def graph_of(batch):
+        s = torch.cuda.Stream()
+        s.wait_stream(stream)
+        ctx.set_stream(s.cuda_stream)
+        with torch.cuda.stream(s):
+            batch.run()
+        s.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=s):
+            batch.run()
+        ctx.set_stream(stream.cuda_stream)
+        return graph
+
+    # the batch both ways: requests grouped into launches by LDS occupancy (batch_mode 1), and
+    # one persistent launch over per-XCD work queues (batch_mode 2); each eagerly and replayed
+    modes = {}
+    for mode in (1, 2):
+        ctx.set_option("batch_mode", mode)
+        batch = rs.Batch(ctx, reqs)
+        ms_b = timed(batch.run) * 1e3
+        graph = graph_of(batch)
+        ms_g = timed(graph.replay) * 1e3
+        ctx.set_timing(True)
         batch.run()
-    s.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph, stream=s):
-        batch.run()
-    ctx.set_stream(stream.cuda_stream)
-    ms_graph = timed(graph.replay) * 1e3
-    ctx.set_timing(True)
-    batch.run()
-    kt = {k: ctx.kernel_time(k) for k in ("ligand_prep", "short", "long", "combine")}
-    ctx.set_timing(False)
+        kt = {k: ctx.kernel_time(k) for k in ("ligand_prep", "sort", "short", "long", "fused", "combine")}
+        ctx.set_timing(False)
+        modes[mode] = dict(batch_ms=ms_b, graph_ms=ms_g, breakdown={k: {"launches": v[0], "ms": v[1]}
+                                                                    for k, v in kt.items() if v[0]})
+        del graph
+        batch.free()
+    ctx.set_option("batch_mode", 0)
+    best = min(modes, key=lambda m: modes[m]["graph_ms"])
+    ms_graph, ms_batch = modes[best]["graph_ms"], modes[best]["batch_ms"]
+    kt = {k: (v["launches"], v["ms"]) for k, v in modes[1]["breakdown"].items()}
     long_ms = kt["long"][1]
+    moved = 0
+    for w, t in zip(pairs, tensors):
+        lay = t.layout()
+        moved += w.cfg.P * w.cfg.L * (lay["shared_mode3"] * (4 * 512 + 64) + (lay["nchunk"] - lay["shared_mode3"]) * 6 * 512)
+    probe = rs.probe_gather(ctx, 2048, 256)
     res = {
         "metric": METRIC, "value": total / (ms_graph / 1e3), "unit": "poses/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph, "higher_is_better": True,
@@ -328,16 +428,20 @@ def run_batched(args, rs, configs, torch, np, dev) -> int:
         "per_request_poses_per_s": total / (ms_req / 1e3), "per_request_ms": ms_req,
         "batch_poses_per_s": total / (ms_batch / 1e3), "batch_ms": ms_batch,
         "graph_poses_per_s": total / (ms_graph / 1e3), "graph_ms": ms_graph,
-        "roofline": {"kernel": "long", "kernel_ms": long_ms, "bound": "hbm", "achieved": alg / (long_ms / 1e3) / 1e9,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / (long_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None},
+        "batch_mode_timed": {1: "grouped launches", 2: "one persistent launch"}[best],
+        "grouped_launches": modes[1], "persistent_launch": modes[2],
+        "roofline": {"kernel": "long", "kernel_ms": long_ms, "bound": "l2_gather",
+                     "achieved": moved / (long_ms / 1e3) / 1e9, "peak": probe["gbs"], "unit": "GB/s",
+                     "frac": moved / (long_ms / 1e3) / 1e9 / probe["gbs"], "traffic": None,
+                     "bytes_per_launch": moved,
+                     "peak_source": "rsd_probe_gather on this GPU (the gather pattern alone, 2048-row chunks)",
+                     "hbm_algorithmic": {"bytes_per_launch": alg, "GB_per_s": alg / (long_ms / 1e3) / 1e9,
+                                         "multiple_of_hbm_peak": alg / (long_ms / 1e3) / 1e9 / HBM_PEAK_GBS}},
         "breakdown": {k: {"launches": v[0], "ms": v[1]} for k, v in kt.items()},
         "per_request_breakdown": {k: {"launches": v[0], "ms": v[1]} for k, v in kt_req.items() if v[0]},
         "tensor_build_s_total": build_s,
     }
     print(json.dumps(res), flush=True)
-    del graph
-    batch.free()
     for t in tensors:
         t.free()
     ctx.close()
@@ -525,17 +629,9 @@ def run_ppiem(args, rs, configs, torch, np, dev) -> int:
     return 0
 
 
-def run_serving(args, rs, configs, torch, np) -> int:
-    """Config 5: 8 resident proteins (1e3..1e5 atoms, n up to 16384) serving a Poisson request stream.
-
-    Reported: served poses/s and arrival-to-result p50/p99 for the continuous-batching server and
-    for plain one-request-at-a-time calls on the same trace, and a sweep of offered rates around
-    the measured capacity (the stated 200 req/s is far beyond it)."""
+def _serving_setup(args, rs, configs, torch, np, note):
+    """The 8 resident proteins of config 5, built on the device once; a warmed-up server."""
     from paper_2510_26611_amd import serve
-
-    def note(msg):
-        print(msg, file=sys.stderr, flush=True)
-
     ctx = rs.Context(0)
     tensors, builds = {}, []
     for i, (c, pos, z) in enumerate(configs.make_serving_proteins()):
@@ -551,70 +647,129 @@ def run_serving(args, rs, configs, torch, np) -> int:
              f"{q['bytes'] / 2**30:.2f} GiB in {builds[-1]['build_s']:.2f} s")
     resident = sum(b["bytes"] for b in builds)
     budget = int(resident + args.hbm_budget_gib * 2**30)
-    Rk = {f"p{i}": b["canonical_rank"] for i, b in enumerate(builds)}
+    srv = serve.Server(tensors, budget, round_poses=args.round_poses, min_slice=args.min_slice,
+                       policy=args.serve_policy)
+    warm = _requests(serve, configs.make_serving_trace(4, rate=1e6, pose_scale=0.01, seed_offset=9))
+    srv.run(warm, realtime=False)
+    serve.serve_plain(ctx, tensors, _requests(serve, configs.make_serving_trace(2, rate=1e6, pose_scale=0.01,
+                                                                                  seed_offset=9)), realtime=False)
+    torch.cuda.synchronize()
+    note("warm-up done")
+    return ctx, tensors, builds, budget, resident, srv
 
-    def requests(tr):
-        return [serve.Request(r.index, f"p{r.protein}", r.ligand_charges, r.ligand_positions, r.quats, r.trans,
-                              r.sigma, r.arrival) for r in tr]
+
+def _requests(serve, tr):
+    return [serve.Request(r.index, f"p{r.protein}", r.ligand_charges, r.ligand_positions, r.quats, r.trans,
+                          r.sigma, r.arrival) for r in tr]
+
+
+def _served_and_plain(serve, srv, ctx, tensors, trace, note, tag, every=0):
+    """The same trace through the continuous-batching server and through plain one-at-a-time
+    calls (arrivals in real time for both); per-mode throughput and latency percentiles."""
+    import numpy as np
+    prog = (lambda m: (lambda d, n: note(f"{tag} {m}: {d}/{n} done") if d % every == 0 or d == n else None)) \
+        if every else (lambda m: None)
+    served = _requests(serve, trace)
+    st = srv.run(served, progress=prog("served"))
+    plain = _requests(serve, trace)
+    sp = serve.serve_plain(ctx, tensors, plain, progress=prog("plain"))
+    # served results equal the same requests scored alone (bitwise), on the three smallest
+    for r in sorted(served, key=lambda r: r.P)[:3]:
+        pl = next(x for x in plain if x.rid == r.rid)
+        for k in ("E", "flags", "counts"):
+            if not np.array_equal(r.result[k], pl.result[k], equal_nan=True):
+                raise RuntimeError(f"served request {r.rid} differs from the same request alone ({k})")
+    keys = ("poses_per_s", "latency_p50_s", "latency_p99_s", "latency_max_s", "queue_wait_p50_s", "wall_s",
+            "served", "poses")
+    note(f"{tag}: served {st['poses_per_s']:.3g} poses/s p50 {st['latency_p50_s']:.2f} s p99 "
+         f"{st['latency_p99_s']:.2f} s | plain {sp['poses_per_s']:.3g} poses/s p50 {sp['latency_p50_s']:.2f} s "
+         f"p99 {sp['latency_p99_s']:.2f} s")
+    return {"served": {k: st[k] for k in keys}, "plain": {k: sp[k] for k in keys}}, served, plain
+
+
+def serving_block(args, rs, configs, torch, np) -> dict:
+    """Config 5 in brief, for the default measurement line: the same arrival traces served by
+    the continuous-batching server and by plain calls, at the stated 200 req/s (far beyond
+    capacity: both queue) and at half the capacity measured on the first trace."""
+    from paper_2510_26611_amd import serve
+
+    def note(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    ctx, tensors, builds, budget, resident, srv = _serving_setup(args, rs, configs, torch, np, note)
+    n = args.serving_requests
+    tr = configs.make_serving_trace(n, rate=args.rate)
+    mean_P = float(np.mean([r.quats.shape[0] for r in tr]))
+    at_rate, _, _ = _served_and_plain(serve, srv, ctx, tensors, tr, note, f"{args.rate:g} req/s")
+    cap = at_rate["served"]["poses_per_s"] / mean_P
+    tr2 = configs.make_serving_trace(n, rate=0.5 * cap, seed_offset=1)
+    at_half, _, _ = _served_and_plain(serve, srv, ctx, tensors, tr2, note, "0.5 x capacity")
+    srv.close()
+    for t in tensors.values():
+        t.free()
+    ctx.close()
+    return {"workload": f"cfg5: {len(builds)} resident proteins of 1e3-1e5 atoms (n = 8192/16384), ligands of "
+                        f"10-200 atoms, 1e4-1e6 poses per request (log-uniform), Poisson arrivals",
+            "arrivals_per_trace": n, "resident_bytes": resident, "hbm_budget_bytes": budget,
+            "at_offered_rate": dict(offered_req_s=args.rate, mean_poses_per_request=mean_P, **at_rate),
+            "capacity_req_s": cap,
+            "at_half_capacity": dict(offered_req_s=0.5 * cap, **at_half),
+            "policy": args.serve_policy, "round_poses": args.round_poses, "min_slice": args.min_slice,
+            "latency": "arrival to the request's last results in host memory"}
+
+
+def run_serving(args, rs, configs, torch, np) -> int:
+    """Config 5: 8 resident proteins (1e3..1e5 atoms, n up to 16384) serving a Poisson request stream.
+
+    Reported: served poses/s and arrival-to-result p50/p99 for the continuous-batching server and
+    for plain one-request-at-a-time calls on the same trace, and the same comparison on one
+    second trace replayed at fractions of the capacity measured on the first (the stated
+    200 req/s is far beyond it)."""
+    from paper_2510_26611_amd import serve
+
+    def note(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    ctx, tensors, builds, budget, resident, srv = _serving_setup(args, rs, configs, torch, np, note)
+    Rk = {f"p{i}": b["canonical_rank"] for i, b in enumerate(builds)}
 
     def alg_bytes(reqs):
         return sum(48.0 * r.L * Rk[r.protein] * r.P for r in reqs if r.state == serve.DONE)
-
-    srv = serve.Server(tensors, budget, round_poses=args.round_poses, min_slice=args.min_slice)
-    warm = requests(configs.make_serving_trace(4, rate=1e6, pose_scale=0.01, seed_offset=9))
-    srv.run(warm, realtime=False)
-    serve.serve_plain(ctx, tensors, requests(configs.make_serving_trace(2, rate=1e6, pose_scale=0.01,
-                                                                        seed_offset=9)), realtime=False)
-    torch.cuda.synchronize()
-    note("warm-up done")
 
     trace = configs.make_serving_trace(args.requests, rate=args.rate)
     mean_P = float(np.mean([r.quats.shape[0] for r in trace]))
     note(f"trace: {len(trace)} requests, {sum(r.quats.shape[0] for r in trace)} poses, offered "
          f"{args.rate * mean_P:.3g} poses/s")
-    every = max(1, args.requests // 10)
-    prog = lambda tag: (lambda d, n: note(f"{tag}: {d}/{n} done") if d % every == 0 or d == n else None)  # noqa: E731
-    served_reqs = requests(trace)
-    st = srv.run(served_reqs, progress=prog("served"))
-    st["alg_bytes_per_s"] = alg_bytes(served_reqs) / st["wall_s"]
-    # served results equal the same requests scored alone (bitwise), on the three smallest
-    for r in sorted(served_reqs, key=lambda r: r.P)[:3]:
-        alone = rs.score_poses(ctx, tensors[r.protein], r.lig_charges, r.lig_positions, r.quats, r.trans, r.vdw_min)
-        for k in ("E", "flags", "counts"):
-            if not np.array_equal(r.result[k], alone[k], equal_nan=True):
-                raise RuntimeError(f"served request {r.rid} differs from the same request alone ({k})")
-    plain_reqs = requests(trace)
-    st_plain = serve.serve_plain(ctx, tensors, plain_reqs, progress=prog("plain"))
-    st_plain["alg_bytes_per_s"] = alg_bytes(plain_reqs) / st_plain["wall_s"]
-
+    main, served_reqs, plain_reqs = _served_and_plain(serve, srv, ctx, tensors, trace, note, f"{args.rate:g} req/s",
+                                                      every=max(1, args.requests // 10))
+    main["served"]["alg_bytes_per_s"] = alg_bytes(served_reqs) / main["served"]["wall_s"]
+    main["plain"]["alg_bytes_per_s"] = alg_bytes(plain_reqs) / main["plain"]["wall_s"]
     if args.dump_requests:
         with open(args.dump_requests, "w") as f:
             f.write("mode,rid,protein,L,P,arrival_s,admit_s,done_s\n")
             for mode, rr in (("served", served_reqs), ("plain", plain_reqs)):
                 for r in rr:
                     f.write(f"{mode},{r.rid},{r.protein},{r.L},{r.P},{r.arrival:.4f},{r.t_admit:.4f},{r.t_done:.4f}\n")
-    cap = st["poses_per_s"] / mean_P
+    cap = main["served"]["poses_per_s"] / mean_P
+    # one second trace, replayed at each offered rate: the same requests, arrival gaps rescaled
     sweep = []
-    for k, frac in enumerate(float(x) for x in args.sweep.split(",") if x):
+    for frac in (float(x) for x in args.sweep.split(",") if x):
         rate = frac * cap
-        tr = requests(configs.make_serving_trace(args.sweep_requests, rate=rate, seed_offset=1 + k))
-        ss = srv.run(tr)
-        sweep.append({"offered_fraction_of_capacity": frac, "offered_req_s": rate, "served_req_s":
-                      ss["served"] / ss["wall_s"], "poses_per_s": ss["poses_per_s"],
-                      "latency_p50_s": ss["latency_p50_s"], "latency_p99_s": ss["latency_p99_s"]})
-        note(f"sweep {frac:.2f} x capacity ({rate:.2f} req/s): p50 {ss['latency_p50_s']:.2f} s "
-             f"p99 {ss['latency_p99_s']:.2f} s")
+        tr = configs.make_serving_trace(args.sweep_requests, rate=rate, seed_offset=1)
+        pt, _, _ = _served_and_plain(serve, srv, ctx, tensors, tr, note, f"{frac:.2f} x capacity",
+                                     every=max(1, args.sweep_requests // 4))
+        sweep.append(dict(offered_fraction_of_capacity=frac, offered_req_s=rate, **pt))
     res = {
-        "metric": METRIC, "value": st["poses_per_s"], "unit": "poses/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": st["wall_s"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "metric": METRIC, "value": main["served"]["poses_per_s"], "unit": "poses/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": main["served"]["wall_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"cfg5-serving-{len(builds)}proteins", "requests": len(trace),
                    "offered_req_s": args.rate, "offered_poses_per_s": args.rate * mean_P,
                    "mean_poses_per_request": mean_P, "hbm_budget_bytes": budget, "resident_bytes": resident,
                    "round_poses": args.round_poses, "min_slice": args.min_slice,
                    "parallelism": "single GPU, continuous batching of pose slices, 2 streams"},
-        "latency_p50_s": st["latency_p50_s"], "latency_p99_s": st["latency_p99_s"],
-        "served": st, "plain_per_request": st_plain,
+        "latency_p50_s": main["served"]["latency_p50_s"], "latency_p99_s": main["served"]["latency_p99_s"],
+        "served": main["served"], "plain_per_request": main["plain"],
         "capacity_req_s": cap, "rate_sweep": sweep, "proteins": builds,
     }
     print(json.dumps(res), flush=True)

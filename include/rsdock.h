@@ -175,9 +175,10 @@ rsd_status rsd_score_poses_noalloc(rsd_context* ctx, const rsd_tensor* tensor,
  * and no gradients; the tensors may differ between requests but belong to one context.
  * rsd_batch_create validates the requests, allocates the batch's device scratch (per-request
  * ligand frames, short-range energies, long-range partials) and enqueues the upload of a
- * request table on the context stream (it returns without waiting for the device).  rsd_batch_run enqueues four launches on the context stream that score
+ * request table on the context stream (it returns without waiting for the device).  rsd_batch_run enqueues the launches on the context stream that score
  * every request (ligand frames; short-range, vdW and counts; long-range in rank-chunk-major
- * order over all requests; combine); it allocates nothing and does not synchronise, so it
+ * order over all requests; combine), grouped by LDS occupancy or as one persistent launch
+ * (option batch_mode); it allocates nothing and does not synchronise, so it
  * may be captured in a HIP graph and replayed.  The request arrays are read at run time:
  * new poses written into the same buffers are scored by the next run.  Each pose scores
  * bit for bit as in rsd_score_poses with option score_mode = 2.  The tensors may come from
@@ -304,6 +305,25 @@ rsd_status rsd_tensor_grid(const rsd_tensor* t, double X0[3], int32_t rows[3], d
 rsd_status rsd_tensor_query(const rsd_tensor* t, int32_t* n, int64_t* R, int32_t ranks[3],
                             size_t* bytes);
 
+/* Factor layout of a tensor, for accounting the bytes the long-range gathers move
+ * (Lemma 3.3: two rows per mode per ligand atom):
+ *   nchunk          number of 64-column rank chunks (R padded to a multiple of 64)
+ *   shared_mode3    chunks whose 64 columns use at most 4 distinct mode-3 columns of the
+ *                   Tucker basis U_3; for them scoring reads the mode-3 rows of the U_3
+ *                   columns once per atom instead of gathering the factor rows (tensors made
+ *                   by the canonical -> Tucker -> canonical step; 0 for imported ones). */
+rsd_status rsd_tensor_layout(const rsd_tensor* t, int32_t* nchunk, int32_t* shared_mode3);
+
+/* Measurement helper: times (best of 5 launches, HIP events on the context stream) a kernel
+ * that performs only the long-range scoring kernel's gathers: per half-wavefront one row i
+ * of a 64-column chunk per step, 16-byte loads of rows i and i+1 of two modes per lane, on a
+ * 2 * n * 512-byte working set per XCD.  Its rate is the ceiling of the L2 -> compute-unit
+ * return path for that pattern, against which the scoring kernel's gathers are reported.
+ *   n      rows per chunk (power of two, 4..16384); iters: steps per wavefront (1..4096)
+ *   ms     best launch time; bytes: bytes loaded per launch.
+ * Synchronous.  Uses the context's workspace.  Errors: RSD_E_INVALID, RSD_E_OOM, RSD_E_HIP. */
+rsd_status rsd_probe_gather(rsd_context* ctx, int32_t n, int32_t iters, double* ms, double* bytes);
+
 /* Copy the factors to host arrays F1, F2, F3 of n*R doubles each (row-major n x R).
  * Synchronous. */
 rsd_status rsd_tensor_export(const rsd_tensor* t, double* F1, double* F2, double* F3);
@@ -326,13 +346,25 @@ void rsd_tensor_free(rsd_tensor* t);
  *   "factors"         1-D factors of rsd_build_rs_tensor: 0 (default) the Gaussians collocated
  *                     at the grid nodes; 1 their averages over the grid cells, i.e. the
  *                     projection onto piecewise-constant basis functions of eq. 2.1 (the Gram
- *                     matrices are then formed densely on the matrix cores)
+ *                     matrices are then formed densely on the matrix cores); 2 (3) the
+ *                     shift-and-window construction of eq. 2.5: every charge is moved to its
+ *                     nearest grid node (j = floor((x - X_0)/h + 1/2), clipped to the grid) and
+ *                     the single-charge reference Gaussians (cell averages) are centred there and
+ *                     windowed onto the grid; the long range then errs to first order in h
+ *                     (Table 3.2), while the short range and the vdW test keep the true positions
  *   "svd_solver"      the k x k SVD inside the rank reduction of explicit factors
  *                     (rsd_tensor_restrict, rsd_tensor_combine): 0 automatic, 1 rocSOLVER gesvd,
  *                     2 rocSOLVER gesdd (divide and conquer), 3 rocSOLVER gesvdj (Jacobi)
  *   "gram_solver"     Gram matrices of the side matrices in the build: 0 automatic (1),
  *                     1 Toeplitz-times-Hankel form of the uniform grid (O(n N K + n^2 K)),
  *                     2 dense product of the generated side matrix on matrix cores (O(n^2 N K))
+ *   "batch_mode"      launches of rsd_batch_run (fixed when the batch is created): 0 automatic
+ *                     (currently 1), 1 requests grouped by LDS occupancy, one short-range and one
+ *                     long-range launch per group; 2 one persistent launch for the transform,
+ *                     short range, vdW test and long range of every request, its workgroups
+ *                     claiming work items from one queue per XCD (requests whose ligands need more
+ *                     than 160 KB of LDS in that form fall back to 1); both add a ligand-frame
+ *                     launch before and a combine launch after, and give the same bits
  *   "short_waves"     wavefronts (poses) per workgroup of the short-range kernel: 0 automatic,
  *                     1, 2 or 4 (must fit 64 KB of LDS for the ligand)
  *   "shared_mode3"    1 (default): for tensors made by the build, a restriction or a combine,
@@ -407,6 +439,19 @@ typedef struct rsd_tune_report {
 rsd_status rsd_autotune(rsd_context* ctx, const rsd_tensor* t, const double* lig_charges,
                         const double* lig_positions, int64_t L, const double* quats, const double* trans,
                         int64_t P, double vdw_min, int32_t grads, rsd_tune_report* report);
+
+/* The cell size of the tensor's short-range cell list, tuned on a sample of a workload
+ * (device pointers, as rsd_autotune): the list is rebuilt with cell edges r_cut / div for
+ * div = 3, 4, 5, 6 (at most 128 cells per axis), scoring of the sample is timed for each
+ * (best of 3 calls, the launch shapes the context would pick), and the fastest edge stays
+ * with the tensor.  ms[4] (may be NULL): milliseconds per call for div = 3..6; *best_div:
+ * the divisor kept.  Pair counts and flags do not depend on the cell size; energies change
+ * only by the order in which the short range adds its pairs.  The tensor must not be in use
+ * by queued work of other streams.  Synchronous.  Errors: as rsd_autotune. */
+rsd_status rsd_autotune_cells(rsd_context* ctx, rsd_tensor* t, const double* lig_charges,
+                              const double* lig_positions, int64_t L, const double* quats,
+                              const double* trans, int64_t P, double vdw_min, int32_t grads,
+                              int32_t* best_div, double* ms);
 
 /* Kernel timing with HIP events on the context stream (off by default).  When on,
  * every library kernel launch is bracketed by events and its duration is added to

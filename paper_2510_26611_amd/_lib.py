@@ -32,6 +32,7 @@ EXPORTED = [
     "rsd_tensor_restrict", "rsd_tensor_grid", "rsd_tensor_combine",
     "rsd_tensor_centre", "rsd_contact_poses", "rsd_orbit_minima",
     "rsd_self_energy", "rsd_pose_order", "rsd_score_poses_noalloc",
+    "rsd_tensor_layout", "rsd_probe_gather", "rsd_autotune_cells",
 ]
 
 
@@ -75,6 +76,9 @@ def _declare(lib: C.CDLL) -> C.CDLL:
                                    C.POINTER(_P)]),
         "rsd_score_poses": (st, [_P, _P, _P, _P, _I64, _P, _P, _I64, _D, _U32, _P, _P, _P, _P, _P]),
         "rsd_score_poses_noalloc": (st, [_P, _P, _P, _P, _I64, _P, _P, _I64, _D, _U32, _P, _P, _P, _P, _P]),
+        "rsd_tensor_layout": (st, [_P, _P, _P]),
+        "rsd_probe_gather": (st, [_P, _I32, _I32, _P, _P]),
+        "rsd_autotune_cells": (st, [_P, _P, _P, _P, _I64, _P, _P, _I64, _D, _I32, _P, _P]),
         "rsd_tensor_query": (st, [_P, C.POINTER(_I32), C.POINTER(_I64), C.POINTER(_I32), C.POINTER(_SZ)]),
         "rsd_tensor_export": (st, [_P, _P, _P, _P]),
         "rsd_tensor_save": (st, [_P, C.c_char_p]),

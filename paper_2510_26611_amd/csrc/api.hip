@@ -574,8 +574,34 @@ static rsd_status make_tensor(rsd_context* ctx, const double* const F[3], int64_
   rsd_status st = tensor_common(ctx, t, n, b, sp, std::move(z), std::move(pos), &d_z, &d_pos);
   if (st == RSD_OK) {
     if (build) {
-      t->galerkin = ctx->opt_factors == 1;
-      st = build_factors(ctx, t, d_z, d_pos);
+      t->galerkin = (ctx->opt_factors & 1) != 0;
+      t->snapped = (ctx->opt_factors & 2) != 0;
+      if (t->snapped) {
+        // eq. 2.5: every charge moves to its nearest grid node, j = floor((x - X_0)/h + 1/2)
+        // clipped to [0, n-1], at X_j = -b + (j + 1) h; the long-range factors are those of the
+        // moved charges (a reference Gaussian centred on the node, windowed onto the grid), while
+        // the short range and the vdW test keep the true positions
+        std::vector<double> snap(t->host_positions.size());
+        for (size_t i = 0; i < snap.size(); ++i) {
+          double j = std::floor((t->host_positions[i] - t->X0) * t->inv_h + 0.5);
+          j = std::min(std::max(j, 0.0), (double)(n - 1));
+          snap[i] = -b + (j + 1.0) * t->h;
+        }
+        double* d_snap = nullptr;
+        st = ctx->dev_alloc((void**)&d_snap, sizeof(double) * snap.size());
+        if (st == RSD_OK) {
+          hipError_t e = hipMemcpy(d_snap, snap.data(), sizeof(double) * snap.size(), hipMemcpyHostToDevice);
+          if (e != hipSuccess) {
+            set_error("hipMemcpy: %s", hipGetErrorString(e));
+            st = RSD_E_HIP;
+          }
+          if (st == RSD_OK) st = build_factors(ctx, t, d_z, d_snap);
+          (void)hipStreamSynchronize(ctx->stream);
+          ctx->dev_free(d_snap, sizeof(double) * snap.size());
+        }
+      } else {
+        st = build_factors(ctx, t, d_z, d_pos);
+      }
     } else {
       st = import_factors(ctx, t, F, R, dev);
     }
@@ -867,6 +893,22 @@ rsd_status rsd_tensor_query(const rsd_tensor* t, int32_t* n, int64_t* R, int32_t
   return RSD_OK;
 }
 
+rsd_status rsd_tensor_layout(const rsd_tensor* t, int32_t* nchunk, int32_t* shared_mode3) {
+  clear_error();
+  RSD_CHECK(t != nullptr, RSD_E_INVALID, "tensor is NULL");
+  if (nchunk) *nchunk = t->nchunk;
+  if (shared_mode3) *shared_mode3 = t->U3 ? t->u3_chunks : 0;
+  return RSD_OK;
+}
+
+rsd_status rsd_probe_gather(rsd_context* ctx, int32_t n, int32_t iters, double* ms, double* bytes) {
+  clear_error();
+  RSD_CHECK(ctx != nullptr && ms != nullptr && bytes != nullptr, RSD_E_INVALID, "NULL argument");
+  RSD_CHECK(!ctx->closing, RSD_E_INVALID, "context has been freed");
+  RSD_HIP(hipSetDevice(ctx->device));
+  return probe_gather(ctx, n, iters, ms, bytes);
+}
+
 rsd_status rsd_tensor_export(const rsd_tensor* t, double* F1, double* F2, double* F3) {
   clear_error();
   RSD_CHECK(t != nullptr, RSD_E_INVALID, "tensor is NULL");
@@ -931,7 +973,7 @@ rsd_status rsd_score_poses(rsd_context* ctx, const rsd_tensor* t, const double* 
   RSD_CHECK(!ctx->closing, RSD_E_INVALID, "context has been freed");
   RSD_CHECK(t->ctx->device == ctx->device, RSD_E_INVALID, "tensor lives on another device");
   RSD_CHECK(L >= 1 && L <= kMaxLigand, RSD_E_UNSUPPORTED, "L=%lld outside [1, %d]", (long long)L, kMaxLigand);
-  RSD_CHECK(P >= 0 && P <= ((int64_t)1 << 33), RSD_E_INVALID, "P=%lld out of range", (long long)P);
+  RSD_CHECK(P >= 0 && P <= (int64_t)INT32_MAX, RSD_E_INVALID, "P=%lld out of range", (long long)P);
   RSD_CHECK(std::isfinite(vdw_min) && vdw_min >= 0, RSD_E_INVALID, "vdw_min must be finite and >= 0");
   RSD_CHECK(lig_charges && lig_positions, RSD_E_INVALID, "ligand pointers are NULL");
   if (P == 0) return RSD_OK;
@@ -1039,7 +1081,7 @@ rsd_status rsd_autotune(rsd_context* ctx, const rsd_tensor* t, const double* lig
   RSD_CHECK(!ctx->closing, RSD_E_INVALID, "context has been freed");
   RSD_CHECK(t->ctx->device == ctx->device, RSD_E_INVALID, "tensor lives on another device");
   RSD_CHECK(L >= 1 && L <= kMaxLigand, RSD_E_UNSUPPORTED, "L=%lld outside [1, %d]", (long long)L, kMaxLigand);
-  RSD_CHECK(P >= 1 && P <= ((int64_t)1 << 33), RSD_E_INVALID, "P=%lld out of range", (long long)P);
+  RSD_CHECK(P >= 1 && P <= (int64_t)INT32_MAX, RSD_E_INVALID, "P=%lld out of range", (long long)P);
   RSD_CHECK(std::isfinite(vdw_min) && vdw_min >= 0, RSD_E_INVALID, "vdw_min must be finite and >= 0");
   RSD_CHECK(lig_charges && lig_positions && quats && trans, RSD_E_INVALID, "input pointers are NULL");
   RSD_HIP(hipSetDevice(ctx->device));
@@ -1061,6 +1103,40 @@ rsd_status rsd_autotune(rsd_context* ctx, const rsd_tensor* t, const double* lig
   io.counts = (int32_t*)(io.E + P * (grads ? 7 : 1));
   io.flags = (uint8_t*)(io.counts + P);
   const rsd_status st = rsd::autotune(ctx, t, io, report);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->block_release(out, bytes);
+  return st;
+}
+
+rsd_status rsd_autotune_cells(rsd_context* ctx, rsd_tensor* t, const double* lig_charges,
+                              const double* lig_positions, int64_t L, const double* quats, const double* trans,
+                              int64_t P, double vdw_min, int32_t grads, int32_t* best_div, double* ms) {
+  clear_error();
+  RSD_CHECK(ctx != nullptr && t != nullptr, RSD_E_INVALID, "ctx or tensor is NULL");
+  RSD_CHECK(!ctx->closing, RSD_E_INVALID, "context has been freed");
+  RSD_CHECK(t->ctx->device == ctx->device, RSD_E_INVALID, "tensor lives on another device");
+  RSD_CHECK(L >= 1 && L <= kMaxLigand, RSD_E_UNSUPPORTED, "L=%lld outside [1, %d]", (long long)L, kMaxLigand);
+  RSD_CHECK(P >= 1 && P <= (int64_t)INT32_MAX, RSD_E_INVALID, "P=%lld out of range", (long long)P);
+  RSD_CHECK(std::isfinite(vdw_min) && vdw_min >= 0, RSD_E_INVALID, "vdw_min must be finite and >= 0");
+  RSD_CHECK(lig_charges && lig_positions && quats && trans, RSD_E_INVALID, "input pointers are NULL");
+  RSD_HIP(hipSetDevice(ctx->device));
+  size_t bytes = (size_t)P * (sizeof(double) * (1 + (grads ? 6 : 0)) + sizeof(int32_t) + 1) + 256;
+  char* out = nullptr;
+  RSD_TRY(ctx->block_alloc((void**)&out, &bytes));
+  ScoreIO io{};
+  io.lig_charges = lig_charges;
+  io.lig_positions = lig_positions;
+  io.L = (int)L;
+  io.quats = quats;
+  io.trans = trans;
+  io.P = P;
+  io.vdw_min = vdw_min;
+  io.E = (double*)out;
+  io.El = nullptr;
+  io.grads = grads ? io.E + P : nullptr;
+  io.counts = (int32_t*)(io.E + P * (grads ? 7 : 1));
+  io.flags = (uint8_t*)(io.counts + P);
+  const rsd_status st = rsd::autotune_cells(ctx, t, io, best_div, ms);
   (void)hipStreamSynchronize(ctx->stream);
   ctx->block_release(out, bytes);
   return st;
@@ -1252,13 +1328,23 @@ rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t va
     ctx->opt_pose_order = (int)value;
     return RSD_OK;
   }
+  if (std::strcmp(name, "qr_solver") == 0) {
+    RSD_CHECK(value == 0 || value == 1, RSD_E_INVALID, "qr_solver must be 0 or 1");
+    ctx->opt_qr = (int)value;
+    return RSD_OK;
+  }
+  if (std::strcmp(name, "batch_mode") == 0) {
+    RSD_CHECK(value >= 0 && value <= 2, RSD_E_INVALID, "batch_mode must be 0, 1 or 2");
+    ctx->opt_batch_mode = (int)value;
+    return RSD_OK;
+  }
   if (std::strcmp(name, "overlap") == 0) {
     RSD_CHECK(value == 0 || value == 1, RSD_E_INVALID, "overlap must be 0 or 1");
     ctx->opt_overlap = (int)value;
     return RSD_OK;
   }
   if (std::strcmp(name, "factors") == 0) {
-    RSD_CHECK(value == 0 || value == 1, RSD_E_INVALID, "factors must be 0 or 1");
+    RSD_CHECK(value >= 0 && value <= 3, RSD_E_INVALID, "factors must be 0, 1, 2 or 3");
     ctx->opt_factors = (int)value;
     return RSD_OK;
   }

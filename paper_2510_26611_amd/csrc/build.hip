@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -548,6 +549,140 @@ __global__ void k_random_fill(double* __restrict__ X, int64_t count, uint64_t se
   }
 }
 
+// ----------------------------------------------------------------- small factorizations in LDS
+// Orthonormal bases of the eigensolver's n x k panels without a long chain of library launches:
+// the randomized Cholesky QR (a Householder QR of a small random sketch Theta Y gives R_s, and
+// Y R_s^{-1} is well conditioned whatever the condition of Y), followed by Cholesky QR passes.
+// Both factorizations below run in one workgroup with the matrix in LDS.
+constexpr int kSmallRows = 144;          // sketch rows (k <= 128 columns): a k + 16 embedding
+constexpr int kSmallCols = 128;
+
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// The inverse of the upper triangular k x k block held in A (row-major, ld k), in place:
+// column j of the inverse above the diagonal is -(sum_{l=i}^{j-1} X[i][l] R[l][j]) / R[j][j]
+// from the columns already inverted.  A diagonal below floor is raised to it (a direction the
+// panel does not resolve; its column of the basis is then noise that later passes normalise).
+__device__ void upper_inverse_lds(double* A, int k, double* tmp, double floor) {
+  const int tid = threadIdx.x;
+  for (int j = 0; j < k; ++j) {
+    double rjj = A[j * k + j];
+    rjj = fabs(rjj) < floor ? (rjj < 0.0 ? -floor : floor) : rjj;
+    for (int i = tid; i < j; i += blockDim.x) {
+      double acc = 0.0;
+      for (int l = i; l < j; ++l) acc = fma(A[i * k + l], A[l * k + j], acc);
+      tmp[i] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < j; i += blockDim.x) A[i * k + j] = -tmp[i] / rjj;
+    if (tid == 0) A[j * k + j] = 1.0 / rjj;
+    __syncthreads();
+  }
+}
+
+// Householder QR of the s x k matrix S (row-major, k <= s <= kSmallRows, k <= kSmallCols) and
+// the inverse of its triangular factor R: Rinv (k x k row-major, zeros below the diagonal).
+// Reflector j (LAPACK's convention): beta = -sign(alpha) ||x||, tau = (beta - alpha)/beta,
+// v = x / (alpha - beta) below the diagonal; none where the column below is already zero.
+__global__ __launch_bounds__(256) void k_qr_rinv(const double* __restrict__ S, int s, int k,
+                                                 double* __restrict__ Rinv) {
+  extern __shared__ double A[];          // s * k, then k
+  double* tmp = A + (size_t)s * k;
+  __shared__ double red[4];
+  __shared__ double s_par[3];            // beta, tau, scale
+  const int tid = threadIdx.x;
+  for (int e = tid; e < s * k; e += 256) A[e] = S[e];
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    double part = 0.0;
+    for (int i = j + 1 + tid; i < s; i += 256) part = fma(A[i * k + j], A[i * k + j], part);
+    const double xn2 = block_sum256(part, red);
+    if (tid == 0) {
+      const double alpha = A[j * k + j];
+      double beta = alpha, tau = 0.0, scale = 0.0;
+      if (xn2 > 0.0) {
+        const double nrm = sqrt(alpha * alpha + xn2);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      s_par[0] = beta;
+      s_par[1] = tau;
+      s_par[2] = scale;
+    }
+    __syncthreads();
+    const double beta = s_par[0], tau = s_par[1], scale = s_par[2];
+    for (int i = j + 1 + tid; i < s; i += 256) A[i * k + j] *= scale;
+    __syncthreads();
+    if (tau != 0.0) {
+      for (int c = j + 1 + tid; c < k; c += 256) {
+        double w = A[j * k + c];
+        for (int i = j + 1; i < s; ++i) w = fma(A[i * k + j], A[i * k + c], w);
+        w *= tau;
+        A[j * k + c] -= w;
+        for (int i = j + 1; i < s; ++i) A[i * k + c] = fma(-A[i * k + j], w, A[i * k + c]);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) A[j * k + j] = beta;
+    __syncthreads();
+  }
+  double dmax = 0.0;
+  for (int j = 0; j < k; ++j) dmax = fmax(dmax, fabs(A[j * k + j]));
+  upper_inverse_lds(A, k, tmp, dmax * 0x1p-63);
+  for (int e = tid; e < k * k; e += 256) {
+    const int i = e / k, c = e % k;
+    Rinv[e] = c >= i ? A[e] : 0.0;
+  }
+}
+
+// Upper Cholesky factor C of the symmetric part of M (k x k row-major, C^T C = (M + M^T)/2)
+// and its inverse Cinv (row-major, zeros below).  A pivot that is not positive (the panel lost
+// rank) sets *bad = 1 and is replaced by the smallest positive one seen, so the launch ends
+// normally; the caller reads *bad.
+__global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ M, int k, double* __restrict__ Cinv,
+                                                  int* __restrict__ bad) {
+  extern __shared__ double A[];          // k * k, then k
+  double* tmp = A + (size_t)k * k;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < k * k; e += 256) {
+    const int i = e / k, l = e % k;
+    A[e] = 0.5 * (M[i * k + l] + M[l * k + i]);
+  }
+  __syncthreads();
+  double dmin = 1e300;
+  for (int j = 0; j < k; ++j) {
+    double piv = A[j * k + j];
+    if (!(piv > 0.0)) {
+      if (tid == 0) *bad = 1;
+      piv = dmin < 1e300 ? dmin * dmin : 1.0;
+    }
+    const double d = sqrt(piv);
+    dmin = fmin(dmin, d);
+    __syncthreads();   // every thread has read the pivot
+    if (tid == 0) A[j * k + j] = d;
+    for (int l = j + 1 + tid; l < k; l += 256) A[j * k + l] /= d;
+    __syncthreads();
+    const int m = k - j - 1;
+    for (int e = tid; e < m * m; e += 256) {
+      const int i = j + 1 + e / m, l = j + 1 + e % m;
+      if (i <= l) A[i * k + l] = fma(-A[j * k + i], A[j * k + l], A[i * k + l]);
+    }
+    __syncthreads();
+  }
+  upper_inverse_lds(A, k, tmp, 0.0);
+  for (int e = tid; e < k * k; e += 256) {
+    const int i = e / k, c = e % k;
+    Cinv[e] = c >= i ? A[e] : 0.0;
+  }
+}
+
 // xi_c = z_m w_k nu1_c nu2_c nu3_c for column c = m*K + k.
 __global__ void k_weights(const double* __restrict__ z, const double* __restrict__ w, int K, int64_t C,
                           const double* __restrict__ nu1, const double* __restrict__ nu2,
@@ -758,6 +893,81 @@ rsd_status check_info(Context* ctx, rocblas_int* d_info, int count, const char* 
   return RSD_OK;
 }
 
+// Dynamic LDS beyond 64 KB for the two small-factorization kernels (once per device).
+rsd_status allow_small_lds() {
+  static std::mutex mu;
+  static std::vector<int> done;
+  int dev = 0;
+  RSD_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if (std::find(done.begin(), done.end(), dev) != done.end()) return RSD_OK;
+  RSD_HIP(hipFuncSetAttribute((const void*)k_qr_rinv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(double) * (kSmallRows * kSmallCols + kSmallCols))));
+  RSD_HIP(hipFuncSetAttribute((const void*)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(double) * (kSmallCols * kSmallCols + kSmallCols))));
+  done.push_back(dev);
+  return RSD_OK;
+}
+
+// Scratch of one mode's orthonormalizations (k <= kSmallCols).
+struct OrthBufs {
+  DevBuf theta, sk, part, w, rinv, tmp;
+  int splits = 1;
+  rsd_status alloc(Context* c, int n, int k) {
+    splits = std::max(1, std::min(32, n / 128));
+    RSD_TRY(theta.alloc(c, (size_t)kSmallRows * n));
+    RSD_TRY(sk.alloc(c, (size_t)kSmallRows * k));
+    RSD_TRY(part.alloc(c, (size_t)splits * kSmallRows * k));
+    RSD_TRY(w.alloc(c, (size_t)k * k));
+    RSD_TRY(rinv.alloc(c, (size_t)k * k));
+    RSD_TRY(tmp.alloc(c, (size_t)k * n));
+    return RSD_OK;
+  }
+};
+
+// C (M x N, ld N) = sum over the K rows of A(k, m) B(k, n), split over the contraction and summed.
+template <class AOp, class BOp>
+rsd_status gemm_split(Context* ctx, const AOp& A, const BOp& B, int M, int N, int64_t K, double* part, int splits,
+                      double* C) {
+  GemmShape g{};
+  g.M = M; g.N = N; g.K = K;
+  g.kper = (int64_t)div_up(K, (int64_t)splits * TK) * TK;
+  g.C = part; g.ldc = N; g.split_stride = (int64_t)M * N; g.accumulate = 0; g.tri = 0;
+  RSD_TRY(gemm(ctx, "eig", A, B, g, splits));
+  RSD_TIMED_LAUNCH(ctx, "eig", (k_reduce_splits<<<grid1d((int64_t)M * N), 256, 0, ctx->stream>>>(
+                                   part, splits, (int64_t)M * N, M, N, N, C, N)));
+  return RSD_OK;
+}
+
+// An orthonormal basis of the k columns of the n x k panel Y, stored transposed (Yt: k x n,
+// row-major, i.e. Y column-major): the randomized Cholesky QR -- the Householder QR of the sketch
+// Theta Y (kSmallRows x k, Theta uniform random) gives R_s, and Q1 = Y R_s^{-1} has a condition
+// number near that of Theta on the range of Y, independent of Y's -- then two Cholesky QR passes,
+// Q <- Q C^{-1} with C^T C = Q^T Q.  The result (transposed, k x n) goes to out; *bad is set when
+// a Cholesky pivot was not positive.  Y and out must differ.
+rsd_status orth_rchol(Context* ctx, const double* Yt, int k, int n, OrthBufs& b, double* out, int* bad) {
+  hipStream_t s = ctx->stream;
+  const int sr = kSmallRows;
+  RSD_TRY(gemm_split(ctx, OpMK{b.theta.p, n, sr}, OpMK{Yt, n, k}, sr, k, n, b.part.p, b.splits, b.sk.p));
+  RSD_TIMED_LAUNCH(ctx, "eig", (k_qr_rinv<<<1, 256, sizeof(double) * ((size_t)sr * k + k), s>>>(b.sk.p, sr, k,
+                                                                                              b.rinv.p)));
+  GemmShape g{};
+  g.M = k; g.N = n; g.K = k; g.kper = ((int64_t)k + TK - 1) / TK * TK; g.ldc = n;
+  g.split_stride = 0; g.accumulate = 0; g.tri = 0;
+  g.C = out;
+  RSD_TRY(gemm(ctx, "eig", OpKM{b.rinv.p, k, k}, OpKM{Yt, n, n}, g, 1));      // out = (Y R_s^{-1})^T
+  double* bufs[2] = {out, b.tmp.p};   // pass 0: out -> tmp, pass 1: tmp -> out
+  for (int pass = 0; pass < 2; ++pass) {
+    const double* src = bufs[pass];
+    RSD_TRY(gemm_split(ctx, OpMK{src, n, k}, OpMK{src, n, k}, k, k, n, b.part.p, b.splits, b.w.p));
+    RSD_TIMED_LAUNCH(ctx, "eig", (k_chol_inv<<<1, 256, sizeof(double) * ((size_t)k * k + k), s>>>(b.w.p, k,
+                                                                                                 b.rinv.p, bad)));
+    g.C = bufs[1 - pass];
+    RSD_TRY(gemm(ctx, "eig", OpKM{b.rinv.p, k, k}, OpKM{src, n, n}, g, 1));
+  }
+  return RSD_OK;
+}
+
 // Dominant eigenvectors of the three modes' symmetric PSD Gram matrices G_d (n x n, row-major
 // and exactly symmetric), by randomized subspace iteration: Y = G Omega with k deterministic
 // test vectors, an orthonormal basis Q of Y (Householder QR), one power step Q <- orth(G Q),
@@ -792,8 +1002,11 @@ rsd_status subspace_eigvecs3(Context* ctx, rocblas_handle hb, double* G3, int n,
   struct Mode {
     int k = 0;
     bool finished = false;
-    DevBuf Om, Y, Z, T, W, E, tau;
+    bool lib = false;          // orthonormalize with rocSOLVER's Householder QR
+    DevBuf Om, Y, Z, T, W, E, tau, Q, flag;
+    OrthBufs ob;
   } m[3];
+  RSD_TRY(allow_small_lds());
   for (int d = 0; d < 3; ++d) m[d].k = std::min(n, 128);
   struct StreamGuard {   // issue a mode's work on its stream; the context stream comes back afterwards
     Context* c;
@@ -809,6 +1022,7 @@ rsd_status subspace_eigvecs3(Context* ctx, rocblas_handle hb, double* G3, int n,
       any = true;
       ctx->stream = st[d];
       const int k = md.k;
+      md.lib = md.lib || ctx->opt_qr == 1 || k > kSmallCols;
       auto issue = [&]() -> rsd_status {
         RSD_TRY(md.Om.alloc(ctx, (size_t)n * k));
         RSD_TRY(md.Y.alloc(ctx, (size_t)n * k));
@@ -820,7 +1034,21 @@ rsd_status subspace_eigvecs3(Context* ctx, rocblas_handle hb, double* G3, int n,
         double* G = G3 + d * nn;
         RSD_TIMED_LAUNCH(ctx, "eig", (k_random_fill<<<grid1d((int64_t)n * k), 256, 0, st[d]>>>(
                                          md.Om.p, (int64_t)n * k, 0x5EEDull + (uint64_t)d)));
-        auto qr = [&](double* A) -> rsd_status {   // A: column-major n x k -> orthonormal Q in place
+        if (!md.lib) {
+          RSD_TRY(md.ob.alloc(ctx, n, k));
+          RSD_TRY(md.Q.alloc(ctx, (size_t)n * k));
+          RSD_TRY(md.flag.alloc(ctx, 1));
+          RSD_HIP(hipMemsetAsync(md.flag.p, 0, sizeof(double), st[d]));
+          RSD_TIMED_LAUNCH(ctx, "eig", (k_random_fill<<<grid1d((int64_t)kSmallRows * n), 256, 0, st[d]>>>(
+                                           md.ob.theta.p, (int64_t)kSmallRows * n, 0x7E7Aull + (uint64_t)d)));
+        }
+        auto qr = [&](DevBuf& P) -> rsd_status {   // P: column-major n x k -> orthonormal Q (in P)
+          if (!md.lib) {
+            RSD_TRY(orth_rchol(ctx, P.p, k, n, md.ob, md.Q.p, (int*)md.flag.p));
+            std::swap(P.p, md.Q.p);
+            return RSD_OK;
+          }
+          double* A = P.p;
           KernelTimer kt;
           if (ctx->timing) RSD_TRY(ctx->timer_begin("eig", &kt));
           RSD_CHECK(rocsolver_dgeqrf(hbs[d], n, k, A, n, md.tau.p) == rocblas_status_success, RSD_E_HIP,
@@ -835,11 +1063,11 @@ rsd_status subspace_eigvecs3(Context* ctx, rocblas_handle hb, double* G3, int n,
         // Y^T = Omega^T G  (k x n row-major = n x k column-major)
         g.M = k; g.N = n; g.K = n; g.kper = ((int64_t)n + TK - 1) / TK * TK; g.C = md.Y.p; g.ldc = n;
         RSD_TRY(gemm(ctx, "eig", OpKM{md.Om.p, k, k}, OpKM{G, n, n}, g, 1));
-        RSD_TRY(qr(md.Y.p));
+        RSD_TRY(qr(md.Y));
         // one power step: Z^T = Q^T G, orthonormalise again
         g.C = md.Z.p;
         RSD_TRY(gemm(ctx, "eig", OpMK{md.Y.p, n, k}, OpKM{G, n, n}, g, 1));
-        RSD_TRY(qr(md.Z.p));
+        RSD_TRY(qr(md.Z));
         // Rayleigh-Ritz: Y^T = Q^T G (k x n), T = Q^T G Q (k x k)
         g.C = md.Y.p;
         RSD_TRY(gemm(ctx, "eig", OpMK{md.Z.p, n, k}, OpKM{G, n, n}, g, 1));
@@ -866,8 +1094,10 @@ rsd_status subspace_eigvecs3(Context* ctx, rocblas_handle hb, double* G3, int n,
       const int k = md.k;
       std::vector<double> w((size_t)k);
       rocblas_int info = 0;
+      int bad = 0;
       hipError_t e = hipMemcpyAsync(&info, d_info + d, sizeof(info), hipMemcpyDeviceToHost, st[d]);
       if (e == hipSuccess) e = hipMemcpyAsync(w.data(), md.W.p, sizeof(double) * k, hipMemcpyDeviceToHost, st[d]);
+      if (e == hipSuccess && !md.lib) e = hipMemcpyAsync(&bad, md.flag.p, sizeof(int), hipMemcpyDeviceToHost, st[d]);
       if (e == hipSuccess) e = hipStreamSynchronize(st[d]);
       if (e != hipSuccess) {
         set_error("Ritz values: %s", hipGetErrorString(e));
@@ -878,6 +1108,10 @@ rsd_status subspace_eigvecs3(Context* ctx, rocblas_handle hb, double* G3, int n,
         set_error("Ritz eigensolver of mode %d did not converge (info %d)", d, (int)info);
         st_all = RSD_E_NUMERIC;
         break;
+      }
+      if (bad) {   // a Cholesky pass lost rank: redo this mode with Householder QR
+        md.lib = true;
+        continue;
       }
       const double lmax = w[k - 1];
       if (!(lmax > 0.0 && std::isfinite(lmax))) {
@@ -1024,6 +1258,11 @@ rsd_status tucker_canonical(Context* ctx, Tensor* t, DevBuf Bt[3], DevBuf U[3], 
   {
     std::vector<int> sl((size_t)R);
     for (int64_t p = 0; p < R; ++p) sl[(size_t)p] = kept[(size_t)p].first;
+    t->u3_chunks = 0;
+    for (int c = 0; c < t->nchunk; ++c) {
+      const int64_t p0 = (int64_t)c * kChunk, p1 = std::min<int64_t>(R, p0 + kChunk) - 1;
+      if (sl[(size_t)p1] - sl[(size_t)p0] < kSharedSlots) ++t->u3_chunks;
+    }
     RSD_TRY(ctx->dev_alloc((void**)&t->U3, sizeof(double) * (size_t)t->nm[2] * ldu[2]));
     RSD_TRY(ctx->dev_alloc((void**)&t->slice, sizeof(int) * (size_t)R));
     t->u3_ld = ldu[2];

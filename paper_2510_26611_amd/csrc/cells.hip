@@ -89,12 +89,13 @@ __global__ void k_cell_gather(const int* __restrict__ order, int64_t N, const do
 
 }  // namespace
 
-// Cell edge: a quarter of the interaction radius max(r_cut, vdw), but at most
-// 128 cells per axis.  Any edge is correct; this one keeps the candidate set
-// close to the sphere the scoring kernel needs while the row count stays small.
-static CellGrid make_grid(double b, double r_cut) {
+// Cell edge: r_cut / div (div = 4 unless the cell tuner chose another), but at most 128 cells
+// per axis.  Any edge is correct (counts and flags do not depend on it, only the order in which
+// the short range sums its pairs does); a quarter keeps the candidate set close to the sphere
+// the scoring kernel needs while the row count stays small.
+static CellGrid make_grid(double b, double r_cut, int div) {
   CellGrid g{};
-  double e = 0.25 * r_cut;
+  double e = r_cut / (double)(div > 0 ? div : 4);
   const double e_min = 2.0 * b / 128.0;
   if (!(e > e_min)) e = e_min;
   g.origin = -b;
@@ -109,11 +110,11 @@ static CellGrid make_grid(double b, double r_cut) {
 
 rsd_status build_cells(Context* ctx, Tensor* t, const double* d_charges, const double* d_positions) {
   const int64_t N = t->N;
-  t->cells = make_grid(t->b, t->sp.r_cut);
+  t->cells = make_grid(t->b, t->sp.r_cut, t->cell_div);
   const CellGrid g = t->cells;
   t->cell_bytes = sizeof(int) * (size_t)(g.ncells + 1);
   RSD_TRY(ctx->dev_alloc((void**)&t->cell_start, t->cell_bytes));
-  RSD_TRY(ctx->dev_alloc((void**)&t->atoms, sizeof(double4) * (size_t)(N > 0 ? N : 1)));
+  if (!t->atoms) RSD_TRY(ctx->dev_alloc((void**)&t->atoms, sizeof(double4) * (size_t)(N > 0 ? N : 1)));
   // scratch: cell_of[N], count[ncells], cursor[ncells], order[N]
   size_t scratch = sizeof(int) * (size_t)(2 * (N > 0 ? N : 1) + 2 * (int64_t)g.ncells);
   void* ws = nullptr;
@@ -137,6 +138,35 @@ rsd_status build_cells(Context* ctx, Tensor* t, const double* d_charges, const d
   }
   RSD_HIP(hipStreamSynchronize(s));
   return RSD_OK;
+}
+// The tensor's cell list again with edge r_cut / div, from the atoms it keeps on the host.
+rsd_status rebuild_cells(Context* ctx, Tensor* t, int div) {
+  RSD_CHECK(div >= 2 && div <= 12, RSD_E_INVALID, "cell divisor %d outside [2, 12]", div);
+  const int64_t N = t->N;
+  const size_t nz = sizeof(double) * (size_t)(N > 0 ? N : 1);
+  double* d_z = nullptr;
+  double* d_pos = nullptr;
+  RSD_TRY(ctx->dev_alloc((void**)&d_z, nz));
+  rsd_status st = ctx->dev_alloc((void**)&d_pos, 3 * nz);
+  if (st == RSD_OK && N > 0) {
+    hipError_t e = hipMemcpyAsync(d_z, t->host_charges.data(), sizeof(double) * N, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_pos, t->host_positions.data(), sizeof(double) * 3 * N, hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) {
+      set_error("cell list upload: %s", hipGetErrorString(e));
+      st = RSD_E_HIP;
+    }
+  }
+  if (st == RSD_OK) {
+    (void)hipStreamSynchronize(ctx->stream);   // no queued work still reads the old cell list
+    ctx->dev_free(t->cell_start, t->cell_bytes);
+    t->cell_start = nullptr;
+    t->cell_div = div;
+    st = build_cells(ctx, t, d_z, d_pos);
+  }
+  if (d_pos) ctx->dev_free(d_pos, 3 * nz);
+  ctx->dev_free(d_z, nz);
+  return st;
 }
 
 }  // namespace rsd

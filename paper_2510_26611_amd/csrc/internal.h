@@ -94,12 +94,15 @@ struct Context {
   int opt_poses_per_wave = 0;  // chunk-major kernel: poses per wavefront (0 = automatic)
   int opt_t2c = 0;             // core slice SVDs: 0 auto, 1 Jacobi in LDS, 2 rocSOLVER
   int opt_eig = 0;             // Gram eigenvectors: 0 auto, 1 dense batched eigensolver, 2 subspace iteration
+  int opt_qr = 0;              // subspace-iteration bases: 0 auto (randomized Cholesky QR, k <= 128), 1 rocSOLVER QR
   int opt_svd = 0;             // small SVD of explicit-factor rank reduction: 0 auto, 1 gesvd, 2 gesdd, 3 Jacobi
-  int opt_factors = 0;         // build factors: 0 collocation at the nodes, 1 Galerkin cell averages
+  int opt_factors = 0;         // build factors: bit 0 Galerkin cell averages (else collocation at the
+                               // nodes), bit 1 charges snapped to their nearest nodes (eq. 2.5)
   int opt_gram = 0;            // Gram matrices: 0 auto, 1 Toeplitz x Hankel form, 2 dense matrix-core product
   int opt_short_waves = 0;     // short-range kernel: wavefronts per workgroup (0 = automatic)
   int opt_use_tuning = 1;      // apply shapes recorded by rsd_autotune to automatic calls
   int opt_overlap = 0;         // chunk-major scoring: short range on a second stream beside the long range
+  int opt_batch_mode = 0;      // batches: 0 automatic (grouped), 1 grouped launches, 2 one persistent launch
   int opt_pose_order = 0;      // chunk-major scoring: poses in spatial order (0 automatic, 1 always, 2 never)
   int opt_short_poly = 1;      // tensors made with this context carry the short-range polynomial table
   int opt_shared_mode3 = 1;    // chunk-major scoring lerps a chunk's distinct U_3 columns once per atom
@@ -165,6 +168,7 @@ struct Tensor {
   int nm[3] = {0, 0, 0};
   bool restricted = false;
   bool galerkin = false;       // built from cell-average (Galerkin) factors
+  bool snapped = false;        // long-range factors of the charges moved to their nearest nodes
   int64_t R = 0;
   int nchunk = 0;              // ceil(R / kChunk); the kernels handle nchunk == 0
   int ranks[3] = {0, 0, 0};
@@ -176,6 +180,7 @@ struct Tensor {
   int* cell_start = nullptr;   // ncells + 1
   size_t cell_bytes = 0;
   CellGrid cells{};
+  int cell_div = 0;            // cell edge r_cut / cell_div (0: 4), chosen by the cell tuner
   double* short_tab = nullptr; // device copy of ShortTable t2[], w[] (2 * kMaxTerms)
   ShortTable shrt{};
   // made by the canonical -> Tucker -> canonical step: column p of F_3 is column slice[p] of
@@ -183,6 +188,7 @@ struct Tensor {
   double* U3 = nullptr;
   int* slice = nullptr;
   int u3_ld = 0;
+  int u3_chunks = 0;           // rank chunks whose columns use at most kSlots columns of U_3
   // the short-range kernel g(x) = sum_k w_k exp(-t_k^2 x) as piecewise polynomials in x = d^2
   // (kPolyCoef monomial coefficients per interval on [-1, 1]); owned by the context's cache,
   // null when not built
@@ -206,6 +212,8 @@ inline void grid_constants(int n, double b, double* h, double* X0, double* inv_h
 
 // ---------------------------------------------------------------- launchers (device work)
 rsd_status build_cells(Context* ctx, Tensor* t, const double* d_charges, const double* d_positions);
+// the tensor's cell list again with edge r_cut / div (cells.hip)
+rsd_status rebuild_cells(Context* ctx, Tensor* t, int div);
 
 struct ScoreIO {
   const double* lig_charges;   // device
@@ -232,11 +240,16 @@ rsd_status score_noalloc(Context* ctx, const Tensor* t, const ScoreIO& io);
 // Looks up (once per device, with that device current) the device address of the static
 // scratch array of score_noalloc.
 rsd_status noalloc_scratch_init(int device);
+// rsd_probe_gather (score.hip): time the long-range kernel's gather pattern alone
+rsd_status probe_gather(Context* ctx, int n, int iters, double* ms, double* bytes);
+constexpr int kSharedSlots = 4;   // distinct U_3 columns a chunk may use to take mode 3 from LDS
 // rsd_pose_order (score.hip): the spatial order of the long-range kernels and the poses in it;
 // *sorted: whether automatic scoring of t sorts poses itself
 rsd_status pose_order(Context* ctx, const Tensor* t, const double* quats, const double* trans, int64_t P, int* perm,
                       double* q_out, double* t_out, int* sorted);
 rsd_status autotune(Context* ctx, const Tensor* t, const ScoreIO& io, rsd_tune_report* rep);
+// rsd_autotune_cells (score.hip): times scoring with cell edges r_cut / {3, 4, 5, 6}, keeps the fastest
+rsd_status autotune_cells(Context* ctx, Tensor* t, const ScoreIO& io, int32_t* best_div, double* ms);
 // a molecule's own energy (score.hip)
 rsd_status launch_self_energy(Context* ctx, const Tensor* t, double* E_long, double* E_short);
 // posing search (score.hip)

@@ -555,7 +555,7 @@ struct LongParams {
   const int* __restrict__ perm;
 };
 
-constexpr int kSlots = 4;        // distinct mode-3 columns per chunk served from LDS
+constexpr int kSlots = kSharedSlots;   // distinct mode-3 columns per chunk served from LDS
 
 struct GridPt {                  // one ligand atom of one pose: grid rows and weights
   double f0, f1, f2;
@@ -995,6 +995,73 @@ __global__ __launch_bounds__(256) void k_batch_long(const BatchDesc* __restrict_
     long_item<false, false>(lp, c, (item % lp.nblk) * (4 * lp.ppw), smem);
 }
 
+// Ligand frames of every request and, for the persistent launch, its eight work counters
+// (zeroed here, in the same stream before it, so that a replayed graph starts from zero).
+__global__ __launch_bounds__(64) void k_batch_prep_fused(const BatchDesc* __restrict__ d, int* __restrict__ next) {
+  if (blockIdx.x == 0 && threadIdx.x < 8) next[threadIdx.x] = 0;
+  const BatchDesc& r = d[blockIdx.x];
+  if (r.sp.P > 0) ligand_prep(r.lig_pos, r.lig_z, r.sp.L, const_cast<double4*>(r.sp.lig), const_cast<double*>(r.sp.rlig));
+}
+
+// The whole batch's transform, short-range, vdW and long-range work in one persistent launch.
+// Each XCD has a queue of work items: first its share of every request's long-range work list
+// (request-major, then chunk-major, the part of XCD x exactly as in k_batch_long), then every
+// eighth short-range block of four poses over all requests.  A workgroup on XCD x (workgroup
+// w runs on XCD w mod 8) claims the next item of queue x with one atomic add and stops once
+// the queue is exhausted, so every workgroup ends.  Requests find their items by binary search
+// over prefix counts (xcd_base: long-range slots; short_base: short-range blocks, both over the
+// whole table).  The per-pose arithmetic is that of rsd_score_poses in chunk-major mode.
+__global__ __launch_bounds__(256) void k_batch_fused(const BatchDesc* __restrict__ d, int nreq, int64_t u_long,
+                                                     int64_t u_short, int* __restrict__ next) {
+  extern __shared__ double4 smem[];
+  __shared__ int s_item;
+  const int x = blockIdx.x & 7;
+  const int64_t n_short = u_short > x ? (u_short - x + 7) / 8 : 0;
+  const int64_t total = u_long + n_short;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (;;) {
+    __syncthreads();   // the previous item is done with the LDS
+    if (threadIdx.x == 0) s_item = atomicAdd(&next[x], 1);
+    __syncthreads();
+    const int64_t it = __builtin_amdgcn_readfirstlane(s_item);
+    if (it >= total) break;
+    if (it < u_long) {
+      const int r = find_request_uniform(d, nreq, it, [](const BatchDesc& q) { return q.xcd_base; });
+      LongParams lp = d[r].lp;
+      make_global(lp);
+      const int64_t jl = it - d[r].xcd_base;
+      if (jl >= lp.per_xcd) continue;
+      const int64_t item = (int64_t)x * lp.per_xcd + jl;
+      if (item >= lp.items) continue;
+      const int c = (int)(item / lp.nblk);
+      int clo = 0;
+      if (chunk_slices(lp, c, &clo))
+        long_item<false, true>(lp, c, (item % lp.nblk) * (4 * lp.ppw), smem);
+      else
+        long_item<false, false>(lp, c, (item % lp.nblk) * (4 * lp.ppw), smem);
+    } else {
+      const int64_t g = (it - u_long) * 8 + x;
+      const int r = find_request_uniform(d, nreq, g, [](const BatchDesc& q) { return q.short_base; });
+      ScoreParams a = d[r].sp;
+      make_global(a);
+      const int L = a.L;
+      double4* s_lig = smem;
+      double4* s_y = smem + L + (size_t)wv * L;
+      char* tail = (char*)(smem + (size_t)L * 5);
+      PairE* q = (PairE*)(tail) + (size_t)wv * kQueue;
+      int* rowoff = (int*)(tail + sizeof(PairE) * kQueue * 4) + wv * 128;
+      int* rowstart = rowoff + 64;
+      double* s_tab = (double*)(tail + sizeof(PairE) * kQueue * 4 + sizeof(int) * 128 * 4);
+      for (int i = threadIdx.x; i < L; i += 256) s_lig[i] = a.lig[i];
+      stage_short_table(a, s_tab);
+      __syncthreads();
+      const int64_t p = (g - d[r].short_base) * 4 + wv;
+      if (p < a.P) score_pose<false, false>(a, p, s_lig, s_y, q, rowoff, rowstart, s_tab, lane);
+    }
+  }
+}
+
 __global__ void k_batch_combine(const BatchDesc* __restrict__ d, int nreq, int64_t poses) {
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < poses; g += (int64_t)gridDim.x * blockDim.x) {
     const int r = find_request(d, nreq, g, [](const BatchDesc& x) { return x.pose_base; });
@@ -1407,6 +1474,93 @@ rsd_status score_noalloc(Context* ctx, const Tensor* t, const ScoreIO& io) {
   return st;
 }
 
+// ---------------------------------------------------------------- gather-rate probe
+// The long-range kernel's memory access without its arithmetic, for its roofline: a
+// half-wavefront takes one row i of a 64-column chunk per step (a pseudo-random row, the same
+// for its 32 lanes) and each lane loads 16 bytes of rows i and i+1 of two modes, two rows per
+// half-wavefront in flight per step, as the kernel does for two atoms.  Workgroup w reads the
+// chunk of XCD w mod 8 (2 * n * 512 bytes, L2-resident for n <= 2048).  The loaded values are
+// summed and stored once per lane so that no load is dropped.
+__global__ __launch_bounds__(256) void k_gather_probe(const double* __restrict__ F, int n, int64_t mode_stride,
+                                                      int64_t chunk_stride, int iters, double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const double* F0 = F + (int64_t)(blockIdx.x & 7) * chunk_stride + 2 * (lane & 31);
+  const double* F1 = F0 + mode_stride;
+  uint32_t s = (uint32_t)(blockIdx.x * 8 + (threadIdx.x >> 5)) * 2654435761u + 12345u;
+  const uint32_t mask = (uint32_t)n - 1u;   // n is a power of two
+  double ax = 0.0, ay = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    double2 A0[2], B0[2], A1[2], B1[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      s = s * 1664525u + 1013904223u;
+      uint32_t i0 = (s >> 7) & mask;
+      s = s * 1664525u + 1013904223u;
+      uint32_t i1 = (s >> 7) & mask;
+      i0 = i0 == mask ? i0 - 1u : i0;
+      i1 = i1 == mask ? i1 - 1u : i1;
+      const double2* q0 = (const double2*)(F0 + (int64_t)i0 * kChunk);
+      const double2* q1 = (const double2*)(F1 + (int64_t)i1 * kChunk);
+      A0[u] = q0[0]; B0[u] = q0[kChunk / 2];
+      A1[u] = q1[0]; B1[u] = q1[kChunk / 2];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      ax += (A0[u].x + B0[u].x) + (A1[u].x + B1[u].x);
+      ay += (A0[u].y + B0[u].y) + (A1[u].y + B1[u].y);
+    }
+  }
+  out[(int64_t)blockIdx.x * 256 + threadIdx.x] = ax + ay;
+}
+
+__global__ void k_fill_probe(double* __restrict__ x, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 1.0 + 1e-3 * (double)(i & 1023);
+}
+
+rsd_status probe_gather(Context* ctx, int n, int iters, double* ms, double* bytes) {
+  RSD_CHECK(n >= 4 && n <= 16384 && (n & (n - 1)) == 0, RSD_E_INVALID, "n must be a power of two in [4, 16384]");
+  RSD_CHECK(iters >= 1 && iters <= 4096, RSD_E_INVALID, "iters must be in [1, 4096]");
+  constexpr int kBlocks = 8192;
+  const int64_t chunk_stride = (int64_t)n * kChunk, mode_stride = 8 * chunk_stride;
+  const int64_t count = 2 * mode_stride;
+  hipStream_t s = ctx->stream;
+  void* ws = nullptr;
+  RSD_TRY(ctx->workspace(sizeof(double) * (size_t)(count + (int64_t)kBlocks * 256), &ws));
+  double* F = (double*)ws;
+  double* out = F + count;
+  k_fill_probe<<<1024, 256, 0, s>>>(F, count);
+  RSD_HIP(hipGetLastError());
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  rsd_status st = RSD_OK;
+  auto run = [&]() -> rsd_status {
+    RSD_HIP(hipEventCreate(&e0));
+    RSD_HIP(hipEventCreate(&e1));
+    k_gather_probe<<<kBlocks, 256, 0, s>>>(F, n, mode_stride, chunk_stride, iters, out);   // warm-up
+    RSD_HIP(hipGetLastError());
+    double best = 1e300;
+    for (int r = 0; r < 5; ++r) {
+      RSD_HIP(hipEventRecord(e0, s));
+      k_gather_probe<<<kBlocks, 256, 0, s>>>(F, n, mode_stride, chunk_stride, iters, out);
+      RSD_HIP(hipGetLastError());
+      RSD_HIP(hipEventRecord(e1, s));
+      RSD_HIP(hipEventSynchronize(e1));
+      float f = 0.0f;
+      RSD_HIP(hipEventElapsedTime(&f, e0, e1));
+      best = std::min(best, (double)f);
+    }
+    *ms = best;
+    // per wavefront and step: two half-wavefronts x two rows in flight x (rows i, i+1 of two
+    // modes) x 32 lanes x 16 bytes
+    *bytes = (double)kBlocks * 4 * iters * 2 * 2 * 4 * 32 * 16;
+    return RSD_OK;
+  };
+  st = run();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return st;
+}
+
 // ---------------------------------------------------------------- launch-shape tuner
 rsd_status autotune(Context* ctx, const Tensor* t, const ScoreIO& io, rsd_tune_report* rep) {
   const bool grad = io.grads != nullptr;
@@ -1482,6 +1636,51 @@ rsd_status autotune(Context* ctx, const Tensor* t, const ScoreIO& io, rsd_tune_r
   return RSD_OK;
 }
 
+// Cell edge of the tensor's short-range cell list: scoring of the sample is timed (best of 3,
+// HIP events on the context stream, the launch shapes the context would use) with the list
+// rebuilt at edges r_cut / {3, 4, 5, 6}; the fastest stays.  ms[i]: time at divisor 3 + i.
+rsd_status autotune_cells(Context* ctx, Tensor* t, const ScoreIO& io, int32_t* best_div, double* ms) {
+  hipStream_t s = ctx->stream;
+  const bool saved_timing = ctx->timing;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double t_div[4] = {0, 0, 0, 0};
+  auto body = [&]() -> rsd_status {
+    RSD_HIP(hipEventCreate(&e0));
+    RSD_HIP(hipEventCreate(&e1));
+    ctx->timing = false;
+    for (int i = 0; i < 4; ++i) {
+      RSD_TRY(rebuild_cells(ctx, t, 3 + i));
+      RSD_TRY(launch_score(ctx, t, io));   // untimed: workspace growth
+      double best = 1e300;
+      for (int r = 0; r < 3; ++r) {
+        RSD_HIP(hipEventRecord(e0, s));
+        RSD_TRY(launch_score(ctx, t, io));
+        RSD_HIP(hipEventRecord(e1, s));
+        RSD_HIP(hipEventSynchronize(e1));
+        float f = 0.0f;
+        RSD_HIP(hipEventElapsedTime(&f, e0, e1));
+        best = std::min(best, (double)f);
+      }
+      t_div[i] = best;
+    }
+    return RSD_OK;
+  };
+  rsd_status st = body();
+  ctx->timing = saved_timing;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  int best = 1;   // r_cut / 4 unless another edge is faster
+  for (int i = 0; i < 4; ++i)
+    if (t_div[i] < t_div[best]) best = i;
+  const rsd_status st2 = rebuild_cells(ctx, t, 3 + best);
+  if (st == RSD_OK) st = st2;
+  if (st != RSD_OK) return st;
+  if (best_div) *best_div = 3 + best;
+  if (ms)
+    for (int i = 0; i < 4; ++i) ms[i] = t_div[i];
+  return RSD_OK;
+}
+
 // ---------------------------------------------------------------- batches
 struct Batch {
   Context* ctx = nullptr;
@@ -1505,6 +1704,13 @@ struct Batch {
   int* sort_hist = nullptr;   // shared by the requests' sorts, which run one after another
   int* sort_cell = nullptr;
   int64_t poses = 0;
+  // persistent mode: one launch of `groups` workgroups over u_long long-range slots per XCD and
+  // u_short short-range blocks, with `lds` bytes of LDS; next: the eight queue counters
+  bool fused = false;
+  int64_t u_long = 0, u_short = 0;
+  size_t lds = 0;
+  int groups = 0;
+  int* next = nullptr;
   std::vector<BatchDesc> host_table;   // source of the (asynchronous) table upload
   hipEvent_t uploaded = nullptr;       // recorded after the upload: host_table may go once it completes
 };
@@ -1561,11 +1767,22 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     x.occ_s = lds_occupancy(x.lds_s, x.W);
     x.occ_l = lds_occupancy(x.lds_l, 4);
   }
+  // persistent mode: one launch whose LDS is the largest any request's long-range items or
+  // four-pose short-range blocks need (automatic: the grouped launches)
+  bool fused = ctx->opt_batch_mode == 2;
+  size_t lds_fused = 0;
+  if (fused) {
+    for (int r = 0; r < nreq; ++r) {
+      lds_fused = std::max(lds_fused, std::max(shp[r].lds_l, short_lds((int)req_in[r].L, 4, false)));
+    }
+    if (lds_fused > kLdsMax) fused = false;
+  }
   // table order: long-range occupancy, then the short-range shape (stable), so that every
   // launch covers a contiguous range and the heavier long-range kernel gets the fewest launches
+  // (persistent mode: request order)
   std::vector<int> order((size_t)nreq);
   for (int r = 0; r < nreq; ++r) order[r] = r;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+  if (!fused) std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     const Shape &a = shp[x], &c = shp[y];
     if (a.occ_l != c.occ_l) return a.occ_l > c.occ_l;
     if (a.W != c.W) return a.W > c.W;
@@ -1602,7 +1819,8 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
   const size_t o_perm = o_part + sizeof(double) * (size_t)npart;
   const size_t o_hist = o_perm + sizeof(int) * (size_t)nperm;
   const size_t o_cell = o_hist + sizeof(int) * (size_t)(nperm ? kSortCells : 0);
-  b->bytes = o_cell + sizeof(int) * (size_t)maxsort;
+  const size_t o_next = (o_cell + sizeof(int) * (size_t)maxsort + 255) / 256 * 256;
+  b->bytes = o_next + 8 * sizeof(int);
   rsd_status st = ctx->block_alloc(&b->mem, &b->bytes);
   if (st != RSD_OK) {
     delete b;
@@ -1643,11 +1861,32 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     h[k].pose_base = pb;
     pb += q.P;
   }
-  // launches: maximal runs of the table with one short-range shape, and with one long-range
-  // occupancy; each launch's LDS is the largest its requests need
   rsd_status lst = RSD_OK;
   size_t lds_long_max = 0;
-  for (int k = 0; k < nreq && lst == RSD_OK;) {
+  if (fused) {
+    // prefix counts over the whole table: long-range slots per XCD and four-pose short blocks
+    for (int k = 0; k < nreq; ++k) {
+      h[k].xcd_base = b->u_long;
+      b->u_long += h[k].lp.per_xcd;
+      h[k].short_base = b->u_short;
+      b->u_short += (h[k].sp.P + 3) / 4;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 8)
+      cus = 256;
+    b->fused = true;
+    b->lds = lds_fused;
+    b->groups = 8 * (cus / 8) * lds_occupancy(lds_fused, 4);
+    b->next = (int*)(m + o_next);
+    if (b->u_long + (b->u_short + 7) / 8 > 0x7fffffffLL) {
+      set_error("batch too large for one launch");
+      lst = RSD_E_UNSUPPORTED;
+    }
+    if (lst == RSD_OK) lst = allow_lds((const void*)k_batch_fused, lds_fused);
+  }
+  // launches: maximal runs of the table with one short-range shape, and with one long-range
+  // occupancy; each launch's LDS is the largest its requests need
+  for (int k = 0; k < nreq && lst == RSD_OK && !fused;) {
     const Shape& s0 = shp[order[k]];
     Batch::Launch la{k, 0, s0.W, 0, 0};
     int e = k;
@@ -1664,7 +1903,7 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     if (la.units > 0) b->shorts.push_back(la);
     k = e;
   }
-  for (int k = 0; k < nreq && lst == RSD_OK;) {
+  for (int k = 0; k < nreq && lst == RSD_OK && !fused;) {
     const int occ = shp[order[k]].occ_l;
     Batch::Launch la{k, 0, 4, 0, 0};
     int e = k;
@@ -1682,7 +1921,7 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     if (la.units > 0) b->longs.push_back(la);
     k = e;
   }
-  if (lst == RSD_OK) lst = allow_lds((const void*)k_batch_long, lds_long_max);
+  if (lst == RSD_OK && !fused) lst = allow_lds((const void*)k_batch_long, lds_long_max);
   if (lst != RSD_OK) {
     ctx->block_release(b->mem, b->bytes);
     delete b;
@@ -1716,9 +1955,17 @@ rsd_status batch_run(Batch* b) {
   Context* ctx = b->ctx;
   hipStream_t s = ctx->stream;
   if (b->poses == 0) return RSD_OK;
-  RSD_TIMED_LAUNCH(ctx, "ligand_prep", (k_batch_prep<<<b->nreq, 64, 0, s>>>(b->d)));
+  if (b->fused) {
+    RSD_TIMED_LAUNCH(ctx, "ligand_prep", (k_batch_prep_fused<<<b->nreq, 64, 0, s>>>(b->d, b->next)));
+  } else {
+    RSD_TIMED_LAUNCH(ctx, "ligand_prep", (k_batch_prep<<<b->nreq, 64, 0, s>>>(b->d)));
+  }
   for (const auto& so : b->sorts)
     RSD_TRY(launch_pose_sort(ctx, s, so.t, so.trans, so.P, b->sort_hist, b->sort_cell, so.perm));
+  if (b->fused) {
+    RSD_TIMED_LAUNCH(ctx, "fused", (k_batch_fused<<<(unsigned)b->groups, 256, b->lds, s>>>(
+                                       b->d, b->nreq, b->u_long, b->u_short, b->next)));
+  }
   for (const auto& la : b->shorts)
     RSD_TIMED_LAUNCH(ctx, "short", (k_batch_short<<<(unsigned)la.units, 64 * la.W, la.lds, s>>>(
                                        b->d, la.first, la.count)));

@@ -103,6 +103,21 @@ class Context:
                                        int(bool(grads)), C.byref(rep)))
         return {k: getattr(rep, k) for k, _ in _lib.TuneReport._fields_}
 
+    def autotune_cells(self, tensor: "Tensor", lig_charges, lig_positions, quats, trans, vdw_min: float,
+                       grads: bool = False) -> dict:
+        """rsd_autotune_cells: the cell edge r_cut/div (div 3..6) of the tensor's cell list that
+        scores a sample fastest; the tensor keeps it.  Returns dict(div, ms={div: ms})."""
+        args = [_arr(x) for x in (lig_charges, lig_positions, quats, trans)]
+        if not all(a[2] for a in args):
+            raise TypeError("autotune_cells takes device tensors")
+        best = C.c_int32()
+        ms = (C.c_double * 4)()
+        _check(_lib.lib().rsd_autotune_cells(self.handle, tensor.handle, args[0][0], args[1][0],
+                                             int(args[0][1].shape[0]), args[2][0], args[3][0],
+                                             int(args[2][1].shape[0]), float(vdw_min), int(bool(grads)),
+                                             C.byref(best), ms))
+        return dict(div=best.value, ms={3 + i: ms[i] for i in range(4)})
+
     def set_timing(self, enable: bool) -> None:
         _check(_lib.lib().rsd_context_set_timing(self.handle, int(bool(enable))))
 
@@ -165,6 +180,12 @@ class Tensor:
         el, es = C.c_double(), C.c_double()
         _check(_lib.lib().rsd_self_energy(ctx.handle, self.handle, C.byref(el), C.byref(es)))
         return el.value, es.value
+
+    def layout(self):
+        """rsd_tensor_layout: rank chunks and those whose mode-3 rows come from U_3."""
+        nchunk, shared = C.c_int32(), C.c_int32()
+        _check(_lib.lib().rsd_tensor_layout(self.handle, C.byref(nchunk), C.byref(shared)))
+        return dict(nchunk=nchunk.value, shared_mode3=shared.value)
 
     def free(self) -> None:
         if getattr(self, "handle", None):
@@ -281,6 +302,13 @@ def score_poses(ctx: Context, tensor: Tensor, lig_charges, lig_positions, quats,
     _check(_lib.lib().rsd_score_poses(ctx.handle, tensor.handle, zp, lp, L, qp, tp, P, float(vdw_min),
                                       RSD_DEVICE_PTRS if qdev else 0, ep, elp, fp, cp, gp))
     return out
+
+
+def probe_gather(ctx: Context, n: int = 2048, iters: int = 256) -> dict:
+    """rsd_probe_gather: the long-range kernel's gather pattern alone; bytes, ms and GB/s."""
+    ms, nbytes = C.c_double(), C.c_double()
+    _check(_lib.lib().rsd_probe_gather(ctx.handle, int(n), int(iters), C.byref(ms), C.byref(nbytes)))
+    return dict(ms=ms.value, bytes=nbytes.value, gbs=nbytes.value / (ms.value * 1e-3) / 1e9)
 
 
 def score_poses_noalloc(ctx: Context, tensor: Tensor, lig_charges, lig_positions, quats, trans, vdw_min: float,

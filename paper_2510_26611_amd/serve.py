@@ -6,7 +6,8 @@ order, once its device memory (inputs and outputs) fits the HBM budget next to t
 tensors and the scratch reserved for the rounds in flight.  Work is issued in rounds: every
 round is one rsd_batch over pose slices of the admitted, unfinished requests, with a fixed
 pose budget shared evenly among them (each gets at least `min_slice` poses while the budget
-lasts, in admission order).  A request that arrives while others are on the device therefore
+lasts, in admission order), or with policy "small_first" given whole to the small requests
+first and then to the larger ones first come, first served.  A request that arrives while others are on the device therefore
 joins the next round instead of waiting for them to finish, and a small request completes
 in a round or two even behind a very large one.
 
@@ -31,6 +32,10 @@ from . import rsdock
 
 # request states
 WAITING, RUNNING, DONE, REJECTED, CANCELLED = "waiting", "running", "done", "rejected", "cancelled"
+
+# how a round's pose budget is shared: evenly among the admitted requests ("share"), or whole
+# small requests first and then the larger ones first come, first served ("small_first")
+POLICIES = ("share", "small_first")
 
 # reasons a request is rejected at submission
 E_UNKNOWN_PROTEIN = -10
@@ -93,7 +98,10 @@ class Scheduler:
     """Admission by byte budget in arrival order, and pose slices per round shared evenly."""
 
     def __init__(self, budget_bytes: int, resident_bytes: int, scratch_bytes: int = 0, max_rounds: int = 2,
-                 round_poses: int = 250_000, min_slice: int = 16_384):
+                 round_poses: int = 250_000, min_slice: int = 16_384, policy: str = "share"):
+        if policy not in POLICIES:
+            raise ValueError(f"policy must be one of {POLICIES}")
+        self.policy = policy
         self.budget = int(budget_bytes)
         self.reserved = int(resident_bytes) + int(scratch_bytes)
         self.in_flight = 0
@@ -142,6 +150,8 @@ class Scheduler:
         live = [r for r in self.active if r._next < r.P]
         if not live:
             return []
+        if self.policy == "small_first":
+            return self._round_small_first(live)
         quota = max(self.min_slice, self.round_poses // len(live))
         left, take = self.round_poses, []
         for r in live:
@@ -160,6 +170,23 @@ class Scheduler:
         for r, n in take:
             out.append((r, r._next, n))
             r._next += n
+        self.rounds += 1
+        return out
+
+    def _round_small_first(self, live: list) -> list:
+        """Policy small_first: every small request (at most 2 min_slice poses) goes whole into the
+        next round, in admission order; the rest of the round goes to the larger requests first
+        come, first served, so a large request is not slowed by other large ones sharing rounds."""
+        small_max = 2 * self.min_slice
+        order = [r for r in live if r.P <= small_max] + [r for r in live if r.P > small_max]
+        left, out = self.round_poses, []
+        for r in order:
+            n = min(r.P - r._next, left)
+            if n <= 0:
+                break
+            out.append((r, r._next, n))
+            r._next += n
+            left -= n
         self.rounds += 1
         return out
 
@@ -223,7 +250,7 @@ class Server:
     """Serve a trace of requests against resident tensors on one GPU."""
 
     def __init__(self, tensors: dict, hbm_budget_bytes: int, streams: int = 2, round_poses: int = 250_000,
-                 min_slice: int = 16_384, device: int = 0, options: dict | None = None):
+                 min_slice: int = 16_384, device: int = 0, options: dict | None = None, policy: str = "share"):
         import torch
         self.torch = torch
         self.tensors = tensors
@@ -236,7 +263,7 @@ class Server:
         nchunk = max(-(-t.query()["R"] // 64) for t in tensors.values())
         resident = sum(t.query()["bytes"] for t in tensors.values())
         self.sched = Scheduler(hbm_budget_bytes, resident, streams * round_scratch_bytes(round_poses, nchunk),
-                               max_rounds=streams, round_poses=round_poses, min_slice=min_slice)
+                               max_rounds=streams, round_poses=round_poses, min_slice=min_slice, policy=policy)
         self.last_compute = None
         self.pose_order = int((options or {}).get("pose_order", 0))
         self.ordered = 0   # requests sliced in spatial order so far

@@ -73,11 +73,14 @@ def _mk_out(torch, P):
                 counts=torch.empty(P, dtype=torch.int32, device="cuda"))
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("order", [0, 1])
-def test_batch_equals_alone_bitwise_and_oracle(env, order):
-    """order 1: every request's long range takes its poses in spatial order (option pose_order)."""
+def test_batch_equals_alone_bitwise_and_oracle(env, order, mode):
+    """order 1: every request's long range takes its poses in spatial order (option pose_order);
+    mode 1: requests grouped into launches by LDS occupancy, 2: one persistent launch."""
     rs, ctx, torch, T = env
     ctx.set_option("pose_order", order)
+    ctx.set_option("batch_mode", mode)
     reqs = _requests(torch, T, 500)
     for r in reqs:
         r["out"] = _mk_out(torch, r["quats"].shape[0])
@@ -106,12 +109,15 @@ def test_batch_equals_alone_bitwise_and_oracle(env, order):
     assert_parity(got, ref, label="batch request with 600 ligand atoms")
     b.free()
     ctx.set_option("pose_order", 0)
+    ctx.set_option("batch_mode", 0)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("order", [0, 1])
-def test_batch_graph_replays_match_eager(env, order):
+def test_batch_graph_replays_match_eager(env, order, mode):
     rs, ctx, torch, T = env
     ctx.set_option("pose_order", order)
+    ctx.set_option("batch_mode", mode)
     reqs = _requests(torch, T, 700)
     for r in reqs:
         r["out"] = _mk_out(torch, r["quats"].shape[0])
@@ -143,6 +149,7 @@ def test_batch_graph_replays_match_eager(env, order):
     del graph
     b.free()
     ctx.set_option("pose_order", 0)
+    ctx.set_option("batch_mode", 0)
 
 
 def test_batch_made_before_a_smaller_one_still_runs(env):

@@ -207,3 +207,85 @@ def test_galerkin_factors_build(rs, ctx):
     assert dcol > 100.0 * max(err_g, err_o)      # the variant really differs from collocation
     t.free()
     col.free()
+
+
+@pytest.mark.parametrize("factors", [2, 3])
+def test_snapped_build_against_the_oracle(rs, ctx, factors):
+    """factors 2 (3): eq. 2.5's shift-and-window build, every charge moved to its nearest grid
+    node and the reference Gaussians (cell averages) centred there, against the oracle's snapped
+    build on config 1: tensor error against the uncompressed tensor of the snapped charges within
+    10x the oracle's own, ranks as the oracle's, and scoring at parity on the exported factors
+    (the short range and the vdW test at the true positions)."""
+    from oracle import rhosvd
+    cfg = configs.CONFIG1
+    wl = configs.make(cfg, P=128)
+    (tl, wlong), _ = sinc_parts(cfg)
+    gal = factors == 3
+    tk, can = rhosvd.build(wl.protein_charges, wl.protein_positions, tl, wlong, cfg.n, cfg.b, cfg.eps,
+                           galerkin=gal, snapped=True)
+    ctx.set_option("factors", factors)
+    try:
+        t = rs.build_rs_tensor(ctx, wl.protein_charges, wl.protein_positions, cfg.n, cfg.b, rs.Sinc.from_config(cfg))
+    finally:
+        ctx.set_option("factors", 0)
+    snapped = otensor.snapped_positions(wl.protein_positions, cfg.n, cfg.b)
+    idx = _nodes(cfg, 3000, 29)
+    if gal:
+        h, _, _, nodes = otensor.grid(cfg.n, cfg.b)
+        G = [otensor.galerkin_columns(snapped[:, d], tl, nodes[idx[:, d]], h) for d in range(3)]
+        T0 = np.einsum("m,k,qmk,qmk,qmk->q", wl.protein_charges, wlong, G[0], G[1], G[2])
+    else:
+        T0 = otensor.long_range_at_nodes(wl.protein_charges, snapped, tl, wlong, cfg.n, cfg.b, idx)
+    F = t.export()
+    err_o = np.max(np.abs(_canon_at(can.F, idx) - T0))
+    err_g = np.max(np.abs(_canon_at(F, idx) - T0))
+    info = t.query()
+    print(f"snapped ({'Galerkin' if gal else 'collocated'}): ranks gpu {info['ranks']} R={info['R']} | oracle "
+          f"{tk.ranks} R={can.R} | max err gpu {err_g:.3e} oracle {err_o:.3e} (max |T0| {np.max(np.abs(T0)):.3e})")
+    assert err_g <= 10.0 * max(err_o, cfg.eps * np.max(np.abs(T0)))
+    for d in range(3):
+        assert info["ranks"][d] >= tk.ranks[d] - 1
+    ref = oracle_score(cfg, wl, F, wl.quats, wl.trans)
+    out = rs.score_poses(ctx, t, wl.ligand_charges, wl.ligand_positions, wl.quats, wl.trans, cfg.sigma)
+    from gpu_common import assert_parity
+    assert_parity(out, ref, label="snapped build")
+    t.free()
+
+
+def test_snapped_build_error_is_first_order_like_table_3_2(rs, ctx):
+    """Two charges 3 a.u. apart (Table 3.2's setting, charge product -1/sqrt(2)), the source 0.3
+    of a cell off its node on every axis: the energy from the device's snapped build errs against
+    Coulomb's by a first-order term in h that halves per grid doubling (the table's error
+    column), and equals the oracle's snapped-build energy on every grid to the truncation level."""
+    import math
+    from oracle import constants, direct, rhosvd, score as oscore, sinc as osinc
+    b, M, K = 8.0, 24, 12
+    L_s = constants.scale_length(b)
+    h_M = constants.optimal_step(M, b)
+    t, w = osinc.sinc_table(M, h_M, L_s)
+    (tl, wl_), (ts, ws) = osinc.split(t, w, K)
+    r_cut = constants.short_cutoff(M, h_M, L_s, K)
+    zeta = np.array([-1.0 / math.sqrt(2.0)])
+    d = np.full(3, math.sqrt(3.0))
+    q1 = np.array([[1.0, 0.0, 0.0, 0.0]])
+    errs = []
+    ctx.set_option("factors", 2)
+    try:
+        for n in (32, 64, 128, 256):
+            h, _, _, nodes = otensor.grid(n, b)
+            src = np.full((1, 3), nodes[n // 2 - 1] + 0.3 * h)
+            lig = src + d[None, :]
+            tg = rs.build_rs_tensor(ctx, np.ones(1), src, n, b, rs.Sinc(M, h_M, L_s, K, r_cut, 1e-8))
+            E = rs.score_poses(ctx, tg, zeta, np.zeros((1, 3)), q1, lig, 0.5)["E"][0]
+            _, can = rhosvd.build(np.ones(1), src, tl, wl_, n, b, 1e-8, snapped=True)
+            ref = oscore.score(can.F, n, b, src, np.ones(1), ts, ws, r_cut, zeta, np.zeros((1, 3)), q1, lig, 0.5)
+            # two rank reductions at eps = 1e-8 agree to the truncation level
+            assert abs(E - ref["E"][0]) <= 1e-7 * abs(ref["E"][0]), (n, E, ref["E"][0])
+            e_true = direct.energies(src, np.ones(1), zeta, np.zeros((1, 3)), q1, lig)[0]
+            errs.append(abs(E - e_true))
+            tg.free()
+    finally:
+        ctx.set_option("factors", 0)
+    ratios = [a / c for a, c in zip(errs, errs[1:])]
+    print(f"snapped two-charge errors {errs}, ratios {ratios}")
+    assert all(1.8 <= q <= 2.2 for q in ratios), (errs, ratios)

@@ -157,3 +157,60 @@ def test_shared_mode3_columns_bitwise(env):
         ctx.set_option("score_mode", 0)
     for tt in (tl, tc, tb):
         tt.free()
+
+
+def test_gather_probe_and_layout():
+    """rsd_probe_gather times the long-range gathers' pattern alone (the roofline the scoring
+    kernel is reported against); rsd_tensor_layout counts the chunks that take mode 3 from U_3."""
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2510_26611_amd as rs
+    ctx = rs.Context(0)
+    r = rs.probe_gather(ctx, 1024, 16)
+    assert r["ms"] > 0 and r["bytes"] == 8192 * 4 * 16 * 2 * 2 * 4 * 32 * 16
+    assert 1e3 < r["gbs"] < 1e6
+    for bad in (1000, 2, 32768):
+        with pytest.raises(rs.RsdError):
+            rs.probe_gather(ctx, bad, 16)
+    # the 5,000-atom protein: about 26 columns per core slice, so most 64-column chunks touch at
+    # most 4 slices (the 200-atom one has 7 per slice: its chunks touch 9 or more)
+    cfg = configs.CONFIG2
+    wl = configs.make(cfg, P=1)
+    t = rs.build_rs_tensor(ctx, wl.protein_charges, wl.protein_positions, cfg.n, cfg.b, rs.Sinc.from_config(cfg))
+    lay = t.layout()
+    print(f"layout: {lay}")
+    assert lay["nchunk"] == -(-t.query()["R"] // 64) and 0 < lay["shared_mode3"] <= lay["nchunk"]
+    ti = rs.tensor_import(ctx, t.export(), cfg.n, cfg.b, rs.Sinc.from_config(cfg), wl.protein_charges,
+                          wl.protein_positions)
+    assert ti.layout()["shared_mode3"] == 0
+    t.free()
+    ti.free()
+    ctx.close()
+
+
+def test_cell_edge_tuner_keeps_parity():
+    """rsd_autotune_cells times scoring with the cell list rebuilt at edges r_cut / 3..6 and keeps
+    the fastest; counts and flags are the same at every edge and energies stay at parity with the
+    oracle (only the order of the short-range sum depends on the cells)."""
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2510_26611_amd as rs
+    cfg = configs.CONFIG2
+    wl = configs.make(cfg, P=16384)
+    ctx = rs.Context(0)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    t = rs.build_rs_tensor(ctx, d(wl.protein_charges), d(wl.protein_positions), cfg.n, cfg.b, rs.Sinc.from_config(cfg))
+    lz, lx, q, tr = d(wl.ligand_charges), d(wl.ligand_positions), d(wl.quats), d(wl.trans)
+    before = {k: v.cpu().numpy() for k, v in rs.score_poses(ctx, t, lz, lx, q, tr, cfg.sigma).items()}
+    rep = ctx.autotune_cells(t, lz, lx, q, tr, cfg.sigma)
+    print(f"cell tuner: {rep}")
+    assert rep["div"] in (3, 4, 5, 6) and all(v > 0 for v in rep["ms"].values())
+    assert rep["ms"][rep["div"]] == min(rep["ms"].values())
+    after = {k: v.cpu().numpy() for k, v in rs.score_poses(ctx, t, lz, lx, q, tr, cfg.sigma).items()}
+    assert np.array_equal(before["flags"], after["flags"]) and np.array_equal(before["counts"], after["counts"])
+    F = t.export()
+    sample = np.arange(0, 16384, 64)
+    ref = oracle_score(cfg, wl, F, wl.quats[sample], wl.trans[sample])
+    assert_parity({k: v[sample] for k, v in after.items()}, ref, label="after the cell tuner")
+    t.free()
+    ctx.close()

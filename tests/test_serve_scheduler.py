@@ -160,3 +160,27 @@ def test_validate_rejects_malformed_and_unknown():
     assert serve.validate(nan, {"a": None}) == serve.E_MALFORMED
     big = _req(4, L=900)
     assert serve.validate(big, {"a": None}) == serve.E_MALFORMED
+
+
+def test_small_first_policy_takes_small_requests_whole_then_fifo():
+    s = serve.Scheduler(budget_bytes=10**12, resident_bytes=0, max_rounds=8, round_poses=100_000, min_slice=1000,
+                        policy="small_first")
+    big1, big2, small = _req(0, P=150_000), _req(1, P=80_000), _req(2, P=1500)
+    for r in (big1, big2, small):
+        s.submit(r, serve.request_bytes(r))
+    s.admit()
+    sl = s.next_round()
+    # the small request whole, then the oldest large request takes the rest of the round
+    assert [(r.rid, off, n) for r, off, n in sl] == [(2, 0, 1500), (0, 0, 98_500)]
+    s.finish_round(sl)
+    sl = s.next_round()
+    assert [(r.rid, off, n) for r, off, n in sl] == [(0, 98_500, 51_500), (1, 0, 48_500)]
+    s.finish_round(sl)
+    rounds = _drain(s)
+    assert all(r.state == serve.DONE for r in (big1, big2, small)) and len(rounds) == 1
+
+
+def test_unknown_policy_is_refused():
+    import pytest
+    with pytest.raises(ValueError):
+        serve.Scheduler(budget_bytes=1, resident_bytes=0, policy="lottery")
