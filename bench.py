@@ -132,7 +132,7 @@ def main() -> int:
                     help="cfg2: leave out the brief config-5 serving comparison of the default line")
     ap.add_argument("--serving-requests", type=int, default=60,
                     help="cfg2: arrivals per trace of the brief serving comparison")
-    ap.add_argument("--serve-policy", default="share", choices=["share", "small_first"],
+    ap.add_argument("--serve-policy", default="small_first", choices=["share", "small_first"],
                     help="cfg5 and the brief serving comparison: how a round's poses are shared among requests")
     ap.add_argument("--dump-requests", default="", help="cfg5: write per-request times (CSV) to this file")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",

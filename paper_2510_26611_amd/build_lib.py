@@ -51,5 +51,40 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Host code built with AddressSanitizer and UndefinedBehaviorSanitizer (device code as usual);
+# each -fsanitize option goes to the host compilation only.
+ASAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
+def build_host_sanitized(driver: str, verbose: bool = False) -> str:
+    """Compile every source and the host-only driver `driver` (a .cpp using the C ABI and
+    internal.h) with the sanitizers on the host code, linked into one executable under
+    _build/asan; returns its path."""
+    out_dir = os.path.join(OBJ, "asan")
+    os.makedirs(out_dir, exist_ok=True)
+
+    def comp(src_path: str, obj: str) -> str:
+        cmd = [HIPCC, *FLAGS, *ASAN_HOST, "-c", src_path, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src_path}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    jobs = [(os.path.join(CSRC, s), os.path.join(out_dir, os.path.splitext(s)[0] + ".o")) for s in SOURCES]
+    jobs.append((driver, os.path.join(out_dir, "driver.o")))
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        objs = list(ex.map(lambda j: comp(*j), jobs))
+    exe = os.path.join(out_dir, "host_asan_check")
+    cmd = [HIPCC, "--offload-arch=gfx950", *ASAN_HOST, *objs, "-o", exe, "-L/opt/rocm/lib", "-lrocsolver",
+           "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print(f"built {exe}", file=sys.stderr)
+    return exe
+
+
 if __name__ == "__main__":
     build(verbose=True)

@@ -207,7 +207,7 @@ void sinc_table(const rsd_sinc_params& sp, double* t, double* w) {
 }
 
 // ---------------------------------------------------------------- helpers
-static rsd_status check_sinc(const rsd_sinc_params* sp) {
+rsd_status check_sinc(const rsd_sinc_params* sp) {
   RSD_CHECK(sp != nullptr, RSD_E_INVALID, "sinc params are NULL");
   RSD_CHECK(sp->M >= 0 && sp->M + 1 <= kMaxTerms, RSD_E_INVALID, "M=%d out of range [0, %d]", sp->M, kMaxTerms - 1);
   RSD_CHECK(sp->K_long >= 0 && sp->K_long <= sp->M + 1, RSD_E_INVALID, "K_long=%d out of range", sp->K_long);
@@ -218,7 +218,7 @@ static rsd_status check_sinc(const rsd_sinc_params* sp) {
   return RSD_OK;
 }
 
-static rsd_status check_grid(int32_t n, double b) {
+rsd_status check_grid(int32_t n, double b) {
   RSD_CHECK(n >= 4 && n <= 32768 && n % 2 == 0, RSD_E_INVALID, "n=%d must be even and in [4, 32768]", n);
   RSD_CHECK(std::isfinite(b) && b > 0, RSD_E_INVALID, "b must be finite and > 0");
   return RSD_OK;
@@ -238,7 +238,7 @@ static rsd_status to_host(const double* src, size_t count, bool dev, std::vector
   return RSD_OK;
 }
 
-static rsd_status check_protein(const std::vector<double>& z, const std::vector<double>& pos, int32_t n, double b) {
+rsd_status check_protein(const std::vector<double>& z, const std::vector<double>& pos, int32_t n, double b) {
   double h, X0, inv_h;
   grid_constants(n, b, &h, &X0, &inv_h);
   for (size_t i = 0; i < z.size(); ++i) {
@@ -261,8 +261,8 @@ static rsd_status check_protein(const std::vector<double>& z, const std::vector<
 // interpolation error of every term is below about 3e-12 of its size; the table is checked
 // against the exact sum at 16 points per interval and discarded (the kernels then evaluate
 // the exponentials) if any relative error exceeds 1e-11, or if it would exceed 8 MB.
-static bool build_short_poly(const ShortTable& st, double rc2, std::vector<double>* coef, int* n1, double* x1,
-                             double* d1, double* d2) {
+bool build_short_poly(const ShortTable& st, double rc2, std::vector<double>* coef, int* n1, double* x1,
+                      double* d1, double* d2) {
   coef->clear();
   if (st.S <= 0 || !(rc2 > 0.0)) return false;
   double amax = 0.0, amin = st.t2[0];

@@ -565,23 +565,38 @@ __device__ __forceinline__ double block_sum256(double v, double* red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// The inverse of the upper triangular k x k block held in A (row-major, ld k), in place:
-// column j of the inverse above the diagonal is -(sum_{l=i}^{j-1} X[i][l] R[l][j]) / R[j][j]
-// from the columns already inverted.  A diagonal below floor is raised to it (a direction the
-// panel does not resolve; its column of the basis is then noise that later passes normalise).
+// The inverse of the upper triangular k x k block held in A (row-major, ld k), in place, by
+// rows from the bottom: X[i][c] = (delta_ic - sum_{l=i+1}^{c} R[i][l] X[l][c]) / R[i][i], the
+// rows below already holding X.  Row i of R is first copied to tmp (k doubles) because it is
+// overwritten while read.  Lanes take consecutive columns, so the X rows are read without bank
+// conflicts and tmp is broadcast; four partial sums shorten the dependency chain.  A diagonal
+// below floor is raised to it (a direction the panel does not resolve; its basis column is then
+// noise that the later passes normalise).
 __device__ void upper_inverse_lds(double* A, int k, double* tmp, double floor) {
   const int tid = threadIdx.x;
-  for (int j = 0; j < k; ++j) {
-    double rjj = A[j * k + j];
-    rjj = fabs(rjj) < floor ? (rjj < 0.0 ? -floor : floor) : rjj;
-    for (int i = tid; i < j; i += blockDim.x) {
-      double acc = 0.0;
-      for (int l = i; l < j; ++l) acc = fma(A[i * k + l], A[l * k + j], acc);
-      tmp[i] = acc;
-    }
+  for (int i = k - 1; i >= 0; --i) {
+    for (int l = i + tid; l < k; l += blockDim.x) tmp[l] = A[i * k + l];
     __syncthreads();
-    for (int i = tid; i < j; i += blockDim.x) A[i * k + j] = -tmp[i] / rjj;
-    if (tid == 0) A[j * k + j] = 1.0 / rjj;
+    double rii = tmp[i];
+    rii = fabs(rii) < floor ? (rii < 0.0 ? -floor : floor) : rii;
+    for (int c = i + tid; c < k; c += blockDim.x) {
+      double x;
+      if (c == i) {
+        x = 1.0 / rii;
+      } else {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int l = i + 1;
+        for (; l + 3 <= c; l += 4) {
+          a0 = fma(tmp[l], A[l * k + c], a0);
+          a1 = fma(tmp[l + 1], A[(l + 1) * k + c], a1);
+          a2 = fma(tmp[l + 2], A[(l + 2) * k + c], a2);
+          a3 = fma(tmp[l + 3], A[(l + 3) * k + c], a3);
+        }
+        for (; l <= c; ++l) a0 = fma(tmp[l], A[l * k + c], a0);
+        x = -((a0 + a1) + (a2 + a3)) / rii;
+      }
+      A[i * k + c] = x;
+    }
     __syncthreads();
   }
 }
@@ -590,6 +605,8 @@ __device__ void upper_inverse_lds(double* A, int k, double* tmp, double floor) {
 // the inverse of its triangular factor R: Rinv (k x k row-major, zeros below the diagonal).
 // Reflector j (LAPACK's convention): beta = -sign(alpha) ||x||, tau = (beta - alpha)/beta,
 // v = x / (alpha - beta) below the diagonal; none where the column below is already zero.
+// The update of the columns right of j takes two lanes per column (alternate rows, combined by
+// a shuffle) and four partial sums per lane.
 __global__ __launch_bounds__(256) void k_qr_rinv(const double* __restrict__ S, int s, int k,
                                                  double* __restrict__ Rinv) {
   extern __shared__ double A[];          // s * k, then k
@@ -599,6 +616,7 @@ __global__ __launch_bounds__(256) void k_qr_rinv(const double* __restrict__ S, i
   const int tid = threadIdx.x;
   for (int e = tid; e < s * k; e += 256) A[e] = S[e];
   __syncthreads();
+  const int h = tid & 1;
   for (int j = 0; j < k; ++j) {
     double part = 0.0;
     for (int i = j + 1 + tid; i < s; i += 256) part = fma(A[i * k + j], A[i * k + j], part);
@@ -621,12 +639,25 @@ __global__ __launch_bounds__(256) void k_qr_rinv(const double* __restrict__ S, i
     for (int i = j + 1 + tid; i < s; i += 256) A[i * k + j] *= scale;
     __syncthreads();
     if (tau != 0.0) {
-      for (int c = j + 1 + tid; c < k; c += 256) {
-        double w = A[j * k + c];
-        for (int i = j + 1; i < s; ++i) w = fma(A[i * k + j], A[i * k + c], w);
-        w *= tau;
-        A[j * k + c] -= w;
-        for (int i = j + 1; i < s; ++i) A[i * k + c] = fma(-A[i * k + j], w, A[i * k + c]);
+      const int c = j + 1 + (tid >> 1);
+      const bool on = c < k;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      if (on) {
+        int i = j + 1 + h;
+        for (; i + 6 < s; i += 8) {
+          a0 = fma(A[i * k + j], A[i * k + c], a0);
+          a1 = fma(A[(i + 2) * k + j], A[(i + 2) * k + c], a1);
+          a2 = fma(A[(i + 4) * k + j], A[(i + 4) * k + c], a2);
+          a3 = fma(A[(i + 6) * k + j], A[(i + 6) * k + c], a3);
+        }
+        for (; i < s; i += 2) a0 = fma(A[i * k + j], A[i * k + c], a0);
+      }
+      double w = (a0 + a1) + (a2 + a3);
+      w += __shfl_xor(w, 1, 64);
+      if (on) {
+        w = tau * (w + A[j * k + c]);
+        if (h == 0) A[j * k + c] -= w;
+        for (int i = j + 1 + h; i < s; i += 2) A[i * k + c] = fma(-A[i * k + j], w, A[i * k + c]);
       }
     }
     __syncthreads();
@@ -645,7 +676,8 @@ __global__ __launch_bounds__(256) void k_qr_rinv(const double* __restrict__ S, i
 // Upper Cholesky factor C of the symmetric part of M (k x k row-major, C^T C = (M + M^T)/2)
 // and its inverse Cinv (row-major, zeros below).  A pivot that is not positive (the panel lost
 // rank) sets *bad = 1 and is replaced by the smallest positive one seen, so the launch ends
-// normally; the caller reads *bad.
+// normally; the caller reads *bad.  The trailing update takes a column per lane (two row
+// halves per column over the 256 lanes).
 __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ M, int k, double* __restrict__ Cinv,
                                                   int* __restrict__ bad) {
   extern __shared__ double A[];          // k * k, then k
@@ -657,6 +689,7 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ M, 
   }
   __syncthreads();
   double dmin = 1e300;
+  const int lc = tid & 127, half = tid >> 7;
   for (int j = 0; j < k; ++j) {
     double piv = A[j * k + j];
     if (!(piv > 0.0)) {
@@ -669,10 +702,10 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ M, 
     if (tid == 0) A[j * k + j] = d;
     for (int l = j + 1 + tid; l < k; l += 256) A[j * k + l] /= d;
     __syncthreads();
-    const int m = k - j - 1;
-    for (int e = tid; e < m * m; e += 256) {
-      const int i = j + 1 + e / m, l = j + 1 + e % m;
-      if (i <= l) A[i * k + l] = fma(-A[j * k + i], A[j * k + l], A[i * k + l]);
+    const int l = j + 1 + lc;
+    if (l < k) {
+      const double ajl = A[j * k + l];
+      for (int i = j + 1 + half; i <= l; i += 2) A[i * k + l] = fma(-A[j * k + i], ajl, A[i * k + l]);
     }
     __syncthreads();
   }
@@ -939,13 +972,15 @@ rsd_status gemm_split(Context* ctx, const AOp& A, const BOp& B, int M, int N, in
   return RSD_OK;
 }
 
-// An orthonormal basis of the k columns of the n x k panel Y, stored transposed (Yt: k x n,
-// row-major, i.e. Y column-major): the randomized Cholesky QR -- the Householder QR of the sketch
-// Theta Y (kSmallRows x k, Theta uniform random) gives R_s, and Q1 = Y R_s^{-1} has a condition
-// number near that of Theta on the range of Y, independent of Y's -- then two Cholesky QR passes,
-// Q <- Q C^{-1} with C^T C = Q^T Q.  The result (transposed, k x n) goes to out; *bad is set when
-// a Cholesky pivot was not positive.  Y and out must differ.
-rsd_status orth_rchol(Context* ctx, const double* Yt, int k, int n, OrthBufs& b, double* out, int* bad) {
+// A basis of the k columns of the n x k panel Y, stored transposed (Yt: k x n, row-major, i.e. Y
+// column-major): the randomized Cholesky QR -- the Householder QR of the sketch Theta Y
+// (kSmallRows x k, Theta uniform random) gives R_s, and Q1 = Y R_s^{-1} has a condition number
+// near that of Theta on the range of Y, independent of Y's -- then `passes` Cholesky QR passes,
+// Q <- Q C^{-1} with C^T C = Q^T Q (two make it orthonormal to rounding; none leaves the well
+// conditioned Q1, enough for a power step).  The result (transposed, k x n) goes to out (passes
+// even); *bad is set when a Cholesky pivot was not positive.  Y and out must differ.
+rsd_status orth_rchol(Context* ctx, const double* Yt, int k, int n, OrthBufs& b, double* out, int* bad,
+                      int passes) {
   hipStream_t s = ctx->stream;
   const int sr = kSmallRows;
   RSD_TRY(gemm_split(ctx, OpMK{b.theta.p, n, sr}, OpMK{Yt, n, k}, sr, k, n, b.part.p, b.splits, b.sk.p));
@@ -957,7 +992,7 @@ rsd_status orth_rchol(Context* ctx, const double* Yt, int k, int n, OrthBufs& b,
   g.C = out;
   RSD_TRY(gemm(ctx, "eig", OpKM{b.rinv.p, k, k}, OpKM{Yt, n, n}, g, 1));      // out = (Y R_s^{-1})^T
   double* bufs[2] = {out, b.tmp.p};   // pass 0: out -> tmp, pass 1: tmp -> out
-  for (int pass = 0; pass < 2; ++pass) {
+  for (int pass = 0; pass < passes; ++pass) {
     const double* src = bufs[pass];
     RSD_TRY(gemm_split(ctx, OpMK{src, n, k}, OpMK{src, n, k}, k, k, n, b.part.p, b.splits, b.w.p));
     RSD_TIMED_LAUNCH(ctx, "eig", (k_chol_inv<<<1, 256, sizeof(double) * ((size_t)k * k + k), s>>>(b.w.p, k,
@@ -1042,9 +1077,11 @@ rsd_status subspace_eigvecs3(Context* ctx, rocblas_handle hb, double* G3, int n,
           RSD_TIMED_LAUNCH(ctx, "eig", (k_random_fill<<<grid1d((int64_t)kSmallRows * n), 256, 0, st[d]>>>(
                                            md.ob.theta.p, (int64_t)kSmallRows * n, 0x7E7Aull + (uint64_t)d)));
         }
-        auto qr = [&](DevBuf& P) -> rsd_status {   // P: column-major n x k -> orthonormal Q (in P)
+        // P: column-major n x k -> a basis of its columns in P: orthonormal (full), or only well
+        // conditioned (before the power step, which needs just the span)
+        auto qr = [&](DevBuf& P, bool full) -> rsd_status {
           if (!md.lib) {
-            RSD_TRY(orth_rchol(ctx, P.p, k, n, md.ob, md.Q.p, (int*)md.flag.p));
+            RSD_TRY(orth_rchol(ctx, P.p, k, n, md.ob, md.Q.p, (int*)md.flag.p, full ? 2 : 0));
             std::swap(P.p, md.Q.p);
             return RSD_OK;
           }
@@ -1063,11 +1100,11 @@ rsd_status subspace_eigvecs3(Context* ctx, rocblas_handle hb, double* G3, int n,
         // Y^T = Omega^T G  (k x n row-major = n x k column-major)
         g.M = k; g.N = n; g.K = n; g.kper = ((int64_t)n + TK - 1) / TK * TK; g.C = md.Y.p; g.ldc = n;
         RSD_TRY(gemm(ctx, "eig", OpKM{md.Om.p, k, k}, OpKM{G, n, n}, g, 1));
-        RSD_TRY(qr(md.Y));
-        // one power step: Z^T = Q^T G, orthonormalise again
+        RSD_TRY(qr(md.Y, false));
+        // one power step: Z^T = Q^T G, orthonormalise
         g.C = md.Z.p;
         RSD_TRY(gemm(ctx, "eig", OpMK{md.Y.p, n, k}, OpKM{G, n, n}, g, 1));
-        RSD_TRY(qr(md.Z));
+        RSD_TRY(qr(md.Z, true));
         // Rayleigh-Ritz: Y^T = Q^T G (k x n), T = Q^T G Q (k x k)
         g.C = md.Y.p;
         RSD_TRY(gemm(ctx, "eig", OpMK{md.Z.p, n, k}, OpKM{G, n, n}, g, 1));

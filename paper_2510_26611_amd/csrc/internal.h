@@ -203,6 +203,13 @@ struct Tensor {
 // sinc table (host): t_k and folded w_k, k = 0..M
 void sinc_table(const rsd_sinc_params& sp, double* t, double* w);
 
+// host-side argument checks and tables (api.hip), also exercised by the sanitizer build
+rsd_status check_sinc(const rsd_sinc_params* sp);
+rsd_status check_grid(int32_t n, double b);
+rsd_status check_protein(const std::vector<double>& z, const std::vector<double>& pos, int32_t n, double b);
+bool build_short_poly(const ShortTable& st, double rc2, std::vector<double>* coef, int* n1, double* x1,
+                      double* d1, double* d2);
+
 // grid constants with the fixed operation order shared by every component
 inline void grid_constants(int n, double b, double* h, double* X0, double* inv_h) {
   *h = (2.0 * b) / (double)n;

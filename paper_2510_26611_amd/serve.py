@@ -98,7 +98,7 @@ class Scheduler:
     """Admission by byte budget in arrival order, and pose slices per round shared evenly."""
 
     def __init__(self, budget_bytes: int, resident_bytes: int, scratch_bytes: int = 0, max_rounds: int = 2,
-                 round_poses: int = 250_000, min_slice: int = 16_384, policy: str = "share"):
+                 round_poses: int = 250_000, min_slice: int = 16_384, policy: str = "small_first"):
         if policy not in POLICIES:
             raise ValueError(f"policy must be one of {POLICIES}")
         self.policy = policy
@@ -250,7 +250,8 @@ class Server:
     """Serve a trace of requests against resident tensors on one GPU."""
 
     def __init__(self, tensors: dict, hbm_budget_bytes: int, streams: int = 2, round_poses: int = 250_000,
-                 min_slice: int = 16_384, device: int = 0, options: dict | None = None, policy: str = "share"):
+                 min_slice: int = 16_384, device: int = 0, options: dict | None = None,
+                 policy: str = "small_first"):
         import torch
         self.torch = torch
         self.tensors = tensors

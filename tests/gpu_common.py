@@ -8,6 +8,15 @@ from workloads import configs
 
 TOL = 1e-10   # relative to the FP64 summation-error scale of each pose
 
+# Build correctness where the oracle's exact-SVD compression is too costly on the host (the
+# n = 4096 and n = 8192/16384 workloads): max|T_gpu - T0| <= P2_C * eps * max|T0| at sampled
+# nodes.  Calibrated on the two workloads where the oracle's own compression is affordable and
+# then frozen: the device builds of the 200-atom (n = 512) and 5,000-atom (n = 2048) proteins
+# give max|T_gpu - T0| / (eps max|T0|) = 3.7 and 4.4 at 4,000 sampled nodes (the oracle's
+# exact-SVD builds: 3.2 and 4.4); P2_C is three times the larger.
+P2_C = 13.5
+P2_CALIBRATION = 4.5   # what the calibration workloads must stay within for P2_C to hold
+
 
 def sinc_parts(cfg):
     t, w = sinc.sinc_table(cfg.M, cfg.h_M, cfg.L_s)

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 sys.path.insert(0, os.path.dirname(__file__))
-from gpu_common import assert_parity, near_threshold_poses, oracle_factors, oracle_score, sinc_parts  # noqa: E402
+from gpu_common import P2_C, assert_parity, near_threshold_poses, oracle_factors, oracle_score, sinc_parts  # noqa: E402
 from oracle import score as oscore, tensor as otensor  # noqa: E402
 from workloads import configs  # noqa: E402
 
@@ -125,7 +125,7 @@ def test_cfg4_full_size_energy_gradient_flags(env, cfg4):
     F = t.export()
     dT = np.abs(_node_values(F, corners["index"]) - corners["value"])      # (points, 8)
     print(f"cfg4 node error at the sampled corners: max {dT.max():.3e} (max |T0| {np.abs(corners['value']).max():.3e})")
-    assert dT.max() <= 20 * cfg.eps * np.abs(corners["value"]).max()
+    assert dT.max() <= P2_C * cfg.eps * np.abs(corners["value"]).max()
     L = cfg.L
     pt_err = np.zeros(len(sample) * L)
     pt_err[corners["points"]] = np.sum(corners["weight"] * dT, axis=1)

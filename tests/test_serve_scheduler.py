@@ -2,6 +2,7 @@
 cancellation, the bound on rounds in flight, and the pose slices shared by a round.  No
 device is used; a simulated executor checks the latency property the slicing is for."""
 import numpy as np
+import pytest
 
 from paper_2510_26611_amd import serve
 
@@ -71,7 +72,8 @@ def test_cancel_frees_the_slot_for_the_next_request():
 
 
 def test_round_budget_is_shared_and_leftovers_redistributed():
-    s = serve.Scheduler(budget_bytes=10 ** 12, resident_bytes=0, max_rounds=4, round_poses=60_000, min_slice=1_000)
+    s = serve.Scheduler(budget_bytes=10 ** 12, resident_bytes=0, max_rounds=4, round_poses=60_000, min_slice=1_000,
+                        policy="share")
     a, b, c = _req(0, P=100_000), _req(1, P=10_000), _req(2, P=300_000)
     for r in (a, b, c):
         s.submit(r, 1)
@@ -115,14 +117,16 @@ def test_rounds_in_flight_are_bounded():
     assert s.next_round() != []
 
 
-def test_small_requests_are_not_held_behind_a_large_one():
+@pytest.mark.parametrize("policy,min_slice", [("share", 1_000), ("small_first", 3_000)])
+def test_small_requests_are_not_held_behind_a_large_one(policy, min_slice):
     """Simulated executor, one pose per time unit, rounds run one after another: requests
     arriving just after a huge one finish long before it; with one whole request per round
-    (round budget >= the largest request, no sharing) they would wait for all of it."""
-    def simulate(round_poses, min_slice):
+    (round budget >= the largest request, no sharing) they would wait for all of it.  Policy
+    small_first takes the 5,000-pose requests (at most 2 min_slice) whole into the next round."""
+    def simulate(round_poses, min_slice, policy):
         reqs = [_req(0, P=200_000, arrival=0.0)] + [_req(i, P=5_000, arrival=1.0 + i) for i in range(1, 6)]
         s = serve.Scheduler(budget_bytes=10 ** 12, resident_bytes=0, max_rounds=1, round_poses=round_poses,
-                            min_slice=min_slice)
+                            min_slice=min_slice, policy=policy)
         t, pending = 0.0, list(reqs)
         while pending or s.active:
             for r in [r for r in pending if r.arrival <= t]:
@@ -138,8 +142,8 @@ def test_small_requests_are_not_held_behind_a_large_one():
                 r.t_done = t
         return reqs
 
-    shared = simulate(20_000, 1_000)
-    whole = simulate(10 ** 9, 10 ** 9)
+    shared = simulate(20_000, min_slice, policy)
+    whole = simulate(10 ** 9, 10 ** 9, "share")
     small_shared = max(r.t_done - r.arrival for r in shared[1:])
     small_whole = min(r.t_done - r.arrival for r in whole[1:])
     # at most the round already running when they arrive plus two shared rounds
