@@ -137,6 +137,8 @@ def main() -> int:
     ap.add_argument("--dump-requests", default="", help="cfg5: write per-request times (CSV) to this file")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="only run a device copy of this many MiB (counter calibration) and exit")
+    ap.add_argument("--build-only", action="store_true",
+                    help="cfg1/cfg2/cfg4: time only the device build of the workload's tensor (steps builds) and exit")
     ap.add_argument("--calibrate-gather", action="store_true",
                     help="only time the long-range kernel's gather pattern alone (rsd_probe_gather) on chunks "
                          "of 512..8192 rows and exit")
@@ -201,6 +203,24 @@ def main() -> int:
     sinc = rs.Sinc.from_config(cfg)
     torch.cuda.synchronize()
 
+    if args.build_only:
+        def one_build():
+            t = rs.build_rs_tensor(ctx, d_z, d_x, cfg.n, cfg.b, sinc)
+            q = t.query()
+            t.free()
+            return q
+        for _ in range(args.warmup):
+            one_build()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            q = one_build()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        print(json.dumps({"workload": cfg.name, "build_ms": ms, "builds": args.steps, "tucker_ranks": list(q["ranks"]),
+                          "canonical_rank": q["R"]}), flush=True)
+        ctx.close()
+        return 0
     info = {}
     tune = None
     if not args.no_autotune and args.score_mode == 0:

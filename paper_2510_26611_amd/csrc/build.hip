@@ -42,15 +42,23 @@ constexpr int LDT = TM + 4;  // padded LDS row (doubles)
 // of its operand, zero outside [k0, k1) x [0, dim).  256 threads; thread t owns row
 // kk = t / 8 and the 8 columns (t % 8) * 8 .. +7.
 
+// Each loader reads its share of a stage into 8 registers (load) and writes them to LDS
+// (store), so that a product can load the next stage while the matrix cores work on this one.
+// Thread t of the (k, m)-ordered loaders owns row kk = t / 8 and the 8 columns (t % 8) * 8 .. +7.
+__device__ __forceinline__ void store_km(double* s, int sld, const double* v) {
+  const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s[kk * sld + c + j] = v[j];
+}
+
 struct OpKM {                 // element (k, m) = p[k * ld + m]
   const double* __restrict__ p;
   int64_t ld;
   int dim;
   __device__ void setup(int) {}
-  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
+  __device__ void load(double* v, int64_t k0, int64_t k1, int m0) const {
     const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
     const int64_t k = k0 + kk;
-    double v[8];
     if (k < k1 && m0 + c + 8 <= dim) {
       const double2* src = reinterpret_cast<const double2*>(p + k * ld + m0 + c);
 #pragma unroll
@@ -63,8 +71,12 @@ struct OpKM {                 // element (k, m) = p[k * ld + m]
 #pragma unroll
       for (int j = 0; j < 8; ++j) v[j] = (k < k1 && m0 + c + j < dim) ? p[k * ld + m0 + c + j] : 0.0;
     }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) s[kk * sld + c + j] = v[j];
+  }
+  __device__ void store(double* s, int sld, const double* v) const { store_km(s, sld, v); }
+  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
+    double v[8];
+    load(v, k0, k1, m0);
+    store(s, sld, v);
   }
 };
 
@@ -73,14 +85,25 @@ struct OpMK {                 // element (k, m) = p[m * ld + k]  (each m-row con
   int64_t ld;
   int dim;
   __device__ void setup(int) {}
-  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
+  // thread t owns m-row mm = t / 4 and the 8 contraction indices (t % 4) * 8 .. +7
+  __device__ void load(double* v, int64_t k0, int64_t k1, int m0) const {
     const int t = threadIdx.x, mm = t >> 2, kk = (t & 3) * 8;
     const int m = m0 + mm;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int64_t k = k0 + kk + j;
-      s[(kk + j) * sld + mm] = (m < dim && k < k1) ? p[(int64_t)m * ld + k] : 0.0;
+      v[j] = (m < dim && k < k1) ? p[(int64_t)m * ld + k] : 0.0;
     }
+  }
+  __device__ void store(double* s, int sld, const double* v) const {
+    const int t = threadIdx.x, mm = t >> 2, kk = (t & 3) * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[(kk + j) * sld + mm] = v[j];
+  }
+  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
+    double v[8];
+    load(v, k0, k1, m0);
+    store(s, sld, v);
   }
 };
 
@@ -90,13 +113,18 @@ struct OpKMScaled {           // element (k, m) = p[k * ld + m] * scale[k]
   int64_t ld;
   int dim;
   __device__ void setup(int) {}
-  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
+  __device__ void load(double* v, int64_t k0, int64_t k1, int m0) const {
     const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
     const int64_t k = k0 + kk;
     const double sc = k < k1 ? scale[k] : 0.0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      s[kk * sld + c + j] = (k < k1 && m0 + c + j < dim) ? p[k * ld + m0 + c + j] * sc : 0.0;
+    for (int j = 0; j < 8; ++j) v[j] = (k < k1 && m0 + c + j < dim) ? p[k * ld + m0 + c + j] * sc : 0.0;
+  }
+  __device__ void store(double* s, int sld, const double* v) const { store_km(s, sld, v); }
+  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
+    double v[8];
+    load(v, k0, k1, m0);
+    store(s, sld, v);
   }
 };
 
@@ -116,12 +144,18 @@ struct OpKhatriRao {          // element (k, m = a*r2 + b) = P1[k*ld1 + a] * P2[
       b_[j] = m < dim ? m % r2 : 0;
     }
   }
-  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
+  __device__ void load(double* v, int64_t k0, int64_t k1, int m0) const {
     const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
     const int64_t k = k0 + kk;
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-      s[kk * sld + c + j] = (k < k1 && m0 + c + j < dim) ? P1[k * ld1 + a_[j]] * P2[k * ld2 + b_[j]] : 0.0;
+      v[j] = (k < k1 && m0 + c + j < dim) ? P1[k * ld1 + a_[j]] * P2[k * ld2 + b_[j]] : 0.0;
+  }
+  __device__ void store(double* s, int sld, const double* v) const { store_km(s, sld, v); }
+  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
+    double v[8];
+    load(v, k0, k1, m0);
+    store(s, sld, v);
   }
 };
 
@@ -182,15 +216,21 @@ struct OpGauss {              // element (k = grid row i, m = column c) = g_c(X_
       }
     }
   }
-  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
-    const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
+  __device__ void load(double* v, int64_t k0, int64_t k1, int m0) const {
+    const int t = threadIdx.x, kk = t >> 3;
     const int64_t i = k0 + kk;
     const double X = -b + (double)(i + 1) * h;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const double dx = X - x_[j];
-      s[kk * sld + c + j] = (i < k1) ? gauss_entry(t2_[j], dx, h, GAL ? 1 : 0) * s_[j] : 0.0;
+      v[j] = (i < k1) ? gauss_entry(t2_[j], dx, h, GAL ? 1 : 0) * s_[j] : 0.0;
     }
+  }
+  __device__ void store(double* s, int sld, const double* v) const { store_km(s, sld, v); }
+  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
+    double v[8];
+    load(v, k0, k1, m0);
+    store(s, sld, v);
   }
 };
 
@@ -282,10 +322,20 @@ __global__ __launch_bounds__(256) void k_gemm(AOp A, BOp B, const GemmShape g) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
+  // the next stage is loaded into registers while the matrix cores work on this one
+  double va[8], vb[8];
+  if (k0 < k1) {
+    A.load(va, k0, k1, m0);
+    B.load(vb, k0, k1, n0);
+  }
   for (int64_t kb = k0; kb < k1; kb += TK) {
-    A.fill(sA, LDT, kb, k1, m0);
-    B.fill(sB, LDT, kb, k1, n0);
+    A.store(sA, LDT, va);
+    B.store(sB, LDT, vb);
     __syncthreads();
+    if (kb + TK < k1) {
+      A.load(va, kb + TK, k1, m0);
+      B.load(vb, kb + TK, k1, n0);
+    }
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       const double a0 = sA[(kk + lk) * LDT + wm + lr];
@@ -324,7 +374,7 @@ constexpr int TNW = 80;
 constexpr int LDTW = 2 * TN + 4;   // B tile: two 64-column fills, padded
 
 template <class AOp, class BOp>
-__global__ __launch_bounds__(256) void k_gemm_w(AOp A, BOp B, const GemmShape g) {
+__global__ __launch_bounds__(256, 3) void k_gemm_w(AOp A, BOp B, const GemmShape g) {
   __shared__ double sA[TK * LDT];
   __shared__ double sB[TK * LDTW];
   const int m0 = blockIdx.x * TM;
@@ -339,11 +389,22 @@ __global__ __launch_bounds__(256) void k_gemm_w(AOp A, BOp B, const GemmShape g)
   d4v acc[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) acc[j] = d4v{0.0, 0.0, 0.0, 0.0};
+  double va[8], vb[8], vb1[8];
+  if (k0 < k1) {
+    A.load(va, k0, k1, m0);
+    B.load(vb, k0, k1, 0);
+    B1.load(vb1, k0, k1, TN);
+  }
   for (int64_t kb = k0; kb < k1; kb += TK) {
-    A.fill(sA, LDT, kb, k1, m0);
-    B.fill(sB, LDTW, kb, k1, 0);
-    B1.fill(sB + TN, LDTW, kb, k1, TN);
+    A.store(sA, LDT, va);
+    B.store(sB, LDTW, vb);
+    B1.store(sB + TN, LDTW, vb1);
     __syncthreads();
+    if (kb + TK < k1) {
+      A.load(va, kb + TK, k1, m0);
+      B.load(vb, kb + TK, k1, 0);
+      B1.load(vb1, kb + TK, k1, TN);
+    }
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       const double a = sA[(kk + lk) * LDT + 16 * w + lr];
@@ -1214,8 +1275,10 @@ rsd_status tucker_canonical(Context* ctx, Tensor* t, DevBuf Bt[3], DevBuf U[3], 
   const double eps = t->sp.eps;
   const int n = t->n;
   const int M12 = r[0] * r[1];
-  const int tiles = div_up(M12, TM) * div_up(r[2], TN);
-  const int csplit = std::max(1, std::min(64, div_up(1024, tiles)));
+  // output tiles (one column tile when r3 <= TNW, the wide kernel), and enough contraction
+  // splits for about eight workgroups per compute unit
+  const int tiles = div_up(M12, TM) * (r[2] <= TNW ? 1 : div_up(r[2], TN));
+  const int csplit = std::max(1, std::min(64, div_up(2048, tiles)));
   DevBuf Cpart, beta;
   RSD_TRY(Cpart.alloc(ctx, (size_t)csplit * M12 * r[2]));
   RSD_TRY(beta.alloc(ctx, (size_t)M12 * r[2]));
