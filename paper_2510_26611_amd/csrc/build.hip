@@ -626,17 +626,17 @@ __device__ __forceinline__ double block_sum256(double v, double* red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// The inverse of the upper triangular k x k block held in A (row-major, ld k), in place, by
-// rows from the bottom: X[i][c] = (delta_ic - sum_{l=i+1}^{c} R[i][l] X[l][c]) / R[i][i], the
-// rows below already holding X.  Row i of R is first copied to tmp (k doubles) because it is
-// overwritten while read.  Lanes take consecutive columns, so the X rows are read without bank
-// conflicts and tmp is broadcast; four partial sums shorten the dependency chain.  A diagonal
-// below floor is raised to it (a direction the panel does not resolve; its basis column is then
-// noise that the later passes normalise).
-__device__ void upper_inverse_lds(double* A, int k, double* tmp, double floor) {
+// The inverse of the upper triangular k x k block held in A (row-major, leading dimension ld),
+// in place, by rows from the bottom: X[i][c] = (delta_ic - sum_{l=i+1}^{c} R[i][l] X[l][c]) /
+// R[i][i], the rows below already holding X.  Row i of R is first copied to tmp (k doubles)
+// because it is overwritten while read.  Lanes take consecutive columns, so the X rows are read
+// without bank conflicts and tmp is broadcast; four partial sums shorten the dependency chain.
+// A diagonal below floor is raised to it (a direction the panel does not resolve; its basis
+// column is then noise that the later passes normalise).
+__device__ void upper_inverse_lds(double* A, int k, int ld, double* tmp, double floor) {
   const int tid = threadIdx.x;
   for (int i = k - 1; i >= 0; --i) {
-    for (int l = i + tid; l < k; l += blockDim.x) tmp[l] = A[i * k + l];
+    for (int l = i + tid; l < k; l += blockDim.x) tmp[l] = A[i * ld + l];
     __syncthreads();
     double rii = tmp[i];
     rii = fabs(rii) < floor ? (rii < 0.0 ? -floor : floor) : rii;
@@ -648,15 +648,15 @@ __device__ void upper_inverse_lds(double* A, int k, double* tmp, double floor) {
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         int l = i + 1;
         for (; l + 3 <= c; l += 4) {
-          a0 = fma(tmp[l], A[l * k + c], a0);
-          a1 = fma(tmp[l + 1], A[(l + 1) * k + c], a1);
-          a2 = fma(tmp[l + 2], A[(l + 2) * k + c], a2);
-          a3 = fma(tmp[l + 3], A[(l + 3) * k + c], a3);
+          a0 = fma(tmp[l], A[l * ld + c], a0);
+          a1 = fma(tmp[l + 1], A[(l + 1) * ld + c], a1);
+          a2 = fma(tmp[l + 2], A[(l + 2) * ld + c], a2);
+          a3 = fma(tmp[l + 3], A[(l + 3) * ld + c], a3);
         }
-        for (; l <= c; ++l) a0 = fma(tmp[l], A[l * k + c], a0);
+        for (; l <= c; ++l) a0 = fma(tmp[l], A[l * ld + c], a0);
         x = -((a0 + a1) + (a2 + a3)) / rii;
       }
-      A[i * k + c] = x;
+      A[i * ld + c] = x;
     }
     __syncthreads();
   }
@@ -667,23 +667,25 @@ __device__ void upper_inverse_lds(double* A, int k, double* tmp, double floor) {
 // Reflector j (LAPACK's convention): beta = -sign(alpha) ||x||, tau = (beta - alpha)/beta,
 // v = x / (alpha - beta) below the diagonal; none where the column below is already zero.
 // The update of the columns right of j takes two lanes per column (alternate rows, combined by
-// a shuffle) and four partial sums per lane.
+// a shuffle) and four partial sums per lane.  LDS rows are k + 1 doubles apart, so the two
+// lanes of a column (rows i and i + 1) fall in different banks.
 __global__ __launch_bounds__(256) void k_qr_rinv(const double* __restrict__ S, int s, int k,
                                                  double* __restrict__ Rinv) {
-  extern __shared__ double A[];          // s * k, then k
-  double* tmp = A + (size_t)s * k;
+  extern __shared__ double A[];          // s rows of k + 1, then k
+  const int ld = k + 1;
+  double* tmp = A + (size_t)s * ld;
   __shared__ double red[4];
   __shared__ double s_par[3];            // beta, tau, scale
   const int tid = threadIdx.x;
-  for (int e = tid; e < s * k; e += 256) A[e] = S[e];
+  for (int e = tid; e < s * k; e += 256) A[(e / k) * ld + e % k] = S[e];
   __syncthreads();
   const int h = tid & 1;
   for (int j = 0; j < k; ++j) {
     double part = 0.0;
-    for (int i = j + 1 + tid; i < s; i += 256) part = fma(A[i * k + j], A[i * k + j], part);
+    for (int i = j + 1 + tid; i < s; i += 256) part = fma(A[i * ld + j], A[i * ld + j], part);
     const double xn2 = block_sum256(part, red);
     if (tid == 0) {
-      const double alpha = A[j * k + j];
+      const double alpha = A[j * ld + j];
       double beta = alpha, tau = 0.0, scale = 0.0;
       if (xn2 > 0.0) {
         const double nrm = sqrt(alpha * alpha + xn2);
@@ -697,7 +699,7 @@ __global__ __launch_bounds__(256) void k_qr_rinv(const double* __restrict__ S, i
     }
     __syncthreads();
     const double beta = s_par[0], tau = s_par[1], scale = s_par[2];
-    for (int i = j + 1 + tid; i < s; i += 256) A[i * k + j] *= scale;
+    for (int i = j + 1 + tid; i < s; i += 256) A[i * ld + j] *= scale;
     __syncthreads();
     if (tau != 0.0) {
       const int c = j + 1 + (tid >> 1);
@@ -706,31 +708,31 @@ __global__ __launch_bounds__(256) void k_qr_rinv(const double* __restrict__ S, i
       if (on) {
         int i = j + 1 + h;
         for (; i + 6 < s; i += 8) {
-          a0 = fma(A[i * k + j], A[i * k + c], a0);
-          a1 = fma(A[(i + 2) * k + j], A[(i + 2) * k + c], a1);
-          a2 = fma(A[(i + 4) * k + j], A[(i + 4) * k + c], a2);
-          a3 = fma(A[(i + 6) * k + j], A[(i + 6) * k + c], a3);
+          a0 = fma(A[i * ld + j], A[i * ld + c], a0);
+          a1 = fma(A[(i + 2) * ld + j], A[(i + 2) * ld + c], a1);
+          a2 = fma(A[(i + 4) * ld + j], A[(i + 4) * ld + c], a2);
+          a3 = fma(A[(i + 6) * ld + j], A[(i + 6) * ld + c], a3);
         }
-        for (; i < s; i += 2) a0 = fma(A[i * k + j], A[i * k + c], a0);
+        for (; i < s; i += 2) a0 = fma(A[i * ld + j], A[i * ld + c], a0);
       }
       double w = (a0 + a1) + (a2 + a3);
       w += __shfl_xor(w, 1, 64);
       if (on) {
-        w = tau * (w + A[j * k + c]);
-        if (h == 0) A[j * k + c] -= w;
-        for (int i = j + 1 + h; i < s; i += 2) A[i * k + c] = fma(-A[i * k + j], w, A[i * k + c]);
+        w = tau * (w + A[j * ld + c]);
+        if (h == 0) A[j * ld + c] -= w;
+        for (int i = j + 1 + h; i < s; i += 2) A[i * ld + c] = fma(-A[i * ld + j], w, A[i * ld + c]);
       }
     }
     __syncthreads();
-    if (tid == 0) A[j * k + j] = beta;
+    if (tid == 0) A[j * ld + j] = beta;
     __syncthreads();
   }
   double dmax = 0.0;
-  for (int j = 0; j < k; ++j) dmax = fmax(dmax, fabs(A[j * k + j]));
-  upper_inverse_lds(A, k, tmp, dmax * 0x1p-63);
+  for (int j = 0; j < k; ++j) dmax = fmax(dmax, fabs(A[j * ld + j]));
+  upper_inverse_lds(A, k, ld, tmp, dmax * 0x1p-63);
   for (int e = tid; e < k * k; e += 256) {
     const int i = e / k, c = e % k;
-    Rinv[e] = c >= i ? A[e] : 0.0;
+    Rinv[e] = c >= i ? A[i * ld + c] : 0.0;
   }
 }
 
@@ -738,21 +740,22 @@ __global__ __launch_bounds__(256) void k_qr_rinv(const double* __restrict__ S, i
 // and its inverse Cinv (row-major, zeros below).  A pivot that is not positive (the panel lost
 // rank) sets *bad = 1 and is replaced by the smallest positive one seen, so the launch ends
 // normally; the caller reads *bad.  The trailing update takes a column per lane (two row
-// halves per column over the 256 lanes).
+// halves per column over the 256 lanes); LDS rows are k + 1 doubles apart.
 __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ M, int k, double* __restrict__ Cinv,
                                                   int* __restrict__ bad) {
-  extern __shared__ double A[];          // k * k, then k
-  double* tmp = A + (size_t)k * k;
+  extern __shared__ double A[];          // k rows of k + 1, then k
+  const int ld = k + 1;
+  double* tmp = A + (size_t)k * ld;
   const int tid = threadIdx.x;
   for (int e = tid; e < k * k; e += 256) {
     const int i = e / k, l = e % k;
-    A[e] = 0.5 * (M[i * k + l] + M[l * k + i]);
+    A[i * ld + l] = 0.5 * (M[i * k + l] + M[l * k + i]);
   }
   __syncthreads();
   double dmin = 1e300;
   const int lc = tid & 127, half = tid >> 7;
   for (int j = 0; j < k; ++j) {
-    double piv = A[j * k + j];
+    double piv = A[j * ld + j];
     if (!(piv > 0.0)) {
       if (tid == 0) *bad = 1;
       piv = dmin < 1e300 ? dmin * dmin : 1.0;
@@ -760,20 +763,20 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ M, 
     const double d = sqrt(piv);
     dmin = fmin(dmin, d);
     __syncthreads();   // every thread has read the pivot
-    if (tid == 0) A[j * k + j] = d;
-    for (int l = j + 1 + tid; l < k; l += 256) A[j * k + l] /= d;
+    if (tid == 0) A[j * ld + j] = d;
+    for (int l = j + 1 + tid; l < k; l += 256) A[j * ld + l] /= d;
     __syncthreads();
     const int l = j + 1 + lc;
     if (l < k) {
-      const double ajl = A[j * k + l];
-      for (int i = j + 1 + half; i <= l; i += 2) A[i * k + l] = fma(-A[j * k + i], ajl, A[i * k + l]);
+      const double ajl = A[j * ld + l];
+      for (int i = j + 1 + half; i <= l; i += 2) A[i * ld + l] = fma(-A[j * ld + i], ajl, A[i * ld + l]);
     }
     __syncthreads();
   }
-  upper_inverse_lds(A, k, tmp, 0.0);
+  upper_inverse_lds(A, k, ld, tmp, 0.0);
   for (int e = tid; e < k * k; e += 256) {
     const int i = e / k, c = e % k;
-    Cinv[e] = c >= i ? A[e] : 0.0;
+    Cinv[e] = c >= i ? A[i * ld + c] : 0.0;
   }
 }
 
@@ -996,9 +999,9 @@ rsd_status allow_small_lds() {
   std::lock_guard<std::mutex> lock(mu);
   if (std::find(done.begin(), done.end(), dev) != done.end()) return RSD_OK;
   RSD_HIP(hipFuncSetAttribute((const void*)k_qr_rinv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(double) * (kSmallRows * kSmallCols + kSmallCols))));
+                              (int)(sizeof(double) * (kSmallRows * (kSmallCols + 1) + kSmallCols))));
   RSD_HIP(hipFuncSetAttribute((const void*)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(double) * (kSmallCols * kSmallCols + kSmallCols))));
+                              (int)(sizeof(double) * (kSmallCols * (kSmallCols + 1) + kSmallCols))));
   done.push_back(dev);
   return RSD_OK;
 }
@@ -1045,8 +1048,8 @@ rsd_status orth_rchol(Context* ctx, const double* Yt, int k, int n, OrthBufs& b,
   hipStream_t s = ctx->stream;
   const int sr = kSmallRows;
   RSD_TRY(gemm_split(ctx, OpMK{b.theta.p, n, sr}, OpMK{Yt, n, k}, sr, k, n, b.part.p, b.splits, b.sk.p));
-  RSD_TIMED_LAUNCH(ctx, "eig", (k_qr_rinv<<<1, 256, sizeof(double) * ((size_t)sr * k + k), s>>>(b.sk.p, sr, k,
-                                                                                              b.rinv.p)));
+  RSD_TIMED_LAUNCH(ctx, "eig", (k_qr_rinv<<<1, 256, sizeof(double) * ((size_t)sr * (k + 1) + k), s>>>(
+                                   b.sk.p, sr, k, b.rinv.p)));
   GemmShape g{};
   g.M = k; g.N = n; g.K = k; g.kper = ((int64_t)k + TK - 1) / TK * TK; g.ldc = n;
   g.split_stride = 0; g.accumulate = 0; g.tri = 0;
@@ -1056,8 +1059,8 @@ rsd_status orth_rchol(Context* ctx, const double* Yt, int k, int n, OrthBufs& b,
   for (int pass = 0; pass < passes; ++pass) {
     const double* src = bufs[pass];
     RSD_TRY(gemm_split(ctx, OpMK{src, n, k}, OpMK{src, n, k}, k, k, n, b.part.p, b.splits, b.w.p));
-    RSD_TIMED_LAUNCH(ctx, "eig", (k_chol_inv<<<1, 256, sizeof(double) * ((size_t)k * k + k), s>>>(b.w.p, k,
-                                                                                                 b.rinv.p, bad)));
+    RSD_TIMED_LAUNCH(ctx, "eig", (k_chol_inv<<<1, 256, sizeof(double) * ((size_t)k * (k + 1) + k), s>>>(
+                                     b.w.p, k, b.rinv.p, bad)));
     g.C = bufs[1 - pass];
     RSD_TRY(gemm(ctx, "eig", OpKM{b.rinv.p, k, k}, OpKM{src, n, n}, g, 1));
   }
