@@ -35,128 +35,116 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 constexpr int TM = 64;       // output tile rows
 constexpr int TN = 64;       // output tile cols
 constexpr int TK = 32;       // contraction depth per LDS stage
-constexpr int LDT = TM + 4;  // padded LDS row (doubles)
+constexpr int TNW = 80;      // the wide product's single column tile
+// LDS rows of a stage.  (k, m)-ordered stages use rows of 80 doubles (160 words, half the
+// 64 banks): the four 16-lane groups of an MFMA operand read (16 consecutive m of rows
+// k .. k+3) then fall in disjoint banks per 32-lane half.  (m, k)-ordered stages use rows of
+// TK + 2 doubles (68 words): lane (m, k) of a read starts at bank 4m + 2k, again disjoint.
+constexpr int LDT = 80;
+constexpr int LDK = TK + 2;
+constexpr int kStage = TNW * LDK;   // doubles per operand stage: max(TK * LDT, TNW * LDK)
 
 // ----------------------------------------------------------------- operand loaders
-// Each loader fills an LDS stage s[kk][mm] (kk < TK, mm < 64) with element (k0+kk, m0+mm)
-// of its operand, zero outside [k0, k1) x [0, dim).  256 threads; thread t owns row
-// kk = t / 8 and the 8 columns (t % 8) * 8 .. +7.
-
-// Each loader reads its share of a stage into 8 registers (load) and writes them to LDS
-// (store), so that a product can load the next stage while the matrix cores work on this one.
-// Thread t of the (k, m)-ordered loaders owns row kk = t / 8 and the 8 columns (t % 8) * 8 .. +7.
-__device__ __forceinline__ void store_km(double* s, int sld, const double* v) {
-  const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) s[kk * sld + c + j] = v[j];
-}
-
+// A loader moves one TK x W stage of its operand (element (k0 + kk, m0 + mm), zero outside
+// [k0, k1) x [0, dim)) into LDS in two steps:
+//   fetch: global loads (or generated values) into registers, with no condition, the row
+//          index clamped into [.., k1 - 1] and the column to a valid one, so the loads of the
+//          next stage stay in flight while the matrix cores work on this one;
+//   store: the mask for rows and columns outside the operand, any arithmetic on the fetched
+//          values, and the LDS write.
+// at(s, k, m) reads element (k, m) of a stored stage.  256 threads; W = 64 or TNW.
+// (k, m)-ordered stages: element e = j * 256 + t of the stage (j < TK * W / 256) is row e / W,
+// column e % W, so the lanes of one load and one LDS write run along memory.
 struct OpKM {                 // element (k, m) = p[k * ld + m]
   const double* __restrict__ p;
   int64_t ld;
   int dim;
+  template <int W> static constexpr int regs() { return TK * W / 256; }
   __device__ void setup(int) {}
-  __device__ void load(double* v, int64_t k0, int64_t k1, int m0) const {
-    const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
-    const int64_t k = k0 + kk;
-    if (k < k1 && m0 + c + 8 <= dim) {
-      const double2* src = reinterpret_cast<const double2*>(p + k * ld + m0 + c);
+  template <int W>
+  __device__ void fetch(double* r, int m0, int64_t kb, int64_t k1) const {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const double2 x = src[j];
-        v[2 * j] = x.x;
-        v[2 * j + 1] = x.y;
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = (k < k1 && m0 + c + j < dim) ? p[k * ld + m0 + c + j] : 0.0;
+    for (int j = 0; j < regs<W>(); ++j) {
+      const int e = j * 256 + (int)threadIdx.x, kk = e / W, m = m0 + e - kk * W;
+      const int64_t k = min(kb + kk, k1 - 1);
+      r[j] = p[k * ld + (m < dim ? m : 0)];
     }
   }
-  __device__ void store(double* s, int sld, const double* v) const { store_km(s, sld, v); }
-  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
-    double v[8];
-    load(v, k0, k1, m0);
-    store(s, sld, v);
+  template <int W>
+  __device__ void store(double* s, const double* r, int m0, int64_t kb, int64_t k1) const {
+#pragma unroll
+    for (int j = 0; j < regs<W>(); ++j) {
+      const int e = j * 256 + (int)threadIdx.x, kk = e / W, mm = e - kk * W;
+      s[kk * LDT + mm] = (kb + kk < k1 && m0 + mm < dim) ? r[j] : 0.0;
+    }
   }
+  static __device__ double at(const double* s, int k, int m) { return s[k * LDT + m]; }
 };
 
+// (m, k)-ordered stages: thread t takes contraction index t % 32 of the columns
+// t / 32 + 8 j, so the lanes of one load run along an m-row of the operand.
 struct OpMK {                 // element (k, m) = p[m * ld + k]  (each m-row contiguous along k)
   const double* __restrict__ p;
   int64_t ld;
   int dim;
+  template <int W> static constexpr int regs() { return W / 8; }
   __device__ void setup(int) {}
-  // thread t owns m-row mm = t / 4 and the 8 contraction indices (t % 4) * 8 .. +7
-  __device__ void load(double* v, int64_t k0, int64_t k1, int m0) const {
-    const int t = threadIdx.x, mm = t >> 2, kk = (t & 3) * 8;
-    const int m = m0 + mm;
+  template <int W>
+  __device__ void fetch(double* r, int m0, int64_t kb, int64_t k1) const {
+    const int kk = threadIdx.x & 31, mg = threadIdx.x >> 5;
+    const int64_t k = min(kb + kk, k1 - 1);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int64_t k = k0 + kk + j;
-      v[j] = (m < dim && k < k1) ? p[(int64_t)m * ld + k] : 0.0;
+    for (int j = 0; j < regs<W>(); ++j) {
+      const int m = m0 + mg + 8 * j;
+      r[j] = p[(int64_t)(m < dim ? m : 0) * ld + k];
     }
   }
-  __device__ void store(double* s, int sld, const double* v) const {
-    const int t = threadIdx.x, mm = t >> 2, kk = (t & 3) * 8;
+  template <int W>
+  __device__ void store(double* s, const double* r, int m0, int64_t kb, int64_t k1) const {
+    const int kk = threadIdx.x & 31, mg = threadIdx.x >> 5;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) s[(kk + j) * sld + mm] = v[j];
+    for (int j = 0; j < regs<W>(); ++j) {
+      const int mm = mg + 8 * j;
+      s[mm * LDK + kk] = (kb + kk < k1 && m0 + mm < dim) ? r[j] : 0.0;
+    }
   }
-  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
-    double v[8];
-    load(v, k0, k1, m0);
-    store(s, sld, v);
-  }
+  static __device__ double at(const double* s, int k, int m) { return s[m * LDK + k]; }
 };
 
-struct OpKMScaled {           // element (k, m) = p[k * ld + m] * scale[k]
-  const double* __restrict__ p;
-  const double* __restrict__ scale;
-  int64_t ld;
-  int dim;
-  __device__ void setup(int) {}
-  __device__ void load(double* v, int64_t k0, int64_t k1, int m0) const {
-    const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
-    const int64_t k = k0 + kk;
-    const double sc = k < k1 ? scale[k] : 0.0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = (k < k1 && m0 + c + j < dim) ? p[k * ld + m0 + c + j] * sc : 0.0;
-  }
-  __device__ void store(double* s, int sld, const double* v) const { store_km(s, sld, v); }
-  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
-    double v[8];
-    load(v, k0, k1, m0);
-    store(s, sld, v);
-  }
-};
-
+// The generated left operands fill 64-wide (k, m)-ordered stages only: thread t owns column
+// t % 64 and rows t / 64 + 4 j.
 struct OpKhatriRao {          // element (k, m = a*r2 + b) = P1[k*ld1 + a] * P2[k*ld2 + b]
   const double* __restrict__ P1;
   const double* __restrict__ P2;
   int64_t ld1, ld2;
   int r2;
   int dim;                    // r1 * r2
-  int a_[8], b_[8];
+  int a_, b_;
+  template <int W> static constexpr int regs() { return 16; }   // both factors of 8 entries
   __device__ void setup(int m0) {
-    const int c = (threadIdx.x & 7) * 8;
+    const int m = m0 + (threadIdx.x & 63);
+    a_ = m < dim ? m / r2 : 0;
+    b_ = m < dim ? m % r2 : 0;
+  }
+  template <int W>
+  __device__ void fetch(double* r, int, int64_t kb, int64_t k1) const {
+    static_assert(W == TM, "generated operands fill 64-wide stages");
+    const int kq = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int m = m0 + c + j;
-      a_[j] = m < dim ? m / r2 : 0;
-      b_[j] = m < dim ? m % r2 : 0;
+      const int64_t k = min(kb + kq + 4 * j, k1 - 1);
+      r[2 * j] = P1[k * ld1 + a_];
+      r[2 * j + 1] = P2[k * ld2 + b_];
     }
   }
-  __device__ void load(double* v, int64_t k0, int64_t k1, int m0) const {
-    const int t = threadIdx.x, kk = t >> 3, c = (t & 7) * 8;
-    const int64_t k = k0 + kk;
+  template <int W>
+  __device__ void store(double* s, const double* r, int m0, int64_t kb, int64_t k1) const {
+    const int mm = threadIdx.x & 63, kq = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-      v[j] = (k < k1 && m0 + c + j < dim) ? P1[k * ld1 + a_[j]] * P2[k * ld2 + b_[j]] : 0.0;
+      s[(kq + 4 * j) * LDT + mm] = (kb + kq + 4 * j < k1 && m0 + mm < dim) ? r[2 * j] * r[2 * j + 1] : 0.0;
   }
-  __device__ void store(double* s, int sld, const double* v) const { store_km(s, sld, v); }
-  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
-    double v[8];
-    load(v, k0, k1, m0);
-    store(s, sld, v);
-  }
+  static __device__ double at(const double* s, int k, int m) { return s[k * LDT + m]; }
 };
 
 // One entry of a 1-D factor column at offset dx = X_i - x_m from the atom: the collocated
@@ -201,37 +189,35 @@ struct OpGauss {              // element (k = grid row i, m = column c) = g_c(X_
   int K, d, n;
   double b, h;
   int dim;                           // number of columns
-  double x_[8], t2_[8], s_[8];
+  double x_, t2_, s_;
+  template <int W> static constexpr int regs() { return 8; }
   __device__ void setup(int m0) {
-    const int c = (threadIdx.x & 7) * 8;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int col = m0 + c + j;
-      if (col < dim) {
-        x_[j] = pos[3 * (col / K) + d];
-        t2_[j] = t2[col % K];
-        s_[j] = inv_nu[col];
-      } else {
-        x_[j] = 0.0; t2_[j] = 0.0; s_[j] = 0.0;
-      }
+    const int col = m0 + (threadIdx.x & 63);
+    if (col < dim) {
+      x_ = pos[3 * (col / K) + d];
+      t2_ = t2[col % K];
+      s_ = inv_nu[col];
+    } else {
+      x_ = 0.0; t2_ = 0.0; s_ = 0.0;
     }
   }
-  __device__ void load(double* v, int64_t k0, int64_t k1, int m0) const {
-    const int t = threadIdx.x, kk = t >> 3;
-    const int64_t i = k0 + kk;
-    const double X = -b + (double)(i + 1) * h;
+  template <int W>
+  __device__ void fetch(double* r, int, int64_t kb, int64_t) const {
+    static_assert(W == TM, "generated operands fill 64-wide stages");
+    const int kq = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const double dx = X - x_[j];
-      v[j] = (i < k1) ? gauss_entry(t2_[j], dx, h, GAL ? 1 : 0) * s_[j] : 0.0;
+      const double X = -b + (double)(kb + kq + 4 * j + 1) * h;
+      r[j] = gauss_entry(t2_, X - x_, h, GAL ? 1 : 0) * s_;
     }
   }
-  __device__ void store(double* s, int sld, const double* v) const { store_km(s, sld, v); }
-  __device__ void fill(double* s, int sld, int64_t k0, int64_t k1, int m0) const {
-    double v[8];
-    load(v, k0, k1, m0);
-    store(s, sld, v);
+  template <int W>
+  __device__ void store(double* s, const double* r, int, int64_t kb, int64_t k1) const {
+    const int mm = threadIdx.x & 63, kq = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[(kq + 4 * j) * LDT + mm] = (kb + kq + 4 * j < k1) ? r[j] : 0.0;
   }
+  static __device__ double at(const double* s, int k, int m) { return s[k * LDT + m]; }
 };
 
 // ----------------------------------------------------------------- rank reduction of explicit factors
@@ -297,8 +283,8 @@ struct GemmShape {
 
 template <class AOp, class BOp>
 __global__ __launch_bounds__(256) void k_gemm(AOp A, BOp B, const GemmShape g) {
-  __shared__ double sA[TK * LDT];
-  __shared__ double sB[TK * LDT];
+  __shared__ double sA[kStage];
+  __shared__ double sB[kStage];
   int bm, bn;
   if (g.tri) {
     int idx = blockIdx.x, row = 0, len = g.tiles_n;
@@ -322,26 +308,24 @@ __global__ __launch_bounds__(256) void k_gemm(AOp A, BOp B, const GemmShape g) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
-  // the next stage is loaded into registers while the matrix cores work on this one
-  double va[8], vb[8];
+  double ra[AOp::template regs<TM>()], rb[BOp::template regs<TN>()];
   if (k0 < k1) {
-    A.load(va, k0, k1, m0);
-    B.load(vb, k0, k1, n0);
+    A.template fetch<TM>(ra, m0, k0, k1);
+    B.template fetch<TN>(rb, n0, k0, k1);
   }
   for (int64_t kb = k0; kb < k1; kb += TK) {
-    A.store(sA, LDT, va);
-    B.store(sB, LDT, vb);
+    A.template store<TM>(sA, ra, m0, kb, k1);
+    B.template store<TN>(sB, rb, n0, kb, k1);
     __syncthreads();
-    if (kb + TK < k1) {
-      A.load(va, kb + TK, k1, m0);
-      B.load(vb, kb + TK, k1, n0);
-    }
+    // the next stage (after the last one: rows clamped to k1 - 1, never stored)
+    A.template fetch<TM>(ra, m0, kb + TK, k1);
+    B.template fetch<TN>(rb, n0, kb + TK, k1);
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
-      const double a0 = sA[(kk + lk) * LDT + wm + lr];
-      const double a1 = sA[(kk + lk) * LDT + wm + 16 + lr];
-      const double b0 = sB[(kk + lk) * LDT + wn + lr];
-      const double b1 = sB[(kk + lk) * LDT + wn + 16 + lr];
+      const double a0 = AOp::at(sA, kk + lk, wm + lr);
+      const double a1 = AOp::at(sA, kk + lk, wm + 16 + lr);
+      const double b0 = BOp::at(sB, kk + lk, wn + lr);
+      const double b1 = BOp::at(sB, kk + lk, wn + 16 + lr);
       acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
@@ -370,47 +354,53 @@ __global__ __launch_bounds__(256) void k_gemm(AOp A, BOp B, const GemmShape g) {
 // is not split over two 64-column tiles of which the second is mostly padding, and an A tile
 // that is generated rather than loaded (the Gaussians) is made once instead of once per
 // column tile.  Each output element sums the same products in the same order as k_gemm.
-constexpr int TNW = 80;
-constexpr int LDTW = 2 * TN + 4;   // B tile: two 64-column fills, padded
+// Workgroups per compute unit the wide product is compiled for: three for the two large
+// contractions of the build (projection, Tucker core), whose registers fit in a third of the
+// file; two elsewhere, where the wider fetches would otherwise spill.
+template <class AOp, class BOp>
+struct WideOcc {
+  static constexpr int value = 2;
+};
+template <>
+struct WideOcc<OpGauss<false>, OpKM> {
+  static constexpr int value = 3;
+};
+template <>
+struct WideOcc<OpKhatriRao, OpKM> {
+  static constexpr int value = 3;
+};
 
 template <class AOp, class BOp>
-__global__ __launch_bounds__(256, 3) void k_gemm_w(AOp A, BOp B, const GemmShape g) {
-  __shared__ double sA[TK * LDT];
-  __shared__ double sB[TK * LDTW];
+__global__ __launch_bounds__(256, (WideOcc<AOp, BOp>::value)) void k_gemm_w(AOp A, BOp B, const GemmShape g) {
+  __shared__ double sA[kStage];
+  __shared__ double sB[kStage];
   const int m0 = blockIdx.x * TM;
   const int64_t k0 = (int64_t)blockIdx.z * g.kper;
   const int64_t k1 = min(g.K, k0 + g.kper);
-  BOp B1 = B;
   A.setup(m0);
   B.setup(0);
-  B1.setup(TN);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   d4v acc[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) acc[j] = d4v{0.0, 0.0, 0.0, 0.0};
-  double va[8], vb[8], vb1[8];
+  double ra[AOp::template regs<TM>()], rb[BOp::template regs<TNW>()];
   if (k0 < k1) {
-    A.load(va, k0, k1, m0);
-    B.load(vb, k0, k1, 0);
-    B1.load(vb1, k0, k1, TN);
+    A.template fetch<TM>(ra, m0, k0, k1);
+    B.template fetch<TNW>(rb, 0, k0, k1);
   }
   for (int64_t kb = k0; kb < k1; kb += TK) {
-    A.store(sA, LDT, va);
-    B.store(sB, LDTW, vb);
-    B1.store(sB + TN, LDTW, vb1);
+    A.template store<TM>(sA, ra, m0, kb, k1);
+    B.template store<TNW>(sB, rb, 0, kb, k1);
     __syncthreads();
-    if (kb + TK < k1) {
-      A.load(va, kb + TK, k1, m0);
-      B.load(vb, kb + TK, k1, 0);
-      B1.load(vb1, kb + TK, k1, TN);
-    }
+    A.template fetch<TM>(ra, m0, kb + TK, k1);
+    B.template fetch<TNW>(rb, 0, kb + TK, k1);
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
-      const double a = sA[(kk + lk) * LDT + 16 * w + lr];
+      const double a = AOp::at(sA, kk + lk, 16 * w + lr);
 #pragma unroll
       for (int j = 0; j < 5; ++j)
-        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sB[(kk + lk) * LDTW + 16 * j + lr], acc[j], 0, 0, 0);
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, BOp::at(sB, kk + lk, 16 * j + lr), acc[j], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -426,6 +416,16 @@ __global__ __launch_bounds__(256, 3) void k_gemm_w(AOp A, BOp B, const GemmShape
         *c = g.accumulate ? *c + acc[j][v] : acc[j][v];
       }
     }
+}
+
+// Rows of a row-major matrix scaled in place: p[r * ld + c] *= scale[r] for c < cols.
+__global__ void k_scale_rows(double* __restrict__ p, int64_t ld, int64_t rows, int cols,
+                             const double* __restrict__ scale) {
+  const int64_t total = rows * ld;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / ld;
+    if (e - r * ld < cols) p[e] = p[e] * scale[r];
+  }
 }
 
 // Sum split slices: out[m*ldo + n] = sum_s part[s*stride + m*ldp + n].
@@ -961,6 +961,41 @@ struct ScratchScope {
 inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 inline unsigned grid1d(int64_t total) { return (unsigned)std::min<int64_t>(std::max<int64_t>(1, (total + 255) / 256), 65536); }
 
+// Issues f(d, stream) for the three modes d on the context stream and the two auxiliary
+// streams, each after the work already queued on the context stream, with the context stream
+// current while f(d) issues; the context stream then waits for all three (also when an f fails).
+// With per-launch timing on, all three go to the context stream, so that each launch's events
+// time that launch alone.
+template <class F>
+rsd_status on_three_streams(Context* ctx, F&& f) {
+  const hipStream_t main = ctx->stream;
+  RSD_TRY(ctx->aux_streams());
+  const bool serial = ctx->timing;
+  const hipStream_t st[3] = {main, serial ? main : ctx->aux_stream[0], serial ? main : ctx->aux_stream[1]};
+  struct Events {
+    hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+    ~Events() {
+      for (auto x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  for (auto& x : ev.e) RSD_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+  RSD_HIP(hipEventRecord(ev.e[0], main));
+  RSD_HIP(hipStreamWaitEvent(st[1], ev.e[0], 0));
+  RSD_HIP(hipStreamWaitEvent(st[2], ev.e[0], 0));
+  rsd_status rs = RSD_OK;
+  for (int d = 0; d < 3 && rs == RSD_OK; ++d) {
+    ctx->stream = st[d];
+    rs = f(d, st[d]);
+    ctx->stream = main;
+  }
+  for (int i = 1; i < 3; ++i) {
+    RSD_HIP(hipEventRecord(ev.e[i], st[i]));
+    RSD_HIP(hipStreamWaitEvent(main, ev.e[i], 0));
+  }
+  return rs;
+}
+
 template <class AOp, class BOp>
 rsd_status gemm(Context* ctx, const char* name, const AOp& A, const BOp& B, GemmShape g, int splits) {
   dim3 grid;
@@ -1102,7 +1137,7 @@ rsd_status subspace_eigvecs3(Context* ctx, rocblas_handle hb, double* G3, int n,
     int k = 0;
     bool finished = false;
     bool lib = false;          // orthonormalize with rocSOLVER's Householder QR
-    DevBuf Om, Y, Z, T, W, E, tau, Q, flag;
+    DevBuf Om, Y, Z, T, W, E, tau, Q, flag, part;
     OrthBufs ob;
   } m[3];
   RSD_TRY(allow_small_lds());
@@ -1130,6 +1165,11 @@ rsd_status subspace_eigvecs3(Context* ctx, rocblas_handle hb, double* G3, int n,
         RSD_TRY(md.W.alloc(ctx, k));
         RSD_TRY(md.E.alloc(ctx, k));
         RSD_TRY(md.tau.alloc(ctx, k));
+        // the k x n and k x k products have only 2 x (n / 64) and 4 output tiles: their
+        // contraction over n is split for about 256 workgroups, and the slices summed
+        const int sp_kn = std::max(1, std::min(n / 256, div_up(256, div_up(k, TM) * div_up(n, TN))));
+        const int sp_kk = std::max(1, std::min(n / 64, div_up(256, div_up(k, TM) * div_up(k, TN))));
+        RSD_TRY(md.part.alloc(ctx, std::max((size_t)sp_kn * k * n, (size_t)sp_kk * k * k)));
         double* G = G3 + d * nn;
         RSD_TIMED_LAUNCH(ctx, "eig", (k_random_fill<<<grid1d((int64_t)n * k), 256, 0, st[d]>>>(
                                          md.Om.p, (int64_t)n * k, 0x5EEDull + (uint64_t)d)));
@@ -1159,33 +1199,38 @@ rsd_status subspace_eigvecs3(Context* ctx, rocblas_handle hb, double* G3, int n,
           if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
           return RSD_OK;
         };
-        GemmShape g{};
-        g.split_stride = 0; g.accumulate = 0; g.tri = 0;
         // Y^T = Omega^T G  (k x n row-major = n x k column-major)
-        g.M = k; g.N = n; g.K = n; g.kper = ((int64_t)n + TK - 1) / TK * TK; g.C = md.Y.p; g.ldc = n;
-        RSD_TRY(gemm(ctx, "eig", OpKM{md.Om.p, k, k}, OpKM{G, n, n}, g, 1));
+        RSD_TRY(gemm_split(ctx, OpKM{md.Om.p, k, k}, OpKM{G, n, n}, k, n, n, md.part.p, sp_kn, md.Y.p));
         RSD_TRY(qr(md.Y, false));
         // one power step: Z^T = Q^T G, orthonormalise
-        g.C = md.Z.p;
-        RSD_TRY(gemm(ctx, "eig", OpMK{md.Y.p, n, k}, OpKM{G, n, n}, g, 1));
+        RSD_TRY(gemm_split(ctx, OpMK{md.Y.p, n, k}, OpKM{G, n, n}, k, n, n, md.part.p, sp_kn, md.Z.p));
         RSD_TRY(qr(md.Z, true));
         // Rayleigh-Ritz: Y^T = Q^T G (k x n), T = Q^T G Q (k x k)
-        g.C = md.Y.p;
-        RSD_TRY(gemm(ctx, "eig", OpMK{md.Z.p, n, k}, OpKM{G, n, n}, g, 1));
-        GemmShape gt = g;
-        gt.M = k; gt.N = k; gt.K = n; gt.C = md.T.p; gt.ldc = k;
-        RSD_TRY(gemm(ctx, "eig", OpMK{md.Z.p, n, k}, OpMK{md.Y.p, n, k}, gt, 1));
-        KernelTimer kt;
-        if (ctx->timing) RSD_TRY(ctx->timer_begin("eig", &kt));
-        const rocblas_status rs = rocsolver_dsyevd(hbs[d], rocblas_evect_original, rocblas_fill_upper, k, md.T.p, k,
-                                                   md.W.p, md.E.p, d_info + d);
-        RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dsyevd failed (%d)", (int)rs);
-        if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+        RSD_TRY(gemm_split(ctx, OpMK{md.Z.p, n, k}, OpKM{G, n, n}, k, n, n, md.part.p, sp_kn, md.Y.p));
+        RSD_TRY(gemm_split(ctx, OpMK{md.Z.p, n, k}, OpMK{md.Y.p, n, k}, k, k, n, md.part.p, sp_kk, md.T.p));
         return RSD_OK;
       };
       st_all = issue();
       ctx->stream = main;
       if (st_all != RSD_OK) break;
+    }
+    // the small eigensolver calls last: a call may wait on the host for its own stream, and
+    // the other modes' products are queued by then
+    for (int d = 0; d < 3 && any && st_all == RSD_OK; ++d) {
+      Mode& md = m[d];
+      if (md.finished) continue;
+      ctx->stream = st[d];
+      auto eig = [&]() -> rsd_status {
+        KernelTimer kt;
+        if (ctx->timing) RSD_TRY(ctx->timer_begin("eig", &kt));
+        const rocblas_status rs = rocsolver_dsyevd(hbs[d], rocblas_evect_original, rocblas_fill_upper, md.k, md.T.p,
+                                                   md.k, md.W.p, md.E.p, d_info + d);
+        RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dsyevd failed (%d)", (int)rs);
+        if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+        return RSD_OK;
+      };
+      st_all = eig();
+      ctx->stream = main;
     }
     if (!any || st_all != RSD_OK) break;
     // read every unfinished mode's Ritz values; finish the modes whose subspace was large enough
@@ -1285,8 +1330,11 @@ rsd_status tucker_canonical(Context* ctx, Tensor* t, DevBuf Bt[3], DevBuf U[3], 
   DevBuf Cpart, beta;
   RSD_TRY(Cpart.alloc(ctx, (size_t)csplit * M12 * r[2]));
   RSD_TRY(beta.alloc(ctx, (size_t)M12 * r[2]));
-  OpKhatriRao kr{Bt[0].p, Bt[1].p, ldu[0], ldu[1], r[1], M12, {}, {}};
-  OpKMScaled b3{Bt[2].p, xi, ldu[2], r[2]};
+  OpKhatriRao kr{Bt[0].p, Bt[1].p, ldu[0], ldu[1], r[1], M12, 0, 0};
+  // the weights go into the mode-3 side matrix (each entry the same rounded product the
+  // contraction would form), which is not read again
+  RSD_TIMED_LAUNCH(ctx, "core", (k_scale_rows<<<grid1d(C * ldu[2]), 256, 0, s>>>(Bt[2].p, ldu[2], C, r[2], xi)));
+  OpKM b3{Bt[2].p, ldu[2], r[2]};
   {
     GemmShape g{};
     g.M = M12; g.N = r[2]; g.K = C;
@@ -1722,7 +1770,7 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
     RSD_TRY(Gpart.alloc(ctx, (size_t)gsplit * nn));
   } else {
     RSD_TRY(Ttab.alloc(ctx, (size_t)K * n));
-    RSD_TRY(Htab.alloc(ctx, (size_t)K * (2 * (size_t)n - 1)));
+    RSD_TRY(Htab.alloc(ctx, 3 * (size_t)K * (2 * (size_t)n - 1)));
   }
   RSD_TRY(W3.alloc(ctx, 3 * (size_t)n));
   RSD_TRY(E3.alloc(ctx, 3 * (size_t)n));
@@ -1736,17 +1784,24 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
   // 1. column norms and the Gram matrix of every mode, chunk by chunk
   if (!dense_gram)
     RSD_TIMED_LAUNCH(ctx, "gram", (k_gram_toeplitz<<<grid1d((int64_t)K * n), 256, 0, s>>>(t2d.p, K, n, h, Ttab.p)));
-  for (int d = 0; d < 3; ++d) {
+  if (!dense_gram) {
+    // the modes are independent, and the Hankel sums of one mode fill only a few hundred
+    // workgroups: the three run side by side
+    RSD_TRY(on_three_streams(ctx, [&](int d, hipStream_t sd) -> rsd_status {
+      RSD_TIMED_LAUNCH(ctx, "gen", (k_col_norms<<<div_up(C, 4), 256, 0, sd>>>(d_pos, t2d.p, K, d, n, b, h, 0, C,
+                                                                                nu[d].p, inv_nu[d].p, gal)));
+      double* Hd = Htab.p + (size_t)d * K * (2 * (size_t)n - 1);
+      const dim3 gh((unsigned)div_up(2 * (int64_t)n - 1, 256), (unsigned)K);
+      RSD_TIMED_LAUNCH(ctx, "gram", (k_gram_hankel<<<gh, 256, 0, sd>>>(d_pos, t2d.p, inv_nu[d].p, K, d, n, b, h, N,
+                                                                       Hd)));
+      const dim3 ga((unsigned)Tn, (unsigned)Tn);
+      RSD_TIMED_LAUNCH(ctx, "gram", (k_gram_assemble<<<ga, 256, 0, sd>>>(Ttab.p, Hd, K, n, G3.p + d * nn)));
+      return RSD_OK;
+    }));
+  }
+  for (int d = 0; d < 3 && dense_gram; ++d) {
     RSD_TIMED_LAUNCH(ctx, "gen", (k_col_norms<<<div_up(C, 4), 256, 0, s>>>(d_pos, t2d.p, K, d, n, b, h, 0, C,
                                                                              nu[d].p, inv_nu[d].p, gal)));
-    if (!dense_gram) {
-      const dim3 gh((unsigned)div_up(2 * (int64_t)n - 1, 256), (unsigned)K);
-      RSD_TIMED_LAUNCH(ctx, "gram", (k_gram_hankel<<<gh, 256, 0, s>>>(d_pos, t2d.p, inv_nu[d].p, K, d, n, b, h, N,
-                                                                      Htab.p)));
-      const dim3 ga((unsigned)Tn, (unsigned)Tn);
-      RSD_TIMED_LAUNCH(ctx, "gram", (k_gram_assemble<<<ga, 256, 0, s>>>(Ttab.p, Htab.p, K, n, G3.p + d * nn)));
-      continue;
-    }
     RSD_HIP(hipMemsetAsync(Gpart.p, 0, Gpart.bytes, s));
     for (int64_t c0 = 0; c0 < C; c0 += chunk_cols) {
       const int64_t c1 = std::min(C, c0 + chunk_cols);
@@ -1779,8 +1834,8 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
     RSD_HIP(hipMemcpy(lam3.data(), W3.p, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
   }
   if (subspace) RSD_TRY(subspace_eigvecs3(ctx, hb, G3.p, n, eps, d_info, U, r, ldu));
-  for (int d = 0; d < 3; ++d) {
-    if (!subspace) {
+  for (int d = 0; d < 3 && !subspace; ++d) {
+    {
       const double* lam = lam3.data() + (size_t)d * n;
       const double lmax = lam[n - 1];
       RSD_CHECK(lmax > 0.0 && std::isfinite(lmax), RSD_E_NUMERIC, "Gram matrix of mode %d has no positive eigenvalue",
@@ -1794,8 +1849,11 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
       RSD_TIMED_LAUNCH(ctx, "eig", (k_take_eigvecs<<<grid1d((int64_t)n * ldu[d]), 256, 0, s>>>(G3.p + d * nn, n, rd,
                                                                                               U[d].p, ldu[d])));
     }
+  }
+  // 3. projections B_d^T[c][a] = sum_i A(i, c) U[i][a], side-matrix columns regenerated in LDS;
+  //    the three modes side by side, so that the last wave of workgroups of one overlaps the next
+  RSD_TRY(on_three_streams(ctx, [&](int d, hipStream_t) -> rsd_status {
     const int rd = r[d];
-    // 3. projection B_d^T[c][a] = sum_i A(i, c) U[i][a], side-matrix columns regenerated in LDS
     RSD_TRY(Bt[d].alloc(ctx, (size_t)C * ldu[d]));
     auto project = [&](auto ga) -> rsd_status {
       ga.pos = d_pos; ga.t2 = t2d.p; ga.inv_nu = inv_nu[d].p; ga.K = K; ga.d = d; ga.n = n; ga.b = b; ga.h = h;
@@ -1806,8 +1864,8 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
       g.C = Bt[d].p; g.ldc = ldu[d]; g.split_stride = 0; g.accumulate = 0; g.tri = 0;
       return gemm(ctx, "project", ga, ub, g, 1);
     };
-    RSD_TRY(gal ? project(OpGauss<true>{}) : project(OpGauss<false>{}));
-  }
+    return gal ? project(OpGauss<true>{}) : project(OpGauss<false>{});
+  }));
   t->ranks[0] = r[0];
   t->ranks[1] = r[1];
   t->ranks[2] = r[2];
