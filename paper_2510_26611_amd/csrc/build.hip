@@ -279,6 +279,8 @@ struct GemmShape {
   int accumulate;             // add into C instead of overwriting
   int tri;                    // enumerate only tiles with m-block <= n-block
   int tiles_n;                // number of n tiles (for tri)
+  int64_t chunk_rows;         // nonzero: C is in the factors' chunked layout, element (m, n) at
+                              // C[((n / kChunk) * chunk_rows + m) * kChunk + n % kChunk]
 };
 
 template <class AOp, class BOp>
@@ -343,7 +345,8 @@ __global__ __launch_bounds__(256) void k_gemm(AOp A, BOp B, const GemmShape g) {
         const int m = m0 + wm + 16 * i + 4 * v + lk;
         const int n = n0 + wn + 16 * j + lr;
         if (m < g.M && n < g.N) {
-          double* c = C + (int64_t)m * g.ldc + n;
+          double* c = g.chunk_rows ? C + ((int64_t)(n / kChunk) * g.chunk_rows + m) * kChunk + n % kChunk
+                                   : C + (int64_t)m * g.ldc + n;
           *c = g.accumulate ? *c + acc[i][j][v] : acc[i][j][v];
         }
       }
@@ -412,7 +415,8 @@ __global__ __launch_bounds__(256, (WideOcc<AOp, BOp>::value)) void k_gemm_w(AOp 
       const int m = m0 + 16 * w + 4 * v + lk;
       const int n = 16 * j + lr;
       if (m < g.M && n < g.N) {
-        double* c = C + (int64_t)m * g.ldc + n;
+        double* c = g.chunk_rows ? C + ((int64_t)(n / kChunk) * g.chunk_rows + m) * kChunk + n % kChunk
+                                 : C + (int64_t)m * g.ldc + n;
         *c = g.accumulate ? *c + acc[j][v] : acc[j][v];
       }
     }
@@ -801,28 +805,101 @@ __global__ void k_core_slices(const double* __restrict__ beta, int r1, int r2, i
   }
 }
 
-// F[chunk][i][j] = sum_a U[i * ldu + a] * V[a * R + p] with p = chunk * kChunk + j (zero for p >= R
-// and for layout rows i >= rows, the rows U has).
-__global__ void k_assemble(const double* __restrict__ U, int ldu, int r, const double* __restrict__ V, int64_t R,
-                           int n, int rows, int nchunk, double* __restrict__ F) {
-  const int64_t total = (int64_t)nchunk * n * kChunk;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int j = (int)(e % kChunk);
-    const int64_t rest = e / kChunk;
-    const int i = (int)(rest % n);
-    const int64_t p = (rest / n) * kChunk + j;
-    double s = 0.0;
-    if (p < R && i < rows) {   // U has `rows` rows; the layout's rows beyond them stay zero
-      const double* u = U + (int64_t)i * ldu;
-      for (int a = 0; a < r; ++a) s = fma(u[a], V[(int64_t)a * R + p], s);
+// Kept canonical terms of the slice SVDs, chosen on the device: term (c, q) is kept when
+// sv[c * ns + q] >= eps * (the largest over all slices) and > 0, and the kept terms are numbered
+// p = 0, 1, ... in (c, q) order.  One workgroup: pos[c * ns + q] = p or -1, slice[p] = c,
+// out[0] = R and out[1] = the number of kChunk-column chunks whose columns come from fewer than
+// kSharedSlots slices (the chunks the scoring kernels serve from U_3).
+constexpr int kSelThreads = 1024;
+__global__ __launch_bounds__(kSelThreads) void k_t2c_select(const double* __restrict__ sv, int total, int ns,
+                                                            double eps, int* __restrict__ pos,
+                                                            int* __restrict__ slice, int* __restrict__ out) {
+  __shared__ double s_max[kSelThreads / 64];
+  __shared__ int s_scan[2][kSelThreads];
+  __shared__ int s_u3[kSelThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double mx = 0.0;
+  for (int e = tid; e < total; e += kSelThreads) mx = fmax(mx, sv[e]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if (lane == 0) s_max[wv] = mx;
+  __syncthreads();
+  double smax = 0.0;
+  for (int w = 0; w < kSelThreads / 64; ++w) smax = fmax(smax, s_max[w]);
+  const double cut = eps * smax;
+  // each thread takes a contiguous run of the (c, q) order
+  const int per = (total + kSelThreads - 1) / kSelThreads;
+  const int e0 = min(total, tid * per), e1 = min(total, e0 + per);
+  int cnt = 0;
+  for (int e = e0; e < e1; ++e) cnt += (sv[e] >= cut && sv[e] > 0.0) ? 1 : 0;
+  // inclusive scan of the counts (Hillis-Steele, two LDS buffers)
+  int cur = 0;
+  s_scan[0][tid] = cnt;
+  __syncthreads();
+  for (int off = 1; off < kSelThreads; off <<= 1) {
+    const int v = s_scan[cur][tid] + (tid >= off ? s_scan[cur][tid - off] : 0);
+    s_scan[cur ^ 1][tid] = v;
+    cur ^= 1;
+    __syncthreads();
+  }
+  int p = s_scan[cur][tid] - cnt;
+  for (int e = e0; e < e1; ++e) {
+    if (sv[e] >= cut && sv[e] > 0.0) {
+      pos[e] = p;
+      slice[p] = e / ns;
+      ++p;
+    } else {
+      pos[e] = -1;
     }
-    F[e] = s;
+  }
+  const int R = s_scan[cur][kSelThreads - 1];
+  __syncthreads();   // slice[] is complete
+  const int nchunk = (R + kChunk - 1) / kChunk;
+  int u3 = 0;
+  for (int ch = tid; ch < nchunk; ch += kSelThreads) {
+    const int p0 = ch * kChunk, p1 = min(R, p0 + kChunk) - 1;
+    u3 += (slice[p1] - slice[p0] < kSharedSlots) ? 1 : 0;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) u3 += __shfl_xor(u3, off, 64);
+  if (lane == 0) s_u3[wv] = u3;
+  __syncthreads();
+  if (tid == 0) {
+    int t3 = 0;
+    for (int w = 0; w < kSelThreads / 64; ++w) t3 += s_u3[w];
+    out[0] = R;
+    out[1] = t3;
+  }
+}
+
+// The kept terms as columns p of V_1 (r1 x R: s_q u_q), V_2 (r2 x R: v_q) and V_3 (r3 x R: e_c),
+// from the slice SVDs in the layout sv[c*ns + q], uv[c*r1*ns + q*r1 + a], vv[c*ns*r2 + b*ns + q].
+__global__ void k_t2c_factors(const double* __restrict__ sv, const double* __restrict__ uv,
+                              const double* __restrict__ vv, const int* __restrict__ pos, int total, int ns,
+                              int r1, int r2, int r3, int64_t R, double* __restrict__ V1, double* __restrict__ V2,
+                              double* __restrict__ V3) {
+  const int rows = r1 + r2 + r3;
+  const int64_t work = (int64_t)total * rows;
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < work; w += (int64_t)gridDim.x * blockDim.x) {
+    const int e = (int)(w / rows), row = (int)(w - (int64_t)e * rows);
+    const int64_t p = pos[e];
+    if (p < 0) continue;
+    const int c = e / ns, q = e - c * ns;
+    if (row < r1) {
+      V1[(int64_t)row * R + p] = sv[e] * uv[((int64_t)c * ns + q) * r1 + row];
+    } else if (row < r1 + r2) {
+      const int b = row - r1;
+      V2[(int64_t)b * R + p] = vv[((int64_t)c * r2 + b) * ns + q];
+    } else {
+      const int c3 = row - r1 - r2;
+      V3[(int64_t)c3 * R + p] = c3 == c ? 1.0 : 0.0;
+    }
   }
 }
 
 // One-sided (Hestenes) Jacobi SVD of the mode-3 slices of the core, one workgroup per
 // slice held in LDS.  Column pairs are orthogonalised in the round-robin order (n/2
-// disjoint pairs per round, one wavefront per pair); a sweep is n-1 rounds; sweeps
+// disjoint pairs per round, eight lanes per pair); a sweep is n-1 rounds; sweeps
 // stop when no pair needed a rotation.  Then column q of the rotated slice is
 // s_q u_q, and v_q = S^T u_q / s_q is taken from the original slice (v_q enters the
 // tensor only multiplied by s_q, so the division loses nothing that matters).
@@ -835,17 +912,22 @@ __device__ __forceinline__ int rr_player(int pos, int round, int np) {
   return pos == 0 ? 0 : 1 + (pos - 1 + round) % (np - 1);
 }
 
-__global__ __launch_bounds__(256) void k_jacobi_svd(const double* __restrict__ S, int m, int n, double skip_rel2,
-                                                    double* __restrict__ sv, double* __restrict__ uv,
-                                                    double* __restrict__ vt, int* __restrict__ sweeps) {
+constexpr int kJacobiThreads = 512;   // eight lanes per column pair, up to 64 pairs per round
+constexpr int kJacobiLanes = 8;
+
+__global__ __launch_bounds__(kJacobiThreads) void k_jacobi_svd(const double* __restrict__ S, int m, int n,
+                                                               double skip_rel2, double* __restrict__ sv,
+                                                               double* __restrict__ uv, double* __restrict__ vt,
+                                                               int* __restrict__ sweeps) {
   extern __shared__ double sA[];
+  constexpr int kWaves = kJacobiThreads / 64;
   __shared__ int s_rot;
-  __shared__ double s_part[4];
+  __shared__ double s_part[kWaves];
   const int c = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double* Sc = S + (int64_t)c * m * n;
   double fro = 0.0;
-  for (int e = tid; e < m * n; e += 256) {
+  for (int e = tid; e < m * n; e += kJacobiThreads) {
     const double x = Sc[e];
     sA[e] = x;
     fro = fma(x, x, fro);
@@ -854,9 +936,12 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* __restrict__ S
   for (int off = 32; off > 0; off >>= 1) fro += __shfl_xor(fro, off, 64);
   if (lane == 0) s_part[wv] = fro;
   __syncthreads();
+  double fro_all = 0.0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) fro_all += s_part[w];
   // columns below sqrt(skip_rel2) of the slice norm hold nothing above the truncation level;
   // pairs involving them are left alone (rotating them only churns rounding noise)
-  const double skip = skip_rel2 * (s_part[0] + s_part[1] + s_part[2] + s_part[3]);
+  const double skip = skip_rel2 * fro_all;
   const int np = n + (n & 1);
   // rotate a pair only when its cosine exceeds the rounding level of an m-term dot product
   const double tol = fmax(1e-14, 4.0 * m * 1.1102230246251565e-16);
@@ -864,37 +949,37 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* __restrict__ S
   for (; sweep < kJacobiMaxSweeps && n > 1; ++sweep) {
     if (tid == 0) s_rot = 0;
     __syncthreads();
-    // four lanes per column pair, each over every fourth row (loads unrolled so that several
-    // are in flight), the three sums combined within the quad: a 64-lane reduction per pair
+    // eight lanes per column pair, each over every eighth row (loads unrolled so that several
+    // are in flight), the three sums combined within the group: a 64-lane reduction per pair
     // or one lane per pair leaves each round waiting on LDS latency
     for (int round = 0; round < np - 1; ++round) {
-      for (int k4 = tid; k4 < (np / 2) * 4; k4 += 256) {
-        const int k = k4 >> 2, part = k4 & 3;
+      for (int k8 = tid; k8 < (np / 2) * kJacobiLanes; k8 += kJacobiThreads) {
+        const int k = k8 / kJacobiLanes, part = k8 % kJacobiLanes;
         const int pa = rr_player(k, round, np), pb = rr_player(np - 1 - k, round, np);
         const int p = min(pa, pb), q = max(pa, pb);
         if (q >= n) continue;
         double* ap = sA + p * m;
         double* aq = sA + q * m;
         double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll 8
-        for (int row = part; row < m; row += 4) {
+#pragma unroll 4
+        for (int row = part; row < m; row += kJacobiLanes) {
           const double x = ap[row], y = aq[row];
           al = fma(x, x, al);
           be = fma(y, y, be);
           ga = fma(x, y, ga);
         }
-        al += __shfl_xor(al, 1, 64);
-        be += __shfl_xor(be, 1, 64);
-        ga += __shfl_xor(ga, 1, 64);
-        al += __shfl_xor(al, 2, 64);
-        be += __shfl_xor(be, 2, 64);
-        ga += __shfl_xor(ga, 2, 64);
+#pragma unroll
+        for (int off = 1; off < kJacobiLanes; off <<= 1) {
+          al += __shfl_xor(al, off, 64);
+          be += __shfl_xor(be, off, 64);
+          ga += __shfl_xor(ga, off, 64);
+        }
         if (ga != 0.0 && fmin(al, be) > skip && fabs(ga) > tol * sqrt(al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-#pragma unroll 8
-          for (int row = part; row < m; row += 4) {
+#pragma unroll 4
+          for (int row = part; row < m; row += kJacobiLanes) {
             const double x = ap[row], y = aq[row];
             ap[row] = cs * x - sn * y;
             aq[row] = sn * x + cs * y;
@@ -910,7 +995,7 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* __restrict__ S
   }
   if (tid == 0) sweeps[c] = sweep;
   // singular values and normalised left vectors
-  for (int q = wv; q < n; q += 4) {
+  for (int q = wv; q < n; q += kWaves) {
     double s2 = 0.0;
     for (int row = lane; row < m; row += 64) s2 = fma(sA[q * m + row], sA[q * m + row], s2);
 #pragma unroll
@@ -926,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const double* __restrict__ S
   }
   __syncthreads();
   // v_q = S^T u_q / s_q
-  for (int e = tid; e < n * n; e += 256) {
+  for (int e = tid; e < n * n; e += kJacobiThreads) {
     const int q = e % n, bcol = e / n;
     const double* scol = Sc + (int64_t)bcol * m;
     const double* u = sA + q * m;
@@ -1363,13 +1448,8 @@ rsd_status tucker_canonical(Context* ctx, Tensor* t, DevBuf Bt[3], DevBuf U[3], 
     RSD_HIP(hipFuncSetAttribute((const void*)k_jacobi_svd, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(sizeof(double) * (size_t)r1 * r2)));
     const double skip_rel2 = std::max(1e-3 * eps * 1e-3 * eps, 1e-30);
-    RSD_TIMED_LAUNCH(ctx, "t2c", (k_jacobi_svd<<<r3, 256, sizeof(double) * (size_t)r1 * r2, s>>>(
+    RSD_TIMED_LAUNCH(ctx, "t2c", (k_jacobi_svd<<<r3, kJacobiThreads, sizeof(double) * (size_t)r1 * r2, s>>>(
                                      S.p, r1, r2, skip_rel2, Sv.p, Uv.p, Vv.p, (int*)d_info)));
-    std::vector<int> sw((size_t)r3);
-    RSD_HIP(hipMemcpyAsync(sw.data(), d_info, sizeof(int) * r3, hipMemcpyDeviceToHost, s));
-    RSD_HIP(hipStreamSynchronize(s));
-    for (int c = 0; c < r3; ++c)
-      RSD_CHECK(sw[c] < kJacobiMaxSweeps, RSD_E_NUMERIC, "Jacobi SVD of core slice %d did not converge", c);
   } else {
     KernelTimer kt;
     if (ctx->timing) RSD_TRY(ctx->timer_begin("t2c", &kt));
@@ -1379,57 +1459,55 @@ rsd_status tucker_canonical(Context* ctx, Tensor* t, DevBuf Bt[3], DevBuf U[3], 
         (rocblas_stride)ns, rocblas_outofplace, d_info, r3);
     RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocsolver_dgesvd_strided_batched failed (%d)", (int)rs);
     if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
-    RSD_TRY(check_info(ctx, d_info, r3, "slice SVD"));
   }
-  std::vector<double> sv((size_t)ns * r3), uv((size_t)r1 * ns * r3), vv((size_t)ns * r2 * r3);
-  RSD_HIP(hipMemcpy(sv.data(), Sv.p, sizeof(double) * sv.size(), hipMemcpyDeviceToHost));
-  RSD_HIP(hipMemcpy(uv.data(), Uv.p, sizeof(double) * uv.size(), hipMemcpyDeviceToHost));
-  RSD_HIP(hipMemcpy(vv.data(), Vv.p, sizeof(double) * vv.size(), hipMemcpyDeviceToHost));
-  double smax = 0.0;
-  for (double x : sv) smax = std::max(smax, x);
-  std::vector<std::pair<int, int>> kept;
-  for (int c = 0; c < r3; ++c)
-    for (int q = 0; q < ns; ++q)
-      if (sv[(size_t)c * ns + q] >= eps * smax && sv[(size_t)c * ns + q] > 0.0) kept.emplace_back(c, q);
-  const int64_t R = (int64_t)kept.size();
+  // the kept terms, chosen and numbered on the device; the host reads R, the count of chunks
+  // served from U_3 and the solver's status (Jacobi sweeps or gesvd info) in one copy
+  const int total = ns * r3;
+  DevBuf Pos, Sl, Out;
+  RSD_TRY(Pos.alloc(ctx, (size_t)total));   // ints, in double-sized scratch
+  RSD_TRY(Sl.alloc(ctx, (size_t)total));
+  RSD_TRY(Out.alloc(ctx, 1));
+  int* pos = (int*)Pos.p;
+  int* sl = (int*)Sl.p;
+  int* out2 = (int*)Out.p;
+  RSD_TIMED_LAUNCH(ctx, "assemble", (k_t2c_select<<<1, kSelThreads, 0, s>>>(Sv.p, total, ns, eps, pos, sl, out2)));
+  std::vector<int> info((size_t)r3 + 2);
+  RSD_HIP(hipMemcpyAsync(info.data(), d_info, sizeof(int) * r3, hipMemcpyDeviceToHost, s));
+  RSD_HIP(hipMemcpyAsync(info.data() + r3, out2, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+  RSD_HIP(hipStreamSynchronize(s));
+  for (int c = 0; c < r3; ++c) {
+    if (jacobi)
+      RSD_CHECK(info[c] < kJacobiMaxSweeps, RSD_E_NUMERIC, "Jacobi SVD of core slice %d did not converge", c);
+    else
+      RSD_CHECK(info[c] == 0, RSD_E_NUMERIC, "slice SVD did not converge (info %d at %d)", info[c], c);
+  }
+  const int64_t R = info[r3];
   RSD_CHECK(R <= ((int64_t)1 << 20), RSD_E_UNSUPPORTED, "canonical rank %lld too large", (long long)R);
-  // V_d (r_d x R) on the host: columns p = s*u (mode 1), v (mode 2), e_c (mode 3)
-  std::vector<double> V1((size_t)r1 * R), V2((size_t)r2 * R), V3((size_t)r3 * R, 0.0);
-  for (int64_t p = 0; p < R; ++p) {
-    const int c = kept[p].first, q = kept[p].second;
-    const double sq = sv[(size_t)c * ns + q];
-    for (int a = 0; a < r1; ++a) V1[(size_t)a * R + p] = sq * uv[(size_t)c * r1 * ns + (size_t)q * r1 + a];
-    for (int bb = 0; bb < r2; ++bb) V2[(size_t)bb * R + p] = vv[(size_t)c * ns * r2 + (size_t)bb * ns + q];
-    V3[(size_t)c * R + p] = 1.0;
-  }
   RSD_TRY(alloc_factors(ctx, t, R));
   if (R == 0) return RSD_OK;
   // keep U_3 and the column -> slice map: the scoring kernels lerp a chunk's few distinct
   // mode-3 columns once per atom instead of gathering all of them
-  {
-    std::vector<int> sl((size_t)R);
-    for (int64_t p = 0; p < R; ++p) sl[(size_t)p] = kept[(size_t)p].first;
-    t->u3_chunks = 0;
-    for (int c = 0; c < t->nchunk; ++c) {
-      const int64_t p0 = (int64_t)c * kChunk, p1 = std::min<int64_t>(R, p0 + kChunk) - 1;
-      if (sl[(size_t)p1] - sl[(size_t)p0] < kSharedSlots) ++t->u3_chunks;
-    }
-    RSD_TRY(ctx->dev_alloc((void**)&t->U3, sizeof(double) * (size_t)t->nm[2] * ldu[2]));
-    RSD_TRY(ctx->dev_alloc((void**)&t->slice, sizeof(int) * (size_t)R));
-    t->u3_ld = ldu[2];
-    RSD_HIP(hipMemcpyAsync(t->U3, U[2].p, sizeof(double) * (size_t)t->nm[2] * ldu[2], hipMemcpyDeviceToDevice, s));
-    RSD_HIP(hipMemcpy(t->slice, sl.data(), sizeof(int) * (size_t)R, hipMemcpyHostToDevice));
-  }
+  t->u3_chunks = info[r3 + 1];
+  RSD_TRY(ctx->dev_alloc((void**)&t->U3, sizeof(double) * (size_t)t->nm[2] * ldu[2]));
+  RSD_TRY(ctx->dev_alloc((void**)&t->slice, sizeof(int) * (size_t)R));
+  t->u3_ld = ldu[2];
+  RSD_HIP(hipMemcpyAsync(t->U3, U[2].p, sizeof(double) * (size_t)t->nm[2] * ldu[2], hipMemcpyDeviceToDevice, s));
+  RSD_HIP(hipMemcpyAsync(t->slice, sl, sizeof(int) * (size_t)R, hipMemcpyDeviceToDevice, s));
+  // V_d (r_d x R): columns p = s*u (mode 1), v (mode 2), e_c (mode 3)
+  DevBuf V[3];
+  for (int d = 0; d < 3; ++d) RSD_TRY(V[d].alloc(ctx, (size_t)r[d] * R));
+  RSD_TIMED_LAUNCH(ctx, "assemble", (k_t2c_factors<<<grid1d((int64_t)total * (r1 + r2 + r3)), 256, 0, s>>>(
+                                        Sv.p, Uv.p, Vv.p, pos, total, ns, r1, r2, r3, R, V[0].p, V[1].p, V[2].p)));
   const int64_t mode = (int64_t)t->nchunk * n * kChunk;
-  const std::vector<double>* Vh[3] = {&V1, &V2, &V3};
   for (int d = 0; d < 3; ++d) {
-    DevBuf Vd;
-    RSD_TRY(Vd.alloc(ctx, Vh[d]->size()));
-    RSD_HIP(hipMemcpyAsync(Vd.p, Vh[d]->data(), sizeof(double) * Vh[d]->size(), hipMemcpyHostToDevice, s));
-    RSD_TIMED_LAUNCH(ctx, "assemble", (k_assemble<<<grid1d(mode), 256, 0, s>>>(U[d].p, ldu[d], r[d], Vd.p, R, n,
-                                                                               t->nm[d], t->nchunk, t->F + d * mode)));
+    // F_d = U_d V_d on the matrix cores, written straight into the chunked layout: rows of the
+    // layout beyond U_d's and columns beyond R come out zero (both operands are masked there).
+    // Mode 3's V is one-hot, so its columns are U_3's columns exactly.
+    GemmShape g{};
+    g.M = n; g.N = t->nchunk * kChunk; g.K = r[d]; g.kper = (int64_t)div_up(r[d], TK) * TK;
+    g.C = t->F + d * mode; g.ldc = kChunk; g.split_stride = 0; g.accumulate = 0; g.tri = 0; g.chunk_rows = n;
+    RSD_TRY(gemm(ctx, "assemble", OpMK{U[d].p, ldu[d], t->nm[d]}, OpKM{V[d].p, R, (int)R}, g, 1));
   }
-  RSD_HIP(hipStreamSynchronize(s));   // the uploads read V1..V3, which go on return
   return RSD_OK;
 }
 
