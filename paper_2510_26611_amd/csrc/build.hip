@@ -455,10 +455,38 @@ __global__ void k_col_norms(const double* __restrict__ pos, const double* __rest
   const double x = pos[3 * (c / K) + d];
   const double tt = t2[c % K];
   double s = 0.0;
-  for (int i = lane; i < n; i += 64) {
-    const double dx = (-b + (double)(i + 1) * h) - x;
-    const double g = gauss_entry(tt, dx, h, gal);
-    s = fma(g, g, s);
+  if (gal) {
+    for (int i = lane; i < n; i += 64) {
+      const double dx = (-b + (double)(i + 1) * h) - x;
+      const double g = gauss_entry(tt, dx, h, gal);
+      s = fma(g, g, s);
+    }
+  } else {
+    // g_i^2 = exp(-2 t^2 dx_i^2) over runs of 8 rows per lane, by the recurrence
+    // g_{i+1}^2 = g_i^2 r_i, r_i = exp(-2 t^2 (2 h dx_i + h^2)), r_{i+1} = r_i q, q = exp(-4 t^2 h^2),
+    // anchored by two exponentials per run (the long-range Gaussians are wide on the grid,
+    // t h << 1, so r stays near 1; a run where r could leave [e^-40, e^40] takes one exponential
+    // per entry); the norms only scale the columns, which the weights undo
+    const double q = exp(-4.0 * tt * (h * h));
+    for (int i0 = 8 * lane; i0 < n; i0 += 8 * 64) {
+      const double dx = (-b + (double)(i0 + 1) * h) - x;
+      const double ar = -2.0 * tt * (2.0 * h * dx + h * h);
+      const int m = min(8, n - i0);
+      if (fabs(ar) * 8.0 < 40.0) {
+        double e = exp(-2.0 * tt * (dx * dx));
+        double r = exp(ar);
+        for (int u = 0; u < m; ++u) {
+          s += e;
+          e *= r;
+          r *= q;
+        }
+      } else {   // a narrow Gaussian: each entry on its own
+        for (int u = 0; u < m; ++u) {
+          const double du = dx + (double)u * h;
+          s += exp(-2.0 * tt * (du * du));
+        }
+      }
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
