@@ -180,8 +180,10 @@ __device__ __forceinline__ double gauss_entry(double t2, double dx, double h, in
 }
 
 // GAL selects the cell-average entries at compile time: their erf code would otherwise set the
-// register budget of the projection for the collocated entries too.
-template <bool GAL>
+// register budget of the projection for the collocated entries too.  REC (collocated only) makes
+// the entries of a thread's rows by a recurrence; the caller picks it when every column's ratio
+// r below stays within [e^-5, e^5] over the whole box.
+template <bool GAL, bool REC = false>
 struct OpGauss {              // element (k = grid row i, m = column c) = g_c(X_i - x_c) / nu_c (gauss_entry)
   const double* __restrict__ pos;    // N x 3
   const double* __restrict__ t2;     // K_long
@@ -189,7 +191,7 @@ struct OpGauss {              // element (k = grid row i, m = column c) = g_c(X_
   int K, d, n;
   double b, h;
   int dim;                           // number of columns
-  double x_, t2_, s_;
+  double x_, t2_, s_, q_;
   template <int W> static constexpr int regs() { return 8; }
   __device__ void setup(int m0) {
     const int col = m0 + (threadIdx.x & 63);
@@ -200,15 +202,30 @@ struct OpGauss {              // element (k = grid row i, m = column c) = g_c(X_
     } else {
       x_ = 0.0; t2_ = 0.0; s_ = 0.0;
     }
+    q_ = exp(-(32.0 * t2_ * (h * h)));
   }
   template <int W>
   __device__ void fetch(double* r, int, int64_t kb, int64_t) const {
     static_assert(W == TM, "generated operands fill 64-wide stages");
     const int kq = threadIdx.x >> 6;
+    const double dx = (-b + (double)(kb + kq + 1) * h) - x_;
+    // collocated entries of the thread's rows (four apart) by the recurrence
+    // g(d + 4h) = g(d) r(d), r(d) = exp(-t^2 (8 h d + 16 h^2)), r(d + 4h) = r(d) q, q = exp(-32 t^2 h^2),
+    // anchored by two exponentials per stage
+    if constexpr (!GAL && REC) {
+      double g = exp(-(t2_ * (dx * dx))), rr = exp(-(t2_ * (8.0 * h * dx + 16.0 * (h * h))));
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const double X = -b + (double)(kb + kq + 4 * j + 1) * h;
-      r[j] = gauss_entry(t2_, X - x_, h, GAL ? 1 : 0) * s_;
+      for (int j = 0; j < 8; ++j) {
+        r[j] = g * s_;
+        g *= rr;
+        rr *= q_;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const double X = -b + (double)(kb + kq + 4 * j + 1) * h;
+        r[j] = gauss_entry(t2_, X - x_, h, GAL ? 1 : 0) * s_;
+      }
     }
   }
   template <int W>
@@ -366,6 +383,10 @@ struct WideOcc {
 };
 template <>
 struct WideOcc<OpGauss<false>, OpKM> {
+  static constexpr int value = 3;
+};
+template <>
+struct WideOcc<OpGauss<false, true>, OpKM> {
   static constexpr int value = 3;
 };
 template <>
@@ -1957,7 +1978,12 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
     }
   }
   // 3. projections B_d^T[c][a] = sum_i A(i, c) U[i][a], side-matrix columns regenerated in LDS;
-  //    the three modes side by side, so that the last wave of workgroups of one overlaps the next
+  //    the three modes side by side, so that the last wave of workgroups of one overlaps the next.
+  //    The collocated Gaussians come by a recurrence when its ratio exp(-t^2 (8 h d + 16 h^2))
+  //    stays within [e^-5, e^5] for every term and every offset |d| <= 2b in the box.
+  double t2max = 0.0;
+  for (double v : t2h) t2max = std::max(t2max, v);
+  const bool rec = t2max * (8.0 * h * 2.0 * b + 16.0 * h * h) < 5.0;
   RSD_TRY(on_three_streams(ctx, [&](int d, hipStream_t) -> rsd_status {
     const int rd = r[d];
     RSD_TRY(Bt[d].alloc(ctx, (size_t)C * ldu[d]));
@@ -1970,7 +1996,7 @@ rsd_status build_factors(Context* ctx, Tensor* t, const double* d_z, const doubl
       g.C = Bt[d].p; g.ldc = ldu[d]; g.split_stride = 0; g.accumulate = 0; g.tri = 0;
       return gemm(ctx, "project", ga, ub, g, 1);
     };
-    return gal ? project(OpGauss<true>{}) : project(OpGauss<false>{});
+    return gal ? project(OpGauss<true>{}) : rec ? project(OpGauss<false, true>{}) : project(OpGauss<false>{});
   }));
   t->ranks[0] = r[0];
   t->ranks[1] = r[1];
