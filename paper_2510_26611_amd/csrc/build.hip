@@ -728,32 +728,26 @@ __global__ __launch_bounds__(256) void k_qr_rinv(const double* __restrict__ S, i
   const int ld = k + 1;
   double* tmp = A + (size_t)s * ld;
   __shared__ double red[4];
-  __shared__ double s_par[3];            // beta, tau, scale
   const int tid = threadIdx.x;
   for (int e = tid; e < s * k; e += 256) A[(e / k) * ld + e % k] = S[e];
   __syncthreads();
   const int h = tid & 1;
+  // Only R is needed, so the reflector's v = scale * (column j below the diagonal) is formed
+  // where it is used and never stored; every thread derives beta, tau and scale itself from the
+  // block's norm (the same operations on the same values), so a step has one barrier besides
+  // the norm's.
   for (int j = 0; j < k; ++j) {
     double part = 0.0;
     for (int i = j + 1 + tid; i < s; i += 256) part = fma(A[i * ld + j], A[i * ld + j], part);
+    const double alpha = A[j * ld + j];   // read before the norm's barriers; thread 0 rewrites it below
     const double xn2 = block_sum256(part, red);
-    if (tid == 0) {
-      const double alpha = A[j * ld + j];
-      double beta = alpha, tau = 0.0, scale = 0.0;
-      if (xn2 > 0.0) {
-        const double nrm = sqrt(alpha * alpha + xn2);
-        beta = alpha >= 0.0 ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-      s_par[0] = beta;
-      s_par[1] = tau;
-      s_par[2] = scale;
+    double beta = alpha, tau = 0.0, scale = 0.0;
+    if (xn2 > 0.0) {
+      const double nrm = sqrt(alpha * alpha + xn2);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
     }
-    __syncthreads();
-    const double beta = s_par[0], tau = s_par[1], scale = s_par[2];
-    for (int i = j + 1 + tid; i < s; i += 256) A[i * ld + j] *= scale;
-    __syncthreads();
     if (tau != 0.0) {
       const int c = j + 1 + (tid >> 1);
       const bool on = c < k;
@@ -761,23 +755,35 @@ __global__ __launch_bounds__(256) void k_qr_rinv(const double* __restrict__ S, i
       if (on) {
         int i = j + 1 + h;
         for (; i + 6 < s; i += 8) {
-          a0 = fma(A[i * ld + j], A[i * ld + c], a0);
-          a1 = fma(A[(i + 2) * ld + j], A[(i + 2) * ld + c], a1);
-          a2 = fma(A[(i + 4) * ld + j], A[(i + 4) * ld + c], a2);
-          a3 = fma(A[(i + 6) * ld + j], A[(i + 6) * ld + c], a3);
+          a0 = fma(A[i * ld + j] * scale, A[i * ld + c], a0);
+          a1 = fma(A[(i + 2) * ld + j] * scale, A[(i + 2) * ld + c], a1);
+          a2 = fma(A[(i + 4) * ld + j] * scale, A[(i + 4) * ld + c], a2);
+          a3 = fma(A[(i + 6) * ld + j] * scale, A[(i + 6) * ld + c], a3);
         }
-        for (; i < s; i += 2) a0 = fma(A[i * ld + j], A[i * ld + c], a0);
+        for (; i < s; i += 2) a0 = fma(A[i * ld + j] * scale, A[i * ld + c], a0);
       }
       double w = (a0 + a1) + (a2 + a3);
       w += __shfl_xor(w, 1, 64);
       if (on) {
         w = tau * (w + A[j * ld + c]);
         if (h == 0) A[j * ld + c] -= w;
-        for (int i = j + 1 + h; i < s; i += 2) A[i * ld + c] = fma(-A[i * ld + j], w, A[i * ld + c]);
+        // rows of this lane in groups of eight: all loads of a group before its stores, so that
+        // they overlap (the compiler cannot tell that column j and column c do not alias)
+        int i = j + 1 + h;
+        for (; i + 14 < s; i += 16) {
+          double vj[8], vc[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            vj[u] = A[(i + 2 * u) * ld + j] * scale;
+            vc[u] = A[(i + 2 * u) * ld + c];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) A[(i + 2 * u) * ld + c] = fma(-vj[u], w, vc[u]);
+        }
+        for (; i < s; i += 2) A[i * ld + c] = fma(-(A[i * ld + j] * scale), w, A[i * ld + c]);
       }
     }
-    __syncthreads();
-    if (tid == 0) A[j * ld + j] = beta;
+    if (tid == 0) A[j * ld + j] = beta;   // no lane reads the diagonal in this step
     __syncthreads();
   }
   double dmax = 0.0;
@@ -822,7 +828,19 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ M, 
     const int l = j + 1 + lc;
     if (l < k) {
       const double ajl = A[j * ld + l];
-      for (int i = j + 1 + half; i <= l; i += 2) A[i * ld + l] = fma(-A[j * ld + i], ajl, A[i * ld + l]);
+      // in groups of eight rows, loads before stores (see the QR kernel)
+      int i = j + 1 + half;
+      for (; i + 14 <= l; i += 16) {
+        double vj[8], vl[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          vj[u] = A[j * ld + i + 2 * u];
+          vl[u] = A[(i + 2 * u) * ld + l];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) A[(i + 2 * u) * ld + l] = fma(-vj[u], ajl, vl[u]);
+      }
+      for (; i <= l; i += 2) A[i * ld + l] = fma(-A[j * ld + i], ajl, A[i * ld + l]);
     }
     __syncthreads();
   }
