@@ -584,8 +584,8 @@ __global__ __launch_bounds__(256) void k_long(const LongParams a) {
   if (item >= a.items) return;
   const int c = (int)(item / a.nblk);
   int clo = 0;
-  if (!GRAD && chunk_slices(a, c, &clo))
-    long_item<false, true>(a, c, (item % a.nblk) * (4 * a.ppw), smem);
+  if (chunk_slices(a, c, &clo))
+    long_item<GRAD, true>(a, c, (item % a.nblk) * (4 * a.ppw), smem);
   else
     long_item<GRAD, false>(a, c, (item % a.nblk) * (4 * a.ppw), smem);
 }
@@ -601,7 +601,8 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
   double4* s_v = (double4*)(s_pt + PB * L);    // GRAD: R u_l per point
   int* s_bad = (int*)(GRAD ? (void*)(s_v + PB * L) : (void*)s_v);
   double* s_out = (double*)(s_bad + PB);        // the block's PB x S results, stored together at the end
-  double* s_l3 = s_out + PB * S;                // U3: per atom kSlots mode-3 lerps
+  double* s_l3 = s_out + PB * S;                // U3: per atom kSlots mode-3 lerps (GRAD: then their row differences)
+  constexpr int L3 = GRAD ? 2 * kSlots : kSlots;
   int clo = 0;
   if (U3) chunk_slices(a, c, &clo);
   const int tid = threadIdx.x;
@@ -630,13 +631,15 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
           g.f2 = s2 - (double)g.i2;
           ok = true;
           if (GRAD) s_v[e] = make_double4(y.x - tv[0], y.y - tv[1], y.z - tv[2], 0.0);
-          if (U3) {   // the mode-3 lerps of the chunk's distinct U_3 columns (as F_3 would give)
+          if (U3) {   // the mode-3 lerps (and differences) of the chunk's distinct U_3 columns, as F_3 would give
             const double* r0 = a.U3 + (int64_t)g.i2 * a.u3_ld + clo;
             const double* r1 = r0 + a.u3_ld;
 #pragma unroll
             for (int q = 0; q < kSlots; ++q) {
               const int cq = clo + q < a.u3_ld ? q : 0;
-              s_l3[e * kSlots + q] = fma(g.f2, r1[cq] - r0[cq], r0[cq]);
+              const double dq = r1[cq] - r0[cq];
+              s_l3[e * L3 + q] = fma(g.f2, dq, r0[cq]);
+              if (GRAD) s_l3[e * L3 + kSlots + q] = dq;
             }
           }
         }
@@ -672,7 +675,7 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
       const GridPt* pts = s_pt + lp * L;
       for (int l0 = 0; l0 < L; l0 += 4) {
         double2 A0[2], B0[2], A1[2], B1[2], A2[2], B2[2];
-        double f0[2], f1[2], f2[2], zeta[2], l3x[2], l3y[2];
+        double f0[2], f1[2], f2[2], zeta[2], l3x[2], l3y[2], d3x[2], d3y[2];
         int la[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -686,9 +689,13 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
           A0[u] = q0[0]; B0[u] = q0[kChunk / 2];
           A1[u] = q1[0]; B1[u] = q1[kChunk / 2];
           if constexpr (U3) {
-            const double* l3 = s_l3 + (lp * L + la[u]) * kSlots;
+            const double* l3 = s_l3 + (lp * L + la[u]) * L3;
             l3x[u] = l3[slot0];
             l3y[u] = l3[slot1];
+            if (GRAD) {
+              d3x[u] = l3[kSlots + slot0];
+              d3y[u] = l3[kSlots + slot1];
+            }
           } else {
             const double2* q2 = (const double2*)(F2 + (int64_t)g.i2 * kChunk);
             A2[u] = q2[0]; B2[u] = q2[kChunk / 2];
@@ -698,7 +705,8 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
         for (int u = 0; u < 2; ++u) {
           const double dx0 = B0[u].x - A0[u].x, dx1 = B1[u].x - A1[u].x;
           const double dy0 = B0[u].y - A0[u].y, dy1 = B1[u].y - A1[u].y;
-          const double dx2 = U3 ? 0.0 : B2[u].x - A2[u].x, dy2 = U3 ? 0.0 : B2[u].y - A2[u].y;
+          const double dx2 = U3 ? (GRAD ? d3x[u] : 0.0) : B2[u].x - A2[u].x;
+          const double dy2 = U3 ? (GRAD ? d3y[u] : 0.0) : B2[u].y - A2[u].y;
           const double lx0 = fma(f0[u], dx0, A0[u].x), lx1 = fma(f1[u], dx1, A1[u].x);
           const double lx2 = U3 ? l3x[u] : fma(f2[u], dx2, A2[u].x);
           const double ly0 = fma(f0[u], dy0, A0[u].y), ly1 = fma(f1[u], dy1, A1[u].y);
@@ -1151,7 +1159,7 @@ size_t long_lds(int L, int ppw, bool grad, bool u3) {
   const int PB = 4 * ppw;
   return sizeof(double4) * (size_t)L + (size_t)PB * L * (sizeof(GridPt) + (grad ? sizeof(double4) : 0)) +
          sizeof(int) * (size_t)PB + sizeof(double) * (size_t)PB * (grad ? 7 : 1) +
-         (grad || !u3 ? 0 : sizeof(double) * (size_t)PB * L * kSlots);
+         (u3 ? sizeof(double) * (size_t)PB * L * kSlots * (grad ? 2 : 1) : 0);
 }
 
 int pick_ppw(int L, bool grad, bool u3, int want) {
@@ -1163,7 +1171,7 @@ int pick_ppw(int L, bool grad, bool u3, int want) {
 // Whether the chunk-major kernel serves the tensor's mode-3 lerps from LDS: the tensor keeps
 // U_3, the option is on, and the extra LDS still fits at the poses per wavefront it gets.
 bool use_u3(const Context* ctx, const Tensor* t, int L, bool grad, int ppw_want) {
-  if (grad || !t->U3 || !ctx->opt_shared_mode3) return false;
+  if (!t->U3 || !ctx->opt_shared_mode3) return false;
   return long_lds(L, pick_ppw(L, grad, true, ppw_want), grad, true) <= kLdsMax;
 }
 

@@ -125,7 +125,7 @@ def test_shared_mode3_columns_bitwise(env):
     """Tensors made by the canonical -> Tucker -> canonical step keep U_3: the chunk-major energy
     kernel lerps a chunk's distinct U_3 columns once per atom.  The values are the same as the
     gathered F_3 columns, so option shared_mode3 gives the same bits on and off, alone and in a
-    batch, for a built, a restricted and a combined tensor."""
+    batch, with and without gradients, for a built, a restricted and a combined tensor."""
     rs, torch, ctx, cfg, wl, F, t, dev = env
     tb = rs.build_rs_tensor(ctx, wl.protein_charges, wl.protein_positions, cfg.n, cfg.b, rs.Sinc.from_config(cfg))
     site = np.array([18.0, 0.0, 0.0])
@@ -152,6 +152,15 @@ def test_shared_mode3_columns_bitwise(env):
             for k, v in b.outputs()[0].items():
                 assert np.array_equal(v.cpu().numpy(), out[1][k], equal_nan=True), k
             b.free()
+            # the adjoint path takes the mode-3 row differences from U_3 too
+            outg = {}
+            for opt in (0, 1):
+                ctx.set_option("shared_mode3", opt)
+                o = rs.score_poses(ctx, tt, dev["z"], dev["x"], qs, ts, cfg.sigma, grads=True)
+                torch.cuda.synchronize()
+                outg[opt] = {k: v.cpu().numpy() for k, v in o.items()}
+            for k in outg[0]:
+                assert np.array_equal(outg[0][k], outg[1][k], equal_nan=True), k
     finally:
         ctx.set_option("shared_mode3", 1)
         ctx.set_option("score_mode", 0)
