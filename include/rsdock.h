@@ -353,8 +353,9 @@ void rsd_tensor_free(rsd_tensor* t);
  *                     windowed onto the grid; the long range then errs to first order in h
  *                     (Table 3.2), while the short range and the vdW test keep the true positions
  *   "svd_solver"      the k x k SVD inside the rank reduction of explicit factors
- *                     (rsd_tensor_restrict, rsd_tensor_combine): 0 automatic, 1 rocSOLVER gesvd,
- *                     2 rocSOLVER gesdd (divide and conquer), 3 rocSOLVER gesvdj (Jacobi)
+ *                     (rsd_tensor_restrict, rsd_tensor_combine): 0 automatic (4), 1 rocSOLVER gesvd,
+ *                     2 rocSOLVER gesdd (divide and conquer), 3 rocSOLVER gesvdj (Jacobi),
+ *                     4 the library's one-sided Jacobi kernel (one workgroup per mode)
  *   "gram_solver"     Gram matrices of the side matrices in the build: 0 automatic (1),
  *                     1 Toeplitz-times-Hankel form of the uniform grid (O(n N K + n^2 K)),
  *                     2 dense product of the generated side matrix on matrix cores (O(n^2 N K))

@@ -1349,7 +1349,7 @@ rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t va
     return RSD_OK;
   }
   if (std::strcmp(name, "svd_solver") == 0) {
-    RSD_CHECK(value >= 0 && value <= 3, RSD_E_INVALID, "svd_solver must be 0, 1, 2 or 3");
+    RSD_CHECK(value >= 0 && value <= 4, RSD_E_INVALID, "svd_solver must be 0, 1, 2, 3 or 4");
     ctx->opt_svd = (int)value;
     return RSD_OK;
   }

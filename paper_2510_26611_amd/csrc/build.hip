@@ -982,11 +982,17 @@ __device__ __forceinline__ int rr_player(int pos, int round, int np) {
 constexpr int kJacobiThreads = 512;   // eight lanes per column pair, up to 64 pairs per round
 constexpr int kJacobiLanes = 8;
 
+// ACCV: the rotations are also applied to V (n x n, from the identity, in LDS after the slice),
+// and vt returns V itself: orthogonal to working precision, so the right vectors of small
+// singular values are as accurate as the large ones' (v = S^T u / s is not, and serves only
+// where v enters multiplied by s).
+template <bool ACCV>
 __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_svd(const double* __restrict__ S, int m, int n,
                                                                double skip_rel2, double* __restrict__ sv,
                                                                double* __restrict__ uv, double* __restrict__ vt,
                                                                int* __restrict__ sweeps) {
   extern __shared__ double sA[];
+  double* sV = sA + (size_t)m * n;       // ACCV: column q of V at sV[q * n .. q * n + n - 1]
   constexpr int kWaves = kJacobiThreads / 64;
   __shared__ int s_rot;
   __shared__ double s_part[kWaves];
@@ -999,6 +1005,8 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_svd(const double* __r
     sA[e] = x;
     fro = fma(x, x, fro);
   }
+  if (ACCV)
+    for (int e = tid; e < n * n; e += kJacobiThreads) sV[e] = (e / n == e % n) ? 1.0 : 0.0;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) fro += __shfl_xor(fro, off, 64);
   if (lane == 0) s_part[wv] = fro;
@@ -1051,6 +1059,16 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_svd(const double* __r
             ap[row] = cs * x - sn * y;
             aq[row] = sn * x + cs * y;
           }
+          if (ACCV) {
+            double* vp = sV + p * n;
+            double* vq = sV + q * n;
+#pragma unroll 4
+            for (int row = part; row < n; row += kJacobiLanes) {
+              const double x = vp[row], y = vq[row];
+              vp[row] = cs * x - sn * y;
+              vq[row] = sn * x + cs * y;
+            }
+          }
           s_rot = 1;
         }
       }
@@ -1077,6 +1095,13 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_svd(const double* __r
     if (lane == 0) sv[(int64_t)c * n + q] = sq;
   }
   __syncthreads();
+  if (ACCV) {   // vt[q + b n] = V[b][q]
+    for (int e = tid; e < n * n; e += kJacobiThreads) {
+      const int q = e % n, b = e / n;
+      vt[(int64_t)c * n * n + e] = sV[q * n + b];
+    }
+    return;
+  }
   // v_q = S^T u_q / s_q
   for (int e = tid; e < n * n; e += kJacobiThreads) {
     const int q = e % n, bcol = e / n;
@@ -1088,6 +1113,33 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_svd(const double* __r
     const double sq = sv[(int64_t)c * n + q];
     vt[(int64_t)c * n * n + q + (int64_t)bcol * n] = sq > 0.0 ? w / sq : 0.0;
   }
+}
+
+// Singular values of a k x k Jacobi SVD (unsorted) into decreasing order, with the rows of the
+// LAPACK-style VT layout vt[q + b k] (right vector q, component b) moved along; ties keep their
+// index order.  info = 0, or 1 when the sweeps hit their limit, 2 when a value is not a number.
+__global__ __launch_bounds__(256) void k_svd_sort(const double* __restrict__ sv_in, const double* __restrict__ vt_in,
+                                                  int k, const int* __restrict__ sweeps, double* __restrict__ sv_out,
+                                                  double* __restrict__ vt_out, rocblas_int* __restrict__ info) {
+  __shared__ int s_nan;
+  if (threadIdx.x == 0) s_nan = 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < k; q += blockDim.x) {
+    const double v = sv_in[q];
+    if (!(v == v)) {
+      s_nan = 1;
+      continue;
+    }
+    int rank = 0;
+    for (int p = 0; p < k; ++p) {
+      const double w = sv_in[p];
+      rank += (w > v || (w == v && p < q)) ? 1 : 0;
+    }
+    sv_out[rank] = v;
+    for (int b = 0; b < k; ++b) vt_out[rank + (int64_t)b * k] = vt_in[q + (int64_t)b * k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *info = s_nan ? 2 : (*sweeps < kJacobiMaxSweeps ? 0 : 1);
 }
 
 // ----------------------------------------------------------------- host helpers
@@ -1212,14 +1264,14 @@ struct OrthBufs {
 // C (M x N, ld N) = sum over the K rows of A(k, m) B(k, n), split over the contraction and summed.
 template <class AOp, class BOp>
 rsd_status gemm_split(Context* ctx, const AOp& A, const BOp& B, int M, int N, int64_t K, double* part, int splits,
-                      double* C) {
+                      double* C, const char* name = "eig") {
   GemmShape g{};
   g.M = M; g.N = N; g.K = K;
   g.kper = (int64_t)div_up(K, (int64_t)splits * TK) * TK;
   g.C = part; g.ldc = N; g.split_stride = (int64_t)M * N; g.accumulate = 0; g.tri = 0;
-  RSD_TRY(gemm(ctx, "eig", A, B, g, splits));
-  RSD_TIMED_LAUNCH(ctx, "eig", (k_reduce_splits<<<grid1d((int64_t)M * N), 256, 0, ctx->stream>>>(
-                                   part, splits, (int64_t)M * N, M, N, N, C, N)));
+  RSD_TRY(gemm(ctx, name, A, B, g, splits));
+  RSD_TIMED_LAUNCH(ctx, name, (k_reduce_splits<<<grid1d((int64_t)M * N), 256, 0, ctx->stream>>>(
+                                  part, splits, (int64_t)M * N, M, N, N, C, N)));
   return RSD_OK;
 }
 
@@ -1231,25 +1283,25 @@ rsd_status gemm_split(Context* ctx, const AOp& A, const BOp& B, int M, int N, in
 // conditioned Q1, enough for a power step).  The result (transposed, k x n) goes to out (passes
 // even); *bad is set when a Cholesky pivot was not positive.  Y and out must differ.
 rsd_status orth_rchol(Context* ctx, const double* Yt, int k, int n, OrthBufs& b, double* out, int* bad,
-                      int passes) {
+                      int passes, const char* name = "eig") {
   hipStream_t s = ctx->stream;
   const int sr = kSmallRows;
-  RSD_TRY(gemm_split(ctx, OpMK{b.theta.p, n, sr}, OpMK{Yt, n, k}, sr, k, n, b.part.p, b.splits, b.sk.p));
-  RSD_TIMED_LAUNCH(ctx, "eig", (k_qr_rinv<<<1, 256, sizeof(double) * ((size_t)sr * (k + 1) + k), s>>>(
-                                   b.sk.p, sr, k, b.rinv.p)));
+  RSD_TRY(gemm_split(ctx, OpMK{b.theta.p, n, sr}, OpMK{Yt, n, k}, sr, k, n, b.part.p, b.splits, b.sk.p, name));
+  RSD_TIMED_LAUNCH(ctx, name, (k_qr_rinv<<<1, 256, sizeof(double) * ((size_t)sr * (k + 1) + k), s>>>(
+                                  b.sk.p, sr, k, b.rinv.p)));
   GemmShape g{};
   g.M = k; g.N = n; g.K = k; g.kper = ((int64_t)k + TK - 1) / TK * TK; g.ldc = n;
   g.split_stride = 0; g.accumulate = 0; g.tri = 0;
   g.C = out;
-  RSD_TRY(gemm(ctx, "eig", OpKM{b.rinv.p, k, k}, OpKM{Yt, n, n}, g, 1));      // out = (Y R_s^{-1})^T
+  RSD_TRY(gemm(ctx, name, OpKM{b.rinv.p, k, k}, OpKM{Yt, n, n}, g, 1));      // out = (Y R_s^{-1})^T
   double* bufs[2] = {out, b.tmp.p};   // pass 0: out -> tmp, pass 1: tmp -> out
   for (int pass = 0; pass < passes; ++pass) {
     const double* src = bufs[pass];
-    RSD_TRY(gemm_split(ctx, OpMK{src, n, k}, OpMK{src, n, k}, k, k, n, b.part.p, b.splits, b.w.p));
-    RSD_TIMED_LAUNCH(ctx, "eig", (k_chol_inv<<<1, 256, sizeof(double) * ((size_t)k * (k + 1) + k), s>>>(
-                                     b.w.p, k, b.rinv.p, bad)));
+    RSD_TRY(gemm_split(ctx, OpMK{src, n, k}, OpMK{src, n, k}, k, k, n, b.part.p, b.splits, b.w.p, name));
+    RSD_TIMED_LAUNCH(ctx, name, (k_chol_inv<<<1, 256, sizeof(double) * ((size_t)k * (k + 1) + k), s>>>(
+                                    b.w.p, k, b.rinv.p, bad)));
     g.C = bufs[1 - pass];
-    RSD_TRY(gemm(ctx, "eig", OpKM{b.rinv.p, k, k}, OpKM{src, n, n}, g, 1));
+    RSD_TRY(gemm(ctx, name, OpKM{b.rinv.p, k, k}, OpKM{src, n, n}, g, 1));
   }
   return RSD_OK;
 }
@@ -1402,14 +1454,14 @@ rsd_status subspace_eigvecs3(Context* ctx, rocblas_handle hb, double* G3, int n,
         st_all = RSD_E_HIP;
         break;
       }
+      if (bad) {   // a Cholesky pass lost rank (its Rayleigh-Ritz input is then meaningless): redo with Householder QR
+        md.lib = true;
+        continue;
+      }
       if (info != 0) {
         set_error("Ritz eigensolver of mode %d did not converge (info %d)", d, (int)info);
         st_all = RSD_E_NUMERIC;
         break;
-      }
-      if (bad) {   // a Cholesky pass lost rank: redo this mode with Householder QR
-        md.lib = true;
-        continue;
       }
       const double lmax = w[k - 1];
       if (!(lmax > 0.0 && std::isfinite(lmax))) {
@@ -1512,10 +1564,10 @@ rsd_status tucker_canonical(Context* ctx, Tensor* t, DevBuf Bt[3], DevBuf U[3], 
                                                                                             r3, S.p)));
   RSD_CHECK(r3 <= 1024, RSD_E_UNSUPPORTED, "too many core slices");
   if (jacobi) {
-    RSD_HIP(hipFuncSetAttribute((const void*)k_jacobi_svd, hipFuncAttributeMaxDynamicSharedMemorySize,
+    RSD_HIP(hipFuncSetAttribute((const void*)k_jacobi_svd<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(sizeof(double) * (size_t)r1 * r2)));
     const double skip_rel2 = std::max(1e-3 * eps * 1e-3 * eps, 1e-30);
-    RSD_TIMED_LAUNCH(ctx, "t2c", (k_jacobi_svd<<<r3, kJacobiThreads, sizeof(double) * (size_t)r1 * r2, s>>>(
+    RSD_TIMED_LAUNCH(ctx, "t2c", (k_jacobi_svd<false><<<r3, kJacobiThreads, sizeof(double) * (size_t)r1 * r2, s>>>(
                                      S.p, r1, r2, skip_rel2, Sv.p, Uv.p, Vv.p, (int*)d_info)));
   } else {
     KernelTimer kt;
@@ -1591,7 +1643,10 @@ rsd_status tucker_canonical(Context* ctx, Tensor* t, DevBuf Bt[3], DevBuf U[3], 
 //     captures the range exactly), B = Q^T A, B^T = Q_b R_b, the SVD of R_b, U = Q V.  If
 //     fewer than 16 of the k singular values fall below the cut and k < min(rows, R), k is
 //     doubled and the mode is redone.
-// Singular values >= eps * the largest are kept.  The three modes run on three streams (the
+// The orthonormal bases come from the randomized Cholesky QR (orth_rchol; B^T's triangular
+// factor is replaced by R' = Q_b^T B^T, which has the same singular values and right singular
+// vectors), or, when a Cholesky pass loses rank or k > kSmallCols, from rocSOLVER's Householder
+// QR.  Singular values >= eps * the largest are kept.  The three modes run on three streams (the
 // context stream and two auxiliary ones with their own rocBLAS handles), since their QR and
 // SVD calls are chains of short launches; the host synchronises once per pass to read the
 // singular values.  U_d is rows_d x ldu_d, row-major, zero beyond column r_d.
@@ -1626,8 +1681,12 @@ static rsd_status left_basis3(Context* ctx, rocblas_handle hb, double* const A[3
   struct Mode {
     int k = 0, kmax = 0;
     bool direct = false, finished = false;
-    DevBuf Om, Y, W, Rb, Sv, VT, E, tau, Ul;
+    bool lib = false;            // orthonormalize with rocSOLVER's Householder QR
+    DevBuf Om, Y, W, Rb, Sv, VT, E, tau, Ul, Qa, Qb, flag, part, Vj, Sj;
+    OrthBufs ob;
+    double* q = nullptr;         // the range basis Q (rows x k column-major) of the last pass
   } m[3];
+  RSD_TRY(allow_small_lds());
   for (int d = 0; d < 3; ++d) {
     m[d].kmax = (int)std::min<int64_t>(rows[d], R);
     m[d].direct = rows[d] <= R && rows[d] <= 96;
@@ -1638,27 +1697,48 @@ static rsd_status left_basis3(Context* ctx, rocblas_handle hb, double* const A[3
     hipStream_t saved;
     ~StreamGuard() { c->stream = saved; }
   } sg{ctx, main};
-  const int solver = ctx->opt_svd == 0 ? 3 : ctx->opt_svd;
+  const int solver_opt = ctx->opt_svd == 0 ? 4 : ctx->opt_svd;
   auto issue = [&](int d) -> rsd_status {
     Mode& md = m[d];
     const int k = md.k, nr = rows[d];
     const bool exact = k == md.kmax;
     hipStream_t s = st[d];
+    md.lib = md.lib || ctx->opt_qr == 1 || k > kSmallCols;
     RSD_TRY(md.W.alloc(ctx, (size_t)R * k));
     RSD_TRY(md.Rb.alloc(ctx, (size_t)k * k));
     RSD_TRY(md.Sv.alloc(ctx, (size_t)k));
     RSD_TRY(md.VT.alloc(ctx, (size_t)k * k));
     RSD_TRY(md.E.alloc(ctx, (size_t)k));
     RSD_TRY(md.tau.alloc(ctx, (size_t)k));
-    auto qr = [&](double* X, int mrows, int64_t ld, bool form_q) -> rsd_status {   // column-major mrows x k
+    const int nmax = (int)std::max<int64_t>(nr, R);
+    if (!md.lib) {
+      // randomized Cholesky QR (orth_rchol): sketch matrix, two output panels, the pivot flag
+      RSD_TRY(md.ob.alloc(ctx, nmax, k));
+      RSD_TRY(md.Qa.alloc(ctx, (size_t)nmax * k));
+      RSD_TRY(md.Qb.alloc(ctx, (size_t)nmax * k));
+      RSD_TRY(md.flag.alloc(ctx, 1));
+      const int sk_split = std::max(1, std::min(64, (int)(R / 64)));
+      RSD_TRY(md.part.alloc(ctx, (size_t)sk_split * k * k));
+      RSD_HIP(hipMemsetAsync(md.flag.p, 0, sizeof(double), s));
+      RSD_TIMED_LAUNCH(ctx, "restrict", (k_random_fill<<<grid1d((int64_t)kSmallRows * nmax), 256, 0, s>>>(
+                                            md.ob.theta.p, (int64_t)kSmallRows * nmax, 0x7E7Aull + (uint64_t)d)));
+    }
+    // an orthonormal basis of the columns of the mrows x k column-major panel X (k x mrows
+    // row-major): in place with rocSOLVER, else into `out`; returns where the basis is
+    auto orth = [&](double* X, int mrows, double* out, double** basis) -> rsd_status {
+      if (!md.lib) {
+        RSD_TRY(orth_rchol(ctx, X, k, mrows, md.ob, out, (int*)md.flag.p, 2, "qr"));
+        *basis = out;
+        return RSD_OK;
+      }
       KernelTimer kt;
       if (ctx->timing) RSD_TRY(ctx->timer_begin("qr", &kt));
-      RSD_CHECK(rocsolver_dgeqrf(hbs[d], mrows, k, X, (rocblas_int)ld, md.tau.p) == rocblas_status_success, RSD_E_HIP,
-                "rocsolver_dgeqrf failed");
-      if (form_q)
-        RSD_CHECK(rocsolver_dorgqr(hbs[d], mrows, k, k, X, (rocblas_int)ld, md.tau.p) == rocblas_status_success,
-                  RSD_E_HIP, "rocsolver_dorgqr failed");
+      RSD_CHECK(rocsolver_dgeqrf(hbs[d], mrows, k, X, (rocblas_int)mrows, md.tau.p) == rocblas_status_success,
+                RSD_E_HIP, "rocsolver_dgeqrf failed");
+      RSD_CHECK(rocsolver_dorgqr(hbs[d], mrows, k, k, X, (rocblas_int)mrows, md.tau.p) == rocblas_status_success,
+                RSD_E_HIP, "rocsolver_dorgqr failed");
       if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
+      *basis = X;
       return RSD_OK;
     };
     GemmShape g{};
@@ -1674,26 +1754,41 @@ static rsd_status left_basis3(Context* ctx, rocblas_handle hb, double* const A[3
       // Y = A Omega as Y^T (k x rows row-major = rows x k column-major)
       g.M = k; g.N = nr; g.K = R; g.kper = (R + TK - 1) / TK * TK; g.C = md.Y.p; g.ldc = nr;
       RSD_TRY(gemm(ctx, "restrict", OpKM{md.Om.p, k, k}, OpMK{A[d], R, nr}, g, 1));
-      RSD_TRY(qr(md.Y.p, nr, nr, true));
+      double* q = nullptr;
+      RSD_TRY(orth(md.Y.p, nr, md.Qa.p, &q));
       if (!exact) {
         // W = A^T Q (R x k row-major), then Y^T = W^T A^T and orthonormalise again
         g.M = (int)R; g.N = k; g.K = nr; g.kper = ((int64_t)nr + TK - 1) / TK * TK; g.C = md.W.p; g.ldc = k;
-        RSD_TRY(gemm(ctx, "restrict", OpKM{A[d], R, (int)R}, OpMK{md.Y.p, nr, k}, g, 1));
+        RSD_TRY(gemm(ctx, "restrict", OpKM{A[d], R, (int)R}, OpMK{q, nr, k}, g, 1));
         g.M = k; g.N = nr; g.K = R; g.kper = (R + TK - 1) / TK * TK; g.C = md.Y.p; g.ldc = nr;
         RSD_TRY(gemm(ctx, "restrict", OpKM{md.W.p, k, k}, OpMK{A[d], R, nr}, g, 1));
-        RSD_TRY(qr(md.Y.p, nr, nr, true));
+        RSD_TRY(orth(md.Y.p, nr, md.Qa.p, &q));
       }
+      md.q = q;
       // B^T = A^T Q as a column-major R x k matrix (k x R row-major)
       RSD_CHECK(div_up(R, TN) <= 65535, RSD_E_UNSUPPORTED, "too many columns (%lld) for the projection",
                 (long long)R);
       g.M = k; g.N = (int)R; g.K = nr; g.kper = ((int64_t)nr + TK - 1) / TK * TK; g.C = md.W.p; g.ldc = R;
-      RSD_TRY(gemm(ctx, "restrict", OpMK{md.Y.p, nr, k}, OpKM{A[d], R, (int)R}, g, 1));
+      RSD_TRY(gemm(ctx, "restrict", OpMK{q, nr, k}, OpKM{A[d], R, (int)R}, g, 1));
     }
-    RSD_TRY(qr(md.W.p, (int)R, R, false));
-    RSD_TIMED_LAUNCH(ctx, "restrict", (k_upper_copy<<<grid1d((int64_t)k * k), 256, 0, s>>>(md.W.p, R, k, md.Rb.p)));
+    if (!md.lib) {
+      // B^T = Q_b R' with Q_b orthonormal: R' = Q_b^T B^T (k x k) has B^T's singular values and
+      // right singular vectors; it is formed transposed (row-major R'^T = column-major R'), the
+      // layout the SVD below reads
+      double* qb = nullptr;
+      RSD_TRY(orth(md.W.p, (int)R, md.Qb.p, &qb));
+      const int sk_split = std::max(1, std::min(64, (int)(R / 64)));
+      RSD_TRY(gemm_split(ctx, OpMK{md.W.p, R, k}, OpMK{qb, R, k}, k, k, R, md.part.p, sk_split, md.Rb.p, "qr"));
+    } else {
+      RSD_CHECK(rocsolver_dgeqrf(hbs[d], (rocblas_int)R, k, md.W.p, (rocblas_int)R, md.tau.p) == rocblas_status_success,
+                RSD_E_HIP, "rocsolver_dgeqrf failed");
+      RSD_TIMED_LAUNCH(ctx, "restrict", (k_upper_copy<<<grid1d((int64_t)k * k), 256, 0, s>>>(md.W.p, R, k, md.Rb.p)));
+    }
     KernelTimer kt;
     if (ctx->timing) RSD_TRY(ctx->timer_begin("svd", &kt));
     rocblas_status rs = rocblas_status_success;
+    // the Jacobi kernel holds R' and its accumulated rotations in LDS: k <= 96
+    const int solver = solver_opt == 4 && 2 * (int64_t)k * k > kJacobiMaxElems ? 3 : solver_opt;
     if (solver == 1) {
       rs = rocsolver_dgesvd(hbs[d], rocblas_svect_none, rocblas_svect_singular, k, k, md.Rb.p, k, md.Sv.p, nullptr, 1,
                             md.VT.p, k, md.E.p, rocblas_outofplace, d_info + d);
@@ -1701,9 +1796,23 @@ static rsd_status left_basis3(Context* ctx, rocblas_handle hb, double* const A[3
       RSD_TRY(md.Ul.alloc(ctx, (size_t)k * k));
       rs = rocsolver_dgesdd(hbs[d], rocblas_svect_singular, rocblas_svect_singular, k, k, md.Rb.p, k, md.Sv.p,
                             md.Ul.p, k, md.VT.p, k, d_info + d);
-    } else {
+    } else if (solver == 3) {
       rs = rocsolver_dgesvdj(hbs[d], rocblas_svect_none, rocblas_svect_singular, k, k, md.Rb.p, k, 0.0, md.E.p, 100,
                              d_info + 3 + d, md.Sv.p, nullptr, 1, md.VT.p, k, d_info + d);
+    } else {
+      // one-sided Jacobi in one workgroup (no host wait, so the three modes overlap), then sorted
+      RSD_TRY(md.Ul.alloc(ctx, (size_t)k * k));
+      RSD_TRY(md.Vj.alloc(ctx, (size_t)k * k));
+      RSD_TRY(md.Sj.alloc(ctx, (size_t)k));
+      RSD_HIP(hipFuncSetAttribute((const void*)k_jacobi_svd<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(sizeof(double) * 2 * (size_t)k * k)));
+      const double skip_rel2 = std::max(1e-3 * eps * 1e-3 * eps, 1e-30);
+      // (timed by the bracket around the whole solver)
+      k_jacobi_svd<true><<<1, kJacobiThreads, sizeof(double) * 2 * (size_t)k * k, s>>>(
+          md.Rb.p, k, k, skip_rel2, md.Sj.p, md.Ul.p, md.Vj.p, (int*)(d_info + 8 + d));
+      RSD_HIP(hipGetLastError());
+      k_svd_sort<<<1, 256, 0, s>>>(md.Sj.p, md.Vj.p, k, (const int*)(d_info + 8 + d), md.Sv.p, md.VT.p, d_info + d);
+      RSD_HIP(hipGetLastError());
     }
     RSD_CHECK(rs == rocblas_status_success, RSD_E_HIP, "rocSOLVER SVD (%d) failed (%d)", solver, (int)rs);
     if (ctx->timing) RSD_TRY(ctx->timer_end(&kt));
@@ -1723,7 +1832,7 @@ static rsd_status left_basis3(Context* ctx, rocblas_handle hb, double* const A[3
       GemmShape g{};
       g.split_stride = 0; g.accumulate = 0; g.tri = 0;
       g.M = nr; g.N = r; g.K = k; g.kper = ((int64_t)k + TK - 1) / TK * TK; g.C = U[d].p; g.ldc = ldu;
-      RSD_TRY(gemm(ctx, "restrict", OpKM{md.Y.p, nr, nr}, OpKM{md.VT.p, k, r}, g, 1));
+      RSD_TRY(gemm(ctx, "restrict", OpKM{md.q, nr, nr}, OpKM{md.VT.p, k, r}, g, 1));
     }
     return RSD_OK;
   };
@@ -1744,13 +1853,19 @@ static rsd_status left_basis3(Context* ctx, rocblas_handle hb, double* const A[3
       const int k = md.k;
       std::vector<double> sv((size_t)k);
       rocblas_int info = 0;
+      int bad = 0;
       hipError_t e = hipMemcpyAsync(&info, d_info + d, sizeof(info), hipMemcpyDeviceToHost, st[d]);
       if (e == hipSuccess) e = hipMemcpyAsync(sv.data(), md.Sv.p, sizeof(double) * k, hipMemcpyDeviceToHost, st[d]);
+      if (e == hipSuccess && !md.lib) e = hipMemcpyAsync(&bad, md.flag.p, sizeof(int), hipMemcpyDeviceToHost, st[d]);
       if (e == hipSuccess) e = hipStreamSynchronize(st[d]);
       if (e != hipSuccess) {
         set_error("singular values: %s", hipGetErrorString(e));
         st_all = RSD_E_HIP;
         break;
+      }
+      if (bad) {   // a Cholesky pass lost rank (its SVD input is then meaningless): redo with Householder QR
+        md.lib = true;
+        continue;
       }
       if (info != 0) {
         set_error("SVD of mode %d did not converge (info %d)", d, (int)info);
