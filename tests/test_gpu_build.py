@@ -145,6 +145,28 @@ def test_eig_subspace_and_dense_agree(rs, ctx):
     assert np.max(np.abs(a - b)) <= 1e-7 * np.max(np.abs(a))
 
 
+def test_subspace_cholesky_and_householder_qr_agree(rs, ctx):
+    """The subspace iteration's bases by the randomized Cholesky QR (default) and by rocSOLVER's
+    Householder QR (option qr_solver 1, the fallback when a Cholesky pass loses rank) give the
+    same tensor on the 5,000-atom protein."""
+    cfg = configs.CONFIG2
+    wl = configs.make(cfg, P=1)
+    F = []
+    try:
+        for solver in (0, 1):
+            ctx.set_option("qr_solver", solver)
+            t = rs.build_rs_tensor(ctx, wl.protein_charges, wl.protein_positions, cfg.n, cfg.b,
+                                   rs.Sinc.from_config(cfg))
+            F.append(t.export())
+            t.free()
+    finally:
+        ctx.set_option("qr_solver", 0)
+    idx = _nodes(cfg, 3000, 8)
+    a, b = _canon_at(F[0], idx), _canon_at(F[1], idx)
+    print(f"max |T_chol - T_householder| {np.max(np.abs(a - b)):.3e} of max |T| {np.max(np.abs(a)):.3e}")
+    assert np.max(np.abs(a - b)) <= 1e-7 * np.max(np.abs(a))
+
+
 @pytest.mark.parametrize("cfg", [configs.CONFIG1, configs.CONFIG2])
 def test_gram_structured_and_dense_agree(rs, ctx, cfg):
     """The Toeplitz-times-Hankel Gram and the dense matrix-core Gram give the same tensor."""

@@ -164,6 +164,39 @@ def test_cfg2_site_restriction_full_size(env):
     tg.free()
 
 
+@pytest.mark.parametrize("qr_solver,svd_solver", [(1, 0), (0, 3), (1, 3)])
+@pytest.mark.parametrize("half", [4.0, 7.0])
+def test_restriction_solver_paths(env, half, qr_solver, svd_solver):
+    """The rank reduction's other solver paths, which the default one falls back to: rocSOLVER's
+    Householder QR for the bases (option qr_solver 1, taken when a Cholesky pass loses rank) and
+    rocSOLVER's gesvdj for the k x k SVD (svd_solver 3, taken for k > 96).  Each gives the
+    oracle's ranks and stays within the oracle-calibrated bound of the exact restricted tensor,
+    for the direct route (8 A box, 87 rows) and the randomized range (14 A box)."""
+    rs, torch, ctx, cfg, wl, F, t = env
+    site = np.array([18.0, 0.0, 0.0])
+    lo, hi = site - half, site + half
+    ref = olocal.restrict(F, cfg.n, cfg.b, lo, hi)
+    tk, rc = olocal.recompress(ref.F, 1e-8)
+    A = otensor.materialize_canonical(*ref.F)
+    err_o = float(np.sqrt(np.sum((otensor.materialize_canonical(*rc.F) - A) ** 2)))
+    norm = float(np.sqrt(np.sum(A * A)))
+    ctx.set_option("qr_solver", qr_solver)
+    ctx.set_option("svd_solver", svd_solver)
+    try:
+        tl = t.restrict(lo, hi, 1e-8)
+    finally:
+        ctx.set_option("qr_solver", 0)
+        ctx.set_option("svd_solver", 0)
+    g = tl.grid()
+    q = tl.query()
+    err_g = float(np.sqrt(np.sum((otensor.materialize_canonical(*_local_factors(tl, g)) - A) ** 2)))
+    print(f"half {half} qr {qr_solver} svd {svd_solver}: R {q['R']} ranks {q['ranks']} | oracle {rc.R} {tk.ranks} | "
+          f"||err|| gpu {err_g:.3e} oracle {err_o:.3e}")
+    assert tuple(q["ranks"]) == tuple(tk.ranks)
+    assert err_g <= 10.0 * max(err_o, 1e-8 * norm)
+    tl.free()
+
+
 def test_restriction_of_a_restriction(env):
     """A local tensor restricted again keeps the source's mesh: the same rows and origins as the
     direct restriction of the global tensor to the inner box, and the same values to the
