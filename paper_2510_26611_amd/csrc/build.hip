@@ -663,53 +663,133 @@ __global__ void k_random_fill(double* __restrict__ X, int64_t count, uint64_t se
   }
 }
 
-// ----------------------------------------------------------------- small factorizations in LDS
+// ----------------------------------------------------------------- small factorizations
 // Orthonormal bases of the eigensolver's n x k panels without a long chain of library launches:
 // the randomized Cholesky QR (a Householder QR of a small random sketch Theta Y gives R_s, and
 // Y R_s^{-1} is well conditioned whatever the condition of Y), followed by Cholesky QR passes.
-// Both factorizations below run in one workgroup with the matrix in LDS.
+// Both factorizations run in one workgroup of 256 lanes with the matrix in registers: a group
+// of eight lanes holds four adjacent columns, each lane a contiguous block of their rows.  A
+// step broadcasts one vector through LDS (double-buffered: one barrier per step), each lane
+// reads only its own rows of it, and a column's sum over its rows takes three lane exchanges.
+// The step loops are unrolled so that the slot of the step's column (and in the Cholesky the
+// register holding its row) is a compile-time constant.  The triangular inverse then works by
+// blocks in LDS.
 constexpr int kSmallRows = 144;          // sketch rows (k <= 128 columns): a k + 16 embedding
 constexpr int kSmallCols = 128;
+constexpr int kQrRowsPerLane = kSmallRows / 8;   // 18
+constexpr int kChRowsPerLane = kSmallCols / 8;   // 16
+constexpr int kInvBlock = 16;
 
-__device__ __forceinline__ double block_sum256(double v, double* red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  return (red[0] + red[1]) + (red[2] + red[3]);
+// Sum over aligned groups of eight lanes by DPP moves, which do not go through LDS: partners
+// one and two lanes apart within each quad, then the mirror within each half-row (lane i and
+// 7 - i).  Every stage adds two values in either order, so all eight lanes end with the same
+// bits.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double group8_sum(double x) {
+  x += dpp_move<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+  x += dpp_move<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+  x += dpp_move<0x141>(x);   // row_half_mirror
+  return x;
 }
 
-// The inverse of the upper triangular k x k block held in A (row-major, leading dimension ld),
-// in place, by rows from the bottom: X[i][c] = (delta_ic - sum_{l=i+1}^{c} R[i][l] X[l][c]) /
-// R[i][i], the rows below already holding X.  Row i of R is first copied to tmp (k doubles)
-// because it is overwritten while read.  Lanes take consecutive columns, so the X rows are read
-// without bank conflicts and tmp is broadcast; four partial sums shorten the dependency chain.
-// A diagonal below floor is raised to it (a direction the panel does not resolve; its basis
-// column is then noise that the later passes normalise).
-__device__ void upper_inverse_lds(double* A, int k, int ld, double* tmp, double floor) {
-  const int tid = threadIdx.x;
-  for (int i = k - 1; i >= 0; --i) {
-    for (int l = i + tid; l < k; l += blockDim.x) tmp[l] = A[i * ld + l];
-    __syncthreads();
-    double rii = tmp[i];
-    rii = fabs(rii) < floor ? (rii < 0.0 ? -floor : floor) : rii;
-    for (int c = i + tid; c < k; c += blockDim.x) {
-      double x;
-      if (c == i) {
-        x = 1.0 / rii;
-      } else {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int l = i + 1;
-        for (; l + 3 <= c; l += 4) {
-          a0 = fma(tmp[l], A[l * ld + c], a0);
-          a1 = fma(tmp[l + 1], A[(l + 1) * ld + c], a1);
-          a2 = fma(tmp[l + 2], A[(l + 2) * ld + c], a2);
-          a3 = fma(tmp[l + 3], A[(l + 3) * ld + c], a3);
-        }
-        for (; l <= c; ++l) a0 = fma(tmp[l], A[l * ld + c], a0);
-        x = -((a0 + a1) + (a2 + a3)) / rii;
+// LDS of the two kernels (doubles): the k x (k + 1) triangle, then the double-buffered step
+// vector (and, for the QR, the two taus).
+constexpr size_t qr_lds_doubles(int k) { return (size_t)k * (k + 1) + 2 * kSmallRows + 2; }
+constexpr size_t chol_lds_doubles(int k) { return (size_t)k * (k + 1) + 8 * kSmallCols; }
+
+// The inverse of the upper triangular k x k matrix in LDS (row-major, leading dimension ld), in
+// place, by blocks of 16 rows and columns.  First the diagonal blocks, one lane per column of a
+// block: the reciprocals of the diagonal, then the substitution up the column with the partial
+// sums of the rows above updated as each entry is found (a chain of one product and one fused
+// multiply-add per entry).  Then, from the second last block row I up, the matrix cores form
+// X_IJ = -D_I^{-1} sum_{I < L <= J} R_IL X_LJ for every J > I at once, one wavefront per J, the
+// blocks below already holding X (only upper triangles are read: the rest of the diagonal
+// blocks is never written).  A diagonal entry below floor in magnitude is raised to it (a
+// direction the panel does not resolve; its basis column is then noise that the later passes
+// normalise).  All four wavefronts of the workgroup call it.
+__device__ void upper_inverse_blocked(double* A, int k, int ld, double floor) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nb = (k + kInvBlock - 1) / kInvBlock;
+  {
+    const int ib = tid / kInvBlock, cc = tid % kInvBlock;   // diagonal block and column in it
+    const int o = ib * kInvBlock;
+    const bool act = ib < nb && o + cc < k;
+    double x[kInvBlock], acc[kInvBlock], rinv[kInvBlock];
+#pragma unroll
+    for (int i = 0; i < kInvBlock; ++i) {
+      x[i] = 0.0;
+      acc[i] = i == cc ? 1.0 : 0.0;
+      rinv[i] = 1.0;
+      if (act && i <= cc) {
+        double rii = A[(o + i) * ld + o + i];
+        rii = fabs(rii) < floor ? (rii < 0.0 ? -floor : floor) : rii;
+        rinv[i] = 1.0 / rii;
       }
-      A[i * ld + c] = x;
+    }
+#pragma unroll
+    for (int l = kInvBlock - 1; l >= 0; --l) {
+      if (act && l <= cc) {   // column cc of the block's inverse is zero below row cc
+        x[l] = acc[l] * rinv[l];
+#pragma unroll
+        for (int i = 0; i < l; ++i) acc[i] = fma(-A[(o + i) * ld + o + l], x[l], acc[i]);
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int i = 0; i < kInvBlock; ++i)
+        if (i <= cc) A[(o + i) * ld + o + cc] = x[i];
+    }
+    __syncthreads();
+  }
+  // v_mfma_f64_16x16x4: lane (lk, lr) = (lane / 16, lane % 16) gives A[lr][lk] and B[lk][lr] of
+  // a 4-wide slice of the inner index and holds D[4v + lk][lr], v = 0..3
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int I = nb - 2; I >= 0; --I) {
+    const int r0 = I * kInvBlock;
+    d4v t[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int J = I + 1 + wv + 4 * h;   // at most seven blocks right of I over four wavefronts
+      t[h] = d4v{0.0, 0.0, 0.0, 0.0};
+      if (J < nb) {
+        const int cJ = J * kInvBlock + lr;
+        for (int L = I + 1; L <= J; ++L) {
+#pragma unroll
+          for (int kq = 0; kq < 4; ++kq) {
+            const int l = L * kInvBlock + 4 * kq + lk;
+            const double a = l < k ? A[(r0 + lr) * ld + l] : 0.0;
+            const double b = (l < k && cJ < k && l <= cJ) ? A[l * ld + cJ] : 0.0;
+            t[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, t[h], 0, 0, 0);
+          }
+        }
+      }
+    }
+    __syncthreads();   // every block of row I of R has been read
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int J = I + 1 + wv + 4 * h;
+      if (J < nb) {
+        // X_IJ = -D_I^{-1} T: T's slice kq is this lane's accumulator entry kq
+        d4v xb = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+          const int q = 4 * kq + lk;
+          const double a = q >= lr ? A[(r0 + lr) * ld + r0 + q] : 0.0;
+          xb = __builtin_amdgcn_mfma_f64_16x16x4f64(a, t[h][kq], xb, 0, 0, 0);
+        }
+        const int cJ = J * kInvBlock + lr;
+        if (cJ < k) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) A[(r0 + 4 * v + lk) * ld + cJ] = -xb[v];
+        }
+      }
     }
     __syncthreads();
   }
@@ -719,135 +799,204 @@ __device__ void upper_inverse_lds(double* A, int k, int ld, double* tmp, double 
 // the inverse of its triangular factor R: Rinv (k x k row-major, zeros below the diagonal).
 // Reflector j (LAPACK's convention): beta = -sign(alpha) ||x||, tau = (beta - alpha)/beta,
 // v = x / (alpha - beta) below the diagonal; none where the column below is already zero.
-// The update of the columns right of j takes two lanes per column (alternate rows, combined by
-// a shuffle) and four partial sums per lane.  LDS rows are k + 1 doubles apart, so the two
-// lanes of a column (rows i and i + 1) fall in different banks.
+// Lanes: group G = tid / 8 holds columns 4G .. 4G+3, lane g = tid % 8 rows 18g .. 18g+17.  At
+// step j the group of column j forms v (1 on row j, zeros above) and puts it in LDS; every
+// lane then applies the reflector to all four of its columns: in those left of j it changes
+// only rows below their diagonal, which are not read again, and in those right of j it leaves
+// row j final.  The registers thus end holding R above the diagonal; beta goes to LDS at once.
 __global__ __launch_bounds__(256) void k_qr_rinv(const double* __restrict__ S, int s, int k,
                                                  double* __restrict__ Rinv) {
-  extern __shared__ double A[];          // s rows of k + 1, then k
+  constexpr int RL = kQrRowsPerLane;
+  extern __shared__ double sm[];
   const int ld = k + 1;
-  double* tmp = A + (size_t)s * ld;
-  __shared__ double red[4];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < s * k; e += 256) A[(e / k) * ld + e % k] = S[e];
-  __syncthreads();
-  const int h = tid & 1;
-  // Only R is needed, so the reflector's v = scale * (column j below the diagonal) is formed
-  // where it is used and never stored; every thread derives beta, tau and scale itself from the
-  // block's norm (the same operations on the same values), so a step has one barrier besides
-  // the norm's.
-  for (int j = 0; j < k; ++j) {
-    double part = 0.0;
-    for (int i = j + 1 + tid; i < s; i += 256) part = fma(A[i * ld + j], A[i * ld + j], part);
-    const double alpha = A[j * ld + j];   // read before the norm's barriers; thread 0 rewrites it below
-    const double xn2 = block_sum256(part, red);
-    double beta = alpha, tau = 0.0, scale = 0.0;
-    if (xn2 > 0.0) {
-      const double nrm = sqrt(alpha * alpha + xn2);
-      beta = alpha >= 0.0 ? -nrm : nrm;
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    if (tau != 0.0) {
-      const int c = j + 1 + (tid >> 1);
-      const bool on = c < k;
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      if (on) {
-        int i = j + 1 + h;
-        for (; i + 6 < s; i += 8) {
-          a0 = fma(A[i * ld + j] * scale, A[i * ld + c], a0);
-          a1 = fma(A[(i + 2) * ld + j] * scale, A[(i + 2) * ld + c], a1);
-          a2 = fma(A[(i + 4) * ld + j] * scale, A[(i + 4) * ld + c], a2);
-          a3 = fma(A[(i + 6) * ld + j] * scale, A[(i + 6) * ld + c], a3);
-        }
-        for (; i < s; i += 2) a0 = fma(A[i * ld + j] * scale, A[i * ld + c], a0);
-      }
-      double w = (a0 + a1) + (a2 + a3);
-      w += __shfl_xor(w, 1, 64);
-      if (on) {
-        w = tau * (w + A[j * ld + c]);
-        if (h == 0) A[j * ld + c] -= w;
-        // rows of this lane in groups of eight: all loads of a group before its stores, so that
-        // they overlap (the compiler cannot tell that column j and column c do not alias)
-        int i = j + 1 + h;
-        for (; i + 14 < s; i += 16) {
-          double vj[8], vc[8];
+  double* Rm = sm;                          // k rows of k + 1: R, then its inverse
+  double* vb = Rm + (size_t)k * ld;         // 2 x kSmallRows
+  double* tb = vb + 2 * kSmallRows;         // 2
+  const int tid = threadIdx.x, G = tid >> 3, g = tid & 7;
+  const int row0 = g * RL, col0 = 4 * G;
+  double a[RL][4];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            vj[u] = A[(i + 2 * u) * ld + j] * scale;
-            vc[u] = A[(i + 2 * u) * ld + c];
-          }
+  for (int rr = 0; rr < RL; ++rr)
 #pragma unroll
-          for (int u = 0; u < 8; ++u) A[(i + 2 * u) * ld + c] = fma(-vj[u], w, vc[u]);
+    for (int q = 0; q < 4; ++q) {
+      const int i = row0 + rr, c = col0 + q;
+      a[rr][q] = (i < s && c < k) ? S[i * k + c] : 0.0;
+    }
+  // steps in blocks of four: within a block the column slot (j mod 4) and the buffer (j mod 2)
+  // are fixed by t
+  for (int jb = 0; jb < k; jb += 4) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int j = jb + t;
+      if (j >= k) continue;   // uniform; no early exit, so that the loop unrolls fully
+      double* v = vb + (t & 1) * kSmallRows;
+      if (G == (j >> 2)) {
+        double part = 0.0, alpha = 0.0;
+#pragma unroll
+        for (int rr = 0; rr < RL; ++rr) {
+          const int i = row0 + rr;
+          const double x = a[rr][t];
+          part = fma(i > j ? x : 0.0, x, part);
+          alpha += i == j ? x : 0.0;
         }
-        for (; i < s; i += 2) A[i * ld + c] = fma(-(A[i * ld + j] * scale), w, A[i * ld + c]);
+        part = group8_sum(part);
+        alpha = group8_sum(alpha);
+        double beta = alpha, tau = 0.0, scale = 0.0;
+        if (part > 0.0) {
+          const double nrm = sqrt(alpha * alpha + part);
+          beta = alpha >= 0.0 ? -nrm : nrm;
+          tau = (beta - alpha) / beta;
+          scale = 1.0 / (alpha - beta);
+        }
+#pragma unroll
+        for (int rr = 0; rr < RL; ++rr) {
+          const int i = row0 + rr;
+          v[i] = i > j ? a[rr][t] * scale : (i == j ? 1.0 : 0.0);
+        }
+        if (g == 0) {
+          tb[t & 1] = tau;
+          Rm[j * ld + j] = beta;
+        }
+      }
+      __syncthreads();
+      const double tau = tb[t & 1];
+      double vr[RL];
+#pragma unroll
+      for (int rr = 0; rr < RL; ++rr) vr[rr] = v[row0 + rr];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double w = 0.0;
+#pragma unroll
+        for (int rr = 0; rr < RL; ++rr) w = fma(vr[rr], a[rr][c], w);
+        w = group8_sum(w) * tau;
+#pragma unroll
+        for (int rr = 0; rr < RL; ++rr) a[rr][c] = fma(-vr[rr], w, a[rr][c]);
       }
     }
-    if (tid == 0) A[j * ld + j] = beta;   // no lane reads the diagonal in this step
-    __syncthreads();
   }
+#pragma unroll
+  for (int rr = 0; rr < RL; ++rr)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = row0 + rr, c = col0 + q;
+      if (i < c && c < k) Rm[i * ld + c] = a[rr][q];
+    }
+  __syncthreads();
   double dmax = 0.0;
-  for (int j = 0; j < k; ++j) dmax = fmax(dmax, fabs(A[j * ld + j]));
-  upper_inverse_lds(A, k, ld, tmp, dmax * 0x1p-63);
+  for (int j = 0; j < k; ++j) dmax = fmax(dmax, fabs(Rm[j * ld + j]));
+  upper_inverse_blocked(Rm, k, ld, dmax * 0x1p-63);
   for (int e = tid; e < k * k; e += 256) {
     const int i = e / k, c = e % k;
-    Rinv[e] = c >= i ? A[i * ld + c] : 0.0;
+    Rinv[e] = c >= i ? Rm[i * ld + c] : 0.0;
   }
 }
 
 // Upper Cholesky factor C of the symmetric part of M (k x k row-major, C^T C = (M + M^T)/2)
 // and its inverse Cinv (row-major, zeros below).  A pivot that is not positive (the panel lost
 // rank) sets *bad = 1 and is replaced by the smallest positive one seen, so the launch ends
-// normally; the caller reads *bad.  The trailing update takes a column per lane (two row
-// halves per column over the 256 lanes); LDS rows are k + 1 doubles apart.
+// normally; the caller reads *bad.  Lanes as in the QR, with rows 16g .. 16g+15, and the
+// matrix padded with the identity to a multiple of four.  Four rows at a time: the lanes
+// holding rows j .. j+3 put them in LDS; every lane factors their 4 x 4 diagonal block D
+// (D = C_D^T C_D), forms rows j .. j+3 of C at its own rows and columns by substitution with
+// C_D^T, and subtracts their products from its entries (those in rows and columns already done
+// are not read again).
 __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ M, int k, double* __restrict__ Cinv,
                                                   int* __restrict__ bad) {
-  extern __shared__ double A[];          // k rows of k + 1, then k
+  constexpr int RL = kChRowsPerLane;
+  extern __shared__ double sm[];
   const int ld = k + 1;
-  double* tmp = A + (size_t)k * ld;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < k * k; e += 256) {
-    const int i = e / k, l = e % k;
-    A[i * ld + l] = 0.5 * (M[i * k + l] + M[l * k + i]);
-  }
-  __syncthreads();
+  double* Cm = sm;                          // k rows of k + 1: C, then its inverse
+  double* rb = Cm + (size_t)k * ld;         // 2 x 4 rows of kSmallCols: rows j .. j+3, double-buffered
+  const int tid = threadIdx.x, G = tid >> 3, g = tid & 7;
+  const int row0 = g * RL, col0 = 4 * G;
+  const int kp = (k + 3) & ~3;
+  double a[RL][4];
+#pragma unroll
+  for (int rr = 0; rr < RL; ++rr)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = row0 + rr, c = col0 + q;
+      a[rr][q] = (i < k && c < k) ? 0.5 * (M[i * k + c] + M[c * k + i]) : (i == c ? 1.0 : 0.0);
+    }
   double dmin = 1e300;
-  const int lc = tid & 127, half = tid >> 7;
-  for (int j = 0; j < k; ++j) {
-    double piv = A[j * ld + j];
-    if (!(piv > 0.0)) {
-      if (tid == 0) *bad = 1;
-      piv = dmin < 1e300 ? dmin * dmin : 1.0;
-    }
-    const double d = sqrt(piv);
-    dmin = fmin(dmin, d);
-    __syncthreads();   // every thread has read the pivot
-    if (tid == 0) A[j * ld + j] = d;
-    for (int l = j + 1 + tid; l < k; l += 256) A[j * ld + l] /= d;
-    __syncthreads();
-    const int l = j + 1 + lc;
-    if (l < k) {
-      const double ajl = A[j * ld + l];
-      // in groups of eight rows, loads before stores (see the QR kernel)
-      int i = j + 1 + half;
-      for (; i + 14 <= l; i += 16) {
-        double vj[8], vl[8];
+  int badv = 0;
+  for (int jb = 0; jb < kp; jb += RL) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          vj[u] = A[j * ld + i + 2 * u];
-          vl[u] = A[(i + 2 * u) * ld + l];
-        }
+    for (int u = 0; u < RL / 4; ++u) {
+      const int j = jb + 4 * u;
+      if (j >= kp) continue;   // uniform; no early exit, so that the loop unrolls fully
+      double* r = rb + (u & 1) * 4 * kSmallCols;
+      if (g == jb / RL) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) A[(i + 2 * u) * ld + l] = fma(-vj[u], ajl, vl[u]);
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) r[t * kSmallCols + col0 + q] = a[4 * u + t][q];
       }
-      for (; i <= l; i += 2) A[i * ld + l] = fma(-A[j * ld + i], ajl, A[i * ld + l]);
+      __syncthreads();
+      // C_D, upper: c[t][s] for s >= t, iv[t] = 1 / c[t][t]
+      double c[4][4], iv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        double p = r[t * kSmallCols + j + t];
+#pragma unroll
+        for (int m = 0; m < t; ++m) p = fma(-c[m][t], c[m][t], p);
+        if (!(p > 0.0)) {
+          badv = 1;
+          p = dmin < 1e300 ? dmin * dmin : 1.0;
+        }
+        c[t][t] = sqrt(p);
+        dmin = fmin(dmin, c[t][t]);
+        iv[t] = 1.0 / c[t][t];
+#pragma unroll
+        for (int s2 = t + 1; s2 < 4; ++s2) {
+          double x = r[t * kSmallCols + j + s2];
+#pragma unroll
+          for (int m = 0; m < t; ++m) x = fma(-c[m][t], c[m][s2], x);
+          c[t][s2] = x * iv[t];
+        }
+      }
+      // rows j .. j+3 of C at column x: the solution y of C_D^T y = (A_jx .. A_j+3,x)
+      auto solve = [&](int x, double y[4]) {
+        double b[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) b[t] = r[t * kSmallCols + x];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          double v = b[t];
+#pragma unroll
+          for (int m = 0; m < t; ++m) v = fma(-c[m][t], y[m], v);
+          y[t] = v * iv[t];
+        }
+      };
+      double yc[4][4];   // [column q][row t]
+#pragma unroll
+      for (int q = 0; q < 4; ++q) solve(col0 + q, yc[q]);
+      if (g == 0) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int row = j + t, col = col0 + q;
+            if (row < k && col >= row && col < k) Cm[row * ld + col] = col == row ? c[t][t] : yc[q][t];
+          }
+      }
+#pragma unroll
+      for (int rr = 0; rr < RL; ++rr) {
+        double y[4];
+        solve(row0 + rr, y);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) a[rr][q] = fma(-y[t], yc[q][t], a[rr][q]);
+      }
     }
-    __syncthreads();
   }
-  upper_inverse_lds(A, k, ld, tmp, 0.0);
+  if (tid == 0 && badv) *bad = 1;
+  __syncthreads();
+  upper_inverse_blocked(Cm, k, ld, 0.0);
   for (int e = tid; e < k * k; e += 256) {
     const int i = e / k, c = e % k;
-    Cinv[e] = c >= i ? A[i * ld + c] : 0.0;
+    Cinv[e] = c >= i ? Cm[i * ld + c] : 0.0;
   }
 }
 
@@ -976,7 +1125,9 @@ constexpr int kJacobiMaxElems = 18432;   // m * n doubles of one slice (144 KB o
 constexpr int kJacobiMaxSweeps = 80;
 
 __device__ __forceinline__ int rr_player(int pos, int round, int np) {
-  return pos == 0 ? 0 : 1 + (pos - 1 + round) % (np - 1);
+  int x = pos - 1 + round;                // < 2 (np - 1): one conditional subtraction
+  x -= x >= np - 1 ? np - 1 : 0;
+  return pos == 0 ? 0 : 1 + x;
 }
 
 constexpr int kJacobiThreads = 512;   // eight lanes per column pair, up to 64 pairs per round
@@ -1043,16 +1194,17 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_svd(const double* __r
           be = fma(y, y, be);
           ga = fma(x, y, ga);
         }
-#pragma unroll
-        for (int off = 1; off < kJacobiLanes; off <<= 1) {
-          al += __shfl_xor(al, off, 64);
-          be += __shfl_xor(be, off, 64);
-          ga += __shfl_xor(ga, off, 64);
-        }
+        al = group8_sum(al);   // the eight lanes of a pair are an aligned group
+        be = group8_sum(be);
+        ga = group8_sum(ga);
         if (ga != 0.0 && fmin(al, be) > skip && fabs(ga) > tol * sqrt(al * be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          // Rutishauser's rotation, tan = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) with
+          // zeta = (be - al) / (2 ga), written over the common denominator: two square roots
+          // and one division in the chain instead of three divisions
+          const double D = be - al, G2 = 2.0 * ga;
+          const double den = fabs(D) + sqrt(fma(D, D, G2 * G2));
+          const double rs = 1.0 / sqrt(fma(den, den, G2 * G2));
+          const double cs = den * rs, sn = (D >= 0.0 ? G2 : -G2) * rs;
 #pragma unroll 4
           for (int row = part; row < m; row += kJacobiLanes) {
             const double x = ap[row], y = aq[row];
@@ -1238,9 +1390,9 @@ rsd_status allow_small_lds() {
   std::lock_guard<std::mutex> lock(mu);
   if (std::find(done.begin(), done.end(), dev) != done.end()) return RSD_OK;
   RSD_HIP(hipFuncSetAttribute((const void*)k_qr_rinv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(double) * (kSmallRows * (kSmallCols + 1) + kSmallCols))));
+                              (int)(sizeof(double) * qr_lds_doubles(kSmallCols))));
   RSD_HIP(hipFuncSetAttribute((const void*)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(double) * (kSmallCols * (kSmallCols + 1) + kSmallCols))));
+                              (int)(sizeof(double) * chol_lds_doubles(kSmallCols))));
   done.push_back(dev);
   return RSD_OK;
 }
@@ -1287,7 +1439,7 @@ rsd_status orth_rchol(Context* ctx, const double* Yt, int k, int n, OrthBufs& b,
   hipStream_t s = ctx->stream;
   const int sr = kSmallRows;
   RSD_TRY(gemm_split(ctx, OpMK{b.theta.p, n, sr}, OpMK{Yt, n, k}, sr, k, n, b.part.p, b.splits, b.sk.p, name));
-  RSD_TIMED_LAUNCH(ctx, name, (k_qr_rinv<<<1, 256, sizeof(double) * ((size_t)sr * (k + 1) + k), s>>>(
+  RSD_TIMED_LAUNCH(ctx, name, (k_qr_rinv<<<1, 256, sizeof(double) * qr_lds_doubles(k), s>>>(
                                   b.sk.p, sr, k, b.rinv.p)));
   GemmShape g{};
   g.M = k; g.N = n; g.K = k; g.kper = ((int64_t)k + TK - 1) / TK * TK; g.ldc = n;
@@ -1298,7 +1450,7 @@ rsd_status orth_rchol(Context* ctx, const double* Yt, int k, int n, OrthBufs& b,
   for (int pass = 0; pass < passes; ++pass) {
     const double* src = bufs[pass];
     RSD_TRY(gemm_split(ctx, OpMK{src, n, k}, OpMK{src, n, k}, k, k, n, b.part.p, b.splits, b.w.p, name));
-    RSD_TIMED_LAUNCH(ctx, name, (k_chol_inv<<<1, 256, sizeof(double) * ((size_t)k * (k + 1) + k), s>>>(
+    RSD_TIMED_LAUNCH(ctx, name, (k_chol_inv<<<1, 256, sizeof(double) * chol_lds_doubles(k), s>>>(
                                     b.w.p, k, b.rinv.p, bad)));
     g.C = bufs[1 - pass];
     RSD_TRY(gemm(ctx, name, OpKM{b.rinv.p, k, k}, OpKM{src, n, n}, g, 1));
