@@ -341,8 +341,10 @@ void rsd_tensor_free(rsd_tensor* t);
  *   "poses_per_wave"  poses per wavefront in mode 2 (0 automatic, 1..4)
  *   "eig_solver"      eigenvectors of the Gram matrices in the build: 0 automatic (subspace
  *                     iteration for n >= 1024), 1 dense batched eigensolver, 2 subspace iteration
- *   "t2c_solver"      SVD of the Tucker core slices in the build: 0 automatic, 1 one-sided
- *                     Jacobi with the slice in LDS, 2 rocSOLVER gesvd
+ *   "t2c_solver"      SVD of the Tucker core slices in the build: 0 automatic (3 where its LDS
+ *                     fits, else 1, else 2), 1 one-sided Jacobi with the slice in LDS,
+ *                     2 rocSOLVER gesvd, 3 one-sided Jacobi on the transposed triangle of a
+ *                     Householder QR of the slice (fewer sweeps on graded slices)
  *   "factors"         1-D factors of rsd_build_rs_tensor: 0 (default) the Gaussians collocated
  *                     at the grid nodes; 1 their averages over the grid cells, i.e. the
  *                     projection onto piecewise-constant basis functions of eq. 2.1 (the Gram

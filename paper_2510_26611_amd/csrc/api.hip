@@ -1299,7 +1299,7 @@ rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t va
     return RSD_OK;
   }
   if (std::strcmp(name, "t2c_solver") == 0) {
-    RSD_CHECK(value >= 0 && value <= 2, RSD_E_INVALID, "t2c_solver must be 0, 1 or 2");
+    RSD_CHECK(value >= 0 && value <= 3, RSD_E_INVALID, "t2c_solver must be 0, 1, 2 or 3");
     ctx->opt_t2c = (int)value;
     return RSD_OK;
   }

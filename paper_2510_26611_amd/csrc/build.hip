@@ -1133,6 +1133,106 @@ __device__ __forceinline__ int rr_player(int pos, int round, int np) {
 constexpr int kJacobiThreads = 512;   // eight lanes per column pair, up to 64 pairs per round
 constexpr int kJacobiLanes = 8;
 
+// The rotation of one column pair from its sums al = |a_p|^2, be = |a_q|^2, ga = a_p . a_q
+// (over the eight lanes of the pair, an aligned group); false when the pair is left alone: its
+// cosine is below the rounding level of the dot product, or a column is below the skip level.
+// Rutishauser's tangent sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (be - al) / (2 ga),
+// is written over the common denominator: two square roots and one division in the chain.
+__device__ __forceinline__ bool jacobi_rotation(double al, double be, double ga, double skip, double tol,
+                                                double& cs, double& sn) {
+  al = group8_sum(al);
+  be = group8_sum(be);
+  ga = group8_sum(ga);
+  if (!(ga != 0.0 && fmin(al, be) > skip && fabs(ga) > tol * sqrt(al * be))) return false;
+  const double D = be - al, G2 = 2.0 * ga;
+  const double den = fabs(D) + sqrt(fma(D, D, G2 * G2));
+  const double rs = 1.0 / sqrt(fma(den, den, G2 * G2));
+  cs = den * rs;
+  sn = (D >= 0.0 ? G2 : -G2) * rs;
+  return true;
+}
+
+// The sweeps of one-sided Jacobi over the nc columns (mr rows each, column-major in LDS at sM):
+// column pairs in the round-robin order, eight lanes per pair, each over every eighth row
+// (loads unrolled so that several are in flight), the three sums combined within the group
+// (a 64-lane reduction per pair, or one lane per pair, leaves each round waiting on LDS
+// latency).  ACCV: every rotation is also applied to the columns of the nv x nc matrix at sV.
+// Pairs with a column whose squared norm is at most skip are left alone, and a pair is rotated
+// only when its cosine exceeds the rounding level of an mr-term dot product; the sweeps stop
+// when none was rotated.  Returns the number of sweeps.  All lanes of the workgroup call it.
+template <bool ACCV>
+__device__ int jacobi_sweeps(double* sM, int mr, int nc, double* sV, int nv, double skip, int* s_rot) {
+  const int tid = threadIdx.x;
+  const int np = nc + (nc & 1);
+  const double tol = fmax(1e-14, 4.0 * mr * 1.1102230246251565e-16);
+  int sweep = 0;
+  for (; sweep < kJacobiMaxSweeps && nc > 1; ++sweep) {
+    if (tid == 0) *s_rot = 0;
+    __syncthreads();
+    for (int round = 0; round < np - 1; ++round) {
+      for (int k8 = tid; k8 < (np / 2) * kJacobiLanes; k8 += kJacobiThreads) {
+        const int k = k8 / kJacobiLanes, part = k8 % kJacobiLanes;
+        const int pa = rr_player(k, round, np), pb = rr_player(np - 1 - k, round, np);
+        const int p = min(pa, pb), q = max(pa, pb);
+        if (q >= nc) continue;
+        double* ap = sM + p * mr;
+        double* aq = sM + q * mr;
+        double cs, sn, al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll 4
+        for (int row = part; row < mr; row += kJacobiLanes) {
+          const double x = ap[row], y = aq[row];
+          al = fma(x, x, al);
+          be = fma(y, y, be);
+          ga = fma(x, y, ga);
+        }
+        if (!jacobi_rotation(al, be, ga, skip, tol, cs, sn)) continue;
+#pragma unroll 4
+        for (int row = part; row < mr; row += kJacobiLanes) {
+          const double x = ap[row], y = aq[row];
+          ap[row] = cs * x - sn * y;
+          aq[row] = sn * x + cs * y;
+        }
+        if (ACCV) {
+          double* vp = sV + p * nv;
+          double* vq = sV + q * nv;
+#pragma unroll 4
+          for (int row = part; row < nv; row += kJacobiLanes) {
+            const double x = vp[row], y = vq[row];
+            vp[row] = cs * x - sn * y;
+            vq[row] = sn * x + cs * y;
+          }
+        }
+        *s_rot = 1;
+      }
+      __syncthreads();
+    }
+    const int rot = *s_rot;
+    __syncthreads();
+    if (!rot) break;
+  }
+  return sweep;
+}
+
+// The Frobenius norm squared of the m x n slice at Sc, copied into LDS at sA on the way.
+__device__ double load_slice(const double* __restrict__ Sc, int m, int n, double* sA, double* s_part) {
+  constexpr int kWaves = kJacobiThreads / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double fro = 0.0;
+  for (int e = tid; e < m * n; e += kJacobiThreads) {
+    const double x = Sc[e];
+    sA[e] = x;
+    fro = fma(x, x, fro);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) fro += __shfl_xor(fro, off, 64);
+  if (lane == 0) s_part[wv] = fro;
+  __syncthreads();
+  double fro_all = 0.0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) fro_all += s_part[w];
+  return fro_all;
+}
+
 // ACCV: the rotations are also applied to V (n x n, from the identity, in LDS after the slice),
 // and vt returns V itself: orthogonal to working precision, so the right vectors of small
 // singular values are as accurate as the large ones' (v = S^T u / s is not, and serves only
@@ -1150,86 +1250,12 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_svd(const double* __r
   const int c = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double* Sc = S + (int64_t)c * m * n;
-  double fro = 0.0;
-  for (int e = tid; e < m * n; e += kJacobiThreads) {
-    const double x = Sc[e];
-    sA[e] = x;
-    fro = fma(x, x, fro);
-  }
   if (ACCV)
     for (int e = tid; e < n * n; e += kJacobiThreads) sV[e] = (e / n == e % n) ? 1.0 : 0.0;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) fro += __shfl_xor(fro, off, 64);
-  if (lane == 0) s_part[wv] = fro;
-  __syncthreads();
-  double fro_all = 0.0;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) fro_all += s_part[w];
   // columns below sqrt(skip_rel2) of the slice norm hold nothing above the truncation level;
   // pairs involving them are left alone (rotating them only churns rounding noise)
-  const double skip = skip_rel2 * fro_all;
-  const int np = n + (n & 1);
-  // rotate a pair only when its cosine exceeds the rounding level of an m-term dot product
-  const double tol = fmax(1e-14, 4.0 * m * 1.1102230246251565e-16);
-  int sweep = 0;
-  for (; sweep < kJacobiMaxSweeps && n > 1; ++sweep) {
-    if (tid == 0) s_rot = 0;
-    __syncthreads();
-    // eight lanes per column pair, each over every eighth row (loads unrolled so that several
-    // are in flight), the three sums combined within the group: a 64-lane reduction per pair
-    // or one lane per pair leaves each round waiting on LDS latency
-    for (int round = 0; round < np - 1; ++round) {
-      for (int k8 = tid; k8 < (np / 2) * kJacobiLanes; k8 += kJacobiThreads) {
-        const int k = k8 / kJacobiLanes, part = k8 % kJacobiLanes;
-        const int pa = rr_player(k, round, np), pb = rr_player(np - 1 - k, round, np);
-        const int p = min(pa, pb), q = max(pa, pb);
-        if (q >= n) continue;
-        double* ap = sA + p * m;
-        double* aq = sA + q * m;
-        double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll 4
-        for (int row = part; row < m; row += kJacobiLanes) {
-          const double x = ap[row], y = aq[row];
-          al = fma(x, x, al);
-          be = fma(y, y, be);
-          ga = fma(x, y, ga);
-        }
-        al = group8_sum(al);   // the eight lanes of a pair are an aligned group
-        be = group8_sum(be);
-        ga = group8_sum(ga);
-        if (ga != 0.0 && fmin(al, be) > skip && fabs(ga) > tol * sqrt(al * be)) {
-          // Rutishauser's rotation, tan = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) with
-          // zeta = (be - al) / (2 ga), written over the common denominator: two square roots
-          // and one division in the chain instead of three divisions
-          const double D = be - al, G2 = 2.0 * ga;
-          const double den = fabs(D) + sqrt(fma(D, D, G2 * G2));
-          const double rs = 1.0 / sqrt(fma(den, den, G2 * G2));
-          const double cs = den * rs, sn = (D >= 0.0 ? G2 : -G2) * rs;
-#pragma unroll 4
-          for (int row = part; row < m; row += kJacobiLanes) {
-            const double x = ap[row], y = aq[row];
-            ap[row] = cs * x - sn * y;
-            aq[row] = sn * x + cs * y;
-          }
-          if (ACCV) {
-            double* vp = sV + p * n;
-            double* vq = sV + q * n;
-#pragma unroll 4
-            for (int row = part; row < n; row += kJacobiLanes) {
-              const double x = vp[row], y = vq[row];
-              vp[row] = cs * x - sn * y;
-              vq[row] = sn * x + cs * y;
-            }
-          }
-          s_rot = 1;
-        }
-      }
-      __syncthreads();
-    }
-    const int rot = s_rot;
-    __syncthreads();
-    if (!rot) break;
-  }
+  const double skip = skip_rel2 * load_slice(Sc, m, n, sA, s_part);
+  const int sweep = jacobi_sweeps<ACCV>(sA, m, n, sV, n, skip, &s_rot);
   if (tid == 0) sweeps[c] = sweep;
   // singular values and normalised left vectors
   for (int q = wv; q < n; q += kWaves) {
@@ -1266,6 +1292,127 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_svd(const double* __r
     vt[(int64_t)c * n * n + q + (int64_t)bcol * n] = sq > 0.0 ? w / sq : 0.0;
   }
 }
+
+// The same slice SVDs, with the slice first reduced by a Householder QR (A = Q R, in place in
+// LDS: R on and above the diagonal, the reflectors below it): one-sided Jacobi then runs on the
+// p = min(m, n) columns of X = R^T (n rows each), whose rows are the rows of R, with the rotations
+// accumulated in W (p x p, from the identity).  On the core slices, whose singular values are
+// strongly graded, this takes 5 to 7 sweeps where the slice itself takes 14 to 17.  With
+// X W = Z: A = (Q W) Z^T, so s_q = |z_q|, v_q = z_q / s_q and u_q = Q w_q (the reflectors applied
+// to w_q padded with zeros).  Singular values q >= p are zero, with zero vectors.  Output layout
+// as k_jacobi_svd's; LDS: m n + max(m, n) p + p^2 + p doubles.
+__global__ __launch_bounds__(kJacobiThreads) void k_jacobi_svd_qr(const double* __restrict__ S, int m, int n,
+                                                                  double skip_rel2, double* __restrict__ sv,
+                                                                  double* __restrict__ uv, double* __restrict__ vt,
+                                                                  int* __restrict__ sweeps) {
+  extern __shared__ double sA[];                     // m x n, column-major
+  constexpr int kWaves = kJacobiThreads / 64;
+  const int p = min(m, n), mx = max(m, n);
+  double* sX = sA + (size_t)m * n;                   // X = R^T (n x p), later U (m x p)
+  double* sW = sX + (size_t)mx * p;                  // W (p x p)
+  double* tau = sW + (size_t)p * p;                  // p
+  __shared__ int s_rot;
+  __shared__ double s_part[kWaves];
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const double* Sc = S + (int64_t)c * m * n;
+  const double skip = skip_rel2 * load_slice(Sc, m, n, sA, s_part);
+  // Householder QR (LAPACK's convention, as in k_qr_rinv); wavefront 0 forms reflector j, then
+  // eight lanes per column apply it to the columns right of j
+  for (int j = 0; j < p; ++j) {
+    double* aj = sA + (size_t)j * m;
+    if (wv == 0) {
+      double part = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) part = fma(aj[i], aj[i], part);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+      const double alpha = aj[j];
+      double beta = alpha, tj = 0.0, scale = 0.0;
+      if (part > 0.0) {
+        const double nrm = sqrt(fma(alpha, alpha, part));
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tj = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      for (int i = j + 1 + lane; i < m; i += 64) aj[i] *= scale;
+      if (lane == 0) {
+        aj[j] = beta;
+        tau[j] = tj;
+      }
+    }
+    __syncthreads();
+    const double tj = tau[j];
+    if (tj != 0.0) {
+      for (int k8 = tid; k8 < (n - j - 1) * kJacobiLanes; k8 += kJacobiThreads) {
+        double* ac = sA + (size_t)(j + 1 + k8 / kJacobiLanes) * m;
+        const int part = k8 % kJacobiLanes;
+        double w = 0.0;
+        for (int i = j + 1 + part; i < m; i += kJacobiLanes) w = fma(aj[i], ac[i], w);
+        w = tj * (group8_sum(w) + ac[j]);
+        if (part == 0) ac[j] -= w;
+        for (int i = j + 1 + part; i < m; i += kJacobiLanes) ac[i] = fma(-aj[i], w, ac[i]);
+      }
+    }
+    __syncthreads();
+  }
+  // X: column a holds row a of R; W = I
+  for (int e = tid; e < n * p; e += kJacobiThreads) {
+    const int a = e / n, b = e % n;
+    sX[e] = b >= a ? sA[a + (size_t)b * m] : 0.0;
+  }
+  for (int e = tid; e < p * p; e += kJacobiThreads) sW[e] = (e / p == e % p) ? 1.0 : 0.0;
+  __syncthreads();
+  const int sweep = jacobi_sweeps<true>(sX, n, p, sW, p, skip, &s_rot);
+  if (tid == 0) sweeps[c] = sweep;
+  // s_q and v_q = z_q / s_q; zeros for q >= p
+  for (int q = wv; q < n; q += kWaves) {
+    const double* z = sX + (size_t)q * n;
+    double s2 = 0.0;
+    if (q < p)
+      for (int row = lane; row < n; row += 64) s2 = fma(z[row], z[row], s2);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+    const double sq = sqrt(s2);
+    const double inv = sq > 0.0 ? 1.0 / sq : 0.0;
+    for (int b = lane; b < n; b += 64) vt[(int64_t)c * n * n + q + (int64_t)b * n] = q < p ? z[b] * inv : 0.0;
+    if (lane == 0) sv[(int64_t)c * n + q] = sq;
+  }
+  __syncthreads();
+  // U = Q [W; 0] in place of X: the reflectors from the last to the first
+  double* sU = sX;
+  for (int e = tid; e < m * p; e += kJacobiThreads) {
+    const int q = e / m, a = e % m;
+    sU[e] = a < p ? sW[(size_t)q * p + a] : 0.0;
+  }
+  __syncthreads();
+  for (int j = p - 1; j >= 0; --j) {
+    const double tj = tau[j];
+    if (tj == 0.0) continue;   // uniform
+    const double* aj = sA + (size_t)j * m;
+    for (int k8 = tid; k8 < p * kJacobiLanes; k8 += kJacobiThreads) {
+      double* uq = sU + (size_t)(k8 / kJacobiLanes) * m;
+      const int part = k8 % kJacobiLanes;
+      double w = 0.0;
+      for (int i = j + 1 + part; i < m; i += kJacobiLanes) w = fma(aj[i], uq[i], w);
+      w = tj * (group8_sum(w) + uq[j]);
+      if (part == 0) uq[j] -= w;
+      for (int i = j + 1 + part; i < m; i += kJacobiLanes) uq[i] = fma(-aj[i], w, uq[i]);
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < m * n; e += kJacobiThreads) {
+    const int q = e / m;
+    uv[(int64_t)c * m * n + e] = q < p ? sU[e] : 0.0;
+  }
+}
+
+// LDS of k_jacobi_svd_qr for an m x n slice, in doubles, and the most it may take (160 KB per
+// workgroup, less the kernel's own few bytes).
+constexpr size_t jacobi_qr_lds_doubles(int m, int n) {
+  return (size_t)m * n + (size_t)(m > n ? m : n) * (m < n ? m : n) + (size_t)(m < n ? m : n) * (m < n ? m : n) +
+         (m < n ? m : n);
+}
+constexpr size_t kJacobiQrMaxLds = 20400;
 
 // Singular values of a k x k Jacobi SVD (unsorted) into decreasing order, with the rows of the
 // LAPACK-style VT layout vt[q + b k] (right vector q, component b) moved along; ties keep their
@@ -1703,8 +1850,13 @@ rsd_status tucker_canonical(Context* ctx, Tensor* t, DevBuf Bt[3], DevBuf U[3], 
 
   // 5. Tucker -> canonical: SVD of the mode-3 slices (r1 x r2, column-major)
   const int r1 = r[0], r2 = r[1], r3 = r[2];
-  const bool jacobi = ctx->opt_t2c == 2 ? false : (ctx->opt_t2c == 1 || (int64_t)r1 * r2 <= kJacobiMaxElems);
-  RSD_CHECK(!jacobi || (int64_t)r1 * r2 <= kJacobiMaxElems, RSD_E_UNSUPPORTED, "core slice too large for LDS");
+  // 0 automatic: the QR-preconditioned Jacobi where its LDS fits, else the plain one, else rocSOLVER
+  const size_t qr_lds = jacobi_qr_lds_doubles(r1, r2);
+  const bool jacobi_qr = ctx->opt_t2c == 3 || (ctx->opt_t2c == 0 && qr_lds <= kJacobiQrMaxLds);
+  const bool jacobi = jacobi_qr || ctx->opt_t2c == 1 || (ctx->opt_t2c == 0 && (int64_t)r1 * r2 <= kJacobiMaxElems);
+  RSD_CHECK(!jacobi_qr || qr_lds <= kJacobiQrMaxLds, RSD_E_UNSUPPORTED, "core slice too large for LDS");
+  RSD_CHECK(!jacobi || jacobi_qr || (int64_t)r1 * r2 <= kJacobiMaxElems, RSD_E_UNSUPPORTED,
+            "core slice too large for LDS");
   const int ns = jacobi ? r2 : std::min(r1, r2);      // singular values per slice
   DevBuf S, Sv, Uv, Vv, Ev;
   RSD_TRY(S.alloc(ctx, (size_t)r1 * r2 * r3));
@@ -1715,10 +1867,15 @@ rsd_status tucker_canonical(Context* ctx, Tensor* t, DevBuf Bt[3], DevBuf U[3], 
   RSD_TIMED_LAUNCH(ctx, "t2c", (k_core_slices<<<grid1d((int64_t)r1 * r2 * r3), 256, 0, s>>>(beta.p, r1, r2, r3,
                                                                                             r3, S.p)));
   RSD_CHECK(r3 <= 1024, RSD_E_UNSUPPORTED, "too many core slices");
-  if (jacobi) {
+  const double skip_rel2 = std::max(1e-3 * eps * 1e-3 * eps, 1e-30);
+  if (jacobi_qr) {
+    RSD_HIP(hipFuncSetAttribute((const void*)k_jacobi_svd_qr, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(double) * qr_lds)));
+    RSD_TIMED_LAUNCH(ctx, "t2c", (k_jacobi_svd_qr<<<r3, kJacobiThreads, sizeof(double) * qr_lds, s>>>(
+                                     S.p, r1, r2, skip_rel2, Sv.p, Uv.p, Vv.p, (int*)d_info)));
+  } else if (jacobi) {
     RSD_HIP(hipFuncSetAttribute((const void*)k_jacobi_svd<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(sizeof(double) * (size_t)r1 * r2)));
-    const double skip_rel2 = std::max(1e-3 * eps * 1e-3 * eps, 1e-30);
     RSD_TIMED_LAUNCH(ctx, "t2c", (k_jacobi_svd<false><<<r3, kJacobiThreads, sizeof(double) * (size_t)r1 * r2, s>>>(
                                      S.p, r1, r2, skip_rel2, Sv.p, Uv.p, Vv.p, (int*)d_info)));
   } else {

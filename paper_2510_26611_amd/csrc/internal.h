@@ -92,7 +92,7 @@ struct Context {
   // tuning options (rsd_context_set_option)
   int opt_score_mode = 0;      // 0 auto, 1 fused per-pose kernel, 2 chunk-major long-range kernel
   int opt_poses_per_wave = 0;  // chunk-major kernel: poses per wavefront (0 = automatic)
-  int opt_t2c = 0;             // core slice SVDs: 0 auto, 1 Jacobi in LDS, 2 rocSOLVER
+  int opt_t2c = 0;             // core slice SVDs: 0 auto, 1 Jacobi in LDS, 2 rocSOLVER, 3 QR then Jacobi
   int opt_eig = 0;             // Gram eigenvectors: 0 auto, 1 dense batched eigensolver, 2 subspace iteration
   int opt_qr = 0;              // subspace-iteration bases: 0 auto (randomized Cholesky QR, k <= 128), 1 rocSOLVER QR
   int opt_svd = 0;             // small SVD of explicit-factor rank reduction: 0 auto, 1 gesvd, 2 gesdd, 3 Jacobi
