@@ -56,6 +56,40 @@ def _traffic(launch_poses: int):
     return rec.get("hbm_bytes_per_launch")
 
 
+def gather_roofline(rs, ctx, t, dom_name: str, dom_ms: float, P: int, L: int, R: int, traffic=None) -> dict:
+    """Roofline of the dominant scoring kernel: the bytes it moves from L2 into the compute units
+    against the rate of its gather pattern alone (rsd_probe_gather, measured here).  The
+    chunk-major long-range kernel moves, per atom and rank chunk, rows i and i+1 of modes 1-2
+    (512 bytes each) and of mode 3 unless the chunk takes its mode-3 lerps from U_3 (read as
+    2 x 4 values per atom); the fused per-pose kernel moves rows i and i+1 of all three modes
+    for every column (48 R bytes per atom).  The factors stay in L2, so the HBM multiple of the
+    algorithmic bytes (Lemma 3.3's 48 L R per pose) is informational only."""
+    lay = t.layout()
+    nch, u3 = lay["nchunk"], lay["shared_mode3"]
+    if dom_name == "long":
+        moved = P * L * (u3 * (4 * 512 + 64) + (nch - u3) * 6 * 512)
+    else:
+        moved = P * L * 48.0 * R
+    pn = 2048                                          # 2 MB per XCD: the L2-resident ceiling
+    probe = rs.probe_gather(ctx, pn, 256)
+    alg_bytes = P * (48.0 * L * R + 56)
+    flops = P * L * nch * 64 * 10.0                    # per atom and column: two lerps, two products, one FMA
+    achieved = moved / (dom_ms / 1e3) / 1e9
+    return {"kernel": dom_name, "kernel_ms": dom_ms, "bound": "l2_gather", "achieved": achieved,
+            "peak": probe["gbs"], "unit": "GB/s", "frac": achieved / probe["gbs"], "traffic": traffic,
+            "bytes_per_launch": moved,
+            "peak_source": (f"rsd_probe_gather on this GPU: the kernel's gather pattern alone (16-byte loads of "
+                            f"rows i, i+1 of two modes per half-wavefront, {pn}-row chunks, one per XCD), "
+                            f"{probe['bytes'] / 1e9:.2f} GB in {probe['ms']:.3f} ms"),
+            "chunks": nch, "chunks_mode3_from_U3": u3,
+            "hbm_algorithmic": {"bytes_per_launch": alg_bytes, "GB_per_s": alg_bytes / (dom_ms / 1e3) / 1e9,
+                                "multiple_of_hbm_peak": alg_bytes / (dom_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                "note": "48 L R bytes per pose (Lemma 3.3's two rows per mode per atom) over the "
+                                        "8 TB/s HBM peak; the factors stay in L2, so this multiple exceeds 1"},
+            "fp64_valu": {"tflops": flops / (dom_ms / 1e3) / 1e12, "peak_tflops": FP64_MFMA_PEAK_TFS,
+                          "frac": flops / (dom_ms / 1e3) / 1e12 / FP64_MFMA_PEAK_TFS}}
+
+
 def cpu_baseline(cfg, wl, sample: int, F_gpu=None, gpu_out=None):
     """The oracle as it stands: its own tensor build (timed), then scoring of a bounded pose sample.
 
@@ -264,40 +298,10 @@ def main() -> int:
     n_dom, ms_dom = kt[dom_name]
     dom_ms = ms_dom / max(n_dom, 1)
     score_ms = sum(kt[k][1] for k in ("score", "long", "short", "combine", "ligand_prep", "sort")) / args.steps
-    alg_bytes = P * (48.0 * cfg.L * R + 56)           # two factor rows per mode per atom + pose inputs
     traffic = _traffic(P) if args.workload == "cfg2" else None
     flags = out["flags"].cpu().numpy()
-    # the roofline of the gathers: bytes the long-range kernel moves from L2 into the compute
-    # units (per atom and rank chunk: rows i and i+1 of modes 1-2, 512 bytes each, and of mode 3
-    # unless the chunk takes its mode-3 lerps from U_3, read as 2 x 4 values per atom), against the
-    # rate of the same gather pattern alone (rsd_probe_gather, measured here)
     t = rs.build_rs_tensor(ctx, d_z, d_x, cfg.n, cfg.b, sinc)
-    lay = t.layout()
-    nch, u3 = lay["nchunk"], lay["shared_mode3"]
-    moved = P * cfg.L * (u3 * (4 * 512 + 64) + (nch - u3) * 6 * 512)
-    pn = 2048                                          # 2 MB per XCD: the L2-resident ceiling
-    probe = rs.probe_gather(ctx, pn, 256)
-    flops = P * cfg.L * nch * 64 * 10.0                # per atom and column: two lerps, two products, one FMA
-    roof = {"kernel": dom_name, "kernel_ms": dom_ms}
-    if dom_name == "long":
-        achieved = moved / (dom_ms / 1e3) / 1e9
-        roof.update({"bound": "l2_gather", "achieved": achieved, "peak": probe["gbs"], "unit": "GB/s",
-                     "frac": achieved / probe["gbs"], "traffic": traffic,
-                     "bytes_per_launch": moved,
-                     "peak_source": (f"rsd_probe_gather on this GPU: the kernel's gather pattern alone (16-byte "
-                                     f"loads of rows i, i+1 of two modes per half-wavefront, {pn}-row chunks, "
-                                     f"one per XCD), {probe['bytes'] / 1e9:.2f} GB in {probe['ms']:.3f} ms"),
-                     "chunks": nch, "chunks_mode3_from_U3": u3})
-    else:
-        achieved = alg_bytes / (dom_ms / 1e3) / 1e9
-        roof.update({"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None})
-    roof["hbm_algorithmic"] = {"bytes_per_launch": alg_bytes, "GB_per_s": alg_bytes / (dom_ms / 1e3) / 1e9,
-                               "multiple_of_hbm_peak": alg_bytes / (dom_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-                               "note": "48 L R bytes per pose (Lemma 3.3's two rows per mode per atom) over the "
-                                       "8 TB/s HBM peak; the factors stay in L2, so this multiple exceeds 1"}
-    roof["fp64_valu"] = {"tflops": flops / (dom_ms / 1e3) / 1e12, "peak_tflops": FP64_MFMA_PEAK_TFS,
-                         "frac": flops / (dom_ms / 1e3) / 1e12 / FP64_MFMA_PEAK_TFS}
+    roof = gather_roofline(rs, ctx, t, dom_name, dom_ms, P, cfg.L, R, traffic)
     F_gpu = None
     if not args.no_cpu_baseline and args.workload == "cfg2":
         F_gpu = t.export()
@@ -535,7 +539,9 @@ def run_site(args, rs, configs, torch, np, dev) -> int:
     Rg = tg.query()["R"]
     dom = "long" if kt["long"][0] else "score"          # chunk-major or fused, whichever the tuner chose
     long_ms = kt[dom][1] / max(kt[dom][0], 1)
-    alg = P * (48.0 * cfg.L * info["R"] + 56)
+    tlr = tg.restrict(site - half, site + half, cfg.eps)
+    roof = gather_roofline(rs, ctx, tlr, dom, long_ms, P, cfg.L, info["R"])
+    tlr.free()
     res = {
         "metric": METRIC, "value": P / (ms_loc / 1e3), "unit": "poses/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_loc, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -548,9 +554,7 @@ def run_site(args, rs, configs, torch, np, dev) -> int:
         "local_ms_including_restriction": ms_loc,
         "restriction_kernels_ms": sum(kt[k][1] for k in ("restrict", "qr", "svd", "core", "t2c", "assemble", "cells"))
         / args.steps,
-        "roofline": {"kernel": dom, "kernel_ms": long_ms, "bound": "hbm", "achieved": alg / (long_ms / 1e3) / 1e9,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / (long_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None},
+        "roofline": roof,
         "autotune": tune, "short_range_on_second_stream": bool(args.overlap),
         "in_box_fraction": float(np.mean(ok)),
         "flags_equal_in_box": bool(np.array_equal(fg[ok], fl[ok])), "counts_equal": bool(np.array_equal(cg, cl)),
@@ -615,7 +619,7 @@ def run_ppiem(args, rs, configs, torch, np, dev) -> int:
     fl = state["res"]["flags"].cpu().numpy()
     order = np.argsort(be[im])
     top = [{"orbit": int(u), "rotation": int(bq[u]), "energy": float(be[u])} for u in np.nonzero(im)[0][order][:5]]
-    dom = max(("long", "score", "contact", "short"), key=lambda k: kt[k][1])
+    dom = max(("long", "score", "contact"), key=lambda k: kt[k][1])   # the gather kernels; a separate short-range launch is vector ALU work
     dom_ms = kt[dom][1] / max(kt[dom][0], 1)
     R = t.query()["R"]
     if dom == "contact":
@@ -625,9 +629,7 @@ def run_ppiem(args, rs, configs, torch, np, dev) -> int:
         roof = {"kernel": "contact", "kernel_ms": dom_ms, "bound": "alu", "achieved": work / (dom_ms / 1e3) / 1e12,
                 "peak": 78.6, "unit": "TFLOP/s", "frac": work / (dom_ms / 1e3) / 1e12 / 78.6, "traffic": None}
     else:
-        alg = P * (48.0 * cfg.L * R + 56)
-        roof = {"kernel": dom, "kernel_ms": dom_ms, "bound": "hbm", "achieved": alg / (dom_ms / 1e3) / 1e9,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / (dom_ms / 1e3) / 1e9 / HBM_PEAK_GBS, "traffic": None}
+        roof = gather_roofline(rs, ctx, t, dom, dom_ms, P, cfg.L, R)
     res = {
         "metric": METRIC, "value": P / (ms / 1e3), "unit": "poses/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
