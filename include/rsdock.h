@@ -341,6 +341,10 @@ void rsd_tensor_free(rsd_tensor* t);
  *   "poses_per_wave"  poses per wavefront in mode 2 (0 automatic, 1..4)
  *   "eig_solver"      eigenvectors of the Gram matrices in the build: 0 automatic (subspace
  *                     iteration for n >= 1024), 1 dense batched eigensolver, 2 subspace iteration
+ *   "qr_solver"       bases of the subspace iteration in the build and of the range panels in
+ *                     the rank reduction: 0 automatic (randomized Cholesky QR in one workgroup for
+ *                     k <= 128 columns, Householder QR where a Cholesky pass loses rank),
+ *                     1 rocSOLVER's Householder QR
  *   "t2c_solver"      SVD of the Tucker core slices in the build: 0 automatic (3 where its LDS
  *                     fits, else 1, else 2), 1 one-sided Jacobi with the slice in LDS,
  *                     2 rocSOLVER gesvd, 3 one-sided Jacobi on the transposed triangle of a
