@@ -669,11 +669,11 @@ __global__ void k_random_fill(double* __restrict__ X, int64_t count, uint64_t se
 // Y R_s^{-1} is well conditioned whatever the condition of Y), followed by Cholesky QR passes.
 // Both factorizations run in one workgroup of 256 lanes with the matrix in registers: a group
 // of eight lanes holds four adjacent columns, each lane a contiguous block of their rows.  A
-// step broadcasts one vector through LDS (double-buffered: one barrier per step), each lane
-// reads only its own rows of it, and a column's sum over its rows takes three lane exchanges.
-// The step loops are unrolled so that the slot of the step's column (and in the Cholesky the
-// register holding its row) is a compile-time constant.  The triangular inverse then works by
-// blocks in LDS.
+// step puts what every lane needs (the QR's reflector, the Cholesky's next four rows) into LDS,
+// double-buffered so that a step has one barrier; each lane reads only its own rows of it, and
+// a column's sum over its rows takes three lane exchanges.  The step loops are unrolled so that
+// the slot of the step's column (and in the Cholesky the registers holding its rows) are
+// compile-time constants.  The triangular inverse then works by 16 x 16 blocks in LDS.
 constexpr int kSmallRows = 144;          // sketch rows (k <= 128 columns): a k + 16 embedding
 constexpr int kSmallCols = 128;
 constexpr int kQrRowsPerLane = kSmallRows / 8;   // 18
