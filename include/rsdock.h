@@ -339,6 +339,9 @@ void rsd_tensor_free(rsd_tensor* t);
  *   "score_mode"      0 automatic, 1 one wavefront per pose for the whole pose,
  *                     2 long-range part in rank-chunk-major order across the XCDs
  *   "poses_per_wave"  poses per wavefront in mode 2 (0 automatic, 1..4)
+ *   "chunks_per_item" rank chunks per work item of the mode-2 long-range kernel (also in
+ *                     batches, fixed when the batch is created): 0 automatic (2), 1..4; the
+ *                     pose transforms and grid rows of an item are formed once for its chunks
  *   "eig_solver"      eigenvectors of the Gram matrices in the build: 0 automatic (subspace
  *                     iteration for n >= 1024), 1 dense batched eigensolver, 2 subspace iteration
  *   "qr_solver"       bases of the subspace iteration in the build and of the range panels in

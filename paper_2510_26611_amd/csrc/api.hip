@@ -1328,6 +1328,11 @@ rsd_status rsd_context_set_option(rsd_context* ctx, const char* name, int64_t va
     ctx->opt_pose_order = (int)value;
     return RSD_OK;
   }
+  if (std::strcmp(name, "chunks_per_item") == 0) {
+    RSD_CHECK(value >= 0 && value <= 4, RSD_E_INVALID, "chunks_per_item must be 0 .. 4");
+    ctx->opt_cpi = (int)value;
+    return RSD_OK;
+  }
   if (std::strcmp(name, "qr_solver") == 0) {
     RSD_CHECK(value == 0 || value == 1, RSD_E_INVALID, "qr_solver must be 0 or 1");
     ctx->opt_qr = (int)value;

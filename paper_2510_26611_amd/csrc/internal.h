@@ -95,6 +95,7 @@ struct Context {
   int opt_t2c = 0;             // core slice SVDs: 0 auto, 1 Jacobi in LDS, 2 rocSOLVER, 3 QR then Jacobi
   int opt_eig = 0;             // Gram eigenvectors: 0 auto, 1 dense batched eigensolver, 2 subspace iteration
   int opt_qr = 0;              // subspace-iteration bases: 0 auto (randomized Cholesky QR, k <= 128), 1 rocSOLVER QR
+  int opt_cpi = 0;             // rank chunks per long-range work item: 0 auto (2), 1..4
   int opt_svd = 0;             // small SVD of explicit-factor rank reduction: 0 auto, 1 gesvd, 2 gesdd, 3 Jacobi
   int opt_factors = 0;         // build factors: bit 0 Galerkin cell averages (else collocation at the
                                // nodes), bit 1 charges snapped to their nearest nodes (eq. 2.5)

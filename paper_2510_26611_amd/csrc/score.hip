@@ -541,8 +541,9 @@ struct LongParams {
   const double* __restrict__ trans;
   int64_t P;
   int ppw;                       // poses per wavefront
+  int cpi;                       // rank chunks per work item
   int64_t nblk;                  // pose blocks of 4 * ppw poses
-  int64_t items, per_xcd;
+  int64_t items, per_xcd;        // items = nblk * ceil(nchunk / cpi)
   double* __restrict__ part;     // [nchunk][P][S], S = 1 (energy) or 7 (energy, dE/dt, dE/domega)
   // tensors made by the canonical -> Tucker -> canonical step: column p of F_3 is column
   // slice[p] of U_3, so a chunk's mode-3 lerps take only a few distinct values per atom
@@ -563,7 +564,7 @@ struct GridPt {                  // one ligand atom of one pose: grid rows and w
 };
 
 template <bool GRAD, bool U3>
-__device__ void long_item(const LongParams& a, const int c, const int64_t p0, double4* smem);
+__device__ void long_item(const LongParams& a, const int c, const int64_t p0, double4* smem, bool reuse);
 
 // The chunk's columns map to the U_3 columns clo .. clo + nsl - 1 (a contiguous range: the
 // terms are grouped by core slice); with nsl <= kSlots the mode-3 lerps come from LDS.
@@ -575,6 +576,24 @@ __device__ __forceinline__ bool chunk_slices(const LongParams& a, int c, int* cl
   return a.slice[p_last] - *clo < kSlots;
 }
 
+// Work item `item`: rank chunks cpi * (item / nblk) .. + cpi - 1 for the pose block item % nblk.
+// The pose transforms and grid rows are formed for the first chunk and kept in LDS for the
+// others, which form only their mode-3 lerps; the chunks of an item follow one another, so the
+// XCD's L2 holds the rows of about cpi chunks at once.  The whole workgroup calls it.
+template <bool GRAD>
+__device__ void long_work(const LongParams& a, const int64_t item, double4* smem) {
+  const int c0 = a.cpi * (int)(item / a.nblk);
+  const int64_t p0 = (item % a.nblk) * (4 * a.ppw);
+  const int c1 = min(c0 + a.cpi, a.nchunk);
+  for (int c = c0; c < c1; ++c) {
+    int clo = 0;
+    if (chunk_slices(a, c, &clo))
+      long_item<GRAD, true>(a, c, p0, smem, c > c0);
+    else
+      long_item<GRAD, false>(a, c, p0, smem, c > c0);
+  }
+}
+
 template <bool GRAD>
 __global__ __launch_bounds__(256) void k_long(const LongParams a) {
   extern __shared__ double4 smem[];
@@ -582,17 +601,16 @@ __global__ __launch_bounds__(256) void k_long(const LongParams a) {
   if (j >= a.per_xcd) return;
   const int64_t item = (int64_t)(blockIdx.x & 7) * a.per_xcd + j;
   if (item >= a.items) return;
-  const int c = (int)(item / a.nblk);
-  int clo = 0;
-  if (chunk_slices(a, c, &clo))
-    long_item<GRAD, true>(a, c, (item % a.nblk) * (4 * a.ppw), smem);
-  else
-    long_item<GRAD, false>(a, c, (item % a.nblk) * (4 * a.ppw), smem);
+  long_work<GRAD>(a, item, smem);
 }
 
 // Chunk c of the long-range sum for the poses [p0, p0 + 4*ppw); the whole workgroup calls it.
+// reuse: the ligand, the pose flags and the grid points (and their R u_l) in LDS are those of
+// the previous call for the same poses; only the mode-3 lerps of this chunk are formed.  The
+// barrier after the ligand load also separates this call's LDS writes from the previous
+// call's final reads.
 template <bool GRAD, bool U3>
-__device__ void long_item(const LongParams& a, const int c, const int64_t p0, double4* smem) {
+__device__ void long_item(const LongParams& a, const int c, const int64_t p0, double4* smem, bool reuse) {
   constexpr int S = GRAD ? 7 : 1;
   const int L = a.L;
   const int PB = 4 * a.ppw;
@@ -606,9 +624,27 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
   int clo = 0;
   if (U3) chunk_slices(a, c, &clo);
   const int tid = threadIdx.x;
-  for (int i = tid; i < L; i += 256) s_lig[i] = a.lig[i];
-  for (int i = tid; i < PB; i += 256) s_bad[i] = 0;
+  if (!reuse) {
+    for (int i = tid; i < L; i += 256) s_lig[i] = a.lig[i];
+    for (int i = tid; i < PB; i += 256) s_bad[i] = 0;
+  }
   __syncthreads();
+  if (reuse) {
+    if (U3) {   // this chunk's mode-3 lerps at the kept grid points (rejected poses are skipped later)
+      for (int e = tid; e < PB * L; e += 256) {
+        const GridPt g = s_pt[e];
+        const double* r0 = a.U3 + (int64_t)g.i2 * a.u3_ld + clo;
+        const double* r1 = r0 + a.u3_ld;
+#pragma unroll
+        for (int q = 0; q < kSlots; ++q) {
+          const int cq = clo + q < a.u3_ld ? q : 0;
+          const double dq = r1[cq] - r0[cq];
+          s_l3[e * L3 + q] = fma(g.f2, dq, r0[cq]);
+          if (GRAD) s_l3[e * L3 + kSlots + q] = dq;
+        }
+      }
+    }
+  } else {
   for (int e = tid; e < PB * L; e += 256) {
     const int lp = e / L, l = e - lp * L;
     const int64_t p = p0 + lp;
@@ -647,6 +683,7 @@ __device__ void long_item(const LongParams& a, const int c, const int64_t p0, do
     }
     s_pt[e] = g;
     if (!ok) atomicOr(&s_bad[lp], 1);
+  }
   }
   __syncthreads();
   const int lane = tid & 63, wv = tid >> 6;
@@ -995,12 +1032,7 @@ __global__ __launch_bounds__(256) void k_batch_long(const BatchDesc* __restrict_
   if (jl >= lp.per_xcd) return;
   const int64_t item = (int64_t)(blockIdx.x & 7) * lp.per_xcd + jl;
   if (item >= lp.items) return;
-  const int c = (int)(item / lp.nblk);
-  int clo = 0;
-  if (chunk_slices(lp, c, &clo))
-    long_item<false, true>(lp, c, (item % lp.nblk) * (4 * lp.ppw), smem);
-  else
-    long_item<false, false>(lp, c, (item % lp.nblk) * (4 * lp.ppw), smem);
+  long_work<false>(lp, item, smem);
 }
 
 // Ligand frames of every request and, for the persistent launch, its eight work counters
@@ -1042,12 +1074,7 @@ __global__ __launch_bounds__(256) void k_batch_fused(const BatchDesc* __restrict
       if (jl >= lp.per_xcd) continue;
       const int64_t item = (int64_t)x * lp.per_xcd + jl;
       if (item >= lp.items) continue;
-      const int c = (int)(item / lp.nblk);
-      int clo = 0;
-      if (chunk_slices(lp, c, &clo))
-        long_item<false, true>(lp, c, (item % lp.nblk) * (4 * lp.ppw), smem);
-      else
-        long_item<false, false>(lp, c, (item % lp.nblk) * (4 * lp.ppw), smem);
+      long_work<false>(lp, item, smem);
     } else {
       const int64_t g = (it - u_long) * 8 + x;
       const int r = find_request_uniform(d, nreq, g, [](const BatchDesc& q) { return q.short_base; });
@@ -1170,13 +1197,19 @@ int pick_ppw(int L, bool grad, bool u3, int want) {
 
 // Whether the chunk-major kernel serves the tensor's mode-3 lerps from LDS: the tensor keeps
 // U_3, the option is on, and the extra LDS still fits at the poses per wavefront it gets.
+// Rank chunks per long-range work item: option chunks_per_item, 0 automatic (2).  Two chunks
+// share one pose transform per atom, and the two chunks' rows of modes 1-2 (2 x 2 x n x 512
+// bytes, 4 MB at n = 2048) still fit an XCD's L2.
+constexpr int kChunksPerItem = 2;
+int chunks_per_item(const Context* ctx) { return ctx->opt_cpi > 0 ? ctx->opt_cpi : kChunksPerItem; }
+
 bool use_u3(const Context* ctx, const Tensor* t, int L, bool grad, int ppw_want) {
   if (!t->U3 || !ctx->opt_shared_mode3) return false;
   return long_lds(L, pick_ppw(L, grad, true, ppw_want), grad, true) <= kLdsMax;
 }
 
 LongParams make_long_params(const Tensor* t, const ScoreIO& io, const double4* lig, int ppw, double* part,
-                            bool shared_mode3) {
+                            bool shared_mode3, int cpi) {
   LongParams lp{};
   lp.F = t->F;
   lp.chunk_stride = (int64_t)t->n * kChunk;
@@ -1194,8 +1227,9 @@ LongParams make_long_params(const Tensor* t, const ScoreIO& io, const double4* l
   lp.trans = io.trans;
   lp.P = io.P;
   lp.ppw = ppw;
+  lp.cpi = std::max(1, cpi);
   lp.nblk = (io.P + 4 * ppw - 1) / (4 * ppw);
-  lp.items = lp.nblk * t->nchunk;
+  lp.items = lp.nblk * ((t->nchunk + lp.cpi - 1) / lp.cpi);
   lp.per_xcd = (lp.items + 7) / 8;
   lp.part = part;
   lp.U3 = shared_mode3 ? t->U3 : nullptr;
@@ -1333,7 +1367,7 @@ rsd_status launch_score(Context* ctx, const Tensor* t, const ScoreIO& io, void* 
     }
     return RSD_OK;
   }
-  LongParams lp = make_long_params(t, io, lig, ppw, (double*)(w8 + off_part), u3);
+  LongParams lp = make_long_params(t, io, lig, ppw, (double*)(w8 + off_part), u3, chunks_per_item(ctx));
   RSD_CHECK(lp.per_xcd * 8 <= 0x7fffffffLL, RSD_E_UNSUPPORTED, "too many poses in one call");
   const int* comb_perm = nullptr;   // slot -> pose of the long-range partials, when sorted
   if (sorted) {
@@ -1858,7 +1892,7 @@ rsd_status batch_create(Context* ctx, const rsd_request* req_in, int32_t nreq, B
     double* es = (double*)(m + o_es) + off_es[k];
     double* part = (double*)(m + o_part) + off_part[k];
     h[k].sp = make_score_params(t, io, lig, rlig, es, nullptr);
-    h[k].lp = make_long_params(t, io, lig, shp[order[k]].ppw, part, shp[order[k]].u3 != 0);
+    h[k].lp = make_long_params(t, io, lig, shp[order[k]].ppw, part, shp[order[k]].u3 != 0, chunks_per_item(ctx));
     if (off_perm[k] >= 0) {
       int* perm = (int*)(m + o_perm) + off_perm[k];
       h[k].lp.perm = perm;

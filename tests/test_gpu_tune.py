@@ -223,3 +223,48 @@ def test_cell_edge_tuner_keeps_parity():
     assert_parity({k: v[sample] for k, v in after.items()}, ref, label="after the cell tuner")
     t.free()
     ctx.close()
+
+
+def test_chunks_per_item_bitwise(env):
+    """A long-range work item may take several rank chunks of one pose block, forming the pose
+    transforms once; each chunk's partial sums are the same arithmetic, so chunks_per_item
+    1 .. 4 give the same bits, alone and in a batch, with and without gradients, with the
+    mode-3 lerps from U_3 and from the gathered columns, in spatial and in input order.  The
+    5,000-atom protein's tensor has 29 rank chunks, so 2, 3 and 4 leave a partial last item."""
+    rs, torch, ctx, cfg, wl, F, t, dev = env
+    c2 = configs.CONFIG2
+    w2 = configs.make(c2, P=1)
+    tb = rs.build_rs_tensor(ctx, w2.protein_charges, w2.protein_positions, c2.n, c2.b, rs.Sinc.from_config(c2))
+    assert tb.layout()["nchunk"] == 29
+    qs, ts = dev["q"], dev["t"]
+    ctx.set_option("score_mode", 2)
+    try:
+        for u3 in (1, 0):
+            ctx.set_option("shared_mode3", u3)
+            for order in (1, 2):
+                ctx.set_option("pose_order", order)
+                ref = {}
+                for grads in (False, True):
+                    out = {}
+                    for cpi in (1, 2, 3, 4):
+                        ctx.set_option("chunks_per_item", cpi)
+                        o = rs.score_poses(ctx, tb, dev["z"], dev["x"], qs, ts, c2.sigma, grads=grads)
+                        torch.cuda.synchronize()
+                        out[cpi] = {k: v.cpu().numpy() for k, v in o.items()}
+                    for cpi in (2, 3, 4):
+                        for k in out[1]:
+                            assert np.array_equal(out[1][k], out[cpi][k], equal_nan=True), (u3, order, grads, cpi, k)
+                    ref[grads] = out[1]
+                ctx.set_option("chunks_per_item", 3)
+                b = rs.Batch(ctx, [dict(tensor=tb, lig_charges=dev["z"], lig_positions=dev["x"], quats=qs,
+                                        trans=ts, vdw_min=c2.sigma)])
+                b.run()
+                torch.cuda.synchronize()
+                for k, v in b.outputs()[0].items():
+                    if k in ref[False]:
+                        assert np.array_equal(v.cpu().numpy(), ref[False][k], equal_nan=True), (u3, order, k)
+                b.free()
+    finally:
+        for name, v in (("chunks_per_item", 0), ("shared_mode3", 1), ("pose_order", 0), ("score_mode", 0)):
+            ctx.set_option(name, v)
+    tb.free()
