@@ -178,8 +178,8 @@ def main() -> int:
                          "of 512..8192 rows and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
-              f"(the multi-GPU design is described but not run)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library "
+              f"scores on one device, and sharding over several is a design, not code", file=sys.stderr)
         return 2
 
     import numpy as np
