@@ -268,3 +268,46 @@ def test_chunks_per_item_bitwise(env):
         for name, v in (("chunks_per_item", 0), ("shared_mode3", 1), ("pose_order", 0), ("score_mode", 0)):
             ctx.set_option(name, v)
     tb.free()
+
+
+# accepted values of every context option (include/rsdock.h); one value just outside each range
+_OPTION_RANGES = {
+    "score_mode": ([0, 1, 2], [-1, 3]),
+    "poses_per_wave": ([0, 1, 2, 3, 4], [-1, 5]),
+    "eig_solver": ([0, 1, 2], [-1, 3]),
+    "t2c_solver": ([0, 1, 2, 3], [-1, 4]),
+    "short_waves": ([0, 1, 2, 4], [-1, 3, 8]),
+    "use_tuning": ([0, 1], [-1, 2]),
+    "shared_mode3": ([0, 1], [-1, 2]),
+    "short_poly": ([0, 1], [-1, 2]),
+    "pose_order": ([0, 1, 2], [-1, 3]),
+    "chunks_per_item": ([0, 1, 2, 3, 4], [-1, 5]),
+    "qr_solver": ([0, 1], [-1, 2]),
+    "batch_mode": ([0, 1, 2], [-1, 3]),
+    "overlap": ([0, 1], [-1, 2]),
+    "factors": ([0, 1, 2, 3], [-1, 4]),
+    "svd_solver": ([0, 1, 2, 3, 4], [-1, 5]),
+    "gram_solver": ([0, 1, 2], [-1, 3]),
+}
+
+
+def test_every_option_accepts_its_range_and_rejects_the_rest():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2510_26611_amd as rs
+    ctx = rs.Context(0)
+    try:
+        for name, (good, bad) in _OPTION_RANGES.items():
+            for v in good:
+                ctx.set_option(name, v)
+            for v in bad:
+                with pytest.raises(rs.RsdError) as e:
+                    ctx.set_option(name, v)
+                assert e.value.code == -1, (name, v)
+            ctx.set_option(name, 0)
+        for name in ("no_such_option", "", "score_mode "):
+            with pytest.raises(rs.RsdError) as e:
+                ctx.set_option(name, 0)
+            assert e.value.code == -1, name
+    finally:
+        ctx.close()
