@@ -91,11 +91,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
-__device__ __forceinline__ int wave_sum_i(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 __device__ __forceinline__ double wave_min(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
@@ -103,6 +98,9 @@ __device__ __forceinline__ double wave_min(double v) {
 }
 __device__ __forceinline__ int lane_prefix(uint64_t mask) {   // set bits of mask below this lane
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+__device__ __forceinline__ int lane_prefix_from(uint64_t mask, int base) {   // base + lane_prefix(mask)
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, (uint32_t)base));
 }
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 // Cell coordinate floor(v) clamped to [0, dim-1]; clamping happens in FP64 so that huge or
@@ -361,8 +359,12 @@ __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4*
     const int cz0 = cell_floor((tz - Rc - g.origin) * g.inv_edge, g.dim);
     const int cz1 = cell_floor((tz + Rc - g.origin) * g.inv_edge, g.dim);
     const int ny = cy1 - cy0 + 1;
-    const int nrows = ny * (cz1 - cz0 + 1);
-    int qh = 0, qt = 0;   // ring head / tail (wave-uniform)
+    // the same on every lane; readfirstlane tells the compiler so, which keeps the loops
+    // below (and the queue counters they carry) uniform
+    const int nrows = __builtin_amdgcn_readfirstlane(ny * (cz1 - cz0 + 1));
+    // ring head / tail, wave-uniform: every update goes through readfirstlane so that the
+    // compiler keeps them (and the drain test) in scalar registers
+    int qh = 0, qt = 0;
     // The accept flag asks whether some pair is closer than sigma.  When sigma <= r_cut every
     // such pair is queued, so the minimum is taken over the queued pairs in the drain instead
     // of over every candidate test.
@@ -411,7 +413,7 @@ __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4*
           gw2 += v0 * G1 - v1 * G0;
         }
       }
-      qh += m;
+      qh = __builtin_amdgcn_readfirstlane(qh + m);
       wave_sync();
     };
 
@@ -442,7 +444,7 @@ __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4*
           const int v = __shfl_up(incl, off, 64);
           if (lane >= off) incl += v;
         }
-        const int total = __shfl(incl, 63, 64);
+        const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
         rowoff[lane] = incl - seg_len;
         rowstart[lane] = seg_start;
         wave_sync();
@@ -459,8 +461,7 @@ __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4*
             }
             at = a.atoms[rowstart[lo] + (k - rowoff[lo])];
           }
-          for (int l = 0; l < L; ++l) {
-            const double4 y = s_y[l];
+          auto test = [&](const double4 y, const int l) {
             const double dx = y.x - at.x, dy = y.y - at.y, dz = y.z - at.z;
             const double d2 = (dx * dx + dy * dy) + dz * dz;     // ((dx^2 + dy^2) + dz^2), no fma
             const bool hit = d2 < a.rc2;                          // +inf for a lane without a candidate
@@ -468,18 +469,30 @@ __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4*
             const uint64_t m = __ballot(hit);
             if (m != 0ull) {
               if (hit) {
-                Pair& e = q[(qt + lane_prefix(m)) & (kQueue - 1)];
+                Pair& e = q[lane_prefix_from(m, qt) & (kQueue - 1)];
                 e.d2 = d2;
                 e.zz = at.w * y.w;
                 if constexpr (GRAD) {
                   e.dx = dx; e.dy = dy; e.dz = dz; e.l = l;
                 }
-                ++cnt;
               }
-              qt += __popcll(m);
+              // the pair count is the wavefront's, like the queue tail
+              cnt = __builtin_amdgcn_readfirstlane(cnt + (int)__popcll(m));
+              qt = __builtin_amdgcn_readfirstlane(qt + (int)__popcll(m));
               if (qt - qh >= 64) drain(64);
             }
+          };
+          int l = 0;
+          if constexpr (GRAD) {
+            // two ligand atoms per step, both coordinate reads in flight together (faster with
+            // gradients; without them the extra registers cost more than the overlap gains)
+            for (; l + 2 <= L; l += 2) {
+              const double4 y0 = s_y[l], y1 = s_y[l + 1];
+              test(y0, l);
+              test(y1, l + 1);
+            }
           }
+          for (; l < L; ++l) test(s_y[l], l);
         }
         wave_sync();
       }
@@ -494,8 +507,7 @@ __device__ void score_pose(const ScoreParams& a, const int64_t p, const double4*
   // ---- A5: reductions and output
   eL = wave_sum(eL);
   eS = wave_sum(eS);
-  cnt = wave_sum_i(cnt);
-  mind = wave_min(mind);
+  mind = wave_min(mind);   // cnt is already the wavefront's total
   if (GRAD) {
     gt0 = wave_sum(gt0); gt1 = wave_sum(gt1); gt2 = wave_sum(gt2);
     gw0 = wave_sum(gw0); gw1 = wave_sum(gw1); gw2 = wave_sum(gw2);
